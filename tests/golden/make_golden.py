@@ -1,0 +1,70 @@
+"""Write the oracle's reference values for the larger workloads.
+
+Calls only the CPU oracle (``oracle/``) on the seeded synthetic inputs
+(``synth``); nothing here touches the GPU library.  The output file
+``oracle_values.json`` holds, per workload, the TOP singular values, E0,
+the right-hand-side and solution norms, E2 and its parts, plus a few sampled
+amplitudes of b, x and of sigma(x) for a seeded random x, addressed by
+their flat index in the seven-box layout.
+
+Usage:  python tests/golden/make_golden.py [c2 c3 c5 ...]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth                                   # noqa: E402
+from oracle import structured, topbasis        # noqa: E402
+
+
+def sample_indices(dim, offsets, seed):
+    rng = np.random.default_rng(seed)
+    idx = []
+    for k in range(7):
+        lo, hi = offsets[k], offsets[k + 1]
+        if hi > lo:
+            idx += list(rng.integers(lo, hi, 24))
+            idx += [lo, hi - 1]
+    return sorted(set(int(i) for i in idx))
+
+
+def run(name):
+    p = synth.config_problem(name)
+    t0 = time.time()
+    lam, R = topbasis.top_rotation(p.F, p.C, p.n_occ)
+    Ft, Bt = topbasis.rotate(p.F, p.B, R)
+    rh = structured.RHS(Ft, Bt, lam, p.n_occ)
+    op = rh.op
+    b = rh.rhs()
+    x, r, it, rel = structured.pcg(op, b, tol=1e-10, max_iter=400)
+    e2_dl = op.dot(b, x) - op.dot(x, r)
+    e2_s = rh.e2_s()
+    from oracle.layout import box_offsets
+    off = [int(v) for v in box_offsets(p.n_occ, p.n_vir)]
+    xr = synth.random_amplitudes(op.dim, 1234)
+    sig = op.sigma(xr)
+    idx = sample_indices(op.dim, off, 99)
+    out = dict(n_occ=p.n_occ, n_vir=p.n_vir, n_aux=p.n_aux, dim=op.dim, offsets=off,
+               lam=lam.tolist(), e0=op.E0, omega=op.omega,
+               b_norm_w=float(np.sqrt(op.dot(b, b))), x_norm_w=float(np.sqrt(op.dot(x, x))),
+               e2=e2_dl + e2_s, e2_dl=e2_dl, e2_s=e2_s, iters=it, rel_resid=rel,
+               sample_idx=idx, b_sample=b[idx].tolist(), x_sample=x[idx].tolist(),
+               sigma_seed=1234, sigma_sample=sig[idx].tolist(),
+               seconds=time.time() - t0)
+    return out
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or ["c1", "c2", "c5", "c3"]
+    path = os.path.join(HERE, "oracle_values.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    for nm in names:
+        data[nm] = run(nm)
+        print(nm, data[nm]["e2"], data[nm]["iters"], data[nm]["seconds"], flush=True)
+        json.dump(data, open(path, "w"), indent=1)
