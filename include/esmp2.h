@@ -1,0 +1,163 @@
+/*
+ * esmp2.h -- C ABI of the MI355X (gfx950) hot path of N^5 excited-state-specific
+ * second-order perturbation theory (ESMP2-TOP(1), singlet).
+ *
+ * The calls follow the paper's statement of the problem:
+ *   1. rotate the ESMF reference to the transition-orbital-pair (TOP) basis
+ *      (Sec. II.A: SVD of the singles coefficients, C = U Lambda V^T, and the
+ *      occupied-occupied / virtual-virtual rotations that make the reference a
+ *      sum of n_occ pair excitations);
+ *   2. build the right-hand side b = Q V |Psi0> = Q H |Psi0> on the first-order
+ *      space of doubles and L-triples (Sec. II.B, Eq. for Psi1 and the triples
+ *      matrix element) and the directly inverted S-triple energy (Sec. II.D);
+ *   3. apply sigma = (H0 - E0) x, the modified zeroth-order Hamiltonian
+ *      (Sec. II.C, the Q F Q replacement: full Fock operator on doubles +
+ *      L-triples);
+ *   4. solve Q (H0 - E0) Q Psi1 = -Q V Psi0 by preconditioned conjugate
+ *      gradient (Sec. III.A) and return E2 = <Psi0|V|Psi1>.
+ *
+ * Conventions
+ *   - Orbitals: n_occ occupied then n_vir virtual spatial orbitals, N = n_occ+n_vir.
+ *   - Hamiltonian input: the Fock matrix F (of the reference's one-body density)
+ *     and a factor B with (pq|rs) = sum_Q B[Q][p][q] B[Q][r][s]; the one-electron
+ *     operator is h = F - G[gamma(Psi0)].
+ *   - Reference: Psi0 = sum_ia C[i][a] (E^up_ai + E^dn_ai)/sqrt(2) |Phi>, singlet,
+ *     ||C||_F = 1.  Only n_top = 1 (one large TOP, "ESMP2-TOP(1)") is supported.
+ *   - TOP basis: singular values in descending order; the TOP virtual of occupied
+ *     l is virtual l; the remaining virtuals (AVOs) diagonalise the Fock matrix in
+ *     their span (ascending).  Every occupied TOP orbital and AVO is signed so that
+ *     its largest-magnitude coefficient in the input basis is positive; a TOP
+ *     virtual takes the sign that makes its singular value positive.
+ *   - Amplitude layout ("seven boxes", t = occupied 0, t' = virtual 0), each box
+ *     contiguous in this order, occupied pair outer, virtual pair inner, pairs
+ *     written "(p<q)" packed row-major over the strict upper triangle:
+ *       0 T2   (i<j),(a<b)                 a+_{a u} a+_{b u} a_{j u} a_{i u}|Phi>
+ *       1 S2   i,j,a,b (dense)             a+_{a u} a+_{b d} a_{j d} a_{i u}|Phi>
+ *       2 T3L  (j<k) in 1..,(b<c) in 1..   a+_{t'u}a+_{b u}a+_{c u}a_{k u}a_{j u}a_{t u}|Phi>
+ *       3 H1P1 (j<k),(b<c)                 a+_{t'u}a+_{b d}a+_{c d}a_{k d}a_{j d}a_{t u}|Phi>
+ *       4 H1P2 (j<k), a in 1.., c in 1..   a+_{a u}a+_{t'd}a+_{c d}a_{k d}a_{j d}a_{t u}|Phi>
+ *       5 H2P1 i in 1..,k in 1..,(b<c)     a+_{t'u}a+_{b d}a+_{c d}a_{k d}a_{t d}a_{i u}|Phi>
+ *       6 H2P2 i,k in 1.., a,c in 1..      a+_{a u}a+_{t'd}a+_{c d}a_{k d}a_{t d}a_{i u}|Phi>
+ *     (u/d = spin up/down).  Boxes other than S2 stand for a spin-flip pair of
+ *     determinants (inner-product weight 2); S2 entries are single determinants
+ *     (weight 1) and enter the operator flip-symmetrised.
+ *
+ * Memory and streams
+ *   - A handle is bound to one device and one stream at creation.  All work is
+ *     ordered on that stream; calls return after queueing unless they return
+ *     host scalars (documented per call), in which case they synchronise it.
+ *   - Pointers marked "device" must be device memory of the handle's device.
+ *     The caller keeps ownership of every pointer it passes; the handle owns
+ *     its internal copies and work buffers (released by esmp2_destroy).
+ *   - A handle is not thread safe.
+ *
+ * Errors: every call returns esmp2_status; no exception crosses the ABI and
+ * nothing aborts.  esmp2_last_error() returns a message for the last failure.
+ */
+#ifndef ESMP2_H
+#define ESMP2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esmp2_handle_* esmp2_handle;
+
+typedef enum {
+  ESMP2_OK = 0,
+  ESMP2_INVALID_ARG = 1,    /* bad size, null pointer, NaN/Inf input, n_vir < n_occ */
+  ESMP2_BAD_ORDER = 2,      /* call sequence violated (e.g. sigma before rotate)   */
+  ESMP2_NOT_SPD = 3,        /* a diagonal denominator <= 0 or p.Ap <= 0 in CG       */
+  ESMP2_NOT_CONVERGED = 4,  /* max_iter reached; result holds the partial state     */
+  ESMP2_OOM = 5,            /* device allocation failed                              */
+  ESMP2_HIP_ERROR = 6,      /* a HIP runtime call failed                             */
+  ESMP2_UNSUPPORTED = 7     /* option not implemented (n_top != 1, triplet, ...)     */
+} esmp2_status;
+
+typedef enum {
+  ESMP2_FP64 = 0,           /* FP64 everywhere                                       */
+  ESMP2_FP32 = 1            /* sigma contractions in FP32 (FP32 accumulation)        */
+} esmp2_precision;
+
+typedef struct {
+  double tol;               /* stop when ||b + A x||_W / ||b||_W <= tol (e.g. 1e-8)   */
+  int max_iter;             /* conjugate-gradient iteration cap                      */
+  int precision;            /* esmp2_precision of the solve: FP64, or FP32 inner
+                               solves inside FP64 iterative refinement               */
+  const double* x0;         /* device, n_amp, initial guess (warm start) or NULL      */
+  double* x_out;            /* device, n_amp, receives the solution, or NULL          */
+  double* resid_hist;       /* host, max_iter entries of ||r||/||b|| per iteration, or NULL */
+} esmp2_solve_opts;
+
+typedef struct {
+  double e2;                /* E2 = e2_dl + e2_s                                      */
+  double e2_dl;             /* doubles + L-triples part, Hylleraas form b.x - x.r     */
+  double e2_s;              /* directly inverted S-triples part                       */
+  double e0;                /* E0 = <Psi0|F|Psi0>                                     */
+  double rel_resid;         /* final ||b + A x||_W / ||b||_W                          */
+  int iterations;           /* conjugate-gradient iterations (all inner ones in FP32) */
+  int outer;                /* refinement steps (FP32 precision), 0 otherwise         */
+  int status;               /* esmp2_status of the solve                              */
+} esmp2_solve_result;
+
+/* Create a handle on `device`, ordering all work on `stream` (a hipStream_t,
+ * NULL = the default stream).  *out receives the handle. */
+esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream);
+
+/* Release the handle and all device memory it owns.  NULL is accepted. */
+esmp2_status esmp2_destroy(esmp2_handle h);
+
+/* Bind a problem (copies the inputs; the caller keeps ownership).
+ *   F: device, N x N row-major, symmetric (the Fock matrix, input orbital basis)
+ *   B: device, n_aux x N x N row-major, B[Q][p][q] == B[Q][q][p]
+ *   C: device, n_occ x n_vir row-major, ||C||_F = 1
+ *   spin: 0 = singlet (only value supported); n_top: 1 (only value supported).
+ * Requires 2 <= n_occ <= n_vir, n_aux >= 1.  Checks F, B, C for NaN/Inf
+ * (synchronises the stream).  Resets any previous problem. */
+esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux,
+                               const double* F, const double* B, const double* C,
+                               int spin, int n_top);
+
+/* Rotate to the TOP basis (paper Sec. II.A).  lambda_out: host, n_occ doubles
+ * (descending singular values) or NULL; when non-NULL the call synchronises. */
+esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out);
+
+/* Size of the amplitude vector and the start offsets of the seven boxes;
+ * box_offsets has 8 entries (box_offsets[7] == *n_amp).  Either may be NULL. */
+esmp2_status esmp2_space(esmp2_handle h, int64_t* n_amp, int64_t* box_offsets);
+
+/* Right-hand side b_mu = <mu|H|Psi0> on the seven boxes, E0 and the
+ * S-triple energy E2_S = -sum_S b^2/D (paper Sec. II.B-II.D).
+ *   b_out: device, n_amp doubles, or NULL (b is kept in the handle either way)
+ *   e0, e2_s: host scalars or NULL (non-NULL synchronises the stream).
+ * Returns ESMP2_NOT_SPD if a denominator of the first-order space is <= 0. */
+esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* e2_s);
+
+/* y = (H0 - E0) x on doubles + L-triples (paper Sec. II.C).
+ *   x, y: device, n_amp elements each (double for ESMP2_FP64, float for
+ *   ESMP2_FP32); x and y must not overlap.  Requires esmp2_rotate_top. */
+esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision);
+
+/* Jacobi-preconditioned conjugate gradient for A x = -b (A = H0 - E0 on D + L,
+ * weighted inner product), then E2 (paper Sec. III.A and Sec. II.C).  Builds the
+ * right-hand side first if esmp2_build_rhs has not been called.  Synchronises.
+ * With precision = ESMP2_FP32 the operator inside each inner CG solve runs in
+ * FP32 and an FP64 residual drives iterative refinement. */
+esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
+                         esmp2_solve_result* result);
+
+/* C = A B for row-major FP64 matrices (A: m x k, B: k x n, C: m x n, all device),
+ * on the matrix cores, queued on the handle's stream.  This is the dense GEMM the
+ * library uses for the TOP-basis rotation and the integral blocks; it is exported
+ * so that its operand layout can be validated directly. */
+esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A, const double* B, double* C);
+
+/* Message of the last failing call on this handle (never NULL). */
+const char* esmp2_last_error(esmp2_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESMP2_H */

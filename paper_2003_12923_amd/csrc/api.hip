@@ -1,0 +1,508 @@
+// C ABI of libesmp2 (see include/esmp2.h).  Host orchestration: validation,
+// buffer ownership, and the stream-ordered sequence of kernel launches.
+#include "common.h"
+#include "sigma.h"
+#include "pcg.h"
+#include <math.h>
+#include <string.h>
+#include <vector>
+#include <new>
+#include <algorithm>
+
+// Kernels come from the other sources of the same translation unit (esmp2_all.hip).
+
+using namespace esmp2;
+
+// ---------------------------------------------------------------------------
+// small helper kernels local to the orchestration
+// ---------------------------------------------------------------------------
+__global__ void k_finite(const double* v, int64_t n, int* bad) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(v[g])) bad[0] = 1;
+}
+
+// shift below the spectrum of F_vv: -(max_a sum_b |F_ab|) - 1
+__global__ void k_shift(const double* F, int n, int no, double* out) {
+  double mx = 0.0;
+  for (int a = threadIdx.x; a < n - no; a += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < n - no; ++b) s += fabs(F[(no + a) * n + no + b]);
+    mx = fmax(mx, s);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  __shared__ double ws[16];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, ws[k]);
+    out[0] = -r - 1.0;
+  }
+}
+
+// TOP-basis Fock blocks, orbital energies, omega / kappa / E0 and the shifted,
+// padded virtual blocks used by the Sylvester kernel.
+//   sc[0] = omega = sum_l lam_l^2 (f_l'l' - f_ll), sc[1] = kappa = f_t't' - f_tt - omega,
+//   sc[2] = E0 = 2 sum_i f_ii + omega
+__global__ void k_topfock(const double* Ft, const double* lam, int no, int nv, int mv, double* fo, double* fv,
+                          double* fov, double* eo, double* ev, double* Fd, double* Fl, double* sc) {
+  const int n = no + nv;
+  double om = 0.0, tr = 0.0;
+  for (int l = 0; l < no; ++l) {
+    om += lam[l] * lam[l] * (Ft[(no + l) * n + no + l] - Ft[l * n + l]);
+    tr += Ft[l * n + l];
+  }
+  const double ka = Ft[no * n + no] - Ft[0] - om;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) { sc[0] = om; sc[1] = ka; sc[2] = 2.0 * tr + om; }
+  if (g < (int64_t)mv * mv) {
+    int a = g / mv, b = g % mv;
+    double v = (a < nv && b < nv) ? Ft[(no + a) * n + no + b] : 0.0;
+    Fd[g] = v + ((a == b && a < nv) ? -0.5 * om : 0.0);
+    Fl[g] = v + ((a == b && a < nv) ? 0.5 * ka : 0.0);
+    if (a < nv && b < nv) fv[a * nv + b] = v;
+  }
+  if (g < no * no) fo[g] = Ft[(g / no) * n + g % no];
+  if (g < no * nv) fov[g] = Ft[(g / nv) * n + no + g % nv];
+  if (g < no) eo[g] = Ft[g * n + g];
+  if (g < nv) ev[g] = Ft[(no + g) * n + no + g];
+}
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct esmp2_handle_ {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err = "no error";
+  int state = 0;                 // 0 empty, 1 problem set, 2 rotated, 3 rhs built
+  Dims d{};
+  std::vector<void*> allocs;     // everything owned, freed at reset/destroy
+  // inputs
+  double *F = nullptr, *B = nullptr, *C = nullptr;
+  // rotation
+  double *lam, *U, *V, *Wm, *G, *M, *rot, *evals, *Z, *R, *avo, *Ft, *T, *Bov, *Bvt, *Boo;
+  int* iinfo;
+  double *fo, *fv, *fov, *eo, *ev, *Fd, *Fl, *sc_rot;
+  double omega = 0, kappa = 0, e0 = 0, e2s = 0;
+  int svd_sweeps = 0, eig_sweeps = 0;
+  // rhs
+  double *fphi, *X, *Vint, *Mint, *b, *dinv, *blockmin, *partial, *sc;
+  bool have_rhs = false;
+  // sigma scratch
+  double *S, *side, *side_tr;
+  int2* jobs = nullptr;
+  int njobs = 0;
+  // Krylov vectors
+  double *x, *r, *p, *q;
+};
+
+static esmp2_status fail(esmp2_handle h, esmp2_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+static void release(esmp2_handle h) {
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  h->state = 0;
+  h->have_rhs = false;
+}
+
+template <class T>
+static bool dalloc(esmp2_handle h, T** p, size_t count) {
+  void* ptr = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&ptr, count * sizeof(T)) != hipSuccess) return false;
+  h->allocs.push_back(ptr);
+  *p = (T*)ptr;
+  return true;
+}
+
+static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+extern "C" {
+
+esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
+  if (!out) return ESMP2_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ESMP2_INVALID_ARG;
+  esmp2_handle h = new (std::nothrow) esmp2_handle_();
+  if (!h) return ESMP2_OOM;
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  *out = h;
+  return ESMP2_OK;
+}
+
+esmp2_status esmp2_destroy(esmp2_handle h) {
+  if (!h) return ESMP2_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  release(h);
+  delete h;
+  return ESMP2_OK;
+}
+
+const char* esmp2_last_error(esmp2_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A, const double* B, double* C) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (m < 0 || n < 0 || k < 0 || (!A && m * k) || (!B && k * n) || (!C && m * n))
+    return fail(h, ESMP2_INVALID_ARG, "bad gemm arguments");
+  ESMP2_HIP(hipSetDevice(h->device));
+  GemmArgs g{};
+  g.A = A; g.B = B; g.C = C; g.M = m; g.N = n; g.K = k;
+  g.sAi = k; g.sAk = 1; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1.0; g.beta = 0.0;
+  ESMP2_HIP(gemm(h->stream, 1, g));
+  return ESMP2_OK;
+}
+
+esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* F,
+                               const double* B, const double* C, int spin, int n_top) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (!F || !B || !C) return fail(h, ESMP2_INVALID_ARG, "null input pointer");
+  if (n_occ < 2 || n_vir < n_occ || n_aux < 1)
+    return fail(h, ESMP2_INVALID_ARG, "need 2 <= n_occ <= n_vir and n_aux >= 1");
+  if (n_occ > 64 || (int64_t)n_occ * n_vir > 8192 || n_vir > 196)
+    return fail(h, ESMP2_UNSUPPORTED, "sizes beyond n_occ <= 64, n_occ*n_vir <= 8192, n_vir <= 196");
+  if (spin != 0) return fail(h, ESMP2_UNSUPPORTED, "only the singlet (spin = 0) is implemented");
+  if (n_top != 1) return fail(h, ESMP2_UNSUPPORTED, "only n_top = 1 (ESMP2-TOP(1)) is implemented");
+  ESMP2_HIP(hipSetDevice(h->device));
+  ESMP2_HIP(hipStreamSynchronize(h->stream));
+  release(h);
+  Dims d = make_dims(n_occ, n_vir, n_aux);
+  h->d = d;
+  const int no = n_occ, nv = n_vir, n = d.n, na = n_aux, mv = d.mv;
+  const int64_t namp = d.off[7];
+  const int P = (nv + 1) / 2 * 2;
+  bool ok = dalloc(h, &h->F, (size_t)n * n) && dalloc(h, &h->B, (size_t)na * n * n) &&
+            dalloc(h, &h->C, (size_t)no * nv) && dalloc(h, &h->lam, no) && dalloc(h, &h->U, no * no) &&
+            dalloc(h, &h->V, (size_t)nv * no) && dalloc(h, &h->Wm, (size_t)nv * no) && dalloc(h, &h->G, no * no) &&
+            dalloc(h, &h->M, (size_t)nv * nv) && dalloc(h, &h->rot, (size_t)2 * 20 * (P - 1) * (P / 2)) &&
+            dalloc(h, &h->evals, nv) && dalloc(h, &h->Z, (size_t)nv * nv) && dalloc(h, &h->R, (size_t)n * n) &&
+            dalloc(h, &h->avo, nv) && dalloc(h, &h->Ft, (size_t)n * n) &&
+            dalloc(h, &h->T, std::max((size_t)na * no * nv, (size_t)n * n)) &&
+            dalloc(h, &h->Bov, (size_t)na * no * nv) && dalloc(h, &h->Bvt, (size_t)na * nv * no) &&
+            dalloc(h, &h->Boo, (size_t)na * no * no) && dalloc(h, &h->iinfo, 8) && dalloc(h, &h->fo, no * no) &&
+            dalloc(h, &h->fv, (size_t)nv * nv) && dalloc(h, &h->fov, (size_t)no * nv) && dalloc(h, &h->eo, no) &&
+            dalloc(h, &h->ev, nv) && dalloc(h, &h->Fd, (size_t)mv * mv) && dalloc(h, &h->Fl, (size_t)mv * mv) &&
+            dalloc(h, &h->sc_rot, 8) && dalloc(h, &h->fphi, (size_t)no * nv) &&
+            dalloc(h, &h->X, (size_t)na * no * nv) && dalloc(h, &h->Vint, (size_t)no * nv * no * nv) &&
+            dalloc(h, &h->Mint, (size_t)no * nv * no * nv) && dalloc(h, &h->b, namp) &&
+            dalloc(h, &h->dinv, namp) && dalloc(h, &h->blockmin, nblk(namp)) &&
+            dalloc(h, &h->partial, (size_t)4 * PCG_BLOCKS) && dalloc(h, &h->sc, SC_N) &&
+            dalloc(h, &h->S, (size_t)no * no * nv * nv) &&
+            dalloc(h, &h->side, (size_t)nv * (3 * d.npo1 + 2 * d.npo + 3 * d.npo + 5 * (no - 1) * (no - 1))) &&
+            dalloc(h, &h->side_tr, (size_t)nv * (d.npo + (no - 1) * (no - 1))) &&
+            dalloc(h, &h->x, namp) && dalloc(h, &h->r, namp) && dalloc(h, &h->p, namp) && dalloc(h, &h->q, namp);
+  if (!ok) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
+  // vv job table
+  std::vector<int2> jobs;
+  int nbat[7] = {d.npo, no * no, d.npo1, d.npo, d.npo, (no - 1) * (no - 1), (no - 1) * (no - 1)};
+  for (int bx = 0; bx < 7; ++bx)
+    for (int k = 0; k < nbat[bx]; ++k) jobs.push_back(make_int2(bx, k));
+  h->njobs = (int)jobs.size();
+  if (!dalloc(h, &h->jobs, jobs.size())) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
+  ESMP2_HIP(hipMemcpyAsync(h->jobs, jobs.data(), jobs.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
+  ESMP2_HIP(hipMemcpyAsync(h->F, F, sizeof(double) * n * n, hipMemcpyDefault, h->stream));
+  ESMP2_HIP(hipMemcpyAsync(h->B, B, sizeof(double) * (size_t)na * n * n, hipMemcpyDefault, h->stream));
+  ESMP2_HIP(hipMemcpyAsync(h->C, C, sizeof(double) * no * nv, hipMemcpyDefault, h->stream));
+  // NaN / Inf check
+  int* bad = h->iinfo;
+  ESMP2_HIP(hipMemsetAsync(bad, 0, sizeof(int), h->stream));
+  hipLaunchKernelGGL(k_finite, dim3(256), dim3(256), 0, h->stream, h->F, (int64_t)n * n, bad);
+  hipLaunchKernelGGL(k_finite, dim3(1024), dim3(256), 0, h->stream, h->B, (int64_t)na * n * n, bad);
+  hipLaunchKernelGGL(k_finite, dim3(64), dim3(256), 0, h->stream, h->C, (int64_t)no * nv, bad);
+  int hbad = 0;
+  ESMP2_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  ESMP2_HIP(hipStreamSynchronize(h->stream));
+  if (hbad) { release(h); return fail(h, ESMP2_INVALID_ARG, "NaN or Inf in F, B or C"); }
+  h->state = 1;
+  return ESMP2_OK;
+}
+
+esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (h->state < 1) return fail(h, ESMP2_BAD_ORDER, "esmp2_set_problem first");
+  ESMP2_HIP(hipSetDevice(h->device));
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv, n = d.n, na = d.naux, mv = d.mv;
+  hipStream_t s = h->stream;
+  // SVD of C
+  size_t lds = sizeof(double) * (no * nv + no * no);
+  ESMP2_HIP(hipFuncSetAttribute((const void*)k_svd_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_svd_jacobi, dim3(1), dim3(1024), lds, s, h->C, no, nv, h->lam, h->U, h->V, h->iinfo);
+  // semicanonical AVOs: eigenvectors of M = P F_vv P + shift V V^T
+  hipLaunchKernelGGL(k_fv_times_v, dim3(nblk(nv * no)), dim3(256), 0, s, h->F, n, no, nv, h->V, h->Wm);
+  hipLaunchKernelGGL(k_vt_w, dim3(nblk(no * no)), dim3(256), 0, s, h->V, h->Wm, no, nv, h->G);
+  hipLaunchKernelGGL(k_shift, dim3(1), dim3(256), 0, s, h->F, n, no, h->sc_rot + 4);
+  double shift = 0;
+  ESMP2_HIP(hipMemcpyAsync(&shift, h->sc_rot + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipStreamSynchronize(s));
+  hipLaunchKernelGGL(k_build_m, dim3(nblk(nv * nv)), dim3(256), 0, s, h->F, n, no, nv, h->V, h->Wm, h->G, shift,
+                     h->M);
+  size_t lds2 = sizeof(double) * (size_t)nv * (nv + 1) / 2;
+  ESMP2_HIP(hipFuncSetAttribute((const void*)k_eig_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+  hipLaunchKernelGGL(k_eig_jacobi, dim3(1), dim3(1024), lds2, s, h->M, nv, 20, h->rot, h->evals, h->iinfo + 1);
+  hipLaunchKernelGGL(k_jacobi_vectors, dim3(nv), dim3(64), sizeof(double) * nv, s, h->rot, nv, h->iinfo + 1, h->Z);
+  hipLaunchKernelGGL(k_assemble_r, dim3(1), dim3(256), 0, s, h->U, h->V, h->Z, h->evals, no, nv, h->R, h->avo);
+  // F~ = R^T F R
+  GemmArgs g{};
+  g.A = h->F; g.B = h->R; g.C = h->T; g.M = n; g.N = n; g.K = n;
+  g.sAi = n; g.sAk = 1; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));   // T = F R
+  g = GemmArgs{};
+  g.A = h->R; g.B = h->T; g.C = h->Ft; g.M = n; g.N = n; g.K = n;
+  g.sAi = 1; g.sAk = n; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));   // Ft = R^T T
+  hipLaunchKernelGGL(k_topfock, dim3(nblk((int64_t)mv * mv > n * n ? (int64_t)mv * mv : (int64_t)n * n)), dim3(256),
+                     0, s, h->Ft, h->lam, no, nv, mv, h->fo, h->fv, h->fov, h->eo, h->ev, h->Fd, h->Fl, h->sc_rot);
+  // B~ blocks: Bov = U^T B_ov W, Bvt = W^T B_vv W[:, :no], Boo = U^T B_oo U
+  const int64_t nn = (int64_t)n * n;
+  // T[Q] (no x nv) = B[Q][occ, vir] W
+  g = GemmArgs{};
+  g.A = h->B + no; g.B = h->R + (int64_t)no * n + no; g.C = h->T; g.M = no; g.N = nv; g.K = nv;
+  g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1;
+  g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, na, g));
+  g = GemmArgs{};
+  g.A = h->R; g.B = h->T; g.C = h->Bov; g.M = no; g.N = nv; g.K = no;
+  g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)no * nv; g.sBk = nv; g.sBj = 1;
+  g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, na, g));
+  // T[Q] (nv x no) = B[Q][vir, vir] W[:, :no]
+  g = GemmArgs{};
+  g.A = h->B + (int64_t)no * n + no; g.B = h->R + (int64_t)no * n + no; g.C = h->T; g.M = nv; g.N = no; g.K = nv;
+  g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1;
+  g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, na, g));
+  g = GemmArgs{};
+  g.A = h->R + (int64_t)no * n + no; g.B = h->T; g.C = h->Bvt; g.M = nv; g.N = no; g.K = nv;
+  g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)nv * no; g.sBk = no; g.sBj = 1;
+  g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, na, g));
+  // T[Q] (no x no) = B[Q][occ, occ] U ; Boo = U^T T
+  g = GemmArgs{};
+  g.A = h->B; g.B = h->R; g.C = h->T; g.M = no; g.N = no; g.K = no;
+  g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)no * no; g.sCi = no; g.sCj = 1;
+  g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, na, g));
+  g = GemmArgs{};
+  g.A = h->R; g.B = h->T; g.C = h->Boo; g.M = no; g.N = no; g.K = no;
+  g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)no * no; g.sBk = no; g.sBj = 1;
+  g.sCb = (int64_t)no * no; g.sCi = no; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, na, g));
+  double sc[3];
+  int info[2];
+  ESMP2_HIP(hipMemcpyAsync(sc, h->sc_rot, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipMemcpyAsync(info, h->iinfo, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  if (lambda_out) ESMP2_HIP(hipMemcpyAsync(lambda_out, h->lam, no * sizeof(double), hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipStreamSynchronize(s));
+  ESMP2_HIP(hipGetLastError());
+  h->omega = sc[0]; h->kappa = sc[1]; h->e0 = sc[2];
+  h->svd_sweeps = info[0]; h->eig_sweeps = info[1];
+  h->state = 2;
+  h->have_rhs = false;
+  return ESMP2_OK;
+}
+
+esmp2_status esmp2_space(esmp2_handle h, int64_t* n_amp, int64_t* box_offsets) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (h->state < 1) return fail(h, ESMP2_BAD_ORDER, "esmp2_set_problem first");
+  if (n_amp) *n_amp = h->d.off[7];
+  if (box_offsets) for (int k = 0; k < 8; ++k) box_offsets[k] = h->d.off[k];
+  return ESMP2_OK;
+}
+
+static esmp2_status build_rhs(esmp2_handle h) {
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
+  const int64_t namp = d.off[7];
+  hipStream_t s = h->stream;
+  hipLaunchKernelGGL(k_fphi, dim3(nblk(nov)), dim3(256), 0, s, h->Ft, h->Bov, h->Bvt, h->Boo, h->lam, no, nv, na,
+                     h->fphi);
+  hipLaunchKernelGGL(k_make_x, dim3(nblk((int64_t)na * nov)), dim3(256), 0, s, h->Bvt, h->Boo, h->lam, no, nv, na,
+                     h->X);
+  GemmArgs g{};
+  // V[(ia),(jb)] = sum_Q Bov[Q][(ia)] Bov[Q][(jb)]
+  g.A = h->Bov; g.B = h->Bov; g.C = h->Vint; g.M = nov; g.N = nov; g.K = na;
+  g.sAi = 1; g.sAk = nov; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));
+  g.A = h->X; g.C = h->Mint;
+  ESMP2_HIP(gemm(s, 1, g));
+  RhsArgs ra{d, h->Vint, h->Mint, h->fphi, h->lam, h->b};
+  hipLaunchKernelGGL(k_rhs, dim3(nblk(namp)), dim3(256), 0, s, ra);
+  DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv, h->blockmin};
+  hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
+  hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
+  // E2_S
+  E2sArgs ea{d, h->Vint, h->lam, h->eo, h->ev, h->omega, h->partial};
+  const int NB = 1024;
+  hipLaunchKernelGGL(k_e2s_same, dim3(NB), dim3(256), 0, s, ea);
+  ea.partial = h->partial + NB;
+  hipLaunchKernelGGL(k_e2s_mixed_a, dim3(NB), dim3(256), 0, s, ea);
+  ea.partial = h->partial + 2 * NB;
+  hipLaunchKernelGGL(k_e2s_mixed_b, dim3(NB), dim3(256), 0, s, ea);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, h->partial, 3 * NB, h->sc + SC_TMP + 1, -1.0);
+  double tmp[2];
+  ESMP2_HIP(hipMemcpyAsync(tmp, h->sc + SC_TMP, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipStreamSynchronize(s));
+  ESMP2_HIP(hipGetLastError());
+  h->e2s = tmp[1];
+  if (!(tmp[0] > 0.0)) return fail(h, ESMP2_NOT_SPD, "a diagonal denominator of the first-order space is <= 0");
+  h->have_rhs = true;
+  h->state = 3;
+  return ESMP2_OK;
+}
+
+esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* e2_s) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
+  ESMP2_HIP(hipSetDevice(h->device));
+  esmp2_status st = build_rhs(h);
+  if (st != ESMP2_OK) return st;
+  if (b_out)
+    ESMP2_HIP(hipMemcpyAsync(b_out, h->b, sizeof(double) * h->d.off[7], hipMemcpyDeviceToDevice, h->stream));
+  if (e0) *e0 = h->e0;
+  if (e2_s) *e2_s = h->e2s;
+  return ESMP2_OK;
+}
+
+// y = A x (FP64), all on the handle's stream
+static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv;
+  hipStream_t s = h->stream;
+  hipLaunchKernelGGL(k_sym_s2, dim3(nblk((int64_t)no * no * nv * nv)), dim3(256), 0, s, d, x, h->S);
+  // side contractions
+  SideArgs sa{};
+  sa.d = d; sa.x = x; sa.fov = h->fov;
+  double* p = h->side;
+  auto take = [&](int64_t rows) { double* r = p; p += rows * nv; return r; };
+  sa.t3_t = take(d.npo1); sa.t3_p1 = take(d.npo1); sa.t3_p2 = take(d.npo1);
+  sa.h11_p1 = take(d.npo); sa.h11_p2 = take(d.npo);
+  sa.h12_t = take(d.npo); sa.h12_u1 = take(d.npo); sa.h12_u2 = take(d.npo);
+  const int n2 = (no - 1) * (no - 1);
+  sa.h21_t = take(n2); sa.h21_k = take(n2);
+  sa.h22_ut = take(n2); sa.h22_i = take(n2); sa.h22_uk = take(n2);
+  const int nside = d.npo1 + 2 * d.npo + 2 * n2;
+  hipLaunchKernelGGL(k_side, dim3(nside), dim3(256), 0, s, sa);
+  // virtual-pair Sylvester products (+ diagonal constants)
+  VVArgs va{d, x, h->S, y, h->Fd, h->Fl, h->side_tr, h->jobs};
+  const int tiles = d.mv / 16;
+  int tw = (tiles + 1) / 2;
+  if (tw > 5) tw = 5;
+  const int nb = (d.mv + 32 * tw - 1) / (32 * tw);
+  dim3 grid(h->njobs, nb, nb);
+  switch (tw) {
+    case 1: hipLaunchKernelGGL(k_vv<1>, grid, dim3(256), 0, s, va); break;
+    case 2: hipLaunchKernelGGL(k_vv<2>, grid, dim3(256), 0, s, va); break;
+    case 3: hipLaunchKernelGGL(k_vv<3>, grid, dim3(256), 0, s, va); break;
+    case 4: hipLaunchKernelGGL(k_vv<4>, grid, dim3(256), 0, s, va); break;
+    default: hipLaunchKernelGGL(k_vv<5>, grid, dim3(256), 0, s, va); break;
+  }
+  GatherArgs ga{};
+  ga.d = d; ga.x = x; ga.S = h->S; ga.y = y; ga.fo = h->fo; ga.fv = h->fv; ga.fov = h->fov; ga.side_tr = h->side_tr;
+  ga.t3_t = sa.t3_t; ga.t3_p1 = sa.t3_p1; ga.t3_p2 = sa.t3_p2; ga.h11_p1 = sa.h11_p1; ga.h11_p2 = sa.h11_p2;
+  ga.h12_t = sa.h12_t; ga.h12_u1 = sa.h12_u1; ga.h12_u2 = sa.h12_u2; ga.h21_t = sa.h21_t; ga.h21_k = sa.h21_k;
+  ga.h22_ut = sa.h22_ut; ga.h22_i = sa.h22_i; ga.h22_uk = sa.h22_uk;
+  hipLaunchKernelGGL(k_gather, dim3(nblk(d.off[7])), dim3(256), 0, s, ga);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
+  if (!x || !y) return fail(h, ESMP2_INVALID_ARG, "null vector");
+  if (x == y) return fail(h, ESMP2_INVALID_ARG, "x and y must not overlap");
+  ESMP2_HIP(hipSetDevice(h->device));
+  if (precision == ESMP2_FP64) return sigma64(h, (const double*)x, (double*)y);
+  return fail(h, ESMP2_UNSUPPORTED, "precision not implemented");
+}
+
+// weighted dot product into h->sc[slot] (stream ordered)
+static void wdot(esmp2_handle h, const double* x, const double* y, int slot) {
+  const Dims& d = h->d;
+  hipLaunchKernelGGL(k_dot, dim3(PCG_BLOCKS), dim3(256), 0, h->stream, x, y, d.off[7], d.off[1], d.off[2],
+                     h->partial);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, h->stream, h->partial, PCG_BLOCKS, h->sc, slot);
+}
+
+esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (!opts || !res) return fail(h, ESMP2_INVALID_ARG, "null opts/result");
+  if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
+  if (!(opts->tol > 0) || opts->max_iter < 1) return fail(h, ESMP2_INVALID_ARG, "tol > 0 and max_iter >= 1");
+  if (opts->precision != ESMP2_FP64) return fail(h, ESMP2_UNSUPPORTED, "precision not implemented");
+  ESMP2_HIP(hipSetDevice(h->device));
+  memset(res, 0, sizeof(*res));
+  if (!h->have_rhs) {
+    esmp2_status st = build_rhs(h);
+    if (st != ESMP2_OK) { res->status = st; return st; }
+  }
+  const Dims& d = h->d;
+  const int64_t n = d.off[7];
+  hipStream_t s = h->stream;
+  const unsigned NB = PCG_BLOCKS;
+  // ||b||_W
+  wdot(h, h->b, h->b, SC_BB);
+  if (opts->x0) {
+    ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    esmp2_status st = sigma64(h, h->x, h->q);
+    if (st != ESMP2_OK) return st;
+    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, h->b, h->q, h->r, h->p, h->dinv, n, d.off[1], d.off[2],
+                       h->partial);
+  } else {
+    ESMP2_HIP(hipMemsetAsync(h->x, 0, sizeof(double) * n, s));
+    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, h->b, (const double*)nullptr, h->r, h->p, h->dinv, n,
+                       d.off[1], d.off[2], h->partial);
+  }
+  hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);  // RHO, then PQ slot
+  // k_finish wrote rho into SC_RHO and rr into SC_RHO+1 = SC_PQ; move rr
+  double hs[SC_N];
+  ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipStreamSynchronize(s));
+  const double bn = sqrt(hs[SC_BB]);
+  double rel = sqrt(hs[SC_PQ]) / bn;
+  int it = 0;
+  esmp2_status status = ESMP2_OK;
+  while (rel > opts->tol && it < opts->max_iter) {
+    esmp2_status st = sigma64(h, h->p, h->q);
+    if (st != ESMP2_OK) return st;
+    wdot(h, h->p, h->q, SC_PQ);
+    hipLaunchKernelGGL(k_update_xr, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, h->dinv, n, d.off[1],
+                       d.off[2], h->sc, h->partial);
+    hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);  // RHO_NEW, RR
+    ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+    ESMP2_HIP(hipStreamSynchronize(s));
+    if (!(hs[SC_PQ] > 0.0)) { status = ESMP2_NOT_SPD; h->err = "p.Ap <= 0 in conjugate gradient"; break; }
+    ++it;
+    rel = sqrt(hs[SC_RR]) / bn;
+    if (opts->resid_hist && it <= opts->max_iter) opts->resid_hist[it - 1] = rel;
+    if (rel <= opts->tol) break;
+    hipLaunchKernelGGL(k_update_p, dim3(NB), dim3(256), 0, s, h->p, h->r, h->dinv, n, h->sc);
+    hipLaunchKernelGGL(k_roll_rho, dim3(1), dim3(64), 0, s, h->sc);
+  }
+  if (status == ESMP2_OK && rel > opts->tol) { status = ESMP2_NOT_CONVERGED; h->err = "max_iter reached"; }
+  // E2 (Hylleraas): <b,x>_W - <x,r>_W
+  wdot(h, h->b, h->x, SC_BX);
+  wdot(h, h->x, h->r, SC_XR);
+  ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+  if (opts->x_out) ESMP2_HIP(hipMemcpyAsync(opts->x_out, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  ESMP2_HIP(hipStreamSynchronize(s));
+  ESMP2_HIP(hipGetLastError());
+  res->e2_dl = hs[SC_BX] - hs[SC_XR];
+  res->e2_s = h->e2s;
+  res->e2 = res->e2_dl + res->e2_s;
+  res->e0 = h->e0;
+  res->rel_resid = rel;
+  res->iterations = it;
+  res->outer = 0;
+  res->status = status;
+  return status;
+}
+
+}  // extern "C"

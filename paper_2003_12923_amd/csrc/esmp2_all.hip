@@ -1,0 +1,6 @@
+// Single translation unit of libesmp2.
+#include "linalg.hip"
+#include "rhs.hip"
+#include "sigma.hip"
+#include "pcg.hip"
+#include "api.hip"

@@ -1,0 +1,381 @@
+// Right-hand side b_mu = <mu|H|Psi0> on doubles + L-triples, the diagonal
+// denominators D_mu = <mu|F|mu> - E0, and the directly inverted S-triple
+// energy E2_S = -sum_S b^2/D (paper Sec. II.B-II.D).
+//
+// Reference Psi0 = sum_l c_l (a+_{l' u} a_{l u} + a+_{l' d} a_{l d})|Phi>,
+// c_l = lambda_l / sqrt(2), TOP basis (t = occupied 0, t' = virtual 0).
+// Singles -> doubles couple through f^Phi (Fock matrix of the closed shell)
+// and the integrals with one TOP index; singles -> triples through the
+// antisymmetrised (ov|ov) integrals.  Integral blocks (DF form):
+//   V[(i,a),(j,b)] = (ia|jb)
+//   M[(i,a),(j,b)] = c_i (a i'|b j) - c_a (a_o i|b j)   (a_o: occupied a, a < n_occ)
+#include "common.h"
+#include "reduce.h"
+#include <math.h>
+
+namespace esmp2 {
+
+// f^Phi_ov = F~_ov - G[gamma - gamma_Phi]_ov, G[g]_pq = sum_rs g_rs((pq|rs) - (ps|rq)/2),
+// gamma - gamma_Phi = diag(-lam_l^2 on l, +lam_l^2 on l').
+__global__ void k_fphi(const double* Ft, const double* Bov, const double* Bvt, const double* Boo,
+                       const double* lam, int no, int nv, int naux, double* fphi) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= no * nv) return;
+  int i = e / nv, a = e % nv;
+  int n = no + nv;
+  double J = 0, Kv = 0, Ko = 0;
+  for (int Q = 0; Q < naux; ++Q) {
+    const double* bov = Bov + (int64_t)Q * no * nv;
+    const double* bvt = Bvt + (int64_t)Q * nv * no;
+    const double* boo = Boo + (int64_t)Q * no * no;
+    double d = 0, kv = 0, ko = 0;
+    for (int l = 0; l < no; ++l) {
+      double w = lam[l] * lam[l];
+      d += w * (bvt[l * no + l] - boo[l * no + l]);
+      kv += w * bov[i * nv + l] * bvt[a * no + l];
+      ko += w * boo[i * no + l] * bov[l * nv + a];
+    }
+    J += d * bov[i * nv + a];
+    Kv += kv;
+    Ko += ko;
+  }
+  fphi[e] = Ft[i * n + no + a] - (J - 0.5 * Kv + 0.5 * Ko);
+}
+
+// X[Q][(i,a)] = c_i Bvt[Q][a][i] - c_a Boo[Q][a][i]  (second term only for a < n_occ)
+__global__ void k_make_x(const double* Bvt, const double* Boo, const double* lam, int no, int nv,
+                         int naux, double* X) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)naux * no * nv) return;
+  int Q = e / (no * nv);
+  int r = e % (no * nv);
+  int i = r / nv, a = r % nv;
+  const double s2 = 0.70710678118654752440;
+  double v = lam[i] * s2 * Bvt[((int64_t)Q * nv + a) * no + i];
+  if (a < no) v -= lam[a] * s2 * Boo[((int64_t)Q * no + a) * no + i];
+  X[e] = v;
+}
+
+struct RhsArgs {
+  Dims d;
+  const double* V;      // (ia|jb)
+  const double* M;      // c_i (a i'|b j) - c_a (a_o i|b j)
+  const double* fphi;   // no x nv
+  const double* lam;
+  double* b;
+};
+
+// Box and local index of a flat amplitude index.
+__device__ inline int box_of(const Dims& d, int64_t g, int64_t& loc) {
+  int k = 0;
+  while (k < 6 && g >= d.off[k + 1]) ++k;
+  loc = g - d.off[k];
+  return k;
+}
+
+__global__ void k_rhs(RhsArgs A) {
+  const Dims& d = A.d;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.off[7]) return;
+  int64_t loc;
+  int box = box_of(d, g, loc);
+  const int no = d.no, nv = d.nv, nov = no * nv;
+  const double s2 = 0.70710678118654752440;
+  auto c = [&](int l) -> double { return A.lam[l] * s2; };
+  auto V = [&](int i, int a, int j, int b) -> double { return A.V[(int64_t)(i * nv + a) * nov + j * nv + b]; };
+  // m[i,j,a,b] = c_i d(a,i) fphi[j][b] + M[(i,a),(j,b)]
+  auto m = [&](int i, int j, int a, int b) -> double {
+    double v = A.M[(int64_t)(i * nv + a) * nov + j * nv + b];
+    if (a == i) v += c(i) * A.fphi[j * nv + b];
+    return v;
+  };
+  double out = 0.0;
+  const double c0 = c(0);
+  switch (box) {
+    case B_T2: {
+      int po = loc / d.npv, pv = loc % d.npv, i, j, a, b;
+      tri_pq(po, no, i, j); tri_pq(pv, nv, a, b);
+      out = m(i, j, a, b) - m(j, i, a, b) - m(i, j, b, a) + m(j, i, b, a);
+      break;
+    }
+    case B_S2: {
+      int i = loc / (nov * nv), r = loc % (nov * nv);
+      int j = r / (nv * nv); r %= nv * nv;
+      int a = r / nv, b = r % nv;
+      out = m(i, j, a, b) + m(j, i, b, a);
+      break;
+    }
+    case B_T3: {
+      int po = loc / d.npv1, pv = loc % d.npv1, j, k, b, cc;
+      tri_pq(po, no - 1, j, k); tri_pq(pv, nv - 1, b, cc);
+      ++j; ++k; ++b; ++cc;
+      auto E = [&](int kk, int x) { return V(0, 0, kk, x) - V(kk, 0, 0, x); };
+      out = c0 * (V(j, b, k, cc) - V(k, b, j, cc));
+      if (b == j) out += c(j) * E(k, cc);
+      if (b == k) out -= c(k) * E(j, cc);
+      if (cc == j) out -= c(j) * E(k, b);
+      if (cc == k) out += c(k) * E(j, b);
+      break;
+    }
+    case B_H11: {
+      int po = loc / d.npv, pv = loc % d.npv, j, k, b, cc;
+      tri_pq(po, no, j, k); tri_pq(pv, nv, b, cc);
+      out = c0 * (V(j, b, k, cc) - V(k, b, j, cc));
+      if (b == j) out += c(j) * V(0, 0, k, cc);
+      if (b == k) out -= c(k) * V(0, 0, j, cc);
+      if (cc == j) out -= c(j) * V(0, 0, k, b);
+      if (cc == k) out += c(k) * V(0, 0, j, b);
+      break;
+    }
+    case B_H12: {
+      int m1 = nv - 1;
+      int po = loc / (m1 * m1), r = loc % (m1 * m1), j, k;
+      tri_pq(po, no, j, k);
+      int a = r / m1 + 1, cc = r % m1 + 1;
+      if (j == 0) out += c0 * V(0, a, k, cc);
+      if (cc == j) out -= c(j) * V(0, a, k, 0);
+      if (k == 0) out -= c0 * V(0, a, j, cc);
+      if (cc == k) out += c(k) * V(0, a, j, 0);
+      break;
+    }
+    case B_H21: {
+      int o = loc / d.npv, pv = loc % d.npv, b, cc;
+      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+      tri_pq(pv, nv, b, cc);
+      if (b == 0) out += c0 * V(i, 0, k, cc);
+      if (b == k) out -= c(k) * V(i, 0, 0, cc);
+      if (cc == 0) out -= c0 * V(i, 0, k, b);
+      if (cc == k) out += c(k) * V(i, 0, 0, b);
+      break;
+    }
+    default: {  // B_H22
+      int m1 = nv - 1;
+      int o = loc / (m1 * m1), r = loc % (m1 * m1);
+      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+      int a = r / m1 + 1, cc = r % m1 + 1;
+      if (a == i) out += c(i) * (V(0, 0, k, cc) - V(k, 0, 0, cc));
+      out += c0 * V(i, a, k, cc);
+      if (cc == k) out += c(k) * V(i, a, 0, 0);
+      break;
+    }
+  }
+  A.b[g] = out;
+}
+
+// Diagonal D_mu = (sum of particle minus hole orbital energies) - omega and its
+// inverse; also records the minimum (for the NOT_SPD check) per block.
+struct DiagArgs {
+  Dims d;
+  const double* eo;     // TOP-basis occupied orbital energies F~_ii
+  const double* ev;     // TOP-basis virtual orbital energies F~_aa
+  double omega;
+  double* dinv;
+  double* blockmin;
+};
+
+__device__ inline double diag_of(const Dims& d, int box, int64_t loc, const double* eo, const double* ev,
+                                 double om) {
+  const int no = d.no, nv = d.nv;
+  const double base = ev[0] - eo[0] - om;
+  switch (box) {
+    case B_T2: {
+      int po = loc / d.npv, pv = loc % d.npv, i, j, a, b;
+      tri_pq(po, no, i, j); tri_pq(pv, nv, a, b);
+      return ev[a] + ev[b] - eo[i] - eo[j] - om;
+    }
+    case B_S2: {
+      int nov = no * nv;
+      int i = loc / (nov * nv), r = loc % (nov * nv);
+      int j = r / (nv * nv); r %= nv * nv;
+      return ev[r / nv] + ev[r % nv] - eo[i] - eo[j] - om;
+    }
+    case B_T3: {
+      int po = loc / d.npv1, pv = loc % d.npv1, j, k, b, c;
+      tri_pq(po, no - 1, j, k); tri_pq(pv, nv - 1, b, c);
+      return base + ev[b + 1] + ev[c + 1] - eo[j + 1] - eo[k + 1];
+    }
+    case B_H11: {
+      int po = loc / d.npv, pv = loc % d.npv, j, k, b, c;
+      tri_pq(po, no, j, k); tri_pq(pv, nv, b, c);
+      return base + ev[b] + ev[c] - eo[j] - eo[k];
+    }
+    case B_H12: {
+      int m1 = nv - 1, po = loc / (m1 * m1), r = loc % (m1 * m1), j, k;
+      tri_pq(po, no, j, k);
+      return base + ev[r / m1 + 1] + ev[r % m1 + 1] - eo[j] - eo[k];
+    }
+    case B_H21: {
+      int o = loc / d.npv, pv = loc % d.npv, b, c;
+      tri_pq(pv, nv, b, c);
+      return base + ev[b] + ev[c] - eo[o / (no - 1) + 1] - eo[o % (no - 1) + 1];
+    }
+    default: {
+      int m1 = nv - 1, o = loc / (m1 * m1), r = loc % (m1 * m1);
+      return base + ev[r / m1 + 1] + ev[r % m1 + 1] - eo[o / (no - 1) + 1] - eo[o % (no - 1) + 1];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_diag(DiagArgs A) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double mn = 1e300;
+  if (g < A.d.off[7]) {
+    int64_t loc;
+    int box = box_of(A.d, g, loc);
+    double D = diag_of(A.d, box, loc, A.eo, A.ev, A.omega);
+    A.dinv[g] = 1.0 / D;
+    mn = D;
+  }
+  // block minimum
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o));
+  __shared__ double ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) A.blockmin[blockIdx.x] = fmin(fmin(ws[0], ws[1]), fmin(ws[2], ws[3]));
+}
+
+__global__ void k_min_reduce(const double* v, int64_t n, double* out) {
+  double mn = 1e300;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) mn = fmin(mn, v[i]);
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o));
+  __shared__ double ws[16];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 1e300;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r = fmin(r, ws[k]);
+    out[0] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// E2_S.  Same-spin sector (up up up; doubled for down down down): triples
+// {l, j, k; l', b, c} enumerated by the smallest TOP l >= 1 they contain, with
+// no smaller TOP m (m in {j,k} and m' in {b,c}); t = 0 is therefore excluded.
+// b = sum over contained TOP pairs (A_p = I_q') of (-1)^{p+q} c_{I_q} <A..||I..>.
+// ---------------------------------------------------------------------------
+struct E2sArgs {
+  Dims d;
+  const double* V; const double* lam; const double* eo; const double* ev;
+  double omega;
+  double* partial;      // one per block
+};
+
+__device__ inline void sort3(int& x, int& y, int& z) {
+  if (x > y) { int t = x; x = y; y = t; }
+  if (y > z) { int t = y; y = z; z = t; }
+  if (x > y) { int t = x; x = y; y = t; }
+}
+
+__global__ __launch_bounds__(256) void k_e2s_same(E2sArgs A) {
+  const Dims& d = A.d;
+  const int no = d.no, nv = d.nv, nov = no * nv;
+  const int64_t per_l = (int64_t)d.npo1 * d.npv1;
+  const int64_t total = per_l * (no - 1);
+  const double s2 = 0.70710678118654752440;
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int l = (int)(g / per_l) + 1;
+    int64_t r = g % per_l;
+    int jr, kr, br, cr;
+    tri_pq((int)(r / d.npv1), no - 1, jr, kr);
+    tri_pq((int)(r % d.npv1), nv - 1, br, cr);
+    int j = jr + (jr >= l), k = kr + (kr >= l), b = br + (br >= l), c = cr + (cr >= l);
+    if ((j < l && (j == b || j == c)) || (k < l && (k == b || k == c))) continue;
+    int I[3] = {l, j, k}, P[3] = {l, b, c};
+    sort3(I[0], I[1], I[2]);
+    sort3(P[0], P[1], P[2]);
+    double bv = 0.0;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) {
+        if (P[p] != I[q]) continue;
+        int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
+        int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
+        double anti = A.V[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2] -
+                      A.V[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2];
+        double sg = ((p + q) & 1) ? -1.0 : 1.0;
+        bv += sg * A.lam[I[q]] * s2 * anti;
+      }
+    double D = A.ev[P[0]] + A.ev[P[1]] + A.ev[P[2]] - A.eo[I[0]] - A.eo[I[1]] - A.eo[I[2]] - A.omega;
+    acc += 2.0 * bv * bv / D;
+  }
+  double s = block_sum(acc);
+  if (threadIdx.x == 0) A.partial[blockIdx.x] = s;
+}
+
+// Mixed sector (up; down down), doubled for its spin flip.  Case A: the up pair
+// is a TOP (a = i >= 1), down pairs arbitrary.  Case B: a != i, the down pairs
+// share a TOP l (smallest such l), holes {l, m}, particles {l', e}.  Triples
+// containing t (0 among the holes and 0 among the particles) are L, skipped.
+__device__ inline double b_mixed(const E2sArgs& A, int i, int a, int j, int k, int b, int c) {
+  const int nv = A.d.nv, nov = A.d.no * nv;
+  const double s2 = 0.70710678118654752440;
+  auto V = [&](int p, int x, int q, int y) { return A.V[(int64_t)(p * nv + x) * nov + q * nv + y]; };
+  double bv = 0.0;
+  if (a == i) bv += A.lam[i] * s2 * (V(j, b, k, c) - V(k, b, j, c));
+  if (b == j) bv += A.lam[j] * s2 * V(i, a, k, c);
+  if (b == k) bv -= A.lam[k] * s2 * V(i, a, j, c);
+  if (c == j) bv -= A.lam[j] * s2 * V(i, a, k, b);
+  if (c == k) bv += A.lam[k] * s2 * V(i, a, j, b);
+  return bv;
+}
+
+__global__ __launch_bounds__(256) void k_e2s_mixed_a(E2sArgs A) {
+  const Dims& d = A.d;
+  const int no = d.no;
+  const int64_t per_i = (int64_t)d.npo * d.npv;
+  const int64_t total = per_i * (no - 1);
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int i = (int)(g / per_i) + 1;
+    int64_t r = g % per_i;
+    int j, k, b, c;
+    tri_pq((int)(r / d.npv), no, j, k);
+    tri_pq((int)(r % d.npv), d.nv, b, c);
+    if ((j == 0 || k == 0) && (b == 0 || c == 0)) continue;     // contains t
+    double bv = b_mixed(A, i, i, j, k, b, c);
+    double D = A.ev[i] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+    acc += 2.0 * bv * bv / D;
+  }
+  double s = block_sum(acc);
+  if (threadIdx.x == 0) A.partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
+  const Dims& d = A.d;
+  const int no = d.no, nv = d.nv;
+  // index = (((i * nv + a) * no + l) * (no-1) + mr) * (nv-1) + er
+  const int64_t total = (int64_t)no * nv * no * (no - 1) * (nv - 1);
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = g;
+    int er = r % (nv - 1); r /= (nv - 1);
+    int mr = r % (no - 1); r /= (no - 1);
+    int l = r % no; r /= no;
+    int a = r % nv; r /= nv;
+    int i = (int)r;
+    if (a == i) continue;
+    int m = mr + (mr >= l), e = er + (er >= l);
+    if (m < l && e == m) continue;                                // smaller down TOP m
+    if ((i == 0 || l == 0 || m == 0) && (a == 0 || l == 0 || e == 0)) continue;   // contains t
+    int j = l < m ? l : m, k = l < m ? m : l;
+    int b = l < e ? l : e, c = l < e ? e : l;
+    double bv = b_mixed(A, i, a, j, k, b, c);
+    double D = A.ev[a] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+    acc += 2.0 * bv * bv / D;
+  }
+  double s = block_sum(acc);
+  if (threadIdx.x == 0) A.partial[blockIdx.x] = s;
+}
+
+__global__ void k_sum_partials(const double* v, int n, double* out, double scale) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += v[i];
+  double s = block_sum(acc);
+  if (threadIdx.x == 0) out[0] = scale * s;
+}
+
+}  // namespace esmp2

@@ -1,0 +1,464 @@
+// sigma = (H0 - E0) x on doubles + L-triples (paper Sec. II.C, modified Q F Q).
+//
+// The Fock operator acts on every index slot of every amplitude.  Per box:
+//   * virtual pair (the dominant N_o^2 N_v^3 work; the paper's hand-coded
+//     "mixed-spin L-triples x Fock" term is its largest part): a batched
+//     Sylvester product Y = F' X + X F' on matrix cores, F' = F_vv + c/2 with
+//     the box's diagonal constant c (-omega on doubles, f_t't' - f_tt - omega on
+//     L-triples), boxes with t' excluded embedded with a zero row/column;
+//   * occupied pair, box transfers (a pinned TOP index moved by one Fock
+//     element), doubles <-> L-triples couplings through f_ov: a per-element
+//     gather (plus per-batch side contractions over one virtual index).
+// S2 enters flip-symmetrised (S~ = (x + flip x)/2).
+#include "common.h"
+#include "mfma.h"
+#include "sigma.h"
+
+namespace esmp2 {
+
+// ---------------------------------------------------------------------------
+// amplitude lookups with antisymmetry (zero where the Pauli principle forbids)
+// ---------------------------------------------------------------------------
+struct Look {
+  Dims d;
+  const double* x;
+  const double* S;      // flip-symmetrised S2, dense [i][j][a][b]
+  __device__ double T2(int i, int j, int a, int b) const {
+    if (i == j || a == b) return 0.0;
+    double s = 1.0;
+    if (i > j) { int t = i; i = j; j = t; s = -s; }
+    if (a > b) { int t = a; a = b; b = t; s = -s; }
+    return s * x[d.off[B_T2] + (int64_t)tri_idx(i, j, d.no) * d.npv + tri_idx(a, b, d.nv)];
+  }
+  __device__ double T3(int j, int k, int b, int c) const {      // all indices >= 1
+    if (j == k || b == c) return 0.0;
+    double s = 1.0;
+    if (j > k) { int t = j; j = k; k = t; s = -s; }
+    if (b > c) { int t = b; b = c; c = t; s = -s; }
+    return s * x[d.off[B_T3] + (int64_t)tri_idx(j - 1, k - 1, d.no - 1) * d.npv1 + tri_idx(b - 1, c - 1, d.nv - 1)];
+  }
+  __device__ double H11(int j, int k, int b, int c) const {
+    if (j == k || b == c) return 0.0;
+    double s = 1.0;
+    if (j > k) { int t = j; j = k; k = t; s = -s; }
+    if (b > c) { int t = b; b = c; c = t; s = -s; }
+    return s * x[d.off[B_H11] + (int64_t)tri_idx(j, k, d.no) * d.npv + tri_idx(b, c, d.nv)];
+  }
+  __device__ double H12(int j, int k, int a, int c) const {     // a, c >= 1
+    if (j == k) return 0.0;
+    double s = 1.0;
+    if (j > k) { int t = j; j = k; k = t; s = -s; }
+    int m1 = d.nv - 1;
+    return s * x[d.off[B_H12] + ((int64_t)tri_idx(j, k, d.no) * m1 + (a - 1)) * m1 + (c - 1)];
+  }
+  __device__ double H21(int i, int k, int b, int c) const {     // i, k >= 1
+    if (b == c) return 0.0;
+    double s = 1.0;
+    if (b > c) { int t = b; b = c; c = t; s = -s; }
+    return s * x[d.off[B_H21] + ((int64_t)(i - 1) * (d.no - 1) + (k - 1)) * d.npv + tri_idx(b, c, d.nv)];
+  }
+  __device__ double H22(int i, int k, int a, int c) const {     // all >= 1
+    int m1 = d.nv - 1;
+    return x[d.off[B_H22] + (((int64_t)(i - 1) * (d.no - 1) + (k - 1)) * m1 + (a - 1)) * m1 + (c - 1)];
+  }
+  __device__ double St(int i, int j, int a, int b) const {
+    return S[(((int64_t)i * d.no + j) * d.nv + a) * d.nv + b];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// S~ = (x_S2 + flip x_S2)/2, flip: (i,j,a,b) -> (j,i,b,a)
+// ---------------------------------------------------------------------------
+__global__ void k_sym_s2(Dims d, const double* x, double* S) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t n = (int64_t)d.no * d.no * d.nv * d.nv;
+  if (g >= n) return;
+  int64_t r = g;
+  int b = r % d.nv; r /= d.nv;
+  int a = r % d.nv; r /= d.nv;
+  int j = r % d.no; int i = r / d.no;
+  const double* s2 = x + d.off[B_S2];
+  S[g] = 0.5 * (s2[g] + s2[(((int64_t)j * d.no + i) * d.nv + b) * d.nv + a]);
+}
+
+// ---------------------------------------------------------------------------
+// Batched Sylvester product on matrix cores.  One job = one batch matrix of one
+// box, embedded in an mv x mv matrix (mv = nv padded to 16).  Output block of
+// (32 TW) x (32 TW) per workgroup, 4 wavefronts of TW x TW 16x16 tiles.
+// K loop: k < mv uses A = F', B = X; k >= mv uses A = X, B = F'.
+// ---------------------------------------------------------------------------
+enum Fmt { F_PACK = 0, F_PACK_RED = 1, F_DENSE_RED = 2, F_DENSE = 3 };
+
+struct JobView {
+  int fmt, m;            // storage format and its matrix dimension
+  const double* src;     // this batch's storage
+  double* dst;
+  double* tr;            // transfer row (row 0 of the embedded product) or null
+};
+
+__device__ inline JobView job_view(const VVArgs& A, int box, int batch) {
+  const Dims& d = A.d;
+  JobView v;
+  v.tr = nullptr;
+  int64_t o = d.off[box];
+  switch (box) {
+    case B_T2: case B_H11: case B_H21:
+      v.fmt = F_PACK; v.m = d.nv; o += (int64_t)batch * d.npv; break;
+    case B_T3:
+      v.fmt = F_PACK_RED; v.m = d.nv - 1; o += (int64_t)batch * d.npv1; break;
+    case B_H12: case B_H22:
+      v.fmt = F_DENSE_RED; v.m = d.nv - 1; o += (int64_t)batch * (d.nv - 1) * (d.nv - 1);
+      v.tr = A.side_tr + ((box == B_H12 ? 0 : d.npo) + (int64_t)batch) * d.nv;
+      break;
+    default:
+      v.fmt = F_DENSE; v.m = d.nv; break;
+  }
+  if (box == B_S2) {
+    v.src = A.S + (int64_t)batch * d.nv * d.nv;
+    v.dst = A.y + d.off[B_S2] + (int64_t)batch * d.nv * d.nv;
+  } else {
+    v.src = A.x + o;
+    v.dst = A.y + o;
+  }
+  return v;
+}
+
+// element (r, c) of the embedded batch matrix
+__device__ inline double xget(const JobView& v, int r, int c) {
+  switch (v.fmt) {
+    case F_PACK: {
+      if (r >= v.m || c >= v.m || r == c) return 0.0;
+      return r < c ? v.src[tri_idx(r, c, v.m)] : -v.src[tri_idx(c, r, v.m)];
+    }
+    case F_PACK_RED: {
+      if (r == 0 || c == 0 || r > v.m || c > v.m || r == c) return 0.0;
+      return r < c ? v.src[tri_idx(r - 1, c - 1, v.m)] : -v.src[tri_idx(c - 1, r - 1, v.m)];
+    }
+    case F_DENSE_RED: {
+      if (r == 0 || c == 0 || r > v.m || c > v.m) return 0.0;
+      return v.src[(r - 1) * v.m + (c - 1)];
+    }
+    default:
+      if (r >= v.m || c >= v.m) return 0.0;
+      return v.src[r * v.m + c];
+  }
+}
+
+__device__ inline void yput(const JobView& v, int r, int c, double val) {
+  switch (v.fmt) {
+    case F_PACK:
+      if (r < c && c < v.m) v.dst[tri_idx(r, c, v.m)] = val;
+      break;
+    case F_PACK_RED:
+      if (r >= 1 && r < c && c <= v.m) v.dst[tri_idx(r - 1, c - 1, v.m)] = val;
+      break;
+    case F_DENSE_RED:
+      if (c >= 1 && c <= v.m && r <= v.m) {
+        if (r >= 1) v.dst[(r - 1) * v.m + (c - 1)] = val;
+        else v.tr[c] = val;
+      }
+      break;
+    default:
+      if (r < v.m && c < v.m) v.dst[r * v.m + c] = val;
+  }
+}
+
+template <int TW>
+__global__ __launch_bounds__(256) void k_vv(VVArgs A) {
+  constexpr int BR = 32 * TW;
+  __shared__ double As[16][BR + 1];
+  __shared__ double Bs[16][BR + 1];
+  const int2 jb = A.jobs[blockIdx.x];
+  const int box = jb.x;
+  const JobView v = job_view(A, box, jb.y);
+  const double* F = (box == B_T2 || box == B_S2) ? A.Fd : A.Fl;
+  const int mv = A.d.mv;
+  const int R0 = blockIdx.y * BR, C0 = blockIdx.z * BR;
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+  const int wr = (wave >> 1) * TW * 16, wc = (wave & 1) * TW * 16;
+  f64x4 acc[TW][TW];
+#pragma unroll
+  for (int i = 0; i < TW; ++i)
+#pragma unroll
+    for (int j = 0; j < TW; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < 2 * mv; k0 += 16) {
+    const bool second = k0 >= mv;
+    const int kb = second ? k0 - mv : k0;
+    for (int e = tid; e < BR * 16; e += 256) {
+      int r = e >> 4, kk = e & 15;
+      int gr = R0 + r, gk = kb + kk;
+      double val = 0.0;
+      if (gr < mv) val = second ? xget(v, gr, gk) : F[gr * mv + gk];
+      As[kk][r] = val;
+    }
+    for (int e = tid; e < BR * 16; e += 256) {
+      int c = e % BR, kk = e / BR;
+      int gc = C0 + c, gk = kb + kk;
+      double val = 0.0;
+      if (gc < mv) val = second ? F[gk * mv + gc] : xget(v, gk, gc);
+      Bs[kk][c] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      double a[TW], b[TW];
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        a[t] = As[ks * 4 + (l >> 4)][wr + t * 16 + (l & 15)];
+        b[t] = Bs[ks * 4 + (l >> 4)][wc + t * 16 + (l & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < TW; ++i)
+#pragma unroll
+        for (int j = 0; j < TW; ++j) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < TW; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TW; ++tj)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int r = R0 + wr + ti * 16 + 4 * (l >> 4) + i;
+        int c = C0 + wc + tj * 16 + (l & 15);
+        yput(v, r, c, acc[ti][tj][i]);
+      }
+}
+
+template __global__ void k_vv<1>(VVArgs);
+template __global__ void k_vv<2>(VVArgs);
+template __global__ void k_vv<3>(VVArgs);
+template __global__ void k_vv<4>(VVArgs);
+template __global__ void k_vv<5>(VVArgs);
+
+// ---------------------------------------------------------------------------
+// Side contractions over one virtual index, per batch of an L box:
+//   row   v[c] = sum_x w[x] X[x][c],   column  u[a] = sum_x X[a][x] w[x],
+// with w a column of f_ov (index 0 = t, or the batch's occupied indices).
+// Output layout: side[slot][batch][nv] for each (box, slot), see sigma.h.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_side(SideArgs A) {
+  const Dims& d = A.d;
+  const int no = d.no, nv = d.nv;
+  const int job = blockIdx.x;
+  Look L{d, A.x, nullptr};
+  const double* fov = A.fov;             // fov[i*nv + a]
+  int box, batch;
+  if (job < d.npo1) { box = B_T3; batch = job; }
+  else if (job < d.npo1 + d.npo) { box = B_H11; batch = job - d.npo1; }
+  else if (job < d.npo1 + 2 * d.npo) { box = B_H12; batch = job - d.npo1 - d.npo; }
+  else if (job < d.npo1 + 2 * d.npo + (no - 1) * (no - 1)) { box = B_H21; batch = job - d.npo1 - 2 * d.npo; }
+  else { box = B_H22; batch = job - d.npo1 - 2 * d.npo - (no - 1) * (no - 1); }
+  const int tid = threadIdx.x;
+  if (box == B_T3) {
+    int j, k; tri_pq(batch, no - 1, j, k); ++j; ++k;
+    for (int c = tid; c < nv; c += blockDim.x) {
+      double vt = 0, v1 = 0, v2 = 0;
+      if (c >= 1)
+        for (int b = 1; b < nv; ++b) {
+          double xv = L.T3(j, k, b, c);
+          vt += fov[b] * xv; v1 += fov[j * nv + b] * xv; v2 += fov[k * nv + b] * xv;
+        }
+      A.t3_t[batch * nv + c] = vt; A.t3_p1[batch * nv + c] = v1; A.t3_p2[batch * nv + c] = v2;
+    }
+  } else if (box == B_H11) {
+    int j, k; tri_pq(batch, no, j, k);
+    for (int c = tid; c < nv; c += blockDim.x) {
+      double v1 = 0, v2 = 0;
+      for (int b = 0; b < nv; ++b) {
+        double xv = L.H11(j, k, b, c);
+        v1 += fov[j * nv + b] * xv; v2 += fov[k * nv + b] * xv;
+      }
+      A.h11_p1[batch * nv + c] = v1; A.h11_p2[batch * nv + c] = v2;
+    }
+  } else if (box == B_H12) {
+    int j, k; tri_pq(batch, no, j, k);
+    for (int c = tid; c < nv; c += blockDim.x) {
+      double vt = 0, u1 = 0, u2 = 0;
+      if (c >= 1)
+        for (int x = 1; x < nv; ++x) {
+          vt += fov[x] * L.H12(j, k, x, c);             // sum_a f_{a t} X[a][c]
+          double xr = L.H12(j, k, c, x);                // row c (= a), column x
+          u1 += xr * fov[j * nv + x]; u2 += xr * fov[k * nv + x];
+        }
+      A.h12_t[batch * nv + c] = vt; A.h12_u1[batch * nv + c] = u1; A.h12_u2[batch * nv + c] = u2;
+    }
+  } else if (box == B_H21) {
+    int i = batch / (no - 1) + 1, k = batch % (no - 1) + 1;
+    for (int c = tid; c < nv; c += blockDim.x) {
+      double vt = 0, vk = 0;
+      for (int b = 0; b < nv; ++b) {
+        double xv = L.H21(i, k, b, c);
+        vt += fov[b] * xv; vk += fov[k * nv + b] * xv;
+      }
+      A.h21_t[batch * nv + c] = vt; A.h21_k[batch * nv + c] = vk;
+    }
+  } else {
+    int i = batch / (no - 1) + 1, k = batch % (no - 1) + 1;
+    for (int c = tid; c < nv; c += blockDim.x) {
+      double ut = 0, vi = 0, uk = 0;
+      if (c >= 1)
+        for (int x = 1; x < nv; ++x) {
+          double xr = L.H22(i, k, c, x);                // row c (= a), column x
+          ut += xr * fov[x]; uk += xr * fov[k * nv + x];
+          vi += fov[i * nv + x] * L.H22(i, k, x, c);    // sum_a f_{a i} X[a][c]
+        }
+      A.h22_ut[batch * nv + c] = ut; A.h22_i[batch * nv + c] = vi; A.h22_uk[batch * nv + c] = uk;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-element gather: occupied-index Fock action, box transfers, doubles <->
+// L-triples couplings.  y += ... (the virtual-pair part is already in y).
+// ---------------------------------------------------------------------------
+__device__ inline int box_of_g(const Dims& d, int64_t g, int64_t& loc) {
+  int k = 0;
+  while (k < 6 && g >= d.off[k + 1]) ++k;
+  loc = g - d.off[k];
+  return k;
+}
+
+__global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
+  const Dims& d = A.d;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.off[7]) return;
+  const int no = d.no, nv = d.nv;
+  Look L{d, A.x, A.S};
+  const double* fo = A.fo;     // fo[m*no + i]
+  const double* fv = A.fv;     // fv[a*nv + b]
+  const double* fov = A.fov;   // fov[i*nv + a]
+  auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
+  const double ftt = FOV(0, 0);
+  int64_t loc;
+  const int box = box_of_g(d, g, loc);
+  double y = 0.0;
+  switch (box) {
+    case B_T2: {
+      int i, j, a, b;
+      tri_pq(loc / d.npv, no, i, j); tri_pq(loc % d.npv, nv, a, b);
+      for (int m = 0; m < no; ++m) y -= fo[m * no + i] * L.T2(m, j, a, b) + fo[m * no + j] * L.T2(i, m, a, b);
+      if (i >= 1 && a >= 1) y += ftt * L.T3(i, j, a, b);
+      y += ftt * L.H11(i, j, a, b);
+      if (i == 0 && a >= 1)
+        for (int m = 1; m < no; ++m) y -= FOV(m, 0) * L.T3(m, j, a, b);
+      if (i == 0)
+        for (int m = 1; m < no; ++m) y += FOV(m, 0) * L.H21(m, j, a, b);
+      if (a == 0) {
+        int po = tri_idx(i, j, no);
+        if (i >= 1) y -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
+        y += A.h12_t[po * nv + b];
+        if (i == 0) {
+          for (int m = 1; m < no; ++m) {
+            if (m < j) y += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
+            else if (m > j) y -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
+            y += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
+          }
+        }
+      }
+      break;
+    }
+    case B_S2: {
+      int64_t r = loc;
+      int b = r % nv; r /= nv;
+      int a = r % nv; r /= nv;
+      int j = r % no, i = r / no;
+      for (int m = 0; m < no; ++m) y -= fo[m * no + i] * L.St(m, j, a, b) + fo[m * no + j] * L.St(i, m, a, b);
+      // d(p,q,x,z) + d(q,p,z,x): de-excitation of the mixed-spin L-triples
+      for (int rep = 0; rep < 2; ++rep) {
+        int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
+        double dd = 0.0;
+        if (p == 0 && xx == 0) {
+          for (int m = 0; m < no; ++m) {
+            if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
+            else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
+          }
+        }
+        if (p == 0 && xx >= 1 && z >= 1)
+          for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
+        if (p == 0 && xx >= 1 && z == 0) {
+          for (int m = 0; m < no; ++m) {
+            if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
+            else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
+          }
+        }
+        if (p >= 1 && q >= 1 && xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
+        if (p >= 1 && q == 0 && xx == 0)
+          for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
+        if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) dd += ftt * L.H22(p, q, xx, z);
+        if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
+          for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
+        if (p >= 1 && q >= 1 && xx >= 1 && z == 0) dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
+        if (p >= 1 && q == 0 && xx >= 1 && z == 0)
+          for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
+        y += dd;
+      }
+      break;
+    }
+    case B_T3: {
+      int j, k, b, c;
+      tri_pq(loc / d.npv1, no - 1, j, k); tri_pq(loc % d.npv1, nv - 1, b, c);
+      ++j; ++k; ++b; ++c;
+      for (int m = 1; m < no; ++m) y -= fo[m * no + j] * L.T3(m, k, b, c) + fo[m * no + k] * L.T3(j, m, b, c);
+      y += ftt * L.T2(j, k, b, c) - FOV(j, 0) * L.T2(0, k, b, c) + FOV(k, 0) * L.T2(0, j, b, c)
+         - FOV(0, b) * L.T2(j, k, 0, c) + FOV(j, b) * L.T2(0, k, 0, c) - FOV(k, b) * L.T2(0, j, 0, c)
+         + FOV(0, c) * L.T2(j, k, 0, b) - FOV(j, c) * L.T2(0, k, 0, b) + FOV(k, c) * L.T2(0, j, 0, b);
+      break;
+    }
+    case B_H11: {
+      int j, k, b, c;
+      tri_pq(loc / d.npv, no, j, k); tri_pq(loc % d.npv, nv, b, c);
+      for (int m = 0; m < no; ++m) y -= fo[m * no + j] * L.H11(m, k, b, c) + fo[m * no + k] * L.H11(j, m, b, c);
+      if (b == 0) y += A.side_tr[(int64_t)tri_idx(j, k, no) * nv + c];
+      if (j == 0)
+        for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H21(m, k, b, c);
+      y += ftt * L.T2(j, k, b, c);
+      y += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
+         - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
+      break;
+    }
+    case B_H12: {
+      int m1 = nv - 1;
+      int j, k;
+      tri_pq(loc / (m1 * m1), no, j, k);
+      int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
+      for (int m = 0; m < no; ++m) y -= fo[m * no + j] * L.H12(m, k, a, c) + fo[m * no + k] * L.H12(j, m, a, c);
+      y += fv[a * nv + 0] * L.H11(j, k, 0, c);
+      if (j == 0)
+        for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H22(m, k, a, c);
+      y += FOV(0, a) * L.T2(j, k, 0, c);
+      y += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
+         - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
+      break;
+    }
+    case B_H21: {
+      int o = loc / d.npv, b, c;
+      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+      tri_pq(loc % d.npv, nv, b, c);
+      for (int m = 1; m < no; ++m) y -= fo[m * no + i] * L.H21(m, k, b, c) + fo[m * no + k] * L.H21(i, m, b, c);
+      y -= fo[0 * no + i] * L.H11(0, k, b, c);
+      if (b == 0) y += A.side_tr[((int64_t)d.npo + o) * nv + c];
+      y += FOV(i, 0) * L.T2(0, k, b, c);
+      y += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
+         - FOV(0, c) * L.St(i, k, 0, b) + FOV(k, c) * L.St(i, 0, 0, b);
+      break;
+    }
+    default: {
+      int m1 = nv - 1;
+      int o = loc / (m1 * m1);
+      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+      int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
+      for (int m = 1; m < no; ++m) y -= fo[m * no + i] * L.H22(m, k, a, c) + fo[m * no + k] * L.H22(i, m, a, c);
+      y -= fo[0 * no + i] * L.H12(0, k, a, c);
+      y += fv[a * nv + 0] * L.H21(i, k, 0, c);
+      y += FOV(i, a) * L.T2(0, k, 0, c);
+      y += ftt * L.St(i, k, a, c) - FOV(k, 0) * L.St(i, 0, a, c)
+         - FOV(0, c) * L.St(i, k, a, 0) + FOV(k, c) * L.St(i, 0, a, 0);
+      break;
+    }
+  }
+  A.y[g] += y;
+}
+
+}  // namespace esmp2

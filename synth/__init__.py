@@ -94,3 +94,31 @@ def batched_sizes():
 def random_amplitudes(n: int, seed) -> np.ndarray:
     """A seeded random vector (for operator-action parity tests)."""
     return np.random.default_rng(seed).standard_normal(n)
+
+
+def make_canonical_problem(n_occ: int, n_vir: int, n_aux: int, seed, fock_noise: float = 1e-3,
+                           b_scale: float = 0.05, pair_weight: float = 0.95) -> Problem:
+    """A problem already expressed in its own TOP basis (random draws only).
+
+    C = [diag(lambda), 0] with lambda descending (lambda_0^2 = pair_weight),
+    and the Fock block of the virtuals beyond n_occ (the AVOs) diagonal and
+    ascending, so the TOP rotation of this input is the identity.  Used to
+    compare amplitude-level quantities element by element.
+    """
+    rng = np.random.default_rng(seed)
+    n = n_occ + n_vir
+    eps_o = np.sort(rng.uniform(-1.5, -0.3, n_occ))[::-1].copy()   # HOMO-like first
+    eps_v = np.sort(rng.uniform(0.1, 3.0, n_vir))
+    E = rng.normal(0.0, fock_noise, (n, n))
+    up = np.triu(E, 1)
+    F = np.diag(np.concatenate([eps_o, eps_v])) + up + up.T
+    avo = np.arange(2 * n_occ, n)
+    F[np.ix_(avo, avo)] = np.diag(eps_v[n_occ:])
+    G = rng.normal(0.0, 1.0, (n_aux, n, n))
+    B = b_scale * (G + G.transpose(0, 2, 1)) / 2.0
+    rest = np.sort(rng.uniform(0.05, 1.0, n_occ - 1))[::-1]
+    rest *= np.sqrt((1.0 - pair_weight) / np.sum(rest * rest))
+    lam = np.concatenate([[np.sqrt(pair_weight)], rest])
+    C = np.zeros((n_occ, n_vir))
+    C[np.arange(n_occ), np.arange(n_occ)] = lam
+    return Problem(n_occ, n_vir, n_aux, F, B, C, seed)

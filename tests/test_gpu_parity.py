@@ -1,0 +1,159 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Element-by-element comparisons use inputs already in their own TOP basis
+(synth.make_canonical_problem), so that both sides' rotations are the
+identity; the full pipeline is compared on rotation-invariant results
+(singular values, E0, E2) at every workload size, and on sampled amplitudes
+stored by tests/golden/make_golden.py (oracle only).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import structured, topbasis
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_12923_amd as p
+    return p
+
+
+def _handle(lib, prob):
+    print(f"[case] n_occ={prob.n_occ} n_vir={prob.n_vir} n_aux={prob.n_aux} seed={prob.seed}", flush=True)
+    return lib.Handle(0).load(prob)
+
+
+def _oracle_rotated(prob):
+    lam, R = topbasis.top_rotation(prob.F, prob.C, prob.n_occ)
+    Ft, Bt = topbasis.rotate(prob.F, prob.B, R)
+    return lam, Ft, Bt
+
+
+def test_gemm_f64_matches_reference(lib):
+    rng = np.random.default_rng(0)
+    h = lib.Handle(0)
+    for (m, n, k) in [(16, 16, 4), (64, 64, 16), (70, 33, 45), (130, 200, 97)]:
+        A = rng.standard_normal((m, k))
+        B = rng.standard_normal((k, n))
+        At, Bt = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        Ct = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+        h.gemm_f64(At, Bt, Ct)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(Ct.cpu().numpy(), A @ B, rtol=0, atol=1e-12 * np.sqrt(k))
+    h.close()
+
+
+CANON = [(3, 5, 8, 1), (4, 7, 9, 2), (4, 16, 48, 3), (5, 40, 30, 4), (6, 100, 40, 5), (3, 180, 20, 6)]
+
+
+@pytest.mark.parametrize("no,nv,na,seed", CANON)
+def test_sigma_elementwise(lib, no, nv, na, seed):
+    prob = synth.make_canonical_problem(no, nv, na, seed)
+    h = _handle(lib, prob)
+    lam_g = h.rotate_top()
+    lam, Ft, Bt = _oracle_rotated(prob)
+    np.testing.assert_allclose(lam_g, lam, rtol=0, atol=1e-14)
+    op = structured.Structured(Ft, lam, no)
+    n, offs = h.space()
+    assert n == op.dim
+    x = synth.random_amplitudes(n, seed + 100)
+    ref = op.sigma(x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.full_like(xt, float("nan"))
+    h.sigma(xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    scale = np.abs(ref).max()
+    for k in range(7):
+        lo, hi = offs[k], offs[k + 1]
+        if hi > lo:
+            err = np.abs(y[lo:hi] - ref[lo:hi]).max()
+            assert err <= 1e-12 * scale, (k, err, scale)
+    h.close()
+
+
+@pytest.mark.parametrize("no,nv,na,seed", CANON[:5])
+def test_rhs_elementwise(lib, no, nv, na, seed):
+    prob = synth.make_canonical_problem(no, nv, na, seed)
+    h = _handle(lib, prob)
+    h.rotate_top()
+    lam, Ft, Bt = _oracle_rotated(prob)
+    rh = structured.RHS(Ft, Bt, lam, no)
+    ref = rh.rhs()
+    n, offs = h.space()
+    bt = torch.zeros(n, dtype=torch.float64, device="cuda")
+    e0, e2s = h.build_rhs(bt)
+    torch.cuda.synchronize()
+    b = bt.cpu().numpy()
+    scale = np.abs(ref).max()
+    for k in range(7):
+        lo, hi = offs[k], offs[k + 1]
+        if hi > lo:
+            assert np.abs(b[lo:hi] - ref[lo:hi]).max() <= 1e-13 * scale, k
+    assert abs(e0 - rh.op.E0) < 1e-12
+    ref_s = rh.e2_s()
+    assert abs(e2s - ref_s) <= 1e-12 * max(1.0, abs(ref_s))
+    h.close()
+
+
+@pytest.mark.parametrize("no,nv,na,seed", [(3, 5, 8, 1), (4, 7, 9, 4), (5, 12, 14, 2)])
+def test_e2_small_random_basis(lib, no, nv, na, seed):
+    """Full pipeline (rotation included) on inputs in a random orbital basis."""
+    prob = synth.make_problem(no, nv, na, seed)
+    h = _handle(lib, prob)
+    lam_g = h.rotate_top()
+    res = h.solve(tol=1e-12, max_iter=200)
+    ref = structured.solve_problem(prob, tol=1e-13)
+    np.testing.assert_allclose(lam_g, ref["lam"], rtol=0, atol=1e-13)
+    assert abs(res["e0"] - ref["e0"]) < 1e-12
+    assert abs(res["e2"] - ref["e2"]) < 1e-10
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["c1", "c5", "c2", "c3"])
+def test_e2_workloads(lib, name):
+    """E2 at the workload sizes within 1e-10 Eh of the oracle (stored values)."""
+    g = GOLD[name]
+    prob = synth.config_problem(name)
+    h = _handle(lib, prob)
+    lam_g = h.rotate_top()
+    np.testing.assert_allclose(lam_g, g["lam"], rtol=0, atol=1e-12)
+    n, offs = h.space()
+    assert n == g["dim"] and offs == g["offsets"]
+    # sampled sigma of the stored random vector
+    x = synth.random_amplitudes(n, g["sigma_seed"])
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.empty_like(xt)
+    h.sigma(xt, yt)
+    idx = np.array(g["sample_idx"])
+    bt = torch.empty_like(xt)
+    e0, e2s = h.build_rhs(bt)
+    torch.cuda.synchronize()
+    sig = yt.cpu().numpy()[idx]
+    ref = np.array(g["sigma_sample"])
+    assert np.abs(sig - ref).max() <= 1e-11 * np.abs(ref).max()
+    b = bt.cpu().numpy()
+    assert np.abs(b[idx] - np.array(g["b_sample"])).max() <= 1e-12 * np.abs(g["b_sample"]).max()
+    assert abs(e0 - g["e0"]) < 1e-11
+    assert abs(e2s - g["e2_s"]) < 1e-10
+    xo = torch.empty_like(xt)
+    res = h.solve(tol=1e-10, max_iter=300, x_out=xo)
+    torch.cuda.synchronize()
+    print(f"[{name}] E2 gpu {res['e2']:.12f} oracle {g['e2']:.12f} diff {res['e2'] - g['e2']:.3e} "
+          f"iters {res['iterations']}", flush=True)
+    assert res["status"] == 0
+    assert abs(res["e2"] - g["e2"]) < 1e-10
+    xs = xo.cpu().numpy()[idx]
+    assert np.abs(xs - np.array(g["x_sample"])).max() <= 1e-8 * np.abs(g["x_sample"]).max()
+    h.close()
