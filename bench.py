@@ -1,0 +1,159 @@
+#!/usr/bin/env python
+"""Benchmark of the ESMP2-TOP(1) hot path on one MI355X.
+
+A step is one pass of the whole hot path on the timed workload (n_occ=16,
+n_vir=160, n_aux=480, seed 2; synthetic ESMF-shaped inputs resident in HBM):
+rotation to the TOP basis, right-hand side + S-triple energy, FP64 Jacobi
+PCG to ||b+Ax||_W/||b||_W <= 1e-8, and E2.
+
+value = effective H0-sigma throughput of the whole job: algorithmic sigma
+flops x sigma applications in the timed steps / wall time (GFLOP/s); the
+time-to-E2 is ms_per_step.  The roofline object covers the dominant kernel
+(the virtual-pair Sylvester kernel on the FP64 matrix cores), timed with HIP
+events on the library's stream.  cpu_baseline times the CPU oracle (one
+sigma application and the right-hand side at the same workload).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding of the path is described in DESIGN.md but not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2003_12923_amd as P
+    from paper_2003_12923_amd import costs
+
+    prob = synth.config_problem(args.workload)
+    no, nv = prob.n_occ, prob.n_vir
+    vv_flops, oo_flops = costs.sigma_flops(no, nv)
+    sig_flops = vv_flops + oo_flops
+    torch.cuda.set_device(0)
+    h = P.Handle(0).load(prob)
+    torch.cuda.synchronize()
+
+    def step():
+        h.rotate_top(lam_out=False)
+        h.build_rhs()
+        return h.solve(tol=args.tol, max_iter=300)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile(True)
+    n_sigma = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+        n_sigma += res["iterations"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vv_ms, vv_n = h.profile(False)
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = n_sigma * sig_flops / wall / 1e9
+
+    # sigma alone (all its kernels), FP64
+    n_amp, _ = h.space()
+    x = torch.from_numpy(synth.random_amplitudes(n_amp, 5)).cuda()
+    y = torch.empty_like(x)
+    for _ in range(3):
+        h.sigma(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        h.sigma(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    sigma_ms = e0.elapsed_time(e1) / reps
+
+    vv_avg_ms = vv_ms / max(vv_n, 1)
+    achieved = vv_flops / (vv_avg_ms * 1e-3) / 1e12
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "k_vv_traffic.json")
+    if os.path.exists(tfile):
+        t = json.load(open(tfile))
+        if t.get("workload") == args.workload and t.get("kernel_rev") == "v1":
+            traffic = t.get("bytes_per_launch")
+
+    gold = None
+    gfile = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
+    if os.path.exists(gfile):
+        gold = json.load(open(gfile)).get(args.workload)
+
+    out = {
+        "metric": "H0 sigma GFLOP/s + time-to-E2 (1e-8 resid), FP64 vs mixed at 1e-6 Eh, N_o=16",
+        "value": round(value, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ESMP2-TOP(1) singlet, n_occ={no}, n_vir={nv}, n_aux={prob.n_aux}, "
+                               f"seed {prob.seed}, PCG to 1e-8",
+                   "n_amplitudes": n_amp, "sigma_alg_flops": sig_flops},
+        "time_to_e2_ms": round(ms_per_step, 4),
+        "fp64": {"e2": res["e2"], "iterations": res["iterations"], "rel_resid": res["rel_resid"],
+                 "e2_minus_oracle": None if gold is None else res["e2"] - gold["e2"],
+                 "sigma_ms": round(sigma_ms, 4), "sigma_gflops": round(sig_flops / sigma_ms / 1e6, 2)},
+        "roofline": {"bound": "mfma", "kernel": "k_vv (virtual-pair Sylvester, FP64 MFMA)",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                     "alg_flops_per_launch": vv_flops, "avg_launch_ms": round(vv_avg_ms, 4),
+                     "launches": vv_n},
+    }
+    h.close()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, sig_flops)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(prob, sig_flops):
+    """The CPU oracle (numpy FP64) on the same workload: one sigma application."""
+    import numpy as np
+    import synth
+    from oracle import structured, topbasis
+    lam, R = topbasis.top_rotation(prob.F, prob.C, prob.n_occ)
+    Ft, Bt = topbasis.rotate(prob.F, prob.B, R)
+    op = structured.Structured(Ft, lam, prob.n_occ)
+    x = synth.random_amplitudes(op.dim, 5)
+    t = time.perf_counter()
+    op.sigma(x)
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(sig_flops / dt / 1e9, 4), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"one sigma application at the timed workload ({dt:.2f} s, numpy FP64)"}
+
+
+if __name__ == "__main__":
+    main()

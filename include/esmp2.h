@@ -154,6 +154,13 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
  * so that its operand layout can be validated directly. */
 esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A, const double* B, double* C);
 
+/* Timing of the virtual-pair Sylvester kernel (the dominant sigma kernel) with
+ * HIP events recorded on the handle's stream around each of its launches.
+ * Returns (host) the accumulated milliseconds and launch count since the last
+ * call, resets them, and switches recording on (enable != 0) or off.  Waits for
+ * the recorded events.  Either output may be NULL. */
+esmp2_status esmp2_profile(esmp2_handle h, int enable, double* vv_ms, int64_t* vv_launches);
+
 /* Message of the last failing call on this handle (never NULL). */
 const char* esmp2_last_error(esmp2_handle h);
 

@@ -40,6 +40,7 @@ _sig = {
     "esmp2_sigma": ([_H, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
     "esmp2_solve": ([_H, C.POINTER(SolveOpts), C.POINTER(SolveResult)], C.c_int),
     "esmp2_gemm_f64": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "esmp2_profile": ([_H, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "esmp2_last_error": ([_H], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -128,6 +129,11 @@ class Handle:
         if hist is not None:
             out["history"] = hist[: r.iterations].copy()
         return out
+
+    def profile(self, enable=True):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(lib.esmp2_profile(self.h, 1 if enable else 0, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def gemm_f64(self, A, B, Cm):
         m, k = A.shape

@@ -21,6 +21,11 @@ __global__ void k_finite(const double* v, int64_t n, int* bad) {
     if (!isfinite(v[g])) bad[0] = 1;
 }
 
+__global__ void k_sub_identity(double* E, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) E[(int64_t)i * n + i] -= 1.0;
+}
+
 // shift below the spectrum of F_vv: -(max_a sum_b |F_ab|) - 1
 __global__ void k_shift(const double* F, int n, int no, double* out) {
   double mx = 0.0;
@@ -81,7 +86,7 @@ struct esmp2_handle_ {
   // inputs
   double *F = nullptr, *B = nullptr, *C = nullptr;
   // rotation
-  double *lam, *U, *V, *Wm, *G, *M, *rot, *evals, *Z, *R, *avo, *Ft, *T, *Bov, *Bvt, *Boo;
+  double *lam, *U, *V, *Wm, *G, *M, *rot, *evals, *Z, *Zw, *R, *avo, *Ft, *T, *Bov, *Bvt, *Boo;
   int* iinfo;
   double *fo, *fv, *fov, *eo, *ev, *Fd, *Fl, *sc_rot;
   double omega = 0, kappa = 0, e0 = 0, e2s = 0;
@@ -95,11 +100,29 @@ struct esmp2_handle_ {
   int njobs = 0;
   // Krylov vectors
   double *x, *r, *p, *q;
+  // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_vv;
+  double vv_ms = 0.0;
+  int64_t vv_launches = 0;
 };
 
 static esmp2_status fail(esmp2_handle h, esmp2_status s, const std::string& msg) {
   if (h) h->err = msg;
   return s;
+}
+
+static void drain_events(esmp2_handle h) {
+  for (auto& e : h->ev_vv) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.second) == hipSuccess && hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+      h->vv_ms += ms;
+      h->vv_launches += 1;
+    }
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  h->ev_vv.clear();
 }
 
 static void release(esmp2_handle h) {
@@ -140,12 +163,25 @@ esmp2_status esmp2_destroy(esmp2_handle h) {
   if (!h) return ESMP2_OK;
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
+  drain_events(h);
   release(h);
   delete h;
   return ESMP2_OK;
 }
 
 const char* esmp2_last_error(esmp2_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+esmp2_status esmp2_profile(esmp2_handle h, int enable, double* vv_ms, int64_t* vv_launches) {
+  if (!h) return ESMP2_INVALID_ARG;
+  ESMP2_HIP(hipSetDevice(h->device));
+  drain_events(h);
+  if (vv_ms) *vv_ms = h->vv_ms;
+  if (vv_launches) *vv_launches = h->vv_launches;
+  h->vv_ms = 0.0;
+  h->vv_launches = 0;
+  h->prof = enable != 0;
+  return ESMP2_OK;
+}
 
 esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A, const double* B, double* C) {
   if (!h) return ESMP2_INVALID_ARG;
@@ -181,7 +217,7 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
             dalloc(h, &h->C, (size_t)no * nv) && dalloc(h, &h->lam, no) && dalloc(h, &h->U, no * no) &&
             dalloc(h, &h->V, (size_t)nv * no) && dalloc(h, &h->Wm, (size_t)nv * no) && dalloc(h, &h->G, no * no) &&
             dalloc(h, &h->M, (size_t)nv * nv) && dalloc(h, &h->rot, (size_t)2 * 20 * (P - 1) * (P / 2)) &&
-            dalloc(h, &h->evals, nv) && dalloc(h, &h->Z, (size_t)nv * nv) && dalloc(h, &h->R, (size_t)n * n) &&
+            dalloc(h, &h->evals, nv) && dalloc(h, &h->Z, (size_t)nv * nv) && dalloc(h, &h->Zw, (size_t)nv * nv) && dalloc(h, &h->R, (size_t)n * n) &&
             dalloc(h, &h->avo, nv) && dalloc(h, &h->Ft, (size_t)n * n) &&
             dalloc(h, &h->T, std::max((size_t)na * no * nv, (size_t)n * n)) &&
             dalloc(h, &h->Bov, (size_t)na * no * nv) && dalloc(h, &h->Bvt, (size_t)na * nv * no) &&
@@ -247,7 +283,21 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   ESMP2_HIP(hipFuncSetAttribute((const void*)k_eig_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
   hipLaunchKernelGGL(k_eig_jacobi, dim3(1), dim3(1024), lds2, s, h->M, nv, 20, h->rot, h->evals, h->iinfo + 1);
   hipLaunchKernelGGL(k_jacobi_vectors, dim3(nv), dim3(64), sizeof(double) * nv, s, h->rot, nv, h->iinfo + 1, h->Z);
-  hipLaunchKernelGGL(k_assemble_r, dim3(1), dim3(256), 0, s, h->U, h->V, h->Z, h->evals, no, nv, h->R, h->avo);
+  // one first-order Loewdin step restores orthonormality lost over the many
+  // accumulated plane rotations: Z <- Z - Z (Z^T Z - 1) / 2
+  {
+    GemmArgs e{};
+    e.A = h->Z; e.B = h->Z; e.C = h->M; e.M = nv; e.N = nv; e.K = nv;
+    e.sAi = 1; e.sAk = nv; e.sBk = nv; e.sBj = 1; e.sCi = nv; e.sCj = 1; e.alpha = 1; e.beta = 0;
+    ESMP2_HIP(gemm(s, 1, e));
+    hipLaunchKernelGGL(k_sub_identity, dim3(nblk(nv)), dim3(256), 0, s, h->M, nv);
+    ESMP2_HIP(hipMemcpyAsync(h->Zw, h->Z, sizeof(double) * nv * nv, hipMemcpyDeviceToDevice, s));
+    e = GemmArgs{};
+    e.A = h->Z; e.B = h->M; e.C = h->Zw; e.M = nv; e.N = nv; e.K = nv;
+    e.sAi = nv; e.sAk = 1; e.sBk = nv; e.sBj = 1; e.sCi = nv; e.sCj = 1; e.alpha = -0.5; e.beta = 1.0;
+    ESMP2_HIP(gemm(s, 1, e));
+  }
+  hipLaunchKernelGGL(k_assemble_r, dim3(1), dim3(256), 0, s, h->U, h->V, h->Zw, h->evals, no, nv, h->R, h->avo);
   // F~ = R^T F R
   GemmArgs g{};
   g.A = h->F; g.B = h->R; g.C = h->T; g.M = n; g.N = n; g.K = n;
@@ -396,12 +446,25 @@ static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
   if (tw > 5) tw = 5;
   const int nb = (d.mv + 32 * tw - 1) / (32 * tw);
   dim3 grid(h->njobs, nb, nb);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof) {
+    if (h->ev_vv.size() >= 4096) drain_events(h);
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+      (void)hipEventRecord(e0, s);
+    } else {
+      e0 = e1 = nullptr;
+    }
+  }
   switch (tw) {
     case 1: hipLaunchKernelGGL(k_vv<1>, grid, dim3(256), 0, s, va); break;
     case 2: hipLaunchKernelGGL(k_vv<2>, grid, dim3(256), 0, s, va); break;
     case 3: hipLaunchKernelGGL(k_vv<3>, grid, dim3(256), 0, s, va); break;
     case 4: hipLaunchKernelGGL(k_vv<4>, grid, dim3(256), 0, s, va); break;
     default: hipLaunchKernelGGL(k_vv<5>, grid, dim3(256), 0, s, va); break;
+  }
+  if (e0) {
+    (void)hipEventRecord(e1, s);
+    h->ev_vv.push_back({e0, e1});
   }
   GatherArgs ga{};
   ga.d = d; ga.x = x; ga.S = h->S; ga.y = y; ga.fo = h->fo; ga.fv = h->fv; ga.fov = h->fov; ga.side_tr = h->side_tr;

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   for (int ti = 0; ti < 2; ++ti)
     for (int tj = 0; tj < 2; ++tj)
       for (int i = 0; i < 4; ++i) {
-        int gi = m0 + wm + ti * 16 + 4 * (l >> 4) + i;
+        int gi = m0 + wm + ti * 16 + mfma_row(l, i);
         int gj = n0 + wn + tj * 16 + (l & 15);
         if (gi < g.M && gj < g.N) {
           double v = g.alpha * acc[ti][tj][i];
@@ -271,24 +271,19 @@ __global__ __launch_bounds__(1024) void k_eig_jacobi(const double* __restrict__ 
   __syncthreads();
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    // convergence test: off-diagonal vs total Frobenius norm
-    double off = 0, all = 0;
-    for (int e = tid; e < n * (n + 1) / 2; e += nt) {
-      double v = A[e];
-      all += v * v;
-      // diagonal entries are at pk(r,r)
-      off += v * v;
-    }
-    double dg = 0;
+    // convergence test: off-diagonal vs diagonal Frobenius norm, both summed
+    // directly (a difference of the two would drown the test in cancellation)
+    double off = 0, dg = 0;
+    for (int r = 0; r < n; ++r)
+      for (int c = r + 1 + tid; c < n; c += nt) { double v = A[pk(r, c, n)]; off += v * v; }
     for (int r = tid; r < n; r += nt) { double v = A[pk(r, r, n)]; dg += v * v; }
-    off -= dg;
-    for (int o = 32; o > 0; o >>= 1) { off += __shfl_xor(off, o); all += __shfl_xor(all, o); }
-    if ((tid & 63) == 0) { offs[tid >> 6] = off; tot[tid >> 6] = all; }
+    for (int o = 32; o > 0; o >>= 1) { off += __shfl_xor(off, o); dg += __shfl_xor(dg, o); }
+    if ((tid & 63) == 0) { offs[tid >> 6] = off; tot[tid >> 6] = dg; }
     __syncthreads();
     if (tid == 0) {
-      double so = 0, sa = 0;
-      for (int w = 0; w < nt / 64; ++w) { so += offs[w]; sa += tot[w]; }
-      done = (so <= 1e-30 * sa);
+      double so = 0, sd = 0;
+      for (int w = 0; w < nt / 64; ++w) { so += offs[w]; sd += tot[w]; }
+      done = (so <= 1e-34 * sd);
     }
     __syncthreads();
     if (done) break;

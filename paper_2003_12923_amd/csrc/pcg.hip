@@ -12,18 +12,18 @@ __device__ inline double wgt(int64_t g, int64_t s0, int64_t s1) { return (g >= s
 // partial[block] = sum_g w_g x_g y_g   (grid-stride, fixed grid -> deterministic)
 __global__ __launch_bounds__(256) void k_dot(const double* x, const double* y, int64_t n, int64_t s0,
                                              int64_t s1, double* partial) {
-  double acc = 0.0;
+  Acc2 acc;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
-    acc += wgt(g, s0, s1) * x[g] * y[g];
-  double s = block_sum(acc);
+    acc.add(wgt(g, s0, s1) * x[g] * y[g]);
+  double s = block_sum2(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 // sc[k] = sum of partials[k*nb .. k*nb+nb-1]  for k < nsum (one block per sum)
 __global__ void k_finish(const double* partial, int nb, double* sc, int base) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partial[(int64_t)blockIdx.x * nb + i];
-  double s = block_sum(acc);
+  Acc2 acc;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc.add(partial[(int64_t)blockIdx.x * nb + i]);
+  double s = block_sum2(acc);
   if (threadIdx.x == 0) sc[base + blockIdx.x] = s;
 }
 

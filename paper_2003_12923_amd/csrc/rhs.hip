@@ -372,9 +372,9 @@ __global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
 }
 
 __global__ void k_sum_partials(const double* v, int n, double* out, double scale) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += v[i];
-  double s = block_sum(acc);
+  Acc2 acc;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc.add(v[i]);
+  double s = block_sum2(acc);
   if (threadIdx.x == 0) out[0] = scale * s;
 }
 

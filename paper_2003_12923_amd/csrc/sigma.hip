@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_vv(VVArgs A) {
     for (int tj = 0; tj < TW; ++tj)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int r = R0 + wr + ti * 16 + 4 * (l >> 4) + i;
+        int r = R0 + wr + ti * 16 + mfma_row(l, i);
         int c = C0 + wc + tj * 16 + (l & 15);
         yput(v, r, c, acc[ti][tj][i]);
       }
