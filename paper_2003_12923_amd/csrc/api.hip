@@ -26,25 +26,6 @@ __global__ void k_sub_identity(double* E, int n) {
   if (i < n) E[(int64_t)i * n + i] -= 1.0;
 }
 
-// shift below the spectrum of F_vv: -(max_a sum_b |F_ab|) - 1
-__global__ void k_shift(const double* F, int n, int no, double* out) {
-  double mx = 0.0;
-  for (int a = threadIdx.x; a < n - no; a += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < n - no; ++b) s += fabs(F[(no + a) * n + no + b]);
-    mx = fmax(mx, s);
-  }
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
-  __shared__ double ws[16];
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = 0.0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r = fmax(r, ws[k]);
-    out[0] = -r - 1.0;
-  }
-}
-
 // TOP-basis Fock blocks, orbital energies, omega / kappa / E0 and the shifted,
 // padded virtual blocks used by the Sylvester kernel.
 //   sc[0] = omega = sum_l lam_l^2 (f_l'l' - f_ll), sc[1] = kappa = f_t't' - f_tt - omega,
@@ -86,11 +67,11 @@ struct esmp2_handle_ {
   // inputs
   double *F = nullptr, *B = nullptr, *C = nullptr;
   // rotation
-  double *lam, *U, *V, *Wm, *G, *M, *rot, *evals, *Z, *Zw, *R, *avo, *Ft, *T, *Bov, *Bvt, *Boo;
+  double *lam, *U, *V, *rs, *evals, *R, *avo, *Ft, *T, *Bov, *Bvt, *Boo;
   int* iinfo;
   double *fo, *fv, *fov, *eo, *ev, *Fd, *Fl, *sc_rot;
   double omega = 0, kappa = 0, e0 = 0, e2s = 0;
-  int svd_sweeps = 0, eig_sweeps = 0;
+  int svd_sweeps = 0;
   // rhs
   double *fphi, *X, *Vint, *Mint, *b, *dinv, *blockmin, *partial, *sc;
   bool have_rhs = false;
@@ -201,8 +182,8 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
   if (!F || !B || !C) return fail(h, ESMP2_INVALID_ARG, "null input pointer");
   if (n_occ < 2 || n_vir < n_occ || n_aux < 1)
     return fail(h, ESMP2_INVALID_ARG, "need 2 <= n_occ <= n_vir and n_aux >= 1");
-  if (n_occ > 64 || (int64_t)n_occ * n_vir > 8192 || n_vir > 196)
-    return fail(h, ESMP2_UNSUPPORTED, "sizes beyond n_occ <= 64, n_occ*n_vir <= 8192, n_vir <= 196");
+  if (n_occ > 64 || (int64_t)n_occ * n_vir > 8192 || n_vir > 192)
+    return fail(h, ESMP2_UNSUPPORTED, "sizes beyond n_occ <= 64, n_occ*n_vir <= 8192, n_vir <= 192");
   if (spin != 0) return fail(h, ESMP2_UNSUPPORTED, "only the singlet (spin = 0) is implemented");
   if (n_top != 1) return fail(h, ESMP2_UNSUPPORTED, "only n_top = 1 (ESMP2-TOP(1)) is implemented");
   ESMP2_HIP(hipSetDevice(h->device));
@@ -212,12 +193,10 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
   h->d = d;
   const int no = n_occ, nv = n_vir, n = d.n, na = n_aux, mv = d.mv;
   const int64_t namp = d.off[7];
-  const int P = (nv + 1) / 2 * 2;
   bool ok = dalloc(h, &h->F, (size_t)n * n) && dalloc(h, &h->B, (size_t)na * n * n) &&
             dalloc(h, &h->C, (size_t)no * nv) && dalloc(h, &h->lam, no) && dalloc(h, &h->U, no * no) &&
-            dalloc(h, &h->V, (size_t)nv * no) && dalloc(h, &h->Wm, (size_t)nv * no) && dalloc(h, &h->G, no * no) &&
-            dalloc(h, &h->M, (size_t)nv * nv) && dalloc(h, &h->rot, (size_t)2 * 20 * (P - 1) * (P / 2)) &&
-            dalloc(h, &h->evals, nv) && dalloc(h, &h->Z, (size_t)nv * nv) && dalloc(h, &h->Zw, (size_t)nv * nv) && dalloc(h, &h->R, (size_t)n * n) &&
+            dalloc(h, &h->V, (size_t)nv * no) && dalloc(h, &h->rs, (size_t)11 * nv * nv) &&
+            dalloc(h, &h->evals, nv) && dalloc(h, &h->R, (size_t)n * n) &&
             dalloc(h, &h->avo, nv) && dalloc(h, &h->Ft, (size_t)n * n) &&
             dalloc(h, &h->T, std::max((size_t)na * no * nv, (size_t)n * n)) &&
             dalloc(h, &h->Bov, (size_t)na * no * nv) && dalloc(h, &h->Bvt, (size_t)na * nv * no) &&
@@ -270,34 +249,54 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   size_t lds = sizeof(double) * (no * nv + no * no);
   ESMP2_HIP(hipFuncSetAttribute((const void*)k_svd_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_svd_jacobi, dim3(1), dim3(1024), lds, s, h->C, no, nv, h->lam, h->U, h->V, h->iinfo);
-  // semicanonical AVOs: eigenvectors of M = P F_vv P + shift V V^T
-  hipLaunchKernelGGL(k_fv_times_v, dim3(nblk(nv * no)), dim3(256), 0, s, h->F, n, no, nv, h->V, h->Wm);
-  hipLaunchKernelGGL(k_vt_w, dim3(nblk(no * no)), dim3(256), 0, s, h->V, h->Wm, no, nv, h->G);
-  hipLaunchKernelGGL(k_shift, dim3(1), dim3(256), 0, s, h->F, n, no, h->sc_rot + 4);
-  double shift = 0;
-  ESMP2_HIP(hipMemcpyAsync(&shift, h->sc_rot + 4, sizeof(double), hipMemcpyDeviceToHost, s));
-  ESMP2_HIP(hipStreamSynchronize(s));
-  hipLaunchKernelGGL(k_build_m, dim3(nblk(nv * nv)), dim3(256), 0, s, h->F, n, no, nv, h->V, h->Wm, h->G, shift,
-                     h->M);
-  size_t lds2 = sizeof(double) * (size_t)nv * (nv + 1) / 2;
-  ESMP2_HIP(hipFuncSetAttribute((const void*)k_eig_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
-  hipLaunchKernelGGL(k_eig_jacobi, dim3(1), dim3(1024), lds2, s, h->M, nv, 20, h->rot, h->evals, h->iinfo + 1);
-  hipLaunchKernelGGL(k_jacobi_vectors, dim3(nv), dim3(64), sizeof(double) * nv, s, h->rot, nv, h->iinfo + 1, h->Z);
-  // one first-order Loewdin step restores orthonormality lost over the many
-  // accumulated plane rotations: Z <- Z - Z (Z^T Z - 1) / 2
+  // semicanonical AVOs: complement of the TOP virtuals, F restricted to it,
+  // tridiagonal eigensolver, back-transformation, Loewdin re-orthonormalisation
   {
-    GemmArgs e{};
-    e.A = h->Z; e.B = h->Z; e.C = h->M; e.M = nv; e.N = nv; e.K = nv;
-    e.sAi = 1; e.sAk = nv; e.sBk = nv; e.sBj = 1; e.sCi = nv; e.sCj = 1; e.alpha = 1; e.beta = 0;
-    ESMP2_HIP(gemm(s, 1, e));
-    hipLaunchKernelGGL(k_sub_identity, dim3(nblk(nv)), dim3(256), 0, s, h->M, nv);
-    ESMP2_HIP(hipMemcpyAsync(h->Zw, h->Z, sizeof(double) * nv * nv, hipMemcpyDeviceToDevice, s));
-    e = GemmArgs{};
-    e.A = h->Z; e.B = h->M; e.C = h->Zw; e.M = nv; e.N = nv; e.K = nv;
-    e.sAi = nv; e.sAk = 1; e.sBk = nv; e.sBj = 1; e.sCi = nv; e.sCj = 1; e.alpha = -0.5; e.beta = 1.0;
-    ESMP2_HIP(gemm(s, 1, e));
+    const int m = nv - no;
+    double* Q2 = h->rs;                                 // nv x m
+    double* Tt = Q2 + (size_t)nv * nv;                  // nv x m
+    double* Fa = Tt + (size_t)nv * nv;                  // m x m
+    double* refl = Fa + (size_t)nv * nv;                // m x m
+    double* Yt = refl + (size_t)nv * nv;                // m x m
+    double* Ym = Yt + (size_t)nv * nv;                  // m x m
+    double* AV = Ym + (size_t)nv * nv;                  // nv x m
+    double* AV2 = AV + (size_t)nv * nv;                 // nv x m
+    double* work = AV2 + (size_t)nv * nv;               // m x 2m
+    double* vec = work + (size_t)2 * nv * nv;           // rbeta, d, e (3 m <= nv*nv); rs holds 11 nv^2
+    size_t lc = sizeof(double) * 2 * (size_t)nv * no;
+    ESMP2_HIP(hipFuncSetAttribute((const void*)k_complement, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
+    hipLaunchKernelGGL(k_complement, dim3(1), dim3(256), lc, s, h->V, nv, no, Q2);
+    GemmArgs g{};
+    g.A = h->F + (int64_t)no * n + no; g.B = Q2; g.C = Tt; g.M = nv; g.N = m; g.K = nv;
+    g.sAi = n; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, 1, g));
+    g = GemmArgs{};
+    g.A = Q2; g.B = Tt; g.C = Fa; g.M = m; g.N = m; g.K = nv;
+    g.sAi = 1; g.sAk = m; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, 1, g));
+    size_t lt = sizeof(double) * (size_t)m * (m + 1) / 2;
+    ESMP2_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lt));
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lt, s, Fa, m, refl, vec, vec + m, vec + 2 * m);
+    hipLaunchKernelGGL(k_tri_eig, dim3(m), dim3(64), 0, s, vec + m, vec + 2 * m, m, h->evals, Yt, work);
+    hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(64), 0, s, h->evals, m, Yt);
+    hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), sizeof(double) * m, s, refl, vec, m, Yt, Ym);
+    g = GemmArgs{};
+    g.A = Q2; g.B = Ym; g.C = AV; g.M = nv; g.N = m; g.K = m;
+    g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, 1, g));
+    // one first-order Loewdin step: AV <- AV - AV (AV^T AV - 1) / 2
+    g = GemmArgs{};
+    g.A = AV; g.B = AV; g.C = Fa; g.M = m; g.N = m; g.K = nv;
+    g.sAi = 1; g.sAk = m; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, 1, g));
+    hipLaunchKernelGGL(k_sub_identity, dim3(nblk(m)), dim3(256), 0, s, Fa, m);
+    ESMP2_HIP(hipMemcpyAsync(AV2, AV, sizeof(double) * nv * m, hipMemcpyDeviceToDevice, s));
+    g = GemmArgs{};
+    g.A = AV; g.B = Fa; g.C = AV2; g.M = nv; g.N = m; g.K = m;
+    g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = -0.5; g.beta = 1.0;
+    ESMP2_HIP(gemm(s, 1, g));
+    hipLaunchKernelGGL(k_assemble_r2, dim3(1), dim3(1024), 0, s, h->U, h->V, AV2, h->evals, no, nv, h->R, h->avo);
   }
-  hipLaunchKernelGGL(k_assemble_r, dim3(1), dim3(256), 0, s, h->U, h->V, h->Zw, h->evals, no, nv, h->R, h->avo);
   // F~ = R^T F R
   GemmArgs g{};
   g.A = h->F; g.B = h->R; g.C = h->T; g.M = n; g.N = n; g.K = n;
@@ -345,14 +344,14 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   g.sCb = (int64_t)no * no; g.sCi = no; g.sCj = 1; g.alpha = 1; g.beta = 0;
   ESMP2_HIP(gemm(s, na, g));
   double sc[3];
-  int info[2];
+  int info[1];
   ESMP2_HIP(hipMemcpyAsync(sc, h->sc_rot, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  ESMP2_HIP(hipMemcpyAsync(info, h->iinfo, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipMemcpyAsync(info, h->iinfo, sizeof(int), hipMemcpyDeviceToHost, s));
   if (lambda_out) ESMP2_HIP(hipMemcpyAsync(lambda_out, h->lam, no * sizeof(double), hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
   ESMP2_HIP(hipGetLastError());
   h->omega = sc[0]; h->kappa = sc[1]; h->e0 = sc[2];
-  h->svd_sweeps = info[0]; h->eig_sweeps = info[1];
+  h->svd_sweeps = info[0];
   h->state = 2;
   h->have_rhs = false;
   return ESMP2_OK;
@@ -371,7 +370,7 @@ static esmp2_status build_rhs(esmp2_handle h) {
   const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
   const int64_t namp = d.off[7];
   hipStream_t s = h->stream;
-  hipLaunchKernelGGL(k_fphi, dim3(nblk(nov)), dim3(256), 0, s, h->Ft, h->Bov, h->Bvt, h->Boo, h->lam, no, nv, na,
+  hipLaunchKernelGGL(k_fphi, dim3(nov), dim3(64), 0, s, h->Ft, h->Bov, h->Bvt, h->Boo, h->lam, no, nv, na,
                      h->fphi);
   hipLaunchKernelGGL(k_make_x, dim3(nblk((int64_t)na * nov)), dim3(256), 0, s, h->Bvt, h->Boo, h->lam, no, nv, na,
                      h->X);

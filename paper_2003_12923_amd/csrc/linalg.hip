@@ -6,6 +6,7 @@
 //   - assembly of the orthogonal rotation R.
 #include "common.h"
 #include "mfma.h"
+#include "reduce.h"
 #include <math.h>
 
 namespace esmp2 {
@@ -207,215 +208,313 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi(const double* __restrict__ 
   }
 }
 
-// ---------------------------------------------------------------------------
-// M = P F_vv P + shift * V V^T with P = 1 - V V^T (nv x nv), whose spectrum is
-// {shift (n_occ-fold, span of the TOP virtuals)} + {eigenvalues of F in the AVO
-// span}.  W = F_vv V and G = V^T F_vv V are formed first.
-// ---------------------------------------------------------------------------
-__global__ void k_fv_times_v(const double* F, int n, int no, int nv, const double* V, double* W) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nv * no) return;
-  int a = e / no, k = e % no;
-  double s = 0;
-  for (int b = 0; b < nv; ++b) s += F[(no + a) * n + no + b] * V[b * no + k];
-  W[a * no + k] = s;
-}
+}  // namespace esmp2
 
-__global__ void k_vt_w(const double* V, const double* W, int no, int nv, double* G) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= no * no) return;
-  int k = e / no, m = e % no;
-  double s = 0;
-  for (int a = 0; a < nv; ++a) s += V[a * no + k] * W[a * no + m];
-  G[k * no + m] = s;
-}
+namespace esmp2 {
 
-__global__ void k_build_m(const double* F, int n, int no, int nv, const double* V, const double* W,
-                          const double* G, double shift, double* M) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nv * nv) return;
-  int a = e / nv, b = e % nv;
-  double s = F[(no + a) * n + no + b];
-  for (int k = 0; k < no; ++k) {
-    s -= V[a * no + k] * W[b * no + k] + W[a * no + k] * V[b * no + k];
-    double t = 0;
-    for (int m = 0; m < no; ++m) t += (G[k * no + m] + (k == m ? shift : 0.0)) * V[b * no + m];
-    s += V[a * no + k] * t;
+// ---------------------------------------------------------------------------
+// Semicanonical AVOs, tridiagonal route.
+//  1. k_complement: Householder QR of the TOP virtuals V (nv x no); Q2 = the
+//     last m = nv - no columns of H_0 ... H_{no-1} (orthonormal complement).
+//  2. F_avo = Q2^T F_vv Q2 (GEMMs).
+//  3. k_tridiag: Householder tridiagonalisation of F_avo (packed in LDS),
+//     T = P^T F_avo P, P = G_0 ... G_{m-3}.
+//  4. k_tri_eig: eigenvalue k of T by wavefront multisection on Sturm counts,
+//     eigenvector by a twisted factorisation of T - lambda.
+//  5. k_cluster_mgs: Gram-Schmidt inside clusters of (nearly) equal eigenvalues.
+//  6. k_backtransform: Y = P Yt, one column per workgroup.
+//  AVO = Q2 Y, followed by a first-order Loewdin step (caller).
+// ---------------------------------------------------------------------------
+
+// Single workgroup (256 threads).  Vin: nv x no row-major.  Q2: nv x m row-major.
+__global__ __launch_bounds__(256) void k_complement(const double* Vin, int nv, int no, double* Q2) {
+  extern __shared__ double sm[];
+  double* W = sm;                    // nv x no working copy, column j reduced in place
+  double* vv = W + nv * no;          // reflectors: no x nv (row j = reflector j, entries j..nv-1)
+  __shared__ double beta[64];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+  for (int e = tid; e < nv * no; e += blockDim.x) W[e] = Vin[e];
+  __syncthreads();
+  for (int j = 0; j < no; ++j) {
+    double s = 0.0;
+    for (int i = j + 1 + tid; i < nv; i += blockDim.x) s += W[i * no + j] * W[i * no + j];
+    s = wave_sum(s);
+    if (l == 0) red[wave] = s;
+    __syncthreads();
+    double sig = red[0] + red[1] + red[2] + red[3];
+    double x0 = W[j * no + j];
+    double nrm = sqrt(x0 * x0 + sig);
+    double alpha = (x0 >= 0) ? -nrm : nrm;
+    double v0 = x0 - alpha;
+    double vtv = v0 * v0 + sig;
+    double b = (vtv > 0) ? 2.0 / vtv : 0.0;
+    for (int i = tid; i < nv; i += blockDim.x) vv[j * nv + i] = (i < j) ? 0.0 : (i == j ? v0 : W[i * no + j]);
+    if (tid == 0) beta[j] = b;
+    __syncthreads();
+    // apply H_j = 1 - b v v^T to the remaining columns c > j (one wave per column)
+    for (int c = j + 1 + wave; c < no; c += blockDim.x >> 6) {
+      double t = 0.0;
+      for (int i = l; i < nv; i += 64) if (i >= j) t += vv[j * nv + i] * W[i * no + c];
+      t = wave_sum(t) * b;
+      for (int i = l; i < nv; i += 64) if (i >= j) W[i * no + c] -= t * vv[j * nv + i];
+    }
+    __syncthreads();
   }
-  M[a * nv + b] = s;
+  // Q2 column c = H_0 H_1 ... H_{no-1} e_{no+c}; one wave per column
+  const int m = nv - no;
+  for (int c = wave; c < m; c += blockDim.x >> 6) {
+    double* q = Q2;   // column c, rows 0..nv-1, stride m
+    for (int i = l; i < nv; i += 64) q[i * m + c] = (i == no + c) ? 1.0 : 0.0;
+    for (int j = no - 1; j >= 0; --j) {
+      // each lane owns rows l, l+64, ...: no cross-lane dependence through memory
+      double t = 0.0;
+      for (int i = l; i < nv; i += 64) if (i >= j) t += vv[j * nv + i] * q[i * m + c];
+      t = wave_sum(t) * beta[j];
+      for (int i = l; i < nv; i += 64) if (i >= j) q[i * m + c] -= t * vv[j * nv + i];
+    }
+  }
 }
 
-// ---------------------------------------------------------------------------
-// Cyclic (round-robin parallel) Jacobi eigensolver for a symmetric n x n matrix
-// held packed (upper triangle) in LDS.  Rotation parameters of every round are
-// written to `rot` (2 doubles per pair); eigenvalues to `evals`.  The
-// eigenvectors are formed afterwards by k_jacobi_vectors.
-// rot layout: [sweep][round][pair] (c, s), P/2 pairs per round, P-1 rounds.
-// ---------------------------------------------------------------------------
 __device__ inline int pk(int r, int c, int n) {   // packed upper index (r <= c)
   return r * n - r * (r - 1) / 2 + (c - r);
 }
 
-__global__ __launch_bounds__(1024) void k_eig_jacobi(const double* __restrict__ Min, int n, int max_sweeps,
-                                                     double* rot, double* evals, int* info) {
-  extern __shared__ double A[];          // n(n+1)/2 packed
-  __shared__ double cs[2 * 256];
-  __shared__ int pp[256], qq[256];
-  __shared__ double offs[1024 / 64];
-  __shared__ double tot[1024 / 64];
-  __shared__ int done;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int P = (n + 1) / 2 * 2, npair = P / 2;
-  for (int r = 0; r < n; ++r)
-    for (int c = r + tid; c < n; c += nt) A[pk(r, c, n)] = Min[r * n + c];
+// Householder tridiagonalisation.  Ain: m x m row-major symmetric.  Single
+// workgroup of 1024 threads, A packed (upper) in dynamic LDS.
+// Outputs: refl (m x m, row k = reflector k on entries k+1..m-1), rbeta[m],
+// d[m] (diagonal), e[m] (e[k] = T[k][k+1]).
+__global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, double* refl, double* rbeta,
+                                                  double* d, double* e) {
+  extern __shared__ double A[];
+  __shared__ double v[256], p[256];
+  __shared__ double red[16];
+  __shared__ double sh[4];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, nw = blockDim.x >> 6;
+  for (int r = 0; r < m; ++r)
+    for (int c = r + tid; c < m; c += blockDim.x) A[pk(r, c, m)] = Ain[r * m + c];
   __syncthreads();
-  int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
-    // convergence test: off-diagonal vs diagonal Frobenius norm, both summed
-    // directly (a difference of the two would drown the test in cancellation)
-    double off = 0, dg = 0;
-    for (int r = 0; r < n; ++r)
-      for (int c = r + 1 + tid; c < n; c += nt) { double v = A[pk(r, c, n)]; off += v * v; }
-    for (int r = tid; r < n; r += nt) { double v = A[pk(r, r, n)]; dg += v * v; }
-    for (int o = 32; o > 0; o >>= 1) { off += __shfl_xor(off, o); dg += __shfl_xor(dg, o); }
-    if ((tid & 63) == 0) { offs[tid >> 6] = off; tot[tid >> 6] = dg; }
+  auto at = [&](int r, int c) -> double { return r <= c ? A[pk(r, c, m)] : A[pk(c, r, m)]; };
+  for (int k = 0; k < m - 2; ++k) {
+    // x = A[k][k+1..m-1]
+    double s = 0.0;
+    for (int i = k + 2 + tid; i < m; i += blockDim.x) { double x = A[pk(k, i, m)]; s += x * x; }
+    s = wave_sum(s);
+    if (l == 0) red[wave] = s;
     __syncthreads();
     if (tid == 0) {
-      double so = 0, sd = 0;
-      for (int w = 0; w < nt / 64; ++w) { so += offs[w]; sd += tot[w]; }
-      done = (so <= 1e-34 * sd);
+      double sig = 0.0;
+      for (int w = 0; w < nw; ++w) sig += red[w];
+      double x0 = A[pk(k, k + 1, m)];
+      double b = 0.0, alpha = x0, v0 = 0.0;
+      if (sig > 0.0) {
+        double nrm = sqrt(x0 * x0 + sig);
+        alpha = (x0 >= 0) ? -nrm : nrm;
+        v0 = x0 - alpha;
+        b = 2.0 / (v0 * v0 + sig);
+      }
+      sh[0] = b; sh[1] = alpha; sh[2] = v0;
     }
     __syncthreads();
-    if (done) break;
-    for (int r = 0; r < P - 1; ++r) {
-      for (int k = tid; k < npair; k += nt) {
-        auto player = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + r) % (P - 1); };
-        int p = player(k), q = player(P - 1 - k);
-        if (p > q) { int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          double apq = A[pk(p, q, n)];
-          if (apq != 0.0) {
-            double tau = (A[pk(q, q, n)] - A[pk(p, p, n)]) / (2.0 * apq);
-            double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
-        }
-        pp[k] = p; qq[k] = q;
-        cs[2 * k] = c; cs[2 * k + 1] = s;
-        int64_t o = ((int64_t)sweep * (P - 1) + r) * npair + k;
-        rot[2 * o] = c; rot[2 * o + 1] = s;
-      }
-      __syncthreads();
-      // A <- J^T A J, block by block over pairs (X, Y) with X <= Y
-      int nblk = npair * (npair + 1) / 2;
-      for (int bi = tid; bi < nblk; bi += nt) {
-        // decode bi -> (X, Y), X <= Y
-        int X = 0, rem = bi;
-        while (rem >= npair - X) { rem -= npair - X; ++X; }
-        int Y = X + rem;
-        int x0 = pp[X], x1 = qq[X], y0 = pp[Y], y1 = qq[Y];
-        double cx = cs[2 * X], sx = cs[2 * X + 1], cy = cs[2 * Y], sy = cs[2 * Y + 1];
-        bool vx1 = x1 < n, vy1 = y1 < n;
-        auto get = [&](int r, int c) -> double {
-          return (r <= c) ? A[pk(r, c, n)] : A[pk(c, r, n)];
-        };
-        auto put = [&](int r, int c, double v) {
-          if (r <= c) A[pk(r, c, n)] = v; else A[pk(c, r, n)] = v;
-        };
-        if (X == Y) {
-          if (!vx1) continue;
-          double app = get(x0, x0), aqq = get(x1, x1), apq = get(x0, x1);
-          double t = (cx != 0.0) ? sx / cx : 0.0;
-          put(x0, x0, app - t * apq);
-          put(x1, x1, aqq + t * apq);
-          put(x0, x1, 0.0);
-        } else {
-          // rows (x0,x1) with J_X, columns (y0,y1) with J_Y; J = [c s; -s c]
-          double a00 = get(x0, y0);
-          double a01 = vy1 ? get(x0, y1) : 0.0;
-          double a10 = vx1 ? get(x1, y0) : 0.0;
-          double a11 = (vx1 && vy1) ? get(x1, y1) : 0.0;
-          // left: rows' = J_X^T rows
-          double b00 = cx * a00 - sx * a10, b01 = cx * a01 - sx * a11;
-          double b10 = sx * a00 + cx * a10, b11 = sx * a01 + cx * a11;
-          // right: cols' = cols J_Y
-          double c00 = b00 * cy - b01 * sy, c01 = b00 * sy + b01 * cy;
-          double c10 = b10 * cy - b11 * sy, c11 = b10 * sy + b11 * cy;
-          put(x0, y0, c00);
-          if (vy1) put(x0, y1, c01);
-          if (vx1) put(x1, y0, c10);
-          if (vx1 && vy1) put(x1, y1, c11);
-        }
-      }
-      __syncthreads();
+    const double b = sh[0];
+    for (int i = k + 1 + tid; i < m; i += blockDim.x) {
+      double vi = (i == k + 1) ? sh[2] : A[pk(k, i, m)];
+      v[i] = (b > 0.0) ? vi : 0.0;
+      refl[k * m + i] = v[i];
     }
+    if (tid == 0) { rbeta[k] = b; e[k] = sh[1]; }
+    __syncthreads();
+    if (b > 0.0) {
+      // p = b A22 v : 8 threads per row
+      const int len = m - k - 1;
+      for (int t = tid; t < len * 8; t += blockDim.x) {
+        int i = k + 1 + t / 8, part = t % 8;
+        double acc = 0.0;
+        for (int j = k + 1 + part; j < m; j += 8) acc += at(i, j) * v[j];
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        acc += __shfl_xor(acc, 4);
+        if (part == 0) p[i] = b * acc;
+      }
+      __syncthreads();
+      double kk = 0.0;
+      for (int i = k + 1 + tid; i < m; i += blockDim.x) kk += v[i] * p[i];
+      kk = wave_sum(kk);
+      if (l == 0) red[wave] = kk;
+      __syncthreads();
+      double K = 0.0;
+      for (int w = 0; w < nw; ++w) K += red[w];
+      K *= 0.5 * b;
+      // w = p - K v (in place in p), then A22 -= v w^T + w v^T (upper part)
+      __syncthreads();
+      for (int i = k + 1 + tid; i < m; i += blockDim.x) p[i] -= K * v[i];
+      __syncthreads();
+      for (int i = k + 1 + wave; i < m; i += nw)
+        for (int j = i + l; j < m; j += 64) A[pk(i, j, m)] -= v[i] * p[j] + p[i] * v[j];
+    }
+    __syncthreads();
   }
-  for (int r = tid; r < n; r += nt) evals[r] = A[pk(r, r, n)];
-  if (tid == 0) info[0] = sweep;
+  for (int i = tid; i < m; i += blockDim.x) d[i] = A[pk(i, i, m)];
+  if (tid == 0 && m >= 2) e[m - 2] = A[pk(m - 2, m - 1, m)];
+  if (tid == 0) e[m - 1] = 0.0;
+  if (m == 1 && tid == 0) e[0] = 0.0;
 }
 
-// Z = J_1 J_2 ... J_R applied to the identity; one row of Z per workgroup of
-// one wavefront: z <- z J with z'_p = c z_p - s z_q, z'_q = s z_p + c z_q.
-// Z[n][n] row-major.  Launch: grid n, block 64, dynamic LDS n doubles.
-__global__ __launch_bounds__(64) void k_jacobi_vectors(const double* rot, int n, const int* sweeps, double* Z) {
-  extern __shared__ double zr[];
+// Number of eigenvalues of the tridiagonal (d, e) smaller than x.
+__device__ inline int sturm_count(const double* d, const double* e, int m, double x, double tiny) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < m; ++i) {
+    if (fabs(q) < tiny) q = -tiny;
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+// One workgroup (64 threads) per eigenvalue k (ascending).  evals[k], Yt[:, k].
+__global__ __launch_bounds__(64) void k_tri_eig(const double* d, const double* e, int m, double* evals,
+                                                double* Yt, double* work) {
+  const int k = blockIdx.x, l = threadIdx.x;
+  __shared__ double lo_s, hi_s;
+  if (l == 0) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+      double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0);
+      lo = fmin(lo, d[i] - r);
+      hi = fmax(hi, d[i] + r);
+    }
+    double span = fmax(hi - lo, 1e-300);
+    lo_s = lo - 1e-3 * span;
+    hi_s = hi + 1e-3 * span;
+  }
+  __syncthreads();
+  double lo = lo_s, hi = hi_s;
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  const double tiny = 1e-300 + 1e-30 * tnorm;
+  for (int it = 0; it < 40; ++it) {
+    double x = lo + (hi - lo) * (double)(l + 1) / 65.0;
+    int c = sturm_count(d, e, m, x, tiny);
+    // first lane whose point has more than k eigenvalues below it
+    unsigned long long mask = __ballot(c > k);
+    int first = mask ? __ffsll((long long)mask) - 1 : 64;
+    double nlo = (first == 0) ? lo : lo + (hi - lo) * (double)first / 65.0;
+    double nhi = (first == 64) ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
+    lo = nlo;
+    hi = nhi;
+    if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
+  }
+  const double lam = 0.5 * (lo + hi);
+  if (l == 0) {
+    evals[k] = lam;
+    // twisted factorisation of T - lam: forward D+ and backward D- pivots
+    double* Dp = work + (size_t)k * 2 * m;
+    double* Dm = Dp + m;
+    Dp[0] = d[0] - lam;
+    for (int i = 1; i < m; ++i) {
+      double q = Dp[i - 1];
+      if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
+      Dp[i] = d[i] - lam - e[i - 1] * e[i - 1] / q;
+    }
+    Dm[m - 1] = d[m - 1] - lam;
+    for (int i = m - 2; i >= 0; --i) {
+      double q = Dm[i + 1];
+      if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
+      Dm[i] = d[i] - lam - e[i] * e[i] / q;
+    }
+    int r = 0;
+    double best = 1e300;
+    for (int i = 0; i < m; ++i) {
+      double g = fabs(Dp[i] + Dm[i] - (d[i] - lam));
+      if (g < best) { best = g; r = i; }
+    }
+    double* y = Yt;   // column k, stride m
+    y[r * m + k] = 1.0;
+    double nrm = 1.0;
+    for (int i = r - 1; i >= 0; --i) {
+      double q = Dp[i];
+      if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
+      double v = -(e[i] / q) * y[(i + 1) * m + k];
+      y[i * m + k] = v;
+      nrm += v * v;
+    }
+    for (int i = r + 1; i < m; ++i) {
+      double q = Dm[i];
+      if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
+      double v = -(e[i - 1] / q) * y[(i - 1) * m + k];
+      y[i * m + k] = v;
+      nrm += v * v;
+    }
+    double inv = 1.0 / sqrt(nrm);
+    for (int i = 0; i < m; ++i) y[i * m + k] *= inv;
+  }
+}
+
+// Gram-Schmidt of eigenvectors inside clusters (relative gap below 1e-6).
+// Single workgroup of 64 threads; cheap when there are no clusters.
+__global__ __launch_bounds__(64) void k_cluster_mgs(const double* evals, int m, double* Yt) {
   const int l = threadIdx.x;
-  const int row = blockIdx.x;
-  for (int c = l; c < n; c += 64) zr[c] = (c == row) ? 1.0 : 0.0;
-  __syncthreads();
-  const int P = (n + 1) / 2 * 2, npair = P / 2;
-  const int ns = sweeps[0];
-  for (int sw = 0; sw < ns; ++sw)
-    for (int r = 0; r < P - 1; ++r) {
-      int64_t base = ((int64_t)sw * (P - 1) + r) * npair;
-      for (int k = l; k < npair; k += 64) {
-        int p = (k == 0) ? 0 : 1 + (k - 1 + r) % (P - 1);
-        int q = 1 + (P - 1 - k - 1 + r) % (P - 1);
-        if (p > q) { int t = p; p = q; q = t; }
-        if (q >= n) continue;
-        double c = rot[2 * (base + k)], s = rot[2 * (base + k) + 1];
-        double zp = zr[p], zq = zr[q];
-        zr[p] = c * zp - s * zq;
-        zr[q] = s * zp + c * zq;
+  double tn = 0.0;
+  for (int k = 0; k < m; ++k) tn = fmax(tn, fabs(evals[k]));
+  int start = 0;
+  for (int k = 1; k < m; ++k) {
+    if (evals[k] - evals[k - 1] > 1e-6 * tn) { start = k; continue; }
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = start; j < k; ++j) {
+        double t = 0.0;
+        for (int i = l; i < m; i += 64) t += Yt[i * m + j] * Yt[i * m + k];
+        t = wave_sum(t);
+        for (int i = l; i < m; i += 64) Yt[i * m + k] -= t * Yt[i * m + j];
+        __syncthreads();
       }
-      __syncthreads();
-    }
-  for (int c = l; c < n; c += 64) Z[(int64_t)row * n + c] = zr[c];
+    double s = 0.0;
+    for (int i = l; i < m; i += 64) s += Yt[i * m + k] * Yt[i * m + k];
+    s = wave_sum(s);
+    double inv = 1.0 / sqrt(s);
+    for (int i = l; i < m; i += 64) Yt[i * m + k] *= inv;
+    __syncthreads();
+  }
 }
 
-// Sort eigenpairs ascending, drop the n_occ lowest (the TOP-virtual span held at
-// `shift`), sign each AVO (largest-|entry| positive) and assemble the rotation
-//   R[:no,:no] = U,  R[no:, no:no+no] = V,  R[no:, 2no:] = AVOs.
-__global__ void k_assemble_r(const double* U, const double* V, const double* Z, const double* evals,
-                             int no, int nv, double* R, double* avo_eps) {
-  __shared__ int order[1024];
-  const int n = no + nv;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    for (int k = 0; k < nv; ++k) order[k] = k;
-    for (int i = 1; i < nv; ++i) {          // insertion sort by eigenvalue
-      int key = order[i]; double kv = evals[key]; int j = i - 1;
-      while (j >= 0 && evals[order[j]] > kv) { order[j + 1] = order[j]; --j; }
-      order[j + 1] = key;
-    }
+// Y[:, k] = G_0 ... G_{m-3} Yt[:, k]; one workgroup (64 threads) per column.
+__global__ __launch_bounds__(64) void k_backtransform(const double* refl, const double* rbeta, int m,
+                                                      const double* Yt, double* Y) {
+  extern __shared__ double y[];
+  const int k = blockIdx.x, l = threadIdx.x;
+  for (int i = l; i < m; i += 64) y[i] = Yt[i * m + k];
+  __syncthreads();
+  for (int j = m - 3; j >= 0; --j) {
+    double b = rbeta[j];
+    if (b == 0.0) continue;
+    double t = 0.0;
+    for (int i = l; i < m; i += 64) if (i > j) t += refl[j * m + i] * y[i];
+    t = wave_sum(t) * b;
+    for (int i = l; i < m; i += 64) if (i > j) y[i] -= t * refl[j * m + i];
+    __syncthreads();
   }
+  for (int i = l; i < m; i += 64) Y[i * m + k] = y[i];
+}
+
+// R[:no,:no] = U,  R[no:, no:2no] = V,  R[no:, 2no + c] = AVO[:, c] (signed:
+// largest-|entry| positive);  avo_eps[c] = eigenvalue c.
+__global__ void k_assemble_r2(const double* U, const double* V, const double* AVO, const double* evals, int no,
+                              int nv, double* R, double* avo_eps) {
+  const int n = no + nv, m = nv - no;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int e = tid; e < n * n; e += gridDim.x * blockDim.x) R[e] = 0.0;
   __syncthreads();
-  for (int e = tid; e < n * n; e += blockDim.x) R[e] = 0.0;
-  __syncthreads();
+  // (single block launch: the zeroing above and the writes below are ordered by the barrier)
   for (int e = tid; e < no * no; e += blockDim.x) R[(e / no) * n + (e % no)] = U[e];
   for (int e = tid; e < nv * no; e += blockDim.x) R[(no + e / no) * n + no + (e % no)] = V[e];
-  for (int k = tid; k < nv - no; k += blockDim.x) {
-    int src = order[no + k];
-    // eigenvector = column src of Z (Z rows are e_r^T J...; A = Z diag Z^T)
+  for (int c = tid; c < m; c += blockDim.x) {
     double best = 0, sg = 1.0;
     for (int a = 0; a < nv; ++a) {
-      double v = Z[a * nv + src];
+      double v = AVO[a * m + c];
       if (fabs(v) > best) { best = fabs(v); sg = v < 0 ? -1.0 : 1.0; }
     }
-    for (int a = 0; a < nv; ++a) R[(no + a) * n + 2 * no + k] = sg * Z[a * nv + src];
-    avo_eps[k] = evals[src];
+    for (int a = 0; a < nv; ++a) R[(no + a) * n + 2 * no + c] = sg * AVO[a * m + c];
+    avo_eps[c] = evals[c];
   }
 }
 

@@ -16,30 +16,29 @@
 namespace esmp2 {
 
 // f^Phi_ov = F~_ov - G[gamma - gamma_Phi]_ov, G[g]_pq = sum_rs g_rs((pq|rs) - (ps|rq)/2),
-// gamma - gamma_Phi = diag(-lam_l^2 on l, +lam_l^2 on l').
-__global__ void k_fphi(const double* Ft, const double* Bov, const double* Bvt, const double* Boo,
-                       const double* lam, int no, int nv, int naux, double* fphi) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= no * nv) return;
-  int i = e / nv, a = e % nv;
-  int n = no + nv;
+// gamma - gamma_Phi = diag(-lam_l^2 on l, +lam_l^2 on l').  One wavefront per (i, a),
+// lanes over the auxiliary index.
+__global__ __launch_bounds__(64) void k_fphi(const double* Ft, const double* Bov, const double* Bvt,
+                                             const double* Boo, const double* lam, int no, int nv, int naux,
+                                             double* fphi) {
+  const int e = blockIdx.x, l = threadIdx.x;
+  const int i = e / nv, a = e % nv, n = no + nv;
   double J = 0, Kv = 0, Ko = 0;
-  for (int Q = 0; Q < naux; ++Q) {
+  for (int Q = l; Q < naux; Q += 64) {
     const double* bov = Bov + (int64_t)Q * no * nv;
     const double* bvt = Bvt + (int64_t)Q * nv * no;
     const double* boo = Boo + (int64_t)Q * no * no;
-    double d = 0, kv = 0, ko = 0;
-    for (int l = 0; l < no; ++l) {
-      double w = lam[l] * lam[l];
-      d += w * (bvt[l * no + l] - boo[l * no + l]);
-      kv += w * bov[i * nv + l] * bvt[a * no + l];
-      ko += w * boo[i * no + l] * bov[l * nv + a];
+    double dq = 0;
+    for (int k = 0; k < no; ++k) {
+      double w = lam[k] * lam[k];
+      dq += w * (bvt[k * no + k] - boo[k * no + k]);
+      Kv += w * bov[i * nv + k] * bvt[a * no + k];
+      Ko += w * boo[i * no + k] * bov[k * nv + a];
     }
-    J += d * bov[i * nv + a];
-    Kv += kv;
-    Ko += ko;
+    J += dq * bov[i * nv + a];
   }
-  fphi[e] = Ft[i * n + no + a] - (J - 0.5 * Kv + 0.5 * Ko);
+  double t = wave_sum(J - 0.5 * Kv + 0.5 * Ko);
+  if (l == 0) fphi[e] = Ft[i * n + no + a] - t;
 }
 
 // X[Q][(i,a)] = c_i Bvt[Q][a][i] - c_a Boo[Q][a][i]  (second term only for a < n_occ)
