@@ -79,6 +79,8 @@ struct esmp2_handle_ {
   double *S, *side, *side_tr;
   int2* jobs = nullptr;
   int njobs = 0;
+  int4* jobs4 = nullptr;
+  int njobs4 = 0;
   // Krylov vectors
   double *x, *r, *p, *q;
   // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream
@@ -219,7 +221,24 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
   for (int bx = 0; bx < 7; ++bx)
     for (int k = 0; k < nbat[bx]; ++k) jobs.push_back(make_int2(bx, k));
   h->njobs = (int)jobs.size();
-  if (!dalloc(h, &h->jobs, jobs.size())) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
+  // k_vv2 jobs: dense-output work first (heaviest), then triangular outputs
+  std::vector<int4> j4;
+  // (box, batch or i, storage/output format code of k_vv3, j)
+  for (int k = 0; k < (no - 1) * (no - 1); ++k) j4.push_back(make_int4(B_H22, k, 2, 0));
+  for (int k = 0; k < d.npo; ++k) j4.push_back(make_int4(B_H12, k, 2, 0));
+  for (int i = 0; i < no; ++i)
+    for (int j = i + 1; j < no; ++j) j4.push_back(make_int4(B_S2, i, 3, j));
+  for (int k = 0; k < (no - 1) * (no - 1); ++k) j4.push_back(make_int4(B_H21, k, 0, 0));
+  for (int k = 0; k < d.npo; ++k) j4.push_back(make_int4(B_H11, k, 0, 0));
+  for (int k = 0; k < d.npo; ++k) j4.push_back(make_int4(B_T2, k, 0, 0));
+  for (int k = 0; k < d.npo1; ++k) j4.push_back(make_int4(B_T3, k, 1, 0));
+  for (int i = 0; i < no; ++i) j4.push_back(make_int4(B_S2, i, 4, i));
+  h->njobs4 = (int)j4.size();
+  if (!dalloc(h, &h->jobs, jobs.size()) || !dalloc(h, &h->jobs4, j4.size())) {
+    release(h);
+    return fail(h, ESMP2_OOM, "device allocation failed");
+  }
+  ESMP2_HIP(hipMemcpyAsync(h->jobs4, j4.data(), j4.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->jobs, jobs.data(), jobs.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->F, F, sizeof(double) * n * n, hipMemcpyDefault, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->B, B, sizeof(double) * (size_t)na * n * n, hipMemcpyDefault, h->stream));
@@ -439,7 +458,7 @@ static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
   const int nside = d.npo1 + 2 * d.npo + 2 * n2;
   hipLaunchKernelGGL(k_side, dim3(nside), dim3(256), 0, s, sa);
   // virtual-pair Sylvester products (+ diagonal constants)
-  VVArgs va{d, x, h->S, y, h->Fd, h->Fl, h->side_tr, h->jobs};
+  VVArgs va{d, x, h->S, y, h->Fd, h->Fl, h->side_tr, h->jobs, h->jobs4};
   const int tiles = d.mv / 16;
   int tw = (tiles + 1) / 2;
   if (tw > 5) tw = 5;
@@ -454,7 +473,13 @@ static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
       e0 = e1 = nullptr;
     }
   }
-  switch (tw) {
+  if (d.mv == 160) {
+    hipLaunchKernelGGL(k_vv3<10>, dim3(h->njobs4), dim3(256), 0, s, va);
+  } else if (d.mv == 112) {
+    hipLaunchKernelGGL(k_vv3<7>, dim3(h->njobs4), dim3(256), 0, s, va);
+  } else if (d.mv == 80) {
+    hipLaunchKernelGGL(k_vv3<5>, dim3(h->njobs4), dim3(256), 0, s, va);
+  } else switch (tw) {
     case 1: hipLaunchKernelGGL(k_vv<1>, grid, dim3(256), 0, s, va); break;
     case 2: hipLaunchKernelGGL(k_vv<2>, grid, dim3(256), 0, s, va); break;
     case 3: hipLaunchKernelGGL(k_vv<3>, grid, dim3(256), 0, s, va); break;

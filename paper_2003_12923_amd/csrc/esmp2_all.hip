@@ -2,5 +2,6 @@
 #include "linalg.hip"
 #include "rhs.hip"
 #include "sigma.hip"
+#include "vv3.hip"
 #include "pcg.hip"
 #include "api.hip"

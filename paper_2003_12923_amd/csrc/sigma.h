@@ -13,6 +13,7 @@ struct VVArgs {
   const double* Fl;      // F_vv + kappa/2, padded mv x mv (L boxes)
   double* side_tr;       // transfer rows: [npo H1P2 batches][nv], then [(no-1)^2 H2P2][nv]
   const int2* jobs;      // (box, batch)
+  const int4* jobs4;     // (box, batch or i, kind, j) for k_vv2
 };
 
 struct SideArgs {
@@ -41,6 +42,8 @@ struct GatherArgs {
 
 __global__ void k_sym_s2(Dims d, const double* x, double* S);
 template <int TW> __global__ void k_vv(VVArgs A);
+__global__ void k_vv2(VVArgs A);
+template <int NT> __global__ void k_vv3(VVArgs A);
 __global__ void k_side(SideArgs A);
 __global__ void k_gather(GatherArgs A);
 

@@ -462,3 +462,150 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
 }
 
 }  // namespace esmp2
+
+namespace esmp2 {
+
+// ---------------------------------------------------------------------------
+// Sylvester kernel for mv <= 160 (at most 10 x 10 tiles of 16), one job per
+// workgroup of 4 wavefronts:
+//   JK_FULL   dense output (H1P2, H2P2)
+//   JK_UPPER  antisymmetric output: only tiles on/above the diagonal
+//   JK_S2PAIR flip-symmetrised S2 pair (i < j): Y written to (i,j), Y^T to (j,i)
+//   JK_S2DIAG S2 with i = j: symmetric Y, tiles on/above the diagonal
+// Global -> LDS staging of the next 16-wide K chunk is prefetched into
+// registers while the current chunk runs on the matrix cores.
+// ---------------------------------------------------------------------------
+enum { JK_FULL = 0, JK_UPPER = 1, JK_S2PAIR = 2, JK_S2DIAG = 3 };
+
+struct Rect { int r0, r1, c0, c1; bool mask; };
+
+__device__ inline Rect wave_rect(int kind, int wave, int T) {
+  const int h = (T + 1) / 2;
+  Rect R;
+  if (kind == JK_FULL || kind == JK_S2PAIR) {
+    int wr = wave >> 1, wc = wave & 1;
+    R.r0 = wr * h; R.r1 = min(T, (wr + 1) * h);
+    R.c0 = wc * h; R.c1 = min(T, (wc + 1) * h);
+    R.mask = false;
+  } else {
+    const int split = h + (T - h) / 2;
+    switch (wave) {
+      case 0: R.r0 = 0; R.r1 = h; R.c0 = 0; R.c1 = h; R.mask = true; break;
+      case 1: R.r0 = 0; R.r1 = h; R.c0 = split; R.c1 = T; R.mask = false; break;
+      case 2: R.r0 = 0; R.r1 = h; R.c0 = h; R.c1 = split; R.mask = false; break;
+      default: R.r0 = h; R.r1 = T; R.c0 = h; R.c1 = T; R.mask = true; break;
+    }
+  }
+  return R;
+}
+
+__global__ __launch_bounds__(256) void k_vv2(VVArgs A) {
+  constexpr int MV = 160, PREF = (MV * 16) / 256;
+  __shared__ double As[16][MV + 1];
+  __shared__ double Bs[16][MV + 1];
+  const int4 jb = A.jobs4[blockIdx.x];
+  const int box = jb.x, kind = jb.z;
+  const Dims& d = A.d;
+  const int mv = d.mv, T = mv / 16;
+  JobView v;
+  int si = 0, sj = 0;
+  if (box == B_S2) {
+    si = jb.y; sj = jb.w;
+    v.fmt = F_DENSE; v.m = d.nv; v.tr = nullptr;
+    v.src = A.S + ((int64_t)si * d.no + sj) * d.nv * d.nv;
+    v.dst = A.y + d.off[B_S2] + ((int64_t)si * d.no + sj) * d.nv * d.nv;
+  } else {
+    v = job_view(A, box, jb.y);
+  }
+  const double* F = (box == B_T2 || box == B_S2) ? A.Fd : A.Fl;
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+  const Rect R = wave_rect(kind, wave, T);
+  f64x4 acc[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  double pa[PREF], pb[PREF];
+  auto fetch = [&](int k0) {
+    const bool second = k0 >= mv;
+    const int kb = second ? k0 - mv : k0;
+#pragma unroll
+    for (int t = 0; t < PREF; ++t) {
+      int e = tid + 256 * t;
+      double va = 0.0, vb = 0.0;
+      if (e < mv * 16) {
+        int r = e >> 4, kk = e & 15;
+        va = second ? xget(v, r, kb + kk) : F[r * mv + kb + kk];
+        int c = e % mv, k2 = e / mv;
+        vb = second ? F[(kb + k2) * mv + c] : xget(v, kb + k2, c);
+      }
+      pa[t] = va;
+      pb[t] = vb;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int t = 0; t < PREF; ++t) {
+      int e = tid + 256 * t;
+      if (e < mv * 16) {
+        As[e & 15][e >> 4] = pa[t];
+        Bs[e / mv][e % mv] = pb[t];
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < 2 * mv; k0 += 16) {
+    __syncthreads();
+    stash();
+    __syncthreads();
+    if (k0 + 16 < 2 * mv) fetch(k0 + 16);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      double a[5], b[5];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        int rr = (R.r0 + t) * 16 + (l & 15), cc = (R.c0 + t) * 16 + (l & 15);
+        a[t] = (R.r0 + t < R.r1) ? As[ks * 4 + (l >> 4)][rr] : 0.0;
+        b[t] = (R.c0 + t < R.c1) ? Bs[ks * 4 + (l >> 4)][cc] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const int ti = R.r0 + i, tj = R.c0 + j;
+          if (ti < R.r1 && tj < R.c1 && (!R.mask || tj >= ti)) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
+        }
+    }
+  }
+  // epilogue
+  double* dstT = (box == B_S2) ? A.y + d.off[B_S2] + ((int64_t)sj * d.no + si) * d.nv * d.nv : nullptr;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int ti = R.r0 + i, tj = R.c0 + j;
+      if (!(ti < R.r1 && tj < R.c1 && (!R.mask || tj >= ti))) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = ti * 16 + mfma_row(l, q), c = tj * 16 + (l & 15);
+        const double val = acc[i][j][q];
+        if (box == B_S2) {
+          if (r < d.nv && c < d.nv) {
+            if (kind == JK_S2PAIR) {
+              v.dst[r * d.nv + c] = val;
+              dstT[c * d.nv + r] = val;
+            } else if (ti == tj) {
+              v.dst[r * d.nv + c] = val;
+            } else {
+              v.dst[r * d.nv + c] = val;
+              v.dst[c * d.nv + r] = val;
+            }
+          }
+        } else {
+          yput(v, r, c, val);
+        }
+      }
+    }
+}
+
+}  // namespace esmp2
