@@ -81,6 +81,7 @@ struct esmp2_handle_ {
   int njobs = 0;
   int4* jobs4 = nullptr;
   int njobs4 = 0;
+  int* pairs = nullptr;          // (p << 16) | q tables: virtual pairs, shifted virtual, occupied, shifted occupied
   // Krylov vectors
   double *x, *r, *p, *q;
   // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream
@@ -234,10 +235,18 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
   for (int k = 0; k < d.npo1; ++k) j4.push_back(make_int4(B_T3, k, 1, 0));
   for (int i = 0; i < no; ++i) j4.push_back(make_int4(B_S2, i, 4, i));
   h->njobs4 = (int)j4.size();
-  if (!dalloc(h, &h->jobs, jobs.size()) || !dalloc(h, &h->jobs4, j4.size())) {
+  std::vector<int> pairs;
+  auto add_pairs = [&](int m) {
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) pairs.push_back((p << 16) | q);
+  };
+  add_pairs(nv); add_pairs(nv - 1); add_pairs(no); add_pairs(no - 1);
+  if (!dalloc(h, &h->jobs, jobs.size()) || !dalloc(h, &h->jobs4, j4.size()) || !dalloc(h, &h->pairs, pairs.size())) {
     release(h);
     return fail(h, ESMP2_OOM, "device allocation failed");
   }
+  if (!pairs.empty())
+    ESMP2_HIP(hipMemcpyAsync(h->pairs, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->jobs4, j4.data(), j4.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->jobs, jobs.data(), jobs.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->F, F, sizeof(double) * n * n, hipMemcpyDefault, h->stream));
@@ -457,8 +466,22 @@ static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
   sa.h22_ut = take(n2); sa.h22_i = take(n2); sa.h22_uk = take(n2);
   const int nside = d.npo1 + 2 * d.npo + 2 * n2;
   hipLaunchKernelGGL(k_side, dim3(nside), dim3(256), 0, s, sa);
-  // virtual-pair Sylvester products (+ diagonal constants)
-  VVArgs va{d, x, h->S, y, h->Fd, h->Fl, h->side_tr, h->jobs, h->jobs4};
+  GatherArgs ga{};
+  ga.d = d; ga.x = x; ga.S = h->S; ga.y = y; ga.fo = h->fo; ga.fv = h->fv; ga.fov = h->fov; ga.side_tr = h->side_tr;
+  ga.t3_t = sa.t3_t; ga.t3_p1 = sa.t3_p1; ga.t3_p2 = sa.t3_p2; ga.h11_p1 = sa.h11_p1; ga.h11_p2 = sa.h11_p2;
+  ga.h12_t = sa.h12_t; ga.h12_u1 = sa.h12_u1; ga.h12_u2 = sa.h12_u2; ga.h21_t = sa.h21_t; ga.h21_k = sa.h21_k;
+  ga.h22_ut = sa.h22_ut; ga.h22_i = sa.h22_i; ga.h22_uk = sa.h22_uk;
+  // tile prefix sums per box for the occupied-index kernels
+  const int inner[7] = {d.npv, nv * nv, d.npv1, d.npv, (nv - 1) * (nv - 1), d.npv, (nv - 1) * (nv - 1)};
+  const int nbat[7] = {d.npo, no * no, d.npo1, d.npo, d.npo, (no - 1) * (no - 1), (no - 1) * (no - 1)};
+  int maxb = 1;
+  for (int k = 0; k < 7; ++k)
+    if (nbat[k] > 0 && inner[k] > 0) maxb = std::max(maxb, nbat[k]);
+  const size_t lds_oo = sizeof(double) * (size_t)2 * maxb * (GO + 1) + 256 * sizeof(int);
+  // occupied-index action on the matrix cores when the occupied range fits one 16x16 tile
+  const bool oo_mfma = no <= 16 && lds_oo <= 160 * 1024 - 2048;
+  // virtual-pair Sylvester products (+ diagonal constants, + per-element couplings when fused)
+  VVArgs va{d, x, h->S, y, h->Fd, h->Fl, h->side_tr, h->jobs, h->jobs4, ga, 0};
   const int tiles = d.mv / 16;
   int tw = (tiles + 1) / 2;
   if (tw > 5) tw = 5;
@@ -490,12 +513,23 @@ static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
     (void)hipEventRecord(e1, s);
     h->ev_vv.push_back({e0, e1});
   }
-  GatherArgs ga{};
-  ga.d = d; ga.x = x; ga.S = h->S; ga.y = y; ga.fo = h->fo; ga.fv = h->fv; ga.fov = h->fov; ga.side_tr = h->side_tr;
-  ga.t3_t = sa.t3_t; ga.t3_p1 = sa.t3_p1; ga.t3_p2 = sa.t3_p2; ga.h11_p1 = sa.h11_p1; ga.h11_p2 = sa.h11_p2;
-  ga.h12_t = sa.h12_t; ga.h12_u1 = sa.h12_u1; ga.h12_u2 = sa.h12_u2; ga.h21_t = sa.h21_t; ga.h21_k = sa.h21_k;
-  ga.h22_ut = sa.h22_ut; ga.h22_i = sa.h22_i; ga.h22_uk = sa.h22_uk;
-  hipLaunchKernelGGL(k_gather, dim3(nblk(d.off[7])), dim3(256), 0, s, ga);
+  if (oo_mfma) {
+    int pre[8] = {0};
+    for (int k = 0; k < 7; ++k) {
+      int nt = (nbat[k] > 0 && inner[k] > 0) ? (inner[k] + GO - 1) / GO : 0;
+      pre[k + 1] = pre[k] + nt;
+    }
+    const int* pv = h->pairs;
+    const int* pv1 = pv + d.npv;
+    const int* po = pv1 + d.npv1;
+    const int* po1 = po + d.npo;
+    hipLaunchKernelGGL(k_gather4, dim3(nblk(d.off[7])), dim3(256), 0, s, ga, pv, pv1, po, po1);
+    ESMP2_HIP(hipFuncSetAttribute((const void*)k_oo, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_oo));
+    hipLaunchKernelGGL(k_oo, dim3(pre[7]), dim3(256), lds_oo, s, ga, make_int4(pre[1], pre[2], pre[3], pre[4]),
+                       make_int4(pre[5], pre[6], pre[7], 0));
+  } else {
+    hipLaunchKernelGGL(k_gather, dim3(nblk(d.off[7])), dim3(256), 0, s, ga);
+  }
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }

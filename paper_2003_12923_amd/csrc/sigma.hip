@@ -461,6 +461,143 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
   A.y[g] += y;
 }
 
+// As k_gather, without the occupied-index contraction (k_oo does it on the
+// matrix cores) and without its two transfer rows; pair indices decoded from
+// tables (pv: virtual pairs of nv, pv1: of nv-1, po: occupied pairs of no,
+// po1: of no-1; each entry (p << 16) | q).
+__global__ __launch_bounds__(256) void k_gather4(GatherArgs A, const int* pv, const int* pv1, const int* po,
+                                                  const int* po1) {
+  const Dims& d = A.d;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.off[7]) return;
+  const int no = d.no, nv = d.nv;
+  Look L{d, A.x, A.S};
+  const double* fo = A.fo;     // fo[m*no + i]
+  const double* fv = A.fv;     // fv[a*nv + b]
+  const double* fov = A.fov;   // fov[i*nv + a]
+  auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
+  const double ftt = FOV(0, 0);
+  int64_t loc;
+  const int box = box_of_g(d, g, loc);
+  double y = 0.0;
+  switch (box) {
+    case B_T2: {
+      int i, j, a, b;
+      { int t = po[loc / d.npv]; i = t >> 16; j = t & 0xffff; t = pv[loc % d.npv]; a = t >> 16; b = t & 0xffff; }
+      if (i >= 1 && a >= 1) y += ftt * L.T3(i, j, a, b);
+      y += ftt * L.H11(i, j, a, b);
+      if (i == 0 && a >= 1)
+        for (int m = 1; m < no; ++m) y -= FOV(m, 0) * L.T3(m, j, a, b);
+      if (i == 0)
+        for (int m = 1; m < no; ++m) y += FOV(m, 0) * L.H21(m, j, a, b);
+      if (a == 0) {
+        int po = tri_idx(i, j, no);
+        if (i >= 1) y -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
+        y += A.h12_t[po * nv + b];
+        if (i == 0) {
+          for (int m = 1; m < no; ++m) {
+            if (m < j) y += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
+            else if (m > j) y -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
+            y += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
+          }
+        }
+      }
+      break;
+    }
+    case B_S2: {
+      int64_t r = loc;
+      int b = r % nv; r /= nv;
+      int a = r % nv; r /= nv;
+      int j = r % no, i = r / no;
+      // d(p,q,x,z) + d(q,p,z,x): de-excitation of the mixed-spin L-triples
+      for (int rep = 0; rep < 2; ++rep) {
+        int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
+        double dd = 0.0;
+        if (p == 0 && xx == 0) {
+          for (int m = 0; m < no; ++m) {
+            if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
+            else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
+          }
+        }
+        if (p == 0 && xx >= 1 && z >= 1)
+          for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
+        if (p == 0 && xx >= 1 && z == 0) {
+          for (int m = 0; m < no; ++m) {
+            if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
+            else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
+          }
+        }
+        if (p >= 1 && q >= 1 && xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
+        if (p >= 1 && q == 0 && xx == 0)
+          for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
+        if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) dd += ftt * L.H22(p, q, xx, z);
+        if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
+          for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
+        if (p >= 1 && q >= 1 && xx >= 1 && z == 0) dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
+        if (p >= 1 && q == 0 && xx >= 1 && z == 0)
+          for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
+        y += dd;
+      }
+      break;
+    }
+    case B_T3: {
+      int j, k, b, c;
+      { int t = po1[loc / d.npv1]; j = t >> 16; k = t & 0xffff; t = pv1[loc % d.npv1]; b = t >> 16; c = t & 0xffff; }
+      ++j; ++k; ++b; ++c;
+      y += ftt * L.T2(j, k, b, c) - FOV(j, 0) * L.T2(0, k, b, c) + FOV(k, 0) * L.T2(0, j, b, c)
+         - FOV(0, b) * L.T2(j, k, 0, c) + FOV(j, b) * L.T2(0, k, 0, c) - FOV(k, b) * L.T2(0, j, 0, c)
+         + FOV(0, c) * L.T2(j, k, 0, b) - FOV(j, c) * L.T2(0, k, 0, b) + FOV(k, c) * L.T2(0, j, 0, b);
+      break;
+    }
+    case B_H11: {
+      int j, k, b, c;
+      { int t = po[loc / d.npv]; j = t >> 16; k = t & 0xffff; t = pv[loc % d.npv]; b = t >> 16; c = t & 0xffff; }
+      if (j == 0)
+        for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H21(m, k, b, c);
+      y += ftt * L.T2(j, k, b, c);
+      y += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
+         - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
+      break;
+    }
+    case B_H12: {
+      int m1 = nv - 1;
+      int j, k;
+      { int t = po[loc / (m1 * m1)]; j = t >> 16; k = t & 0xffff; }
+      int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
+      y += fv[a * nv + 0] * L.H11(j, k, 0, c);
+      if (j == 0)
+        for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H22(m, k, a, c);
+      y += FOV(0, a) * L.T2(j, k, 0, c);
+      y += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
+         - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
+      break;
+    }
+    case B_H21: {
+      int o = loc / d.npv, b, c;
+      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+      { int t = pv[loc % d.npv]; b = t >> 16; c = t & 0xffff; }
+      y -= fo[0 * no + i] * L.H11(0, k, b, c);
+      y += FOV(i, 0) * L.T2(0, k, b, c);
+      y += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
+         - FOV(0, c) * L.St(i, k, 0, b) + FOV(k, c) * L.St(i, 0, 0, b);
+      break;
+    }
+    default: {
+      int m1 = nv - 1;
+      int o = loc / (m1 * m1);
+      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+      int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
+      y -= fo[0 * no + i] * L.H12(0, k, a, c);
+      y += fv[a * nv + 0] * L.H21(i, k, 0, c);
+      y += FOV(i, a) * L.T2(0, k, 0, c);
+      y += ftt * L.St(i, k, a, c) - FOV(k, 0) * L.St(i, 0, a, c)
+         - FOV(0, c) * L.St(i, k, a, 0) + FOV(k, c) * L.St(i, 0, a, 0);
+      break;
+    }
+  }
+  A.y[g] += y;
+}
+
 }  // namespace esmp2
 
 namespace esmp2 {
@@ -606,6 +743,548 @@ __global__ __launch_bounds__(256) void k_vv2(VVArgs A) {
         }
       }
     }
+}
+
+}  // namespace esmp2
+
+namespace esmp2 {
+
+// ---------------------------------------------------------------------------
+// Tiled gather: one workgroup = one box x a tile of GT consecutive inner
+// (virtual-pair) indices x all occupied batches of that box, staged in LDS;
+// the occupied-index Fock action reads the tile, the remaining terms (box
+// transfers, doubles <-> L-triples, side contractions) are read from global.
+// y += result.
+// ---------------------------------------------------------------------------
+constexpr int GT = 32;
+
+__device__ inline int sgn_pair(int p, int q) { return p < q ? 1 : -1; }
+
+__global__ __launch_bounds__(256) void k_gather2(GatherArgs A, int4 tiles0, int4 tiles1) {
+  extern __shared__ double tile[];                  // nbat x (GT + 1)
+  const Dims& d = A.d;
+  const int no = d.no, nv = d.nv;
+  // box of this workgroup from the tile prefix sums
+  const int tstart[8] = {0, tiles0.x, tiles0.y, tiles0.z, tiles0.w, tiles1.x, tiles1.y, tiles1.z};
+  int box = 0;
+  while (box < 6 && (int)blockIdx.x >= tstart[box + 1]) ++box;
+  const int t0 = ((int)blockIdx.x - tstart[box]) * GT;
+  int nbat, inner;
+  switch (box) {
+    case B_T2: case B_H11: nbat = d.npo; inner = d.npv; break;
+    case B_S2: nbat = no * no; inner = nv * nv; break;
+    case B_T3: nbat = d.npo1; inner = d.npv1; break;
+    case B_H12: nbat = d.npo; inner = (nv - 1) * (nv - 1); break;
+    case B_H21: nbat = (no - 1) * (no - 1); inner = d.npv; break;
+    default: nbat = (no - 1) * (no - 1); inner = (nv - 1) * (nv - 1); break;
+  }
+  const double* src = (box == B_S2) ? A.S : A.x + d.off[box];
+  const int tw = min(GT, inner - t0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nbat * GT; e += blockDim.x) {
+    int o = e / GT, vl = e % GT;
+    tile[o * (GT + 1) + vl] = (vl < tw) ? src[(int64_t)o * inner + t0 + vl] : 0.0;
+  }
+  __syncthreads();
+  const int vl = tid % GT, grp = tid / GT, ngrp = blockDim.x / GT;
+  if (vl >= tw) return;
+  const int v = t0 + vl;
+  Look L{d, A.x, A.S};
+  const double* fo = A.fo;
+  const double* fv = A.fv;
+  const double* fov = A.fov;
+  auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
+  const double ftt = FOV(0, 0);
+  auto T = [&](int o) { return tile[o * (GT + 1) + vl]; };
+  double* y = A.y + d.off[box];
+  switch (box) {
+    case B_T2: {
+      int a, b;
+      tri_pq(v, nv, a, b);
+      for (int o = grp; o < nbat; o += ngrp) {
+        int i, j;
+        tri_pq(o, no, i, j);
+        double acc = 0.0;
+        for (int m = 0; m < no; ++m) {
+          if (m != j) acc -= fo[m * no + i] * sgn_pair(m, j) * T(tri_idx(min(m, j), max(m, j), no));
+          if (m != i) acc -= fo[m * no + j] * sgn_pair(i, m) * T(tri_idx(min(i, m), max(i, m), no));
+        }
+        if (i >= 1 && a >= 1) acc += ftt * L.T3(i, j, a, b);
+        acc += ftt * L.H11(i, j, a, b);
+        if (i == 0 && a >= 1)
+          for (int m = 1; m < no; ++m) acc -= FOV(m, 0) * L.T3(m, j, a, b);
+        if (i == 0)
+          for (int m = 1; m < no; ++m) acc += FOV(m, 0) * L.H21(m, j, a, b);
+        if (a == 0) {
+          if (i >= 1) acc -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
+          acc += A.h12_t[o * nv + b];
+          if (i == 0)
+            for (int m = 1; m < no; ++m) {
+              if (m < j) acc += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
+              else if (m > j) acc -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
+              acc += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
+            }
+        }
+        y[(int64_t)o * inner + v] += acc;
+      }
+      break;
+    }
+    case B_S2: {
+      const int a = v / nv, b = v % nv;
+      for (int o = grp; o < nbat; o += ngrp) {
+        const int i = o / no, j = o % no;
+        double acc = 0.0;
+        for (int m = 0; m < no; ++m) acc -= fo[m * no + i] * T(m * no + j) + fo[m * no + j] * T(i * no + m);
+        for (int rep = 0; rep < 2; ++rep) {
+          int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
+          double dd = 0.0;
+          if (p == 0 && xx == 0)
+            for (int m = 0; m < no; ++m) {
+              if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
+              else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
+            }
+          if (p == 0 && xx >= 1 && z >= 1)
+            for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
+          if (p == 0 && xx >= 1 && z == 0)
+            for (int m = 0; m < no; ++m) {
+              if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
+              else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
+            }
+          if (p >= 1 && q >= 1 && xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
+          if (p >= 1 && q == 0 && xx == 0)
+            for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
+          if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) dd += ftt * L.H22(p, q, xx, z);
+          if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
+            for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
+          if (p >= 1 && q >= 1 && xx >= 1 && z == 0) dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
+          if (p >= 1 && q == 0 && xx >= 1 && z == 0)
+            for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
+          acc += dd;
+        }
+        y[(int64_t)o * inner + v] += acc;
+      }
+      break;
+    }
+    case B_T3: {
+      int b, c;
+      tri_pq(v, nv - 1, b, c);
+      ++b; ++c;
+      for (int o = grp; o < nbat; o += ngrp) {
+        int j, k;
+        tri_pq(o, no - 1, j, k);
+        ++j; ++k;
+        double acc = 0.0;
+        for (int m = 1; m < no; ++m) {
+          if (m != k) acc -= fo[m * no + j] * sgn_pair(m, k) * T(tri_idx(min(m, k) - 1, max(m, k) - 1, no - 1));
+          if (m != j) acc -= fo[m * no + k] * sgn_pair(j, m) * T(tri_idx(min(j, m) - 1, max(j, m) - 1, no - 1));
+        }
+        acc += ftt * L.T2(j, k, b, c) - FOV(j, 0) * L.T2(0, k, b, c) + FOV(k, 0) * L.T2(0, j, b, c)
+             - FOV(0, b) * L.T2(j, k, 0, c) + FOV(j, b) * L.T2(0, k, 0, c) - FOV(k, b) * L.T2(0, j, 0, c)
+             + FOV(0, c) * L.T2(j, k, 0, b) - FOV(j, c) * L.T2(0, k, 0, b) + FOV(k, c) * L.T2(0, j, 0, b);
+        y[(int64_t)o * inner + v] += acc;
+      }
+      break;
+    }
+    case B_H11: {
+      int b, c;
+      tri_pq(v, nv, b, c);
+      for (int o = grp; o < nbat; o += ngrp) {
+        int j, k;
+        tri_pq(o, no, j, k);
+        double acc = 0.0;
+        for (int m = 0; m < no; ++m) {
+          if (m != k) acc -= fo[m * no + j] * sgn_pair(m, k) * T(tri_idx(min(m, k), max(m, k), no));
+          if (m != j) acc -= fo[m * no + k] * sgn_pair(j, m) * T(tri_idx(min(j, m), max(j, m), no));
+        }
+        if (b == 0) acc += A.side_tr[(int64_t)o * nv + c];
+        if (j == 0)
+          for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H21(m, k, b, c);
+        acc += ftt * L.T2(j, k, b, c);
+        acc += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
+             - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
+        y[(int64_t)o * inner + v] += acc;
+      }
+      break;
+    }
+    case B_H12: {
+      const int m1 = nv - 1;
+      const int a = v / m1 + 1, c = v % m1 + 1;
+      for (int o = grp; o < nbat; o += ngrp) {
+        int j, k;
+        tri_pq(o, no, j, k);
+        double acc = 0.0;
+        for (int m = 0; m < no; ++m) {
+          if (m != k) acc -= fo[m * no + j] * sgn_pair(m, k) * T(tri_idx(min(m, k), max(m, k), no));
+          if (m != j) acc -= fo[m * no + k] * sgn_pair(j, m) * T(tri_idx(min(j, m), max(j, m), no));
+        }
+        acc += fv[a * nv + 0] * L.H11(j, k, 0, c);
+        if (j == 0)
+          for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H22(m, k, a, c);
+        acc += FOV(0, a) * L.T2(j, k, 0, c);
+        acc += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
+             - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
+        y[(int64_t)o * inner + v] += acc;
+      }
+      break;
+    }
+    case B_H21: {
+      int b, c;
+      tri_pq(v, nv, b, c);
+      for (int o = grp; o < nbat; o += ngrp) {
+        const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+        double acc = 0.0;
+        for (int m = 1; m < no; ++m)
+          acc -= fo[m * no + i] * T((m - 1) * (no - 1) + (k - 1)) + fo[m * no + k] * T((i - 1) * (no - 1) + (m - 1));
+        acc -= fo[0 * no + i] * L.H11(0, k, b, c);
+        if (b == 0) acc += A.side_tr[((int64_t)d.npo + o) * nv + c];
+        acc += FOV(i, 0) * L.T2(0, k, b, c);
+        acc += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
+             - FOV(0, c) * L.St(i, k, 0, b) + FOV(k, c) * L.St(i, 0, 0, b);
+        y[(int64_t)o * inner + v] += acc;
+      }
+      break;
+    }
+    default: {
+      const int m1 = nv - 1;
+      const int a = v / m1 + 1, c = v % m1 + 1;
+      for (int o = grp; o < nbat; o += ngrp) {
+        const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+        double acc = 0.0;
+        for (int m = 1; m < no; ++m)
+          acc -= fo[m * no + i] * T((m - 1) * (no - 1) + (k - 1)) + fo[m * no + k] * T((i - 1) * (no - 1) + (m - 1));
+        acc -= fo[0 * no + i] * L.H12(0, k, a, c);
+        acc += fv[a * nv + 0] * L.H21(i, k, 0, c);
+        acc += FOV(i, a) * L.T2(0, k, 0, c);
+        acc += ftt * L.St(i, k, a, c) - FOV(k, 0) * L.St(i, 0, a, c)
+             - FOV(0, c) * L.St(i, k, a, 0) + FOV(k, c) * L.St(i, 0, a, 0);
+        y[(int64_t)o * inner + v] += acc;
+      }
+      break;
+    }
+  }
+}
+
+}  // namespace esmp2
+
+namespace esmp2 {
+
+// ---------------------------------------------------------------------------
+// Gather with the occupied-index Fock action on matrix cores.  Per workgroup:
+// one box, GT consecutive inner (virtual-pair) indices v, all occupied batches.
+//  1. stage x (S~ for S2) for the tile in LDS;
+//  2. per element: box transfers, doubles <-> L-triples and side terms into an
+//     LDS output tile;
+//  3. per v: Y_v = -(F_o X_v + X_v F_o) on a 16x16 tile (X_v = the occupied
+//     matrix of the box at v, antisymmetric for pair boxes), added to the tile;
+//  4. coalesced y += tile.
+// Requires the occupied dimension of every box <= 16.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather3(GatherArgs A, int4 tiles0, int4 tiles1) {
+  extern __shared__ double sm[];
+  const Dims& d = A.d;
+  const int no = d.no, nv = d.nv;
+  const int tstart[8] = {0, tiles0.x, tiles0.y, tiles0.z, tiles0.w, tiles1.x, tiles1.y, tiles1.z};
+  int box = 0;
+  while (box < 6 && (int)blockIdx.x >= tstart[box + 1]) ++box;
+  const int t0 = ((int)blockIdx.x - tstart[box]) * GT;
+  int nbat, inner, n, sh;      // n: occupied matrix dimension, sh: index shift (1 when t is excluded)
+  bool anti;
+  switch (box) {
+    case B_T2: case B_H11: nbat = d.npo; inner = d.npv; n = no; sh = 0; anti = true; break;
+    case B_S2: nbat = no * no; inner = nv * nv; n = no; sh = 0; anti = false; break;
+    case B_T3: nbat = d.npo1; inner = d.npv1; n = no - 1; sh = 1; anti = true; break;
+    case B_H12: nbat = d.npo; inner = (nv - 1) * (nv - 1); n = no; sh = 0; anti = true; break;
+    case B_H21: nbat = (no - 1) * (no - 1); inner = d.npv; n = no - 1; sh = 1; anti = false; break;
+    default: nbat = (no - 1) * (no - 1); inner = (nv - 1) * (nv - 1); n = no - 1; sh = 1; anti = false; break;
+  }
+  double* tin = sm;                                 // nbat x (GT+1)
+  double* tout = tin + nbat * (GT + 1);             // nbat x (GT+1)
+  int* xi = (int*)(tout + nbat * (GT + 1));         // 16 x 16: signed (batch+1), 0 = zero entry
+  const double* src = (box == B_S2) ? A.S : A.x + d.off[box];
+  const int tw = min(GT, inner - t0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nbat * GT; e += blockDim.x) {
+    int o = e / GT, vl = e % GT;
+    tin[o * (GT + 1) + vl] = (vl < tw) ? src[(int64_t)o * inner + t0 + vl] : 0.0;
+  }
+  if (tid < 256) {
+    int p = tid >> 4, q = tid & 15, code = 0;
+    if (p < n && q < n) {
+      if (!anti) code = p * n + q + 1;
+      else if (p < q) code = tri_idx(p, q, n) + 1;
+      else if (p > q) code = -(tri_idx(q, p, n) + 1);
+    }
+    xi[tid] = code;
+  }
+  __syncthreads();
+  // ---- 2. per-element terms ----------------------------------------------
+  Look L{d, A.x, A.S};
+  const double* fv = A.fv;
+  const double* fov = A.fov;
+  const double* fo = A.fo;
+  auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
+  const double ftt = FOV(0, 0);
+  for (int e = tid; e < nbat * GT; e += blockDim.x) {
+    const int o = e / GT, vl = e % GT;
+    double acc = 0.0;
+    if (vl < tw) {
+      const int v = t0 + vl;
+      switch (box) {
+        case B_T2: {
+          int a, b, i, j;
+          tri_pq(v, nv, a, b);
+          tri_pq(o, no, i, j);
+          if (i >= 1 && a >= 1) acc += ftt * L.T3(i, j, a, b);
+          acc += ftt * L.H11(i, j, a, b);
+          if (i == 0 && a >= 1)
+            for (int m = 1; m < no; ++m) acc -= FOV(m, 0) * L.T3(m, j, a, b);
+          if (i == 0)
+            for (int m = 1; m < no; ++m) acc += FOV(m, 0) * L.H21(m, j, a, b);
+          if (a == 0) {
+            if (i >= 1) acc -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
+            acc += A.h12_t[o * nv + b];
+            if (i == 0)
+              for (int m = 1; m < no; ++m) {
+                if (m < j) acc += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
+                else if (m > j) acc -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
+                acc += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
+              }
+          }
+          break;
+        }
+        case B_S2: {
+          const int a = v / nv, b = v % nv, i = o / no, j = o % no;
+          for (int rep = 0; rep < 2; ++rep) {
+            int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
+            double dd = 0.0;
+            if (p == 0 && xx == 0)
+              for (int m = 0; m < no; ++m) {
+                if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
+                else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
+              }
+            if (p == 0 && xx >= 1 && z >= 1)
+              for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
+            if (p == 0 && xx >= 1 && z == 0)
+              for (int m = 0; m < no; ++m) {
+                if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
+                else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
+              }
+            if (p >= 1 && q >= 1 && xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
+            if (p >= 1 && q == 0 && xx == 0)
+              for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
+            if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) dd += ftt * L.H22(p, q, xx, z);
+            if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
+              for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
+            if (p >= 1 && q >= 1 && xx >= 1 && z == 0) dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
+            if (p >= 1 && q == 0 && xx >= 1 && z == 0)
+              for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
+            acc += dd;
+          }
+          break;
+        }
+        case B_T3: {
+          int b, c, j, k;
+          tri_pq(v, nv - 1, b, c);
+          tri_pq(o, no - 1, j, k);
+          ++b; ++c; ++j; ++k;
+          acc += ftt * L.T2(j, k, b, c) - FOV(j, 0) * L.T2(0, k, b, c) + FOV(k, 0) * L.T2(0, j, b, c)
+               - FOV(0, b) * L.T2(j, k, 0, c) + FOV(j, b) * L.T2(0, k, 0, c) - FOV(k, b) * L.T2(0, j, 0, c)
+               + FOV(0, c) * L.T2(j, k, 0, b) - FOV(j, c) * L.T2(0, k, 0, b) + FOV(k, c) * L.T2(0, j, 0, b);
+          break;
+        }
+        case B_H11: {
+          int b, c, j, k;
+          tri_pq(v, nv, b, c);
+          tri_pq(o, no, j, k);
+          if (b == 0) acc += A.side_tr[(int64_t)o * nv + c];
+          if (j == 0)
+            for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H21(m, k, b, c);
+          acc += ftt * L.T2(j, k, b, c);
+          acc += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
+               - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
+          break;
+        }
+        case B_H12: {
+          const int m1 = nv - 1, a = v / m1 + 1, c = v % m1 + 1;
+          int j, k;
+          tri_pq(o, no, j, k);
+          acc += fv[a * nv + 0] * L.H11(j, k, 0, c);
+          if (j == 0)
+            for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H22(m, k, a, c);
+          acc += FOV(0, a) * L.T2(j, k, 0, c);
+          acc += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
+               - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
+          break;
+        }
+        case B_H21: {
+          int b, c;
+          tri_pq(v, nv, b, c);
+          const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+          acc -= fo[0 * no + i] * L.H11(0, k, b, c);
+          if (b == 0) acc += A.side_tr[((int64_t)d.npo + o) * nv + c];
+          acc += FOV(i, 0) * L.T2(0, k, b, c);
+          acc += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
+               - FOV(0, c) * L.St(i, k, 0, b) + FOV(k, c) * L.St(i, 0, 0, b);
+          break;
+        }
+        default: {
+          const int m1 = nv - 1, a = v / m1 + 1, c = v % m1 + 1;
+          const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+          acc -= fo[0 * no + i] * L.H12(0, k, a, c);
+          acc += fv[a * nv + 0] * L.H21(i, k, 0, c);
+          acc += FOV(i, a) * L.T2(0, k, 0, c);
+          acc += ftt * L.St(i, k, a, c) - FOV(k, 0) * L.St(i, 0, a, c)
+               - FOV(0, c) * L.St(i, k, a, 0) + FOV(k, c) * L.St(i, 0, a, 0);
+          break;
+        }
+      }
+    }
+    tout[o * (GT + 1) + vl] = acc;
+  }
+  __syncthreads();
+  // ---- 3. occupied Sylvester on matrix cores: Y_v = -(F X_v + X_v F) -----
+  {
+    const int wave = tid >> 6, l = tid & 63;
+    const int r16 = l & 15, k4 = l >> 4;
+    // F_o restricted to the box's occupied range (padded to 16), symmetric
+    auto Fs = [&](int p, int q) -> double {
+      return (p < n && q < n) ? fo[(p + sh) * no + (q + sh)] : 0.0;
+    };
+    double fa[4], fb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      fa[s] = Fs(r16, 4 * s + k4);        // A operand (row r16, k)
+      fb[s] = Fs(4 * s + k4, r16);        // B operand (k, col r16)
+    }
+    for (int vl = wave; vl < tw; vl += 4) {
+      auto X = [&](int p, int q) -> double {
+        int code = xi[p * 16 + q];
+        if (code == 0) return 0.0;
+        double val = tin[((code > 0 ? code : -code) - 1) * (GT + 1) + vl];
+        return code > 0 ? val : -val;
+      };
+      f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        acc = mfma16x16x4(fa[s], X(4 * s + k4, r16), acc);       // F X
+        acc = mfma16x16x4(X(r16, 4 * s + k4), fb[s], acc);       // X F
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = mfma_row(l, q), c = r16;
+        if (r < n && c < n && (!anti || r < c)) {
+          int bidx = anti ? tri_idx(r, c, n) : r * n + c;
+          tout[bidx * (GT + 1) + vl] -= acc[q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // ---- 4. write back ------------------------------------------------------
+  double* y = A.y + d.off[box];
+  for (int e = tid; e < nbat * GT; e += blockDim.x) {
+    const int o = e / GT, vl = e % GT;
+    if (vl < tw) y[(int64_t)o * inner + t0 + vl] += tout[o * (GT + 1) + vl];
+  }
+}
+
+}  // namespace esmp2
+
+namespace esmp2 {
+
+// ---------------------------------------------------------------------------
+// Occupied-index Fock action on matrix cores, y += -(F_o X_v + X_v F_o) for
+// every inner index v of every box (F_o restricted to the box's occupied
+// range), plus the two box-transfer rows that the Sylvester kernel produces
+// (H1P2 -> H1P1 and H2P2 -> H2P1 through f_{t' E}).  One workgroup: one box,
+// GO consecutive inner indices, all occupied batches staged in LDS.
+// ---------------------------------------------------------------------------
+constexpr int GO = 8;
+
+__global__ __launch_bounds__(256) void k_oo(GatherArgs A, int4 tiles0, int4 tiles1) {
+  extern __shared__ double sm[];
+  const Dims& d = A.d;
+  const int no = d.no, nv = d.nv;
+  const int tstart[8] = {0, tiles0.x, tiles0.y, tiles0.z, tiles0.w, tiles1.x, tiles1.y, tiles1.z};
+  int box = 0;
+  while (box < 6 && (int)blockIdx.x >= tstart[box + 1]) ++box;
+  const int t0 = ((int)blockIdx.x - tstart[box]) * GO;
+  int nbat, inner, n, sh;
+  bool anti;
+  switch (box) {
+    case B_T2: case B_H11: nbat = d.npo; inner = d.npv; n = no; sh = 0; anti = true; break;
+    case B_S2: nbat = no * no; inner = nv * nv; n = no; sh = 0; anti = false; break;
+    case B_T3: nbat = d.npo1; inner = d.npv1; n = no - 1; sh = 1; anti = true; break;
+    case B_H12: nbat = d.npo; inner = (nv - 1) * (nv - 1); n = no; sh = 0; anti = true; break;
+    case B_H21: nbat = (no - 1) * (no - 1); inner = d.npv; n = no - 1; sh = 1; anti = false; break;
+    default: nbat = (no - 1) * (no - 1); inner = (nv - 1) * (nv - 1); n = no - 1; sh = 1; anti = false; break;
+  }
+  double* tin = sm;                                 // nbat x (GO+1)
+  double* tout = tin + nbat * (GO + 1);             // nbat x (GO+1)
+  int* xi = (int*)(tout + nbat * (GO + 1));         // 16 x 16
+  const double* src = (box == B_S2) ? A.S : A.x + d.off[box];
+  const int tw = min(GO, inner - t0);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nbat * GO; e += blockDim.x) {
+    const int o = e / GO, vl = e % GO;
+    const bool ok = vl < tw;
+    tin[o * (GO + 1) + vl] = ok ? src[(int64_t)o * inner + t0 + vl] : 0.0;
+    double t = 0.0;
+    // box-transfer rows (inner pairs (t', c) are the first nv-1 packed pairs)
+    if (ok && (box == B_H11 || box == B_H21) && t0 + vl < nv - 1) {
+      const int c = t0 + vl + 1;
+      t = A.side_tr[((box == B_H11 ? 0 : (int64_t)d.npo) + o) * nv + c];
+    }
+    tout[o * (GO + 1) + vl] = t;
+  }
+  {
+    int p = tid >> 4, q = tid & 15, code = 0;
+    if (p < n && q < n) {
+      if (!anti) code = p * n + q + 1;
+      else if (p < q) code = tri_idx(p, q, n) + 1;
+      else if (p > q) code = -(tri_idx(q, p, n) + 1);
+    }
+    xi[tid] = code;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, l = tid & 63;
+  const int r16 = l & 15, k4 = l >> 4;
+  const double* fo = A.fo;
+  auto Fs = [&](int p, int q) -> double { return (p < n && q < n) ? fo[(p + sh) * no + (q + sh)] : 0.0; };
+  double fa[4], fb[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    fa[s] = Fs(r16, 4 * s + k4);
+    fb[s] = Fs(4 * s + k4, r16);
+  }
+  for (int vl = wave; vl < tw; vl += 4) {
+    auto X = [&](int p, int q) -> double {
+      int code = xi[p * 16 + q];
+      if (code == 0) return 0.0;
+      double val = tin[((code > 0 ? code : -code) - 1) * (GO + 1) + vl];
+      return code > 0 ? val : -val;
+    };
+    f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      acc = mfma16x16x4(fa[s], X(4 * s + k4, r16), acc);
+      acc = mfma16x16x4(X(r16, 4 * s + k4), fb[s], acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = mfma_row(l, q), c = r16;
+      if (r < n && c < n && (!anti || r < c)) {
+        const int bidx = anti ? tri_idx(r, c, n) : r * n + c;
+        tout[bidx * (GO + 1) + vl] -= acc[q];
+      }
+    }
+  }
+  __syncthreads();
+  double* y = A.y + d.off[box];
+  for (int e = tid; e < nbat * GO; e += blockDim.x) {
+    const int o = e / GO, vl = e % GO;
+    if (vl < tw) y[(int64_t)o * inner + t0 + vl] += tout[o * (GO + 1) + vl];
+  }
 }
 
 }  // namespace esmp2

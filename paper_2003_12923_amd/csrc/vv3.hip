@@ -15,6 +15,9 @@ namespace esmp2 {
 enum { K3_PACK = 0, K3_PACKRED = 1, K3_DENSERED = 2, K3_S2PAIR = 3, K3_S2DIAG = 4 };
 
 struct V3Ctx {
+  int box, bi, bj;       // box and the occupied indices of this batch (actual orbital indices)
+  int o;                 // batch index within the box
+  const GatherArgs* g;   // coupling terms (null: Sylvester part only)
   const double* src;     // batch storage (S~ for S2)
   double* dst;
   double* dstT;          // S2 pair: transposed destination
@@ -47,26 +50,148 @@ __device__ inline double x3(const V3Ctx& c, int r, int col) {
   }
 }
 
+__device__ inline double special(const V3Ctx& c, int r, int col);
+
 template <int FMT>
 __device__ inline void y3(const V3Ctx& c, int r, int col, double val, bool diag_tile) {
   if (FMT == K3_PACK) {
-    if (r < col && col < c.m) c.dst[r * c.m - r * (r + 1) / 2 + (col - r - 1)] = val;
+    if (r < col && col < c.m) {
+            c.dst[r * c.m - r * (r + 1) / 2 + (col - r - 1)] = val;
+    }
   } else if (FMT == K3_PACKRED) {
     int rr = r - 1, cc = col - 1;
-    if (rr >= 0 && rr < cc && cc < c.m) c.dst[rr * c.m - rr * (rr + 1) / 2 + (cc - rr - 1)] = val;
+    if (rr >= 0 && rr < cc && cc < c.m) {
+            c.dst[rr * c.m - rr * (rr + 1) / 2 + (cc - rr - 1)] = val;
+    }
   } else if (FMT == K3_DENSERED) {
     if (col >= 1 && col <= c.m && r <= c.m) {
-      if (r >= 1) c.dst[(r - 1) * c.m + (col - 1)] = val;
-      else c.tr[col] = val;
+      if (r >= 1) {
+                c.dst[(r - 1) * c.m + (col - 1)] = val;
+      } else {
+        c.tr[col] = val;
+      }
     }
   } else if (FMT == K3_S2PAIR) {
-    if (r < c.m && col < c.m) { c.dst[r * c.m + col] = val; c.dstT[col * c.m + r] = val; }
+    if (r < c.m && col < c.m) {
+            c.dst[r * c.m + col] = val;
+      c.dstT[col * c.m + r] = val;
+    }
   } else {
     if (r < c.m && col < c.m) {
-      c.dst[r * c.m + col] = val;
+            c.dst[r * c.m + col] = val;
       if (!diag_tile) c.dst[col * c.m + r] = val;
     }
   }
+}
+
+// Per-element couplings other than the occupied-index Fock action: pinned
+// TOP-index transfers, doubles <-> L-triples through f_ov and the side
+// contractions.  (r, col) are the actual virtual indices of the output.
+__device__ inline double special(const V3Ctx& c, int r, int col) {
+  const GatherArgs& A = *c.g;
+  const Dims& d = A.d;
+  const int no = d.no, nv = d.nv;
+  Look L{d, A.x, A.S};
+  const double* fo = A.fo;
+  const double* fv = A.fv;
+  auto FOV = [&](int i, int a) { return A.fov[i * nv + a]; };
+  const double ftt = FOV(0, 0);
+  double acc = 0.0;
+  switch (c.box) {
+    case B_T2: {
+      const int i = c.bi, j = c.bj, a = r, b = col;
+      if (i >= 1 && a >= 1) acc += ftt * L.T3(i, j, a, b);
+      acc += ftt * L.H11(i, j, a, b);
+      if (i == 0) {
+        if (a >= 1)
+          for (int m = 1; m < no; ++m) acc -= FOV(m, 0) * L.T3(m, j, a, b);
+        for (int m = 1; m < no; ++m) acc += FOV(m, 0) * L.H21(m, j, a, b);
+      }
+      if (a == 0) {
+        if (i >= 1) acc -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
+        acc += A.h12_t[c.o * nv + b];
+        if (i == 0)
+          for (int m = 1; m < no; ++m) {
+            if (m < j) acc += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
+            else if (m > j) acc -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
+            acc += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
+          }
+      }
+      break;
+    }
+    case B_S2: {
+      const int i = c.bi, j = c.bj, a = r, b = col;
+      for (int rep = 0; rep < 2; ++rep) {
+        int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
+        if (p == 0 && xx == 0)
+          for (int m = 0; m < no; ++m) {
+            if (m < q) acc += A.h11_p1[tri_idx(m, q, no) * nv + z];
+            else if (m > q) acc -= A.h11_p2[tri_idx(q, m, no) * nv + z];
+          }
+        if (p == 0 && xx >= 1 && z >= 1)
+          for (int m = 0; m < no; ++m) acc += FOV(m, 0) * L.H12(m, q, xx, z);
+        if (p == 0 && xx >= 1 && z == 0)
+          for (int m = 0; m < no; ++m) {
+            if (m < q) acc -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
+            else if (m > q) acc += A.h12_u2[tri_idx(q, m, no) * nv + xx];
+          }
+        if (p >= 1 && q >= 1 && xx == 0) acc += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
+        if (p >= 1 && q == 0 && xx == 0)
+          for (int m = 1; m < no; ++m) acc -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
+        if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) acc += ftt * L.H22(p, q, xx, z);
+        if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
+          for (int m = 1; m < no; ++m) acc -= FOV(m, 0) * L.H22(p, m, xx, z);
+        if (p >= 1 && q >= 1 && xx >= 1 && z == 0) acc -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
+        if (p >= 1 && q == 0 && xx >= 1 && z == 0)
+          for (int m = 1; m < no; ++m) acc += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
+      }
+      break;
+    }
+    case B_T3: {
+      const int j = c.bi, k = c.bj, b = r, cc = col;
+      acc += ftt * L.T2(j, k, b, cc) - FOV(j, 0) * L.T2(0, k, b, cc) + FOV(k, 0) * L.T2(0, j, b, cc)
+           - FOV(0, b) * L.T2(j, k, 0, cc) + FOV(j, b) * L.T2(0, k, 0, cc) - FOV(k, b) * L.T2(0, j, 0, cc)
+           + FOV(0, cc) * L.T2(j, k, 0, b) - FOV(j, cc) * L.T2(0, k, 0, b) + FOV(k, cc) * L.T2(0, j, 0, b);
+      break;
+    }
+    case B_H11: {
+      const int j = c.bi, k = c.bj, b = r, cc = col;
+      if (j == 0)
+        for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H21(m, k, b, cc);
+      acc += ftt * L.T2(j, k, b, cc);
+      acc += FOV(j, b) * L.St(0, k, 0, cc) - FOV(k, b) * L.St(0, j, 0, cc)
+           - FOV(j, cc) * L.St(0, k, 0, b) + FOV(k, cc) * L.St(0, j, 0, b);
+      break;
+    }
+    case B_H12: {
+      const int j = c.bi, k = c.bj, a = r, cc = col;
+      acc += fv[a * nv + 0] * L.H11(j, k, 0, cc);
+      if (j == 0)
+        for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H22(m, k, a, cc);
+      acc += FOV(0, a) * L.T2(j, k, 0, cc);
+      acc += FOV(j, 0) * L.St(0, k, a, cc) - FOV(k, 0) * L.St(0, j, a, cc)
+           - FOV(j, cc) * L.St(0, k, a, 0) + FOV(k, cc) * L.St(0, j, a, 0);
+      break;
+    }
+    case B_H21: {
+      const int i = c.bi, k = c.bj, b = r, cc = col;
+      acc -= fo[0 * no + i] * L.H11(0, k, b, cc);
+      acc += FOV(i, 0) * L.T2(0, k, b, cc);
+      acc += FOV(0, b) * L.St(i, k, 0, cc) - FOV(k, b) * L.St(i, 0, 0, cc)
+           - FOV(0, cc) * L.St(i, k, 0, b) + FOV(k, cc) * L.St(i, 0, 0, b);
+      break;
+    }
+    default: {
+      const int i = c.bi, k = c.bj, a = r, cc = col;
+      acc -= fo[0 * no + i] * L.H12(0, k, a, cc);
+      acc += fv[a * nv + 0] * L.H21(i, k, 0, cc);
+      acc += FOV(i, a) * L.T2(0, k, 0, cc);
+      acc += ftt * L.St(i, k, a, cc) - FOV(k, 0) * L.St(i, 0, a, cc)
+           - FOV(0, cc) * L.St(i, k, a, 0) + FOV(k, cc) * L.St(i, 0, a, 0);
+      break;
+    }
+  }
+  return acc;
 }
 
 // tile block owned by a wavefront
@@ -167,6 +292,31 @@ __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx& c, d
     }
 }
 
+// y += couplings for every output of this batch; rows by wavefront, columns by lane.
+__device__ __attribute__((noinline)) void couplings_pass(V3Ctx c, int fmt) {
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int m = c.m;
+  if (fmt == K3_PACK || fmt == K3_PACKRED) {
+    const int off = (fmt == K3_PACKRED) ? 1 : 0;
+    for (int r = wave; r < m; r += 4) {
+      const int base = r * m - r * (r + 1) / 2 - r - 1;
+      for (int col = r + 1 + l; col < m; col += 64) c.dst[base + col] += special(c, r + off, col + off);
+    }
+  } else if (fmt == K3_DENSERED) {
+    for (int r = wave; r < m; r += 4)
+      for (int col = l; col < m; col += 64) c.dst[r * m + col] += special(c, r + 1, col + 1);
+  } else {
+    for (int r = wave; r < m; r += 4)
+      for (int col = l; col < m; col += 64) c.dst[r * m + col] += special(c, r, col);
+    if (fmt == K3_S2PAIR) {
+      V3Ctx t = c;
+      t.bi = c.bj; t.bj = c.bi;
+      for (int r = wave; r < m; r += 4)
+        for (int col = l; col < m; col += 64) c.dstT[r * m + col] += special(t, r, col);
+    }
+  }
+}
+
 template <int FMT, int NT>
 __device__ inline void vv3_dispatch(const V3Ctx& c, double (*As)[16][16 * NT + 1], double (*Bs)[16][16 * NT + 1]) {
   switch (threadIdx.x >> 6) {
@@ -187,11 +337,15 @@ __global__ __launch_bounds__(256) void k_vv3(VVArgs A) {
   const int box = jb.x, fmt = jb.z;
   V3Ctx c;
   c.nv = d.nv;
+  c.box = box;
+  c.g = A.use_ga ? &A.ga : nullptr;
+  c.o = jb.y;
   c.F = (box == B_T2 || box == B_S2) ? A.Fd : A.Fl;
   c.dstT = nullptr;
   c.tr = nullptr;
   if (box == B_S2) {
     const int si = jb.y, sj = jb.w;
+    c.bi = si; c.bj = sj;
     c.m = d.nv;
     c.src = A.S + ((int64_t)si * d.no + sj) * d.nv * d.nv;
     c.dst = A.y + d.off[B_S2] + ((int64_t)si * d.no + sj) * d.nv * d.nv;
@@ -199,6 +353,9 @@ __global__ __launch_bounds__(256) void k_vv3(VVArgs A) {
   } else {
     int64_t o = d.off[box];
     const int batch = jb.y;
+    if (box == B_T2 || box == B_H11 || box == B_H12) { tri_pq(batch, d.no, c.bi, c.bj); }
+    else if (box == B_T3) { tri_pq(batch, d.no - 1, c.bi, c.bj); c.bi += 1; c.bj += 1; }
+    else { c.bi = batch / (d.no - 1) + 1; c.bj = batch % (d.no - 1) + 1; }
     if (box == B_T3) { c.m = d.nv - 1; o += (int64_t)batch * d.npv1; }
     else if (box == B_H12 || box == B_H22) {
       c.m = d.nv - 1;
@@ -215,6 +372,40 @@ __global__ __launch_bounds__(256) void k_vv3(VVArgs A) {
     case K3_S2PAIR: vv3_dispatch<K3_S2PAIR, NT>(c, As, Bs); break;
     default: vv3_dispatch<K3_S2DIAG, NT>(c, As, Bs); break;
   }
+}
+
+// Coupling terms (everything except the two Fock contractions over the free
+// index pairs) for every output: one workgroup per batch matrix; y += ...
+// jobs: (box, batch) for every batch of every box; S2 batches are (i, j).
+__global__ __launch_bounds__(256) void k_couple(GatherArgs G, const int2* jobs) {
+  const int2 jb = jobs[blockIdx.x];
+  const Dims& d = G.d;
+  const int box = jb.x, batch = jb.y;
+  V3Ctx c;
+  c.box = box;
+  c.g = &G;
+  c.o = batch;
+  c.nv = d.nv;
+  c.tr = nullptr;
+  c.dstT = nullptr;
+  int fmt;
+  int64_t o = d.off[box];
+  switch (box) {
+    case B_T2: case B_H11: tri_pq(batch, d.no, c.bi, c.bj); c.m = d.nv; o += (int64_t)batch * d.npv; fmt = K3_PACK; break;
+    case B_T3: tri_pq(batch, d.no - 1, c.bi, c.bj); c.bi += 1; c.bj += 1; c.m = d.nv - 1;
+               o += (int64_t)batch * d.npv1; fmt = K3_PACKRED; break;
+    case B_H12: tri_pq(batch, d.no, c.bi, c.bj); c.m = d.nv - 1; o += (int64_t)batch * (d.nv - 1) * (d.nv - 1);
+                fmt = K3_DENSERED; break;
+    case B_S2: c.bi = batch / d.no; c.bj = batch % d.no; c.m = d.nv; o += (int64_t)batch * d.nv * d.nv;
+               fmt = K3_S2DIAG; break;
+    default: c.bi = batch / (d.no - 1) + 1; c.bj = batch % (d.no - 1) + 1; c.m = d.nv - 1;
+             o += (int64_t)batch * (box == B_H21 ? d.npv : (d.nv - 1) * (d.nv - 1));
+             fmt = (box == B_H21) ? K3_PACK : K3_DENSERED;
+             if (box == B_H21) c.m = d.nv;
+             break;
+  }
+  c.dst = G.y + o;
+  couplings_pass(c, fmt);
 }
 
 template __global__ void k_vv3<10>(VVArgs);
