@@ -71,7 +71,7 @@ def main():
         n_sigma += res["iterations"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    vv_ms, vv_n = h.profile(False)
+    vv_ms, vv_n = h.profile(False)[P.ESMP2_FP64]
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
     value = n_sigma * sig_flops / wall / 1e9

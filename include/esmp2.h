@@ -78,7 +78,8 @@ typedef enum {
 
 typedef enum {
   ESMP2_FP64 = 0,           /* FP64 everywhere                                       */
-  ESMP2_FP32 = 1            /* sigma contractions in FP32 (FP32 accumulation)        */
+  ESMP2_FP32 = 1            /* the operator in FP32 (FP32 inputs, Fock blocks rounded
+                               to FP32, FP32 matrix-core accumulation)               */
 } esmp2_precision;
 
 typedef struct {
@@ -88,7 +89,10 @@ typedef struct {
                                solves inside FP64 iterative refinement               */
   const double* x0;         /* device, n_amp, initial guess (warm start) or NULL      */
   double* x_out;            /* device, n_amp, receives the solution, or NULL          */
-  double* resid_hist;       /* host, max_iter entries of ||r||/||b|| per iteration, or NULL */
+  double* resid_hist;       /* host, max_iter entries of ||r||/||b|| per iteration, or NULL
+                               (FP32: the inner residual estimate times the outer one) */
+  double inner_tol;         /* FP32 only: smallest relative residual reduction asked of
+                               one inner FP32 solve, in [0, 1); 0 selects 1e-5         */
 } esmp2_solve_opts;
 
 typedef struct {
@@ -143,8 +147,12 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision);
 /* Jacobi-preconditioned conjugate gradient for A x = -b (A = H0 - E0 on D + L,
  * weighted inner product), then E2 (paper Sec. III.A and Sec. II.C).  Builds the
  * right-hand side first if esmp2_build_rhs has not been called.  Synchronises.
- * With precision = ESMP2_FP32 the operator inside each inner CG solve runs in
- * FP32 and an FP64 residual drives iterative refinement. */
+ * With precision = ESMP2_FP32, iterative refinement: the FP64 residual
+ * r = -b - A x is recomputed with the FP64 operator after each inner solve
+ * A d = r / ||r|| run by FP32 conjugate gradient (FP32 operator and vectors, FP64
+ * reductions) to a relative reduction max(inner_tol, tol / (2 ||r||/||b||)); the
+ * FP64 x accumulates ||r|| d.  The stopping test, x and E2 are FP64 in both modes;
+ * result.iterations counts the inner iterations and result.outer the FP64 steps. */
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
                          esmp2_solve_result* result);
 
@@ -156,9 +164,10 @@ esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A
 
 /* Timing of the virtual-pair Sylvester kernel (the dominant sigma kernel) with
  * HIP events recorded on the handle's stream around each of its launches.
- * Returns (host) the accumulated milliseconds and launch count since the last
- * call, resets them, and switches recording on (enable != 0) or off.  Waits for
- * the recorded events.  Either output may be NULL. */
+ * vv_ms[2], vv_launches[2] (host, indexed by esmp2_precision) receive the
+ * accumulated milliseconds and launch counts since the last call, which are then
+ * reset; recording is switched on (enable != 0) or off.  Waits for the recorded
+ * events.  Either output may be NULL. */
 esmp2_status esmp2_profile(esmp2_handle h, int enable, double* vv_ms, int64_t* vv_launches);
 
 /* Message of the last failing call on this handle (never NULL). */

@@ -19,7 +19,8 @@ STATUS_NAMES = ["OK", "INVALID_ARG", "BAD_ORDER", "NOT_SPD", "NOT_CONVERGED", "O
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
-                ("x0", C.c_void_p), ("x_out", C.c_void_p), ("resid_hist", C.c_void_p)]
+                ("x0", C.c_void_p), ("x_out", C.c_void_p), ("resid_hist", C.c_void_p),
+                ("inner_tol", C.c_double)]
 
 
 class SolveResult(C.Structure):
@@ -117,12 +118,12 @@ class Handle:
         return self._check(lib.esmp2_sigma(self.h, _ptr(x), _ptr(y), precision))
 
     def solve(self, tol=1e-8, max_iter=200, precision=ESMP2_FP64, x0=None, x_out=None,
-              history=False, allow=(ESMP2_NOT_CONVERGED,)):
+              history=False, inner_tol=0.0, allow=(ESMP2_NOT_CONVERGED,)):
         import numpy as np
         hist = np.zeros(max_iter, dtype=np.float64) if history else None
         o = SolveOpts(tol, max_iter, precision, None if x0 is None else x0.data_ptr(),
                       None if x_out is None else x_out.data_ptr(),
-                      None if hist is None else hist.ctypes.data)
+                      None if hist is None else hist.ctypes.data, inner_tol)
         r = SolveResult()
         self._check(lib.esmp2_solve(self.h, C.byref(o), C.byref(r)), allow=allow)
         out = {k: getattr(r, k) for k, _ in SolveResult._fields_}
@@ -131,9 +132,10 @@ class Handle:
         return out
 
     def profile(self, enable=True):
-        ms, n = C.c_double(), C.c_int64()
-        self._check(lib.esmp2_profile(self.h, 1 if enable else 0, C.byref(ms), C.byref(n)))
-        return ms.value, n.value
+        """{precision: (ms, launches)} of the Sylvester kernel since the last call."""
+        ms, n = (C.c_double * 2)(), (C.c_int64 * 2)()
+        self._check(lib.esmp2_profile(self.h, 1 if enable else 0, ms, n))
+        return {ESMP2_FP64: (ms[0], n[0]), ESMP2_FP32: (ms[1], n[1])}
 
     def gemm_f64(self, A, B, Cm):
         m, k = A.shape

@@ -84,11 +84,17 @@ struct esmp2_handle_ {
   int* pairs = nullptr;          // (p << 16) | q tables: virtual pairs, shifted virtual, occupied, shifted occupied
   // Krylov vectors
   double *x, *r, *p, *q;
-  // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream
+  // FP32 operator (Fock blocks rounded from the FP64 ones, work buffers) and
+  // the FP32 vectors of the inner solves of the mixed-precision refinement
+  float *Fd32, *Fl32, *fo32, *fv32, *fov32, *S32, *side32, *side_tr32;
+  float *d32, *r32, *p32, *q32, *dinv32;
+  // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream,
+  // per operator precision (index = esmp2_precision)
   bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_vv;
-  double vv_ms = 0.0;
-  int64_t vv_launches = 0;
+  struct Ev { hipEvent_t a, b; int prec; };
+  std::vector<Ev> ev_vv;
+  double vv_ms[2] = {0.0, 0.0};
+  int64_t vv_launches[2] = {0, 0};
 };
 
 static esmp2_status fail(esmp2_handle h, esmp2_status s, const std::string& msg) {
@@ -99,12 +105,12 @@ static esmp2_status fail(esmp2_handle h, esmp2_status s, const std::string& msg)
 static void drain_events(esmp2_handle h) {
   for (auto& e : h->ev_vv) {
     float ms = 0.f;
-    if (hipEventSynchronize(e.second) == hipSuccess && hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
-      h->vv_ms += ms;
-      h->vv_launches += 1;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      h->vv_ms[e.prec] += ms;
+      h->vv_launches[e.prec] += 1;
     }
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
   }
   h->ev_vv.clear();
 }
@@ -159,10 +165,12 @@ esmp2_status esmp2_profile(esmp2_handle h, int enable, double* vv_ms, int64_t* v
   if (!h) return ESMP2_INVALID_ARG;
   ESMP2_HIP(hipSetDevice(h->device));
   drain_events(h);
-  if (vv_ms) *vv_ms = h->vv_ms;
-  if (vv_launches) *vv_launches = h->vv_launches;
-  h->vv_ms = 0.0;
-  h->vv_launches = 0;
+  for (int k = 0; k < 2; ++k) {
+    if (vv_ms) vv_ms[k] = h->vv_ms[k];
+    if (vv_launches) vv_launches[k] = h->vv_launches[k];
+    h->vv_ms[k] = 0.0;
+    h->vv_launches[k] = 0;
+  }
   h->prof = enable != 0;
   return ESMP2_OK;
 }
@@ -215,6 +223,13 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
             dalloc(h, &h->side, (size_t)nv * (3 * d.npo1 + 2 * d.npo + 3 * d.npo + 5 * (no - 1) * (no - 1))) &&
             dalloc(h, &h->side_tr, (size_t)nv * (d.npo + (no - 1) * (no - 1))) &&
             dalloc(h, &h->x, namp) && dalloc(h, &h->r, namp) && dalloc(h, &h->p, namp) && dalloc(h, &h->q, namp);
+  ok = ok && dalloc(h, &h->Fd32, (size_t)mv * mv) && dalloc(h, &h->Fl32, (size_t)mv * mv) &&
+       dalloc(h, &h->fo32, no * no) && dalloc(h, &h->fv32, (size_t)nv * nv) && dalloc(h, &h->fov32, (size_t)no * nv) &&
+       dalloc(h, &h->S32, (size_t)no * no * nv * nv) &&
+       dalloc(h, &h->side32, (size_t)nv * (3 * d.npo1 + 2 * d.npo + 3 * d.npo + 5 * (no - 1) * (no - 1))) &&
+       dalloc(h, &h->side_tr32, (size_t)nv * (d.npo + (no - 1) * (no - 1))) && dalloc(h, &h->d32, namp) &&
+       dalloc(h, &h->r32, namp) && dalloc(h, &h->p32, namp) && dalloc(h, &h->q32, namp) &&
+       dalloc(h, &h->dinv32, namp);
   if (!ok) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
   // vv job table
   std::vector<int2> jobs;
@@ -336,6 +351,12 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   ESMP2_HIP(gemm(s, 1, g));   // Ft = R^T T
   hipLaunchKernelGGL(k_topfock, dim3(nblk((int64_t)mv * mv > n * n ? (int64_t)mv * mv : (int64_t)n * n)), dim3(256),
                      0, s, h->Ft, h->lam, no, nv, mv, h->fo, h->fv, h->fov, h->eo, h->ev, h->Fd, h->Fl, h->sc_rot);
+  // the FP32 operator's Fock blocks, rounded from the FP64 ones
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, h->Fd, h->Fd32, (int64_t)mv * mv);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, h->Fl, h->Fl32, (int64_t)mv * mv);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk(no * no)), dim3(256), 0, s, h->fo, h->fo32, (int64_t)no * no);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, h->fv, h->fv32, (int64_t)nv * nv);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)no * nv)), dim3(256), 0, s, h->fov, h->fov32, (int64_t)no * nv);
   // B~ blocks: Bov = U^T B_ov W, Bvt = W^T B_vv W[:, :no], Boo = U^T B_oo U
   const int64_t nn = (int64_t)n * n;
   // T[Q] (no x nv) = B[Q][occ, vir] W
@@ -413,6 +434,7 @@ static esmp2_status build_rhs(esmp2_handle h) {
   hipLaunchKernelGGL(k_rhs, dim3(nblk(namp)), dim3(256), 0, s, ra);
   DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv, h->blockmin};
   hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
+  hipLaunchKernelGGL(k_to_f32, dim3(PCG_BLOCKS), dim3(256), 0, s, (const double*)h->dinv, h->dinv32, namp);
   hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
   // E2_S
   E2sArgs ea{d, h->Vint, h->lam, h->eo, h->ev, h->omega, h->partial};
@@ -447,17 +469,38 @@ esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* 
   return ESMP2_OK;
 }
 
-// y = A x (FP64), all on the handle's stream
-static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
+}  // extern "C"
+
+// Operator data of one precision
+template <class T>
+struct SigmaBufs {
+  const T *Fd, *Fl, *fo, *fv, *fov;
+  T *S, *side, *side_tr;
+  int prec;
+};
+
+static SigmaBufs<double> bufs64(esmp2_handle h) {
+  return SigmaBufs<double>{h->Fd, h->Fl, h->fo, h->fv, h->fov, h->S, h->side, h->side_tr, ESMP2_FP64};
+}
+
+static SigmaBufs<float> bufs32(esmp2_handle h) {
+  return SigmaBufs<float>{h->Fd32, h->Fl32, h->fo32, h->fv32, h->fov32, h->S32, h->side32, h->side_tr32, ESMP2_FP32};
+}
+
+// y = A x in the precision of T, all on the handle's stream:
+// S~ (flip-symmetrised S2) -> side contractions -> virtual-pair Sylvester
+// products (y = ...) -> couplings (y += ...) -> occupied-index action (y += ...)
+template <class T>
+static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv;
   hipStream_t s = h->stream;
-  hipLaunchKernelGGL(k_sym_s2, dim3(nblk((int64_t)no * no * nv * nv)), dim3(256), 0, s, d, x, h->S);
+  hipLaunchKernelGGL(k_sym_s2<T>, dim3(nblk((int64_t)no * no * nv * nv)), dim3(256), 0, s, d, x, w.S);
   // side contractions
-  SideArgs sa{};
-  sa.d = d; sa.x = x; sa.fov = h->fov;
-  double* p = h->side;
-  auto take = [&](int64_t rows) { double* r = p; p += rows * nv; return r; };
+  SideArgs<T> sa{};
+  sa.d = d; sa.x = x; sa.fov = w.fov;
+  T* p = w.side;
+  auto take = [&](int64_t rows) { T* r = p; p += rows * nv; return r; };
   sa.t3_t = take(d.npo1); sa.t3_p1 = take(d.npo1); sa.t3_p2 = take(d.npo1);
   sa.h11_p1 = take(d.npo); sa.h11_p2 = take(d.npo);
   sa.h12_t = take(d.npo); sa.h12_u1 = take(d.npo); sa.h12_u2 = take(d.npo);
@@ -465,23 +508,23 @@ static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
   sa.h21_t = take(n2); sa.h21_k = take(n2);
   sa.h22_ut = take(n2); sa.h22_i = take(n2); sa.h22_uk = take(n2);
   const int nside = d.npo1 + 2 * d.npo + 2 * n2;
-  hipLaunchKernelGGL(k_side, dim3(nside), dim3(256), 0, s, sa);
-  GatherArgs ga{};
-  ga.d = d; ga.x = x; ga.S = h->S; ga.y = y; ga.fo = h->fo; ga.fv = h->fv; ga.fov = h->fov; ga.side_tr = h->side_tr;
+  hipLaunchKernelGGL(k_side<T>, dim3(nside), dim3(256), 0, s, sa);
+  GatherArgs<T> ga{};
+  ga.d = d; ga.x = x; ga.S = w.S; ga.y = y; ga.fo = w.fo; ga.fv = w.fv; ga.fov = w.fov; ga.side_tr = w.side_tr;
   ga.t3_t = sa.t3_t; ga.t3_p1 = sa.t3_p1; ga.t3_p2 = sa.t3_p2; ga.h11_p1 = sa.h11_p1; ga.h11_p2 = sa.h11_p2;
   ga.h12_t = sa.h12_t; ga.h12_u1 = sa.h12_u1; ga.h12_u2 = sa.h12_u2; ga.h21_t = sa.h21_t; ga.h21_k = sa.h21_k;
   ga.h22_ut = sa.h22_ut; ga.h22_i = sa.h22_i; ga.h22_uk = sa.h22_uk;
-  // tile prefix sums per box for the occupied-index kernels
+  // tile prefix sums per box for the occupied-index kernel
   const int inner[7] = {d.npv, nv * nv, d.npv1, d.npv, (nv - 1) * (nv - 1), d.npv, (nv - 1) * (nv - 1)};
   const int nbat[7] = {d.npo, no * no, d.npo1, d.npo, d.npo, (no - 1) * (no - 1), (no - 1) * (no - 1)};
   int maxb = 1;
   for (int k = 0; k < 7; ++k)
     if (nbat[k] > 0 && inner[k] > 0) maxb = std::max(maxb, nbat[k]);
-  const size_t lds_oo = sizeof(double) * (size_t)2 * maxb * (GO + 1) + 256 * sizeof(int);
+  const size_t lds_oo = sizeof(T) * (size_t)2 * maxb * (GO + 1) + 256 * sizeof(int);
   // occupied-index action on the matrix cores when the occupied range fits one 16x16 tile
   const bool oo_mfma = no <= 16 && lds_oo <= 160 * 1024 - 2048;
-  // virtual-pair Sylvester products (+ diagonal constants, + per-element couplings when fused)
-  VVArgs va{d, x, h->S, y, h->Fd, h->Fl, h->side_tr, h->jobs, h->jobs4, ga, 0};
+  // virtual-pair Sylvester products (+ the diagonal constants folded into F')
+  VVArgs<T> va{d, x, w.S, y, w.Fd, w.Fl, w.side_tr, h->jobs, h->jobs4};
   const int tiles = d.mv / 16;
   int tw = (tiles + 1) / 2;
   if (tw > 5) tw = 5;
@@ -497,42 +540,45 @@ static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) {
     }
   }
   if (d.mv == 160) {
-    hipLaunchKernelGGL(k_vv3<10>, dim3(h->njobs4), dim3(256), 0, s, va);
+    hipLaunchKernelGGL((k_vv3<T, 10>), dim3(h->njobs4), dim3(256), 0, s, va);
   } else if (d.mv == 112) {
-    hipLaunchKernelGGL(k_vv3<7>, dim3(h->njobs4), dim3(256), 0, s, va);
+    hipLaunchKernelGGL((k_vv3<T, 7>), dim3(h->njobs4), dim3(256), 0, s, va);
   } else if (d.mv == 80) {
-    hipLaunchKernelGGL(k_vv3<5>, dim3(h->njobs4), dim3(256), 0, s, va);
+    hipLaunchKernelGGL((k_vv3<T, 5>), dim3(h->njobs4), dim3(256), 0, s, va);
   } else switch (tw) {
-    case 1: hipLaunchKernelGGL(k_vv<1>, grid, dim3(256), 0, s, va); break;
-    case 2: hipLaunchKernelGGL(k_vv<2>, grid, dim3(256), 0, s, va); break;
-    case 3: hipLaunchKernelGGL(k_vv<3>, grid, dim3(256), 0, s, va); break;
-    case 4: hipLaunchKernelGGL(k_vv<4>, grid, dim3(256), 0, s, va); break;
-    default: hipLaunchKernelGGL(k_vv<5>, grid, dim3(256), 0, s, va); break;
+    case 1: hipLaunchKernelGGL((k_vv<T, 1>), grid, dim3(256), 0, s, va); break;
+    case 2: hipLaunchKernelGGL((k_vv<T, 2>), grid, dim3(256), 0, s, va); break;
+    case 3: hipLaunchKernelGGL((k_vv<T, 3>), grid, dim3(256), 0, s, va); break;
+    case 4: hipLaunchKernelGGL((k_vv<T, 4>), grid, dim3(256), 0, s, va); break;
+    default: hipLaunchKernelGGL((k_vv<T, 5>), grid, dim3(256), 0, s, va); break;
   }
   if (e0) {
     (void)hipEventRecord(e1, s);
-    h->ev_vv.push_back({e0, e1});
+    h->ev_vv.push_back({e0, e1, w.prec});
   }
+  const int* pv = h->pairs;
+  PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
+  hipLaunchKernelGGL(k_couple<T>, dim3(nblk(d.off[7])), dim3(256), 0, s, ga, pt);
   if (oo_mfma) {
     int pre[8] = {0};
     for (int k = 0; k < 7; ++k) {
       int nt = (nbat[k] > 0 && inner[k] > 0) ? (inner[k] + GO - 1) / GO : 0;
       pre[k + 1] = pre[k] + nt;
     }
-    const int* pv = h->pairs;
-    const int* pv1 = pv + d.npv;
-    const int* po = pv1 + d.npv1;
-    const int* po1 = po + d.npo;
-    hipLaunchKernelGGL(k_gather4, dim3(nblk(d.off[7])), dim3(256), 0, s, ga, pv, pv1, po, po1);
-    ESMP2_HIP(hipFuncSetAttribute((const void*)k_oo, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_oo));
-    hipLaunchKernelGGL(k_oo, dim3(pre[7]), dim3(256), lds_oo, s, ga, make_int4(pre[1], pre[2], pre[3], pre[4]),
+    ESMP2_HIP(hipFuncSetAttribute((const void*)k_oo<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_oo));
+    hipLaunchKernelGGL(k_oo<T>, dim3(pre[7]), dim3(256), lds_oo, s, ga, make_int4(pre[1], pre[2], pre[3], pre[4]),
                        make_int4(pre[5], pre[6], pre[7], 0));
   } else {
-    hipLaunchKernelGGL(k_gather, dim3(nblk(d.off[7])), dim3(256), 0, s, ga);
+    hipLaunchKernelGGL(k_oo_plain<T>, dim3(nblk(d.off[7])), dim3(256), 0, s, ga);
   }
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
+
+static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) { return sigma_t(h, bufs64(h), x, y); }
+static esmp2_status sigma32(esmp2_handle h, const float* x, float* y) { return sigma_t(h, bufs32(h), x, y); }
+
+extern "C" {
 
 esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision) {
   if (!h) return ESMP2_INVALID_ARG;
@@ -541,35 +587,53 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision) 
   if (x == y) return fail(h, ESMP2_INVALID_ARG, "x and y must not overlap");
   ESMP2_HIP(hipSetDevice(h->device));
   if (precision == ESMP2_FP64) return sigma64(h, (const double*)x, (double*)y);
-  return fail(h, ESMP2_UNSUPPORTED, "precision not implemented");
+  if (precision == ESMP2_FP32) return sigma32(h, (const float*)x, (float*)y);
+  return fail(h, ESMP2_INVALID_ARG, "unknown precision");
 }
 
+}  // extern "C"
+
 // weighted dot product into h->sc[slot] (stream ordered)
-static void wdot(esmp2_handle h, const double* x, const double* y, int slot) {
+template <class T>
+static void wdot(esmp2_handle h, const T* x, const T* y, int slot) {
   const Dims& d = h->d;
-  hipLaunchKernelGGL(k_dot, dim3(PCG_BLOCKS), dim3(256), 0, h->stream, x, y, d.off[7], d.off[1], d.off[2],
+  hipLaunchKernelGGL(k_dot<T>, dim3(PCG_BLOCKS), dim3(256), 0, h->stream, x, y, d.off[7], d.off[1], d.off[2],
                      h->partial);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, h->stream, h->partial, PCG_BLOCKS, h->sc, slot);
 }
 
-esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res) {
-  if (!h) return ESMP2_INVALID_ARG;
-  if (!opts || !res) return fail(h, ESMP2_INVALID_ARG, "null opts/result");
-  if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
-  if (!(opts->tol > 0) || opts->max_iter < 1) return fail(h, ESMP2_INVALID_ARG, "tol > 0 and max_iter >= 1");
-  if (opts->precision != ESMP2_FP64) return fail(h, ESMP2_UNSUPPORTED, "precision not implemented");
-  ESMP2_HIP(hipSetDevice(h->device));
-  memset(res, 0, sizeof(*res));
-  if (!h->have_rhs) {
-    esmp2_status st = build_rhs(h);
-    if (st != ESMP2_OK) { res->status = st; return st; }
-  }
+extern "C" {
+
+// E2 (Hylleraas form <b,x>_W - <x,r>_W, r = -b - A x) and the result record
+static esmp2_status finish_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res, double rel,
+                                 int it, int outer, esmp2_status status) {
+  const int64_t n = h->d.off[7];
+  hipStream_t s = h->stream;
+  double hs[SC_N];
+  wdot(h, (const double*)h->b, (const double*)h->x, SC_BX);
+  wdot(h, (const double*)h->x, (const double*)h->r, SC_XR);
+  ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+  if (opts->x_out) ESMP2_HIP(hipMemcpyAsync(opts->x_out, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  ESMP2_HIP(hipStreamSynchronize(s));
+  ESMP2_HIP(hipGetLastError());
+  res->e2_dl = hs[SC_BX] - hs[SC_XR];
+  res->e2_s = h->e2s;
+  res->e2 = res->e2_dl + res->e2_s;
+  res->e0 = h->e0;
+  res->rel_resid = rel;
+  res->iterations = it;
+  res->outer = outer;
+  res->status = status;
+  return status;
+}
+
+// Jacobi-preconditioned conjugate gradient in FP64 for A x = -b
+static esmp2_status solve64(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res) {
   const Dims& d = h->d;
   const int64_t n = d.off[7];
   hipStream_t s = h->stream;
   const unsigned NB = PCG_BLOCKS;
-  // ||b||_W
-  wdot(h, h->b, h->b, SC_BB);
+  wdot(h, (const double*)h->b, (const double*)h->b, SC_BB);   // ||b||_W^2
   if (opts->x0) {
     ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     esmp2_status st = sigma64(h, h->x, h->q);
@@ -581,8 +645,8 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
     hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, h->b, (const double*)nullptr, h->r, h->p, h->dinv, n,
                        d.off[1], d.off[2], h->partial);
   }
-  hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);  // RHO, then PQ slot
-  // k_finish wrote rho into SC_RHO and rr into SC_RHO+1 = SC_PQ; move rr
+  // rho = <r, D^-1 r> into SC_RHO and <r, r> into SC_RHO + 1 = SC_PQ
+  hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);
   double hs[SC_N];
   ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
@@ -593,8 +657,8 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
   while (rel > opts->tol && it < opts->max_iter) {
     esmp2_status st = sigma64(h, h->p, h->q);
     if (st != ESMP2_OK) return st;
-    wdot(h, h->p, h->q, SC_PQ);
-    hipLaunchKernelGGL(k_update_xr, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, h->dinv, n, d.off[1],
+    wdot(h, (const double*)h->p, (const double*)h->q, SC_PQ);
+    hipLaunchKernelGGL(k_update_xr<double>, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, h->dinv, n, d.off[1],
                        d.off[2], h->sc, h->partial);
     hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);  // RHO_NEW, RR
     ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
@@ -602,28 +666,106 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
     if (!(hs[SC_PQ] > 0.0)) { status = ESMP2_NOT_SPD; h->err = "p.Ap <= 0 in conjugate gradient"; break; }
     ++it;
     rel = sqrt(hs[SC_RR]) / bn;
-    if (opts->resid_hist && it <= opts->max_iter) opts->resid_hist[it - 1] = rel;
+    if (opts->resid_hist) opts->resid_hist[it - 1] = rel;
     if (rel <= opts->tol) break;
-    hipLaunchKernelGGL(k_update_p, dim3(NB), dim3(256), 0, s, h->p, h->r, h->dinv, n, h->sc);
+    hipLaunchKernelGGL(k_update_p<double>, dim3(NB), dim3(256), 0, s, h->p, h->r, h->dinv, n, h->sc);
     hipLaunchKernelGGL(k_roll_rho, dim3(1), dim3(64), 0, s, h->sc);
   }
   if (status == ESMP2_OK && rel > opts->tol) { status = ESMP2_NOT_CONVERGED; h->err = "max_iter reached"; }
-  // E2 (Hylleraas): <b,x>_W - <x,r>_W
-  wdot(h, h->b, h->x, SC_BX);
-  wdot(h, h->x, h->r, SC_XR);
+  return finish_solve(h, opts, res, rel, it, 0, status);
+}
+
+// Mixed precision: FP64 iterative refinement around FP32 inner solves.
+//   r = -b - A64 x;  repeat: d = A32^-1 (r / ||r||) by FP32 Jacobi-PCG to a
+//   relative reduction eta;  x += ||r|| d;  r = -b - A64 x;  until ||r||/||b|| <= tol.
+// eta = max(inner_tol, tol / (2 ||r||/||b||)): the last inner solve stops as soon
+// as it reaches the target; inner_tol bounds what an FP32 operator can deliver.
+static esmp2_status solve_mixed(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res) {
+  const Dims& d = h->d;
+  const int64_t n = d.off[7];
+  hipStream_t s = h->stream;
+  const unsigned NB = PCG_BLOCKS;
+  const double floor_eta = opts->inner_tol > 0 ? opts->inner_tol : 1e-5;
+  wdot(h, (const double*)h->b, (const double*)h->b, SC_BB);
+  if (opts->x0) {
+    ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    esmp2_status st = sigma64(h, h->x, h->q);
+    if (st != ESMP2_OK) return st;
+    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, h->b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
+                       h->partial);
+  } else {
+    ESMP2_HIP(hipMemsetAsync(h->x, 0, sizeof(double) * n, s));
+    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, h->b, (const double*)nullptr, h->r, n, d.off[1],
+                       d.off[2], h->partial);
+  }
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RR);
+  double hs[SC_N];
   ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
-  if (opts->x_out) ESMP2_HIP(hipMemcpyAsync(opts->x_out, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   ESMP2_HIP(hipStreamSynchronize(s));
-  ESMP2_HIP(hipGetLastError());
-  res->e2_dl = hs[SC_BX] - hs[SC_XR];
-  res->e2_s = h->e2s;
-  res->e2 = res->e2_dl + res->e2_s;
-  res->e0 = h->e0;
-  res->rel_resid = rel;
-  res->iterations = it;
-  res->outer = 0;
-  res->status = status;
-  return status;
+  const double bn = sqrt(hs[SC_BB]);
+  double rel = sqrt(hs[SC_RR]) / bn;
+  int it = 0, outer = 0;
+  esmp2_status status = ESMP2_OK;
+  while (rel > opts->tol && it < opts->max_iter && status == ESMP2_OK) {
+    ++outer;
+    const double scale = rel * bn;
+    const double eta = std::max(floor_eta, 0.5 * opts->tol / rel);
+    hipLaunchKernelGGL(k_init_inner, dim3(NB), dim3(256), 0, s, (const double*)h->r, scale, h->r32, h->p32, h->d32,
+                       (const float*)h->dinv32, n, d.off[1], d.off[2], h->partial);
+    hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);  // RHO, rr0
+    ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+    ESMP2_HIP(hipStreamSynchronize(s));
+    const double rr0 = hs[SC_PQ];
+    while (it < opts->max_iter) {
+      esmp2_status st = sigma32(h, h->p32, h->q32);
+      if (st != ESMP2_OK) return st;
+      wdot(h, (const float*)h->p32, (const float*)h->q32, SC_PQ);
+      hipLaunchKernelGGL(k_update_xr<float>, dim3(NB), dim3(256), 0, s, h->d32, h->r32, (const float*)h->p32,
+                         (const float*)h->q32, (const float*)h->dinv32, n, d.off[1], d.off[2], (const double*)h->sc,
+                         h->partial);
+      hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);
+      ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+      ESMP2_HIP(hipStreamSynchronize(s));
+      if (!(hs[SC_PQ] > 0.0)) { status = ESMP2_NOT_SPD; h->err = "p.Ap <= 0 in conjugate gradient"; break; }
+      ++it;
+      const double irel = sqrt(hs[SC_RR] / rr0);
+      if (opts->resid_hist) opts->resid_hist[it - 1] = irel * rel;   // estimate of the FP64 residual
+      if (irel <= eta) break;
+      hipLaunchKernelGGL(k_update_p<float>, dim3(NB), dim3(256), 0, s, h->p32, (const float*)h->r32,
+                         (const float*)h->dinv32, n, (const double*)h->sc);
+      hipLaunchKernelGGL(k_roll_rho, dim3(1), dim3(64), 0, s, h->sc);
+    }
+    if (status != ESMP2_OK) break;
+    hipLaunchKernelGGL(k_refine, dim3(NB), dim3(256), 0, s, h->x, (const float*)h->d32, scale, n);
+    esmp2_status st = sigma64(h, h->x, h->q);
+    if (st != ESMP2_OK) return st;
+    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, h->b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
+                       h->partial);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RR);
+    ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+    ESMP2_HIP(hipStreamSynchronize(s));
+    rel = sqrt(hs[SC_RR]) / bn;
+  }
+  if (status == ESMP2_OK && rel > opts->tol) { status = ESMP2_NOT_CONVERGED; h->err = "max_iter reached"; }
+  return finish_solve(h, opts, res, rel, it, outer, status);
+}
+
+esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (!opts || !res) return fail(h, ESMP2_INVALID_ARG, "null opts/result");
+  if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
+  if (!(opts->tol > 0) || opts->max_iter < 1) return fail(h, ESMP2_INVALID_ARG, "tol > 0 and max_iter >= 1");
+  if (opts->precision != ESMP2_FP64 && opts->precision != ESMP2_FP32)
+    return fail(h, ESMP2_INVALID_ARG, "unknown precision");
+  if (opts->precision == ESMP2_FP32 && !(opts->inner_tol >= 0 && opts->inner_tol < 1))
+    return fail(h, ESMP2_INVALID_ARG, "inner_tol must lie in [0, 1)");
+  ESMP2_HIP(hipSetDevice(h->device));
+  memset(res, 0, sizeof(*res));
+  if (!h->have_rhs) {
+    esmp2_status st = build_rhs(h);
+    if (st != ESMP2_OK) { res->status = st; return st; }
+  }
+  return opts->precision == ESMP2_FP64 ? solve64(h, opts, res) : solve_mixed(h, opts, res);
 }
 
 }  // extern "C"

@@ -1,6 +1,8 @@
 // Krylov vector kernels: weighted dot products and fused preconditioned CG
-// updates (FP64).  Inner-product weight w = 1 on the S2 box, 2 elsewhere
-// (every other stored amplitude stands for a spin-flip pair of determinants).
+// updates, for FP64 vectors and for the FP32 vectors of the inner solves of
+// the mixed-precision refinement (whose reductions still accumulate in FP64).
+// Inner-product weight w = 1 on the S2 box, 2 elsewhere (every other stored
+// amplitude stands for a spin-flip pair of determinants).
 #include "common.h"
 #include "reduce.h"
 #include "pcg.h"
@@ -10,16 +12,17 @@ namespace esmp2 {
 __device__ inline double wgt(int64_t g, int64_t s0, int64_t s1) { return (g >= s0 && g < s1) ? 1.0 : 2.0; }
 
 // partial[block] = sum_g w_g x_g y_g   (grid-stride, fixed grid -> deterministic)
-__global__ __launch_bounds__(256) void k_dot(const double* x, const double* y, int64_t n, int64_t s0,
-                                             int64_t s1, double* partial) {
+template <class T>
+__global__ __launch_bounds__(256) void k_dot(const T* x, const T* y, int64_t n, int64_t s0, int64_t s1,
+                                             double* partial) {
   Acc2 acc;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
-    acc.add(wgt(g, s0, s1) * x[g] * y[g]);
+    acc.add(wgt(g, s0, s1) * (double)x[g] * (double)y[g]);
   double s = block_sum2(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// sc[k] = sum of partials[k*nb .. k*nb+nb-1]  for k < nsum (one block per sum)
+// sc[base + k] = sum of partials[k*nb .. k*nb+nb-1], one block per sum
 __global__ void k_finish(const double* partial, int nb, double* sc, int base) {
   Acc2 acc;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) acc.add(partial[(int64_t)blockIdx.x * nb + i]);
@@ -28,29 +31,29 @@ __global__ void k_finish(const double* partial, int nb, double* sc, int base) {
 }
 
 // alpha = sc[RHO] / sc[PQ];  x += alpha p;  r -= alpha q;
-// partials of <r, D^-1 r>_W and <r, r>_W (two partial arrays of nb each)
-__global__ __launch_bounds__(256) void k_update_xr(double* x, double* r, const double* p, const double* q,
-                                                   const double* dinv, int64_t n, int64_t s0, int64_t s1,
-                                                   const double* sc, double* partial) {
-  const double alpha = sc[SC_RHO] / sc[SC_PQ];
+// partials of <r, D^-1 r>_W and <r, r>_W (two partial arrays of gridDim.x each)
+template <class T>
+__global__ __launch_bounds__(256) void k_update_xr(T* x, T* r, const T* p, const T* q, const T* dinv, int64_t n,
+                                                   int64_t s0, int64_t s1, const double* sc, double* partial) {
+  const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
   double rz = 0.0, rr = 0.0;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-    double rg = r[g] - alpha * q[g];
+    const T rg = r[g] - alpha * q[g];
     x[g] += alpha * p[g];
     r[g] = rg;
-    double w = wgt(g, s0, s1);
-    rz += w * rg * rg * dinv[g];
-    rr += w * rg * rg;
+    const double w = wgt(g, s0, s1), rd = (double)rg;
+    rz += w * rd * rd * (double)dinv[g];
+    rr += w * rd * rd;
   }
   double a = block_sum(rz);
   double b = block_sum(rr);
   if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = b; }
 }
 
-// p = D^-1 r + beta p,  beta = sc[RHO_NEW] / sc[RHO]; then sc[RHO] = sc[RHO_NEW] (block 0 after use)
-__global__ __launch_bounds__(256) void k_update_p(double* p, const double* r, const double* dinv, int64_t n,
-                                                  const double* sc) {
-  const double beta = sc[SC_RHO_NEW] / sc[SC_RHO];
+// p = D^-1 r + beta p,  beta = sc[RHO_NEW] / sc[RHO]
+template <class T>
+__global__ __launch_bounds__(256) void k_update_p(T* p, const T* r, const T* dinv, int64_t n, const double* sc) {
+  const T beta = (T)(sc[SC_RHO_NEW] / sc[SC_RHO]);
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
     p[g] = dinv[g] * r[g] + beta * p[g];
 }
@@ -77,10 +80,60 @@ __global__ __launch_bounds__(256) void k_init(const double* b, const double* y, 
   if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = c; }
 }
 
-// x += d (refinement); also used to copy
-__global__ void k_axpy(double* y, const double* x, double a, int64_t n) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
-    y[g] += a * x[g];
+// FP64 residual of the refinement: r = -b - y (y = A x, or NULL for x = 0);  partials of <r, r>_W
+__global__ __launch_bounds__(256) void k_resid(const double* b, const double* y, double* r, int64_t n, int64_t s0,
+                                               int64_t s1, double* partial) {
+  Acc2 acc;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    const double rg = -b[g] - (y ? y[g] : 0.0);
+    r[g] = rg;
+    acc.add(wgt(g, s0, s1) * rg * rg);
+  }
+  double s = block_sum2(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
+
+// Start of an inner FP32 solve A d = r64 / s (s = scale, the norm of r64):
+// r = fl(r64 / s), d = 0, p = D^-1 r; partials of <r, D^-1 r>, <r, r> (FP64 sums)
+__global__ __launch_bounds__(256) void k_init_inner(const double* r64, double scale, float* r, float* p,
+                                                    float* d, const float* dinv, int64_t n, int64_t s0, int64_t s1,
+                                                    double* partial) {
+  const double inv = 1.0 / scale;
+  double rz = 0.0, rr = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+    const float rg = (float)(r64[g] * inv);
+    r[g] = rg;
+    d[g] = 0.f;
+    p[g] = dinv[g] * rg;
+    const double w = wgt(g, s0, s1), rd = (double)rg;
+    rz += w * rd * rd * (double)dinv[g];
+    rr += w * rd * rd;
+  }
+  double a = block_sum(rz);
+  double c = block_sum(rr);
+  if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = c; }
+}
+
+// x += scale d, the refinement update in FP64
+__global__ __launch_bounds__(256) void k_refine(double* x, const float* d, double scale, int64_t n) {
+  const double s = scale;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+    x[g] += s * (double)d[g];
+}
+
+// b = fl32(a), round to nearest
+__global__ void k_to_f32(const double* a, float* b, int64_t n) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+    b[g] = (float)a[g];
+}
+
+template __global__ void k_dot<double>(const double*, const double*, int64_t, int64_t, int64_t, double*);
+template __global__ void k_dot<float>(const float*, const float*, int64_t, int64_t, int64_t, double*);
+template __global__ void k_update_xr<double>(double*, double*, const double*, const double*, const double*, int64_t,
+                                             int64_t, int64_t, const double*, double*);
+template __global__ void k_update_xr<float>(float*, float*, const float*, const float*, const float*, int64_t,
+                                            int64_t, int64_t, const double*, double*);
+template __global__ void k_update_p<double>(double*, const double*, const double*, int64_t, const double*);
+template __global__ void k_update_p<float>(float*, const float*, const float*, int64_t, const double*);
 
 }  // namespace esmp2

@@ -19,49 +19,50 @@ namespace esmp2 {
 // ---------------------------------------------------------------------------
 // amplitude lookups with antisymmetry (zero where the Pauli principle forbids)
 // ---------------------------------------------------------------------------
+template <class T>
 struct Look {
   Dims d;
-  const double* x;
-  const double* S;      // flip-symmetrised S2, dense [i][j][a][b]
-  __device__ double T2(int i, int j, int a, int b) const {
-    if (i == j || a == b) return 0.0;
-    double s = 1.0;
+  const T* x;
+  const T* S;      // flip-symmetrised S2, dense [i][j][a][b]
+  __device__ T T2(int i, int j, int a, int b) const {
+    if (i == j || a == b) return 0;
+    T s = 1;
     if (i > j) { int t = i; i = j; j = t; s = -s; }
     if (a > b) { int t = a; a = b; b = t; s = -s; }
     return s * x[d.off[B_T2] + (int64_t)tri_idx(i, j, d.no) * d.npv + tri_idx(a, b, d.nv)];
   }
-  __device__ double T3(int j, int k, int b, int c) const {      // all indices >= 1
-    if (j == k || b == c) return 0.0;
-    double s = 1.0;
+  __device__ T T3(int j, int k, int b, int c) const {      // all indices >= 1
+    if (j == k || b == c) return 0;
+    T s = 1;
     if (j > k) { int t = j; j = k; k = t; s = -s; }
     if (b > c) { int t = b; b = c; c = t; s = -s; }
     return s * x[d.off[B_T3] + (int64_t)tri_idx(j - 1, k - 1, d.no - 1) * d.npv1 + tri_idx(b - 1, c - 1, d.nv - 1)];
   }
-  __device__ double H11(int j, int k, int b, int c) const {
-    if (j == k || b == c) return 0.0;
-    double s = 1.0;
+  __device__ T H11(int j, int k, int b, int c) const {
+    if (j == k || b == c) return 0;
+    T s = 1;
     if (j > k) { int t = j; j = k; k = t; s = -s; }
     if (b > c) { int t = b; b = c; c = t; s = -s; }
     return s * x[d.off[B_H11] + (int64_t)tri_idx(j, k, d.no) * d.npv + tri_idx(b, c, d.nv)];
   }
-  __device__ double H12(int j, int k, int a, int c) const {     // a, c >= 1
-    if (j == k) return 0.0;
-    double s = 1.0;
+  __device__ T H12(int j, int k, int a, int c) const {     // a, c >= 1
+    if (j == k) return 0;
+    T s = 1;
     if (j > k) { int t = j; j = k; k = t; s = -s; }
     int m1 = d.nv - 1;
     return s * x[d.off[B_H12] + ((int64_t)tri_idx(j, k, d.no) * m1 + (a - 1)) * m1 + (c - 1)];
   }
-  __device__ double H21(int i, int k, int b, int c) const {     // i, k >= 1
-    if (b == c) return 0.0;
-    double s = 1.0;
+  __device__ T H21(int i, int k, int b, int c) const {     // i, k >= 1
+    if (b == c) return 0;
+    T s = 1;
     if (b > c) { int t = b; b = c; c = t; s = -s; }
     return s * x[d.off[B_H21] + ((int64_t)(i - 1) * (d.no - 1) + (k - 1)) * d.npv + tri_idx(b, c, d.nv)];
   }
-  __device__ double H22(int i, int k, int a, int c) const {     // all >= 1
+  __device__ T H22(int i, int k, int a, int c) const {     // all >= 1
     int m1 = d.nv - 1;
     return x[d.off[B_H22] + (((int64_t)(i - 1) * (d.no - 1) + (k - 1)) * m1 + (a - 1)) * m1 + (c - 1)];
   }
-  __device__ double St(int i, int j, int a, int b) const {
+  __device__ T St(int i, int j, int a, int b) const {
     return S[(((int64_t)i * d.no + j) * d.nv + a) * d.nv + b];
   }
 };
@@ -69,7 +70,8 @@ struct Look {
 // ---------------------------------------------------------------------------
 // S~ = (x_S2 + flip x_S2)/2, flip: (i,j,a,b) -> (j,i,b,a)
 // ---------------------------------------------------------------------------
-__global__ void k_sym_s2(Dims d, const double* x, double* S) {
+template <class T>
+__global__ void k_sym_s2(Dims d, const T* x, T* S) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t n = (int64_t)d.no * d.no * d.nv * d.nv;
   if (g >= n) return;
@@ -77,8 +79,8 @@ __global__ void k_sym_s2(Dims d, const double* x, double* S) {
   int b = r % d.nv; r /= d.nv;
   int a = r % d.nv; r /= d.nv;
   int j = r % d.no; int i = r / d.no;
-  const double* s2 = x + d.off[B_S2];
-  S[g] = 0.5 * (s2[g] + s2[(((int64_t)j * d.no + i) * d.nv + b) * d.nv + a]);
+  const T* s2 = x + d.off[B_S2];
+  S[g] = T(0.5) * (s2[g] + s2[(((int64_t)j * d.no + i) * d.nv + b) * d.nv + a]);
 }
 
 // ---------------------------------------------------------------------------
@@ -89,16 +91,18 @@ __global__ void k_sym_s2(Dims d, const double* x, double* S) {
 // ---------------------------------------------------------------------------
 enum Fmt { F_PACK = 0, F_PACK_RED = 1, F_DENSE_RED = 2, F_DENSE = 3 };
 
+template <class T>
 struct JobView {
   int fmt, m;            // storage format and its matrix dimension
-  const double* src;     // this batch's storage
-  double* dst;
-  double* tr;            // transfer row (row 0 of the embedded product) or null
+  const T* src;          // this batch's storage
+  T* dst;
+  T* tr;               // transfer row (row 0 of the embedded product) or null
 };
 
-__device__ inline JobView job_view(const VVArgs& A, int box, int batch) {
+template <class T>
+__device__ inline JobView<T> job_view(const VVArgs<T>& A, int box, int batch) {
   const Dims& d = A.d;
-  JobView v;
+  JobView<T> v;
   v.tr = nullptr;
   int64_t o = d.off[box];
   switch (box) {
@@ -124,7 +128,8 @@ __device__ inline JobView job_view(const VVArgs& A, int box, int batch) {
 }
 
 // element (r, c) of the embedded batch matrix
-__device__ inline double xget(const JobView& v, int r, int c) {
+template <class T>
+__device__ inline T xget(const JobView<T>& v, int r, int c) {
   switch (v.fmt) {
     case F_PACK: {
       if (r >= v.m || c >= v.m || r == c) return 0.0;
@@ -144,7 +149,8 @@ __device__ inline double xget(const JobView& v, int r, int c) {
   }
 }
 
-__device__ inline void yput(const JobView& v, int r, int c, double val) {
+template <class T>
+__device__ inline void yput(const JobView<T>& v, int r, int c, T val) {
   switch (v.fmt) {
     case F_PACK:
       if (r < c && c < v.m) v.dst[tri_idx(r, c, v.m)] = val;
@@ -163,45 +169,46 @@ __device__ inline void yput(const JobView& v, int r, int c, double val) {
   }
 }
 
-template <int TW>
-__global__ __launch_bounds__(256) void k_vv(VVArgs A) {
+template <class T, int TW>
+__global__ __launch_bounds__(256) void k_vv(VVArgs<T> A) {
   constexpr int BR = 32 * TW;
-  __shared__ double As[16][BR + 1];
-  __shared__ double Bs[16][BR + 1];
+  __shared__ T As[16][BR + 1];
+  __shared__ T Bs[16][BR + 1];
   const int2 jb = A.jobs[blockIdx.x];
   const int box = jb.x;
-  const JobView v = job_view(A, box, jb.y);
-  const double* F = (box == B_T2 || box == B_S2) ? A.Fd : A.Fl;
+  const JobView<T> v = job_view(A, box, jb.y);
+  const T* F = (box == B_T2 || box == B_S2) ? A.Fd : A.Fl;
   const int mv = A.d.mv;
   const int R0 = blockIdx.y * BR, C0 = blockIdx.z * BR;
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
   const int wr = (wave >> 1) * TW * 16, wc = (wave & 1) * TW * 16;
-  f64x4 acc[TW][TW];
+  typedef typename MfmaAcc<T>::type AccT;
+  AccT acc[TW][TW];
 #pragma unroll
   for (int i = 0; i < TW; ++i)
 #pragma unroll
-    for (int j = 0; j < TW; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TW; ++j) acc[i][j] = AccT{0, 0, 0, 0};
   for (int k0 = 0; k0 < 2 * mv; k0 += 16) {
     const bool second = k0 >= mv;
     const int kb = second ? k0 - mv : k0;
     for (int e = tid; e < BR * 16; e += 256) {
       int r = e >> 4, kk = e & 15;
       int gr = R0 + r, gk = kb + kk;
-      double val = 0.0;
+      T val = 0;
       if (gr < mv) val = second ? xget(v, gr, gk) : F[gr * mv + gk];
       As[kk][r] = val;
     }
     for (int e = tid; e < BR * 16; e += 256) {
       int c = e % BR, kk = e / BR;
       int gc = C0 + c, gk = kb + kk;
-      double val = 0.0;
+      T val = 0;
       if (gc < mv) val = second ? F[gk * mv + gc] : xget(v, gk, gc);
       Bs[kk][c] = val;
     }
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      double a[TW], b[TW];
+      T a[TW], b[TW];
 #pragma unroll
       for (int t = 0; t < TW; ++t) {
         a[t] = As[ks * 4 + (l >> 4)][wr + t * 16 + (l & 15)];
@@ -220,17 +227,12 @@ __global__ __launch_bounds__(256) void k_vv(VVArgs A) {
     for (int tj = 0; tj < TW; ++tj)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        int r = R0 + wr + ti * 16 + mfma_row(l, i);
+        int r = R0 + wr + ti * 16 + mfma_row_t<T>(l, i);
         int c = C0 + wc + tj * 16 + (l & 15);
         yput(v, r, c, acc[ti][tj][i]);
       }
 }
 
-template __global__ void k_vv<1>(VVArgs);
-template __global__ void k_vv<2>(VVArgs);
-template __global__ void k_vv<3>(VVArgs);
-template __global__ void k_vv<4>(VVArgs);
-template __global__ void k_vv<5>(VVArgs);
 
 // ---------------------------------------------------------------------------
 // Side contractions over one virtual index, per batch of an L box:
@@ -238,12 +240,13 @@ template __global__ void k_vv<5>(VVArgs);
 // with w a column of f_ov (index 0 = t, or the batch's occupied indices).
 // Output layout: side[slot][batch][nv] for each (box, slot), see sigma.h.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_side(SideArgs A) {
+template <class T>
+__global__ __launch_bounds__(256) void k_side(SideArgs<T> A) {
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv;
   const int job = blockIdx.x;
-  Look L{d, A.x, nullptr};
-  const double* fov = A.fov;             // fov[i*nv + a]
+  Look<T> L{d, A.x, nullptr};
+  const T* fov = A.fov;                 // fov[i*nv + a]
   int box, batch;
   if (job < d.npo1) { box = B_T3; batch = job; }
   else if (job < d.npo1 + d.npo) { box = B_H11; batch = job - d.npo1; }
@@ -254,10 +257,10 @@ __global__ __launch_bounds__(256) void k_side(SideArgs A) {
   if (box == B_T3) {
     int j, k; tri_pq(batch, no - 1, j, k); ++j; ++k;
     for (int c = tid; c < nv; c += blockDim.x) {
-      double vt = 0, v1 = 0, v2 = 0;
+      T vt = 0, v1 = 0, v2 = 0;
       if (c >= 1)
         for (int b = 1; b < nv; ++b) {
-          double xv = L.T3(j, k, b, c);
+          T xv = L.T3(j, k, b, c);
           vt += fov[b] * xv; v1 += fov[j * nv + b] * xv; v2 += fov[k * nv + b] * xv;
         }
       A.t3_t[batch * nv + c] = vt; A.t3_p1[batch * nv + c] = v1; A.t3_p2[batch * nv + c] = v2;
@@ -265,9 +268,9 @@ __global__ __launch_bounds__(256) void k_side(SideArgs A) {
   } else if (box == B_H11) {
     int j, k; tri_pq(batch, no, j, k);
     for (int c = tid; c < nv; c += blockDim.x) {
-      double v1 = 0, v2 = 0;
+      T v1 = 0, v2 = 0;
       for (int b = 0; b < nv; ++b) {
-        double xv = L.H11(j, k, b, c);
+        T xv = L.H11(j, k, b, c);
         v1 += fov[j * nv + b] * xv; v2 += fov[k * nv + b] * xv;
       }
       A.h11_p1[batch * nv + c] = v1; A.h11_p2[batch * nv + c] = v2;
@@ -275,11 +278,11 @@ __global__ __launch_bounds__(256) void k_side(SideArgs A) {
   } else if (box == B_H12) {
     int j, k; tri_pq(batch, no, j, k);
     for (int c = tid; c < nv; c += blockDim.x) {
-      double vt = 0, u1 = 0, u2 = 0;
+      T vt = 0, u1 = 0, u2 = 0;
       if (c >= 1)
         for (int x = 1; x < nv; ++x) {
           vt += fov[x] * L.H12(j, k, x, c);             // sum_a f_{a t} X[a][c]
-          double xr = L.H12(j, k, c, x);                // row c (= a), column x
+          T xr = L.H12(j, k, c, x);                // row c (= a), column x
           u1 += xr * fov[j * nv + x]; u2 += xr * fov[k * nv + x];
         }
       A.h12_t[batch * nv + c] = vt; A.h12_u1[batch * nv + c] = u1; A.h12_u2[batch * nv + c] = u2;
@@ -287,9 +290,9 @@ __global__ __launch_bounds__(256) void k_side(SideArgs A) {
   } else if (box == B_H21) {
     int i = batch / (no - 1) + 1, k = batch % (no - 1) + 1;
     for (int c = tid; c < nv; c += blockDim.x) {
-      double vt = 0, vk = 0;
+      T vt = 0, vk = 0;
       for (int b = 0; b < nv; ++b) {
-        double xv = L.H21(i, k, b, c);
+        T xv = L.H21(i, k, b, c);
         vt += fov[b] * xv; vk += fov[k * nv + b] * xv;
       }
       A.h21_t[batch * nv + c] = vt; A.h21_k[batch * nv + c] = vk;
@@ -297,10 +300,10 @@ __global__ __launch_bounds__(256) void k_side(SideArgs A) {
   } else {
     int i = batch / (no - 1) + 1, k = batch % (no - 1) + 1;
     for (int c = tid; c < nv; c += blockDim.x) {
-      double ut = 0, vi = 0, uk = 0;
+      T ut = 0, vi = 0, uk = 0;
       if (c >= 1)
         for (int x = 1; x < nv; ++x) {
-          double xr = L.H22(i, k, c, x);                // row c (= a), column x
+          T xr = L.H22(i, k, c, x);                // row c (= a), column x
           ut += xr * fov[x]; uk += xr * fov[k * nv + x];
           vi += fov[i * nv + x] * L.H22(i, k, x, c);    // sum_a f_{a i} X[a][c]
         }
@@ -310,8 +313,11 @@ __global__ __launch_bounds__(256) void k_side(SideArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-element gather: occupied-index Fock action, box transfers, doubles <->
-// L-triples couplings.  y += ... (the virtual-pair part is already in y).
+// Per-element couplings other than the two Fock contractions over the free
+// index pairs: box transfers through a pinned TOP index (f_{t' a}, f_{m t}),
+// doubles <-> L-triples through f_ov (with the side contractions of k_side),
+// y += ... (the virtual-pair part is already in y, k_oo adds the occupied
+// pair part).  One thread per amplitude; pair indices decoded from tables.
 // ---------------------------------------------------------------------------
 __device__ inline int box_of_g(const Dims& d, int64_t g, int64_t& loc) {
   int k = 0;
@@ -320,166 +326,22 @@ __device__ inline int box_of_g(const Dims& d, int64_t g, int64_t& loc) {
   return k;
 }
 
-__global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
+template <class T>
+__global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
+  const int *pv = P.pv, *pv1 = P.pv1, *po = P.po, *po1 = P.po1;
   const Dims& d = A.d;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= d.off[7]) return;
   const int no = d.no, nv = d.nv;
-  Look L{d, A.x, A.S};
-  const double* fo = A.fo;     // fo[m*no + i]
-  const double* fv = A.fv;     // fv[a*nv + b]
-  const double* fov = A.fov;   // fov[i*nv + a]
+  Look<T> L{d, A.x, A.S};
+  const T* fo = A.fo;     // fo[m*no + i]
+  const T* fv = A.fv;     // fv[a*nv + b]
+  const T* fov = A.fov;   // fov[i*nv + a]
   auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
-  const double ftt = FOV(0, 0);
+  const T ftt = FOV(0, 0);
   int64_t loc;
   const int box = box_of_g(d, g, loc);
-  double y = 0.0;
-  switch (box) {
-    case B_T2: {
-      int i, j, a, b;
-      tri_pq(loc / d.npv, no, i, j); tri_pq(loc % d.npv, nv, a, b);
-      for (int m = 0; m < no; ++m) y -= fo[m * no + i] * L.T2(m, j, a, b) + fo[m * no + j] * L.T2(i, m, a, b);
-      if (i >= 1 && a >= 1) y += ftt * L.T3(i, j, a, b);
-      y += ftt * L.H11(i, j, a, b);
-      if (i == 0 && a >= 1)
-        for (int m = 1; m < no; ++m) y -= FOV(m, 0) * L.T3(m, j, a, b);
-      if (i == 0)
-        for (int m = 1; m < no; ++m) y += FOV(m, 0) * L.H21(m, j, a, b);
-      if (a == 0) {
-        int po = tri_idx(i, j, no);
-        if (i >= 1) y -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
-        y += A.h12_t[po * nv + b];
-        if (i == 0) {
-          for (int m = 1; m < no; ++m) {
-            if (m < j) y += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
-            else if (m > j) y -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
-            y += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
-          }
-        }
-      }
-      break;
-    }
-    case B_S2: {
-      int64_t r = loc;
-      int b = r % nv; r /= nv;
-      int a = r % nv; r /= nv;
-      int j = r % no, i = r / no;
-      for (int m = 0; m < no; ++m) y -= fo[m * no + i] * L.St(m, j, a, b) + fo[m * no + j] * L.St(i, m, a, b);
-      // d(p,q,x,z) + d(q,p,z,x): de-excitation of the mixed-spin L-triples
-      for (int rep = 0; rep < 2; ++rep) {
-        int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
-        double dd = 0.0;
-        if (p == 0 && xx == 0) {
-          for (int m = 0; m < no; ++m) {
-            if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
-            else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
-          }
-        }
-        if (p == 0 && xx >= 1 && z >= 1)
-          for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
-        if (p == 0 && xx >= 1 && z == 0) {
-          for (int m = 0; m < no; ++m) {
-            if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
-            else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
-          }
-        }
-        if (p >= 1 && q >= 1 && xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
-        if (p >= 1 && q == 0 && xx == 0)
-          for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
-        if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) dd += ftt * L.H22(p, q, xx, z);
-        if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
-          for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
-        if (p >= 1 && q >= 1 && xx >= 1 && z == 0) dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
-        if (p >= 1 && q == 0 && xx >= 1 && z == 0)
-          for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
-        y += dd;
-      }
-      break;
-    }
-    case B_T3: {
-      int j, k, b, c;
-      tri_pq(loc / d.npv1, no - 1, j, k); tri_pq(loc % d.npv1, nv - 1, b, c);
-      ++j; ++k; ++b; ++c;
-      for (int m = 1; m < no; ++m) y -= fo[m * no + j] * L.T3(m, k, b, c) + fo[m * no + k] * L.T3(j, m, b, c);
-      y += ftt * L.T2(j, k, b, c) - FOV(j, 0) * L.T2(0, k, b, c) + FOV(k, 0) * L.T2(0, j, b, c)
-         - FOV(0, b) * L.T2(j, k, 0, c) + FOV(j, b) * L.T2(0, k, 0, c) - FOV(k, b) * L.T2(0, j, 0, c)
-         + FOV(0, c) * L.T2(j, k, 0, b) - FOV(j, c) * L.T2(0, k, 0, b) + FOV(k, c) * L.T2(0, j, 0, b);
-      break;
-    }
-    case B_H11: {
-      int j, k, b, c;
-      tri_pq(loc / d.npv, no, j, k); tri_pq(loc % d.npv, nv, b, c);
-      for (int m = 0; m < no; ++m) y -= fo[m * no + j] * L.H11(m, k, b, c) + fo[m * no + k] * L.H11(j, m, b, c);
-      if (b == 0) y += A.side_tr[(int64_t)tri_idx(j, k, no) * nv + c];
-      if (j == 0)
-        for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H21(m, k, b, c);
-      y += ftt * L.T2(j, k, b, c);
-      y += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
-         - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
-      break;
-    }
-    case B_H12: {
-      int m1 = nv - 1;
-      int j, k;
-      tri_pq(loc / (m1 * m1), no, j, k);
-      int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
-      for (int m = 0; m < no; ++m) y -= fo[m * no + j] * L.H12(m, k, a, c) + fo[m * no + k] * L.H12(j, m, a, c);
-      y += fv[a * nv + 0] * L.H11(j, k, 0, c);
-      if (j == 0)
-        for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H22(m, k, a, c);
-      y += FOV(0, a) * L.T2(j, k, 0, c);
-      y += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
-         - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
-      break;
-    }
-    case B_H21: {
-      int o = loc / d.npv, b, c;
-      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-      tri_pq(loc % d.npv, nv, b, c);
-      for (int m = 1; m < no; ++m) y -= fo[m * no + i] * L.H21(m, k, b, c) + fo[m * no + k] * L.H21(i, m, b, c);
-      y -= fo[0 * no + i] * L.H11(0, k, b, c);
-      if (b == 0) y += A.side_tr[((int64_t)d.npo + o) * nv + c];
-      y += FOV(i, 0) * L.T2(0, k, b, c);
-      y += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
-         - FOV(0, c) * L.St(i, k, 0, b) + FOV(k, c) * L.St(i, 0, 0, b);
-      break;
-    }
-    default: {
-      int m1 = nv - 1;
-      int o = loc / (m1 * m1);
-      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-      int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
-      for (int m = 1; m < no; ++m) y -= fo[m * no + i] * L.H22(m, k, a, c) + fo[m * no + k] * L.H22(i, m, a, c);
-      y -= fo[0 * no + i] * L.H12(0, k, a, c);
-      y += fv[a * nv + 0] * L.H21(i, k, 0, c);
-      y += FOV(i, a) * L.T2(0, k, 0, c);
-      y += ftt * L.St(i, k, a, c) - FOV(k, 0) * L.St(i, 0, a, c)
-         - FOV(0, c) * L.St(i, k, a, 0) + FOV(k, c) * L.St(i, 0, a, 0);
-      break;
-    }
-  }
-  A.y[g] += y;
-}
-
-// As k_gather, without the occupied-index contraction (k_oo does it on the
-// matrix cores) and without its two transfer rows; pair indices decoded from
-// tables (pv: virtual pairs of nv, pv1: of nv-1, po: occupied pairs of no,
-// po1: of no-1; each entry (p << 16) | q).
-__global__ __launch_bounds__(256) void k_gather4(GatherArgs A, const int* pv, const int* pv1, const int* po,
-                                                  const int* po1) {
-  const Dims& d = A.d;
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= d.off[7]) return;
-  const int no = d.no, nv = d.nv;
-  Look L{d, A.x, A.S};
-  const double* fo = A.fo;     // fo[m*no + i]
-  const double* fv = A.fv;     // fv[a*nv + b]
-  const double* fov = A.fov;   // fov[i*nv + a]
-  auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
-  const double ftt = FOV(0, 0);
-  int64_t loc;
-  const int box = box_of_g(d, g, loc);
-  double y = 0.0;
+  T y = 0;
   switch (box) {
     case B_T2: {
       int i, j, a, b;
@@ -512,7 +374,7 @@ __global__ __launch_bounds__(256) void k_gather4(GatherArgs A, const int* pv, co
       // d(p,q,x,z) + d(q,p,z,x): de-excitation of the mixed-spin L-triples
       for (int rep = 0; rep < 2; ++rep) {
         int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
-        double dd = 0.0;
+        T dd = 0;
         if (p == 0 && xx == 0) {
           for (int m = 0; m < no; ++m) {
             if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
@@ -603,606 +465,17 @@ __global__ __launch_bounds__(256) void k_gather4(GatherArgs A, const int* pv, co
 namespace esmp2 {
 
 // ---------------------------------------------------------------------------
-// Sylvester kernel for mv <= 160 (at most 10 x 10 tiles of 16), one job per
-// workgroup of 4 wavefronts:
-//   JK_FULL   dense output (H1P2, H2P2)
-//   JK_UPPER  antisymmetric output: only tiles on/above the diagonal
-//   JK_S2PAIR flip-symmetrised S2 pair (i < j): Y written to (i,j), Y^T to (j,i)
-//   JK_S2DIAG S2 with i = j: symmetric Y, tiles on/above the diagonal
-// Global -> LDS staging of the next 16-wide K chunk is prefetched into
-// registers while the current chunk runs on the matrix cores.
-// ---------------------------------------------------------------------------
-enum { JK_FULL = 0, JK_UPPER = 1, JK_S2PAIR = 2, JK_S2DIAG = 3 };
-
-struct Rect { int r0, r1, c0, c1; bool mask; };
-
-__device__ inline Rect wave_rect(int kind, int wave, int T) {
-  const int h = (T + 1) / 2;
-  Rect R;
-  if (kind == JK_FULL || kind == JK_S2PAIR) {
-    int wr = wave >> 1, wc = wave & 1;
-    R.r0 = wr * h; R.r1 = min(T, (wr + 1) * h);
-    R.c0 = wc * h; R.c1 = min(T, (wc + 1) * h);
-    R.mask = false;
-  } else {
-    const int split = h + (T - h) / 2;
-    switch (wave) {
-      case 0: R.r0 = 0; R.r1 = h; R.c0 = 0; R.c1 = h; R.mask = true; break;
-      case 1: R.r0 = 0; R.r1 = h; R.c0 = split; R.c1 = T; R.mask = false; break;
-      case 2: R.r0 = 0; R.r1 = h; R.c0 = h; R.c1 = split; R.mask = false; break;
-      default: R.r0 = h; R.r1 = T; R.c0 = h; R.c1 = T; R.mask = true; break;
-    }
-  }
-  return R;
-}
-
-__global__ __launch_bounds__(256) void k_vv2(VVArgs A) {
-  constexpr int MV = 160, PREF = (MV * 16) / 256;
-  __shared__ double As[16][MV + 1];
-  __shared__ double Bs[16][MV + 1];
-  const int4 jb = A.jobs4[blockIdx.x];
-  const int box = jb.x, kind = jb.z;
-  const Dims& d = A.d;
-  const int mv = d.mv, T = mv / 16;
-  JobView v;
-  int si = 0, sj = 0;
-  if (box == B_S2) {
-    si = jb.y; sj = jb.w;
-    v.fmt = F_DENSE; v.m = d.nv; v.tr = nullptr;
-    v.src = A.S + ((int64_t)si * d.no + sj) * d.nv * d.nv;
-    v.dst = A.y + d.off[B_S2] + ((int64_t)si * d.no + sj) * d.nv * d.nv;
-  } else {
-    v = job_view(A, box, jb.y);
-  }
-  const double* F = (box == B_T2 || box == B_S2) ? A.Fd : A.Fl;
-  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
-  const Rect R = wave_rect(kind, wave, T);
-  f64x4 acc[5][5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i)
-#pragma unroll
-    for (int j = 0; j < 5; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  double pa[PREF], pb[PREF];
-  auto fetch = [&](int k0) {
-    const bool second = k0 >= mv;
-    const int kb = second ? k0 - mv : k0;
-#pragma unroll
-    for (int t = 0; t < PREF; ++t) {
-      int e = tid + 256 * t;
-      double va = 0.0, vb = 0.0;
-      if (e < mv * 16) {
-        int r = e >> 4, kk = e & 15;
-        va = second ? xget(v, r, kb + kk) : F[r * mv + kb + kk];
-        int c = e % mv, k2 = e / mv;
-        vb = second ? F[(kb + k2) * mv + c] : xget(v, kb + k2, c);
-      }
-      pa[t] = va;
-      pb[t] = vb;
-    }
-  };
-  auto stash = [&]() {
-#pragma unroll
-    for (int t = 0; t < PREF; ++t) {
-      int e = tid + 256 * t;
-      if (e < mv * 16) {
-        As[e & 15][e >> 4] = pa[t];
-        Bs[e / mv][e % mv] = pb[t];
-      }
-    }
-  };
-  fetch(0);
-  for (int k0 = 0; k0 < 2 * mv; k0 += 16) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + 16 < 2 * mv) fetch(k0 + 16);
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      double a[5], b[5];
-#pragma unroll
-      for (int t = 0; t < 5; ++t) {
-        int rr = (R.r0 + t) * 16 + (l & 15), cc = (R.c0 + t) * 16 + (l & 15);
-        a[t] = (R.r0 + t < R.r1) ? As[ks * 4 + (l >> 4)][rr] : 0.0;
-        b[t] = (R.c0 + t < R.c1) ? Bs[ks * 4 + (l >> 4)][cc] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < 5; ++i)
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-          const int ti = R.r0 + i, tj = R.c0 + j;
-          if (ti < R.r1 && tj < R.c1 && (!R.mask || tj >= ti)) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
-        }
-    }
-  }
-  // epilogue
-  double* dstT = (box == B_S2) ? A.y + d.off[B_S2] + ((int64_t)sj * d.no + si) * d.nv * d.nv : nullptr;
-#pragma unroll
-  for (int i = 0; i < 5; ++i)
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const int ti = R.r0 + i, tj = R.c0 + j;
-      if (!(ti < R.r1 && tj < R.c1 && (!R.mask || tj >= ti))) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = ti * 16 + mfma_row(l, q), c = tj * 16 + (l & 15);
-        const double val = acc[i][j][q];
-        if (box == B_S2) {
-          if (r < d.nv && c < d.nv) {
-            if (kind == JK_S2PAIR) {
-              v.dst[r * d.nv + c] = val;
-              dstT[c * d.nv + r] = val;
-            } else if (ti == tj) {
-              v.dst[r * d.nv + c] = val;
-            } else {
-              v.dst[r * d.nv + c] = val;
-              v.dst[c * d.nv + r] = val;
-            }
-          }
-        } else {
-          yput(v, r, c, val);
-        }
-      }
-    }
-}
-
-}  // namespace esmp2
-
-namespace esmp2 {
-
-// ---------------------------------------------------------------------------
-// Tiled gather: one workgroup = one box x a tile of GT consecutive inner
-// (virtual-pair) indices x all occupied batches of that box, staged in LDS;
-// the occupied-index Fock action reads the tile, the remaining terms (box
-// transfers, doubles <-> L-triples, side contractions) are read from global.
-// y += result.
-// ---------------------------------------------------------------------------
-constexpr int GT = 32;
-
-__device__ inline int sgn_pair(int p, int q) { return p < q ? 1 : -1; }
-
-__global__ __launch_bounds__(256) void k_gather2(GatherArgs A, int4 tiles0, int4 tiles1) {
-  extern __shared__ double tile[];                  // nbat x (GT + 1)
-  const Dims& d = A.d;
-  const int no = d.no, nv = d.nv;
-  // box of this workgroup from the tile prefix sums
-  const int tstart[8] = {0, tiles0.x, tiles0.y, tiles0.z, tiles0.w, tiles1.x, tiles1.y, tiles1.z};
-  int box = 0;
-  while (box < 6 && (int)blockIdx.x >= tstart[box + 1]) ++box;
-  const int t0 = ((int)blockIdx.x - tstart[box]) * GT;
-  int nbat, inner;
-  switch (box) {
-    case B_T2: case B_H11: nbat = d.npo; inner = d.npv; break;
-    case B_S2: nbat = no * no; inner = nv * nv; break;
-    case B_T3: nbat = d.npo1; inner = d.npv1; break;
-    case B_H12: nbat = d.npo; inner = (nv - 1) * (nv - 1); break;
-    case B_H21: nbat = (no - 1) * (no - 1); inner = d.npv; break;
-    default: nbat = (no - 1) * (no - 1); inner = (nv - 1) * (nv - 1); break;
-  }
-  const double* src = (box == B_S2) ? A.S : A.x + d.off[box];
-  const int tw = min(GT, inner - t0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nbat * GT; e += blockDim.x) {
-    int o = e / GT, vl = e % GT;
-    tile[o * (GT + 1) + vl] = (vl < tw) ? src[(int64_t)o * inner + t0 + vl] : 0.0;
-  }
-  __syncthreads();
-  const int vl = tid % GT, grp = tid / GT, ngrp = blockDim.x / GT;
-  if (vl >= tw) return;
-  const int v = t0 + vl;
-  Look L{d, A.x, A.S};
-  const double* fo = A.fo;
-  const double* fv = A.fv;
-  const double* fov = A.fov;
-  auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
-  const double ftt = FOV(0, 0);
-  auto T = [&](int o) { return tile[o * (GT + 1) + vl]; };
-  double* y = A.y + d.off[box];
-  switch (box) {
-    case B_T2: {
-      int a, b;
-      tri_pq(v, nv, a, b);
-      for (int o = grp; o < nbat; o += ngrp) {
-        int i, j;
-        tri_pq(o, no, i, j);
-        double acc = 0.0;
-        for (int m = 0; m < no; ++m) {
-          if (m != j) acc -= fo[m * no + i] * sgn_pair(m, j) * T(tri_idx(min(m, j), max(m, j), no));
-          if (m != i) acc -= fo[m * no + j] * sgn_pair(i, m) * T(tri_idx(min(i, m), max(i, m), no));
-        }
-        if (i >= 1 && a >= 1) acc += ftt * L.T3(i, j, a, b);
-        acc += ftt * L.H11(i, j, a, b);
-        if (i == 0 && a >= 1)
-          for (int m = 1; m < no; ++m) acc -= FOV(m, 0) * L.T3(m, j, a, b);
-        if (i == 0)
-          for (int m = 1; m < no; ++m) acc += FOV(m, 0) * L.H21(m, j, a, b);
-        if (a == 0) {
-          if (i >= 1) acc -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
-          acc += A.h12_t[o * nv + b];
-          if (i == 0)
-            for (int m = 1; m < no; ++m) {
-              if (m < j) acc += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
-              else if (m > j) acc -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
-              acc += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
-            }
-        }
-        y[(int64_t)o * inner + v] += acc;
-      }
-      break;
-    }
-    case B_S2: {
-      const int a = v / nv, b = v % nv;
-      for (int o = grp; o < nbat; o += ngrp) {
-        const int i = o / no, j = o % no;
-        double acc = 0.0;
-        for (int m = 0; m < no; ++m) acc -= fo[m * no + i] * T(m * no + j) + fo[m * no + j] * T(i * no + m);
-        for (int rep = 0; rep < 2; ++rep) {
-          int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
-          double dd = 0.0;
-          if (p == 0 && xx == 0)
-            for (int m = 0; m < no; ++m) {
-              if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
-              else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
-            }
-          if (p == 0 && xx >= 1 && z >= 1)
-            for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
-          if (p == 0 && xx >= 1 && z == 0)
-            for (int m = 0; m < no; ++m) {
-              if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
-              else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
-            }
-          if (p >= 1 && q >= 1 && xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
-          if (p >= 1 && q == 0 && xx == 0)
-            for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
-          if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) dd += ftt * L.H22(p, q, xx, z);
-          if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
-            for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
-          if (p >= 1 && q >= 1 && xx >= 1 && z == 0) dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
-          if (p >= 1 && q == 0 && xx >= 1 && z == 0)
-            for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
-          acc += dd;
-        }
-        y[(int64_t)o * inner + v] += acc;
-      }
-      break;
-    }
-    case B_T3: {
-      int b, c;
-      tri_pq(v, nv - 1, b, c);
-      ++b; ++c;
-      for (int o = grp; o < nbat; o += ngrp) {
-        int j, k;
-        tri_pq(o, no - 1, j, k);
-        ++j; ++k;
-        double acc = 0.0;
-        for (int m = 1; m < no; ++m) {
-          if (m != k) acc -= fo[m * no + j] * sgn_pair(m, k) * T(tri_idx(min(m, k) - 1, max(m, k) - 1, no - 1));
-          if (m != j) acc -= fo[m * no + k] * sgn_pair(j, m) * T(tri_idx(min(j, m) - 1, max(j, m) - 1, no - 1));
-        }
-        acc += ftt * L.T2(j, k, b, c) - FOV(j, 0) * L.T2(0, k, b, c) + FOV(k, 0) * L.T2(0, j, b, c)
-             - FOV(0, b) * L.T2(j, k, 0, c) + FOV(j, b) * L.T2(0, k, 0, c) - FOV(k, b) * L.T2(0, j, 0, c)
-             + FOV(0, c) * L.T2(j, k, 0, b) - FOV(j, c) * L.T2(0, k, 0, b) + FOV(k, c) * L.T2(0, j, 0, b);
-        y[(int64_t)o * inner + v] += acc;
-      }
-      break;
-    }
-    case B_H11: {
-      int b, c;
-      tri_pq(v, nv, b, c);
-      for (int o = grp; o < nbat; o += ngrp) {
-        int j, k;
-        tri_pq(o, no, j, k);
-        double acc = 0.0;
-        for (int m = 0; m < no; ++m) {
-          if (m != k) acc -= fo[m * no + j] * sgn_pair(m, k) * T(tri_idx(min(m, k), max(m, k), no));
-          if (m != j) acc -= fo[m * no + k] * sgn_pair(j, m) * T(tri_idx(min(j, m), max(j, m), no));
-        }
-        if (b == 0) acc += A.side_tr[(int64_t)o * nv + c];
-        if (j == 0)
-          for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H21(m, k, b, c);
-        acc += ftt * L.T2(j, k, b, c);
-        acc += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
-             - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
-        y[(int64_t)o * inner + v] += acc;
-      }
-      break;
-    }
-    case B_H12: {
-      const int m1 = nv - 1;
-      const int a = v / m1 + 1, c = v % m1 + 1;
-      for (int o = grp; o < nbat; o += ngrp) {
-        int j, k;
-        tri_pq(o, no, j, k);
-        double acc = 0.0;
-        for (int m = 0; m < no; ++m) {
-          if (m != k) acc -= fo[m * no + j] * sgn_pair(m, k) * T(tri_idx(min(m, k), max(m, k), no));
-          if (m != j) acc -= fo[m * no + k] * sgn_pair(j, m) * T(tri_idx(min(j, m), max(j, m), no));
-        }
-        acc += fv[a * nv + 0] * L.H11(j, k, 0, c);
-        if (j == 0)
-          for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H22(m, k, a, c);
-        acc += FOV(0, a) * L.T2(j, k, 0, c);
-        acc += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
-             - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
-        y[(int64_t)o * inner + v] += acc;
-      }
-      break;
-    }
-    case B_H21: {
-      int b, c;
-      tri_pq(v, nv, b, c);
-      for (int o = grp; o < nbat; o += ngrp) {
-        const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-        double acc = 0.0;
-        for (int m = 1; m < no; ++m)
-          acc -= fo[m * no + i] * T((m - 1) * (no - 1) + (k - 1)) + fo[m * no + k] * T((i - 1) * (no - 1) + (m - 1));
-        acc -= fo[0 * no + i] * L.H11(0, k, b, c);
-        if (b == 0) acc += A.side_tr[((int64_t)d.npo + o) * nv + c];
-        acc += FOV(i, 0) * L.T2(0, k, b, c);
-        acc += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
-             - FOV(0, c) * L.St(i, k, 0, b) + FOV(k, c) * L.St(i, 0, 0, b);
-        y[(int64_t)o * inner + v] += acc;
-      }
-      break;
-    }
-    default: {
-      const int m1 = nv - 1;
-      const int a = v / m1 + 1, c = v % m1 + 1;
-      for (int o = grp; o < nbat; o += ngrp) {
-        const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-        double acc = 0.0;
-        for (int m = 1; m < no; ++m)
-          acc -= fo[m * no + i] * T((m - 1) * (no - 1) + (k - 1)) + fo[m * no + k] * T((i - 1) * (no - 1) + (m - 1));
-        acc -= fo[0 * no + i] * L.H12(0, k, a, c);
-        acc += fv[a * nv + 0] * L.H21(i, k, 0, c);
-        acc += FOV(i, a) * L.T2(0, k, 0, c);
-        acc += ftt * L.St(i, k, a, c) - FOV(k, 0) * L.St(i, 0, a, c)
-             - FOV(0, c) * L.St(i, k, a, 0) + FOV(k, c) * L.St(i, 0, a, 0);
-        y[(int64_t)o * inner + v] += acc;
-      }
-      break;
-    }
-  }
-}
-
-}  // namespace esmp2
-
-namespace esmp2 {
-
-// ---------------------------------------------------------------------------
-// Gather with the occupied-index Fock action on matrix cores.  Per workgroup:
-// one box, GT consecutive inner (virtual-pair) indices v, all occupied batches.
-//  1. stage x (S~ for S2) for the tile in LDS;
-//  2. per element: box transfers, doubles <-> L-triples and side terms into an
-//     LDS output tile;
-//  3. per v: Y_v = -(F_o X_v + X_v F_o) on a 16x16 tile (X_v = the occupied
-//     matrix of the box at v, antisymmetric for pair boxes), added to the tile;
-//  4. coalesced y += tile.
-// Requires the occupied dimension of every box <= 16.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gather3(GatherArgs A, int4 tiles0, int4 tiles1) {
-  extern __shared__ double sm[];
-  const Dims& d = A.d;
-  const int no = d.no, nv = d.nv;
-  const int tstart[8] = {0, tiles0.x, tiles0.y, tiles0.z, tiles0.w, tiles1.x, tiles1.y, tiles1.z};
-  int box = 0;
-  while (box < 6 && (int)blockIdx.x >= tstart[box + 1]) ++box;
-  const int t0 = ((int)blockIdx.x - tstart[box]) * GT;
-  int nbat, inner, n, sh;      // n: occupied matrix dimension, sh: index shift (1 when t is excluded)
-  bool anti;
-  switch (box) {
-    case B_T2: case B_H11: nbat = d.npo; inner = d.npv; n = no; sh = 0; anti = true; break;
-    case B_S2: nbat = no * no; inner = nv * nv; n = no; sh = 0; anti = false; break;
-    case B_T3: nbat = d.npo1; inner = d.npv1; n = no - 1; sh = 1; anti = true; break;
-    case B_H12: nbat = d.npo; inner = (nv - 1) * (nv - 1); n = no; sh = 0; anti = true; break;
-    case B_H21: nbat = (no - 1) * (no - 1); inner = d.npv; n = no - 1; sh = 1; anti = false; break;
-    default: nbat = (no - 1) * (no - 1); inner = (nv - 1) * (nv - 1); n = no - 1; sh = 1; anti = false; break;
-  }
-  double* tin = sm;                                 // nbat x (GT+1)
-  double* tout = tin + nbat * (GT + 1);             // nbat x (GT+1)
-  int* xi = (int*)(tout + nbat * (GT + 1));         // 16 x 16: signed (batch+1), 0 = zero entry
-  const double* src = (box == B_S2) ? A.S : A.x + d.off[box];
-  const int tw = min(GT, inner - t0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nbat * GT; e += blockDim.x) {
-    int o = e / GT, vl = e % GT;
-    tin[o * (GT + 1) + vl] = (vl < tw) ? src[(int64_t)o * inner + t0 + vl] : 0.0;
-  }
-  if (tid < 256) {
-    int p = tid >> 4, q = tid & 15, code = 0;
-    if (p < n && q < n) {
-      if (!anti) code = p * n + q + 1;
-      else if (p < q) code = tri_idx(p, q, n) + 1;
-      else if (p > q) code = -(tri_idx(q, p, n) + 1);
-    }
-    xi[tid] = code;
-  }
-  __syncthreads();
-  // ---- 2. per-element terms ----------------------------------------------
-  Look L{d, A.x, A.S};
-  const double* fv = A.fv;
-  const double* fov = A.fov;
-  const double* fo = A.fo;
-  auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
-  const double ftt = FOV(0, 0);
-  for (int e = tid; e < nbat * GT; e += blockDim.x) {
-    const int o = e / GT, vl = e % GT;
-    double acc = 0.0;
-    if (vl < tw) {
-      const int v = t0 + vl;
-      switch (box) {
-        case B_T2: {
-          int a, b, i, j;
-          tri_pq(v, nv, a, b);
-          tri_pq(o, no, i, j);
-          if (i >= 1 && a >= 1) acc += ftt * L.T3(i, j, a, b);
-          acc += ftt * L.H11(i, j, a, b);
-          if (i == 0 && a >= 1)
-            for (int m = 1; m < no; ++m) acc -= FOV(m, 0) * L.T3(m, j, a, b);
-          if (i == 0)
-            for (int m = 1; m < no; ++m) acc += FOV(m, 0) * L.H21(m, j, a, b);
-          if (a == 0) {
-            if (i >= 1) acc -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
-            acc += A.h12_t[o * nv + b];
-            if (i == 0)
-              for (int m = 1; m < no; ++m) {
-                if (m < j) acc += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
-                else if (m > j) acc -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
-                acc += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
-              }
-          }
-          break;
-        }
-        case B_S2: {
-          const int a = v / nv, b = v % nv, i = o / no, j = o % no;
-          for (int rep = 0; rep < 2; ++rep) {
-            int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
-            double dd = 0.0;
-            if (p == 0 && xx == 0)
-              for (int m = 0; m < no; ++m) {
-                if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
-                else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
-              }
-            if (p == 0 && xx >= 1 && z >= 1)
-              for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
-            if (p == 0 && xx >= 1 && z == 0)
-              for (int m = 0; m < no; ++m) {
-                if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
-                else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
-              }
-            if (p >= 1 && q >= 1 && xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
-            if (p >= 1 && q == 0 && xx == 0)
-              for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
-            if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) dd += ftt * L.H22(p, q, xx, z);
-            if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
-              for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
-            if (p >= 1 && q >= 1 && xx >= 1 && z == 0) dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
-            if (p >= 1 && q == 0 && xx >= 1 && z == 0)
-              for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
-            acc += dd;
-          }
-          break;
-        }
-        case B_T3: {
-          int b, c, j, k;
-          tri_pq(v, nv - 1, b, c);
-          tri_pq(o, no - 1, j, k);
-          ++b; ++c; ++j; ++k;
-          acc += ftt * L.T2(j, k, b, c) - FOV(j, 0) * L.T2(0, k, b, c) + FOV(k, 0) * L.T2(0, j, b, c)
-               - FOV(0, b) * L.T2(j, k, 0, c) + FOV(j, b) * L.T2(0, k, 0, c) - FOV(k, b) * L.T2(0, j, 0, c)
-               + FOV(0, c) * L.T2(j, k, 0, b) - FOV(j, c) * L.T2(0, k, 0, b) + FOV(k, c) * L.T2(0, j, 0, b);
-          break;
-        }
-        case B_H11: {
-          int b, c, j, k;
-          tri_pq(v, nv, b, c);
-          tri_pq(o, no, j, k);
-          if (b == 0) acc += A.side_tr[(int64_t)o * nv + c];
-          if (j == 0)
-            for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H21(m, k, b, c);
-          acc += ftt * L.T2(j, k, b, c);
-          acc += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
-               - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
-          break;
-        }
-        case B_H12: {
-          const int m1 = nv - 1, a = v / m1 + 1, c = v % m1 + 1;
-          int j, k;
-          tri_pq(o, no, j, k);
-          acc += fv[a * nv + 0] * L.H11(j, k, 0, c);
-          if (j == 0)
-            for (int m = 1; m < no; ++m) acc -= fo[m * no + 0] * L.H22(m, k, a, c);
-          acc += FOV(0, a) * L.T2(j, k, 0, c);
-          acc += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
-               - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
-          break;
-        }
-        case B_H21: {
-          int b, c;
-          tri_pq(v, nv, b, c);
-          const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-          acc -= fo[0 * no + i] * L.H11(0, k, b, c);
-          if (b == 0) acc += A.side_tr[((int64_t)d.npo + o) * nv + c];
-          acc += FOV(i, 0) * L.T2(0, k, b, c);
-          acc += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
-               - FOV(0, c) * L.St(i, k, 0, b) + FOV(k, c) * L.St(i, 0, 0, b);
-          break;
-        }
-        default: {
-          const int m1 = nv - 1, a = v / m1 + 1, c = v % m1 + 1;
-          const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-          acc -= fo[0 * no + i] * L.H12(0, k, a, c);
-          acc += fv[a * nv + 0] * L.H21(i, k, 0, c);
-          acc += FOV(i, a) * L.T2(0, k, 0, c);
-          acc += ftt * L.St(i, k, a, c) - FOV(k, 0) * L.St(i, 0, a, c)
-               - FOV(0, c) * L.St(i, k, a, 0) + FOV(k, c) * L.St(i, 0, a, 0);
-          break;
-        }
-      }
-    }
-    tout[o * (GT + 1) + vl] = acc;
-  }
-  __syncthreads();
-  // ---- 3. occupied Sylvester on matrix cores: Y_v = -(F X_v + X_v F) -----
-  {
-    const int wave = tid >> 6, l = tid & 63;
-    const int r16 = l & 15, k4 = l >> 4;
-    // F_o restricted to the box's occupied range (padded to 16), symmetric
-    auto Fs = [&](int p, int q) -> double {
-      return (p < n && q < n) ? fo[(p + sh) * no + (q + sh)] : 0.0;
-    };
-    double fa[4], fb[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      fa[s] = Fs(r16, 4 * s + k4);        // A operand (row r16, k)
-      fb[s] = Fs(4 * s + k4, r16);        // B operand (k, col r16)
-    }
-    for (int vl = wave; vl < tw; vl += 4) {
-      auto X = [&](int p, int q) -> double {
-        int code = xi[p * 16 + q];
-        if (code == 0) return 0.0;
-        double val = tin[((code > 0 ? code : -code) - 1) * (GT + 1) + vl];
-        return code > 0 ? val : -val;
-      };
-      f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        acc = mfma16x16x4(fa[s], X(4 * s + k4, r16), acc);       // F X
-        acc = mfma16x16x4(X(r16, 4 * s + k4), fb[s], acc);       // X F
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = mfma_row(l, q), c = r16;
-        if (r < n && c < n && (!anti || r < c)) {
-          int bidx = anti ? tri_idx(r, c, n) : r * n + c;
-          tout[bidx * (GT + 1) + vl] -= acc[q];
-        }
-      }
-    }
-  }
-  __syncthreads();
-  // ---- 4. write back ------------------------------------------------------
-  double* y = A.y + d.off[box];
-  for (int e = tid; e < nbat * GT; e += blockDim.x) {
-    const int o = e / GT, vl = e % GT;
-    if (vl < tw) y[(int64_t)o * inner + t0 + vl] += tout[o * (GT + 1) + vl];
-  }
-}
-
-}  // namespace esmp2
-
-namespace esmp2 {
-
-// ---------------------------------------------------------------------------
 // Occupied-index Fock action on matrix cores, y += -(F_o X_v + X_v F_o) for
 // every inner index v of every box (F_o restricted to the box's occupied
 // range), plus the two box-transfer rows that the Sylvester kernel produces
 // (H1P2 -> H1P1 and H2P2 -> H2P1 through f_{t' E}).  One workgroup: one box,
 // GO consecutive inner indices, all occupied batches staged in LDS.
 // ---------------------------------------------------------------------------
-constexpr int GO = 8;
 
-__global__ __launch_bounds__(256) void k_oo(GatherArgs A, int4 tiles0, int4 tiles1) {
-  extern __shared__ double sm[];
+template <class T>
+__global__ __launch_bounds__(256) void k_oo(GatherArgs<T> A, int4 tiles0, int4 tiles1) {
+  extern __shared__ __align__(16) unsigned char sm_raw[];
+  T* sm = reinterpret_cast<T*>(sm_raw);
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv;
   const int tstart[8] = {0, tiles0.x, tiles0.y, tiles0.z, tiles0.w, tiles1.x, tiles1.y, tiles1.z};
@@ -1219,17 +492,17 @@ __global__ __launch_bounds__(256) void k_oo(GatherArgs A, int4 tiles0, int4 tile
     case B_H21: nbat = (no - 1) * (no - 1); inner = d.npv; n = no - 1; sh = 1; anti = false; break;
     default: nbat = (no - 1) * (no - 1); inner = (nv - 1) * (nv - 1); n = no - 1; sh = 1; anti = false; break;
   }
-  double* tin = sm;                                 // nbat x (GO+1)
-  double* tout = tin + nbat * (GO + 1);             // nbat x (GO+1)
+  T* tin = sm;                                      // nbat x (GO+1)
+  T* tout = tin + nbat * (GO + 1);                  // nbat x (GO+1)
   int* xi = (int*)(tout + nbat * (GO + 1));         // 16 x 16
-  const double* src = (box == B_S2) ? A.S : A.x + d.off[box];
+  const T* src = (box == B_S2) ? A.S : A.x + d.off[box];
   const int tw = min(GO, inner - t0);
   const int tid = threadIdx.x;
   for (int e = tid; e < nbat * GO; e += blockDim.x) {
     const int o = e / GO, vl = e % GO;
     const bool ok = vl < tw;
-    tin[o * (GO + 1) + vl] = ok ? src[(int64_t)o * inner + t0 + vl] : 0.0;
-    double t = 0.0;
+    tin[o * (GO + 1) + vl] = ok ? src[(int64_t)o * inner + t0 + vl] : T(0);
+    T t = 0;
     // box-transfer rows (inner pairs (t', c) are the first nv-1 packed pairs)
     if (ok && (box == B_H11 || box == B_H21) && t0 + vl < nv - 1) {
       const int c = t0 + vl + 1;
@@ -1249,22 +522,22 @@ __global__ __launch_bounds__(256) void k_oo(GatherArgs A, int4 tiles0, int4 tile
   __syncthreads();
   const int wave = tid >> 6, l = tid & 63;
   const int r16 = l & 15, k4 = l >> 4;
-  const double* fo = A.fo;
-  auto Fs = [&](int p, int q) -> double { return (p < n && q < n) ? fo[(p + sh) * no + (q + sh)] : 0.0; };
-  double fa[4], fb[4];
+  const T* fo = A.fo;
+  auto Fs = [&](int p, int q) -> T { return (p < n && q < n) ? fo[(p + sh) * no + (q + sh)] : T(0); };
+  T fa[4], fb[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     fa[s] = Fs(r16, 4 * s + k4);
     fb[s] = Fs(4 * s + k4, r16);
   }
   for (int vl = wave; vl < tw; vl += 4) {
-    auto X = [&](int p, int q) -> double {
+    auto X = [&](int p, int q) -> T {
       int code = xi[p * 16 + q];
-      if (code == 0) return 0.0;
-      double val = tin[((code > 0 ? code : -code) - 1) * (GO + 1) + vl];
+      if (code == 0) return T(0);
+      T val = tin[((code > 0 ? code : -code) - 1) * (GO + 1) + vl];
       return code > 0 ? val : -val;
     };
-    f64x4 acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+    typename MfmaAcc<T>::type acc = {0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       acc = mfma16x16x4(fa[s], X(4 * s + k4, r16), acc);
@@ -1272,7 +545,7 @@ __global__ __launch_bounds__(256) void k_oo(GatherArgs A, int4 tiles0, int4 tile
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int r = mfma_row(l, q), c = r16;
+      const int r = mfma_row_t<T>(l, q), c = r16;
       if (r < n && c < n && (!anti || r < c)) {
         const int bidx = anti ? tri_idx(r, c, n) : r * n + c;
         tout[bidx * (GO + 1) + vl] -= acc[q];
@@ -1280,11 +553,99 @@ __global__ __launch_bounds__(256) void k_oo(GatherArgs A, int4 tiles0, int4 tile
     }
   }
   __syncthreads();
-  double* y = A.y + d.off[box];
+  T* y = A.y + d.off[box];
   for (int e = tid; e < nbat * GO; e += blockDim.x) {
     const int o = e / GO, vl = e % GO;
     if (vl < tw) y[(int64_t)o * inner + t0 + vl] += tout[o * (GO + 1) + vl];
   }
 }
+
+
+// Occupied-index Fock action and the two transfer rows, one thread per
+// amplitude: the fallback of k_oo when an occupied range exceeds one 16 x 16
+// matrix-core tile or the staged batches exceed the LDS.
+template <class T>
+__global__ __launch_bounds__(256) void k_oo_plain(GatherArgs<T> A) {
+  const Dims& d = A.d;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.off[7]) return;
+  const int no = d.no, nv = d.nv;
+  Look<T> L{d, A.x, A.S};
+  const T* fo = A.fo;
+  int64_t loc;
+  const int box = box_of_g(d, g, loc);
+  T y = 0;
+  switch (box) {
+    case B_T2: {
+      int i, j, a, b;
+      tri_pq(loc / d.npv, no, i, j); tri_pq(loc % d.npv, nv, a, b);
+      for (int m = 0; m < no; ++m) y -= fo[m * no + i] * L.T2(m, j, a, b) + fo[m * no + j] * L.T2(i, m, a, b);
+      break;
+    }
+    case B_S2: {
+      int64_t r = loc;
+      int b = r % nv; r /= nv;
+      int a = r % nv; r /= nv;
+      int j = r % no, i = r / no;
+      for (int m = 0; m < no; ++m) y -= fo[m * no + i] * L.St(m, j, a, b) + fo[m * no + j] * L.St(i, m, a, b);
+      break;
+    }
+    case B_T3: {
+      int j, k, b, c;
+      tri_pq(loc / d.npv1, no - 1, j, k); tri_pq(loc % d.npv1, nv - 1, b, c);
+      ++j; ++k; ++b; ++c;
+      for (int m = 1; m < no; ++m) y -= fo[m * no + j] * L.T3(m, k, b, c) + fo[m * no + k] * L.T3(j, m, b, c);
+      break;
+    }
+    case B_H11: {
+      int j, k, b, c;
+      tri_pq(loc / d.npv, no, j, k); tri_pq(loc % d.npv, nv, b, c);
+      for (int m = 0; m < no; ++m) y -= fo[m * no + j] * L.H11(m, k, b, c) + fo[m * no + k] * L.H11(j, m, b, c);
+      if (b == 0) y += A.side_tr[(int64_t)tri_idx(j, k, no) * nv + c];
+      break;
+    }
+    case B_H12: {
+      const int m1 = nv - 1;
+      int j, k;
+      tri_pq(loc / (m1 * m1), no, j, k);
+      const int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
+      for (int m = 0; m < no; ++m) y -= fo[m * no + j] * L.H12(m, k, a, c) + fo[m * no + k] * L.H12(j, m, a, c);
+      break;
+    }
+    case B_H21: {
+      const int o = loc / d.npv;
+      const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+      int b, c;
+      tri_pq(loc % d.npv, nv, b, c);
+      for (int m = 1; m < no; ++m) y -= fo[m * no + i] * L.H21(m, k, b, c) + fo[m * no + k] * L.H21(i, m, b, c);
+      if (b == 0) y += A.side_tr[((int64_t)d.npo + o) * nv + c];
+      break;
+    }
+    default: {
+      const int m1 = nv - 1;
+      const int o = loc / (m1 * m1);
+      const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
+      const int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
+      for (int m = 1; m < no; ++m) y -= fo[m * no + i] * L.H22(m, k, a, c) + fo[m * no + k] * L.H22(i, m, a, c);
+      break;
+    }
+  }
+  A.y[g] += y;
+}
+
+#define ESMP2_SIGMA_INSTANCES(T)                                                        \
+  template __global__ void k_sym_s2<T>(Dims, const T*, T*);                             \
+  template __global__ void k_vv<T, 1>(VVArgs<T>);                                       \
+  template __global__ void k_vv<T, 2>(VVArgs<T>);                                       \
+  template __global__ void k_vv<T, 3>(VVArgs<T>);                                       \
+  template __global__ void k_vv<T, 4>(VVArgs<T>);                                       \
+  template __global__ void k_vv<T, 5>(VVArgs<T>);                                       \
+  template __global__ void k_side<T>(SideArgs<T>);                                      \
+  template __global__ void k_couple<T>(GatherArgs<T>, PairTables);                      \
+  template __global__ void k_oo<T>(GatherArgs<T>, int4, int4);                          \
+  template __global__ void k_oo_plain<T>(GatherArgs<T>);
+ESMP2_SIGMA_INSTANCES(double)
+ESMP2_SIGMA_INSTANCES(float)
+#undef ESMP2_SIGMA_INSTANCES
 
 }  // namespace esmp2
