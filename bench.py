@@ -4,14 +4,16 @@
 A step is one pass of the whole hot path on the timed workload (n_occ=16,
 n_vir=160, n_aux=480, seed 2; synthetic ESMF-shaped inputs resident in HBM):
 rotation to the TOP basis, right-hand side + S-triple energy, FP64 Jacobi
-PCG to ||b+Ax||_W/||b||_W <= 1e-8, and E2.
+PCG to ||b+Ax||_W/||b||_W <= 1e-8, and E2.  The same steps are then timed
+with the mixed-precision solve (FP32 inner CG inside FP64 refinement, same
+FP64 stopping test) and reported beside it with its E2 difference.
 
-value = effective H0-sigma throughput of the whole job: algorithmic sigma
-flops x sigma applications in the timed steps / wall time (GFLOP/s); the
-time-to-E2 is ms_per_step.  The roofline object covers the dominant kernel
-(the virtual-pair Sylvester kernel on the FP64 matrix cores), timed with HIP
-events on the library's stream.  cpu_baseline times the CPU oracle (one
-sigma application and the right-hand side at the same workload).
+value = effective H0-sigma throughput of the whole FP64 job: algorithmic
+sigma flops x sigma applications in the timed steps / wall time (GFLOP/s);
+the FP64 time-to-E2 is ms_per_step.  The roofline object covers the dominant
+kernel (the virtual-pair Sylvester kernel on the FP64 matrix cores), timed
+with HIP events on the library's stream.  cpu_baseline times the CPU oracle
+(one FP64 sigma application at the same workload).
 """
 import argparse
 import json
@@ -23,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
+PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -34,6 +37,9 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counter-run", type=int, default=0, metavar="N",
+                    help="for hardware-counter passes: a 256 MiB device copy (the calibration "
+                         "kernel of known size), then N FP64 and N FP32 sigma applications; no timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -46,6 +52,10 @@ def main():
     import paper_2003_12923_amd as P
     from paper_2003_12923_amd import costs
 
+    if args.counter_run:
+        counter_run(args)
+        return
+
     prob = synth.config_problem(args.workload)
     no, nv = prob.n_occ, prob.n_vir
     vv_flops, oo_flops = costs.sigma_flops(no, nv)
@@ -54,10 +64,10 @@ def main():
     h = P.Handle(0).load(prob)
     torch.cuda.synchronize()
 
-    def step():
+    def step(precision=P.ESMP2_FP64):
         h.rotate_top(lam_out=False)
         h.build_rhs()
-        return h.solve(tol=args.tol, max_iter=300)
+        return h.solve(tol=args.tol, max_iter=300, precision=precision)
 
     for _ in range(args.warmup):
         step()
@@ -76,20 +86,37 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     value = n_sigma * sig_flops / wall / 1e9
 
-    # sigma alone (all its kernels), FP64
+    # the same steps with the mixed-precision solve
+    for _ in range(args.warmup):
+        step(P.ESMP2_FP32)
+    torch.cuda.synchronize()
+    h.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res_m = step(P.ESMP2_FP32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vv32_ms, vv32_n = h.profile(False)[P.ESMP2_FP32]
+    mixed_ms = 1e3 * (t1 - t0) / args.steps
+
+    # sigma alone (all its kernels), FP64 and FP32; events on the library's stream
     n_amp, _ = h.space()
     x = torch.from_numpy(synth.random_amplitudes(n_amp, 5)).cuda()
-    y = torch.empty_like(x)
-    for _ in range(3):
-        h.sigma(x, y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
-    e0.record()
-    for _ in range(reps):
-        h.sigma(x, y)
-    e1.record()
-    torch.cuda.synchronize()
-    sigma_ms = e0.elapsed_time(e1) / reps
+
+    def time_sigma(xv, precision, reps=20):
+        y = torch.empty_like(xv)
+        for _ in range(3):
+            h.sigma(xv, y, precision)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            h.sigma(xv, y, precision)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    sigma_ms = time_sigma(x, P.ESMP2_FP64)
+    sigma32_ms = time_sigma(x.float(), P.ESMP2_FP32)
 
     vv_avg_ms = vv_ms / max(vv_n, 1)
     achieved = vv_flops / (vv_avg_ms * 1e-3) / 1e12
@@ -125,7 +152,16 @@ def main():
         "fp64": {"e2": res["e2"], "iterations": res["iterations"], "rel_resid": res["rel_resid"],
                  "e2_minus_oracle": None if gold is None else res["e2"] - gold["e2"],
                  "sigma_ms": round(sigma_ms, 4), "sigma_gflops": round(sig_flops / sigma_ms / 1e6, 2)},
-        "roofline": {"bound": "mfma", "kernel": "k_vv (virtual-pair Sylvester, FP64 MFMA)",
+        "mixed": {"time_to_e2_ms": round(mixed_ms, 4), "speedup_vs_fp64": round(ms_per_step / mixed_ms, 3),
+                  "e2": res_m["e2"], "e2_minus_fp64": res_m["e2"] - res["e2"],
+                  "e2_minus_oracle": None if gold is None else res_m["e2"] - gold["e2"],
+                  "inner_fp32_iterations": res_m["iterations"], "outer_fp64_steps": res_m["outer"],
+                  "rel_resid": res_m["rel_resid"], "sigma_fp32_ms": round(sigma32_ms, 4),
+                  "sigma_fp32_gflops": round(sig_flops / sigma32_ms / 1e6, 2),
+                  "sylvester_fp32": {"avg_launch_ms": round(vv32_ms / max(vv32_n, 1), 4), "launches": vv32_n,
+                                     "achieved_tflops": round(vv_flops / (vv32_ms / max(vv32_n, 1) * 1e-3) / 1e12, 3),
+                                     "peak_tflops": PEAK_FP32_TFLOPS}},
+        "roofline": {"bound": "mfma", "kernel": "k_vv3 (virtual-pair Sylvester, FP64 MFMA)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                      "alg_flops_per_launch": vv_flops, "avg_launch_ms": round(vv_avg_ms, 4),
@@ -136,6 +172,33 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, sig_flops)
     print(json.dumps(out), flush=True)
+
+
+def counter_run(args):
+    """Kernels for the FETCH_SIZE / WRITE_SIZE passes: one copy of 2^25 doubles
+    (256 MiB read + 256 MiB written), then sigma applications of the workload."""
+    import torch
+    import synth
+    import paper_2003_12923_amd as P
+    src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copy done", flush=True)
+    prob = synth.config_problem(args.workload)
+    h = P.Handle(0).load(prob)
+    h.rotate_top(lam_out=False)
+    n_amp, _ = h.space()
+    x = torch.from_numpy(synth.random_amplitudes(n_amp, 5)).cuda()
+    y = torch.empty_like(x)
+    for _ in range(args.counter_run):
+        h.sigma(x, y)
+    x32, y32 = x.float(), torch.empty(n_amp, dtype=torch.float32, device="cuda")
+    for _ in range(args.counter_run):
+        h.sigma(x32, y32, P.ESMP2_FP32)
+    torch.cuda.synchronize()
+    h.close()
+    print("sigma done", flush=True)
 
 
 def cpu_baseline(prob, sig_flops):

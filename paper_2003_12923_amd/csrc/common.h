@@ -41,6 +41,21 @@ inline Dims make_dims(int no, int nv, int naux) {
   return d;
 }
 
+// XCD-aware workgroup order.  The workgroups of one launch are dealt to the
+// 8 XCDs round-robin (b -> XCD b % 8) and each XCD has its own L2.  Renumber
+// them so that each XCD walks runs of C consecutive logical blocks (data
+// shared by neighbouring blocks is fetched into one L2 once) while the runs
+// still rotate over the XCDs (work of uneven cost stays balanced).  A
+// bijection of [0, nblocks); the tail that does not fill 8 C blocks keeps
+// its order.
+template <unsigned C>
+__device__ inline unsigned xcd_remap(unsigned b, unsigned nblocks) {
+  const unsigned full = nblocks / (8u * C) * (8u * C);
+  if (b >= full) return b;
+  const unsigned x = b & 7u, r = b >> 3;
+  return ((r / C) * 8u + x) * C + (r % C);
+}
+
 // Packed strict-upper-triangle index of (p,q), p<q, in an m x m matrix.
 __host__ __device__ inline int tri_idx(int p, int q, int m) {
   return p * m - p * (p + 1) / 2 + (q - p - 1);

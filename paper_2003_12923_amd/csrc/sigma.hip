@@ -72,15 +72,14 @@ struct Look {
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void k_sym_s2(Dims d, const T* x, T* S) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t n = (int64_t)d.no * d.no * d.nv * d.nv;
-  if (g >= n) return;
-  int64_t r = g;
-  int b = r % d.nv; r /= d.nv;
-  int a = r % d.nv; r /= d.nv;
-  int j = r % d.no; int i = r / d.no;
+  const int g = (int)xcd_remap<16>(blockIdx.x, gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
+  const int nv2 = d.nv * d.nv;
+  if (g >= d.no * d.no * nv2) return;     // the S2 box holds < 2^31 amplitudes
+  const int o = g / nv2, v = g - o * nv2;
+  const int i = o / d.no, j = o - i * d.no;
+  const int a = v / d.nv, b = v - a * d.nv;
   const T* s2 = x + d.off[B_S2];
-  S[g] = T(0.5) * (s2[g] + s2[(((int64_t)j * d.no + i) * d.nv + b) * d.nv + a]);
+  S[g] = T(0.5) * (s2[g] + s2[(j * d.no + i) * nv2 + b * d.nv + a]);
 }
 
 // ---------------------------------------------------------------------------
@@ -319,10 +318,11 @@ __global__ __launch_bounds__(256) void k_side(SideArgs<T> A) {
 // y += ... (the virtual-pair part is already in y, k_oo adds the occupied
 // pair part).  One thread per amplitude; pair indices decoded from tables.
 // ---------------------------------------------------------------------------
-__device__ inline int box_of_g(const Dims& d, int64_t g, int64_t& loc) {
+// box of amplitude g and its index within the box (a box holds < 2^31 amplitudes)
+__device__ inline int box_of_g(const Dims& d, int64_t g, int& loc) {
   int k = 0;
   while (k < 6 && g >= d.off[k + 1]) ++k;
-  loc = g - d.off[k];
+  loc = (int)(g - d.off[k]);
   return k;
 }
 
@@ -330,7 +330,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
   const int *pv = P.pv, *pv1 = P.pv1, *po = P.po, *po1 = P.po1;
   const Dims& d = A.d;
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t g = (int64_t)xcd_remap<16>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= d.off[7]) return;
   const int no = d.no, nv = d.nv;
   Look<T> L{d, A.x, A.S};
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
   const T* fov = A.fov;   // fov[i*nv + a]
   auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
   const T ftt = FOV(0, 0);
-  int64_t loc;
+  int loc;
   const int box = box_of_g(d, g, loc);
   T y = 0;
   switch (box) {
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
       break;
     }
     case B_S2: {
-      int64_t r = loc;
+      int r = loc;
       int b = r % nv; r /= nv;
       int a = r % nv; r /= nv;
       int j = r % no, i = r / no;
@@ -479,9 +479,10 @@ __global__ __launch_bounds__(256) void k_oo(GatherArgs<T> A, int4 tiles0, int4 t
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv;
   const int tstart[8] = {0, tiles0.x, tiles0.y, tiles0.z, tiles0.w, tiles1.x, tiles1.y, tiles1.z};
+  const int blk = (int)xcd_remap<16>(blockIdx.x, gridDim.x);
   int box = 0;
-  while (box < 6 && (int)blockIdx.x >= tstart[box + 1]) ++box;
-  const int t0 = ((int)blockIdx.x - tstart[box]) * GO;
+  while (box < 6 && blk >= tstart[box + 1]) ++box;
+  const int t0 = (blk - tstart[box]) * GO;
   int nbat, inner, n, sh;
   bool anti;
   switch (box) {
@@ -567,12 +568,12 @@ __global__ __launch_bounds__(256) void k_oo(GatherArgs<T> A, int4 tiles0, int4 t
 template <class T>
 __global__ __launch_bounds__(256) void k_oo_plain(GatherArgs<T> A) {
   const Dims& d = A.d;
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t g = (int64_t)xcd_remap<16>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= d.off[7]) return;
   const int no = d.no, nv = d.nv;
   Look<T> L{d, A.x, A.S};
   const T* fo = A.fo;
-  int64_t loc;
+  int loc;
   const int box = box_of_g(d, g, loc);
   T y = 0;
   switch (box) {
@@ -583,7 +584,7 @@ __global__ __launch_bounds__(256) void k_oo_plain(GatherArgs<T> A) {
       break;
     }
     case B_S2: {
-      int64_t r = loc;
+      int r = loc;
       int b = r % nv; r /= nv;
       int a = r % nv; r /= nv;
       int j = r % no, i = r / no;
