@@ -117,7 +117,11 @@ def _anti_occ(x):
 class Structured:
     """sigma = (H0 - E0) x on doubles + L-triples, in the seven-box layout."""
 
-    def __init__(self, f, lam, n_occ):
+    def __init__(self, f, lam, n_occ, omega=None):
+        """f: Fock matrix in the TOP basis, or in any basis that differs from
+        it by a rotation of the occupied orbitals other than t and of the
+        virtuals other than t'; then omega (computed in the TOP basis) must be
+        given, since it reads the TOP orbitals' diagonal Fock elements."""
         f = np.asarray(f, dtype=np.float64)
         self.no = no = n_occ
         self.nv = nv = f.shape[0] - n_occ
@@ -125,7 +129,9 @@ class Structured:
         self.fo = f[:no, :no]
         self.fv = f[no:, no:]
         self.fov = f[:no, no:]          # fov[i, a] = f_{i a} = f_{a i}
-        self.omega = float(np.sum(self.lam ** 2 * (np.diag(self.fv)[:no] - np.diag(self.fo))))
+        if omega is None:
+            omega = np.sum(self.lam ** 2 * (np.diag(self.fv)[:no] - np.diag(self.fo)))
+        self.omega = float(omega)
         self.E0 = float(2.0 * np.trace(self.fo) + self.omega)
         # diagonal constant of the pinned TOP pair in every L box
         self.kappa = self.fv[0, 0] - self.fo[0, 0] - self.omega
@@ -302,6 +308,28 @@ class Structured:
 # ---------------------------------------------------------------------------
 # right-hand side b = <mu|H|Psi0>, and E2_S
 # ---------------------------------------------------------------------------
+# index ranges (occupied, virtual) of the free indices of each box: 0 = all
+# orbitals of the kind, 1 = all but the pinned TOP orbital (t or t')
+BOX_RANGES = {"T2": (0, 0), "S2": (0, 0), "T3L": (1, 1), "H11": (0, 0), "H12": (0, 1), "H21": (1, 0),
+              "H22": (1, 1)}
+
+
+def transform_amplitudes(x, no, nv, To, Tv):
+    """Amplitudes after the orbital rotation that fixes t and t': new orbital
+    P' = sum_P To[P, P'] P (occupied, To[0] = e_0), likewise Tv for the
+    virtuals.  Every free index of every box is contracted with the matching
+    block of To or Tv.  D + L is invariant under such rotations, so this is an
+    orthogonal map of the first-order space onto itself."""
+    bx = Boxes(no, nv)
+    d = bx.unpack(x)
+    out = {}
+    for k, X in d.items():
+        lo_o, lo_v = BOX_RANGES[k]
+        U, V = To[lo_o:, lo_o:], Tv[lo_v:, lo_v:]
+        out[k] = np.einsum("ijab,iI,jJ,aA,bB->IJAB", X, U, U, V, V, optimize=True)
+    return bx.pack(out)
+
+
 def _anti2(x):
     """P(ij) P(ab) on a [i,j,a,b] tensor."""
     x = x - x.transpose(1, 0, 2, 3)

@@ -204,6 +204,46 @@ def test_rotation_invariance(name):
     assert abs(r1["e0"] - r2["e0"]) < 1e-12 * abs(r1["e0"])
 
 
+@pytest.mark.parametrize("name", ["micro", "c1"])
+def test_rotations_fixing_the_pinned_pair(name):
+    """Doubles + L-triples are mapped onto themselves by any rotation of the
+    occupied orbitals other than t and of the virtuals other than t' (an
+    L-triple keeps t among its holes and t' among its particles), so the
+    operator is covariant, sigma(T x) = T sigma(x) with the Fock matrix
+    rotated, the right-hand side transforms like an amplitude vector, and
+    E2_DL = -b^T A^-1 b is unchanged.  Such a rotation that diagonalises the
+    non-pinned Fock blocks makes the operator nearly diagonal."""
+    p = synth.make_problem(4, 7, 9, 4) if name == "micro" else synth.config_problem("c1")
+    no, nv = p.n_occ, p.n_vir
+    lam, R = topbasis.top_rotation(p.F, p.C, no)
+    Ft, Bt = topbasis.rotate(p.F, p.B, R)
+    rh = structured.RHS(Ft, Bt, lam, no)
+    op, b = rh.op, rh.rhs()
+    rng = np.random.default_rng(5)
+    for kind in ("random", "semicanonical"):
+        To, Tv = np.eye(no), np.eye(nv)
+        if kind == "random":
+            To[1:, 1:], Tv[1:, 1:] = _rand_orth(no - 1, rng), _rand_orth(nv - 1, rng)
+        else:
+            To[1:, 1:] = np.linalg.eigh(Ft[1:no, 1:no])[1]
+            Tv[1:, 1:] = np.linalg.eigh(Ft[no + 1:, no + 1:])[1]
+        T = np.zeros_like(Ft)
+        T[:no, :no], T[no:, no:] = To, Tv
+        op2 = structured.Structured(T.T @ Ft @ T, lam, no, omega=op.omega)
+        assert abs(op2.E0 - op.E0) < 1e-12 and abs(op2.kappa - op.kappa) < 1e-12
+        x = synth.random_amplitudes(op.dim, 3)
+        tx = structured.transform_amplitudes(x, no, nv, To, Tv)
+        np.testing.assert_allclose(op2.sigma(tx), structured.transform_amplitudes(op.sigma(x), no, nv, To, Tv),
+                                   rtol=0, atol=1e-12 * np.abs(op.sigma(x)).max())
+        assert abs(op2.dot(tx, tx) - op.dot(x, x)) < 1e-12 * op.dot(x, x)
+        b2 = structured.transform_amplitudes(b, no, nv, To, Tv)
+        x1, _, it1, _ = structured.pcg(op, b, tol=1e-12)
+        x2, _, it2, _ = structured.pcg(op2, b2, tol=1e-12)
+        assert abs(op.dot(b, x1) - op2.dot(b2, x2)) < 1e-12 * abs(op.dot(b, x1))
+        if kind == "semicanonical":
+            assert it2 < it1
+
+
 def test_rank_one_reference_has_no_s_rhs():
     """For a single-CSF reference (rank-1 C) only TOP t has a non-zero
     coefficient, so the S-triples have no right-hand side and E2_S = 0.
