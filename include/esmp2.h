@@ -82,6 +82,13 @@ typedef enum {
                                to FP32, FP32 matrix-core accumulation)               */
 } esmp2_precision;
 
+typedef enum {
+  ESMP2_BASIS_TOP = 0,            /* solve in the TOP basis                           */
+  ESMP2_BASIS_SEMICANONICAL = 1   /* solve after rotating the occupied orbitals other
+                                     than t and the virtuals other than t' so that their
+                                     Fock blocks are diagonal ("pinned semicanonical")   */
+} esmp2_basis;
+
 typedef struct {
   double tol;               /* stop when ||b + A x||_W / ||b||_W <= tol (e.g. 1e-8)   */
   int max_iter;             /* conjugate-gradient iteration cap                      */
@@ -93,6 +100,7 @@ typedef struct {
                                (FP32: the inner residual estimate times the outer one) */
   double inner_tol;         /* FP32 only: smallest relative residual reduction asked of
                                one inner FP32 solve, in [0, 1); 0 selects 1e-5         */
+  int basis;                /* esmp2_basis of the Krylov solve (results are the same) */
 } esmp2_solve_opts;
 
 typedef struct {
@@ -152,7 +160,15 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision);
  * A d = r / ||r|| run by FP32 conjugate gradient (FP32 operator and vectors, FP64
  * reductions) to a relative reduction max(inner_tol, tol / (2 ||r||/||b||)); the
  * FP64 x accumulates ||r|| d.  The stopping test, x and E2 are FP64 in both modes;
- * result.iterations counts the inner iterations and result.outer the FP64 steps. */
+ * result.iterations counts the inner iterations and result.outer the FP64 steps.
+ * basis = ESMP2_BASIS_SEMICANONICAL: doubles + L-triples are mapped onto
+ * themselves by any rotation of the occupied orbitals other than t and of the
+ * virtuals other than t' (Sec. II.B: an L-triple keeps t and t'), so the
+ * operator is covariant and E2 unchanged; the solve runs after the rotation
+ * that diagonalises those two Fock blocks, where the Jacobi preconditioner is
+ * close to the operator.  The first such solve after build_rhs computes the
+ * rotation (two small eigenproblems) and rotates b.  In both bases x0 and x_out
+ * are amplitudes of the TOP basis (rotated on the way in and out). */
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
                          esmp2_solve_result* result);
 

@@ -13,6 +13,7 @@ lib = C.CDLL(LIB_PATH)
 (ESMP2_OK, ESMP2_INVALID_ARG, ESMP2_BAD_ORDER, ESMP2_NOT_SPD, ESMP2_NOT_CONVERGED,
  ESMP2_OOM, ESMP2_HIP_ERROR, ESMP2_UNSUPPORTED) = range(8)
 ESMP2_FP64, ESMP2_FP32 = 0, 1
+ESMP2_BASIS_TOP, ESMP2_BASIS_SEMICANONICAL = 0, 1
 STATUS_NAMES = ["OK", "INVALID_ARG", "BAD_ORDER", "NOT_SPD", "NOT_CONVERGED", "OOM",
                 "HIP_ERROR", "UNSUPPORTED"]
 
@@ -20,7 +21,7 @@ STATUS_NAMES = ["OK", "INVALID_ARG", "BAD_ORDER", "NOT_SPD", "NOT_CONVERGED", "O
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
                 ("x0", C.c_void_p), ("x_out", C.c_void_p), ("resid_hist", C.c_void_p),
-                ("inner_tol", C.c_double)]
+                ("inner_tol", C.c_double), ("basis", C.c_int)]
 
 
 class SolveResult(C.Structure):
@@ -118,12 +119,12 @@ class Handle:
         return self._check(lib.esmp2_sigma(self.h, _ptr(x), _ptr(y), precision))
 
     def solve(self, tol=1e-8, max_iter=200, precision=ESMP2_FP64, x0=None, x_out=None,
-              history=False, inner_tol=0.0, allow=(ESMP2_NOT_CONVERGED,)):
+              history=False, inner_tol=0.0, basis=ESMP2_BASIS_TOP, allow=(ESMP2_NOT_CONVERGED,)):
         import numpy as np
         hist = np.zeros(max_iter, dtype=np.float64) if history else None
         o = SolveOpts(tol, max_iter, precision, None if x0 is None else x0.data_ptr(),
                       None if x_out is None else x_out.data_ptr(),
-                      None if hist is None else hist.ctypes.data, inner_tol)
+                      None if hist is None else hist.ctypes.data, inner_tol, basis)
         r = SolveResult()
         self._check(lib.esmp2_solve(self.h, C.byref(o), C.byref(r)), allow=allow)
         out = {k: getattr(r, k) for k, _ in SolveResult._fields_}

@@ -82,12 +82,20 @@ struct esmp2_handle_ {
   int4* jobs4 = nullptr;
   int njobs4 = 0;
   int* pairs = nullptr;          // (p << 16) | q tables: virtual pairs, shifted virtual, occupied, shifted occupied
+  int4* chunks = nullptr;        // coupling kernel work: (box, batch, first inner index, (p << 16) | q)
+  int nchunks = 0;
   // Krylov vectors
   double *x, *r, *p, *q;
   // FP32 operator (Fock blocks rounded from the FP64 ones, work buffers) and
   // the FP32 vectors of the inner solves of the mixed-precision refinement
   float *Fd32, *Fl32, *fo32, *fv32, *fov32, *S32, *side32, *side_tr32;
   float *d32, *r32, *p32, *q32, *dinv32;
+  // pinned-semicanonical basis: rotations (t and t' fixed), operator blocks, rotated rhs,
+  // Jacobi diagonal, dense scratch of the amplitude rotation
+  bool have_sc = false;
+  double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *dinv_sc, *b_sc;
+  float *Fd32_sc, *Fl32_sc, *fo32_sc, *fv32_sc, *fov32_sc, *dinv32_sc;
+  double *dense0, *dense1;
   // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream,
   // per operator precision (index = esmp2_precision)
   bool prof = false;
@@ -120,6 +128,7 @@ static void release(esmp2_handle h) {
   h->allocs.clear();
   h->state = 0;
   h->have_rhs = false;
+  h->have_sc = false;
 }
 
 template <class T>
@@ -230,6 +239,15 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
        dalloc(h, &h->side_tr32, (size_t)nv * (d.npo + (no - 1) * (no - 1))) && dalloc(h, &h->d32, namp) &&
        dalloc(h, &h->r32, namp) && dalloc(h, &h->p32, namp) && dalloc(h, &h->q32, namp) &&
        dalloc(h, &h->dinv32, namp);
+  const size_t dense = (size_t)no * no * nv * nv;
+  ok = ok && dalloc(h, &h->To, no * no) && dalloc(h, &h->Tv, (size_t)nv * nv) && dalloc(h, &h->Tsc, (size_t)n * n) &&
+       dalloc(h, &h->Fh, (size_t)n * n) && dalloc(h, &h->fo_sc, no * no) && dalloc(h, &h->fv_sc, (size_t)nv * nv) &&
+       dalloc(h, &h->fov_sc, (size_t)no * nv) && dalloc(h, &h->eo_sc, no) && dalloc(h, &h->ev_sc, nv) &&
+       dalloc(h, &h->Fd_sc, (size_t)mv * mv) && dalloc(h, &h->Fl_sc, (size_t)mv * mv) &&
+       dalloc(h, &h->dinv_sc, namp) && dalloc(h, &h->b_sc, namp) && dalloc(h, &h->Fd32_sc, (size_t)mv * mv) &&
+       dalloc(h, &h->Fl32_sc, (size_t)mv * mv) && dalloc(h, &h->fo32_sc, no * no) &&
+       dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
+       dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense);
   if (!ok) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
   // vv job table
   std::vector<int2> jobs;
@@ -256,12 +274,36 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
       for (int q = p + 1; q < m; ++q) pairs.push_back((p << 16) | q);
   };
   add_pairs(nv); add_pairs(nv - 1); add_pairs(no); add_pairs(no - 1);
-  if (!dalloc(h, &h->jobs, jobs.size()) || !dalloc(h, &h->jobs4, j4.size()) || !dalloc(h, &h->pairs, pairs.size())) {
+  std::vector<int4> chunks;
+  {
+    const int inner[7] = {d.npv, nv * nv, d.npv1, d.npv, (nv - 1) * (nv - 1), d.npv, (nv - 1) * (nv - 1)};
+    for (int bx = 0; bx < 7; ++bx)
+      for (int k = 0; k < nbat[bx]; ++k) {
+        int p = 0, q = 0;
+        if (bx == B_T2 || bx == B_H11 || bx == B_H12 || bx == B_T3) {
+          const int m = bx == B_T3 ? no - 1 : no;
+          int r = k;
+          while (r >= m - 1 - p) { r -= m - 1 - p; ++p; }
+          q = p + 1 + r;
+          if (bx == B_T3) { ++p; ++q; }
+        } else if (bx == B_S2) {
+          p = k / no; q = k % no;
+        } else {
+          p = k / (no - 1) + 1; q = k % (no - 1) + 1;
+        }
+        for (int v0 = 0; v0 < inner[bx]; v0 += 256) chunks.push_back(make_int4(bx, k, v0, (p << 16) | q));
+      }
+  }
+  h->nchunks = (int)chunks.size();
+  if (!dalloc(h, &h->jobs, jobs.size()) || !dalloc(h, &h->jobs4, j4.size()) || !dalloc(h, &h->pairs, pairs.size()) ||
+      !dalloc(h, &h->chunks, chunks.size())) {
     release(h);
     return fail(h, ESMP2_OOM, "device allocation failed");
   }
   if (!pairs.empty())
     ESMP2_HIP(hipMemcpyAsync(h->pairs, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  if (!chunks.empty())
+    ESMP2_HIP(hipMemcpyAsync(h->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->jobs4, j4.data(), j4.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->jobs, jobs.data(), jobs.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->F, F, sizeof(double) * n * n, hipMemcpyDefault, h->stream));
@@ -403,6 +445,7 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   h->svd_sweeps = info[0];
   h->state = 2;
   h->have_rhs = false;
+  h->have_sc = false;
   return ESMP2_OK;
 }
 
@@ -452,6 +495,7 @@ static esmp2_status build_rhs(esmp2_handle h) {
   h->e2s = tmp[1];
   if (!(tmp[0] > 0.0)) return fail(h, ESMP2_NOT_SPD, "a diagonal denominator of the first-order space is <= 0");
   h->have_rhs = true;
+  h->have_sc = false;
   h->state = 3;
   return ESMP2_OK;
 }
@@ -558,7 +602,8 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
   }
   const int* pv = h->pairs;
   PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
-  hipLaunchKernelGGL(k_couple<T>, dim3(nblk(d.off[7])), dim3(256), 0, s, ga, pt);
+  if (h->nchunks > 0)
+    hipLaunchKernelGGL(k_couple<T>, dim3(h->nchunks), dim3(256), 0, s, ga, pt, (const int4*)h->chunks);
   if (oo_mfma) {
     int pre[8] = {0};
     for (int k = 0; k < 7; ++k) {
@@ -577,6 +622,170 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
 
 static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) { return sigma_t(h, bufs64(h), x, y); }
 static esmp2_status sigma32(esmp2_handle h, const float* x, float* y) { return sigma_t(h, bufs32(h), x, y); }
+
+// ---------------------------------------------------------------------------
+// pinned-semicanonical basis
+// ---------------------------------------------------------------------------
+// Eigenpairs of a symmetric m x m matrix A (device, contiguous) by the
+// tridiagonal route of the AVO step: evals ascending, Y[i*m + k] = component i
+// of eigenvector k.  Scratch ws: 4 m^2 + 3 m doubles.
+static esmp2_status sym_eig(esmp2_handle h, const double* A, int m, double* evals, double* Y, double* ws) {
+  hipStream_t s = h->stream;
+  if (m <= 0) return ESMP2_OK;
+  double* refl = ws;
+  double* Yt = refl + (size_t)m * m;
+  double* work = Yt + (size_t)m * m;        // 2 m^2
+  double* vec = work + (size_t)2 * m * m;   // rbeta, d, e
+  if (m == 1) {
+    ESMP2_HIP(hipMemcpyAsync(evals, A, sizeof(double), hipMemcpyDeviceToDevice, s));
+    const double one = 1.0;
+    ESMP2_HIP(hipMemcpyAsync(Y, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    ESMP2_HIP(hipStreamSynchronize(s));
+    return ESMP2_OK;
+  }
+  size_t lt = sizeof(double) * (size_t)m * (m + 1) / 2;
+  ESMP2_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lt));
+  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lt, s, A, m, refl, vec, vec + m, vec + 2 * m);
+  hipLaunchKernelGGL(k_tri_eig, dim3(m), dim3(64), 0, s, vec + m, vec + 2 * m, m, evals, Yt, work);
+  hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(64), 0, s, evals, m, Yt);
+  hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), sizeof(double) * m, s, refl, vec, m, Yt, Y);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+// Contract index `which` (0: P, 1: Q, 2: A, 3: B) of dense[P][Q][A][B]
+// (ranges ro, ro, rv, rv) with G: out[..c'..] = sum_c G(c, c') in[..c..],
+// G(c, c') = Gm[c*sr + c'*sc].
+static hipError_t contract_index(hipStream_t s, int which, int ro, int rv, const double* Gm, int64_t sr,
+                                 int64_t sc, const double* in, double* out) {
+  GemmArgs g{};
+  g.alpha = 1; g.beta = 0;
+  const int64_t v2 = (int64_t)rv * rv;
+  if (which == 3) {                 // out[R][B'] = sum_B in[R][B] G(B, B')
+    g.A = in; g.B = Gm; g.C = out; g.M = ro * ro * rv; g.N = rv; g.K = rv;
+    g.sAi = rv; g.sAk = 1; g.sBk = sr; g.sBj = sc; g.sCi = rv; g.sCj = 1;
+    return gemm(s, 1, g);
+  }
+  if (which == 2) {                 // out[PQ][A'][B] = sum_A G(A, A') in[PQ][A][B]
+    g.A = Gm; g.B = in; g.C = out; g.M = rv; g.N = rv; g.K = rv;
+    g.sAb = 0; g.sAi = sc; g.sAk = sr; g.sBb = v2; g.sBk = rv; g.sBj = 1; g.sCb = v2; g.sCi = rv; g.sCj = 1;
+    return gemm(s, ro * ro, g);
+  }
+  if (which == 0) {                 // out[P'][rest] = sum_P G(P, P') in[P][rest]
+    g.A = Gm; g.B = in; g.C = out; g.M = ro; g.N = (int)(ro * v2); g.K = ro;
+    g.sAi = sc; g.sAk = sr; g.sBk = ro * v2; g.sBj = 1; g.sCi = ro * v2; g.sCj = 1;
+    return gemm(s, 1, g);
+  }
+  // out[P][Q'][AB] = sum_Q G(Q, Q') in[P][Q][AB]
+  g.A = Gm; g.B = in; g.C = out; g.M = ro; g.N = (int)v2; g.K = ro;
+  g.sAb = 0; g.sAi = sc; g.sAk = sr; g.sBb = ro * v2; g.sBk = v2; g.sBj = 1; g.sCb = ro * v2; g.sCi = v2; g.sCj = 1;
+  return gemm(s, ro, g);
+}
+
+// y = rotation of the amplitude vector x: forward (TOP basis -> pinned
+// semicanonical basis) contracts every free index with the rotation block,
+// G = T; backward with its transpose.  x and y must not overlap.
+static esmp2_status rotate_amplitudes(esmp2_handle h, const double* x, double* y, bool forward) {
+  const Dims& d = h->d;
+  hipStream_t s = h->stream;
+  for (int box = 0; box < 7; ++box) {
+    if (d.off[box + 1] == d.off[box]) continue;
+    int lo_o, lo_v;
+    box_ranges(box, lo_o, lo_v);
+    const int ro = d.no - lo_o, rv = d.nv - lo_v;
+    const double* Go = h->To + lo_o * d.no + lo_o;
+    const double* Gv = h->Tv + lo_v * d.nv + lo_v;
+    const int64_t sro = forward ? d.no : 1, sco = forward ? 1 : d.no;
+    const int64_t srv = forward ? d.nv : 1, scv = forward ? 1 : d.nv;
+    const int64_t nd = (int64_t)ro * ro * rv * rv;
+    hipLaunchKernelGGL(k_unpack_box, dim3(nblk(nd)), dim3(256), 0, s, d, box, x, h->dense0);
+    ESMP2_HIP(contract_index(s, 3, ro, rv, Gv, srv, scv, h->dense0, h->dense1));
+    ESMP2_HIP(contract_index(s, 2, ro, rv, Gv, srv, scv, h->dense1, h->dense0));
+    ESMP2_HIP(contract_index(s, 0, ro, rv, Go, sro, sco, h->dense0, h->dense1));
+    ESMP2_HIP(contract_index(s, 1, ro, rv, Go, sro, sco, h->dense1, h->dense0));
+    hipLaunchKernelGGL(k_pack_box, dim3(nblk(d.off[box + 1] - d.off[box])), dim3(256), 0, s, d, box,
+                       (const double*)h->dense0, y);
+  }
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+// Rotation diagonalising F~_oo[1:,1:] and F~_vv[1:,1:], the operator blocks in
+// the new basis (TOP-basis omega and kappa), its Jacobi diagonal and the
+// rotated right-hand side.  Requires the right-hand side.
+static esmp2_status semican_setup(esmp2_handle h) {
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv, n = d.n, mv = d.mv;
+  const int64_t namp = d.off[7];
+  hipStream_t s = h->stream;
+  double* A = h->rs;                                   // (nv-1)^2 block copy
+  double* evals = A + (size_t)nv * nv;
+  double* Y = evals + nv;
+  double* ws = Y + (size_t)nv * nv;                    // 4 nv^2 + 3 nv  (rs holds 11 nv^2)
+  // occupied block (t fixed)
+  hipLaunchKernelGGL(k_block_copy, dim3(64), dim3(256), 0, s, (const double*)h->Ft, (int64_t)n + 1, n, no - 1, A);
+  esmp2_status st = sym_eig(h, A, no - 1, evals, Y, ws);
+  if (st != ESMP2_OK) return st;
+  hipLaunchKernelGGL(k_embed_rotation, dim3(nblk(no * no)), dim3(256), 0, s, (const double*)Y, no, h->To);
+  // virtual block (t' fixed)
+  hipLaunchKernelGGL(k_block_copy, dim3(256), dim3(256), 0, s, (const double*)h->Ft, (int64_t)(no + 1) * n + no + 1,
+                     n, nv - 1, A);
+  st = sym_eig(h, A, nv - 1, evals, Y, ws);
+  if (st != ESMP2_OK) return st;
+  hipLaunchKernelGGL(k_embed_rotation, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, (const double*)Y, nv, h->Tv);
+  // Fh = T^T F~ T
+  hipLaunchKernelGGL(k_blkdiag, dim3(nblk((int64_t)n * n)), dim3(256), 0, s, (const double*)h->To,
+                     (const double*)h->Tv, no, nv, h->Tsc);
+  GemmArgs g{};
+  g.A = h->Ft; g.B = h->Tsc; g.C = h->T; g.M = n; g.N = n; g.K = n;
+  g.sAi = n; g.sAk = 1; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));
+  g = GemmArgs{};
+  g.A = h->Tsc; g.B = h->T; g.C = h->Fh; g.M = n; g.N = n; g.K = n;
+  g.sAi = 1; g.sAk = n; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));
+  hipLaunchKernelGGL(k_fock_blocks, dim3(nblk((int64_t)mv * mv > n * n ? (int64_t)mv * mv : (int64_t)n * n)),
+                     dim3(256), 0, s, (const double*)h->Fh, no, nv, mv, h->omega, h->kappa, h->fo_sc, h->fv_sc,
+                     h->fov_sc, h->eo_sc, h->ev_sc, h->Fd_sc, h->Fl_sc);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, (const double*)h->Fd_sc, h->Fd32_sc,
+                     (int64_t)mv * mv);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, (const double*)h->Fl_sc, h->Fl32_sc,
+                     (int64_t)mv * mv);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk(no * no)), dim3(256), 0, s, (const double*)h->fo_sc, h->fo32_sc,
+                     (int64_t)no * no);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, (const double*)h->fv_sc, h->fv32_sc,
+                     (int64_t)nv * nv);
+  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)no * nv)), dim3(256), 0, s, (const double*)h->fov_sc,
+                     h->fov32_sc, (int64_t)no * nv);
+  DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv_sc, h->blockmin};
+  hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
+  hipLaunchKernelGGL(k_to_f32, dim3(PCG_BLOCKS), dim3(256), 0, s, (const double*)h->dinv_sc, h->dinv32_sc, namp);
+  st = rotate_amplitudes(h, h->b, h->b_sc, true);
+  if (st != ESMP2_OK) return st;
+  ESMP2_HIP(hipGetLastError());
+  h->have_sc = true;
+  return ESMP2_OK;
+}
+
+// Everything a solve needs in one basis
+struct OpCtx {
+  const double* b;
+  const double* dinv;
+  const float* dinv32;
+  SigmaBufs<double> s64;
+  SigmaBufs<float> s32;
+  bool rotated;      // pinned-semicanonical basis: x_out is rotated back
+};
+
+static OpCtx ctx_top(esmp2_handle h) { return OpCtx{h->b, h->dinv, h->dinv32, bufs64(h), bufs32(h), false}; }
+
+static OpCtx ctx_sc(esmp2_handle h) {
+  OpCtx c{h->b_sc, h->dinv_sc, h->dinv32_sc, bufs64(h), bufs32(h), true};
+  c.s64.Fd = h->Fd_sc; c.s64.Fl = h->Fl_sc; c.s64.fo = h->fo_sc; c.s64.fv = h->fv_sc; c.s64.fov = h->fov_sc;
+  c.s32.Fd = h->Fd32_sc; c.s32.Fl = h->Fl32_sc; c.s32.fo = h->fo32_sc; c.s32.fv = h->fv32_sc;
+  c.s32.fov = h->fov32_sc;
+  return c;
+}
 
 extern "C" {
 
@@ -605,15 +814,22 @@ static void wdot(esmp2_handle h, const T* x, const T* y, int slot) {
 extern "C" {
 
 // E2 (Hylleraas form <b,x>_W - <x,r>_W, r = -b - A x) and the result record
-static esmp2_status finish_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res, double rel,
-                                 int it, int outer, esmp2_status status) {
+static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
+                                 esmp2_solve_result* res, double rel, int it, int outer, esmp2_status status) {
   const int64_t n = h->d.off[7];
   hipStream_t s = h->stream;
   double hs[SC_N];
-  wdot(h, (const double*)h->b, (const double*)h->x, SC_BX);
+  wdot(h, c.b, (const double*)h->x, SC_BX);
   wdot(h, (const double*)h->x, (const double*)h->r, SC_XR);
   ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
-  if (opts->x_out) ESMP2_HIP(hipMemcpyAsync(opts->x_out, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  if (opts->x_out) {
+    if (c.rotated) {
+      esmp2_status st = rotate_amplitudes(h, h->x, opts->x_out, false);
+      if (st != ESMP2_OK) return st;
+    } else {
+      ESMP2_HIP(hipMemcpyAsync(opts->x_out, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+  }
   ESMP2_HIP(hipStreamSynchronize(s));
   ESMP2_HIP(hipGetLastError());
   res->e2_dl = hs[SC_BX] - hs[SC_XR];
@@ -628,21 +844,27 @@ static esmp2_status finish_solve(esmp2_handle h, const esmp2_solve_opts* opts, e
 }
 
 // Jacobi-preconditioned conjugate gradient in FP64 for A x = -b
-static esmp2_status solve64(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res) {
+static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
+                            esmp2_solve_result* res) {
   const Dims& d = h->d;
   const int64_t n = d.off[7];
   hipStream_t s = h->stream;
   const unsigned NB = PCG_BLOCKS;
-  wdot(h, (const double*)h->b, (const double*)h->b, SC_BB);   // ||b||_W^2
+  wdot(h, c.b, c.b, SC_BB);   // ||b||_W^2
   if (opts->x0) {
-    ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    esmp2_status st = sigma64(h, h->x, h->q);
+    if (c.rotated) {
+      esmp2_status st0 = rotate_amplitudes(h, opts->x0, h->x, true);
+      if (st0 != ESMP2_OK) return st0;
+    } else {
+      ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+    esmp2_status st = sigma_t(h, c.s64, (const double*)h->x, h->q);
     if (st != ESMP2_OK) return st;
-    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, h->b, h->q, h->r, h->p, h->dinv, n, d.off[1], d.off[2],
+    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, h->q, h->r, h->p, c.dinv, n, d.off[1], d.off[2],
                        h->partial);
   } else {
     ESMP2_HIP(hipMemsetAsync(h->x, 0, sizeof(double) * n, s));
-    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, h->b, (const double*)nullptr, h->r, h->p, h->dinv, n,
+    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv, n,
                        d.off[1], d.off[2], h->partial);
   }
   // rho = <r, D^-1 r> into SC_RHO and <r, r> into SC_RHO + 1 = SC_PQ
@@ -655,10 +877,10 @@ static esmp2_status solve64(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_
   int it = 0;
   esmp2_status status = ESMP2_OK;
   while (rel > opts->tol && it < opts->max_iter) {
-    esmp2_status st = sigma64(h, h->p, h->q);
+    esmp2_status st = sigma_t(h, c.s64, (const double*)h->p, h->q);
     if (st != ESMP2_OK) return st;
     wdot(h, (const double*)h->p, (const double*)h->q, SC_PQ);
-    hipLaunchKernelGGL(k_update_xr<double>, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, h->dinv, n, d.off[1],
+    hipLaunchKernelGGL(k_update_xr<double>, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, c.dinv, n, d.off[1],
                        d.off[2], h->sc, h->partial);
     hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);  // RHO_NEW, RR
     ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
@@ -668,11 +890,11 @@ static esmp2_status solve64(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_
     rel = sqrt(hs[SC_RR]) / bn;
     if (opts->resid_hist) opts->resid_hist[it - 1] = rel;
     if (rel <= opts->tol) break;
-    hipLaunchKernelGGL(k_update_p<double>, dim3(NB), dim3(256), 0, s, h->p, h->r, h->dinv, n, h->sc);
+    hipLaunchKernelGGL(k_update_p<double>, dim3(NB), dim3(256), 0, s, h->p, h->r, c.dinv, n, h->sc);
     hipLaunchKernelGGL(k_roll_rho, dim3(1), dim3(64), 0, s, h->sc);
   }
   if (status == ESMP2_OK && rel > opts->tol) { status = ESMP2_NOT_CONVERGED; h->err = "max_iter reached"; }
-  return finish_solve(h, opts, res, rel, it, 0, status);
+  return finish_solve(h, c, opts, res, rel, it, 0, status);
 }
 
 // Mixed precision: FP64 iterative refinement around FP32 inner solves.
@@ -680,22 +902,28 @@ static esmp2_status solve64(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_
 //   relative reduction eta;  x += ||r|| d;  r = -b - A64 x;  until ||r||/||b|| <= tol.
 // eta = max(inner_tol, tol / (2 ||r||/||b||)): the last inner solve stops as soon
 // as it reaches the target; inner_tol bounds what an FP32 operator can deliver.
-static esmp2_status solve_mixed(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res) {
+static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
+                                esmp2_solve_result* res) {
   const Dims& d = h->d;
   const int64_t n = d.off[7];
   hipStream_t s = h->stream;
   const unsigned NB = PCG_BLOCKS;
   const double floor_eta = opts->inner_tol > 0 ? opts->inner_tol : 1e-5;
-  wdot(h, (const double*)h->b, (const double*)h->b, SC_BB);
+  wdot(h, c.b, c.b, SC_BB);
   if (opts->x0) {
-    ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    esmp2_status st = sigma64(h, h->x, h->q);
+    if (c.rotated) {
+      esmp2_status st0 = rotate_amplitudes(h, opts->x0, h->x, true);
+      if (st0 != ESMP2_OK) return st0;
+    } else {
+      ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+    esmp2_status st = sigma_t(h, c.s64, (const double*)h->x, h->q);
     if (st != ESMP2_OK) return st;
-    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, h->b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
+    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, c.b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
                        h->partial);
   } else {
     ESMP2_HIP(hipMemsetAsync(h->x, 0, sizeof(double) * n, s));
-    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, h->b, (const double*)nullptr, h->r, n, d.off[1],
+    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, n, d.off[1],
                        d.off[2], h->partial);
   }
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RR);
@@ -711,17 +939,17 @@ static esmp2_status solve_mixed(esmp2_handle h, const esmp2_solve_opts* opts, es
     const double scale = rel * bn;
     const double eta = std::max(floor_eta, 0.5 * opts->tol / rel);
     hipLaunchKernelGGL(k_init_inner, dim3(NB), dim3(256), 0, s, (const double*)h->r, scale, h->r32, h->p32, h->d32,
-                       (const float*)h->dinv32, n, d.off[1], d.off[2], h->partial);
+                       c.dinv32, n, d.off[1], d.off[2], h->partial);
     hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);  // RHO, rr0
     ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
     ESMP2_HIP(hipStreamSynchronize(s));
     const double rr0 = hs[SC_PQ];
     while (it < opts->max_iter) {
-      esmp2_status st = sigma32(h, h->p32, h->q32);
+      esmp2_status st = sigma_t(h, c.s32, (const float*)h->p32, h->q32);
       if (st != ESMP2_OK) return st;
       wdot(h, (const float*)h->p32, (const float*)h->q32, SC_PQ);
       hipLaunchKernelGGL(k_update_xr<float>, dim3(NB), dim3(256), 0, s, h->d32, h->r32, (const float*)h->p32,
-                         (const float*)h->q32, (const float*)h->dinv32, n, d.off[1], d.off[2], (const double*)h->sc,
+                         (const float*)h->q32, c.dinv32, n, d.off[1], d.off[2], (const double*)h->sc,
                          h->partial);
       hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);
       ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
@@ -732,14 +960,14 @@ static esmp2_status solve_mixed(esmp2_handle h, const esmp2_solve_opts* opts, es
       if (opts->resid_hist) opts->resid_hist[it - 1] = irel * rel;   // estimate of the FP64 residual
       if (irel <= eta) break;
       hipLaunchKernelGGL(k_update_p<float>, dim3(NB), dim3(256), 0, s, h->p32, (const float*)h->r32,
-                         (const float*)h->dinv32, n, (const double*)h->sc);
+                         c.dinv32, n, (const double*)h->sc);
       hipLaunchKernelGGL(k_roll_rho, dim3(1), dim3(64), 0, s, h->sc);
     }
     if (status != ESMP2_OK) break;
     hipLaunchKernelGGL(k_refine, dim3(NB), dim3(256), 0, s, h->x, (const float*)h->d32, scale, n);
-    esmp2_status st = sigma64(h, h->x, h->q);
+    esmp2_status st = sigma_t(h, c.s64, (const double*)h->x, h->q);
     if (st != ESMP2_OK) return st;
-    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, h->b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
+    hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, c.b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
                        h->partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RR);
     ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
@@ -747,7 +975,7 @@ static esmp2_status solve_mixed(esmp2_handle h, const esmp2_solve_opts* opts, es
     rel = sqrt(hs[SC_RR]) / bn;
   }
   if (status == ESMP2_OK && rel > opts->tol) { status = ESMP2_NOT_CONVERGED; h->err = "max_iter reached"; }
-  return finish_solve(h, opts, res, rel, it, outer, status);
+  return finish_solve(h, c, opts, res, rel, it, outer, status);
 }
 
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_solve_result* res) {
@@ -757,6 +985,8 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
   if (!(opts->tol > 0) || opts->max_iter < 1) return fail(h, ESMP2_INVALID_ARG, "tol > 0 and max_iter >= 1");
   if (opts->precision != ESMP2_FP64 && opts->precision != ESMP2_FP32)
     return fail(h, ESMP2_INVALID_ARG, "unknown precision");
+  if (opts->basis != ESMP2_BASIS_TOP && opts->basis != ESMP2_BASIS_SEMICANONICAL)
+    return fail(h, ESMP2_INVALID_ARG, "unknown basis");
   if (opts->precision == ESMP2_FP32 && !(opts->inner_tol >= 0 && opts->inner_tol < 1))
     return fail(h, ESMP2_INVALID_ARG, "inner_tol must lie in [0, 1)");
   ESMP2_HIP(hipSetDevice(h->device));
@@ -765,7 +995,15 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
     esmp2_status st = build_rhs(h);
     if (st != ESMP2_OK) { res->status = st; return st; }
   }
-  return opts->precision == ESMP2_FP64 ? solve64(h, opts, res) : solve_mixed(h, opts, res);
+  OpCtx c = ctx_top(h);
+  if (opts->basis == ESMP2_BASIS_SEMICANONICAL) {
+    if (!h->have_sc) {
+      esmp2_status st = semican_setup(h);
+      if (st != ESMP2_OK) { res->status = st; return st; }
+    }
+    c = ctx_sc(h);
+  }
+  return opts->precision == ESMP2_FP64 ? solve64(h, c, opts, res) : solve_mixed(h, c, opts, res);
 }
 
 }  // extern "C"

@@ -4,4 +4,5 @@
 #include "sigma.hip"
 #include "vv3.hip"
 #include "pcg.hip"
+#include "semican.hip"
 #include "api.hip"

@@ -59,7 +59,7 @@ template <class T> __global__ void k_sym_s2(Dims d, const T* x, T* S);
 template <class T, int TW> __global__ void k_vv(VVArgs<T> A);
 template <class T, int NT> __global__ void k_vv3(VVArgs<T> A);
 template <class T> __global__ void k_side(SideArgs<T> A);
-template <class T> __global__ void k_couple(GatherArgs<T> A, PairTables P);
+template <class T> __global__ void k_couple(GatherArgs<T> A, PairTables P, const int4* chunks);
 template <class T> __global__ void k_oo(GatherArgs<T> A, int4 tiles0, int4 tiles1);
 template <class T> __global__ void k_oo_plain(GatherArgs<T> A);
 

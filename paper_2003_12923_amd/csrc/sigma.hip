@@ -316,7 +316,8 @@ __global__ __launch_bounds__(256) void k_side(SideArgs<T> A) {
 // index pairs: box transfers through a pinned TOP index (f_{t' a}, f_{m t}),
 // doubles <-> L-triples through f_ov (with the side contractions of k_side),
 // y += ... (the virtual-pair part is already in y, k_oo adds the occupied
-// pair part).  One thread per amplitude; pair indices decoded from tables.
+// pair part).  One workgroup per chunk of 256 inner indices of one batch
+// matrix, one thread per amplitude; virtual pairs decoded from tables.
 // ---------------------------------------------------------------------------
 // box of amplitude g and its index within the box (a box holds < 2^31 amplitudes)
 __device__ inline int box_of_g(const Dims& d, int64_t g, int& loc) {
@@ -327,35 +328,41 @@ __device__ inline int box_of_g(const Dims& d, int64_t g, int& loc) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
-  const int *pv = P.pv, *pv1 = P.pv1, *po = P.po, *po1 = P.po1;
+__global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P, const int4* chunks) {
   const Dims& d = A.d;
-  int64_t g = (int64_t)xcd_remap<16>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (g >= d.off[7]) return;
-  const int no = d.no, nv = d.nv;
+  // chunk: (box, batch, first inner index, (p << 16) | q occupied indices of the batch)
+  const int4 ch = chunks[xcd_remap<16>(blockIdx.x, gridDim.x)];
+  const int box = ch.x, batch = ch.y, v = ch.z + (int)threadIdx.x;
+  const int p0 = ch.w >> 16, q0 = ch.w & 0xffff;
+  const int no = d.no, nv = d.nv, m1 = nv - 1;
+  int inner;
+  switch (box) {
+    case B_T2: case B_H11: case B_H21: inner = d.npv; break;
+    case B_S2: inner = nv * nv; break;
+    case B_T3: inner = d.npv1; break;
+    default: inner = m1 * m1; break;
+  }
+  if (v >= inner) return;
   Look<T> L{d, A.x, A.S};
   const T* fo = A.fo;     // fo[m*no + i]
   const T* fv = A.fv;     // fv[a*nv + b]
   const T* fov = A.fov;   // fov[i*nv + a]
   auto FOV = [&](int i, int a) { return fov[i * nv + a]; };
   const T ftt = FOV(0, 0);
-  int loc;
-  const int box = box_of_g(d, g, loc);
   T y = 0;
   switch (box) {
     case B_T2: {
-      int i, j, a, b;
-      { int t = po[loc / d.npv]; i = t >> 16; j = t & 0xffff; t = pv[loc % d.npv]; a = t >> 16; b = t & 0xffff; }
+      const int i = p0, j = q0, t = P.pv[v], a = t >> 16, b = t & 0xffff;
       if (i >= 1 && a >= 1) y += ftt * L.T3(i, j, a, b);
       y += ftt * L.H11(i, j, a, b);
-      if (i == 0 && a >= 1)
-        for (int m = 1; m < no; ++m) y -= FOV(m, 0) * L.T3(m, j, a, b);
-      if (i == 0)
+      if (i == 0) {
+        if (a >= 1)
+          for (int m = 1; m < no; ++m) y -= FOV(m, 0) * L.T3(m, j, a, b);
         for (int m = 1; m < no; ++m) y += FOV(m, 0) * L.H21(m, j, a, b);
+      }
       if (a == 0) {
-        int po = tri_idx(i, j, no);
         if (i >= 1) y -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
-        y += A.h12_t[po * nv + b];
+        y += A.h12_t[batch * nv + b];
         if (i == 0) {
           for (int m = 1; m < no; ++m) {
             if (m < j) y += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
@@ -367,53 +374,51 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
       break;
     }
     case B_S2: {
-      int r = loc;
-      int b = r % nv; r /= nv;
-      int a = r % nv; r /= nv;
-      int j = r % no, i = r / no;
+      const int i = p0, j = q0, a = v / nv, b = v - a * nv;
       // d(p,q,x,z) + d(q,p,z,x): de-excitation of the mixed-spin L-triples
       for (int rep = 0; rep < 2; ++rep) {
-        int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
+        const int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
         T dd = 0;
-        if (p == 0 && xx == 0) {
-          for (int m = 0; m < no; ++m) {
-            if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
-            else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
+        if (p == 0) {
+          if (xx == 0) {
+            for (int m = 0; m < no; ++m) {
+              if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
+              else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
+            }
+          } else if (z >= 1) {
+            for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
+          } else {
+            for (int m = 0; m < no; ++m) {
+              if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
+              else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
+            }
+          }
+        } else if (q >= 1) {
+          if (xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
+          else if (z >= 1) dd += ftt * L.H22(p, q, xx, z);
+          else dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
+        } else {
+          if (xx == 0) {
+            for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
+          } else if (z >= 1) {
+            for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
+          } else {
+            for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
           }
         }
-        if (p == 0 && xx >= 1 && z >= 1)
-          for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
-        if (p == 0 && xx >= 1 && z == 0) {
-          for (int m = 0; m < no; ++m) {
-            if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
-            else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
-          }
-        }
-        if (p >= 1 && q >= 1 && xx == 0) dd += A.h21_t[((p - 1) * (no - 1) + (q - 1)) * nv + z];
-        if (p >= 1 && q == 0 && xx == 0)
-          for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
-        if (p >= 1 && q >= 1 && xx >= 1 && z >= 1) dd += ftt * L.H22(p, q, xx, z);
-        if (p >= 1 && q == 0 && xx >= 1 && z >= 1)
-          for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
-        if (p >= 1 && q >= 1 && xx >= 1 && z == 0) dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
-        if (p >= 1 && q == 0 && xx >= 1 && z == 0)
-          for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
         y += dd;
       }
       break;
     }
     case B_T3: {
-      int j, k, b, c;
-      { int t = po1[loc / d.npv1]; j = t >> 16; k = t & 0xffff; t = pv1[loc % d.npv1]; b = t >> 16; c = t & 0xffff; }
-      ++j; ++k; ++b; ++c;
+      const int j = p0, k = q0, t = P.pv1[v], b = (t >> 16) + 1, c = (t & 0xffff) + 1;
       y += ftt * L.T2(j, k, b, c) - FOV(j, 0) * L.T2(0, k, b, c) + FOV(k, 0) * L.T2(0, j, b, c)
          - FOV(0, b) * L.T2(j, k, 0, c) + FOV(j, b) * L.T2(0, k, 0, c) - FOV(k, b) * L.T2(0, j, 0, c)
          + FOV(0, c) * L.T2(j, k, 0, b) - FOV(j, c) * L.T2(0, k, 0, b) + FOV(k, c) * L.T2(0, j, 0, b);
       break;
     }
     case B_H11: {
-      int j, k, b, c;
-      { int t = po[loc / d.npv]; j = t >> 16; k = t & 0xffff; t = pv[loc % d.npv]; b = t >> 16; c = t & 0xffff; }
+      const int j = p0, k = q0, t = P.pv[v], b = t >> 16, c = t & 0xffff;
       if (j == 0)
         for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H21(m, k, b, c);
       y += ftt * L.T2(j, k, b, c);
@@ -422,10 +427,7 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
       break;
     }
     case B_H12: {
-      int m1 = nv - 1;
-      int j, k;
-      { int t = po[loc / (m1 * m1)]; j = t >> 16; k = t & 0xffff; }
-      int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
+      const int j = p0, k = q0, a = v / m1 + 1, c = v - (a - 1) * m1 + 1;
       y += fv[a * nv + 0] * L.H11(j, k, 0, c);
       if (j == 0)
         for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H22(m, k, a, c);
@@ -435,9 +437,7 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
       break;
     }
     case B_H21: {
-      int o = loc / d.npv, b, c;
-      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-      { int t = pv[loc % d.npv]; b = t >> 16; c = t & 0xffff; }
+      const int i = p0, k = q0, t = P.pv[v], b = t >> 16, c = t & 0xffff;
       y -= fo[0 * no + i] * L.H11(0, k, b, c);
       y += FOV(i, 0) * L.T2(0, k, b, c);
       y += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
@@ -445,10 +445,7 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
       break;
     }
     default: {
-      int m1 = nv - 1;
-      int o = loc / (m1 * m1);
-      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-      int a = (loc % (m1 * m1)) / m1 + 1, c = loc % m1 + 1;
+      const int i = p0, k = q0, a = v / m1 + 1, c = v - (a - 1) * m1 + 1;
       y -= fo[0 * no + i] * L.H12(0, k, a, c);
       y += fv[a * nv + 0] * L.H21(i, k, 0, c);
       y += FOV(i, a) * L.T2(0, k, 0, c);
@@ -457,7 +454,7 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P) {
       break;
     }
   }
-  A.y[g] += y;
+  A.y[d.off[box] + (int64_t)batch * inner + v] += y;
 }
 
 }  // namespace esmp2
@@ -642,7 +639,7 @@ __global__ __launch_bounds__(256) void k_oo_plain(GatherArgs<T> A) {
   template __global__ void k_vv<T, 4>(VVArgs<T>);                                       \
   template __global__ void k_vv<T, 5>(VVArgs<T>);                                       \
   template __global__ void k_side<T>(SideArgs<T>);                                      \
-  template __global__ void k_couple<T>(GatherArgs<T>, PairTables);                      \
+  template __global__ void k_couple<T>(GatherArgs<T>, PairTables, const int4*);          \
   template __global__ void k_oo<T>(GatherArgs<T>, int4, int4);                          \
   template __global__ void k_oo_plain<T>(GatherArgs<T>);
 ESMP2_SIGMA_INSTANCES(double)
