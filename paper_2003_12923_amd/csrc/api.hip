@@ -96,6 +96,7 @@ struct esmp2_handle_ {
   double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *dinv_sc, *b_sc;
   float *Fd32_sc, *Fl32_sc, *fo32_sc, *fv32_sc, *fov32_sc, *dinv32_sc;
   double *dense0, *dense1;
+  double* gv;                    // row/column GEMVs of the arrow-shaped Fock blocks (FP64 or FP32 use)
   // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream,
   // per operator precision (index = esmp2_precision)
   bool prof = false;
@@ -247,7 +248,8 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
        dalloc(h, &h->dinv_sc, namp) && dalloc(h, &h->b_sc, namp) && dalloc(h, &h->Fd32_sc, (size_t)mv * mv) &&
        dalloc(h, &h->Fl32_sc, (size_t)mv * mv) && dalloc(h, &h->fo32_sc, no * no) &&
        dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
-       dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense);
+       dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense) &&
+       dalloc(h, &h->gv, (size_t)nv * (2 * d.npo + 2 * no * no + (no - 1) * (no - 1)));
   if (!ok) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
   // vv job table
   std::vector<int2> jobs;
@@ -534,13 +536,14 @@ static SigmaBufs<float> bufs32(esmp2_handle h) {
 // y = A x in the precision of T, all on the handle's stream:
 // S~ (flip-symmetrised S2) -> side contractions -> virtual-pair Sylvester
 // products (y = ...) -> couplings (y += ...) -> occupied-index action (y += ...)
+// S~ and the per-batch side contractions with f_ov; returns the argument
+// block of the coupling terms.
 template <class T>
-static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y) {
+static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv;
   hipStream_t s = h->stream;
   hipLaunchKernelGGL(k_sym_s2<T>, dim3(nblk((int64_t)no * no * nv * nv)), dim3(256), 0, s, d, x, w.S);
-  // side contractions
   SideArgs<T> sa{};
   sa.d = d; sa.x = x; sa.fov = w.fov;
   T* p = w.side;
@@ -558,6 +561,15 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
   ga.t3_t = sa.t3_t; ga.t3_p1 = sa.t3_p1; ga.t3_p2 = sa.t3_p2; ga.h11_p1 = sa.h11_p1; ga.h11_p2 = sa.h11_p2;
   ga.h12_t = sa.h12_t; ga.h12_u1 = sa.h12_u1; ga.h12_u2 = sa.h12_u2; ga.h21_t = sa.h21_t; ga.h21_k = sa.h21_k;
   ga.h22_ut = sa.h22_ut; ga.h22_i = sa.h22_i; ga.h22_uk = sa.h22_uk;
+  return ga;
+}
+
+template <class T>
+static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y) {
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv;
+  hipStream_t s = h->stream;
+  GatherArgs<T> ga = sigma_prologue(h, w, x, y);
   // tile prefix sums per box for the occupied-index kernel
   const int inner[7] = {d.npv, nv * nv, d.npv1, d.npv, (nv - 1) * (nv - 1), d.npv, (nv - 1) * (nv - 1)};
   const int nbat[7] = {d.npo, no * no, d.npo1, d.npo, d.npo, (no - 1) * (no - 1), (no - 1) * (no - 1)};
@@ -616,6 +628,26 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
   } else {
     hipLaunchKernelGGL(k_oo_plain<T>, dim3(nblk(d.off[7])), dim3(256), 0, s, ga);
   }
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+// sigma in the pinned-semicanonical basis, where the non-pinned Fock blocks
+// are diagonal: O(N_o^2 N_v^2) arrow kernels instead of the Sylvester products
+template <class T>
+static esmp2_status sigma_arrow(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y) {
+  const Dims& d = h->d;
+  const int no = d.no;
+  hipStream_t s = h->stream;
+  GatherArgs<T> ga = sigma_prologue(h, w, x, y);
+  ArrowArgs<T> aa{ga, w.Fd, w.Fl, w.side_tr, (T*)h->gv};
+  const int n2 = (no - 1) * (no - 1);
+  const int jobs = 3 * d.npo + no * no + 2 * n2;
+  hipLaunchKernelGGL(k_arrow_side<T>, dim3(jobs), dim3(256), 0, s, aa);
+  const int* pv = h->pairs;
+  PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
+  if (h->nchunks > 0)
+    hipLaunchKernelGGL(k_arrow<T>, dim3(h->nchunks), dim3(256), 0, s, aa, pt, (const int4*)h->chunks);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
@@ -775,12 +807,18 @@ struct OpCtx {
   SigmaBufs<double> s64;
   SigmaBufs<float> s32;
   bool rotated;      // pinned-semicanonical basis: x_out is rotated back
+  bool arrow;        // the operator through the arrow kernels
 };
 
-static OpCtx ctx_top(esmp2_handle h) { return OpCtx{h->b, h->dinv, h->dinv32, bufs64(h), bufs32(h), false}; }
+template <class T>
+static esmp2_status apply_op(esmp2_handle h, const OpCtx& c, const SigmaBufs<T>& w, const T* x, T* y) {
+  return c.arrow ? sigma_arrow(h, w, x, y) : sigma_t(h, w, x, y);
+}
+
+static OpCtx ctx_top(esmp2_handle h) { return OpCtx{h->b, h->dinv, h->dinv32, bufs64(h), bufs32(h), false, false}; }
 
 static OpCtx ctx_sc(esmp2_handle h) {
-  OpCtx c{h->b_sc, h->dinv_sc, h->dinv32_sc, bufs64(h), bufs32(h), true};
+  OpCtx c{h->b_sc, h->dinv_sc, h->dinv32_sc, bufs64(h), bufs32(h), true, true};
   c.s64.Fd = h->Fd_sc; c.s64.Fl = h->Fl_sc; c.s64.fo = h->fo_sc; c.s64.fv = h->fv_sc; c.s64.fov = h->fov_sc;
   c.s32.Fd = h->Fd32_sc; c.s32.Fl = h->Fl32_sc; c.s32.fo = h->fo32_sc; c.s32.fv = h->fv32_sc;
   c.s32.fov = h->fov32_sc;
@@ -858,7 +896,7 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
     } else {
       ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     }
-    esmp2_status st = sigma_t(h, c.s64, (const double*)h->x, h->q);
+    esmp2_status st = apply_op(h, c, c.s64, (const double*)h->x, h->q);
     if (st != ESMP2_OK) return st;
     hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, h->q, h->r, h->p, c.dinv, n, d.off[1], d.off[2],
                        h->partial);
@@ -877,7 +915,7 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   int it = 0;
   esmp2_status status = ESMP2_OK;
   while (rel > opts->tol && it < opts->max_iter) {
-    esmp2_status st = sigma_t(h, c.s64, (const double*)h->p, h->q);
+    esmp2_status st = apply_op(h, c, c.s64, (const double*)h->p, h->q);
     if (st != ESMP2_OK) return st;
     wdot(h, (const double*)h->p, (const double*)h->q, SC_PQ);
     hipLaunchKernelGGL(k_update_xr<double>, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, c.dinv, n, d.off[1],
@@ -917,7 +955,7 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
     } else {
       ESMP2_HIP(hipMemcpyAsync(h->x, opts->x0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     }
-    esmp2_status st = sigma_t(h, c.s64, (const double*)h->x, h->q);
+    esmp2_status st = apply_op(h, c, c.s64, (const double*)h->x, h->q);
     if (st != ESMP2_OK) return st;
     hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, c.b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
                        h->partial);
@@ -945,7 +983,7 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
     ESMP2_HIP(hipStreamSynchronize(s));
     const double rr0 = hs[SC_PQ];
     while (it < opts->max_iter) {
-      esmp2_status st = sigma_t(h, c.s32, (const float*)h->p32, h->q32);
+      esmp2_status st = apply_op(h, c, c.s32, (const float*)h->p32, h->q32);
       if (st != ESMP2_OK) return st;
       wdot(h, (const float*)h->p32, (const float*)h->q32, SC_PQ);
       hipLaunchKernelGGL(k_update_xr<float>, dim3(NB), dim3(256), 0, s, h->d32, h->r32, (const float*)h->p32,
@@ -965,7 +1003,7 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
     }
     if (status != ESMP2_OK) break;
     hipLaunchKernelGGL(k_refine, dim3(NB), dim3(256), 0, s, h->x, (const float*)h->d32, scale, n);
-    esmp2_status st = sigma_t(h, c.s64, (const double*)h->x, h->q);
+    esmp2_status st = apply_op(h, c, c.s64, (const double*)h->x, h->q);
     if (st != ESMP2_OK) return st;
     hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, c.b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
                        h->partial);

@@ -5,4 +5,5 @@
 #include "vv3.hip"
 #include "pcg.hip"
 #include "semican.hip"
+#include "arrow.hip"
 #include "api.hip"

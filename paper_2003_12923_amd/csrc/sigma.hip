@@ -327,22 +327,14 @@ __device__ inline int box_of_g(const Dims& d, int64_t g, int& loc) {
   return k;
 }
 
+// Coupling terms of amplitude (box, batch, v) (occupied indices p0, q0 of the
+// batch): box transfers through a pinned TOP index and doubles <-> L-triples
+// through f_ov.
 template <class T>
-__global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P, const int4* chunks) {
+__device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs<T>& A, const PairTables& P, int box,
+                                                                int batch, int p0, int q0, int v) {
   const Dims& d = A.d;
-  // chunk: (box, batch, first inner index, (p << 16) | q occupied indices of the batch)
-  const int4 ch = chunks[xcd_remap<16>(blockIdx.x, gridDim.x)];
-  const int box = ch.x, batch = ch.y, v = ch.z + (int)threadIdx.x;
-  const int p0 = ch.w >> 16, q0 = ch.w & 0xffff;
   const int no = d.no, nv = d.nv, m1 = nv - 1;
-  int inner;
-  switch (box) {
-    case B_T2: case B_H11: case B_H21: inner = d.npv; break;
-    case B_S2: inner = nv * nv; break;
-    case B_T3: inner = d.npv1; break;
-    default: inner = m1 * m1; break;
-  }
-  if (v >= inner) return;
   Look<T> L{d, A.x, A.S};
   const T* fo = A.fo;     // fo[m*no + i]
   const T* fv = A.fv;     // fv[a*nv + b]
@@ -454,6 +446,26 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P, c
       break;
     }
   }
+  return y;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P, const int4* chunks) {
+  const Dims& d = A.d;
+  // chunk: (box, batch, first inner index, (p << 16) | q occupied indices of the batch)
+  const int4 ch = chunks[xcd_remap<16>(blockIdx.x, gridDim.x)];
+  const int box = ch.x, batch = ch.y, v = ch.z + (int)threadIdx.x;
+  const int p0 = ch.w >> 16, q0 = ch.w & 0xffff;
+  const int nv = d.nv, m1 = nv - 1;
+  int inner;
+  switch (box) {
+    case B_T2: case B_H11: case B_H21: inner = d.npv; break;
+    case B_S2: inner = nv * nv; break;
+    case B_T3: inner = d.npv1; break;
+    default: inner = m1 * m1; break;
+  }
+  if (v >= inner) return;
+  const T y = couple_terms(A, P, box, batch, p0, q0, v);
   A.y[d.off[box] + (int64_t)batch * inner + v] += y;
 }
 
