@@ -351,8 +351,9 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     double* work = AV2 + (size_t)nv * nv;               // m x 2m
     double* vec = work + (size_t)2 * nv * nv;           // rbeta, d, e (3 m <= nv*nv); rs holds 11 nv^2
     size_t lc = sizeof(double) * 2 * (size_t)nv * no;
-    ESMP2_HIP(hipFuncSetAttribute((const void*)k_complement, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
-    hipLaunchKernelGGL(k_complement, dim3(1), dim3(256), lc, s, h->V, nv, no, Q2);
+    ESMP2_HIP(hipFuncSetAttribute((const void*)k_complement_qr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
+    hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), lc, s, (const double*)h->V, nv, no, refl);
+    if (m > 0) hipLaunchKernelGGL(k_complement_apply, dim3(m), dim3(64), 0, s, (const double*)refl, nv, no, Q2);
     GemmArgs g{};
     g.A = h->F + (int64_t)no * n + no; g.B = Q2; g.C = Tt; g.M = nv; g.N = m; g.K = nv;
     g.sAi = n; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
@@ -555,7 +556,7 @@ static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const
   sa.h21_t = take(n2); sa.h21_k = take(n2);
   sa.h22_ut = take(n2); sa.h22_i = take(n2); sa.h22_uk = take(n2);
   const int nside = d.npo1 + 2 * d.npo + 2 * n2;
-  hipLaunchKernelGGL(k_side<T>, dim3(nside), dim3(256), 0, s, sa);
+  hipLaunchKernelGGL(k_side<T>, dim3(nside, (nv + 63) / 64), dim3(256), 0, s, sa);
   GatherArgs<T> ga{};
   ga.d = d; ga.x = x; ga.S = w.S; ga.y = y; ga.fo = w.fo; ga.fv = w.fv; ga.fov = w.fov; ga.side_tr = w.side_tr;
   ga.t3_t = sa.t3_t; ga.t3_p1 = sa.t3_p1; ga.t3_p2 = sa.t3_p2; ga.h11_p1 = sa.h11_p1; ga.h11_p2 = sa.h11_p2;
@@ -643,7 +644,7 @@ static esmp2_status sigma_arrow(esmp2_handle h, const SigmaBufs<T>& w, const T* 
   ArrowArgs<T> aa{ga, w.Fd, w.Fl, w.side_tr, (T*)h->gv};
   const int n2 = (no - 1) * (no - 1);
   const int jobs = 3 * d.npo + no * no + 2 * n2;
-  hipLaunchKernelGGL(k_arrow_side<T>, dim3(jobs), dim3(256), 0, s, aa);
+  hipLaunchKernelGGL(k_arrow_side<T>, dim3(jobs, (d.nv + 63) / 64), dim3(256), 0, s, aa);
   const int* pv = h->pairs;
   PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
   if (h->nchunks > 0)

@@ -54,44 +54,45 @@ __global__ __launch_bounds__(256) void k_arrow_side(ArrowArgs<T> A) {
   else if ((job -= d.npo) < n2) box = B_H21;
   else if ((job -= n2) < d.npo) box = B_H12;
   else { job -= d.npo; box = B_H22; }
-  const int b = threadIdx.x;
-  if (b >= nv) return;
+  // lane -> output column b (64 per workgroup along y), wavefront -> a quarter
+  // of the contracted range 1..nv-1; partial sums meet in LDS
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.y * 64 + lane;
+  const bool col = b < nv;
+  const int lo = 1 + (nv - 1) * wave / 4, hi = 1 + (nv - 1) * (wave + 1) / 4;
   int p, q;
   if (box == B_S2) { p = job / no; q = job % no; }
   else if (box == B_H21 || box == B_H22) { p = job / (no - 1) + 1; q = job % (no - 1) + 1; }
   else tri_pq(job, no, p, q);
   T g = 0, hh = 0;
+  if (col) {
+    switch (box) {
+      case B_T2: for (int c = lo; c < hi; ++c) g += u[c] * L.T2(p, q, c, b); break;
+      case B_S2:
+        for (int c = lo; c < hi; ++c) {
+          g += u[c] * L.St(p, q, c, b);
+          hh += L.St(p, q, b, c) * u[c];
+        }
+        break;
+      case B_H11: for (int c = lo; c < hi; ++c) g += u[c] * L.H11(p, q, c, b); break;
+      case B_H21: for (int c = lo; c < hi; ++c) g += u[c] * L.H21(p, q, c, b); break;
+      case B_H12: if (b >= 1) for (int c = lo; c < hi; ++c) g += u[c] * L.H12(p, q, c, b); break;
+      default: if (b >= 1) for (int c = lo; c < hi; ++c) g += u[c] * L.H22(p, q, c, b); break;
+    }
+  }
+  __shared__ T part[2][4][64];
+  part[0][wave][lane] = g; part[1][wave][lane] = hh;
+  __syncthreads();
+  if (wave != 0 || !col) return;
+  g = part[0][0][lane] + part[0][1][lane] + part[0][2][lane] + part[0][3][lane];
+  hh = part[1][0][lane] + part[1][1][lane] + part[1][2][lane] + part[1][3][lane];
   switch (box) {
-    case B_T2:
-      for (int c = 1; c < nv; ++c) g += u[c] * L.T2(p, q, c, b);
-      A.gv[off[0] + (int64_t)job * nv + b] = g;
-      break;
-    case B_S2:
-      for (int c = 1; c < nv; ++c) {
-        g += u[c] * L.St(p, q, c, b);
-        hh += L.St(p, q, b, c) * u[c];
-      }
-      A.gv[off[1] + (int64_t)job * nv + b] = g;
-      A.gv[off[2] + (int64_t)job * nv + b] = hh;
-      break;
-    case B_H11:
-      for (int c = 1; c < nv; ++c) g += u[c] * L.H11(p, q, c, b);
-      A.gv[off[3] + (int64_t)job * nv + b] = g;
-      break;
-    case B_H21:
-      for (int c = 1; c < nv; ++c) g += u[c] * L.H21(p, q, c, b);
-      A.gv[off[4] + (int64_t)job * nv + b] = g;
-      break;
-    case B_H12:   // transfer row of the embedded product (b >= 1), into H1P1
-      if (b >= 1)
-        for (int c = 1; c < nv; ++c) g += u[c] * L.H12(p, q, c, b);
-      A.tr[(int64_t)job * nv + b] = g;
-      break;
-    default:      // H2P2 transfer row, into H2P1
-      if (b >= 1)
-        for (int c = 1; c < nv; ++c) g += u[c] * L.H22(p, q, c, b);
-      A.tr[((int64_t)d.npo + job) * nv + b] = g;
-      break;
+    case B_T2: A.gv[off[0] + (int64_t)job * nv + b] = g; break;
+    case B_S2: A.gv[off[1] + (int64_t)job * nv + b] = g; A.gv[off[2] + (int64_t)job * nv + b] = hh; break;
+    case B_H11: A.gv[off[3] + (int64_t)job * nv + b] = g; break;
+    case B_H21: A.gv[off[4] + (int64_t)job * nv + b] = g; break;
+    case B_H12: A.tr[(int64_t)job * nv + b] = g; break;              // transfer row into H1P1
+    default: A.tr[((int64_t)d.npo + job) * nv + b] = g; break;      // transfer row into H2P1
   }
 }
 

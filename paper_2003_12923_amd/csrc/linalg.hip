@@ -214,8 +214,9 @@ namespace esmp2 {
 
 // ---------------------------------------------------------------------------
 // Semicanonical AVOs, tridiagonal route.
-//  1. k_complement: Householder QR of the TOP virtuals V (nv x no); Q2 = the
-//     last m = nv - no columns of H_0 ... H_{no-1} (orthonormal complement).
+//  1. k_complement_qr / k_complement_apply: Householder QR of the TOP virtuals
+//     V (nv x no); Q2 = the last m = nv - no columns of H_0 ... H_{no-1}
+//     (orthonormal complement), one wavefront per column.
 //  2. F_avo = Q2^T F_vv Q2 (GEMMs).
 //  3. k_tridiag: Householder tridiagonalisation of F_avo (packed in LDS),
 //     T = P^T F_avo P, P = G_0 ... G_{m-3}.
@@ -226,8 +227,10 @@ namespace esmp2 {
 //  AVO = Q2 Y, followed by a first-order Loewdin step (caller).
 // ---------------------------------------------------------------------------
 
-// Single workgroup (256 threads).  Vin: nv x no row-major.  Q2: nv x m row-major.
-__global__ __launch_bounds__(256) void k_complement(const double* Vin, int nv, int no, double* Q2) {
+// Single workgroup (256 threads).  Vin: nv x no row-major.  Householder QR of
+// Vin; reflector j (entries j..nv-1, zero above) into refl[j*nv + i], its
+// coefficient into refl[no*nv + j].
+__global__ __launch_bounds__(256) void k_complement_qr(const double* Vin, int nv, int no, double* refl) {
   extern __shared__ double sm[];
   double* W = sm;                    // nv x no working copy, column j reduced in place
   double* vv = W + nv * no;          // reflectors: no x nv (row j = reflector j, entries j..nv-1)
@@ -261,18 +264,38 @@ __global__ __launch_bounds__(256) void k_complement(const double* Vin, int nv, i
     }
     __syncthreads();
   }
-  // Q2 column c = H_0 H_1 ... H_{no-1} e_{no+c}; one wave per column
-  const int m = nv - no;
-  for (int c = wave; c < m; c += blockDim.x >> 6) {
-    double* q = Q2;   // column c, rows 0..nv-1, stride m
-    for (int i = l; i < nv; i += 64) q[i * m + c] = (i == no + c) ? 1.0 : 0.0;
-    for (int j = no - 1; j >= 0; --j) {
-      // each lane owns rows l, l+64, ...: no cross-lane dependence through memory
-      double t = 0.0;
-      for (int i = l; i < nv; i += 64) if (i >= j) t += vv[j * nv + i] * q[i * m + c];
-      t = wave_sum(t) * beta[j];
-      for (int i = l; i < nv; i += 64) if (i >= j) q[i * m + c] -= t * vv[j * nv + i];
+  for (int e = tid; e < no * nv; e += blockDim.x) refl[e] = vv[e];
+  for (int j = tid; j < no; j += blockDim.x) refl[no * nv + j] = beta[j];
+}
+
+// Q2 (nv x m, m = nv - no) column c = H_0 H_1 ... H_{no-1} e_{no+c}: the
+// orthonormal complement of the TOP virtuals.  One wavefront per column; lane
+// l owns rows l, l + 64, l + 128 (nv <= 192).
+__global__ __launch_bounds__(64) void k_complement_apply(const double* refl, int nv, int no, double* Q2) {
+  const int c = blockIdx.x, l = threadIdx.x, m = nv - no;
+  const double* beta = refl + no * nv;
+  double q[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) q[k] = (l + 64 * k == no + c) ? 1.0 : 0.0;
+  for (int j = no - 1; j >= 0; --j) {
+    const double* v = refl + j * nv;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = l + 64 * k;
+      if (i < nv && i >= j) t += v[i] * q[k];
     }
+    t = wave_sum(t) * beta[j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int i = l + 64 * k;
+      if (i < nv && i >= j) q[k] -= t * v[i];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int i = l + 64 * k;
+    if (i < nv) Q2[i * m + c] = q[k];
   }
 }
 

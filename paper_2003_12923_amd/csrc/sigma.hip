@@ -252,62 +252,67 @@ __global__ __launch_bounds__(256) void k_side(SideArgs<T> A) {
   else if (job < d.npo1 + 2 * d.npo) { box = B_H12; batch = job - d.npo1 - d.npo; }
   else if (job < d.npo1 + 2 * d.npo + (no - 1) * (no - 1)) { box = B_H21; batch = job - d.npo1 - 2 * d.npo; }
   else { box = B_H22; batch = job - d.npo1 - 2 * d.npo - (no - 1) * (no - 1); }
-  const int tid = threadIdx.x;
+  // lane -> output column c (64 per workgroup along y), wavefront -> a quarter
+  // of the contracted range; partial sums meet in LDS
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.y * 64 + lane;
+  const bool col = c < nv;
+  const int b0 = (box == B_H11 || box == B_H21) ? 0 : 1;
+  const int lo = b0 + (nv - b0) * wave / 4, hi = b0 + (nv - b0) * (wave + 1) / 4;
+  T r0 = 0, r1 = 0, r2 = 0;
+  int p = 0, q = 0;
   if (box == B_T3) {
-    int j, k; tri_pq(batch, no - 1, j, k); ++j; ++k;
-    for (int c = tid; c < nv; c += blockDim.x) {
-      T vt = 0, v1 = 0, v2 = 0;
-      if (c >= 1)
-        for (int b = 1; b < nv; ++b) {
-          T xv = L.T3(j, k, b, c);
-          vt += fov[b] * xv; v1 += fov[j * nv + b] * xv; v2 += fov[k * nv + b] * xv;
-        }
-      A.t3_t[batch * nv + c] = vt; A.t3_p1[batch * nv + c] = v1; A.t3_p2[batch * nv + c] = v2;
-    }
+    tri_pq(batch, no - 1, p, q); ++p; ++q;
+    if (col && c >= 1)
+      for (int x = lo; x < hi; ++x) {
+        const T xv = L.T3(p, q, x, c);
+        r0 += fov[x] * xv; r1 += fov[p * nv + x] * xv; r2 += fov[q * nv + x] * xv;
+      }
   } else if (box == B_H11) {
-    int j, k; tri_pq(batch, no, j, k);
-    for (int c = tid; c < nv; c += blockDim.x) {
-      T v1 = 0, v2 = 0;
-      for (int b = 0; b < nv; ++b) {
-        T xv = L.H11(j, k, b, c);
-        v1 += fov[j * nv + b] * xv; v2 += fov[k * nv + b] * xv;
+    tri_pq(batch, no, p, q);
+    if (col)
+      for (int x = lo; x < hi; ++x) {
+        const T xv = L.H11(p, q, x, c);
+        r0 += fov[p * nv + x] * xv; r1 += fov[q * nv + x] * xv;
       }
-      A.h11_p1[batch * nv + c] = v1; A.h11_p2[batch * nv + c] = v2;
-    }
   } else if (box == B_H12) {
-    int j, k; tri_pq(batch, no, j, k);
-    for (int c = tid; c < nv; c += blockDim.x) {
-      T vt = 0, u1 = 0, u2 = 0;
-      if (c >= 1)
-        for (int x = 1; x < nv; ++x) {
-          vt += fov[x] * L.H12(j, k, x, c);             // sum_a f_{a t} X[a][c]
-          T xr = L.H12(j, k, c, x);                // row c (= a), column x
-          u1 += xr * fov[j * nv + x]; u2 += xr * fov[k * nv + x];
-        }
-      A.h12_t[batch * nv + c] = vt; A.h12_u1[batch * nv + c] = u1; A.h12_u2[batch * nv + c] = u2;
-    }
-  } else if (box == B_H21) {
-    int i = batch / (no - 1) + 1, k = batch % (no - 1) + 1;
-    for (int c = tid; c < nv; c += blockDim.x) {
-      T vt = 0, vk = 0;
-      for (int b = 0; b < nv; ++b) {
-        T xv = L.H21(i, k, b, c);
-        vt += fov[b] * xv; vk += fov[k * nv + b] * xv;
+    tri_pq(batch, no, p, q);
+    if (col && c >= 1)
+      for (int x = lo; x < hi; ++x) {
+        r0 += fov[x] * L.H12(p, q, x, c);             // sum_a f_{a t} X[a][c]
+        const T xr = L.H12(p, q, c, x);                // row c (= a), column x
+        r1 += xr * fov[p * nv + x]; r2 += xr * fov[q * nv + x];
       }
-      A.h21_t[batch * nv + c] = vt; A.h21_k[batch * nv + c] = vk;
-    }
+  } else if (box == B_H21) {
+    p = batch / (no - 1) + 1; q = batch % (no - 1) + 1;
+    if (col)
+      for (int x = lo; x < hi; ++x) {
+        const T xv = L.H21(p, q, x, c);
+        r0 += fov[x] * xv; r1 += fov[q * nv + x] * xv;
+      }
   } else {
-    int i = batch / (no - 1) + 1, k = batch % (no - 1) + 1;
-    for (int c = tid; c < nv; c += blockDim.x) {
-      T ut = 0, vi = 0, uk = 0;
-      if (c >= 1)
-        for (int x = 1; x < nv; ++x) {
-          T xr = L.H22(i, k, c, x);                // row c (= a), column x
-          ut += xr * fov[x]; uk += xr * fov[k * nv + x];
-          vi += fov[i * nv + x] * L.H22(i, k, x, c);    // sum_a f_{a i} X[a][c]
-        }
-      A.h22_ut[batch * nv + c] = ut; A.h22_i[batch * nv + c] = vi; A.h22_uk[batch * nv + c] = uk;
-    }
+    p = batch / (no - 1) + 1; q = batch % (no - 1) + 1;
+    if (col && c >= 1)
+      for (int x = lo; x < hi; ++x) {
+        const T xr = L.H22(p, q, c, x);                // row c (= a), column x
+        r0 += xr * fov[x]; r2 += xr * fov[q * nv + x];
+        r1 += fov[p * nv + x] * L.H22(p, q, x, c);     // sum_a f_{a i} X[a][c]
+      }
+  }
+  __shared__ T part[3][4][64];
+  part[0][wave][lane] = r0; part[1][wave][lane] = r1; part[2][wave][lane] = r2;
+  __syncthreads();
+  if (wave != 0 || !col) return;
+  T s[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = part[k][0][lane] + part[k][1][lane] + part[k][2][lane] + part[k][3][lane];
+  const int64_t o = (int64_t)batch * nv + c;
+  switch (box) {
+    case B_T3: A.t3_t[o] = s[0]; A.t3_p1[o] = s[1]; A.t3_p2[o] = s[2]; break;
+    case B_H11: A.h11_p1[o] = s[0]; A.h11_p2[o] = s[1]; break;
+    case B_H12: A.h12_t[o] = s[0]; A.h12_u1[o] = s[1]; A.h12_u2[o] = s[2]; break;
+    case B_H21: A.h21_t[o] = s[0]; A.h21_k[o] = s[1]; break;
+    default: A.h22_ut[o] = s[0]; A.h22_i[o] = s[1]; A.h22_uk[o] = s[2]; break;
   }
 }
 
