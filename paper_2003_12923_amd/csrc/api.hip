@@ -351,6 +351,7 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     double* work = AV2 + (size_t)nv * nv;               // m x 2m
     double* vec = work + (size_t)2 * nv * nv;           // rbeta, d, e (3 m <= nv*nv); rs holds 11 nv^2
     size_t lc = sizeof(double) * 2 * (size_t)nv * no;
+    if (m > 0) {   // n_vir == n_occ: no AVOs
     ESMP2_HIP(hipFuncSetAttribute((const void*)k_complement_qr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
     hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), lc, s, (const double*)h->V, nv, no, refl);
     if (m > 0) hipLaunchKernelGGL(k_complement_apply, dim3(m), dim3(64), 0, s, (const double*)refl, nv, no, Q2);
@@ -383,6 +384,7 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     g.A = AV; g.B = Fa; g.C = AV2; g.M = nv; g.N = m; g.K = m;
     g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = -0.5; g.beta = 1.0;
     ESMP2_HIP(gemm(s, 1, g));
+    }
     hipLaunchKernelGGL(k_assemble_r2, dim3(1), dim3(1024), 0, s, h->U, h->V, AV2, h->evals, no, nv, h->R, h->avo);
   }
   // F~ = R^T F R

@@ -157,10 +157,13 @@ __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx<T>& c
 #pragma unroll
           for (int j = 0; j < Rc::NC; ++j)
             if (!Rc::TRI || Rc::C0 + j >= Rc::R0 + i) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
+        // staging of later chunks placed between the matrix-core groups, so that
+        // its loads and LDS stores issue while the matrix cores are busy
+        if (ks == 0 && q + 1 < NCH) stash(buf ^ 1);        // chunk q+1 (loaded one iteration ago)
+        if (ks == 1 && q + 2 < NCH) fetch((q + 2) * 16);
       }
-    }
-    if (q + 1 < NCH) {
-      stash(buf ^ 1);                       // chunk q+1 (loaded during the previous iteration)
+    } else if (q + 1 < NCH) {
+      stash(buf ^ 1);
       if (q + 2 < NCH) fetch((q + 2) * 16);
     }
     __syncthreads();
