@@ -73,7 +73,7 @@ struct esmp2_handle_ {
   double omega = 0, kappa = 0, e0 = 0, e2s = 0;
   int svd_sweeps = 0;
   // rhs
-  double *fphi, *X, *Vint, *Mint, *b, *dinv, *blockmin, *partial, *sc;
+  double *fphi, *fphi_part, *X, *Vint, *Mint, *b, *dinv, *blockmin, *partial, *sc;
   bool have_rhs = false;
   // sigma scratch
   double *S, *side, *side_tr;
@@ -93,6 +93,12 @@ struct esmp2_handle_ {
   // pinned-semicanonical basis: rotations (t and t' fixed), operator blocks, rotated rhs,
   // Jacobi diagonal, dense scratch of the amplitude rotation
   bool have_sc = false;
+  // side stream: the semicanonical eigenproblems run there while the main
+  // stream builds the right-hand side (default priority, non-blocking)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fock_ready = nullptr, ev_sc_eig = nullptr;
+  bool sc_pending = false;       // eigenproblems queued on the side stream, not yet joined
+  bool sc_eig = false;           // To, Tv hold the rotation of the current TOP basis
   double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *dinv_sc, *b_sc;
   float *Fd32_sc, *Fl32_sc, *fo32_sc, *fv32_sc, *fov32_sc, *dinv32_sc;
   double *dense0, *dense1;
@@ -125,11 +131,15 @@ static void drain_events(esmp2_handle h) {
 }
 
 static void release(esmp2_handle h) {
+  if (h->aux) (void)hipStreamSynchronize(h->aux);      // side-stream work may still read these buffers
+  if (!h->allocs.empty()) (void)hipStreamSynchronize(h->stream);
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   h->state = 0;
   h->have_rhs = false;
   h->have_sc = false;
+  h->sc_pending = false;
+  h->sc_eig = false;
 }
 
 template <class T>
@@ -144,6 +154,59 @@ static bool dalloc(esmp2_handle h, T** p, size_t count) {
 
 static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+// Eigenpairs of a symmetric m x m matrix A (device, contiguous) by the
+// tridiagonal route of the AVO step: evals ascending, Y[i*m + k] = component i
+// of eigenvector k.  Scratch ws: 4 m^2 + 3 m doubles.
+static esmp2_status sym_eig(esmp2_handle h, hipStream_t s, const double* A, int m, double* evals, double* Y,
+                            double* ws) {
+  if (m <= 0) return ESMP2_OK;
+  double* refl = ws;
+  double* Yt = refl + (size_t)m * m;
+  double* work = Yt + (size_t)m * m;        // 2 m^2
+  double* vec = work + (size_t)2 * m * m;   // rbeta, d, e
+  if (m == 1) {
+    hipLaunchKernelGGL(k_eig1, dim3(1), dim3(1), 0, s, A, evals, Y);
+    return ESMP2_OK;
+  }
+  size_t lt = sizeof(double) * (size_t)m * (m + 1) / 2;
+  ESMP2_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lt));
+  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lt, s, A, m, refl, vec, vec + m, vec + 2 * m);
+  hipLaunchKernelGGL(k_tri_eig, dim3(m), dim3(64), 0, s, vec + m, vec + 2 * m, m, evals, Yt, work);
+  hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(64), 0, s, evals, m, Yt);
+  hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), sizeof(double) * m, s, refl, vec, m, Yt, Y);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+
+// The two eigenproblems of the pinned-semicanonical rotation (F~_oo[1:,1:],
+// F~_vv[1:,1:]), queued on the side stream as soon as F~ exists; semican_setup
+// joins them.  Scratch: rs.
+static esmp2_status launch_semican_eig(esmp2_handle h) {
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv, n = d.n;
+  hipStream_t s = h->aux;
+  ESMP2_HIP(hipEventRecord(h->ev_fock_ready, h->stream));
+  ESMP2_HIP(hipStreamWaitEvent(s, h->ev_fock_ready, 0));
+  double* A = h->rs;                                   // (nv-1)^2 block copy
+  double* evals = A + (size_t)nv * nv;
+  double* Y = evals + nv;
+  double* ws = Y + (size_t)nv * nv;                    // 4 nv^2 + 3 nv  (rs holds 11 nv^2)
+  hipLaunchKernelGGL(k_block_copy, dim3(64), dim3(256), 0, s, (const double*)h->Ft, (int64_t)n + 1, n, no - 1, A);
+  esmp2_status st = sym_eig(h, s, A, no - 1, evals, Y, ws);
+  if (st != ESMP2_OK) return st;
+  hipLaunchKernelGGL(k_embed_rotation, dim3(nblk(no * no)), dim3(256), 0, s, (const double*)Y, no, h->To);
+  hipLaunchKernelGGL(k_block_copy, dim3(256), dim3(256), 0, s, (const double*)h->Ft, (int64_t)(no + 1) * n + no + 1,
+                     n, nv - 1, A);
+  st = sym_eig(h, s, A, nv - 1, evals, Y, ws);
+  if (st != ESMP2_OK) return st;
+  hipLaunchKernelGGL(k_embed_rotation, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, (const double*)Y, nv, h->Tv);
+  ESMP2_HIP(hipGetLastError());
+  ESMP2_HIP(hipEventRecord(h->ev_sc_eig, s));
+  h->sc_pending = true;
+  return ESMP2_OK;
+}
+
 extern "C" {
 
 esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
@@ -155,6 +218,15 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
   if (!h) return ESMP2_OOM;
   h->device = device;
   h->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fock_ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_sc_eig, hipEventDisableTiming) != hipSuccess) {
+    if (h->aux) (void)hipStreamDestroy(h->aux);
+    if (h->ev_fock_ready) (void)hipEventDestroy(h->ev_fock_ready);
+    if (h->ev_sc_eig) (void)hipEventDestroy(h->ev_sc_eig);
+    delete h;
+    return ESMP2_HIP_ERROR;
+  }
   *out = h;
   return ESMP2_OK;
 }
@@ -163,8 +235,12 @@ esmp2_status esmp2_destroy(esmp2_handle h) {
   if (!h) return ESMP2_OK;
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
+  (void)hipStreamSynchronize(h->aux);
   drain_events(h);
   release(h);
+  (void)hipStreamDestroy(h->aux);
+  (void)hipEventDestroy(h->ev_fock_ready);
+  (void)hipEventDestroy(h->ev_sc_eig);
   delete h;
   return ESMP2_OK;
 }
@@ -225,6 +301,7 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
             dalloc(h, &h->fv, (size_t)nv * nv) && dalloc(h, &h->fov, (size_t)no * nv) && dalloc(h, &h->eo, no) &&
             dalloc(h, &h->ev, nv) && dalloc(h, &h->Fd, (size_t)mv * mv) && dalloc(h, &h->Fl, (size_t)mv * mv) &&
             dalloc(h, &h->sc_rot, 8) && dalloc(h, &h->fphi, (size_t)no * nv) &&
+            dalloc(h, &h->fphi_part, (size_t)FPHI_QCHUNKS * no * nv + na) &&
             dalloc(h, &h->X, (size_t)na * no * nv) && dalloc(h, &h->Vint, (size_t)no * nv * no * nv) &&
             dalloc(h, &h->Mint, (size_t)no * nv * no * nv) && dalloc(h, &h->b, namp) &&
             dalloc(h, &h->dinv, namp) && dalloc(h, &h->blockmin, nblk(namp)) &&
@@ -332,6 +409,12 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, n = d.n, na = d.naux, mv = d.mv;
   hipStream_t s = h->stream;
+  // side-stream work of a previous rotation shares the scratch: order after it
+  if (h->sc_pending) {
+    ESMP2_HIP(hipStreamWaitEvent(s, h->ev_sc_eig, 0));
+    h->sc_pending = false;
+  }
+  h->sc_eig = false;
   // SVD of C
   size_t lds = sizeof(double) * (no * nv + no * no);
   ESMP2_HIP(hipFuncSetAttribute((const void*)k_svd_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -404,6 +487,10 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   hipLaunchKernelGGL(k_to_f32, dim3(nblk(no * no)), dim3(256), 0, s, h->fo, h->fo32, (int64_t)no * no);
   hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, h->fv, h->fv32, (int64_t)nv * nv);
   hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)no * nv)), dim3(256), 0, s, h->fov, h->fov32, (int64_t)no * nv);
+  {
+    esmp2_status st = launch_semican_eig(h);
+    if (st != ESMP2_OK) return st;
+  }
   // B~ blocks: Bov = U^T B_ov W, Bvt = W^T B_vv W[:, :no], Boo = U^T B_oo U
   const int64_t nn = (int64_t)n * n;
   // T[Q] (no x nv) = B[Q][occ, vir] W
@@ -467,8 +554,14 @@ static esmp2_status build_rhs(esmp2_handle h) {
   const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
   const int64_t namp = d.off[7];
   hipStream_t s = h->stream;
-  hipLaunchKernelGGL(k_fphi, dim3(nov), dim3(64), 0, s, h->Ft, h->Bov, h->Bvt, h->Boo, h->lam, no, nv, na,
-                     h->fphi);
+  double* dq = h->fphi_part + (size_t)FPHI_QCHUNKS * nov;
+  hipLaunchKernelGGL(k_fphi_dq, dim3(nblk(na)), dim3(256), 0, s, (const double*)h->Bvt, (const double*)h->Boo,
+                     (const double*)h->lam, no, nv, na, dq);
+  hipLaunchKernelGGL(k_fphi_part, dim3(FPHI_QCHUNKS, no), dim3(256), 0, s, (const double*)h->Bov,
+                     (const double*)h->Bvt, (const double*)h->Boo, (const double*)h->lam, (const double*)dq, no, nv,
+                     na, h->fphi_part);
+  hipLaunchKernelGGL(k_fphi_sum, dim3(nblk(nov)), dim3(256), 0, s, (const double*)h->Ft,
+                     (const double*)h->fphi_part, no, nv, FPHI_QCHUNKS, h->fphi);
   hipLaunchKernelGGL(k_make_x, dim3(nblk((int64_t)na * nov)), dim3(256), 0, s, h->Bvt, h->Boo, h->lam, no, nv, na,
                      h->X);
   GemmArgs g{};
@@ -485,14 +578,19 @@ static esmp2_status build_rhs(esmp2_handle h) {
   hipLaunchKernelGGL(k_to_f32, dim3(PCG_BLOCKS), dim3(256), 0, s, (const double*)h->dinv, h->dinv32, namp);
   hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
   // E2_S
-  E2sArgs ea{d, h->Vint, h->lam, h->eo, h->ev, h->omega, h->partial};
-  const int NB = 1024;
-  hipLaunchKernelGGL(k_e2s_same, dim3(NB), dim3(256), 0, s, ea);
-  ea.partial = h->partial + NB;
-  hipLaunchKernelGGL(k_e2s_mixed_a, dim3(NB), dim3(256), 0, s, ea);
-  ea.partial = h->partial + 2 * NB;
-  hipLaunchKernelGGL(k_e2s_mixed_b, dim3(NB), dim3(256), 0, s, ea);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, h->partial, 3 * NB, h->sc + SC_TMP + 1, -1.0);
+  // grids of at most 1024 blocks each; partials laid out one kernel after the other
+  const int* pv = h->pairs;
+  E2sArgs ea{d, h->Vint, h->lam, h->eo, h->ev, h->omega, h->partial, pv, pv + d.npv, pv + d.npv + d.npv1,
+             pv + d.npv + d.npv1 + d.npo};
+  const int y1 = std::max(1, no - 1), x1 = std::max(1, 1024 / y1);
+  const int y3 = std::min(1024, no * nv), x3 = std::max(1, 1024 / y3);
+  const int nb1 = x1 * y1, nb3 = x3 * y3;
+  hipLaunchKernelGGL(k_e2s_same, dim3(x1, y1), dim3(256), 0, s, ea);
+  ea.partial = h->partial + nb1;
+  hipLaunchKernelGGL(k_e2s_mixed_a, dim3(x1, y1), dim3(256), 0, s, ea);
+  ea.partial = h->partial + 2 * nb1;
+  hipLaunchKernelGGL(k_e2s_mixed_b, dim3(x3, y3), dim3(256), 0, s, ea);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, h->partial, 2 * nb1 + nb3, h->sc + SC_TMP + 1, -1.0);
   double tmp[2];
   ESMP2_HIP(hipMemcpyAsync(tmp, h->sc + SC_TMP, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
@@ -661,33 +759,6 @@ static esmp2_status sigma32(esmp2_handle h, const float* x, float* y) { return s
 // ---------------------------------------------------------------------------
 // pinned-semicanonical basis
 // ---------------------------------------------------------------------------
-// Eigenpairs of a symmetric m x m matrix A (device, contiguous) by the
-// tridiagonal route of the AVO step: evals ascending, Y[i*m + k] = component i
-// of eigenvector k.  Scratch ws: 4 m^2 + 3 m doubles.
-static esmp2_status sym_eig(esmp2_handle h, const double* A, int m, double* evals, double* Y, double* ws) {
-  hipStream_t s = h->stream;
-  if (m <= 0) return ESMP2_OK;
-  double* refl = ws;
-  double* Yt = refl + (size_t)m * m;
-  double* work = Yt + (size_t)m * m;        // 2 m^2
-  double* vec = work + (size_t)2 * m * m;   // rbeta, d, e
-  if (m == 1) {
-    ESMP2_HIP(hipMemcpyAsync(evals, A, sizeof(double), hipMemcpyDeviceToDevice, s));
-    const double one = 1.0;
-    ESMP2_HIP(hipMemcpyAsync(Y, &one, sizeof(double), hipMemcpyHostToDevice, s));
-    ESMP2_HIP(hipStreamSynchronize(s));
-    return ESMP2_OK;
-  }
-  size_t lt = sizeof(double) * (size_t)m * (m + 1) / 2;
-  ESMP2_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lt));
-  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lt, s, A, m, refl, vec, vec + m, vec + 2 * m);
-  hipLaunchKernelGGL(k_tri_eig, dim3(m), dim3(64), 0, s, vec + m, vec + 2 * m, m, evals, Yt, work);
-  hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(64), 0, s, evals, m, Yt);
-  hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), sizeof(double) * m, s, refl, vec, m, Yt, Y);
-  ESMP2_HIP(hipGetLastError());
-  return ESMP2_OK;
-}
-
 // Contract index `which` (0: P, 1: Q, 2: A, 3: B) of dense[P][Q][A][B]
 // (ranges ro, ro, rv, rv) with G: out[..c'..] = sum_c G(c, c') in[..c..],
 // G(c, c') = Gm[c*sr + c'*sc].
@@ -753,21 +824,14 @@ static esmp2_status semican_setup(esmp2_handle h) {
   const int no = d.no, nv = d.nv, n = d.n, mv = d.mv;
   const int64_t namp = d.off[7];
   hipStream_t s = h->stream;
-  double* A = h->rs;                                   // (nv-1)^2 block copy
-  double* evals = A + (size_t)nv * nv;
-  double* Y = evals + nv;
-  double* ws = Y + (size_t)nv * nv;                    // 4 nv^2 + 3 nv  (rs holds 11 nv^2)
-  // occupied block (t fixed)
-  hipLaunchKernelGGL(k_block_copy, dim3(64), dim3(256), 0, s, (const double*)h->Ft, (int64_t)n + 1, n, no - 1, A);
-  esmp2_status st = sym_eig(h, A, no - 1, evals, Y, ws);
-  if (st != ESMP2_OK) return st;
-  hipLaunchKernelGGL(k_embed_rotation, dim3(nblk(no * no)), dim3(256), 0, s, (const double*)Y, no, h->To);
-  // virtual block (t' fixed)
-  hipLaunchKernelGGL(k_block_copy, dim3(256), dim3(256), 0, s, (const double*)h->Ft, (int64_t)(no + 1) * n + no + 1,
-                     n, nv - 1, A);
-  st = sym_eig(h, A, nv - 1, evals, Y, ws);
-  if (st != ESMP2_OK) return st;
-  hipLaunchKernelGGL(k_embed_rotation, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, (const double*)Y, nv, h->Tv);
+  // the rotation's eigenproblems, queued on the side stream by esmp2_rotate_top
+  if (h->sc_pending) {
+    ESMP2_HIP(hipStreamWaitEvent(s, h->ev_sc_eig, 0));
+    h->sc_pending = false;
+    h->sc_eig = true;
+  }
+  if (!h->sc_eig) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
+  esmp2_status st;
   // Fh = T^T F~ T
   hipLaunchKernelGGL(k_blkdiag, dim3(nblk((int64_t)n * n)), dim3(256), 0, s, (const double*)h->To,
                      (const double*)h->Tv, no, nv, h->Tsc);

@@ -16,29 +16,53 @@
 namespace esmp2 {
 
 // f^Phi_ov = F~_ov - G[gamma - gamma_Phi]_ov, G[g]_pq = sum_rs g_rs((pq|rs) - (ps|rq)/2),
-// gamma - gamma_Phi = diag(-lam_l^2 on l, +lam_l^2 on l').  One wavefront per (i, a),
-// lanes over the auxiliary index.
-__global__ __launch_bounds__(64) void k_fphi(const double* Ft, const double* Bov, const double* Bvt,
-                                             const double* Boo, const double* lam, int no, int nv, int naux,
-                                             double* fphi) {
-  const int e = blockIdx.x, l = threadIdx.x;
-  const int i = e / nv, a = e % nv, n = no + nv;
-  double J = 0, Kv = 0, Ko = 0;
-  for (int Q = l; Q < naux; Q += 64) {
+// gamma - gamma_Phi = diag(-lam_l^2 on l, +lam_l^2 on l'):
+//   G_ia = sum_Q [ dq_Q Bov_Q[i][a] - (1/2) sum_k w_k Bov_Q[i][k] Bvt_Q[a][k]
+//                  + (1/2) sum_k w_k Boo_Q[i][k] Bov_Q[k][a] ],
+//   dq_Q = sum_k w_k (Bvt_Q[k][k] - Boo_Q[k][k]),  w_k = lam_k^2.
+constexpr int FPHI_QCHUNKS = 16;
+
+__global__ void k_fphi_dq(const double* Bvt, const double* Boo, const double* lam, int no, int nv, int naux,
+                          double* dq) {
+  const int Q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (Q >= naux) return;
+  const double* bvt = Bvt + (int64_t)Q * nv * no;
+  const double* boo = Boo + (int64_t)Q * no * no;
+  double t = 0.0;
+  for (int k = 0; k < no; ++k) t += lam[k] * lam[k] * (bvt[k * no + k] - boo[k * no + k]);
+  dq[Q] = t;
+}
+
+// partial G_ia over one chunk of the auxiliary index: grid (FPHI_QCHUNKS, no), thread = a
+__global__ __launch_bounds__(256) void k_fphi_part(const double* Bov, const double* Bvt, const double* Boo,
+                                                   const double* lam, const double* dq, int no, int nv, int naux,
+                                                   double* part) {
+  const int i = blockIdx.y, a = threadIdx.x;
+  if (a >= nv) return;
+  const int q0 = (int)((int64_t)naux * blockIdx.x / gridDim.x), q1 = (int)((int64_t)naux * (blockIdx.x + 1) / gridDim.x);
+  double g = 0.0;
+  for (int Q = q0; Q < q1; ++Q) {
     const double* bov = Bov + (int64_t)Q * no * nv;
     const double* bvt = Bvt + (int64_t)Q * nv * no;
     const double* boo = Boo + (int64_t)Q * no * no;
-    double dq = 0;
+    double kv = 0.0, ko = 0.0;
     for (int k = 0; k < no; ++k) {
-      double w = lam[k] * lam[k];
-      dq += w * (bvt[k * no + k] - boo[k * no + k]);
-      Kv += w * bov[i * nv + k] * bvt[a * no + k];
-      Ko += w * boo[i * no + k] * bov[k * nv + a];
+      const double w = lam[k] * lam[k];
+      kv += w * bov[i * nv + k] * bvt[a * no + k];
+      ko += w * boo[i * no + k] * bov[k * nv + a];
     }
-    J += dq * bov[i * nv + a];
+    g += dq[Q] * bov[i * nv + a] - 0.5 * kv + 0.5 * ko;
   }
-  double t = wave_sum(J - 0.5 * Kv + 0.5 * Ko);
-  if (l == 0) fphi[e] = Ft[i * n + no + a] - t;
+  part[((int64_t)blockIdx.x * no + i) * nv + a] = g;
+}
+
+__global__ void k_fphi_sum(const double* Ft, const double* part, int no, int nv, int nchunks, double* fphi) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= no * nv) return;
+  const int i = e / nv, a = e % nv, n = no + nv;
+  double g = 0.0;
+  for (int c = 0; c < nchunks; ++c) g += part[(int64_t)c * no * nv + e];
+  fphi[e] = Ft[i * n + no + a] - g;
 }
 
 // X[Q][(i,a)] = c_i Bvt[Q][a][i] - c_a Boo[Q][a][i]  (second term only for a < n_occ)
@@ -257,7 +281,8 @@ struct E2sArgs {
   Dims d;
   const double* V; const double* lam; const double* eo; const double* ev;
   double omega;
-  double* partial;      // one per block
+  double* partial;      // one per block (blockIdx.y * gridDim.x + blockIdx.x)
+  const int *pv, *pv1, *po, *po1;   // pair tables ((p << 16) | q, p < q) of nv, nv-1, no, no-1
 };
 
 __device__ inline void sort3(int& x, int& y, int& z) {
@@ -266,41 +291,39 @@ __device__ inline void sort3(int& x, int& y, int& z) {
   if (x > y) { int t = x; x = y; y = t; }
 }
 
+// grid (x, y): y walks the smallest TOP l >= 1, x the (j<k, b<c) pairs
+// excluding l (grid-stride in x).
 __global__ __launch_bounds__(256) void k_e2s_same(E2sArgs A) {
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv, nov = no * nv;
-  const int64_t per_l = (int64_t)d.npo1 * d.npv1;
-  const int64_t total = per_l * (no - 1);
+  const int per_l = d.npo1 * d.npv1;
   const double s2 = 0.70710678118654752440;
   double acc = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int l = (int)(g / per_l) + 1;
-    int64_t r = g % per_l;
-    int jr, kr, br, cr;
-    tri_pq((int)(r / d.npv1), no - 1, jr, kr);
-    tri_pq((int)(r % d.npv1), nv - 1, br, cr);
-    int j = jr + (jr >= l), k = kr + (kr >= l), b = br + (br >= l), c = cr + (cr >= l);
-    if ((j < l && (j == b || j == c)) || (k < l && (k == b || k == c))) continue;
-    int I[3] = {l, j, k}, P[3] = {l, b, c};
-    sort3(I[0], I[1], I[2]);
-    sort3(P[0], P[1], P[2]);
-    double bv = 0.0;
-    for (int p = 0; p < 3; ++p)
-      for (int q = 0; q < 3; ++q) {
-        if (P[p] != I[q]) continue;
-        int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
-        int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
-        double anti = A.V[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2] -
-                      A.V[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2];
-        double sg = ((p + q) & 1) ? -1.0 : 1.0;
-        bv += sg * A.lam[I[q]] * s2 * anti;
-      }
-    double D = A.ev[P[0]] + A.ev[P[1]] + A.ev[P[2]] - A.eo[I[0]] - A.eo[I[1]] - A.eo[I[2]] - A.omega;
-    acc += 2.0 * bv * bv / D;
-  }
+  for (int l = 1 + blockIdx.y; l < no; l += gridDim.y)
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < per_l; r += gridDim.x * blockDim.x) {
+      const int to = A.po1[r / d.npv1], tv = A.pv1[r % d.npv1];
+      const int jr = to >> 16, kr = to & 0xffff, br = tv >> 16, cr = tv & 0xffff;
+      const int j = jr + (jr >= l), k = kr + (kr >= l), b = br + (br >= l), c = cr + (cr >= l);
+      if ((j < l && (j == b || j == c)) || (k < l && (k == b || k == c))) continue;
+      int I[3] = {l, j, k}, P[3] = {l, b, c};
+      sort3(I[0], I[1], I[2]);
+      sort3(P[0], P[1], P[2]);
+      double bv = 0.0;
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+          if (P[p] != I[q]) continue;
+          int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
+          int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
+          double anti = A.V[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2] -
+                        A.V[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2];
+          double sg = ((p + q) & 1) ? -1.0 : 1.0;
+          bv += sg * A.lam[I[q]] * s2 * anti;
+        }
+      double D = A.ev[P[0]] + A.ev[P[1]] + A.ev[P[2]] - A.eo[I[0]] - A.eo[I[1]] - A.eo[I[2]] - A.omega;
+      acc += 2.0 * bv * bv / D;
+    }
   double s = block_sum(acc);
-  if (threadIdx.x == 0) A.partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
 // Mixed sector (up; down down), doubled for its spin flip.  Case A: the up pair
@@ -320,54 +343,50 @@ __device__ inline double b_mixed(const E2sArgs& A, int i, int a, int j, int k, i
   return bv;
 }
 
+// grid (x, y): y walks the up hole i >= 1 of the up TOP pair, x the (j<k, b<c) pairs
 __global__ __launch_bounds__(256) void k_e2s_mixed_a(E2sArgs A) {
   const Dims& d = A.d;
   const int no = d.no;
-  const int64_t per_i = (int64_t)d.npo * d.npv;
-  const int64_t total = per_i * (no - 1);
+  const int per_i = d.npo * d.npv;
   double acc = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int i = (int)(g / per_i) + 1;
-    int64_t r = g % per_i;
-    int j, k, b, c;
-    tri_pq((int)(r / d.npv), no, j, k);
-    tri_pq((int)(r % d.npv), d.nv, b, c);
-    if ((j == 0 || k == 0) && (b == 0 || c == 0)) continue;     // contains t
-    double bv = b_mixed(A, i, i, j, k, b, c);
-    double D = A.ev[i] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
-    acc += 2.0 * bv * bv / D;
-  }
+  for (int i = 1 + blockIdx.y; i < no; i += gridDim.y)
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < per_i; r += gridDim.x * blockDim.x) {
+      const int to = A.po[r / d.npv], tv = A.pv[r % d.npv];
+      const int j = to >> 16, k = to & 0xffff, b = tv >> 16, c = tv & 0xffff;
+      if ((j == 0 || k == 0) && (b == 0 || c == 0)) continue;     // contains t
+      double bv = b_mixed(A, i, i, j, k, b, c);
+      double D = A.ev[i] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+      acc += 2.0 * bv * bv / D;
+    }
   double s = block_sum(acc);
-  if (threadIdx.x == 0) A.partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
+// grid (x, y): y walks the up excitation (i, a), a != i; x the (l, m, e) triples
+// of the down pair (holes {l, m}, particles {l', e})
 __global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv;
-  // index = (((i * nv + a) * no + l) * (no-1) + mr) * (nv-1) + er
-  const int64_t total = (int64_t)no * nv * no * (no - 1) * (nv - 1);
+  const int inner = no * (no - 1) * (nv - 1);       // index = (l * (no-1) + mr) * (nv-1) + er
   double acc = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int64_t r = g;
-    int er = r % (nv - 1); r /= (nv - 1);
-    int mr = r % (no - 1); r /= (no - 1);
-    int l = r % no; r /= no;
-    int a = r % nv; r /= nv;
-    int i = (int)r;
+  for (int ia = blockIdx.y; ia < no * nv; ia += gridDim.y) {
+    const int i = ia / nv, a = ia - i * nv;
     if (a == i) continue;
-    int m = mr + (mr >= l), e = er + (er >= l);
-    if (m < l && e == m) continue;                                // smaller down TOP m
-    if ((i == 0 || l == 0 || m == 0) && (a == 0 || l == 0 || e == 0)) continue;   // contains t
-    int j = l < m ? l : m, k = l < m ? m : l;
-    int b = l < e ? l : e, c = l < e ? e : l;
-    double bv = b_mixed(A, i, a, j, k, b, c);
-    double D = A.ev[a] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
-    acc += 2.0 * bv * bv / D;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < inner; r += gridDim.x * blockDim.x) {
+      const int er = r % (nv - 1), q = r / (nv - 1);
+      const int mr = q % (no - 1), l = q / (no - 1);
+      const int m = mr + (mr >= l), e = er + (er >= l);
+      if (m < l && e == m) continue;                                // smaller down TOP m
+      if ((i == 0 || l == 0 || m == 0) && (a == 0 || l == 0 || e == 0)) continue;   // contains t
+      const int j = l < m ? l : m, k = l < m ? m : l;
+      const int b = l < e ? l : e, c = l < e ? e : l;
+      const double bv = b_mixed(A, i, a, j, k, b, c);
+      const double D = A.ev[a] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+      acc += 2.0 * bv * bv / D;
+    }
   }
   double s = block_sum(acc);
-  if (threadIdx.x == 0) A.partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
 __global__ void k_sum_partials(const double* v, int n, double* out, double scale) {

@@ -25,6 +25,12 @@ __global__ void k_block_copy(const double* src, int64_t off, int ld, int m, doub
     dst[e] = src[off + (int64_t)(e / m) * ld + (e % m)];
 }
 
+// eigenpair of a 1 x 1 matrix
+__global__ void k_eig1(const double* A, double* evals, double* Y) {
+  evals[0] = A[0];
+  Y[0] = 1.0;
+}
+
 // T (n x n) = identity with T[1:, 1:] = Y (Y: (n-1) x (n-1), column k = eigenvector k).
 // Each eigenvector is signed so that its largest-magnitude entry is positive.
 __global__ void k_embed_rotation(const double* Y, int n, double* T) {
