@@ -84,6 +84,7 @@ struct esmp2_handle_ {
   int* pairs = nullptr;          // (p << 16) | q tables: virtual pairs, shifted virtual, occupied, shifted occupied
   int4* chunks = nullptr;        // coupling kernel work: (box, batch, first inner index, (p << 16) | q)
   int nchunks = 0;
+  double* pq_part = nullptr;     // per-chunk parts of <p, Ap>_W
   // Krylov vectors
   double *x, *r, *p, *q;
   // FP32 operator (Fock blocks rounded from the FP64 ones, work buffers) and
@@ -375,7 +376,7 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
   }
   h->nchunks = (int)chunks.size();
   if (!dalloc(h, &h->jobs, jobs.size()) || !dalloc(h, &h->jobs4, j4.size()) || !dalloc(h, &h->pairs, pairs.size()) ||
-      !dalloc(h, &h->chunks, chunks.size())) {
+      !dalloc(h, &h->chunks, chunks.size()) || !dalloc(h, &h->pq_part, chunks.size())) {
     release(h);
     return fail(h, ESMP2_OOM, "device allocation failed");
   }
@@ -640,7 +641,7 @@ static SigmaBufs<float> bufs32(esmp2_handle h) {
 // S~ and the per-batch side contractions with f_ov; returns the argument
 // block of the coupling terms.
 template <class T>
-static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y) {
+static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y, bool arrow = false) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv;
   hipStream_t s = h->stream;
@@ -655,8 +656,11 @@ static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const
   const int n2 = (no - 1) * (no - 1);
   sa.h21_t = take(n2); sa.h21_k = take(n2);
   sa.h22_ut = take(n2); sa.h22_i = take(n2); sa.h22_uk = take(n2);
-  const int nside = d.npo1 + 2 * d.npo + 2 * n2;
-  hipLaunchKernelGGL(k_side<T>, dim3(nside, (nv + 63) / 64), dim3(256), 0, s, sa);
+  // per-batch GEMVs: the side contractions, and with the arrow-shaped Fock blocks
+  // also the t'-row products (T2 and S2 batches join the job list)
+  GemvArgs<T> gva{sa, w.S, w.fv, (T*)h->gv, w.side_tr, arrow ? 1 : 0};
+  const int jobs = d.npo1 + 2 * d.npo + 2 * n2 + (arrow ? d.npo + no * no : 0);
+  hipLaunchKernelGGL(k_gemv<T>, dim3(jobs), dim3(256), 0, s, gva);
   GatherArgs<T> ga{};
   ga.d = d; ga.x = x; ga.S = w.S; ga.y = y; ga.fo = w.fo; ga.fv = w.fv; ga.fov = w.fov; ga.side_tr = w.side_tr;
   ga.t3_t = sa.t3_t; ga.t3_p1 = sa.t3_p1; ga.t3_p2 = sa.t3_p2; ga.h11_p1 = sa.h11_p1; ga.h11_p2 = sa.h11_p2;
@@ -735,20 +739,18 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
 
 // sigma in the pinned-semicanonical basis, where the non-pinned Fock blocks
 // are diagonal: O(N_o^2 N_v^2) arrow kernels instead of the Sylvester products
+// pq != nullptr: also the per-workgroup parts of <x, y>_W (h->nchunks of them)
 template <class T>
-static esmp2_status sigma_arrow(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y) {
+static esmp2_status sigma_arrow(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y, double* pq = nullptr) {
   const Dims& d = h->d;
   const int no = d.no;
   hipStream_t s = h->stream;
-  GatherArgs<T> ga = sigma_prologue(h, w, x, y);
+  GatherArgs<T> ga = sigma_prologue(h, w, x, y, true);
   ArrowArgs<T> aa{ga, w.Fd, w.Fl, w.side_tr, (T*)h->gv};
-  const int n2 = (no - 1) * (no - 1);
-  const int jobs = 3 * d.npo + no * no + 2 * n2;
-  hipLaunchKernelGGL(k_arrow_side<T>, dim3(jobs, (d.nv + 63) / 64), dim3(256), 0, s, aa);
   const int* pv = h->pairs;
   PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
   if (h->nchunks > 0)
-    hipLaunchKernelGGL(k_arrow<T>, dim3(h->nchunks), dim3(256), 0, s, aa, pt, (const int4*)h->chunks);
+    hipLaunchKernelGGL(k_arrow<T>, dim3(h->nchunks), dim3(256), 0, s, aa, pt, (const int4*)h->chunks, pq);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
@@ -882,6 +884,25 @@ static esmp2_status apply_op(esmp2_handle h, const OpCtx& c, const SigmaBufs<T>&
   return c.arrow ? sigma_arrow(h, w, x, y) : sigma_t(h, w, x, y);
 }
 
+template <class T>
+static void wdot(esmp2_handle h, const T* x, const T* y, int slot);
+
+// y = A x and sc[SC_PQ] = <x, y>_W (fused into the operator where it writes every element once)
+template <class T>
+static esmp2_status apply_op_dot(esmp2_handle h, const OpCtx& c, const SigmaBufs<T>& w, const T* x, T* y) {
+  if (c.arrow && h->nchunks > 0) {
+    esmp2_status st = sigma_arrow(h, w, x, y, h->pq_part);
+    if (st != ESMP2_OK) return st;
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, h->stream, (const double*)h->pq_part, h->nchunks, h->sc,
+                       (int)SC_PQ);
+    return ESMP2_OK;
+  }
+  esmp2_status st = sigma_t(h, w, x, y);
+  if (st != ESMP2_OK) return st;
+  wdot(h, x, (const T*)y, SC_PQ);
+  return ESMP2_OK;
+}
+
 static OpCtx ctx_top(esmp2_handle h) { return OpCtx{h->b, h->dinv, h->dinv32, bufs64(h), bufs32(h), false, false}; }
 
 static OpCtx ctx_sc(esmp2_handle h) {
@@ -982,9 +1003,8 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   int it = 0;
   esmp2_status status = ESMP2_OK;
   while (rel > opts->tol && it < opts->max_iter) {
-    esmp2_status st = apply_op(h, c, c.s64, (const double*)h->p, h->q);
+    esmp2_status st = apply_op_dot(h, c, c.s64, (const double*)h->p, h->q);
     if (st != ESMP2_OK) return st;
-    wdot(h, (const double*)h->p, (const double*)h->q, SC_PQ);
     hipLaunchKernelGGL(k_update_xr<double>, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, c.dinv, n, d.off[1],
                        d.off[2], h->sc, h->partial);
     hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);  // RHO_NEW, RR
@@ -1050,9 +1070,8 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
     ESMP2_HIP(hipStreamSynchronize(s));
     const double rr0 = hs[SC_PQ];
     while (it < opts->max_iter) {
-      esmp2_status st = apply_op(h, c, c.s32, (const float*)h->p32, h->q32);
+      esmp2_status st = apply_op_dot(h, c, c.s32, (const float*)h->p32, h->q32);
       if (st != ESMP2_OK) return st;
-      wdot(h, (const float*)h->p32, (const float*)h->q32, SC_PQ);
       hipLaunchKernelGGL(k_update_xr<float>, dim3(NB), dim3(256), 0, s, h->d32, h->r32, (const float*)h->p32,
                          (const float*)h->q32, c.dinv32, n, d.off[1], d.off[2], (const double*)h->sc,
                          h->partial);

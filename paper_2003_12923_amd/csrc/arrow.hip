@@ -13,6 +13,7 @@
 // the operator costs O(N_o^2 N_v^2) instead of O(N_o^2 N_v^3).
 #include "common.h"
 #include "sigma.h"
+#include "reduce.h"
 
 namespace esmp2 {
 
@@ -99,14 +100,20 @@ __global__ __launch_bounds__(256) void k_arrow_side(ArrowArgs<T> A) {
 // y = sigma for every amplitude: diagonal, arrow terms of both Fock blocks,
 // transfer rows, couplings.  One workgroup per chunk of 256 inner indices of
 // one batch matrix (the coupling kernel's chunk table).
+// With pq != nullptr each workgroup also writes its part of <x, y>_W (the CG
+// denominator p.Ap) to pq[blockIdx.x].
 template <class T>
-__global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, const int4* chunks) {
-  const GatherArgs<T>& G = A.ga;
-  const Dims& d = G.d;
+__device__ __attribute__((always_inline)) inline double arrow_element(const ArrowArgs<T>& A, const PairTables& P,
+                                                                      int box, int batch, int i, int j, int v,
+                                                                      int inner);
+
+template <class T>
+__global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, const int4* chunks, double* pq) {
+  const Dims& d = A.ga.d;
   const int4 ch = chunks[xcd_remap<16>(blockIdx.x, gridDim.x)];
   const int box = ch.x, batch = ch.y, v = ch.z + (int)threadIdx.x;
   const int i = ch.w >> 16, j = ch.w & 0xffff;      // occupied indices of the batch (actual orbitals)
-  const int no = d.no, nv = d.nv, m1 = nv - 1, mv = d.mv;
+  const int nv = d.nv, m1 = nv - 1;
   int inner;
   switch (box) {
     case B_T2: case B_H11: case B_H21: inner = d.npv; break;
@@ -114,7 +121,21 @@ __global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, con
     case B_T3: inner = d.npv1; break;
     default: inner = m1 * m1; break;
   }
-  if (v >= inner) return;
+  double part = 0.0;
+  if (v < inner) part = arrow_element(A, P, box, batch, i, j, v, inner);
+  if (pq) {
+    const double s = block_sum(part);
+    if (threadIdx.x == 0) pq[blockIdx.x] = s;
+  }
+}
+
+template <class T>
+__device__ __attribute__((always_inline)) inline double arrow_element(const ArrowArgs<T>& A, const PairTables& P,
+                                                                      int box, int batch, int i, int j, int v,
+                                                                      int inner) {
+  const GatherArgs<T>& G = A.ga;
+  const Dims& d = G.d;
+  const int no = d.no, nv = d.nv, m1 = nv - 1, mv = d.mv;
   int a, b;                                         // virtual indices (actual orbitals)
   switch (box) {
     case B_T2: case B_H11: case B_H21: { const int t = P.pv[v]; a = t >> 16; b = t & 0xffff; break; }
@@ -169,12 +190,14 @@ __global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, con
   if ((box == B_H11 || box == B_H21) && a == 0)
     y += G.side_tr[((box == B_H11 ? 0 : (int64_t)d.npo) + batch) * nv + b];
   y += couple_terms(G, P, box, batch, i, j, v);
-  G.y[d.off[box] + (int64_t)batch * inner + v] = y;
+  const int64_t g = d.off[box] + (int64_t)batch * inner + v;
+  G.y[g] = y;
+  return (box == B_S2 ? 1.0 : 2.0) * (double)G.x[g] * (double)y;     // weighted product for <x, y>_W
 }
 
 #define ESMP2_ARROW_INSTANCES(T)                                                        \
   template __global__ void k_arrow_side<T>(ArrowArgs<T>);                               \
-  template __global__ void k_arrow<T>(ArrowArgs<T>, PairTables, const int4*);
+  template __global__ void k_arrow<T>(ArrowArgs<T>, PairTables, const int4*, double*);
 ESMP2_ARROW_INSTANCES(double)
 ESMP2_ARROW_INSTANCES(float)
 #undef ESMP2_ARROW_INSTANCES
