@@ -42,6 +42,7 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 32-state batched workload")
     ap.add_argument("--counter-run", type=int, default=0, metavar="N",
                     help="for hardware-counter passes: a 256 MiB device copy (the calibration "
                          "kernel of known size), then N FP64 and N FP32 sigma applications; no timing")
@@ -137,6 +138,32 @@ def main():
     sigma_ms = time_sigma(x, P.ESMP2_FP64)
     sigma32_ms = time_sigma(x.float(), P.ESMP2_FP32)
 
+    # the batched workload: 32 independent states of uneven size, one handle and one
+    # stream each, solved together (pinned-semicanonical basis, FP64)
+    batch = None
+    if not args.no_batch:
+        hs = [P.Handle(0, stream="new").load(synth.make_problem(*sz)) for sz in synth.batched_sizes()]
+        torch.cuda.synchronize()
+        P.solve_batch(hs, tol=args.tol, basis=P.ESMP2_BASIS_SEMICANONICAL)          # warm-up
+        t0 = time.perf_counter()
+        rb = P.solve_batch(hs, tol=args.tol, basis=P.ESMP2_BASIS_SEMICANONICAL)
+        batch_ms = 1e3 * (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for hh in hs:
+            hh.rotate_top(lam_out=False)
+            hh.build_rhs()
+            hh.solve(tol=args.tol, max_iter=300, basis=P.ESMP2_BASIS_SEMICANONICAL)
+        torch.cuda.synchronize()
+        seq_ms = 1e3 * (time.perf_counter() - t0)
+        gb = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_values.json"))).get("c4")
+        err = None if gb is None else max(abs(r["e2"] - g["e2"]) for r, g in zip(rb, gb["states"]))
+        batch = {"states": len(hs), "ms": round(batch_ms, 3), "states_per_s": round(len(hs) / batch_ms * 1e3, 2),
+                 "one_by_one_ms": round(seq_ms, 3), "speedup_vs_one_by_one": round(seq_ms / batch_ms, 3),
+                 "max_abs_e2_minus_oracle": err, "basis": "pinned semicanonical", "dtype": "f64"}
+        for hh in hs:
+            hh.close()
+        del hs
+
     vv_avg_ms = vv_ms / max(vv_n, 1)
     achieved = vv_flops / (vv_avg_ms * 1e-3) / 1e12
     # HBM bytes per launch from the committed counter passes, valid while the
@@ -198,6 +225,7 @@ def main():
                       "inner_fp32_iterations": res_scm["iterations"],
                       "outer_fp64_steps": res_scm["outer"], "rel_resid": res_scm["rel_resid"],
                       "e2_minus_top_fp64": res_scm["e2"] - res["e2"]}},
+        "batched_32_states": batch,
         "roofline": {"bound": "mfma", "kernel": "k_vv3 (virtual-pair Sylvester, FP64 MFMA)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,

@@ -172,6 +172,18 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision);
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
                          esmp2_solve_result* result);
 
+/* Batched workload: n independent states, one handle each (esmp2_set_problem
+ * done, every handle on its own stream for the states to overlap on the
+ * device).  For every handle: rotation, right-hand side, solve with `opts`,
+ * E2 into results[i] (host array of n).  A pool of n_threads host threads
+ * (<= 0: 8) takes the states in order; each state's calls are the ones above,
+ * issued on that state's stream, so the device runs several states' kernels
+ * at once.  opts->x0, x_out and resid_hist must be NULL.  Synchronises.  Every
+ * state is attempted; returns ESMP2_OK or the status of the first failing
+ * state (results[i].status holds each one). */
+esmp2_status esmp2_solve_batch(esmp2_handle* handles, int n, const esmp2_solve_opts* opts,
+                               esmp2_solve_result* results, int n_threads);
+
 /* C = A B for row-major FP64 matrices (A: m x k, B: k x n, C: m x n, all device),
  * on the matrix cores, queued on the handle's stream.  This is the dense GEMM the
  * library uses for the TOP-basis rotation and the integral blocks; it is exported

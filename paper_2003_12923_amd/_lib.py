@@ -43,6 +43,8 @@ _sig = {
     "esmp2_solve": ([_H, C.POINTER(SolveOpts), C.POINTER(SolveResult)], C.c_int),
     "esmp2_gemm_f64": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "esmp2_profile": ([_H, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+    "esmp2_solve_batch": ([C.POINTER(_H), C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveResult), C.c_int],
+                          C.c_int),
     "esmp2_last_error": ([_H], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -67,6 +69,8 @@ class Handle:
     def __init__(self, device=0, stream=None):
         import torch
         self.device = device
+        if stream == "new":
+            stream = torch.cuda.Stream(device)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
@@ -153,3 +157,19 @@ class Handle:
         self._n_occ = prob.n_occ
         self.set_problem(self._F, self._B, self._C, prob.n_occ, prob.n_vir, prob.n_aux)
         return self
+
+
+def solve_batch(handles, tol=1e-8, max_iter=300, precision=ESMP2_FP64, basis=ESMP2_BASIS_TOP, inner_tol=0.0,
+                n_threads=8):
+    """Rotation, right-hand side, solve and E2 for every handle (each bound to a
+    problem and to its own stream); returns one result dict per handle."""
+    n = len(handles)
+    arr = (_H * n)(*[hd.h for hd in handles])
+    o = SolveOpts(tol, max_iter, precision, None, None, None, inner_tol, basis)
+    res = (SolveResult * n)()
+    st = lib.esmp2_solve_batch(arr, n, C.byref(o), res, n_threads)
+    out = [{k: getattr(r, k) for k, _ in SolveResult._fields_} for r in res]
+    if st not in (ESMP2_OK, ESMP2_NOT_CONVERGED):
+        bad = next((i for i, r in enumerate(out) if r["status"] not in (ESMP2_OK, ESMP2_NOT_CONVERGED)), 0)
+        raise Esmp2Error(st, lib.esmp2_last_error(handles[bad].h).decode())
+    return out

@@ -8,6 +8,8 @@
 #include <vector>
 #include <new>
 #include <algorithm>
+#include <atomic>
+#include <thread>
 
 // Kernels come from the other sources of the same translation unit (esmp2_all.hip).
 
@@ -809,8 +811,18 @@ static esmp2_status rotate_amplitudes(esmp2_handle h, const double* x, double* y
     hipLaunchKernelGGL(k_unpack_box, dim3(nblk(nd)), dim3(256), 0, s, d, box, x, h->dense0);
     ESMP2_HIP(contract_index(s, 3, ro, rv, Gv, srv, scv, h->dense0, h->dense1));
     ESMP2_HIP(contract_index(s, 2, ro, rv, Gv, srv, scv, h->dense1, h->dense0));
-    ESMP2_HIP(contract_index(s, 0, ro, rv, Go, sro, sco, h->dense0, h->dense1));
-    ESMP2_HIP(contract_index(s, 1, ro, rv, Go, sro, sco, h->dense1, h->dense0));
+    const int64_t v2 = (int64_t)rv * rv;
+    dim3 grid_o((unsigned)((v2 + 255) / 256), (unsigned)ro);
+    auto rot_occ = [&](const double* in, double* out, int which) {
+      if (ro <= 16)
+        hipLaunchKernelGGL(k_rot_occ<16>, grid_o, dim3(256), 0, s, in, out, Go, sro, sco, ro, v2, which);
+      else if (ro <= 32)
+        hipLaunchKernelGGL(k_rot_occ<32>, grid_o, dim3(256), 0, s, in, out, Go, sro, sco, ro, v2, which);
+      else
+        hipLaunchKernelGGL(k_rot_occ<64>, grid_o, dim3(256), 0, s, in, out, Go, sro, sco, ro, v2, which);
+    };
+    rot_occ(h->dense0, h->dense1, 0);
+    rot_occ(h->dense1, h->dense0, 1);
     hipLaunchKernelGGL(k_pack_box, dim3(nblk(d.off[box + 1] - d.off[box])), dim3(256), 0, s, d, box,
                        (const double*)h->dense0, y);
   }
@@ -1128,6 +1140,45 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
     c = ctx_sc(h);
   }
   return opts->precision == ESMP2_FP64 ? solve64(h, c, opts, res) : solve_mixed(h, c, opts, res);
+}
+
+esmp2_status esmp2_solve_batch(esmp2_handle* hs, int n, const esmp2_solve_opts* opts, esmp2_solve_result* res,
+                               int n_threads) {
+  if (n < 0 || (n > 0 && (!hs || !res)) || !opts) return ESMP2_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i]) return ESMP2_INVALID_ARG;
+    if (opts->x0 || opts->x_out || opts->resid_hist)
+      return fail(hs[i], ESMP2_INVALID_ARG, "x0, x_out and resid_hist are per-state: use esmp2_solve");
+    if (hs[i]->state < 1) return fail(hs[i], ESMP2_BAD_ORDER, "esmp2_set_problem first");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(hs[i], ESMP2_INVALID_ARG, "a handle appears twice in the batch");
+  }
+  if (n == 0) return ESMP2_OK;
+  const int nt = std::max(1, std::min(n, n_threads > 0 ? n_threads : 8));
+  std::vector<esmp2_status> st(n, ESMP2_OK);
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int i = next++; i < n; i = next++) {
+      esmp2_handle h = hs[i];
+      memset(&res[i], 0, sizeof(res[i]));
+      esmp2_status s = esmp2_rotate_top(h, nullptr);
+      if (s == ESMP2_OK) s = esmp2_build_rhs(h, nullptr, nullptr, nullptr);
+      if (s == ESMP2_OK) s = esmp2_solve(h, opts, &res[i]);
+      else res[i].status = s;
+      st[i] = s;
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  } catch (...) {
+    // fewer host threads than asked: the remaining ones (and this one) take the states
+  }
+  work();
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < n; ++i)
+    if (st[i] != ESMP2_OK) return st[i];
+  return ESMP2_OK;
 }
 
 }  // extern "C"

@@ -134,4 +134,47 @@ __global__ void k_pack_box(Dims d, int box, const double* dense, double* y) {
   }
 }
 
+// Rotation of one occupied index of dense[P][Q][v] (ranges ro, ro, nvv):
+//   which = 1: out[P][Q'][v] = sum_Q G(Q, Q') in[P][Q][v]
+//   which = 0: out[P'][Q][v] = sum_P G(P, P') in[P][Q][v]
+// G(c, c') = Gm[c*sr + c'*sc], staged in LDS.  Thread per (fixed occupied index, v):
+// ro coalesced loads, ro^2 multiply-adds, ro coalesced stores; R >= ro is the
+// compile-time bound that keeps the accumulators in registers.
+template <int R>
+__global__ __launch_bounds__(256) void k_rot_occ(const double* in, double* out, const double* Gm, int64_t sr,
+                                                 int64_t sc, int ro, int64_t nvv, int which) {
+  __shared__ double G[R * R];
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int c = e / R, c2 = e % R;
+    G[e] = (c < ro && c2 < ro) ? Gm[c * sr + c2 * sc] : 0.0;
+  }
+  __syncthreads();
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;                          // the occupied index that stays
+  if (v >= nvv) return;
+  double acc[R];
+#pragma unroll
+  for (int c2 = 0; c2 < R; ++c2) acc[c2] = 0.0;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    if (c < ro) {
+      const int64_t src = which == 1 ? ((int64_t)f * ro + c) * nvv + v : ((int64_t)c * ro + f) * nvv + v;
+      const double y = in[src];
+#pragma unroll
+      for (int c2 = 0; c2 < R; ++c2) acc[c2] += G[c * R + c2] * y;
+    }
+  }
+#pragma unroll
+  for (int c2 = 0; c2 < R; ++c2) {
+    if (c2 < ro) {
+      const int64_t dst = which == 1 ? ((int64_t)f * ro + c2) * nvv + v : ((int64_t)c2 * ro + f) * nvv + v;
+      out[dst] = acc[c2];
+    }
+  }
+}
+
+template __global__ void k_rot_occ<16>(const double*, double*, const double*, int64_t, int64_t, int, int64_t, int);
+template __global__ void k_rot_occ<32>(const double*, double*, const double*, int64_t, int64_t, int, int64_t, int);
+template __global__ void k_rot_occ<64>(const double*, double*, const double*, int64_t, int64_t, int, int64_t, int);
+
 }  // namespace esmp2
