@@ -23,6 +23,11 @@ definition written out on Slater determinants (tiny sizes only):
 * first-order equation Q(H0 - E0)Q Psi1 = -Q V Psi0 with Q V Psi0 = Q H Psi0,
   and E2 = <Psi0|V|Psi1> = sum_mu b_mu x_mu; S-triples are inverted
   directly (their block is diagonal), N-triples have b = 0.
+
+``solve_original`` is the unmodified zeroth-order Hamiltonian of Sec. II.C
+(Eq. for the original H0, the N^7 theory the paper starts from): the full
+Fock operator on every double and triple, S and N triples included, so that
+the E2 shift of the modification can be measured at tiny sizes.
 """
 from __future__ import annotations
 
@@ -167,6 +172,29 @@ class ExplicitESMP2:
         self.bS, self.DS = bS, DS
         return dict(e2=e2_dl + e2_s, e2_dl=e2_dl, e2_s=e2_s, e0=self.E0,
                     max_bN=float(np.max(np.abs(bN))) if len(bN) else 0.0)
+
+    def solve_original(self):
+        """E2 with the original Q F Q: the full Fock operator coupling all
+        doubles and triples (D, L, S, N), no diagonal blocks.  The first-order
+        space stays doubles + triples (reading: the original theory is the
+        modified one with the S/N diagonal approximation removed)."""
+        space = self.D + self.L + self.S + self.N
+        index = {d: k for k, d in enumerate(space)}
+        rows, cols, vals = [], [], []
+        for k, d in enumerate(space):
+            out = fm.apply_one_body({d: 1.0}, self.f, self.n)
+            for d2, v in out.items():
+                j = index.get(d2)
+                if j is not None and v != 0.0:
+                    rows.append(j)
+                    cols.append(k)
+                    vals.append(v)
+        m = len(space)
+        A = (sp.csr_matrix((vals, (rows, cols)), shape=(m, m)) - self.E0 * sp.identity(m, format="csr")).toarray()
+        hp = self.h_psi0()
+        b = np.array([hp.get(d, 0.0) for d in space])
+        x = np.linalg.solve(A, -b)
+        return dict(e2=float(b @ x), e0=self.E0, dim=m)
 
     # ----- spin ---------------------------------------------------------
     def s_plus(self, vec):

@@ -244,6 +244,28 @@ def test_rotations_fixing_the_pinned_pair(name):
             assert it2 < it1
 
 
+@pytest.mark.parametrize("no,nv,na,seed", [(2, 4, 6, 0), (3, 5, 8, 1)])
+def test_original_h0_shift(no, nv, na, seed):
+    """The original zeroth-order Hamiltonian (full Fock operator on all
+    triples) differs from the modified one only through the S/N blocks: the
+    shift of E2 is small against E2, vanishes when the Fock matrix is
+    diagonal in the TOP basis (then F^(diag) = F on every block), and the
+    original operator is symmetric positive definite on D + T."""
+    p, lam, Ft, Bt = _rotated(no, nv, na, seed)
+    eri = topbasis.eri_from_factor(Bt)
+    ex = explicit.ExplicitESMP2(Ft, eri, lam, no)
+    mod = ex.solve()
+    org = ex.solve_original()
+    assert org["dim"] == len(ex.D) + len(ex.L) + len(ex.S) + len(ex.N)
+    assert org["e2"] < 0
+    shift = org["e2"] - mod["e2"]
+    assert 0 < abs(shift) < 0.05 * abs(mod["e2"])
+    # diagonal Fock matrix: both theories give the same E2
+    Fd = np.diag(np.diag(Ft))
+    exd = explicit.ExplicitESMP2(Fd, eri, lam, no)
+    assert abs(exd.solve_original()["e2"] - exd.solve()["e2"]) < 1e-14 * abs(exd.solve()["e2"])
+
+
 def test_rank_one_reference_has_no_s_rhs():
     """For a single-CSF reference (rank-1 C) only TOP t has a non-zero
     coefficient, so the S-triples have no right-hand side and E2_S = 0.
