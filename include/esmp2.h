@@ -172,6 +172,20 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision);
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
                          esmp2_solve_result* result);
 
+/* The Fock operator of the reference's one-body density (paper Sec. II.C: the
+ * zeroth-order Hamiltonian uses the Fock operator of Psi0's density), for a
+ * caller that holds the one-electron operator instead of F:
+ *   F = h + G[gamma],  G[g]_pq = sum_rs g_rs ((pq|rs) - (ps|rq)/2),
+ *   gamma = spin-summed density of Psi0: 2 - C C^T (occupied block), C^T C
+ *   (virtual block), zero between them; (pq|rs) = sum_Q B[Q][p][q] B[Q][r][s].
+ * hcore (N x N), B (n_aux x N x N), C (n_occ x n_vir), F_out (N x N): device,
+ * row-major, input orbital basis.  Allocates and frees temporary device memory
+ * (about n_aux N^2 doubles) and synchronises.  Needs a handle (for its device
+ * and stream) but no problem bound to it; F_out can then go to
+ * esmp2_set_problem. */
+esmp2_status esmp2_fock_from_core(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* hcore,
+                                  const double* B, const double* C, double* F_out);
+
 /* Batched workload: n independent states, one handle each (esmp2_set_problem
  * done, every handle on its own stream for the states to overlap on the
  * device).  For every handle: rotation, right-hand side, solve with `opts`,

@@ -15,6 +15,7 @@ Two tiers, both plain FP64:
   layout, applied with dense tensor contractions (numpy).  It is pinned to
   ``explicit`` by brute force and runs at every workload size.
 
-``topbasis`` rotates the input to the transition-orbital-pair (TOP) basis and
-``layout`` maps the seven-box layout to determinants.
+``topbasis`` rotates the input to the transition-orbital-pair (TOP) basis,
+``layout`` maps the seven-box layout to determinants and ``frontend`` builds
+the Fock operator of the reference's density from the one-electron operator.
 """

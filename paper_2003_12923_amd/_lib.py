@@ -45,6 +45,8 @@ _sig = {
     "esmp2_profile": ([_H, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "esmp2_solve_batch": ([C.POINTER(_H), C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveResult), C.c_int],
                           C.c_int),
+    "esmp2_fock_from_core": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                             C.c_int),
     "esmp2_last_error": ([_H], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -141,6 +143,10 @@ class Handle:
         ms, n = (C.c_double * 2)(), (C.c_int64 * 2)()
         self._check(lib.esmp2_profile(self.h, 1 if enable else 0, ms, n))
         return {ESMP2_FP64: (ms[0], n[0]), ESMP2_FP32: (ms[1], n[1])}
+
+    def fock_from_core(self, hcore, B, Cm, n_occ, n_vir, n_aux, F_out):
+        return self._check(lib.esmp2_fock_from_core(self.h, n_occ, n_vir, n_aux, _ptr(hcore), _ptr(B), _ptr(Cm),
+                                                    _ptr(F_out)))
 
     def gemm_f64(self, A, B, Cm):
         m, k = A.shape

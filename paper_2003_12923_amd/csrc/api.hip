@@ -1181,4 +1181,49 @@ esmp2_status esmp2_solve_batch(esmp2_handle* hs, int n, const esmp2_solve_opts* 
   return ESMP2_OK;
 }
 
+esmp2_status esmp2_fock_from_core(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* hcore,
+                                  const double* B, const double* C, double* F_out) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (!hcore || !B || !C || !F_out) return fail(h, ESMP2_INVALID_ARG, "null pointer");
+  if (n_occ < 1 || n_vir < n_occ || n_aux < 1 || n_occ + n_vir > 256)
+    return fail(h, ESMP2_INVALID_ARG, "need 1 <= n_occ <= n_vir, n_aux >= 1, n_occ + n_vir <= 256");
+  ESMP2_HIP(hipSetDevice(h->device));
+  const int n = n_occ + n_vir;
+  const int64_t nn = (int64_t)n * n;
+  hipStream_t s = h->stream;
+  double *gam = nullptr, *d = nullptr, *T = nullptr, *K = nullptr;
+  auto cleanup = [&]() {
+    if (gam) (void)hipFree(gam);
+    if (d) (void)hipFree(d);
+    if (T) (void)hipFree(T);
+    if (K) (void)hipFree(K);
+  };
+  if (hipMalloc(&gam, sizeof(double) * nn) != hipSuccess || hipMalloc(&d, sizeof(double) * n_aux) != hipSuccess ||
+      hipMalloc(&T, sizeof(double) * nn * n_aux) != hipSuccess || hipMalloc(&K, sizeof(double) * nn) != hipSuccess) {
+    cleanup();
+    return fail(h, ESMP2_OOM, "device allocation failed");
+  }
+  hipLaunchKernelGGL(k_ref_density, dim3(nblk(nn)), dim3(256), 0, s, C, n_occ, n_vir, gam);
+  hipLaunchKernelGGL(k_coulomb_weights, dim3(n_aux), dim3(256), 0, s, B, (const double*)gam, n, d);
+  // T[p][Q][r] = (B[Q] gamma)[p][r]
+  GemmArgs g{};
+  g.A = B; g.B = gam; g.C = T; g.M = n; g.N = n; g.K = n;
+  g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1;
+  g.sCb = n; g.sCi = (int64_t)n_aux * n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  hipError_t e1 = gemm(s, n_aux, g);
+  // K[p][q] = sum_{Q, r} T[p][Q][r] B[Q][r][q]
+  g = GemmArgs{};
+  g.A = T; g.B = B; g.C = K; g.M = n; g.N = n; g.K = n_aux * n;
+  g.sAi = (int64_t)n_aux * n; g.sAk = 1; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  hipError_t e2 = gemm(s, 1, g);
+  hipLaunchKernelGGL(k_fock_combine, dim3(nblk(nn)), dim3(256), 0, s, hcore, B, (const double*)d, (const double*)K, n,
+                     n_aux, F_out);
+  hipError_t e3 = hipStreamSynchronize(s);
+  hipError_t e4 = hipGetLastError();
+  cleanup();
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
+    return fail(h, ESMP2_HIP_ERROR, "HIP error in esmp2_fock_from_core");
+  return ESMP2_OK;
+}
+
 }  // extern "C"

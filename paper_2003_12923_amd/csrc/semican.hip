@@ -16,6 +16,7 @@
 // the rotation (four GEMMs), pack.
 #include "common.h"
 #include "sigma.h"
+#include "reduce.h"
 
 namespace esmp2 {
 
@@ -170,6 +171,45 @@ __global__ __launch_bounds__(256) void k_rot_occ(const double* in, double* out, 
       const int64_t dst = which == 1 ? ((int64_t)f * ro + c2) * nvv + v : ((int64_t)c2 * ro + f) * nvv + v;
       out[dst] = acc[c2];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fock operator of the reference's density: F = h + J[gamma] - K[gamma]/2
+// ---------------------------------------------------------------------------
+// gamma (spin-summed, input orbital basis): 2 delta - C C^T (occupied block),
+// C^T C (virtual block), zero between them
+__global__ void k_ref_density(const double* C, int no, int nv, double* gam) {
+  const int n = no + nv;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+    const int p = e / n, q = e % n;
+    double v = 0.0;
+    if (p < no && q < no) {
+      for (int a = 0; a < nv; ++a) v -= C[p * nv + a] * C[q * nv + a];
+      if (p == q) v += 2.0;
+    } else if (p >= no && q >= no) {
+      for (int i = 0; i < no; ++i) v += C[i * nv + (p - no)] * C[i * nv + (q - no)];
+    }
+    gam[e] = v;
+  }
+}
+
+// d[Q] = sum_rs B[Q][r][s] gamma[r][s]; one workgroup per Q
+__global__ __launch_bounds__(256) void k_coulomb_weights(const double* B, const double* gam, int n, double* d) {
+  const double* b = B + (int64_t)blockIdx.x * n * n;
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) acc += b[e] * gam[e];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) d[blockIdx.x] = s;
+}
+
+// F = h + sum_Q d[Q] B[Q] - K / 2
+__global__ void k_fock_combine(const double* hcore, const double* B, const double* d, const double* K, int n,
+                               int naux, double* F) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+    double j = 0.0;
+    for (int Q = 0; Q < naux; ++Q) j += d[Q] * B[(int64_t)Q * n * n + e];
+    F[e] = hcore[e] + j - 0.5 * K[e];
   }
 }
 

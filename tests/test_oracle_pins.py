@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import explicit, layout, structured, topbasis
+from oracle import explicit, frontend, layout, structured, topbasis
 
 MICRO = [(2, 4, 6, 0), (3, 5, 8, 1), (3, 6, 8, 2), (4, 6, 10, 3), (4, 7, 9, 4)]
 
@@ -373,3 +373,28 @@ def test_diagonal_fock_limit_closed_form():
     r = structured.solve(Ft, Bt, lam, no, tol=1e-13)
     assert abs(r["e2"] - closed) < 1e-15
     assert r["iters"] == 1
+
+
+@pytest.mark.parametrize("no,nv,seed", [(2, 3, 0), (3, 4, 1), (2, 5, 2)])
+def test_reference_density_and_fock(no, nv, seed):
+    """The closed-form one-body density of Psi0 equals the determinant
+    expansion's (Slater-Condon), its trace is the electron count 2 n_occ, and
+    the Fock operator built from it inverts the definition of the one-electron
+    operator h = F - G[gamma] (both directions)."""
+    p = synth.make_problem(no, nv, 7, seed)
+    g = frontend.density(p.C, no)
+    np.testing.assert_allclose(frontend.density_explicit(p.C, no), g, rtol=0, atol=1e-14)
+    assert abs(np.trace(g) - 2 * no) < 1e-13
+    h = p.F - frontend.g_matrix(g, p.B)
+    np.testing.assert_allclose(frontend.fock_from_core(h, p.B, p.C, no), p.F, rtol=0, atol=1e-13)
+    # G[gamma] against the four-index integrals written out
+    eri = topbasis.eri_from_factor(p.B)
+    Gx = np.einsum("rs,pqrs->pq", g, eri) - 0.5 * np.einsum("rs,psrq->pq", g, eri)
+    np.testing.assert_allclose(frontend.g_matrix(g, p.B), Gx, rtol=0, atol=1e-13)
+    # in the TOP basis the density is diagonal (2 - lam^2 on occupied l, lam^2 on l')
+    lam, R = topbasis.top_rotation(p.F, p.C, no)
+    gt = R.T @ g @ R
+    d = np.zeros(no + nv)
+    d[:no] = 2 - lam ** 2
+    d[no:2 * no] = lam ** 2
+    np.testing.assert_allclose(gt, np.diag(d), rtol=0, atol=1e-13)
