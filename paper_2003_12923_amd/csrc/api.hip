@@ -159,24 +159,24 @@ static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs
 
 // Eigenpairs of a symmetric m x m matrix A (device, contiguous) by the
 // tridiagonal route of the AVO step: evals ascending, Y[i*m + k] = component i
-// of eigenvector k.  Scratch ws: 4 m^2 + 3 m doubles.
+// of eigenvector k.  Scratch ws: 2 m^2 + 3 m doubles (m <= TRI_MAX).
 static esmp2_status sym_eig(esmp2_handle h, hipStream_t s, const double* A, int m, double* evals, double* Y,
                             double* ws) {
   if (m <= 0) return ESMP2_OK;
   double* refl = ws;
-  double* Yt = refl + (size_t)m * m;
-  double* work = Yt + (size_t)m * m;        // 2 m^2
-  double* vec = work + (size_t)2 * m * m;   // rbeta, d, e
+  double* Zt = refl + (size_t)m * m;        // eigenvectors of the tridiagonal, one per row
+  double* vec = Zt + (size_t)m * m;         // rbeta, d, e
   if (m == 1) {
     hipLaunchKernelGGL(k_eig1, dim3(1), dim3(1), 0, s, A, evals, Y);
     return ESMP2_OK;
   }
+  if (m > TRI_MAX) return fail(h, ESMP2_UNSUPPORTED, "eigenproblem order beyond the tridiagonal solver's limit");
   size_t lt = sizeof(double) * (size_t)m * (m + 1) / 2;
   ESMP2_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lt));
   hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lt, s, A, m, refl, vec, vec + m, vec + 2 * m);
-  hipLaunchKernelGGL(k_tri_eig, dim3(m), dim3(64), 0, s, vec + m, vec + 2 * m, m, evals, Yt, work);
-  hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(64), 0, s, evals, m, Yt);
-  hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), sizeof(double) * m, s, refl, vec, m, Yt, Y);
+  hipLaunchKernelGGL(k_tri_eig, dim3(m), dim3(64), 0, s, vec + m, vec + 2 * m, m, evals, Zt);
+  hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(64), 0, s, evals, m, Zt);
+  hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), 0, s, refl, vec, m, Zt, Y);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
@@ -194,7 +194,7 @@ static esmp2_status launch_semican_eig(esmp2_handle h) {
   double* A = h->rs;                                   // (nv-1)^2 block copy
   double* evals = A + (size_t)nv * nv;
   double* Y = evals + nv;
-  double* ws = Y + (size_t)nv * nv;                    // 4 nv^2 + 3 nv  (rs holds 11 nv^2)
+  double* ws = Y + (size_t)nv * nv;                    // 2 nv^2 + 3 nv  (rs holds 11 nv^2)
   hipLaunchKernelGGL(k_block_copy, dim3(64), dim3(256), 0, s, (const double*)h->Ft, (int64_t)n + 1, n, no - 1, A);
   esmp2_status st = sym_eig(h, s, A, no - 1, evals, Y, ws);
   if (st != ESMP2_OK) return st;
@@ -429,13 +429,10 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     double* Q2 = h->rs;                                 // nv x m
     double* Tt = Q2 + (size_t)nv * nv;                  // nv x m
     double* Fa = Tt + (size_t)nv * nv;                  // m x m
-    double* refl = Fa + (size_t)nv * nv;                // m x m
-    double* Yt = refl + (size_t)nv * nv;                // m x m
-    double* Ym = Yt + (size_t)nv * nv;                  // m x m
-    double* AV = Ym + (size_t)nv * nv;                  // nv x m
-    double* AV2 = AV + (size_t)nv * nv;                 // nv x m
-    double* work = AV2 + (size_t)nv * nv;               // m x 2m
-    double* vec = work + (size_t)2 * nv * nv;           // rbeta, d, e (3 m <= nv*nv); rs holds 11 nv^2
+    double* refl = Fa + (size_t)nv * nv;                // complement reflectors (nv x nv)
+    double* Ym = refl + (size_t)nv * nv;                // m x m
+    double* AV = Ym + (size_t)nv * nv;                  // nv x m; with AV2.. the eigensolver's scratch
+    double* AV2 = AV + (size_t)nv * nv;                 // nv x m  (rs holds 11 nv^2)
     size_t lc = sizeof(double) * 2 * (size_t)nv * no;
     if (m > 0) {   // n_vir == n_occ: no AVOs
     ESMP2_HIP(hipFuncSetAttribute((const void*)k_complement_qr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
@@ -449,12 +446,10 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     g.A = Q2; g.B = Tt; g.C = Fa; g.M = m; g.N = m; g.K = nv;
     g.sAi = 1; g.sAk = m; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
     ESMP2_HIP(gemm(s, 1, g));
-    size_t lt = sizeof(double) * (size_t)m * (m + 1) / 2;
-    ESMP2_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lt));
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lt, s, Fa, m, refl, vec, vec + m, vec + 2 * m);
-    hipLaunchKernelGGL(k_tri_eig, dim3(m), dim3(64), 0, s, vec + m, vec + 2 * m, m, h->evals, Yt, work);
-    hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(64), 0, s, h->evals, m, Yt);
-    hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), sizeof(double) * m, s, refl, vec, m, Yt, Ym);
+    {
+      const esmp2_status st = sym_eig(h, s, Fa, m, h->evals, Ym, AV);   // 2 m^2 + 3 m <= 6 nv^2 free from AV on
+      if (st != ESMP2_OK) return st;
+    }
     g = GemmArgs{};
     g.A = Q2; g.B = Ym; g.C = AV; g.M = nv; g.N = m; g.K = m;
     g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;

@@ -1,8 +1,10 @@
 // Dense linear algebra for the TOP-basis rotation (paper Sec. II.A):
 //   - a batched FP64 matrix-core GEMM with arbitrary strides,
 //   - one-sided Jacobi SVD of the singles coefficients C (n_occ x n_vir),
-//   - cyclic Jacobi eigensolver for the Fock matrix restricted to the span of
-//     the additional virtual orbitals (semicanonical AVOs),
+//   - a symmetric eigensolver (Householder tridiagonalisation, multisection on
+//     Sturm counts, twisted-factorisation eigenvectors) for the Fock matrix
+//     restricted to the span of the additional virtual orbitals (semicanonical
+//     AVOs) and to the non-pinned occupied and virtual orbitals,
 //   - assembly of the orthogonal rotation R.
 #include "common.h"
 #include "mfma.h"
@@ -383,140 +385,203 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
   if (m == 1 && tid == 0) e[0] = 0.0;
 }
 
-// Number of eigenvalues of the tridiagonal (d, e) smaller than x.
-__device__ inline int sturm_count(const double* d, const double* e, int m, double x, double tiny) {
+// Largest tridiagonal order the eigensolver stages in LDS (callers keep m below it).
+constexpr int TRI_MAX = 256;
+
+// Number of eigenvalues of the tridiagonal (d, e) smaller than x; e2 = e^2.
+// d and e2 live in LDS (all lanes read the same element: a broadcast).
+__device__ inline int sturm_count(const double* d, const double* e2, int m, double x, double tiny) {
   int cnt = 0;
   double q = d[0] - x;
   if (q < 0) ++cnt;
   for (int i = 1; i < m; ++i) {
     if (fabs(q) < tiny) q = -tiny;
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    q = d[i] - x - e2[i - 1] / q;
     if (q < 0) ++cnt;
   }
   return cnt;
 }
 
-// One workgroup (64 threads) per eigenvalue k (ascending).  evals[k], Yt[:, k].
-__global__ __launch_bounds__(64) void k_tri_eig(const double* d, const double* e, int m, double* evals,
-                                                double* Yt, double* work) {
+// One workgroup (64 threads) per eigenvalue k (ascending): evals[k], and the
+// eigenvector into Z[k*m + i] (row k of Z).  m <= TRI_MAX.
+__global__ __launch_bounds__(64) void k_tri_eig(const double* d, const double* e, int m, double* evals, double* Z) {
   const int k = blockIdx.x, l = threadIdx.x;
-  __shared__ double lo_s, hi_s;
-  if (l == 0) {
-    double lo = 1e300, hi = -1e300;
-    for (int i = 0; i < m; ++i) {
-      double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0);
-      lo = fmin(lo, d[i] - r);
-      hi = fmax(hi, d[i] + r);
-    }
-    double span = fmax(hi - lo, 1e-300);
-    lo_s = lo - 1e-3 * span;
-    hi_s = hi + 1e-3 * span;
+  __shared__ double ds[TRI_MAX], es[TRI_MAX], e2s[TRI_MAX];
+  __shared__ double Dp[TRI_MAX], Dm[TRI_MAX], y[TRI_MAX];
+  for (int i = l; i < m; i += 64) {
+    ds[i] = d[i];
+    es[i] = e[i];
+    e2s[i] = e[i] * e[i];
   }
   __syncthreads();
-  double lo = lo_s, hi = hi_s;
+  // Gershgorin interval
+  double lo = 1e300, hi = -1e300;
+  for (int i = l; i < m; i += 64) {
+    const double r = (i > 0 ? fabs(es[i - 1]) : 0.0) + (i < m - 1 ? fabs(es[i]) : 0.0);
+    lo = fmin(lo, ds[i] - r);
+    hi = fmax(hi, ds[i] + r);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+  }
+  {
+    const double span = fmax(hi - lo, 1e-300);
+    lo -= 1e-3 * span;
+    hi += 1e-3 * span;
+  }
   const double tnorm = fmax(fabs(lo), fabs(hi));
   const double tiny = 1e-300 + 1e-30 * tnorm;
+  // multisection: 64 Sturm counts per step shrink the bracket of eigenvalue k 65-fold
   for (int it = 0; it < 40; ++it) {
-    double x = lo + (hi - lo) * (double)(l + 1) / 65.0;
-    int c = sturm_count(d, e, m, x, tiny);
+    const double x = lo + (hi - lo) * (double)(l + 1) / 65.0;
+    const int c = sturm_count(ds, e2s, m, x, tiny);
     // first lane whose point has more than k eigenvalues below it
-    unsigned long long mask = __ballot(c > k);
-    int first = mask ? __ffsll((long long)mask) - 1 : 64;
-    double nlo = (first == 0) ? lo : lo + (hi - lo) * (double)first / 65.0;
-    double nhi = (first == 64) ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
+    const unsigned long long mask = __ballot(c > k);
+    const int first = mask ? __ffsll((long long)mask) - 1 : 64;
+    const double nlo = (first == 0) ? lo : lo + (hi - lo) * (double)first / 65.0;
+    const double nhi = (first == 64) ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
     lo = nlo;
     hi = nhi;
     if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
   }
   const double lam = 0.5 * (lo + hi);
-  if (l == 0) {
-    evals[k] = lam;
-    // twisted factorisation of T - lam: forward D+ and backward D- pivots
-    double* Dp = work + (size_t)k * 2 * m;
-    double* Dm = Dp + m;
-    Dp[0] = d[0] - lam;
-    for (int i = 1; i < m; ++i) {
-      double q = Dp[i - 1];
+  // twisted factorisation of T - lam: lane 0 runs the forward pivots D+, lane 1
+  // the backward pivots D- (the same recurrence on the reversed arrays)
+  if (l < 2) {
+    const bool fw = (l == 0);
+    double* D = fw ? Dp : Dm;
+    int i0 = fw ? 0 : m - 1;
+    double q = ds[i0] - lam;
+    D[i0] = q;
+    for (int s = 1; s < m; ++s) {
+      const int i = fw ? s : m - 1 - s;
+      const double ee = fw ? e2s[i - 1] : e2s[i];
       if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
-      Dp[i] = d[i] - lam - e[i - 1] * e[i - 1] / q;
+      q = ds[i] - lam - ee / q;
+      D[i] = q;
     }
-    Dm[m - 1] = d[m - 1] - lam;
-    for (int i = m - 2; i >= 0; --i) {
-      double q = Dm[i + 1];
-      if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
-      Dm[i] = d[i] - lam - e[i] * e[i] / q;
-    }
-    int r = 0;
-    double best = 1e300;
-    for (int i = 0; i < m; ++i) {
-      double g = fabs(Dp[i] + Dm[i] - (d[i] - lam));
-      if (g < best) { best = g; r = i; }
-    }
-    double* y = Yt;   // column k, stride m
-    y[r * m + k] = 1.0;
-    double nrm = 1.0;
-    for (int i = r - 1; i >= 0; --i) {
-      double q = Dp[i];
-      if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
-      double v = -(e[i] / q) * y[(i + 1) * m + k];
-      y[i * m + k] = v;
-      nrm += v * v;
-    }
-    for (int i = r + 1; i < m; ++i) {
-      double q = Dm[i];
-      if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
-      double v = -(e[i - 1] / q) * y[(i - 1) * m + k];
-      y[i * m + k] = v;
-      nrm += v * v;
-    }
-    double inv = 1.0 / sqrt(nrm);
-    for (int i = 0; i < m; ++i) y[i * m + k] *= inv;
   }
+  __syncthreads();
+  // twist index r: smallest |gamma_i| = |D+_i + D-_i - (d_i - lam)|
+  double best = 1e300;
+  int r = m;
+  for (int i = l; i < m; i += 64) {
+    const double g = fabs(Dp[i] + Dm[i] - (ds[i] - lam));
+    if (g < best) { best = g; r = i; }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o);
+    const int orr = __shfl_xor(r, o);
+    if (ob < best || (ob == best && orr < r)) { best = ob; r = orr; }
+  }
+  if (r >= m) r = 0;
+  // eigenvector: 1 at r, lane 0 recurs downwards from r, lane 1 upwards
+  if (l < 2) {
+    const bool dn = (l == 0);
+    if (dn) y[r] = 1.0;
+    double v = 1.0;
+    if (dn) {
+      for (int i = r - 1; i >= 0; --i) {
+        double q = Dp[i];
+        if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
+        v = -(es[i] / q) * v;
+        y[i] = v;
+      }
+    } else {
+      for (int i = r + 1; i < m; ++i) {
+        double q = Dm[i];
+        if (fabs(q) < tiny) q = (q < 0 ? -tiny : tiny);
+        v = -(es[i - 1] / q) * v;
+        y[i] = v;
+      }
+    }
+  }
+  __syncthreads();
+  double nrm = 0.0;
+  for (int i = l; i < m; i += 64) nrm += y[i] * y[i];
+  nrm = wave_sum(nrm);
+  const double inv = 1.0 / sqrt(nrm);
+  if (l == 0) evals[k] = lam;
+  for (int i = l; i < m; i += 64) Z[(size_t)k * m + i] = y[i] * inv;
 }
 
 // Gram-Schmidt of eigenvectors inside clusters (relative gap below 1e-6).
 // Single workgroup of 64 threads; cheap when there are no clusters.
-__global__ __launch_bounds__(64) void k_cluster_mgs(const double* evals, int m, double* Yt) {
+__global__ __launch_bounds__(64) void k_cluster_mgs(const double* evals, int m, double* Z) {
   const int l = threadIdx.x;
   double tn = 0.0;
   for (int k = 0; k < m; ++k) tn = fmax(tn, fabs(evals[k]));
   int start = 0;
   for (int k = 1; k < m; ++k) {
     if (evals[k] - evals[k - 1] > 1e-6 * tn) { start = k; continue; }
+    double* zk = Z + (size_t)k * m;
     for (int pass = 0; pass < 2; ++pass)
       for (int j = start; j < k; ++j) {
+        const double* zj = Z + (size_t)j * m;
         double t = 0.0;
-        for (int i = l; i < m; i += 64) t += Yt[i * m + j] * Yt[i * m + k];
+        for (int i = l; i < m; i += 64) t += zj[i] * zk[i];
         t = wave_sum(t);
-        for (int i = l; i < m; i += 64) Yt[i * m + k] -= t * Yt[i * m + j];
+        for (int i = l; i < m; i += 64) zk[i] -= t * zj[i];
         __syncthreads();
       }
     double s = 0.0;
-    for (int i = l; i < m; i += 64) s += Yt[i * m + k] * Yt[i * m + k];
+    for (int i = l; i < m; i += 64) s += zk[i] * zk[i];
     s = wave_sum(s);
     double inv = 1.0 / sqrt(s);
-    for (int i = l; i < m; i += 64) Yt[i * m + k] *= inv;
+    for (int i = l; i < m; i += 64) zk[i] *= inv;
     __syncthreads();
   }
 }
 
-// Y[:, k] = G_0 ... G_{m-3} Yt[:, k]; one workgroup (64 threads) per column.
+// Y[:, k] = G_0 ... G_{m-3} Z[k, :]; one workgroup (64 threads) per column.
+// Each lane keeps its entries of the column (i = l + 64 s) in registers and
+// has the next reflector's entries in flight while it applies the current one.
 __global__ __launch_bounds__(64) void k_backtransform(const double* refl, const double* rbeta, int m,
-                                                      const double* Yt, double* Y) {
-  extern __shared__ double y[];
+                                                      const double* Z, double* Y) {
+  constexpr int S = TRI_MAX / 64;
   const int k = blockIdx.x, l = threadIdx.x;
-  for (int i = l; i < m; i += 64) y[i] = Yt[i * m + k];
-  __syncthreads();
-  for (int j = m - 3; j >= 0; --j) {
-    double b = rbeta[j];
-    if (b == 0.0) continue;
-    double t = 0.0;
-    for (int i = l; i < m; i += 64) if (i > j) t += refl[j * m + i] * y[i];
-    t = wave_sum(t) * b;
-    for (int i = l; i < m; i += 64) if (i > j) y[i] -= t * refl[j * m + i];
-    __syncthreads();
+  double y[S], cur[S], nxt[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = l + 64 * s;
+    y[s] = (i < m) ? Z[(size_t)k * m + i] : 0.0;
   }
-  for (int i = l; i < m; i += 64) Y[i * m + k] = y[i];
+  const int j0 = m - 3;
+  if (j0 >= 0) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int i = l + 64 * s;
+      cur[s] = (i < m && i > j0) ? refl[(size_t)j0 * m + i] : 0.0;
+    }
+  }
+  for (int j = j0; j >= 0; --j) {
+    const double b = rbeta[j];
+    if (j > 0) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int i = l + 64 * s;
+        nxt[s] = (i < m && i > j - 1) ? refl[(size_t)(j - 1) * m + i] : 0.0;
+      }
+    }
+    if (b != 0.0) {
+      double t = 0.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) t += cur[s] * y[s];
+      t = wave_sum(t) * b;
+#pragma unroll
+      for (int s = 0; s < S; ++s) y[s] -= t * cur[s];
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) cur[s] = nxt[s];
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int i = l + 64 * s;
+    if (i < m) Y[(size_t)i * m + k] = y[s];
+  }
 }
 
 // R[:no,:no] = U,  R[no:, no:2no] = V,  R[no:, 2no + c] = AVO[:, c] (signed:
