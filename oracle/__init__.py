@@ -16,6 +16,9 @@ Two tiers, both plain FP64:
   ``explicit`` by brute force and runs at every workload size.
 
 ``topbasis`` rotates the input to the transition-orbital-pair (TOP) basis,
-``layout`` maps the seven-box layout to determinants and ``frontend`` builds
-the Fock operator of the reference's density from the one-electron operator.
+``layout`` maps the seven-box layout to determinants, ``frontend`` builds
+the Fock operator of the reference's density from the one-electron operator
+and ``gradient`` differentiates E2 with respect to the TOP-basis Fock matrix
+and factor (stationary functional at fixed amplitudes, exact central
+differences).
 """

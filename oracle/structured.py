@@ -415,11 +415,16 @@ class RHS:
     # -- E2_S: direct inversion over the S-triples --------------------------
     def e2_s(self):
         """-sum over S-triple determinants of b^2 / D (both spin-flip partners)."""
+        return -sum(2.0 * np.sum(b * b / D) for b, D in self.s_terms())
+
+    def s_terms(self):
+        """(b, D) arrays over the S-triple determinants, chunk by chunk in a
+        fixed order; each determinant stands for itself and its spin-flip
+        partner, which has the same b and D."""
         no, nv = self.no, self.nv
         c, V = self.c, self.V
         eo, ev = np.diag(self.op.fo), np.diag(self.op.fv)
         om = self.op.omega
-        total = 0.0
         # ---- same-spin sector (up up up; x2 for down down down) --------------
         # enumerated by the smallest TOP l contained; t = 0 excluded.
         for l in range(1, no):
@@ -453,7 +458,7 @@ class RHS:
                     anti = V[i1, a1, i2, a2] - V[i2, a1, i1, a2]
                     b[hit] += (-1) ** (p + qq) * c[I[hit][:, qq]] * anti
             D = ev[A].sum(1) - eo[I].sum(1) - om
-            total += 2.0 * np.sum(b * b / D)
+            yield b, D
         # ---- mixed sector (up; down down), x2 for its flip ---------------------
         occ_pairs = np.array([(j, k) for j in range(no) for k in range(j + 1, no)]).reshape(-1, 2)
         vir_pairs = np.array([(b, cc) for b in range(nv) for cc in range(b + 1, nv)]).reshape(-1, 2)
@@ -492,8 +497,7 @@ class RHS:
                 m = cc == kk
                 b[m] += c[kk[m]] * V[i, a, jj[m], bb[m]]
                 D = ev[a] + ev[bb] + ev[cc] - eo[i] - eo[jj] - eo[kk] - om
-                total += 2.0 * np.sum(b * b / D)
-        return -total
+                yield b, D
 
 
 # ---------------------------------------------------------------------------

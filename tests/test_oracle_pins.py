@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import explicit, frontend, layout, structured, topbasis
+from oracle import explicit, frontend, gradient, layout, structured, topbasis
 
 MICRO = [(2, 4, 6, 0), (3, 5, 8, 1), (3, 6, 8, 2), (4, 6, 10, 3), (4, 7, 9, 4)]
 
@@ -398,3 +398,68 @@ def test_reference_density_and_fock(no, nv, seed):
     d[:no] = 2 - lam ** 2
     d[no:2 * no] = lam ** 2
     np.testing.assert_allclose(gt, np.diag(d), rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# derivatives of E2 (TOP-basis Fock matrix and factor, rotation held fixed)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("no,nv,na,seed", [(3, 6, 5, 1), (2, 5, 4, 3)])
+def test_gradient_equals_full_resolve_differences(no, nv, na, seed):
+    """The derivative of the functional at fixed amplitudes (the adjoint of
+    the symmetric first-order equation is its own solution) equals the
+    central difference of E2 itself, re-solved at each displaced point, on
+    entries of every Fock block and of every factor block."""
+    _, lam, Ft, Bt = _rotated(no, nv, na, seed)
+    L = gradient.Lagrangian(Ft, Bt, lam, no)
+    assert abs(L.value() - L.e2) < 1e-15                       # the functional's value is E2
+    n = no + nv
+    h = 1e-5
+    f_entries = [(0, 0), (1, 1), (0, no), (no, no), (1, no + 2), (no + 1, n - 1), (0, 1), (no + 2, no + 2)]
+    for p, q in f_entries:
+        E = np.zeros_like(Ft)
+        E[p, q] = E[q, p] = h
+        fd = (gradient.e2_of(Ft + E, Bt, lam, no) - gradient.e2_of(Ft - E, Bt, lam, no)) / (2 * h)
+        fd /= 1.0 if p == q else 2.0
+        g = L.grad_F(p, q)
+        assert abs(g - fd) <= 1e-7 * max(abs(fd), 1e-4), (p, q, g, fd)
+    b_entries = [(0, 0, no), (1, 1, no + 1), (na - 1, 0, 0), (2, no, n - 1), (0, 1, 1), (1, 0, 1), (2, no, no + 1)]
+    for Q, p, q in b_entries:
+        E = np.zeros_like(Bt)
+        E[Q, p, q] = E[Q, q, p] = h
+        fd = (gradient.e2_of(Ft, Bt + E, lam, no) - gradient.e2_of(Ft, Bt - E, lam, no)) / (2 * h)
+        fd /= 1.0 if p == q else 2.0
+        g = L.grad_B(Q, p, q)
+        assert abs(g - fd) <= 1e-7 * max(abs(fd), 1e-4), (Q, p, q, g, fd)
+
+
+def test_gradient_differences_are_exact():
+    """At fixed amplitudes the functional is linear in F~ and of degree two in
+    each factor entry: its second (F) and third (B) differences vanish, so
+    central differences give the exact derivative for any step."""
+    no = 3
+    _, lam, Ft, Bt = _rotated(no, 6, 5, 4)
+    L = gradient.Lagrangian(Ft, Bt, lam, no)
+    E = np.zeros_like(Ft)
+    E[1, 5] = E[5, 1] = 0.05
+    assert abs(L.value(Ft=Ft + E) - 2 * L.value() + L.value(Ft=Ft - E)) < 1e-15
+    E = np.zeros_like(Bt)
+    E[2, 1, 5] = E[2, 5, 1] = 0.05
+    vals = [L.value(Bt=Bt + k * E) for k in (-1, 0, 1, 2)]
+    assert abs(vals[3] - 3 * vals[2] + 3 * vals[1] - vals[0]) < 1e-15
+    assert abs(L.grad_B(2, 1, 5, h=1e-1) - L.grad_B(2, 1, 5, h=1e-4)) < 1e-12
+
+
+def test_gradient_homogeneity():
+    """H scales by s when F~ -> s F~ and B~ -> sqrt(s) B~, and E2 with it
+    (b, A, D_S and b_S all scale by s), so Euler's theorem fixes
+    <F~, dE2/dF~> + <B~, dE2/dB~> / 2 = E2 over the whole gradient."""
+    no = 3
+    _, lam, Ft, Bt = _rotated(no, 5, 4, 6)
+    L = gradient.Lagrangian(Ft, Bt, lam, no)
+    GF, GB = L.full_gradient()
+    assert np.allclose(GF, GF.T, rtol=0, atol=0) and np.allclose(GB, GB.transpose(0, 2, 1), rtol=0, atol=0)
+    euler = np.sum(Ft * GF) + 0.5 * np.sum(Bt * GB)
+    assert abs(euler - L.e2) < 1e-13 * max(1.0, abs(L.e2)) + 1e-15
+    # and directly: E2(s F~, sqrt(s) B~) = s E2
+    s = 1.7
+    assert abs(gradient.e2_of(s * Ft, np.sqrt(s) * Bt, lam, no) - s * L.e2) < 1e-14
