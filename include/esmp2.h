@@ -132,6 +132,22 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux,
                                const double* F, const double* B, const double* C,
                                int spin, int n_top);
 
+/* Bind a problem stated in the TOP basis already (paper Sec. II.A: the basis in
+ * which the singles coefficients are diagonal), for a caller that holds the
+ * rotated quantities, e.g. to differentiate E2 with respect to them:
+ *   Ft: device, N x N row-major, symmetric: the TOP-basis Fock matrix, occupied
+ *       orbitals first (t = occupied 0), then the virtuals (t' = virtual 0, the
+ *       partner of occupied l is virtual l for l < n_occ)
+ *   Bt: device, n_aux x N x N row-major, symmetric in its orbital pair
+ *   lam: device or host, n_occ singular values, lam[0] the largest, all >= 0,
+ *        sum lam^2 = 1 (within 1e-10)
+ * Copies the inputs (the caller keeps ownership), checks them for NaN/Inf and
+ * synchronises.  esmp2_rotate_top then keeps the basis as given (identity
+ * rotation, lambda_out reports lam); everything else is as after
+ * esmp2_set_problem.  Resets any previous problem. */
+esmp2_status esmp2_set_problem_top(esmp2_handle h, int n_occ, int n_vir, int n_aux,
+                                   const double* Ft, const double* Bt, const double* lam);
+
 /* Rotate to the TOP basis (paper Sec. II.A).  lambda_out: host, n_occ doubles
  * (descending singular values) or NULL; when non-NULL the call synchronises. */
 esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out);
@@ -171,6 +187,25 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision);
  * are amplitudes of the TOP basis (rotated on the way in and out). */
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
                          esmp2_solve_result* result);
+
+/* Derivatives of E2 (paper Sec. II.C-II.D) with respect to the TOP-basis Fock
+ * matrix F~ and factor B~, with the rotation and lam held fixed.  E2_DL is the
+ * stationary value of 2 <b, x>_W + <x, A x>_W at the solution x of A x = -b; A is
+ * symmetric, so the adjoint solution is x itself and
+ *   dE2 = 2 <x, db>_W + <x, dA x>_W + dE2_S       (x held fixed),
+ * evaluated without a second solve.
+ *   x: device, n_amp doubles: the TOP-basis solution (esmp2_solve's x_out) of the
+ *      problem whose right-hand side was built last; its accuracy bounds the
+ *      gradient's (the error is first order in the residual)
+ *   dF: device, N x N, or NULL; dB: device, n_aux x N x N, or NULL (not both).
+ * Both outputs are symmetric and hold G with dE2 = sum_pq G[p][q] dF[p][q] for
+ * every symmetric perturbation (per auxiliary index for B~); entries that E2
+ * does not depend on are zero.  Requires esmp2_build_rhs.  Allocates a
+ * workspace on first use (about 8 n_occ^2 n_vir^2 + 2 (n_occ n_vir)^2 doubles,
+ * kept by the handle) and queues the work on the handle's stream without
+ * synchronising.  The scatter steps use FP64 atomic adds, so the last bits
+ * may differ between runs. */
+esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double* dB);
 
 /* The Fock operator of the reference's one-body density (paper Sec. II.C: the
  * zeroth-order Hamiltonian uses the Fock operator of Psi0's density), for a

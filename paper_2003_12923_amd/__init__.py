@@ -9,3 +9,4 @@ from ._lib import (ESMP2_OK, ESMP2_INVALID_ARG, ESMP2_BAD_ORDER, ESMP2_NOT_SPD, 
                    ESMP2_NOT_CONVERGED, ESMP2_OOM, ESMP2_HIP_ERROR, ESMP2_UNSUPPORTED,
                    ESMP2_FP64, ESMP2_FP32, ESMP2_BASIS_TOP, ESMP2_BASIS_SEMICANONICAL, Esmp2Error,
                    Handle, lib, LIB_PATH, solve_batch)
+from .autograd import e2_top  # noqa: F401,E402

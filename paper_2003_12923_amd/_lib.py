@@ -47,6 +47,8 @@ _sig = {
                           C.c_int),
     "esmp2_fock_from_core": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
                              C.c_int),
+    "esmp2_set_problem_top": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "esmp2_gradient": ([_H, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "esmp2_last_error": ([_H], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -62,7 +64,13 @@ class Esmp2Error(RuntimeError):
 
 
 def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+    """Device address of a tensor; the C ABI takes dense row-major arrays, so a
+    strided view is refused rather than read in the wrong order."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor arguments must be contiguous (row-major)")
+    return C.c_void_p(t.data_ptr())
 
 
 class Handle:
@@ -98,8 +106,17 @@ class Handle:
             pass
 
     def set_problem(self, F, B, Cm, n_occ, n_vir, n_aux, spin=0, n_top=1):
+        self._n_occ = n_occ
         return self._check(lib.esmp2_set_problem(self.h, n_occ, n_vir, n_aux, _ptr(F), _ptr(B),
                                                  _ptr(Cm), spin, n_top))
+
+    def set_problem_top(self, Ft, Bt, lam, n_occ, n_vir, n_aux):
+        self._n_occ = n_occ
+        return self._check(lib.esmp2_set_problem_top(self.h, n_occ, n_vir, n_aux, _ptr(Ft), _ptr(Bt), _ptr(lam)))
+
+    def gradient(self, x, dF=None, dB=None):
+        """dE2/dF~ into dF (N x N) and dE2/dB~ into dB (n_aux x N x N), either may be None."""
+        return self._check(lib.esmp2_gradient(self.h, _ptr(x), _ptr(dF), _ptr(dB)))
 
     def rotate_top(self, lam_out=True):
         import numpy as np

@@ -64,6 +64,9 @@ struct esmp2_handle_ {
   hipStream_t stream = nullptr;
   std::string err = "no error";
   int state = 0;                 // 0 empty, 1 problem set, 2 rotated, 3 rhs built
+  bool top_given = false;        // the problem was stated in the TOP basis (no rotation)
+  double* gws = nullptr;         // workspace of the gradient (allocated on first use)
+  size_t gws_n = 0;
   Dims d{};
   std::vector<void*> allocs;     // everything owned, freed at reset/destroy
   // inputs
@@ -143,6 +146,8 @@ static void release(esmp2_handle h) {
   h->have_sc = false;
   h->sc_pending = false;
   h->sc_eig = false;
+  h->gws = nullptr;
+  h->gws_n = 0;
 }
 
 template <class T>
@@ -276,16 +281,19 @@ esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A
   return ESMP2_OK;
 }
 
-esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* F,
-                               const double* B, const double* C, int spin, int n_top) {
-  if (!h) return ESMP2_INVALID_ARG;
-  if (!F || !B || !C) return fail(h, ESMP2_INVALID_ARG, "null input pointer");
+static esmp2_status check_sizes(esmp2_handle h, int n_occ, int n_vir, int n_aux) {
   if (n_occ < 2 || n_vir < n_occ || n_aux < 1)
     return fail(h, ESMP2_INVALID_ARG, "need 2 <= n_occ <= n_vir and n_aux >= 1");
   if (n_occ > 64 || (int64_t)n_occ * n_vir > 8192 || n_vir > 192)
     return fail(h, ESMP2_UNSUPPORTED, "sizes beyond n_occ <= 64, n_occ*n_vir <= 8192, n_vir <= 192");
-  if (spin != 0) return fail(h, ESMP2_UNSUPPORTED, "only the singlet (spin = 0) is implemented");
-  if (n_top != 1) return fail(h, ESMP2_UNSUPPORTED, "only n_top = 1 (ESMP2-TOP(1)) is implemented");
+  return ESMP2_OK;
+}
+
+// Allocation, tables and input copies shared by both ways of stating a problem:
+// either C (the ESMF singles, rotated to the TOP basis later) or, for a problem
+// already in the TOP basis, its singular values lam.
+static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* F,
+                                  const double* B, const double* C, const double* lam) {
   ESMP2_HIP(hipSetDevice(h->device));
   ESMP2_HIP(hipStreamSynchronize(h->stream));
   release(h);
@@ -390,19 +398,51 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
   ESMP2_HIP(hipMemcpyAsync(h->jobs, jobs.data(), jobs.size() * sizeof(int2), hipMemcpyHostToDevice, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->F, F, sizeof(double) * n * n, hipMemcpyDefault, h->stream));
   ESMP2_HIP(hipMemcpyAsync(h->B, B, sizeof(double) * (size_t)na * n * n, hipMemcpyDefault, h->stream));
-  ESMP2_HIP(hipMemcpyAsync(h->C, C, sizeof(double) * no * nv, hipMemcpyDefault, h->stream));
+  if (C) ESMP2_HIP(hipMemcpyAsync(h->C, C, sizeof(double) * no * nv, hipMemcpyDefault, h->stream));
+  else ESMP2_HIP(hipMemcpyAsync(h->lam, lam, sizeof(double) * no, hipMemcpyDefault, h->stream));
   // NaN / Inf check
   int* bad = h->iinfo;
   ESMP2_HIP(hipMemsetAsync(bad, 0, sizeof(int), h->stream));
   hipLaunchKernelGGL(k_finite, dim3(256), dim3(256), 0, h->stream, h->F, (int64_t)n * n, bad);
   hipLaunchKernelGGL(k_finite, dim3(1024), dim3(256), 0, h->stream, h->B, (int64_t)na * n * n, bad);
-  hipLaunchKernelGGL(k_finite, dim3(64), dim3(256), 0, h->stream, h->C, (int64_t)no * nv, bad);
+  if (C) hipLaunchKernelGGL(k_finite, dim3(64), dim3(256), 0, h->stream, h->C, (int64_t)no * nv, bad);
+  else hipLaunchKernelGGL(k_finite, dim3(1), dim3(64), 0, h->stream, h->lam, (int64_t)no, bad);
   int hbad = 0;
   ESMP2_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   ESMP2_HIP(hipStreamSynchronize(h->stream));
-  if (hbad) { release(h); return fail(h, ESMP2_INVALID_ARG, "NaN or Inf in F, B or C"); }
+  if (hbad) { release(h); return fail(h, ESMP2_INVALID_ARG, C ? "NaN or Inf in F, B or C" : "NaN or Inf in F, B or lam"); }
+  h->top_given = (C == nullptr);
   h->state = 1;
   return ESMP2_OK;
+}
+
+esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* F,
+                               const double* B, const double* C, int spin, int n_top) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (!F || !B || !C) return fail(h, ESMP2_INVALID_ARG, "null input pointer");
+  esmp2_status st = check_sizes(h, n_occ, n_vir, n_aux);
+  if (st != ESMP2_OK) return st;
+  if (spin != 0) return fail(h, ESMP2_UNSUPPORTED, "only the singlet (spin = 0) is implemented");
+  if (n_top != 1) return fail(h, ESMP2_UNSUPPORTED, "only n_top = 1 (ESMP2-TOP(1)) is implemented");
+  return setup_problem(h, n_occ, n_vir, n_aux, F, B, C, nullptr);
+}
+
+esmp2_status esmp2_set_problem_top(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* Ft,
+                                   const double* Bt, const double* lam) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (!Ft || !Bt || !lam) return fail(h, ESMP2_INVALID_ARG, "null input pointer");
+  esmp2_status st = check_sizes(h, n_occ, n_vir, n_aux);
+  if (st != ESMP2_OK) return st;
+  std::vector<double> l(n_occ);
+  ESMP2_HIP(hipSetDevice(h->device));
+  ESMP2_HIP(hipMemcpy(l.data(), lam, sizeof(double) * n_occ, hipMemcpyDefault));
+  double s2 = 0.0;
+  for (int k = 0; k < n_occ; ++k) {
+    if (!(l[k] >= 0.0) || !(l[k] <= l[0])) return fail(h, ESMP2_INVALID_ARG, "lam must be >= 0 with lam[0] the largest");
+    s2 += l[k] * l[k];
+  }
+  if (!(fabs(s2 - 1.0) <= 1e-10)) return fail(h, ESMP2_INVALID_ARG, "sum of lam^2 must be 1 (normalised reference)");
+  return setup_problem(h, n_occ, n_vir, n_aux, Ft, Bt, nullptr, lam);
 }
 
 esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
@@ -418,65 +458,73 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     h->sc_pending = false;
   }
   h->sc_eig = false;
-  // SVD of C
-  size_t lds = sizeof(double) * (no * nv + no * no);
-  ESMP2_HIP(hipFuncSetAttribute((const void*)k_svd_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_svd_jacobi, dim3(1), dim3(1024), lds, s, h->C, no, nv, h->lam, h->U, h->V, h->iinfo);
-  // semicanonical AVOs: complement of the TOP virtuals, F restricted to it,
-  // tridiagonal eigensolver, back-transformation, Loewdin re-orthonormalisation
-  {
-    const int m = nv - no;
-    double* Q2 = h->rs;                                 // nv x m
-    double* Tt = Q2 + (size_t)nv * nv;                  // nv x m
-    double* Fa = Tt + (size_t)nv * nv;                  // m x m
-    double* refl = Fa + (size_t)nv * nv;                // complement reflectors (nv x nv)
-    double* Ym = refl + (size_t)nv * nv;                // m x m
-    double* AV = Ym + (size_t)nv * nv;                  // nv x m; with AV2.. the eigensolver's scratch
-    double* AV2 = AV + (size_t)nv * nv;                 // nv x m  (rs holds 11 nv^2)
-    size_t lc = sizeof(double) * 2 * (size_t)nv * no;
-    if (m > 0) {   // n_vir == n_occ: no AVOs
-    ESMP2_HIP(hipFuncSetAttribute((const void*)k_complement_qr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
-    hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), lc, s, (const double*)h->V, nv, no, refl);
-    if (m > 0) hipLaunchKernelGGL(k_complement_apply, dim3(m), dim3(64), 0, s, (const double*)refl, nv, no, Q2);
-    GemmArgs g{};
-    g.A = h->F + (int64_t)no * n + no; g.B = Q2; g.C = Tt; g.M = nv; g.N = m; g.K = nv;
-    g.sAi = n; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
-    ESMP2_HIP(gemm(s, 1, g));
-    g = GemmArgs{};
-    g.A = Q2; g.B = Tt; g.C = Fa; g.M = m; g.N = m; g.K = nv;
-    g.sAi = 1; g.sAk = m; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
-    ESMP2_HIP(gemm(s, 1, g));
-    {
-      const esmp2_status st = sym_eig(h, s, Fa, m, h->evals, Ym, AV);   // 2 m^2 + 3 m <= 6 nv^2 free from AV on
-      if (st != ESMP2_OK) return st;
-    }
-    g = GemmArgs{};
-    g.A = Q2; g.B = Ym; g.C = AV; g.M = nv; g.N = m; g.K = m;
-    g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
-    ESMP2_HIP(gemm(s, 1, g));
-    // one first-order Loewdin step: AV <- AV - AV (AV^T AV - 1) / 2
-    g = GemmArgs{};
-    g.A = AV; g.B = AV; g.C = Fa; g.M = m; g.N = m; g.K = nv;
-    g.sAi = 1; g.sAk = m; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
-    ESMP2_HIP(gemm(s, 1, g));
-    hipLaunchKernelGGL(k_sub_identity, dim3(nblk(m)), dim3(256), 0, s, Fa, m);
-    ESMP2_HIP(hipMemcpyAsync(AV2, AV, sizeof(double) * nv * m, hipMemcpyDeviceToDevice, s));
-    g = GemmArgs{};
-    g.A = AV; g.B = Fa; g.C = AV2; g.M = nv; g.N = m; g.K = m;
-    g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = -0.5; g.beta = 1.0;
-    ESMP2_HIP(gemm(s, 1, g));
-    }
-    hipLaunchKernelGGL(k_assemble_r2, dim3(1), dim3(1024), 0, s, h->U, h->V, AV2, h->evals, no, nv, h->R, h->avo);
-  }
-  // F~ = R^T F R
   GemmArgs g{};
-  g.A = h->F; g.B = h->R; g.C = h->T; g.M = n; g.N = n; g.K = n;
-  g.sAi = n; g.sAk = 1; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, 1, g));   // T = F R
-  g = GemmArgs{};
-  g.A = h->R; g.B = h->T; g.C = h->Ft; g.M = n; g.N = n; g.K = n;
-  g.sAi = 1; g.sAk = n; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, 1, g));   // Ft = R^T T
+  if (!h->top_given) {
+    // SVD of C
+    size_t lds = sizeof(double) * (no * nv + no * no);
+    ESMP2_HIP(hipFuncSetAttribute((const void*)k_svd_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_svd_jacobi, dim3(1), dim3(1024), lds, s, h->C, no, nv, h->lam, h->U, h->V, h->iinfo);
+    // semicanonical AVOs: complement of the TOP virtuals, F restricted to it,
+    // tridiagonal eigensolver, back-transformation, Loewdin re-orthonormalisation
+    {
+      const int m = nv - no;
+      double* Q2 = h->rs;                                 // nv x m
+      double* Tt = Q2 + (size_t)nv * nv;                  // nv x m
+      double* Fa = Tt + (size_t)nv * nv;                  // m x m
+      double* refl = Fa + (size_t)nv * nv;                // complement reflectors (nv x nv)
+      double* Ym = refl + (size_t)nv * nv;                // m x m
+      double* AV = Ym + (size_t)nv * nv;                  // nv x m; with AV2.. the eigensolver's scratch
+      double* AV2 = AV + (size_t)nv * nv;                 // nv x m  (rs holds 11 nv^2)
+      size_t lc = sizeof(double) * 2 * (size_t)nv * no;
+      if (m > 0) {   // n_vir == n_occ: no AVOs
+      ESMP2_HIP(hipFuncSetAttribute((const void*)k_complement_qr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
+      hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), lc, s, (const double*)h->V, nv, no, refl);
+      if (m > 0) hipLaunchKernelGGL(k_complement_apply, dim3(m), dim3(64), 0, s, (const double*)refl, nv, no, Q2);
+      GemmArgs g{};
+      g.A = h->F + (int64_t)no * n + no; g.B = Q2; g.C = Tt; g.M = nv; g.N = m; g.K = nv;
+      g.sAi = n; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+      ESMP2_HIP(gemm(s, 1, g));
+      g = GemmArgs{};
+      g.A = Q2; g.B = Tt; g.C = Fa; g.M = m; g.N = m; g.K = nv;
+      g.sAi = 1; g.sAk = m; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+      ESMP2_HIP(gemm(s, 1, g));
+      {
+        const esmp2_status st = sym_eig(h, s, Fa, m, h->evals, Ym, AV);   // 2 m^2 + 3 m <= 6 nv^2 free from AV on
+        if (st != ESMP2_OK) return st;
+      }
+      g = GemmArgs{};
+      g.A = Q2; g.B = Ym; g.C = AV; g.M = nv; g.N = m; g.K = m;
+      g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+      ESMP2_HIP(gemm(s, 1, g));
+      // one first-order Loewdin step: AV <- AV - AV (AV^T AV - 1) / 2
+      g = GemmArgs{};
+      g.A = AV; g.B = AV; g.C = Fa; g.M = m; g.N = m; g.K = nv;
+      g.sAi = 1; g.sAk = m; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+      ESMP2_HIP(gemm(s, 1, g));
+      hipLaunchKernelGGL(k_sub_identity, dim3(nblk(m)), dim3(256), 0, s, Fa, m);
+      ESMP2_HIP(hipMemcpyAsync(AV2, AV, sizeof(double) * nv * m, hipMemcpyDeviceToDevice, s));
+      g = GemmArgs{};
+      g.A = AV; g.B = Fa; g.C = AV2; g.M = nv; g.N = m; g.K = m;
+      g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = -0.5; g.beta = 1.0;
+      ESMP2_HIP(gemm(s, 1, g));
+      }
+      hipLaunchKernelGGL(k_assemble_r2, dim3(1), dim3(1024), 0, s, h->U, h->V, AV2, h->evals, no, nv, h->R, h->avo);
+    }
+    // F~ = R^T F R
+    g = GemmArgs{};
+    g.A = h->F; g.B = h->R; g.C = h->T; g.M = n; g.N = n; g.K = n;
+    g.sAi = n; g.sAk = 1; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, 1, g));   // T = F R
+    g = GemmArgs{};
+    g.A = h->R; g.B = h->T; g.C = h->Ft; g.M = n; g.N = n; g.K = n;
+    g.sAi = 1; g.sAk = n; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, 1, g));   // Ft = R^T T
+  } else {
+    // stated in the TOP basis: the rotation is the identity
+    ESMP2_HIP(hipMemcpyAsync(h->Ft, h->F, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_identity, dim3(nblk((int64_t)n * n)), dim3(256), 0, s, h->R, n);
+    ESMP2_HIP(hipMemsetAsync(h->iinfo, 0, sizeof(int), s));
+  }
   hipLaunchKernelGGL(k_topfock, dim3(nblk((int64_t)mv * mv > n * n ? (int64_t)mv * mv : (int64_t)n * n)), dim3(256),
                      0, s, h->Ft, h->lam, no, nv, mv, h->fo, h->fv, h->fov, h->eo, h->ev, h->Fd, h->Fl, h->sc_rot);
   // the FP32 operator's Fock blocks, rounded from the FP64 ones
@@ -489,41 +537,47 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     esmp2_status st = launch_semican_eig(h);
     if (st != ESMP2_OK) return st;
   }
-  // B~ blocks: Bov = U^T B_ov W, Bvt = W^T B_vv W[:, :no], Boo = U^T B_oo U
-  const int64_t nn = (int64_t)n * n;
-  // T[Q] (no x nv) = B[Q][occ, vir] W
-  g = GemmArgs{};
-  g.A = h->B + no; g.B = h->R + (int64_t)no * n + no; g.C = h->T; g.M = no; g.N = nv; g.K = nv;
-  g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1;
-  g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, na, g));
-  g = GemmArgs{};
-  g.A = h->R; g.B = h->T; g.C = h->Bov; g.M = no; g.N = nv; g.K = no;
-  g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)no * nv; g.sBk = nv; g.sBj = 1;
-  g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1; g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, na, g));
-  // T[Q] (nv x no) = B[Q][vir, vir] W[:, :no]
-  g = GemmArgs{};
-  g.A = h->B + (int64_t)no * n + no; g.B = h->R + (int64_t)no * n + no; g.C = h->T; g.M = nv; g.N = no; g.K = nv;
-  g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1;
-  g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, na, g));
-  g = GemmArgs{};
-  g.A = h->R + (int64_t)no * n + no; g.B = h->T; g.C = h->Bvt; g.M = nv; g.N = no; g.K = nv;
-  g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)nv * no; g.sBk = no; g.sBj = 1;
-  g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1; g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, na, g));
-  // T[Q] (no x no) = B[Q][occ, occ] U ; Boo = U^T T
-  g = GemmArgs{};
-  g.A = h->B; g.B = h->R; g.C = h->T; g.M = no; g.N = no; g.K = no;
-  g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)no * no; g.sCi = no; g.sCj = 1;
-  g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, na, g));
-  g = GemmArgs{};
-  g.A = h->R; g.B = h->T; g.C = h->Boo; g.M = no; g.N = no; g.K = no;
-  g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)no * no; g.sBk = no; g.sBj = 1;
-  g.sCb = (int64_t)no * no; g.sCi = no; g.sCj = 1; g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, na, g));
+  if (!h->top_given) {
+    // B~ blocks: Bov = U^T B_ov W, Bvt = W^T B_vv W[:, :no], Boo = U^T B_oo U
+    const int64_t nn = (int64_t)n * n;
+    // T[Q] (no x nv) = B[Q][occ, vir] W
+    g = GemmArgs{};
+    g.A = h->B + no; g.B = h->R + (int64_t)no * n + no; g.C = h->T; g.M = no; g.N = nv; g.K = nv;
+    g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1;
+    g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, na, g));
+    g = GemmArgs{};
+    g.A = h->R; g.B = h->T; g.C = h->Bov; g.M = no; g.N = nv; g.K = no;
+    g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)no * nv; g.sBk = nv; g.sBj = 1;
+    g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, na, g));
+    // T[Q] (nv x no) = B[Q][vir, vir] W[:, :no]
+    g = GemmArgs{};
+    g.A = h->B + (int64_t)no * n + no; g.B = h->R + (int64_t)no * n + no; g.C = h->T; g.M = nv; g.N = no; g.K = nv;
+    g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1;
+    g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, na, g));
+    g = GemmArgs{};
+    g.A = h->R + (int64_t)no * n + no; g.B = h->T; g.C = h->Bvt; g.M = nv; g.N = no; g.K = nv;
+    g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)nv * no; g.sBk = no; g.sBj = 1;
+    g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, na, g));
+    // T[Q] (no x no) = B[Q][occ, occ] U ; Boo = U^T T
+    g = GemmArgs{};
+    g.A = h->B; g.B = h->R; g.C = h->T; g.M = no; g.N = no; g.K = no;
+    g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)no * no; g.sCi = no; g.sCj = 1;
+    g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, na, g));
+    g = GemmArgs{};
+    g.A = h->R; g.B = h->T; g.C = h->Boo; g.M = no; g.N = no; g.K = no;
+    g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)no * no; g.sBk = no; g.sBj = 1;
+    g.sCb = (int64_t)no * no; g.sCi = no; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, na, g));
+  } else {
+    // the factor is given in the TOP basis: its blocks are read off directly
+    hipLaunchKernelGGL(k_extract_blocks, dim3(1024), dim3(256), 0, s, (const double*)h->B, no, nv, na, h->Bov,
+                       h->Bvt, h->Boo);
+  }
   double sc[3];
   int info[1];
   ESMP2_HIP(hipMemcpyAsync(sc, h->sc_rot, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1173,6 +1227,274 @@ esmp2_status esmp2_solve_batch(esmp2_handle* hs, int n, const esmp2_solve_opts* 
   for (auto& t : pool) t.join();
   for (int i = 0; i < n; ++i)
     if (st[i] != ESMP2_OK) return st[i];
+  return ESMP2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// dE2/dF~ and dE2/dB~ (rotation held fixed)
+// ---------------------------------------------------------------------------
+// lenA, lenB, lenOut: element counts of the operands and the output; every index the
+// launch can form is checked against them on the host first.
+static esmp2_status contract(esmp2_handle h, double* part, const Contr& c, int64_t lenA, int64_t lenB,
+                             double alpha, double* out, int64_t lenOut, int64_t dst, int64_t so0, int64_t so1) {
+  const int64_t ncon = (int64_t)c.nC[0] * c.nC[1] * c.nC[2] * c.nC[3];
+  const int nout = c.nE[0] * c.nE[1];
+  if (nout <= 0 || ncon <= 0) return ESMP2_OK;
+  int64_t hiA = c.oA, hiB = c.oB, hiO = dst + (c.nE[0] - 1) * so0 + (c.nE[1] - 1) * so1;
+  for (int k = 0; k < 2; ++k) { hiA += (c.nE[k] - 1) * c.aE[k]; hiB += (c.nE[k] - 1) * c.bE[k]; }
+  for (int k = 0; k < 4; ++k) { hiA += (c.nC[k] - 1) * c.aC[k]; hiB += (c.nC[k] - 1) * c.bC[k]; }
+  if (c.oA < 0 || c.oB < 0 || dst < 0 || hiA >= lenA || hiB >= lenB || hiO >= lenOut)
+    return fail(h, ESMP2_HIP_ERROR, "internal: gradient contraction out of range");
+  const int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, ncon / 4096));
+  hipLaunchKernelGGL(k_contract, dim3(nout, nsplit), dim3(256), 0, h->stream, c, part);
+  hipLaunchKernelGGL(k_contract_fin, dim3(nblk(nout)), dim3(256), 0, h->stream, (const double*)part, c.nE[0],
+                     c.nE[1], nsplit, alpha, out, dst, so0, so1);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+// G[i * ld + j] += alpha * sum_b sum_k X[b*sb + i*si + k*sk] X[b*sb + j*si + k*sk]   (i, j < m)
+static esmp2_status gram(esmp2_handle h, const double* X, int nb, int64_t sb, int m, int64_t si, int K, int64_t sk,
+                         double alpha, double* G, int ld, double* tmp) {
+  if (nb <= 0 || m <= 0 || K <= 0) return ESMP2_OK;
+  GemmArgs g{};
+  g.A = X; g.B = X; g.C = tmp; g.M = m; g.N = m; g.K = K;
+  g.sAb = sb; g.sAi = si; g.sAk = sk; g.sBb = sb; g.sBk = sk; g.sBj = si;
+  g.sCb = (int64_t)m * m; g.sCi = m; g.sCj = 1; g.alpha = 1.0; g.beta = 0.0;
+  ESMP2_HIP(gemm(h->stream, nb, g));
+  hipLaunchKernelGGL(k_batch_sum_acc, dim3(nblk((int64_t)m * m)), dim3(256), 0, h->stream, (const double*)tmp, nb, m,
+                     m, alpha, G, ld);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+#define ESMP2_TRY(call)                          \
+  do {                                           \
+    esmp2_status st_ = (call);                   \
+    if (st_ != ESMP2_OK) return st_;             \
+  } while (0)
+
+esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double* dB) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (h->state < 3) return fail(h, ESMP2_BAD_ORDER, "esmp2_build_rhs (and a solve for x) first");
+  if (!x || (!dF && !dB)) return fail(h, ESMP2_INVALID_ARG, "x and at least one of dF, dB are required");
+  ESMP2_HIP(hipSetDevice(h->device));
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv, n = d.n, na = d.naux, nov = no * nv;
+  const int o1 = no - 1, v1 = nv - 1;
+  hipStream_t s = h->stream;
+  // ---- workspace
+  const int64_t nd = (int64_t)no * no * nv * nv;
+  const int64_t dsz[7] = {nd, nd, (int64_t)o1 * o1 * v1 * v1, nd, (int64_t)no * no * v1 * v1,
+                          (int64_t)o1 * o1 * nv * nv, (int64_t)o1 * o1 * v1 * v1};
+  constexpr int NB_NORM = 256;
+  int64_t need = nd;                                           // swap
+  for (int k = 0; k < 7; ++k) need += dsz[k];
+  const int64_t ntmp = (int64_t)no * nv * nv + (int64_t)no * no * no;
+  const int64_t npart = (int64_t)64 * nov;
+  need += ntmp + (int64_t)n * n + 2 * (int64_t)nov * nov + nov + nv + no + 8 + npart + 7 * NB_NORM + 8 +
+          2 * (int64_t)na * nov + (int64_t)na * nv * no + (int64_t)na * no * no;
+  if (h->gws_n < (size_t)need) {
+    if (!dalloc(h, &h->gws, (size_t)need)) return fail(h, ESMP2_OOM, "gradient workspace allocation failed");
+    h->gws_n = (size_t)need;
+  }
+  double* w = h->gws;
+  double* dn[7];
+  for (int k = 0; k < 7; ++k) { dn[k] = w; w += dsz[k]; }
+  double* swp = w; w += nd;
+  double* tmp = w; w += ntmp;
+  double* G = w; w += (int64_t)n * n;
+  double* GV = w; w += (int64_t)nov * nov;
+  double* GM = w; w += (int64_t)nov * nov;
+  double* Gf = w; w += nov;
+  double* Gev = w; w += nv;
+  double* Geo = w; w += no;
+  double* scal = w; w += 8;
+  double* part = w; w += npart;
+  double* npt = w; w += 7 * NB_NORM;
+  double* sbox = w; w += 8;
+  double* dBov = w; w += (int64_t)na * nov;
+  double* dX = w; w += (int64_t)na * nov;
+  double* dBvt = w; w += (int64_t)na * nv * no;
+  double* dBoo = w; w += (int64_t)na * no * no;
+  // everything accumulated into starts at zero (one contiguous range from G to sbox)
+  ESMP2_HIP(hipMemsetAsync(G, 0, sizeof(double) * (size_t)(sbox - G), s));
+  ESMP2_HIP(hipMemsetAsync(dBov, 0, sizeof(double) * (size_t)(w - dBov), s));
+  // box scales s = W / (copies of a stored amplitude in the dense tensor)
+  const double sb_h[8] = {0.5, 1.0, 0.5, 0.5, 1.0, 1.0, 2.0, 0.0};
+  ESMP2_HIP(hipMemcpyAsync(sbox, sb_h, sizeof(sb_h), hipMemcpyHostToDevice, s));
+  // ---- 1. dense boxes (S2 flip-symmetrised)
+  for (int k = 0; k < 7; ++k) {
+    if (k == B_S2) hipLaunchKernelGGL(k_sym_s2<double>, dim3(nblk(nd)), dim3(256), 0, s, d, x, dn[k]);
+    else hipLaunchKernelGGL(k_unpack_box, dim3(1024), dim3(256), 0, s, d, k, x, dn[k]);
+  }
+  ESMP2_HIP(hipGetLastError());
+  // ---- 2a. Fock blocks on the free indices: Gram matrices of the batch matrices
+  for (int k = 0; k < 7; ++k) {
+    int lo_o, lo_v;
+    box_ranges(k, lo_o, lo_v);
+    const int ro = no - lo_o, rv = nv - lo_v;
+    const double sc = sb_h[k];
+    const int64_t pq = (int64_t)ro * rv * rv;
+    double* Gv = G + (int64_t)(no + lo_v) * n + no + lo_v;
+    double* Go = G + (int64_t)lo_o * n + lo_o;
+    // virtual slots: sum over (P, Q, c) of X[P][Q][c][a] X[P][Q][c][e] (left slot); the
+    // right slot equals it for virtual-antisymmetric boxes and S~, else from the transposed copy
+    const bool vir_dense = (k == B_H12 || k == B_H22);
+    ESMP2_TRY(gram(h, dn[k], ro, pq, rv, 1, ro * rv, rv, vir_dense ? sc : 2.0 * sc, Gv, n, tmp));
+    if (vir_dense) {
+      hipLaunchKernelGGL(k_swap_mid, dim3(1024), dim3(256), 0, s, (const double*)dn[k], swp, (int64_t)ro * ro, rv,
+                         rv, (int64_t)1);
+      ESMP2_TRY(gram(h, swp, ro, pq, rv, 1, ro * rv, rv, sc, Gv, n, tmp));
+    }
+    // occupied slots: -sum over (k, A, B) of X[i][k][AB] X[m][k][AB] (first slot); the second
+    // equals it for occupied-antisymmetric boxes and S~, else from the transposed copy
+    const bool occ_dense = (k == B_H21 || k == B_H22);
+    const int64_t v2 = (int64_t)rv * rv;
+    ESMP2_TRY(gram(h, dn[k], ro, v2, ro, ro * v2, (int)v2, 1, occ_dense ? -sc : -2.0 * sc, Go, n, tmp));
+    if (occ_dense) {
+      hipLaunchKernelGGL(k_swap_mid, dim3(1024), dim3(256), 0, s, (const double*)dn[k], swp, (int64_t)1, ro, ro, v2);
+      ESMP2_TRY(gram(h, swp, ro, v2, ro, ro * v2, (int)v2, 1, -sc, Go, n, tmp));
+    }
+    hipLaunchKernelGGL(k_sumsq, dim3(NB_NORM), dim3(256), 0, s, (const double*)dn[k], dsz[k], npt + k * NB_NORM);
+  }
+  hipLaunchKernelGGL(k_norm_scalars, dim3(1), dim3(64), 0, s, (const double*)npt, NB_NORM, (const double*)sbox, scal);
+  ESMP2_HIP(hipGetLastError());
+  // ---- 2b. pinned-row transfers and f_ov couplings (strided contractions)
+  {
+    const double *T2 = dn[B_T2], *St = dn[B_S2], *T3 = dn[B_T3], *H11 = dn[B_H11], *H12 = dn[B_H12],
+                 *H21 = dn[B_H21], *H22 = dn[B_H22];
+    const int64_t N = n;
+    // tensor strides (dims d0 d1 d2 d3 -> d1 d2 d3, d2 d3, d3, 1)
+    const int64_t sT2[4] = {(int64_t)no * nv * nv, (int64_t)nv * nv, nv, 1};            // also St, H11
+    const int64_t sT3[4] = {(int64_t)o1 * v1 * v1, (int64_t)v1 * v1, v1, 1};
+    const int64_t sH12[4] = {(int64_t)no * v1 * v1, (int64_t)v1 * v1, v1, 1};
+    const int64_t sH21[4] = {(int64_t)o1 * nv * nv, (int64_t)nv * nv, nv, 1};
+    const int64_t sH22[4] = {(int64_t)o1 * v1 * v1, (int64_t)v1 * v1, v1, 1};
+    auto C = [&](const double* A, int64_t oA, const double* B, int64_t oB) {
+      Contr c{};
+      c.A = A; c.B = B; c.oA = oA; c.oB = oB;
+      c.nE[0] = c.nE[1] = 1;
+      c.nC[0] = c.nC[1] = c.nC[2] = c.nC[3] = 1;
+      return c;
+    };
+    auto E = [](Contr& c, int slot, int nE, int64_t a, int64_t b) { c.nE[slot] = nE; c.aE[slot] = a; c.bE[slot] = b; };
+    auto len = [&](const double* p) -> int64_t {
+      for (int k = 0; k < 7; ++k) if (p == dn[k]) return dsz[k];
+      return 0;
+    };
+    auto K = [](Contr& c, int slot, int nC, int64_t a, int64_t b) { c.nC[slot] = nC; c.aC[slot] = a; c.bC[slot] = b; };
+    Contr c;
+    // transfers through the t' row of F_vv: G[t'][e], e >= 1
+    c = C(H11, 1, H12, 0); E(c, 0, v1, 0, v1);
+    K(c, 0, no, sT2[0], sH12[0]); K(c, 1, no, sT2[1], sH12[1]); K(c, 2, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 2.0, G, N * N, N * no + no + 1, 1, 0));
+    c = C(H21, 1, H22, 0); E(c, 0, v1, 0, v1);
+    K(c, 0, o1, sH21[0], sH22[0]); K(c, 1, o1, sH21[1], sH22[1]); K(c, 2, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N * no + no + 1, 1, 0));
+    // transfers through the t column of F_oo: G[m][t], m >= 1
+    c = C(H11, (int64_t)nv * nv, H21, 0); E(c, 0, o1, 0, sH21[0]);
+    K(c, 0, o1, sT2[1], sH21[1]); K(c, 1, nv * nv, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -2.0, G, N * N, N, N, 0));
+    c = C(H12, (int64_t)v1 * v1, H22, 0); E(c, 0, o1, 0, sH22[0]);
+    K(c, 0, o1, sH12[1], sH22[1]); K(c, 1, v1 * v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, N, N, 0));
+    // f_ov couplings (doubles -> L-triples; the de-excitation doubles them): G[i][n_occ + a]
+    const int64_t ov = no;     // column offset of the virtual block
+    // L-triples <- T2
+    c = C(T3, 0, T2, sT2[0] + sT2[1] + sT2[2] + 1);
+    K(c, 0, o1, sT3[0], sT2[0]); K(c, 1, o1, sT3[1], sT2[1]); K(c, 2, v1, sT3[2], sT2[2]); K(c, 3, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 1.0, G, N * N, ov, 0, 0));
+    c = C(T3, 0, T2, sT2[1] + sT2[2] + 1); E(c, 0, o1, sT3[0], 0);
+    K(c, 0, o1, sT3[1], sT2[1]); K(c, 1, v1, sT3[2], sT2[2]); K(c, 2, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -2.0, G, N * N, N + ov, N, 0));
+    c = C(T3, 0, T2, sT2[0] + sT2[1] + 1); E(c, 0, v1, sT3[2], 0);
+    K(c, 0, o1, sT3[0], sT2[0]); K(c, 1, o1, sT3[1], sT2[1]); K(c, 2, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -2.0, G, N * N, ov + 1, 1, 0));
+    c = C(T3, 0, T2, sT2[1] + 1); E(c, 0, o1, sT3[0], 0); E(c, 1, v1, sT3[2], 0);
+    K(c, 0, o1, sT3[1], sT2[1]); K(c, 1, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
+    // S3 boxes <- T2
+    c = C(H11, 0, T2, 0); K(c, 0, (int)nd, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 1.0, G, N * N, ov, 0, 0));
+    c = C(H12, 0, T2, 1); E(c, 0, v1, v1, 0);
+    K(c, 0, no, sH12[0], sT2[0]); K(c, 1, no, sH12[1], sT2[1]); K(c, 2, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 2.0, G, N * N, ov + 1, 1, 0));
+    c = C(H21, 0, T2, sT2[1]); E(c, 0, o1, sH21[0], 0);
+    K(c, 0, o1, sH21[1], sT2[1]); K(c, 1, nv * nv, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 2.0, G, N * N, N + ov, N, 0));
+    c = C(H22, 0, T2, sT2[1] + 1); E(c, 0, o1, sH22[0], 0); E(c, 1, v1, v1, 0);
+    K(c, 0, o1, sH22[1], sT2[1]); K(c, 1, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
+    // S3 boxes <- S~
+    c = C(H11, 0, St, 0); E(c, 0, no, sT2[0], 0); E(c, 1, nv, nv, 0);
+    K(c, 0, no, sT2[1], sT2[1]); K(c, 1, nv, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, ov, N, 1));
+    c = C(H12, 0, St, nv + 1); E(c, 0, no, sH12[0], 0);
+    K(c, 0, no, sH12[1], sT2[1]); K(c, 1, v1, v1, nv); K(c, 2, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, ov, N, 0));
+    c = C(H12, 0, St, nv); E(c, 0, no, sH12[0], 0); E(c, 1, v1, 1, 0);
+    K(c, 0, no, sH12[1], sT2[1]); K(c, 1, v1, v1, nv);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, ov + 1, N, 1));
+    c = C(H21, 0, St, sT2[0] + sT2[1]); E(c, 0, nv, nv, 0);
+    K(c, 0, o1, sH21[0], sT2[0]); K(c, 1, o1, sH21[1], sT2[1]); K(c, 2, nv, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, ov, 1, 0));
+    c = C(H21, 0, St, sT2[0]); E(c, 0, o1, sH21[1], 0); E(c, 1, nv, nv, 0);
+    K(c, 0, o1, sH21[0], sT2[0]); K(c, 1, nv, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, N + ov, N, 1));
+    c = C(H22, 0, St, sT2[0] + sT2[1] + nv + 1);
+    K(c, 0, o1, sH22[0], sT2[0]); K(c, 1, o1, sH22[1], sT2[1]); K(c, 2, v1, v1, nv); K(c, 3, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, ov, 0, 0));
+    c = C(H22, 0, St, sT2[0] + nv + 1); E(c, 0, o1, sH22[1], 0);
+    K(c, 0, o1, sH22[0], sT2[0]); K(c, 1, v1, v1, nv); K(c, 2, v1, 1, 1);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, N + ov, N, 0));
+    c = C(H22, 0, St, sT2[0] + sT2[1] + nv); E(c, 0, v1, 1, 0);
+    K(c, 0, o1, sH22[0], sT2[0]); K(c, 1, o1, sH22[1], sT2[1]); K(c, 2, v1, v1, nv);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, ov + 1, 1, 0));
+    c = C(H22, 0, St, sT2[0] + nv); E(c, 0, o1, sH22[1], 0); E(c, 1, v1, 1, 0);
+    K(c, 0, o1, sH22[0], sT2[0]); K(c, 1, v1, v1, nv);
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
+  }
+  // ---- 3. transposes of the right-hand side and of E2_S
+  RhsAdjArgs ra{d, x, h->lam, GV, GM, Gf};
+  hipLaunchKernelGGL(k_rhs_adj, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
+  {
+    const int* pv = h->pairs;
+    E2sAdjArgs ea{d, h->Vint, h->lam, h->eo, h->ev, h->omega, pv, pv + d.npv, pv + d.npv + d.npv1,
+                  pv + d.npv + d.npv1 + d.npo, GV, Gev, Geo, scal + 2};
+    const int y1 = std::max(1, no - 1), x1 = std::max(1, 1024 / y1);
+    const int y3 = std::min(1024, no * nv), x3 = std::max(1, 1024 / y3);
+    hipLaunchKernelGGL(k_e2s_same_adj, dim3(x1, y1), dim3(256), 0, s, ea);
+    hipLaunchKernelGGL(k_e2s_mixed_a_adj, dim3(x1, y1), dim3(256), 0, s, ea);
+    hipLaunchKernelGGL(k_e2s_mixed_b_adj, dim3(x3, y3), dim3(256), 0, s, ea);
+  }
+  ESMP2_HIP(hipGetLastError());
+  // ---- 4. chain to the factor blocks
+  if (dB) {
+    GemmArgs g{};
+    // dBov = Bov (GV + GV^T)
+    g.A = h->Bov; g.B = GV; g.C = dBov; g.M = na; g.N = nov; g.K = nov;
+    g.sAi = nov; g.sAk = 1; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1.0; g.beta = 1.0;
+    ESMP2_HIP(gemm(s, 1, g));
+    g.sBk = 1; g.sBj = nov;
+    ESMP2_HIP(gemm(s, 1, g));
+    // dBov += X GM ; dX = Bov GM^T
+    g.A = h->X; g.B = GM; g.sBk = nov; g.sBj = 1;
+    ESMP2_HIP(gemm(s, 1, g));
+    g.A = h->Bov; g.C = dX; g.sBk = 1; g.sBj = nov; g.beta = 0.0;
+    ESMP2_HIP(gemm(s, 1, g));
+    hipLaunchKernelGGL(k_make_x_adj, dim3(nblk((int64_t)na * nov)), dim3(256), 0, s, (const double*)dX,
+                       (const double*)h->lam, no, nv, na, dBvt, dBoo);
+    hipLaunchKernelGGL(k_fphi_adj, dim3(na), dim3(256), 0, s, (const double*)h->Bov, (const double*)h->Bvt,
+                       (const double*)h->Boo, (const double*)h->lam, (const double*)Gf, no, nv, dBov, dBvt, dBoo);
+    hipLaunchKernelGGL(k_grad_b_assemble, dim3(2048), dim3(256), 0, s, (const double*)dBov, (const double*)dBvt,
+                       (const double*)dBoo, no, nv, na, dB);
+  }
+  // ---- 5. the Fock gradient
+  if (dF)
+    hipLaunchKernelGGL(k_grad_f_finish, dim3(nblk((int64_t)n * n)), dim3(256), 0, s, G, (const double*)h->lam,
+                       (const double*)Gf, (const double*)Gev, (const double*)Geo, (const double*)scal, no, nv, dF);
+  ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
 

@@ -10,7 +10,12 @@ their flat index in the seven-box layout.
 For the batched workload ("c4": 32 independent states of uneven size) it
 holds E0 and E2 with its parts per state.
 
-Usage:  python tests/golden/make_golden.py [c2 c3 c5 c4 ...]
+For the differentiation workload ("c5_grad", the n_occ = 8 problem) it holds
+dE2/dF~ and dE2/dB~ (TOP basis, rotation held fixed) on seeded samples of
+entries, from ``oracle.gradient`` (exact central differences of the
+stationary functional at the oracle's own solution).
+
+Usage:  python tests/golden/make_golden.py [c2 c3 c5 c4 c5_grad ...]
 """
 import json
 import os
@@ -23,7 +28,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import synth                                   # noqa: E402
-from oracle import structured, topbasis        # noqa: E402
+from oracle import gradient, structured, topbasis        # noqa: E402
 
 
 def sample_indices(dim, offsets, seed):
@@ -75,11 +80,50 @@ def run_batched():
     return dict(states=states)
 
 
+def gradient_entries(no, nv, na, seed):
+    """Seeded sample of entries: (p, q) of F~ and (Q, p, q) of B~ with p <= q;
+    most of B~'s inside the blocks E2 depends on (a row or column among the
+    occupied orbitals or the TOP virtuals), the rest anywhere."""
+    n = no + nv
+    rng = np.random.default_rng(seed)
+    fe = set()
+    while len(fe) < 50:
+        p, q = sorted(int(v) for v in rng.integers(0, n, 2))
+        fe.add((p, q))
+    be = set()
+    while len(be) < 35:
+        p = int(rng.integers(0, 2 * no))
+        q = int(rng.integers(0, n))
+        be.add((int(rng.integers(0, na)),) + tuple(sorted((p, q))))
+    while len(be) < 50:
+        p, q = sorted(int(v) for v in rng.integers(0, n, 2))
+        be.add((int(rng.integers(0, na)), p, q))
+    return sorted(fe), sorted(be)
+
+
+def run_gradient(name):
+    p = synth.config_problem(name)
+    t0 = time.time()
+    lam, R = topbasis.top_rotation(p.F, p.C, p.n_occ)
+    Ft, Bt = topbasis.rotate(p.F, p.B, R)
+    L = gradient.Lagrangian(Ft, Bt, lam, p.n_occ, tol=1e-12, max_iter=600)
+    fe, be = gradient_entries(p.n_occ, p.n_vir, p.n_aux, 2024)
+    gF = [L.grad_F(a, b) for a, b in fe]
+    gB = [L.grad_B(Q, a, b) for Q, a, b in be]
+    return dict(workload=name, n_occ=p.n_occ, n_vir=p.n_vir, n_aux=p.n_aux, e2=L.e2, f_entries=fe, f_grad=gF,
+                b_entries=be, b_grad=gB, seconds=time.time() - t0)
+
+
 if __name__ == "__main__":
     names = sys.argv[1:] or ["c1", "c2", "c5", "c3"]
     path = os.path.join(HERE, "oracle_values.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
     for nm in names:
+        if nm.endswith("_grad"):
+            data[nm] = run_gradient(nm[:-5])
+            print(nm, data[nm]["e2"], "%.1fs" % data[nm]["seconds"], flush=True)
+            json.dump(data, open(path, "w"), indent=1)
+            continue
         data[nm] = run_batched() if nm == "c4" else run(nm)
         if nm == "c4":
             print(nm, len(data[nm]["states"]), "states", flush=True)
