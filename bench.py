@@ -164,6 +164,51 @@ def main():
             hh.close()
         del hs
 
+    # the adjoint: dE2/dF~ and dE2/dB~ after the FP64 solve, on the differentiation
+    # workload (n_occ=8, n_vir=80, n_aux=240, seed 4) and on this workload
+    grad = {}
+    gall = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_values.json")))
+    for wl in ("c5", args.workload):
+        pg = synth.config_problem(wl)
+        hg = P.Handle(0).load(pg)
+        ng = pg.n_occ + pg.n_vir
+        hg.rotate_top(lam_out=False)
+        hg.build_rhs()
+        namp_g, _ = hg.space()
+        xg = torch.empty(namp_g, dtype=torch.float64, device="cuda")
+        dFg = torch.empty((ng, ng), dtype=torch.float64, device="cuda")
+        dBg = torch.empty((pg.n_aux, ng, ng), dtype=torch.float64, device="cuda")
+        rg = hg.solve(tol=1e-10, max_iter=500, basis=P.ESMP2_BASIS_SEMICANONICAL, x_out=xg)
+        hg.gradient(xg, dFg, dBg)                       # first call allocates the workspace
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        ev0.record()
+        for _ in range(reps):
+            hg.gradient(xg, dFg, dBg)
+        ev1.record()
+        torch.cuda.synchronize()
+        g_ms = ev0.elapsed_time(ev1) / reps
+        t0 = time.perf_counter()
+        hg.rotate_top(lam_out=False)
+        hg.build_rhs()
+        hg.solve(tol=1e-10, max_iter=500, basis=P.ESMP2_BASIS_SEMICANONICAL, x_out=xg)
+        hg.gradient(xg, dFg, dBg)
+        torch.cuda.synchronize()
+        fb_ms = 1e3 * (time.perf_counter() - t0)
+        entry = {"n_occ": pg.n_occ, "n_vir": pg.n_vir, "n_aux": pg.n_aux, "gradient_ms": round(g_ms, 3),
+                 "e2_and_gradient_ms": round(fb_ms, 3), "e2": rg["e2"], "solve_tol": 1e-10}
+        gg = gall.get(wl + "_grad")
+        if gg is not None:
+            dFh, dBh = dFg.cpu().numpy(), dBg.cpu().numpy()
+            sc = max(abs(dFh).max(), abs(dBh).max())
+            err = max(max(abs(dFh[a, b] - v) for (a, b), v in zip(gg["f_entries"], gg["f_grad"])),
+                      max(abs(dBh[Q, a, b] - v) for (Q, a, b), v in zip(gg["b_entries"], gg["b_grad"])))
+            entry["max_err_vs_oracle_samples_rel"] = err / sc
+        grad[wl] = entry
+        hg.close()
+        del xg, dFg, dBg
+
     vv_avg_ms = vv_ms / max(vv_n, 1)
     achieved = vv_flops / (vv_avg_ms * 1e-3) / 1e12
     # HBM bytes per launch from the committed counter passes, valid while the
@@ -226,6 +271,7 @@ def main():
                       "outer_fp64_steps": res_scm["outer"], "rel_resid": res_scm["rel_resid"],
                       "e2_minus_top_fp64": res_scm["e2"] - res["e2"]}},
         "batched_32_states": batch,
+        "gradient_fp64": grad,
         "roofline": {"bound": "mfma", "kernel": "k_vv3 (virtual-pair Sylvester, FP64 MFMA)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,

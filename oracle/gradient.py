@@ -44,22 +44,23 @@ from .structured import RHS, solve
 class Lagrangian:
     """L(F~, B~) with the first-order amplitudes of the point (Ft, Bt) held fixed."""
 
-    def __init__(self, Ft, Bt, lam, n_occ, tol=1e-13, max_iter=500):
+    def __init__(self, Ft, Bt, lam, n_occ, tol=1e-13, max_iter=500, spin=0):
+        self.spin = spin
         self.Ft = np.array(Ft, dtype=np.float64)
         self.Bt = np.array(Bt, dtype=np.float64)
         self.lam = np.asarray(lam, dtype=np.float64)
         self.no = n_occ
-        out = solve(self.Ft, self.Bt, self.lam, n_occ, tol=tol, max_iter=max_iter)
+        out = solve(self.Ft, self.Bt, self.lam, n_occ, tol=tol, max_iter=max_iter, spin=spin)
         self.x = out["x"]
         self.e2 = out["e2"]
         self.e2_dl, self.e2_s = out["e2_dl"], out["e2_s"]
-        rh = RHS(self.Ft, self.Bt, self.lam, n_occ)
+        rh = RHS(self.Ft, self.Bt, self.lam, n_occ, spin=spin)
         self.xs = [-b / D for b, D in rh.s_terms()]
 
     def value(self, Ft=None, Bt=None):
         Ft = self.Ft if Ft is None else Ft
         Bt = self.Bt if Bt is None else Bt
-        rh = RHS(Ft, Bt, self.lam, self.no)
+        rh = RHS(Ft, Bt, self.lam, self.no, spin=self.spin)
         op, x = rh.op, self.x
         b = rh.rhs()
         val = 2.0 * op.dot(b, x) + op.dot(x, op.sigma(x))
@@ -93,6 +94,6 @@ class Lagrangian:
         return GF, GB
 
 
-def e2_of(Ft, Bt, lam, n_occ, tol=1e-13, max_iter=500):
+def e2_of(Ft, Bt, lam, n_occ, tol=1e-13, max_iter=500, spin=0):
     """E2 by a full solve at (Ft, Bt): the function being differentiated."""
-    return solve(Ft, Bt, lam, n_occ, tol=tol, max_iter=max_iter)["e2"]
+    return solve(Ft, Bt, lam, n_occ, tol=tol, max_iter=max_iter, spin=spin)["e2"]

@@ -99,19 +99,23 @@ def _det_of(ops, phi, n, flip=False):
     return fm.apply_string(phi, so)
 
 
-def rep_map(no, nv):
+def rep_map(no, nv, spin=0):
     """For every stored amplitude: list of (det, sign * factor) it contributes
-    to the wave function, and (det, sign) of its own (unflipped) determinant."""
+    to the wave function, and (det, sign) of its own (unflipped) determinant.
+    spin = 0: the spin-flip partner carries the same amplitude (singlet);
+    spin = 1: the opposite one (the M_s = 0 triplet, antisymmetric under the
+    flip of every spin)."""
     n = no + nv
     phi = sum(1 << p for p in range(no)) | sum(1 << (n + p) for p in range(no))
+    fs = -1.0 if spin else 1.0
     out = []
     for box, ops in enumerate_ops(no, nv):
         s0, d0 = _det_of(ops, phi, n)
         s1, d1 = _det_of(ops, phi, n, flip=True)
         if box == 1:
-            contrib = [(d0, 0.5 * s0), (d1, 0.5 * s1)]
+            contrib = [(d0, 0.5 * s0), (d1, 0.5 * fs * s1)]
         else:
-            contrib = [(d0, float(s0)), (d1, float(s1))]
+            contrib = [(d0, float(s0)), (d1, fs * float(s1))]
         out.append((box, contrib, (d0, s0)))
     return out
 

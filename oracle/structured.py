@@ -117,12 +117,18 @@ def _anti_occ(x):
 class Structured:
     """sigma = (H0 - E0) x on doubles + L-triples, in the seven-box layout."""
 
-    def __init__(self, f, lam, n_occ, omega=None):
+    def __init__(self, f, lam, n_occ, omega=None, spin=0):
         """f: Fock matrix in the TOP basis, or in any basis that differs from
         it by a rotation of the occupied orbitals other than t and of the
         virtuals other than t'; then omega (computed in the TOP basis) must be
-        given, since it reads the TOP orbitals' diagonal Fock elements."""
+        given, since it reads the TOP orbitals' diagonal Fock elements.
+        spin = 0: singlet reference; 1: the M_s = 0 triplet (Sec. II.A: the
+        beta singles enter Psi0 with the opposite sign), whose first-order
+        amplitudes are antisymmetric under the flip of every spin: a stored
+        amplitude's flip partner carries the amplitude times sg = -1."""
         f = np.asarray(f, dtype=np.float64)
+        self.spin = spin
+        self.sg = -1.0 if spin else 1.0
         self.no = no = n_occ
         self.nv = nv = f.shape[0] - n_occ
         self.lam = np.asarray(lam, dtype=np.float64)
@@ -155,7 +161,7 @@ class Structured:
         fo1, fv1 = fo[1:, 1:], fv[1:, 1:]
         om, ka = self.omega, self.kappa
         T2, T3, H11, H12, H21, H22 = d["T2"], d["T3L"], d["H11"], d["H12"], d["H21"], d["H22"]
-        S = 0.5 * (d["S2"] + d["S2"].transpose(1, 0, 3, 2))     # flip-symmetrised S2
+        S = 0.5 * (d["S2"] + self.sg * d["S2"].transpose(1, 0, 3, 2))     # flip-(anti)symmetrised S2
         o = {}
         # ---- diagonal-block (same box) Fock action ------------------------
         o["T2"] = self._vv(fv, fv, T2) - self._oo(fo, fo, T2) - om * T2
@@ -209,11 +215,12 @@ class Structured:
         g4 = g4 - g4.transpose(0, 1, 3, 2)
         x += g4
         o["T3L"] += x
-        # S3 boxes <- T2 (down-down copy; up pair = f_{a i})
-        o["H11"] += fov[0, 0] * T2
-        o["H12"] += fov[0, 1:][None, None, :, None] * T2[:, :, 0, 1:][:, :, None, :]
-        o["H21"] += fov[1:, 0][:, None, None, None] * T2[0, 1:][None]
-        o["H22"] += fov[1:, 1:][:, None, :, None] * T2[0, 1:, 0, 1:][None, :, None, :]
+        # S3 boxes <- T2 (down-down copy = flip partner of T2, amplitude sg T2; up pair = f_{a i})
+        sg = self.sg
+        o["H11"] += sg * fov[0, 0] * T2
+        o["H12"] += sg * fov[0, 1:][None, None, :, None] * T2[:, :, 0, 1:][:, :, None, :]
+        o["H21"] += sg * fov[1:, 0][:, None, None, None] * T2[0, 1:][None]
+        o["H22"] += sg * fov[1:, 1:][:, None, :, None] * T2[0, 1:, 0, 1:][None, :, None, :]
         # S3 boxes <- S2 (down pair = f_{b j}), S = flip-symmetrised S2
         s = S[0, :, 0, :]                                           # s[k, c] = S[t k t' c]
         h = fov.T[None, None, :, :] * 0                              # placeholder shape check
@@ -255,7 +262,9 @@ class Structured:
         t2[1:, 0, 0, 1:] -= v
         t2[0, 1:, 1:, 0] -= v
         t2[1:, 0, 1:, 0] += v
-        # from the S3 boxes (down-down copy of T2)
+        o["T2"] += t2
+        # from the S3 boxes, through their flip partners (down-down copy of T2): sg
+        t2 = np.zeros_like(o["T2"])
         t2 += fov[0, 0] * H11
         v = np.einsum("a,jkac->jkc", fov[0, 1:], H12)               # T2[j k][t' c]
         t2[:, :, 0, 1:] += v
@@ -268,7 +277,7 @@ class Structured:
         t2[1:, 0, 0, 1:] -= v
         t2[0, 1:, 1:, 0] -= v
         t2[1:, 0, 1:, 0] += v
-        o["T2"] += t2
+        o["T2"] += self.sg * t2
         # S2 <- S3 boxes: d = E^T x (per determinant), sigma_S2 += d + flip(d)
         d = np.zeros_like(o["S2"])
         d[0, :, 0, :] += np.einsum("jb,jkbc->kc", fov, H11)
@@ -280,7 +289,7 @@ class Structured:
         d[1:, 0, 1:, 1:] -= np.einsum("k,ikac->iac", fov[1:, 0], H22)
         d[1:, 1:, 1:, 0] -= np.einsum("c,ikac->ika", fov[0, 1:], H22)
         d[1:, 0, 1:, 0] += np.einsum("kc,ikac->ia", fov[1:, 1:], H22)
-        o["S2"] += d + d.transpose(1, 0, 3, 2)
+        o["S2"] += d + self.sg * d.transpose(1, 0, 3, 2)
 
     def sigma(self, x):
         return self.boxes.pack(self.sigma_boxes(self.boxes.unpack(x)))
@@ -343,13 +352,14 @@ class RHS:
     (pq|rs) = sum_Q Bt[Q,p,q] Bt[Q,r,s].
     """
 
-    def __init__(self, Ft, Bt, lam, n_occ):
+    def __init__(self, Ft, Bt, lam, n_occ, spin=0):
         no = n_occ
         self.no, self.nv = no, Ft.shape[0] - no
         nv = self.nv
         self.lam = np.asarray(lam, dtype=np.float64)
         self.c = self.lam / np.sqrt(2.0)
-        self.op = Structured(Ft, lam, n_occ)
+        self.sg = -1.0 if spin else 1.0       # sign of the beta singles in Psi0
+        self.op = Structured(Ft, lam, n_occ, spin=spin)
         Bov = Bt[:, :no, no:]
         self.V = np.einsum("Qia,Qjb->iajb", Bov, Bov, optimize=True)           # (ia|jb)
         self.W = np.einsum("Qal,Qjb->albj", Bt[:, no:, no:2 * no], Bov, optimize=True)  # (a l'|b j)
@@ -378,9 +388,10 @@ class RHS:
         zz[:, :, :no, :] = Z.transpose(1, 3, 0, 2)[:, :, :, :]                # Z[a,i,b,j] -> [i,j,a,b], a < no
         k = -cv[None, None, :, None] * zz
         m = g + h + k
+        sg = self.sg
         d = {}
         d["T2"] = _anti2(m)
-        d["S2"] = m + m.transpose(1, 0, 3, 2)
+        d["S2"] = m + sg * m.transpose(1, 0, 3, 2)       # second term: the beta singles
         # triples
         c0 = c[0]
         Vx = V.transpose(0, 2, 1, 3)                                           # [j,k,b,c] = (jb|kc)
@@ -391,22 +402,22 @@ class RHS:
         q = (c[:, None] * dlt)[1:, None, 1:, None] * (e_tt - e_kt)[None, 1:, None, 1:]
         d["T3L"] = c0 * AS[1:, 1:, 1:, 1:] + _anti2(q)
         q = (c[:, None] * dlt)[:, None, :, None] * e_tt[None, :, None, :]
-        d["H11"] = c0 * AS + _anti2(q)
+        d["H11"] = c0 * AS + sg * _anti2(q)                 # alpha single t -> t'; beta singles
         # H1P2 [j,k,a,c], a,c in 1..
         r = np.zeros((no, no, nv - 1, nv - 1))
         r[0] += c0 * V[0, 1:, :, 1:].transpose(1, 0, 2)                      # d(j,t) c_t (a t|c k)
         r -= (c[:, None] * dlt[:, 1:])[:, None, None, :] * V[0, 1:, :, 0].T[None, :, :, None]
-        d["H12"] = r - r.transpose(1, 0, 2, 3)
+        d["H12"] = sg * (r - r.transpose(1, 0, 2, 3))     # beta singles only
         # H2P1 [i,k,b,c], i,k in 1..
         s = np.zeros((no - 1, no - 1, nv, nv))
         s[:, :, 0, :] += c0 * V[1:, 0, 1:, :]
         s -= (c[:, None] * dlt)[None, 1:, :, None] * V[1:, 0, 0, :][:, None, None, :]
-        d["H21"] = s - s.transpose(0, 1, 3, 2)
+        d["H21"] = sg * (s - s.transpose(0, 1, 3, 2))     # beta singles only
         # H2P2 [i,k,a,c]
-        u = (c[:, None] * dlt)[1:, None, 1:, None] * (e_tt - e_kt)[None, 1:, None, 1:]
-        u = u + c0 * V[1:, 1:, 1:, 1:].transpose(0, 2, 1, 3)
-        u = u + (c[:, None] * dlt)[None, 1:, None, 1:] * V[1:, 1:, 0, 0][:, None, :, None]
-        d["H22"] = u
+        u = (c[:, None] * dlt)[1:, None, 1:, None] * (e_tt - e_kt)[None, 1:, None, 1:]      # alpha single i -> i'
+        w = c0 * V[1:, 1:, 1:, 1:].transpose(0, 2, 1, 3)                                    # beta singles
+        w = w + (c[:, None] * dlt)[None, 1:, None, 1:] * V[1:, 1:, 0, 0][:, None, :, None]
+        d["H22"] = u + sg * w
         return d
 
     def rhs(self):
@@ -485,17 +496,18 @@ class RHS:
                 kk = np.broadcast_to(K, keep.shape)[keep]
                 bb = np.broadcast_to(Bb, keep.shape)[keep]
                 cc = np.broadcast_to(Cc, keep.shape)[keep]
-                b = np.zeros(len(jj))
-                if up_top:
-                    b += c[i] * (V[jj, bb, kk, cc] - V[kk, bb, jj, cc])
+                bd = np.zeros(len(jj))                # from the beta singles (down TOP pairs)
                 m = bb == jj
-                b[m] += c[jj[m]] * V[i, a, kk[m], cc[m]]
+                bd[m] += c[jj[m]] * V[i, a, kk[m], cc[m]]
                 m = bb == kk
-                b[m] -= c[kk[m]] * V[i, a, jj[m], cc[m]]
+                bd[m] -= c[kk[m]] * V[i, a, jj[m], cc[m]]
                 m = cc == jj
-                b[m] -= c[jj[m]] * V[i, a, kk[m], bb[m]]
+                bd[m] -= c[jj[m]] * V[i, a, kk[m], bb[m]]
                 m = cc == kk
-                b[m] += c[kk[m]] * V[i, a, jj[m], bb[m]]
+                bd[m] += c[kk[m]] * V[i, a, jj[m], bb[m]]
+                b = self.sg * bd
+                if up_top:                            # the alpha single i -> i'
+                    b = b + c[i] * (V[jj, bb, kk, cc] - V[kk, bb, jj, cc])
                 D = ev[a] + ev[bb] + ev[cc] - eo[i] - eo[jj] - eo[kk] - om
                 yield b, D
 
@@ -538,8 +550,8 @@ def pcg(op, b, tol=1e-8, max_iter=200, x0=None, history=None):
     return x, r, it, rel
 
 
-def solve(Ft, Bt, lam, n_occ, tol=1e-8, max_iter=200):
-    rh = RHS(Ft, Bt, lam, n_occ)
+def solve(Ft, Bt, lam, n_occ, tol=1e-8, max_iter=200, spin=0):
+    rh = RHS(Ft, Bt, lam, n_occ, spin=spin)
     op = rh.op
     b = rh.rhs()
     x, r, it, rel = pcg(op, b, tol=tol, max_iter=max_iter)
@@ -549,10 +561,10 @@ def solve(Ft, Bt, lam, n_occ, tol=1e-8, max_iter=200):
                 x=x, b=b)
 
 
-def solve_problem(prob, tol=1e-8, max_iter=200):
+def solve_problem(prob, tol=1e-8, max_iter=200, spin=0):
     from .topbasis import top_rotation, rotate
     lam, R = top_rotation(prob.F, prob.C, prob.n_occ)
     Ft, Bt = rotate(prob.F, prob.B, R)
-    out = solve(Ft, Bt, lam, prob.n_occ, tol=tol, max_iter=max_iter)
+    out = solve(Ft, Bt, lam, prob.n_occ, tol=tol, max_iter=max_iter, spin=spin)
     out["lam"] = lam
     return out

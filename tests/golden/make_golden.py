@@ -10,12 +10,15 @@ their flat index in the seven-box layout.
 For the batched workload ("c4": 32 independent states of uneven size) it
 holds E0 and E2 with its parts per state.
 
+Names ending in "_triplet" hold the same quantities for the M_s = 0 triplet
+reference (beta singles with the opposite sign).
+
 For the differentiation workload ("c5_grad", the n_occ = 8 problem) it holds
 dE2/dF~ and dE2/dB~ (TOP basis, rotation held fixed) on seeded samples of
 entries, from ``oracle.gradient`` (exact central differences of the
 stationary functional at the oracle's own solution).
 
-Usage:  python tests/golden/make_golden.py [c2 c3 c5 c4 c5_grad ...]
+Usage:  python tests/golden/make_golden.py [c2 c3 c5 c4 c5_grad c5_triplet ...]
 """
 import json
 import os
@@ -42,12 +45,12 @@ def sample_indices(dim, offsets, seed):
     return sorted(set(int(i) for i in idx))
 
 
-def run(name):
+def run(name, spin=0):
     p = synth.config_problem(name)
     t0 = time.time()
     lam, R = topbasis.top_rotation(p.F, p.C, p.n_occ)
     Ft, Bt = topbasis.rotate(p.F, p.B, R)
-    rh = structured.RHS(Ft, Bt, lam, p.n_occ)
+    rh = structured.RHS(Ft, Bt, lam, p.n_occ, spin=spin)
     op = rh.op
     b = rh.rhs()
     x, r, it, rel = structured.pcg(op, b, tol=1e-10, max_iter=400)
@@ -58,7 +61,7 @@ def run(name):
     xr = synth.random_amplitudes(op.dim, 1234)
     sig = op.sigma(xr)
     idx = sample_indices(op.dim, off, 99)
-    out = dict(n_occ=p.n_occ, n_vir=p.n_vir, n_aux=p.n_aux, dim=op.dim, offsets=off,
+    out = dict(n_occ=p.n_occ, n_vir=p.n_vir, n_aux=p.n_aux, spin=spin, dim=op.dim, offsets=off,
                lam=lam.tolist(), e0=op.E0, omega=op.omega,
                b_norm_w=float(np.sqrt(op.dot(b, b))), x_norm_w=float(np.sqrt(op.dot(x, x))),
                e2=e2_dl + e2_s, e2_dl=e2_dl, e2_s=e2_s, iters=it, rel_resid=rel,
@@ -119,6 +122,11 @@ if __name__ == "__main__":
     path = os.path.join(HERE, "oracle_values.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
     for nm in names:
+        if nm.endswith("_triplet"):
+            data[nm] = run(nm[:-8], spin=1)
+            print(nm, data[nm]["e2"], data[nm]["iters"], data[nm]["seconds"], flush=True)
+            json.dump(data, open(path, "w"), indent=1)
+            continue
         if nm.endswith("_grad"):
             data[nm] = run_gradient(nm[:-5])
             print(nm, data[nm]["e2"], "%.1fs" % data[nm]["seconds"], flush=True)

@@ -55,6 +55,52 @@ def test_structured_equals_explicit(no, nv, na, seed):
     assert r1["max_bN"] == 0.0          # N-triples have no right-hand side (Sec. II.B)
 
 
+@pytest.mark.parametrize("no,nv,na,seed", MICRO)
+def test_structured_equals_explicit_triplet(no, nv, na, seed):
+    """P-a for the M_s = 0 triplet reference (beta singles with the opposite
+    sign): the seven-box operator, right-hand side and E2 with the spin-flip
+    partners carrying opposite amplitudes equal the determinant construction."""
+    p, lam, Ft, Bt = _rotated(no, nv, na, seed)
+    ex = explicit.ExplicitESMP2(Ft, topbasis.eri_from_factor(Bt), lam, no, sign=-1)
+    r1 = ex.solve()
+    rm = layout.rep_map(no, nv, spin=1)
+    st = structured.Structured(Ft, lam, no, spin=1)
+    x = np.random.default_rng(seed + 10).standard_normal(st.dim)
+    y = ex.A @ _phi(rm, ex.index, x)
+    sig_ex = np.array([own[1] * y[ex.index[own[0]]] for (_, _, own) in rm])
+    np.testing.assert_allclose(st.sigma(x), sig_ex, rtol=0, atol=1e-13)
+    hp = ex.h_psi0()
+    b_ex = np.array([own[1] * hp.get(own[0], 0.0) for (_, _, own) in rm])
+    np.testing.assert_allclose(structured.RHS(Ft, Bt, lam, no, spin=1).rhs(), b_ex, rtol=0, atol=1e-15)
+    r2 = structured.solve(Ft, Bt, lam, no, tol=1e-13, spin=1)
+    assert abs(r2["e2"] - r1["e2"]) < 1e-14
+    assert abs(r2["e2_s"] - r1["e2_s"]) < 1e-15
+    r0 = structured.solve(Ft, Bt, lam, no, tol=1e-13)
+    assert abs(r2["e2"] - r0["e2"]) > 1e-6 * abs(r0["e2"])      # the two references differ
+
+
+@pytest.mark.parametrize("no,nv,na,seed", MICRO[1:4])
+def test_triplet_spin_purity(no, nv, na, seed):
+    """The triplet reference and its first-order wave function are pure
+    triplets: ||S+ Psi||^2 = S(S+1) ||Psi||^2 = 2 ||Psi||^2 for M_s = 0; the
+    layout with antisymmetric flip partners reproduces the determinant
+    solution."""
+    p, lam, Ft, Bt = _rotated(no, nv, na, seed)
+    ex = explicit.ExplicitESMP2(Ft, topbasis.eri_from_factor(Bt), lam, no, sign=-1)
+    ex.solve()
+    for psi in (ex.psi0, None):
+        if psi is None:
+            psi = {d: c for d, c in zip(ex.DL, ex.x)}
+            for d, b, D in zip(ex.S, ex.bS, ex.DS):
+                psi[d] = -b / D
+        sp = ex.s_plus(psi)
+        n2 = sum(v * v for v in psi.values())
+        assert abs(sum(v * v for v in sp.values()) - 2.0 * n2) < 1e-12 * n2
+    x = structured.solve(Ft, Bt, lam, no, tol=1e-14, spin=1)["x"]
+    v = _phi(layout.rep_map(no, nv, spin=1), ex.index, x)
+    np.testing.assert_allclose(v, ex.x, atol=1e-13)
+
+
 def test_structured_equals_explicit_config1():
     """P-a at the smallest workload (n_occ=4, n_vir=16, n_aux=48, seed 0)."""
     p = synth.config_problem("c1")
@@ -403,14 +449,14 @@ def test_reference_density_and_fock(no, nv, seed):
 # ---------------------------------------------------------------------------
 # derivatives of E2 (TOP-basis Fock matrix and factor, rotation held fixed)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("no,nv,na,seed", [(3, 6, 5, 1), (2, 5, 4, 3)])
-def test_gradient_equals_full_resolve_differences(no, nv, na, seed):
+@pytest.mark.parametrize("no,nv,na,seed,spin", [(3, 6, 5, 1, 0), (2, 5, 4, 3, 0), (3, 6, 5, 2, 1)])
+def test_gradient_equals_full_resolve_differences(no, nv, na, seed, spin):
     """The derivative of the functional at fixed amplitudes (the adjoint of
     the symmetric first-order equation is its own solution) equals the
     central difference of E2 itself, re-solved at each displaced point, on
     entries of every Fock block and of every factor block."""
     _, lam, Ft, Bt = _rotated(no, nv, na, seed)
-    L = gradient.Lagrangian(Ft, Bt, lam, no)
+    L = gradient.Lagrangian(Ft, Bt, lam, no, spin=spin)
     assert abs(L.value() - L.e2) < 1e-15                       # the functional's value is E2
     n = no + nv
     h = 1e-5
@@ -418,7 +464,7 @@ def test_gradient_equals_full_resolve_differences(no, nv, na, seed):
     for p, q in f_entries:
         E = np.zeros_like(Ft)
         E[p, q] = E[q, p] = h
-        fd = (gradient.e2_of(Ft + E, Bt, lam, no) - gradient.e2_of(Ft - E, Bt, lam, no)) / (2 * h)
+        fd = (gradient.e2_of(Ft + E, Bt, lam, no, spin=spin) - gradient.e2_of(Ft - E, Bt, lam, no, spin=spin)) / (2 * h)
         fd /= 1.0 if p == q else 2.0
         g = L.grad_F(p, q)
         assert abs(g - fd) <= 1e-7 * max(abs(fd), 1e-4), (p, q, g, fd)
@@ -426,7 +472,7 @@ def test_gradient_equals_full_resolve_differences(no, nv, na, seed):
     for Q, p, q in b_entries:
         E = np.zeros_like(Bt)
         E[Q, p, q] = E[Q, q, p] = h
-        fd = (gradient.e2_of(Ft, Bt + E, lam, no) - gradient.e2_of(Ft, Bt - E, lam, no)) / (2 * h)
+        fd = (gradient.e2_of(Ft, Bt + E, lam, no, spin=spin) - gradient.e2_of(Ft, Bt - E, lam, no, spin=spin)) / (2 * h)
         fd /= 1.0 if p == q else 2.0
         g = L.grad_B(Q, p, q)
         assert abs(g - fd) <= 1e-7 * max(abs(fd), 1e-4), (Q, p, q, g, fd)
