@@ -125,7 +125,10 @@ esmp2_status esmp2_destroy(esmp2_handle h);
  *   F: device, N x N row-major, symmetric (the Fock matrix, input orbital basis)
  *   B: device, n_aux x N x N row-major, B[Q][p][q] == B[Q][q][p]
  *   C: device, n_occ x n_vir row-major, ||C||_F = 1
- *   spin: 0 = singlet (only value supported); n_top: 1 (only value supported).
+ *   spin: 0 = singlet reference, 1 = the M_s = 0 component of the triplet
+ *         (paper Sec. II.A: the beta singles enter Psi0 with the opposite
+ *         sign; the first-order amplitudes are then antisymmetric under the
+ *         flip of every spin); n_top: 1 (only value supported).
  * Requires 2 <= n_occ <= n_vir, n_aux >= 1.  Checks F, B, C for NaN/Inf
  * (synchronises the stream).  Resets any previous problem. */
 esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux,
@@ -141,12 +144,13 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux,
  *   Bt: device, n_aux x N x N row-major, symmetric in its orbital pair
  *   lam: device or host, n_occ singular values, lam[0] the largest, all >= 0,
  *        sum lam^2 = 1 (within 1e-10)
+ *   spin: 0 singlet, 1 triplet (as in esmp2_set_problem)
  * Copies the inputs (the caller keeps ownership), checks them for NaN/Inf and
  * synchronises.  esmp2_rotate_top then keeps the basis as given (identity
  * rotation, lambda_out reports lam); everything else is as after
  * esmp2_set_problem.  Resets any previous problem. */
 esmp2_status esmp2_set_problem_top(esmp2_handle h, int n_occ, int n_vir, int n_aux,
-                                   const double* Ft, const double* Bt, const double* lam);
+                                   const double* Ft, const double* Bt, const double* lam, int spin);
 
 /* Rotate to the TOP basis (paper Sec. II.A).  lambda_out: host, n_occ doubles
  * (descending singular values) or NULL; when non-NULL the call synchronises. */

@@ -16,6 +16,11 @@ omega = sum_l lambda_l^2 (f_{l'l'} - f_{ll}).  The de-excitation terms are
 the adjoint (in the weighted inner product) of the excitation terms, since
 the operator is symmetric.
 
+Singlet (spin = 0) or the M_s = 0 triplet (spin = 1, beta singles of Psi0
+negated): for the triplet the first-order amplitudes are antisymmetric under
+the flip of every spin, so every term that reaches a stored amplitude through
+the flip partner of another picks up a factor -1.
+
 The right-hand side is <mu|H|Psi0> for the single-excitation reference
 (singles -> doubles: f^Phi_{ov} and the integrals with one TOP index;
 singles -> triples: antisymmetrised (ov|ov)).  E2_S is the direct

@@ -47,7 +47,8 @@ _sig = {
                           C.c_int),
     "esmp2_fock_from_core": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
                              C.c_int),
-    "esmp2_set_problem_top": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "esmp2_set_problem_top": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int],
+                              C.c_int),
     "esmp2_gradient": ([_H, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "esmp2_last_error": ([_H], C.c_char_p),
 }
@@ -110,9 +111,10 @@ class Handle:
         return self._check(lib.esmp2_set_problem(self.h, n_occ, n_vir, n_aux, _ptr(F), _ptr(B),
                                                  _ptr(Cm), spin, n_top))
 
-    def set_problem_top(self, Ft, Bt, lam, n_occ, n_vir, n_aux):
+    def set_problem_top(self, Ft, Bt, lam, n_occ, n_vir, n_aux, spin=0):
         self._n_occ = n_occ
-        return self._check(lib.esmp2_set_problem_top(self.h, n_occ, n_vir, n_aux, _ptr(Ft), _ptr(Bt), _ptr(lam)))
+        return self._check(lib.esmp2_set_problem_top(self.h, n_occ, n_vir, n_aux, _ptr(Ft), _ptr(Bt), _ptr(lam),
+                                                     spin))
 
     def gradient(self, x, dF=None, dB=None):
         """dE2/dF~ into dF (N x N) and dE2/dB~ into dB (n_aux x N x N), either may be None."""
@@ -171,14 +173,14 @@ class Handle:
         return self._check(lib.esmp2_gemm_f64(self.h, m, n, k, _ptr(A), _ptr(B), _ptr(Cm)))
 
     # convenience: bind a synthetic problem held in numpy arrays
-    def load(self, prob):
+    def load(self, prob, spin=0):
         import torch
         dev = f"cuda:{self.device}"
         self._F = torch.from_numpy(prob.F).to(dev)
         self._B = torch.from_numpy(prob.B).to(dev)
         self._C = torch.from_numpy(prob.C).to(dev)
         self._n_occ = prob.n_occ
-        self.set_problem(self._F, self._B, self._C, prob.n_occ, prob.n_vir, prob.n_aux)
+        self.set_problem(self._F, self._B, self._C, prob.n_occ, prob.n_vir, prob.n_aux, spin=spin)
         return self
 
 

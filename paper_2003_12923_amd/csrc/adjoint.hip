@@ -5,8 +5,8 @@
 // J(x) = 2 <b, x>_W + <x, A x>_W at x = -A^-1 b.  A = H0 - E0 is symmetric, so
 // the adjoint of the first-order equation is the solution x itself and
 //   dE2_DL = 2 <x, db>_W + <x, dA x>_W         (x held fixed).
-// E2_S = -sum_S b_S^2 / D_S is explicit: dE2_S = sum_S (-2 b_S db_S + (b_S/D_S)^2 dD_S) / D_S ... per
-// determinant, i.e. -2 (b/D) db + (b/D)^2 dD, counted twice (spin-flip partner).
+// E2_S = -sum_S b_S^2 / D_S is explicit: per determinant (counted twice, with
+// its spin-flip partner) dE2_S = -2 (b/D) db + (b/D)^2 dD.
 //
 // F~ enters A linearly (Fock blocks, omega, kappa), b through f^Phi_ov, and
 // D_S through its diagonal and omega.  B~ enters b through the integral blocks
@@ -161,6 +161,7 @@ __global__ void k_rhs_adj(RhsAdjArgs A) {
   const double cf = 2.0 * w * A.x[g];
   if (cf == 0.0) return;
   const double c0 = c(0);
+  const double sg = (double)d.sg;        // beta singles' terms carry sg
   switch (box) {
     case B_T2: {
       int po = loc / d.npv, pv = loc % d.npv, i, j, a, b;
@@ -172,7 +173,7 @@ __global__ void k_rhs_adj(RhsAdjArgs A) {
       int i = loc / (nov * nv), r = loc % (nov * nv);
       int j = r / (nv * nv); r %= nv * nv;
       int a = r / nv, b = r % nv;
-      addm(i, j, a, b, cf); addm(j, i, b, a, cf);
+      addm(i, j, a, b, cf); addm(j, i, b, a, sg * cf);
       break;
     }
     case B_T3: {
@@ -190,10 +191,10 @@ __global__ void k_rhs_adj(RhsAdjArgs A) {
       int po = loc / d.npv, pv = loc % d.npv, j, k, b, cc;
       tri_pq(po, no, j, k); tri_pq(pv, nv, b, cc);
       addV(j, b, k, cc, c0 * cf); addV(k, b, j, cc, -c0 * cf);
-      if (b == j) addV(0, 0, k, cc, c(j) * cf);
-      if (b == k) addV(0, 0, j, cc, -c(k) * cf);
-      if (cc == j) addV(0, 0, k, b, -c(j) * cf);
-      if (cc == k) addV(0, 0, j, b, c(k) * cf);
+      if (b == j) addV(0, 0, k, cc, sg * c(j) * cf);
+      if (b == k) addV(0, 0, j, cc, -sg * c(k) * cf);
+      if (cc == j) addV(0, 0, k, b, -sg * c(j) * cf);
+      if (cc == k) addV(0, 0, j, b, sg * c(k) * cf);
       break;
     }
     case B_H12: {
@@ -201,20 +202,22 @@ __global__ void k_rhs_adj(RhsAdjArgs A) {
       int po = loc / (m1 * m1), r = loc % (m1 * m1), j, k;
       tri_pq(po, no, j, k);
       const int a = r / m1 + 1, cc = r % m1 + 1;
-      if (j == 0) addV(0, a, k, cc, c0 * cf);
-      if (cc == j) addV(0, a, k, 0, -c(j) * cf);
-      if (k == 0) addV(0, a, j, cc, -c0 * cf);
-      if (cc == k) addV(0, a, j, 0, c(k) * cf);
+      const double sf = sg * cf;
+      if (j == 0) addV(0, a, k, cc, c0 * sf);
+      if (cc == j) addV(0, a, k, 0, -c(j) * sf);
+      if (k == 0) addV(0, a, j, cc, -c0 * sf);
+      if (cc == k) addV(0, a, j, 0, c(k) * sf);
       break;
     }
     case B_H21: {
       int o = loc / d.npv, pv = loc % d.npv, b, cc;
       const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
       tri_pq(pv, nv, b, cc);
-      if (b == 0) addV(i, 0, k, cc, c0 * cf);
-      if (b == k) addV(i, 0, 0, cc, -c(k) * cf);
-      if (cc == 0) addV(i, 0, k, b, -c0 * cf);
-      if (cc == k) addV(i, 0, 0, b, c(k) * cf);
+      const double sf = sg * cf;
+      if (b == 0) addV(i, 0, k, cc, c0 * sf);
+      if (b == k) addV(i, 0, 0, cc, -c(k) * sf);
+      if (cc == 0) addV(i, 0, k, b, -c0 * sf);
+      if (cc == k) addV(i, 0, 0, b, c(k) * sf);
       break;
     }
     default: {  // B_H22
@@ -223,8 +226,8 @@ __global__ void k_rhs_adj(RhsAdjArgs A) {
       const int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
       const int a = r / m1 + 1, cc = r % m1 + 1;
       if (a == i) addE(k, cc, c(i) * cf);
-      addV(i, a, k, cc, c0 * cf);
-      if (cc == k) addV(i, a, 0, 0, c(k) * cf);
+      addV(i, a, k, cc, sg * c0 * cf);
+      if (cc == k) addV(i, a, 0, 0, sg * c(k) * cf);
       break;
     }
   }
@@ -329,12 +332,13 @@ __device__ inline double b_mixed_adj(const E2sAdjArgs& A, int i, int a, int j, i
   const int nv = A.d.nv, nov = A.d.no * nv;
   const double s2 = 0.70710678118654752440;
   auto V = [&](int p, int x, int q, int y) { return A.V[(int64_t)(p * nv + x) * nov + q * nv + y]; };
-  double bv = 0.0;
+  double bd = 0.0;
+  if (b == j) bd += A.lam[j] * s2 * V(i, a, k, c);
+  if (b == k) bd -= A.lam[k] * s2 * V(i, a, j, c);
+  if (c == j) bd -= A.lam[j] * s2 * V(i, a, k, b);
+  if (c == k) bd += A.lam[k] * s2 * V(i, a, j, b);
+  double bv = (double)A.d.sg * bd;
   if (a == i) bv += A.lam[i] * s2 * (V(j, b, k, c) - V(k, b, j, c));
-  if (b == j) bv += A.lam[j] * s2 * V(i, a, k, c);
-  if (b == k) bv -= A.lam[k] * s2 * V(i, a, j, c);
-  if (c == j) bv -= A.lam[j] * s2 * V(i, a, k, b);
-  if (c == k) bv += A.lam[k] * s2 * V(i, a, j, b);
   return bv;
 }
 
@@ -345,6 +349,7 @@ __device__ inline void scatter_mixed(const E2sAdjArgs& A, int i, int a, int j, i
     unsafeAtomicAdd(&A.GV[(int64_t)(p * nv + x) * nov + q * nv + y], v);
   };
   if (a == i) { add(j, b, k, c, g * A.lam[i] * s2); add(k, b, j, c, -g * A.lam[i] * s2); }
+  g *= (double)A.d.sg;                    // the remaining terms come from the beta singles
   if (b == j) add(i, a, k, c, g * A.lam[j] * s2);
   if (b == k) add(i, a, j, c, -g * A.lam[k] * s2);
   if (c == j) add(i, a, k, b, -g * A.lam[j] * s2);

@@ -293,11 +293,12 @@ static esmp2_status check_sizes(esmp2_handle h, int n_occ, int n_vir, int n_aux)
 // either C (the ESMF singles, rotated to the TOP basis later) or, for a problem
 // already in the TOP basis, its singular values lam.
 static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* F,
-                                  const double* B, const double* C, const double* lam) {
+                                  const double* B, const double* C, const double* lam, int spin) {
   ESMP2_HIP(hipSetDevice(h->device));
   ESMP2_HIP(hipStreamSynchronize(h->stream));
   release(h);
   Dims d = make_dims(n_occ, n_vir, n_aux);
+  d.sg = spin ? -1 : 1;
   h->d = d;
   const int no = n_occ, nv = n_vir, n = d.n, na = n_aux, mv = d.mv;
   const int64_t namp = d.off[7];
@@ -422,15 +423,16 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
   if (!F || !B || !C) return fail(h, ESMP2_INVALID_ARG, "null input pointer");
   esmp2_status st = check_sizes(h, n_occ, n_vir, n_aux);
   if (st != ESMP2_OK) return st;
-  if (spin != 0) return fail(h, ESMP2_UNSUPPORTED, "only the singlet (spin = 0) is implemented");
+  if (spin != 0 && spin != 1) return fail(h, ESMP2_INVALID_ARG, "spin must be 0 (singlet) or 1 (triplet)");
   if (n_top != 1) return fail(h, ESMP2_UNSUPPORTED, "only n_top = 1 (ESMP2-TOP(1)) is implemented");
-  return setup_problem(h, n_occ, n_vir, n_aux, F, B, C, nullptr);
+  return setup_problem(h, n_occ, n_vir, n_aux, F, B, C, nullptr, spin);
 }
 
 esmp2_status esmp2_set_problem_top(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* Ft,
-                                   const double* Bt, const double* lam) {
+                                   const double* Bt, const double* lam, int spin) {
   if (!h) return ESMP2_INVALID_ARG;
   if (!Ft || !Bt || !lam) return fail(h, ESMP2_INVALID_ARG, "null input pointer");
+  if (spin != 0 && spin != 1) return fail(h, ESMP2_INVALID_ARG, "spin must be 0 (singlet) or 1 (triplet)");
   esmp2_status st = check_sizes(h, n_occ, n_vir, n_aux);
   if (st != ESMP2_OK) return st;
   std::vector<double> l(n_occ);
@@ -442,7 +444,7 @@ esmp2_status esmp2_set_problem_top(esmp2_handle h, int n_occ, int n_vir, int n_a
     s2 += l[k] * l[k];
   }
   if (!(fabs(s2 - 1.0) <= 1e-10)) return fail(h, ESMP2_INVALID_ARG, "sum of lam^2 must be 1 (normalised reference)");
-  return setup_problem(h, n_occ, n_vir, n_aux, Ft, Bt, nullptr, lam);
+  return setup_problem(h, n_occ, n_vir, n_aux, Ft, Bt, nullptr, lam, spin);
 }
 
 esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
@@ -1414,18 +1416,19 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
     c = C(T3, 0, T2, sT2[1] + 1); E(c, 0, o1, sT3[0], 0); E(c, 1, v1, sT3[2], 0);
     K(c, 0, o1, sT3[1], sT2[1]); K(c, 1, v1, 1, 1);
     ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
-    // S3 boxes <- T2
+    // S3 boxes <- T2 (through the flip partner of T2: sg)
+    const double sg = (double)d.sg;
     c = C(H11, 0, T2, 0); K(c, 0, (int)nd, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 1.0, G, N * N, ov, 0, 0));
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), sg * 1.0, G, N * N, ov, 0, 0));
     c = C(H12, 0, T2, 1); E(c, 0, v1, v1, 0);
     K(c, 0, no, sH12[0], sT2[0]); K(c, 1, no, sH12[1], sT2[1]); K(c, 2, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 2.0, G, N * N, ov + 1, 1, 0));
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), sg * 2.0, G, N * N, ov + 1, 1, 0));
     c = C(H21, 0, T2, sT2[1]); E(c, 0, o1, sH21[0], 0);
     K(c, 0, o1, sH21[1], sT2[1]); K(c, 1, nv * nv, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 2.0, G, N * N, N + ov, N, 0));
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), sg * 2.0, G, N * N, N + ov, N, 0));
     c = C(H22, 0, T2, sT2[1] + 1); E(c, 0, o1, sH22[0], 0); E(c, 1, v1, v1, 0);
     K(c, 0, o1, sH22[1], sT2[1]); K(c, 1, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
+    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), sg * 4.0, G, N * N, N + ov + 1, N, 1));
     // S3 boxes <- S~
     c = C(H11, 0, St, 0); E(c, 0, no, sT2[0], 0); E(c, 1, nv, nv, 0);
     K(c, 0, no, sT2[1], sT2[1]); K(c, 1, nv, 1, 1);

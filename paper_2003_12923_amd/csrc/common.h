@@ -15,6 +15,7 @@ struct Dims {
   int npv;               // C(nv,2)   virtual pairs
   int npv1;              // C(nv-1,2) virtual pairs excluding t'
   int mv;                // nv rounded up to a multiple of 16 (padded virtual dimension)
+  int sg;                // spin-flip sign of the first-order amplitudes: +1 singlet, -1 M_s = 0 triplet
   int64_t off[8];        // box offsets, off[7] = total amplitudes
 };
 
@@ -28,6 +29,7 @@ inline Dims make_dims(int no, int nv, int naux) {
   d.npv = nv * (nv - 1) / 2;
   d.npv1 = (nv - 1) * (nv - 2) / 2;
   d.mv = (nv + 15) / 16 * 16;
+  d.sg = 1;
   int64_t s[7];
   s[0] = (int64_t)d.npo * d.npv;
   s[1] = (int64_t)no * no * nv * nv;

@@ -2,8 +2,12 @@
 // denominators D_mu = <mu|F|mu> - E0, and the directly inverted S-triple
 // energy E2_S = -sum_S b^2/D (paper Sec. II.B-II.D).
 //
-// Reference Psi0 = sum_l c_l (a+_{l' u} a_{l u} + a+_{l' d} a_{l d})|Phi>,
-// c_l = lambda_l / sqrt(2), TOP basis (t = occupied 0, t' = virtual 0).
+// Reference Psi0 = sum_l c_l (a+_{l' u} a_{l u} + sg a+_{l' d} a_{l d})|Phi>,
+// c_l = lambda_l / sqrt(2), TOP basis (t = occupied 0, t' = virtual 0);
+// sg = +1 for the singlet, -1 for the M_s = 0 triplet.  A stored amplitude
+// receives the alpha singles' terms as they are and the beta singles' terms
+// times sg (the flip partner of a stored determinant carries sg times its
+// amplitude).
 // Singles -> doubles couple through f^Phi (Fock matrix of the closed shell)
 // and the integrals with one TOP index; singles -> triples through the
 // antisymmetrised (ov|ov) integrals.  Integral blocks (DF form):
@@ -114,6 +118,7 @@ __global__ void k_rhs(RhsArgs A) {
   };
   double out = 0.0;
   const double c0 = c(0);
+  const double sg = (double)d.sg;
   switch (box) {
     case B_T2: {
       int po = loc / d.npv, pv = loc % d.npv, i, j, a, b;
@@ -125,7 +130,7 @@ __global__ void k_rhs(RhsArgs A) {
       int i = loc / (nov * nv), r = loc % (nov * nv);
       int j = r / (nv * nv); r %= nv * nv;
       int a = r / nv, b = r % nv;
-      out = m(i, j, a, b) + m(j, i, b, a);
+      out = m(i, j, a, b) + sg * m(j, i, b, a);        // second term: the beta singles
       break;
     }
     case B_T3: {
@@ -143,11 +148,12 @@ __global__ void k_rhs(RhsArgs A) {
     case B_H11: {
       int po = loc / d.npv, pv = loc % d.npv, j, k, b, cc;
       tri_pq(po, no, j, k); tri_pq(pv, nv, b, cc);
-      out = c0 * (V(j, b, k, cc) - V(k, b, j, cc));
-      if (b == j) out += c(j) * V(0, 0, k, cc);
-      if (b == k) out -= c(k) * V(0, 0, j, cc);
-      if (cc == j) out -= c(j) * V(0, 0, k, b);
-      if (cc == k) out += c(k) * V(0, 0, j, b);
+      double o2 = 0.0;                                    // beta singles (down TOP pairs)
+      if (b == j) o2 += c(j) * V(0, 0, k, cc);
+      if (b == k) o2 -= c(k) * V(0, 0, j, cc);
+      if (cc == j) o2 -= c(j) * V(0, 0, k, b);
+      if (cc == k) o2 += c(k) * V(0, 0, j, b);
+      out = c0 * (V(j, b, k, cc) - V(k, b, j, cc)) + sg * o2;
       break;
     }
     case B_H12: {
@@ -155,20 +161,22 @@ __global__ void k_rhs(RhsArgs A) {
       int po = loc / (m1 * m1), r = loc % (m1 * m1), j, k;
       tri_pq(po, no, j, k);
       int a = r / m1 + 1, cc = r % m1 + 1;
-      if (j == 0) out += c0 * V(0, a, k, cc);
+      if (j == 0) out += c0 * V(0, a, k, cc);            // all from the beta singles
       if (cc == j) out -= c(j) * V(0, a, k, 0);
       if (k == 0) out -= c0 * V(0, a, j, cc);
       if (cc == k) out += c(k) * V(0, a, j, 0);
+      out *= sg;
       break;
     }
     case B_H21: {
       int o = loc / d.npv, pv = loc % d.npv, b, cc;
       int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
       tri_pq(pv, nv, b, cc);
-      if (b == 0) out += c0 * V(i, 0, k, cc);
+      if (b == 0) out += c0 * V(i, 0, k, cc);            // all from the beta singles
       if (b == k) out -= c(k) * V(i, 0, 0, cc);
       if (cc == 0) out -= c0 * V(i, 0, k, b);
       if (cc == k) out += c(k) * V(i, 0, 0, b);
+      out *= sg;
       break;
     }
     default: {  // B_H22
@@ -176,9 +184,10 @@ __global__ void k_rhs(RhsArgs A) {
       int o = loc / (m1 * m1), r = loc % (m1 * m1);
       int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
       int a = r / m1 + 1, cc = r % m1 + 1;
-      if (a == i) out += c(i) * (V(0, 0, k, cc) - V(k, 0, 0, cc));
-      out += c0 * V(i, a, k, cc);
-      if (cc == k) out += c(k) * V(i, a, 0, 0);
+      double o2 = c0 * V(i, a, k, cc);                   // beta singles
+      if (cc == k) o2 += c(k) * V(i, a, 0, 0);
+      out = sg * o2;
+      if (a == i) out += c(i) * (V(0, 0, k, cc) - V(k, 0, 0, cc));    // the alpha single i -> i'
       break;
     }
   }
@@ -334,12 +343,13 @@ __device__ inline double b_mixed(const E2sArgs& A, int i, int a, int j, int k, i
   const int nv = A.d.nv, nov = A.d.no * nv;
   const double s2 = 0.70710678118654752440;
   auto V = [&](int p, int x, int q, int y) { return A.V[(int64_t)(p * nv + x) * nov + q * nv + y]; };
-  double bv = 0.0;
-  if (a == i) bv += A.lam[i] * s2 * (V(j, b, k, c) - V(k, b, j, c));
-  if (b == j) bv += A.lam[j] * s2 * V(i, a, k, c);
-  if (b == k) bv -= A.lam[k] * s2 * V(i, a, j, c);
-  if (c == j) bv -= A.lam[j] * s2 * V(i, a, k, b);
-  if (c == k) bv += A.lam[k] * s2 * V(i, a, j, b);
+  double bd = 0.0;                                 // beta singles (down TOP pairs)
+  if (b == j) bd += A.lam[j] * s2 * V(i, a, k, c);
+  if (b == k) bd -= A.lam[k] * s2 * V(i, a, j, c);
+  if (c == j) bd -= A.lam[j] * s2 * V(i, a, k, b);
+  if (c == k) bd += A.lam[k] * s2 * V(i, a, j, b);
+  double bv = (double)A.d.sg * bd;
+  if (a == i) bv += A.lam[i] * s2 * (V(j, b, k, c) - V(k, b, j, c));     // the alpha single i -> i'
   return bv;
 }
 

@@ -68,7 +68,7 @@ struct Look {
 };
 
 // ---------------------------------------------------------------------------
-// S~ = (x_S2 + flip x_S2)/2, flip: (i,j,a,b) -> (j,i,b,a)
+// S~ = (x_S2 + sg flip x_S2)/2, flip: (i,j,a,b) -> (j,i,b,a); sg = +1 singlet, -1 triplet
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void k_sym_s2(Dims d, const T* x, T* S) {
@@ -79,7 +79,7 @@ __global__ void k_sym_s2(Dims d, const T* x, T* S) {
   const int i = o / d.no, j = o - i * d.no;
   const int a = v / d.nv, b = v - a * d.nv;
   const T* s2 = x + d.off[B_S2];
-  S[g] = T(0.5) * (s2[g] + s2[(j * d.no + i) * nv2 + b * d.nv + a]);
+  S[g] = T(0.5) * (s2[g] + T(d.sg) * s2[(j * d.no + i) * nv2 + b * d.nv + a]);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,29 +350,33 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
   switch (box) {
     case B_T2: {
       const int i = p0, j = q0, t = P.pv[v], a = t >> 16, b = t & 0xffff;
+      // from the L-triples: the same-spin T3L directly, the mixed-spin boxes
+      // through their spin-flip partners (amplitude sg x)
+      T ys = 0;
       if (i >= 1 && a >= 1) y += ftt * L.T3(i, j, a, b);
-      y += ftt * L.H11(i, j, a, b);
+      ys += ftt * L.H11(i, j, a, b);
       if (i == 0) {
         if (a >= 1)
           for (int m = 1; m < no; ++m) y -= FOV(m, 0) * L.T3(m, j, a, b);
-        for (int m = 1; m < no; ++m) y += FOV(m, 0) * L.H21(m, j, a, b);
+        for (int m = 1; m < no; ++m) ys += FOV(m, 0) * L.H21(m, j, a, b);
       }
       if (a == 0) {
         if (i >= 1) y -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
-        y += A.h12_t[batch * nv + b];
+        ys += A.h12_t[batch * nv + b];
         if (i == 0) {
           for (int m = 1; m < no; ++m) {
             if (m < j) y += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
             else if (m > j) y -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
-            y += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
+            ys += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
           }
         }
       }
+      y += T(d.sg) * ys;
       break;
     }
     case B_S2: {
       const int i = p0, j = q0, a = v / nv, b = v - a * nv;
-      // d(p,q,x,z) + d(q,p,z,x): de-excitation of the mixed-spin L-triples
+      // d(p,q,x,z) + sg d(q,p,z,x): de-excitation of the mixed-spin L-triples and their flip partners
       for (int rep = 0; rep < 2; ++rep) {
         const int p = rep ? j : i, q = rep ? i : j, xx = rep ? b : a, z = rep ? a : b;
         T dd = 0;
@@ -403,7 +407,7 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
             for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
           }
         }
-        y += dd;
+        y += (rep ? T(d.sg) : T(1)) * dd;
       }
       break;
     }
@@ -418,7 +422,7 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
       const int j = p0, k = q0, t = P.pv[v], b = t >> 16, c = t & 0xffff;
       if (j == 0)
         for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H21(m, k, b, c);
-      y += ftt * L.T2(j, k, b, c);
+      y += T(d.sg) * ftt * L.T2(j, k, b, c);                 // flip partner of T2 (down-down)
       y += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
          - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
       break;
@@ -428,7 +432,7 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
       y += fv[a * nv + 0] * L.H11(j, k, 0, c);
       if (j == 0)
         for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H22(m, k, a, c);
-      y += FOV(0, a) * L.T2(j, k, 0, c);
+      y += T(d.sg) * FOV(0, a) * L.T2(j, k, 0, c);
       y += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
          - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
       break;
@@ -436,7 +440,7 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
     case B_H21: {
       const int i = p0, k = q0, t = P.pv[v], b = t >> 16, c = t & 0xffff;
       y -= fo[0 * no + i] * L.H11(0, k, b, c);
-      y += FOV(i, 0) * L.T2(0, k, b, c);
+      y += T(d.sg) * FOV(i, 0) * L.T2(0, k, b, c);
       y += FOV(0, b) * L.St(i, k, 0, c) - FOV(k, b) * L.St(i, 0, 0, c)
          - FOV(0, c) * L.St(i, k, 0, b) + FOV(k, c) * L.St(i, 0, 0, b);
       break;
@@ -445,7 +449,7 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
       const int i = p0, k = q0, a = v / m1 + 1, c = v - (a - 1) * m1 + 1;
       y -= fo[0 * no + i] * L.H12(0, k, a, c);
       y += fv[a * nv + 0] * L.H21(i, k, 0, c);
-      y += FOV(i, a) * L.T2(0, k, 0, c);
+      y += T(d.sg) * FOV(i, a) * L.T2(0, k, 0, c);
       y += ftt * L.St(i, k, a, c) - FOV(k, 0) * L.St(i, 0, a, c)
          - FOV(0, c) * L.St(i, k, a, 0) + FOV(k, c) * L.St(i, 0, a, 0);
       break;

@@ -22,6 +22,7 @@ struct V3Ctx {
   T* tr;                 // H1P2/H2P2: transfer row
   const T* F;            // F' (mv x mv)
   int m;                 // storage dimension (nv or nv-1)
+  T sg;                  // S2: the flip partner of batch (i, j) is sg times the transpose of (j, i)
 };
 
 // element (r, c) of the embedded batch matrix; branch-free select, in-bounds address
@@ -70,12 +71,12 @@ __device__ inline void y3(const V3Ctx<T>& c, int r, int col, T val, bool diag_ti
   } else if (FMT == K3_S2PAIR) {
     if (r < c.m && col < c.m) {
       c.dst[r * c.m + col] = val;
-      c.dstT[col * c.m + r] = val;
+      c.dstT[col * c.m + r] = c.sg * val;
     }
   } else {
     if (r < c.m && col < c.m) {
       c.dst[r * c.m + col] = val;
-      if (!diag_tile) c.dst[col * c.m + r] = val;
+      if (!diag_tile) c.dst[col * c.m + r] = c.sg * val;
     }
   }
 }
@@ -204,6 +205,7 @@ __global__ __launch_bounds__(256) void k_vv3(VVArgs<T> A) {
   c.F = (box == B_T2 || box == B_S2) ? A.Fd : A.Fl;
   c.dstT = nullptr;
   c.tr = nullptr;
+  c.sg = T(d.sg);
   if (box == B_S2) {
     const int si = jb.y, sj = jb.w;
     c.m = d.nv;
