@@ -754,11 +754,11 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
     }
   }
   if (d.mv == 160) {
-    hipLaunchKernelGGL((k_vv3<T, 10>), dim3(h->njobs4), dim3(256), 0, s, va);
+    hipLaunchKernelGGL((k_vv3<T, 10>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
   } else if (d.mv == 112) {
-    hipLaunchKernelGGL((k_vv3<T, 7>), dim3(h->njobs4), dim3(256), 0, s, va);
+    hipLaunchKernelGGL((k_vv3<T, 7>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
   } else if (d.mv == 80) {
-    hipLaunchKernelGGL((k_vv3<T, 5>), dim3(h->njobs4), dim3(256), 0, s, va);
+    hipLaunchKernelGGL((k_vv3<T, 5>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
   } else switch (tw) {
     case 1: hipLaunchKernelGGL((k_vv<T, 1>), grid, dim3(256), 0, s, va); break;
     case 2: hipLaunchKernelGGL((k_vv<T, 2>), grid, dim3(256), 0, s, va); break;

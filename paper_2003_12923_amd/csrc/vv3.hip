@@ -1,11 +1,16 @@
 // Specialised Sylvester kernel Y = F' X + X F' on FP64 matrix cores for the
 // padded virtual dimension mv = 16 * NT (NT <= 10 tiles), one batch matrix per
-// workgroup of 4 wavefronts.  Everything that varies per job -- the storage
-// format of X, the output symmetry, and the block of 16x16 output tiles a
-// wavefront owns -- is a template parameter, so the matrix-core loop is
-// straight-line code.  K runs over 2*mv (k < mv: A = F', B = X; k >= mv:
-// A = X, B = F') in 16-wide chunks staged through double-buffered LDS; the
-// next chunk is loaded into registers while the current one is multiplied.
+// workgroup of 8 wavefronts, two per SIMD: the output tiles are dealt to the
+// four SIMDs in blocks and each block is split between the SIMD's two
+// wavefronts, so that one wavefront's LDS waits and staging overlap the
+// other's matrix-core work (and each holds half the accumulators).
+// Everything that varies per job -- the storage format of X, the output
+// symmetry, and the block of 16x16 output tiles a wavefront owns -- is a
+// template parameter, so the matrix-core loop is straight-line code.  K runs
+// over 2*mv (k < mv: A = F', B = X; k >= mv: A = X, B = F') in 16-wide chunks
+// staged through double-buffered LDS; the next chunk is loaded into registers
+// while the current one is multiplied.
+#include <type_traits>
 #include "common.h"
 #include "mfma.h"
 #include "sigma.h"
@@ -81,17 +86,37 @@ __device__ inline void y3(const V3Ctx<T>& c, int r, int col, T val, bool diag_ti
   }
 }
 
-// tile block owned by a wavefront
+constexpr int V3_THREADS = 512;
+
+// rows of the first part when the upper triangle (diagonal included) of an
+// n x n tile block is split by rows into two parts of nearly equal tile counts
+constexpr int tri_split_rows(int n) {
+  int acc = 0, r = 0;
+  while (r < n && 2 * (acc + (n - r)) <= n * (n + 1) / 2 + (n - r)) { acc += n - r; ++r; }
+  return r;
+}
+
+// tile block owned by a wavefront.  SIMD s = WAVE % 4 owns a block (one of the
+// four quadrants of a dense output; for an upper-triangular output: the two
+// diagonal triangles and two rectangles above them); wavefront WAVE / 4 of
+// that SIMD takes the first or the second part of it (triangles split by rows,
+// rectangles by columns).
 template <int NT, bool TRIKIND, int WAVE>
 struct WRect {
+  static constexpr int S = WAVE & 3, PART = WAVE >> 2;
   static constexpr int H = (NT + 1) / 2;
   static constexpr int SPLIT = H + (NT - H) / 2;
-  static constexpr int R0 = TRIKIND ? (WAVE == 3 ? H : 0) : ((WAVE >> 1) * H);
-  static constexpr int R1 = TRIKIND ? (WAVE == 3 ? NT : H) : ((WAVE >> 1) ? NT : H);
-  static constexpr int C0 = TRIKIND ? (WAVE == 0 ? 0 : WAVE == 1 ? SPLIT : H) : ((WAVE & 1) * H);
-  static constexpr int C1 = TRIKIND ? (WAVE == 0 ? H : WAVE == 1 ? NT : WAVE == 2 ? SPLIT : NT)
-                                    : ((WAVE & 1) ? NT : H);
-  static constexpr bool TRI = TRIKIND && (WAVE == 0 || WAVE == 3);
+  static constexpr int BR0 = TRIKIND ? (S == 3 ? H : 0) : ((S >> 1) * H);
+  static constexpr int BR1 = TRIKIND ? (S == 3 ? NT : H) : ((S >> 1) ? NT : H);
+  static constexpr int BC0 = TRIKIND ? (S == 0 ? 0 : S == 1 ? SPLIT : H) : ((S & 1) * H);
+  static constexpr int BC1 = TRIKIND ? (S == 0 ? H : S == 1 ? NT : S == 2 ? SPLIT : NT) : ((S & 1) ? NT : H);
+  static constexpr bool TRI = TRIKIND && (S == 0 || S == 3);
+  static constexpr int RS = tri_split_rows(BR1 - BR0);        // triangle: rows of the first part
+  static constexpr int CS = (BC1 - BC0 + 1) / 2;              // rectangle: columns of the first part
+  static constexpr int R0 = TRI ? (PART ? BR0 + RS : BR0) : BR0;
+  static constexpr int R1 = TRI ? (PART ? BR1 : BR0 + RS) : BR1;
+  static constexpr int C0 = TRI ? (PART ? BC0 + RS : BC0) : (PART ? BC0 + CS : BC0);
+  static constexpr int C1 = TRI ? BC1 : (PART ? BC1 : BC0 + CS);
   static constexpr int NR = R1 - R0 > 0 ? R1 - R0 : 1;
   static constexpr int NC = C1 - C0 > 0 ? C1 - C0 : 1;
   static constexpr bool EMPTY = (R1 <= R0) || (C1 <= C0);
@@ -110,65 +135,85 @@ __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx<T>& c
   for (int i = 0; i < Rc::NR; ++i)
 #pragma unroll
     for (int j = 0; j < Rc::NC; ++j) acc[i][j] = AccT{0, 0, 0, 0};
-  // staging map: A chunk (MV rows x 16 k): thread -> k = tid & 15, rows (tid >> 4) + 16 t;
-  //              B chunk (16 k x MV cols): thread -> k = tid >> 4, cols (tid & 15) + 16 t
-  T pa[NT], pb[NT];
-  const int lo4 = tid & 15, hi4 = tid >> 4;
+  // staging map (512 threads): A chunk (MV rows x 16 k): thread -> k = tid & 15,
+  //   rows (tid >> 4) + 32 t;  B chunk (16 k x MV cols): thread -> k = tid >> 5,
+  //   cols (tid & 31) + 32 t;  t < ceil(NT / 2), rows / cols < MV
+  constexpr int NS = (NT + 1) / 2;
+  T pa[NS], pb[NS];
+  const int ka = tid & 15, ra = tid >> 4, kb4 = tid >> 5, cb = tid & 31;
   auto fetch = [&](int k0) {
     const bool second = k0 >= MV;
     const int kb = second ? k0 - MV : k0;
-    if (second) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        pa[t] = x3<FMT, T>(c, hi4 + 16 * t, kb + lo4);
-        pb[t] = c.F[(kb + hi4) * MV + lo4 + 16 * t];
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        pa[t] = c.F[(hi4 + 16 * t) * MV + kb + lo4];
-        pb[t] = x3<FMT, T>(c, kb + hi4, lo4 + 16 * t);
+    for (int t = 0; t < NS; ++t) {
+      const int r = ra + 32 * t, col = cb + 32 * t;
+      const bool okr = (2 * NS == NT) || r < MV, okc = (2 * NS == NT) || col < MV;
+      if (second) {
+        pa[t] = okr ? x3<FMT, T>(c, r, kb + ka) : T(0);
+        pb[t] = okc ? c.F[(kb + kb4) * MV + col] : T(0);
+      } else {
+        pa[t] = okr ? c.F[r * MV + kb + ka] : T(0);
+        pb[t] = okc ? x3<FMT, T>(c, kb + kb4, col) : T(0);
       }
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      As[buf][lo4][hi4 + 16 * t] = pa[t];
-      Bs[buf][hi4][lo4 + 16 * t] = pb[t];
+    for (int t = 0; t < NS; ++t) {
+      const int r = ra + 32 * t, col = cb + 32 * t;
+      if ((2 * NS == NT) || r < MV) As[buf][ka][r] = pa[t];
+      if ((2 * NS == NT) || col < MV) Bs[buf][kb4][col] = pb[t];
     }
   };
-  constexpr int NCH = 2 * MV / 16;
-  fetch(0);
-  stash(0);
-  fetch(16);
-  __syncthreads();
-  for (int q = 0; q < NCH; ++q) {
-    const int buf = q & 1;
-    if (!Rc::EMPTY) {
+  constexpr int NCH = 2 * MV / 16;                 // even for every instantiated NT
+  // One K chunk from LDS buffer BUF; with STASH / FETCH the staging of chunks
+  // q+1 and q+2 is placed between the matrix-core groups, so that its loads
+  // and LDS stores issue while the matrix cores are busy.  The buffer and the
+  // staging switches are compile-time, so the loop body has no branches and
+  // the accumulators stay in place across iterations.
+  auto chunk = [&](int q, auto buf_c, auto stash_c, auto fetch_c) {
+    constexpr int BUF = decltype(buf_c)::value;
+    constexpr bool STASH = decltype(stash_c)::value, FETCH = decltype(fetch_c)::value;
+    if constexpr (!Rc::EMPTY) {
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         T a[Rc::NR], b[Rc::NC];
 #pragma unroll
-        for (int t = 0; t < Rc::NR; ++t) a[t] = As[buf][ks * 4 + (l >> 4)][(Rc::R0 + t) * 16 + (l & 15)];
+        for (int t = 0; t < Rc::NR; ++t) a[t] = As[BUF][ks * 4 + (l >> 4)][(Rc::R0 + t) * 16 + (l & 15)];
 #pragma unroll
-        for (int t = 0; t < Rc::NC; ++t) b[t] = Bs[buf][ks * 4 + (l >> 4)][(Rc::C0 + t) * 16 + (l & 15)];
+        for (int t = 0; t < Rc::NC; ++t) b[t] = Bs[BUF][ks * 4 + (l >> 4)][(Rc::C0 + t) * 16 + (l & 15)];
 #pragma unroll
         for (int i = 0; i < Rc::NR; ++i)
 #pragma unroll
           for (int j = 0; j < Rc::NC; ++j)
             if (!Rc::TRI || Rc::C0 + j >= Rc::R0 + i) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
-        // staging of later chunks placed between the matrix-core groups, so that
-        // its loads and LDS stores issue while the matrix cores are busy
-        if (ks == 0 && q + 1 < NCH) stash(buf ^ 1);        // chunk q+1 (loaded one iteration ago)
-        if (ks == 1 && q + 2 < NCH) fetch((q + 2) * 16);
+        if constexpr (STASH) { if (ks == 0) stash(BUF ^ 1); }     // chunk q+1 (loaded one chunk ago)
+        if constexpr (FETCH) { if (ks == 1) fetch((q + 2) * 16); }
       }
-    } else if (q + 1 < NCH) {
-      stash(buf ^ 1);
-      if (q + 2 < NCH) fetch((q + 2) * 16);
+    } else {
+      if constexpr (STASH) stash(BUF ^ 1);
+      if constexpr (FETCH) fetch((q + 2) * 16);
     }
     __syncthreads();
+  };
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
+  using Yes = std::true_type;
+  using No = std::false_type;
+  fetch(0);
+  stash(0);
+  fetch(16);
+  __syncthreads();
+  // the first pair of chunks outside the loop: the accumulators enter the loop
+  // as matrix-core results rather than as the zero initialisation
+  chunk(0, B0{}, Yes{}, Yes{});
+  chunk(1, B1{}, Yes{}, Yes{});
+  for (int q = 2; q < NCH - 2; q += 2) {
+    chunk(q, B0{}, Yes{}, Yes{});
+    chunk(q + 1, B1{}, Yes{}, Yes{});
   }
+  chunk(NCH - 2, B0{}, Yes{}, No{});
+  chunk(NCH - 1, B1{}, No{}, No{});
   if (Rc::EMPTY) return;
 #pragma unroll
   for (int i = 0; i < Rc::NR; ++i)
@@ -189,13 +234,17 @@ __device__ inline void vv3_dispatch(const V3Ctx<T>& c, T (*As)[16][16 * NT + 1],
     case 0: vv3_body<T, FMT, NT, 0>(c, As, Bs); break;
     case 1: vv3_body<T, FMT, NT, 1>(c, As, Bs); break;
     case 2: vv3_body<T, FMT, NT, 2>(c, As, Bs); break;
-    default: vv3_body<T, FMT, NT, 3>(c, As, Bs); break;
+    case 3: vv3_body<T, FMT, NT, 3>(c, As, Bs); break;
+    case 4: vv3_body<T, FMT, NT, 4>(c, As, Bs); break;
+    case 5: vv3_body<T, FMT, NT, 5>(c, As, Bs); break;
+    case 6: vv3_body<T, FMT, NT, 6>(c, As, Bs); break;
+    default: vv3_body<T, FMT, NT, 7>(c, As, Bs); break;
   }
 }
 
 // jobs4: (box, batch or i, format code, j)
 template <class T, int NT>
-__global__ __launch_bounds__(256) void k_vv3(VVArgs<T> A) {
+__global__ __launch_bounds__(V3_THREADS, 1) void k_vv3(VVArgs<T> A) {
   __shared__ T As[2][16][16 * NT + 1];
   __shared__ T Bs[2][16][16 * NT + 1];
   const int4 jb = A.jobs4[blockIdx.x];
