@@ -250,16 +250,53 @@ struct E2sAdjArgs {
   double* Gom;      // 1
 };
 
+// Orbital-energy parts of the S-triple gradient, summed in LDS per workgroup.
+// The loops below keep every lane of a wavefront in step (an out-of-range lane
+// carries gd = 0), so that wavefront-wide reductions can replace atomics on
+// keys that many lanes share:
+//   * a key fixed for a whole row of the grid: per-thread registers, one
+//     workgroup sum per row;
+//   * a key that changes slowly along the lanes: wave_keyed_add (one LDS atomic
+//     per distinct key in the wavefront);
+//   * a key that differs from lane to lane: a plain LDS atomic.
 struct SAcc {
   double* ev;     // LDS, 192
   double* eo;     // LDS, 64
   double* om;     // LDS, 1
 };
 
-__device__ inline void s_diag(const SAcc& s, const int* P, const int* I, double gd) {
-  for (int k = 0; k < 3; ++k) atomicAdd(&s.ev[P[k]], gd);
-  for (int k = 0; k < 3; ++k) atomicAdd(&s.eo[I[k]], -gd);
-  atomicAdd(s.om, -gd);
+// acc1[key] += v (and acc2[key] += v2 when acc2 is given) summed over the
+// wavefront, one LDS atomic per distinct key.  Every lane of the wavefront
+// calls it; a lane with nothing to add passes v = 0 and any valid key.
+__device__ inline void wave_keyed_add(double* acc1, double* acc2, int key, double v, double v2) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = ~0ull;
+  while (pending) {
+    const int src = __ffsll((long long)pending) - 1;
+    const int k0 = __shfl(key, src);
+    const bool mine = (key == k0);
+    const double s1 = wave_sum(mine ? v : 0.0);
+    const double s2 = acc2 ? wave_sum(mine ? v2 : 0.0) : 0.0;
+    if (lane == src) {
+      atomicAdd(&acc1[k0], s1);
+      if (acc2) atomicAdd(&acc2[k0], s2);
+    }
+    pending &= ~__ballot(mine);
+  }
+}
+
+// adds the row-fixed registers (particle pf, hole hf, omega) of the workgroup
+__device__ inline void s_row_flush(const SAcc& s, int pf, int hf, double& rp, double& rh, double& ro) {
+  const double a = block_sum(rp);
+  const double b = block_sum(rh);
+  const double c = block_sum(ro);
+  if (threadIdx.x == 0) {
+    s.ev[pf] += a;
+    s.eo[hf] += b;
+    s.om[0] += c;
+  }
+  rp = rh = ro = 0.0;
+  __syncthreads();
 }
 
 __device__ inline void s_flush(const E2sAdjArgs& A, const SAcc& s) {
@@ -283,47 +320,63 @@ __device__ inline void sort3_adj(int& x, int& y, int& z) {
   if (x > y) { int t = x; x = y; y = t; }
 }
 
-// same-spin sector (enumeration of the energy kernel)
+// same-spin sector (enumeration of the energy kernel): triples {l, j, k; l', b, c},
+// l fixed per grid row
 __global__ __launch_bounds__(256) void k_e2s_same_adj(E2sAdjArgs A) {
   ESMP2_SACC_DECL
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv, nov = no * nv;
   const int per_l = d.npo1 * d.npv1;
   const double s2 = 0.70710678118654752440;
-  for (int l = 1 + blockIdx.y; l < no; l += gridDim.y)
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < per_l; r += gridDim.x * blockDim.x) {
-      const int to = A.po1[r / d.npv1], tv = A.pv1[r % d.npv1];
-      const int jr = to >> 16, kr = to & 0xffff, br = tv >> 16, cr = tv & 0xffff;
-      const int j = jr + (jr >= l), k = kr + (kr >= l), b = br + (br >= l), c = cr + (cr >= l);
-      if ((j < l && (j == b || j == c)) || (k < l && (k == b || k == c))) continue;
-      int I[3] = {l, j, k}, P[3] = {l, b, c};
-      sort3_adj(I[0], I[1], I[2]);
-      sort3_adj(P[0], P[1], P[2]);
-      double bv = 0.0;
-      for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) {
-          if (P[p] != I[q]) continue;
-          const int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
-          const int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
-          const double anti = A.V[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2] -
-                              A.V[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2];
-          const double sg = ((p + q) & 1) ? -1.0 : 1.0;
-          bv += sg * A.lam[I[q]] * s2 * anti;
+  double rp = 0.0, rh = 0.0, ro = 0.0;
+  for (int l = 1 + blockIdx.y; l < no; l += gridDim.y) {
+    for (int base = blockIdx.x * blockDim.x; base < per_l; base += gridDim.x * blockDim.x) {
+      const int r = base + threadIdx.x;
+      int j = 0, k = 0, b = 0, c = 0;
+      double gd = 0.0;
+      if (r < per_l) {
+        const int to = A.po1[r / d.npv1], tv = A.pv1[r % d.npv1];
+        const int jr = to >> 16, kr = to & 0xffff, br = tv >> 16, cr = tv & 0xffff;
+        j = jr + (jr >= l); k = kr + (kr >= l); b = br + (br >= l); c = cr + (cr >= l);
+        if (!((j < l && (j == b || j == c)) || (k < l && (k == b || k == c)))) {
+          int I[3] = {l, j, k}, P[3] = {l, b, c};
+          sort3_adj(I[0], I[1], I[2]);
+          sort3_adj(P[0], P[1], P[2]);
+          double bv = 0.0;
+          for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+              if (P[p] != I[q]) continue;
+              const int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
+              const int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
+              const double anti = A.V[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2] -
+                                  A.V[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2];
+              const double sg = ((p + q) & 1) ? -1.0 : 1.0;
+              bv += sg * A.lam[I[q]] * s2 * anti;
+            }
+          const double D = A.ev[P[0]] + A.ev[P[1]] + A.ev[P[2]] - A.eo[I[0]] - A.eo[I[1]] - A.eo[I[2]] - A.omega;
+          const double gb = -4.0 * bv / D;
+          gd = 2.0 * (bv / D) * (bv / D);
+          for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+              if (P[p] != I[q]) continue;
+              const int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
+              const int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
+              const double sg = ((p + q) & 1) ? -1.0 : 1.0;
+              const double v = gb * sg * A.lam[I[q]] * s2;
+              unsafeAtomicAdd(&A.GV[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2], v);
+              unsafeAtomicAdd(&A.GV[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2], -v);
+            }
+          atomicAdd(&sacc.ev[c], gd);
         }
-      const double D = A.ev[P[0]] + A.ev[P[1]] + A.ev[P[2]] - A.eo[I[0]] - A.eo[I[1]] - A.eo[I[2]] - A.omega;
-      const double gb = -4.0 * bv / D, gd = 2.0 * (bv / D) * (bv / D);
-      for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) {
-          if (P[p] != I[q]) continue;
-          const int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
-          const int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
-          const double sg = ((p + q) & 1) ? -1.0 : 1.0;
-          const double v = gb * sg * A.lam[I[q]] * s2;
-          unsafeAtomicAdd(&A.GV[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2], v);
-          unsafeAtomicAdd(&A.GV[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2], -v);
-        }
-      s_diag(sacc, P, I, gd);
+      }
+      // particles {l, b, c}, holes {l, j, k}, omega
+      rp += gd; rh -= gd; ro -= gd;
+      wave_keyed_add(sacc.ev, nullptr, b, gd, 0.0);
+      wave_keyed_add(sacc.eo, nullptr, j, -gd, 0.0);
+      wave_keyed_add(sacc.eo, nullptr, k, -gd, 0.0);
     }
+    s_row_flush(sacc, l, l, rp, rh, ro);
+  }
   s_flush(A, sacc);
 }
 
@@ -356,47 +409,78 @@ __device__ inline void scatter_mixed(const E2sAdjArgs& A, int i, int a, int j, i
   if (c == k) add(i, a, j, b, g * A.lam[k] * s2);
 }
 
+// mixed sector, case A (a = i >= 1 fixed per grid row)
 __global__ __launch_bounds__(256) void k_e2s_mixed_a_adj(E2sAdjArgs A) {
   ESMP2_SACC_DECL
   const Dims& d = A.d;
   const int no = d.no;
   const int per_i = d.npo * d.npv;
-  for (int i = 1 + blockIdx.y; i < no; i += gridDim.y)
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < per_i; r += gridDim.x * blockDim.x) {
-      const int to = A.po[r / d.npv], tv = A.pv[r % d.npv];
-      const int j = to >> 16, k = to & 0xffff, b = tv >> 16, c = tv & 0xffff;
-      if ((j == 0 || k == 0) && (b == 0 || c == 0)) continue;
-      const double bv = b_mixed_adj(A, i, i, j, k, b, c);
-      const double D = A.ev[i] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
-      scatter_mixed(A, i, i, j, k, b, c, -4.0 * bv / D);
-      const int P[3] = {i, b, c}, I[3] = {i, j, k};
-      s_diag(sacc, P, I, 2.0 * (bv / D) * (bv / D));
+  double rp = 0.0, rh = 0.0, ro = 0.0;
+  for (int i = 1 + blockIdx.y; i < no; i += gridDim.y) {
+    for (int base = blockIdx.x * blockDim.x; base < per_i; base += gridDim.x * blockDim.x) {
+      const int r = base + threadIdx.x;
+      int j = 0, k = 0, b = 0;
+      double gd = 0.0;
+      if (r < per_i) {
+        const int to = A.po[r / d.npv], tv = A.pv[r % d.npv];
+        j = to >> 16; k = to & 0xffff; b = tv >> 16;
+        const int c = tv & 0xffff;
+        if (!((j == 0 || k == 0) && (b == 0 || c == 0))) {
+          const double bv = b_mixed_adj(A, i, i, j, k, b, c);
+          const double D = A.ev[i] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+          scatter_mixed(A, i, i, j, k, b, c, -4.0 * bv / D);
+          gd = 2.0 * (bv / D) * (bv / D);
+          atomicAdd(&sacc.ev[c], gd);
+        }
+      }
+      // particles {i, b, c}, holes {i, j, k}, omega
+      rp += gd; rh -= gd; ro -= gd;
+      wave_keyed_add(sacc.ev, nullptr, b, gd, 0.0);
+      wave_keyed_add(sacc.eo, nullptr, j, -gd, 0.0);
+      wave_keyed_add(sacc.eo, nullptr, k, -gd, 0.0);
     }
+    s_row_flush(sacc, i, i, rp, rh, ro);
+  }
   s_flush(A, sacc);
 }
 
+// mixed sector, case B (up excitation i -> a, a != i, fixed per grid row; down pair
+// holes {l, m}, particles {l', e})
 __global__ __launch_bounds__(256) void k_e2s_mixed_b_adj(E2sAdjArgs A) {
   ESMP2_SACC_DECL
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv;
   const int inner = no * (no - 1) * (nv - 1);
+  double rp = 0.0, rh = 0.0, ro = 0.0;
   for (int ia = blockIdx.y; ia < no * nv; ia += gridDim.y) {
     const int i = ia / nv, a = ia - i * nv;
-    if (a == i) continue;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < inner; r += gridDim.x * blockDim.x) {
-      const int er = r % (nv - 1), q = r / (nv - 1);
-      const int mr = q % (no - 1), l = q / (no - 1);
-      const int m = mr + (mr >= l), e = er + (er >= l);
-      if (m < l && e == m) continue;
-      if ((i == 0 || l == 0 || m == 0) && (a == 0 || l == 0 || e == 0)) continue;
-      const int j = l < m ? l : m, k = l < m ? m : l;
-      const int b = l < e ? l : e, c = l < e ? e : l;
-      const double bv = b_mixed_adj(A, i, a, j, k, b, c);
-      const double D = A.ev[a] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
-      scatter_mixed(A, i, a, j, k, b, c, -4.0 * bv / D);
-      const int P[3] = {a, b, c}, I[3] = {i, j, k};
-      s_diag(sacc, P, I, 2.0 * (bv / D) * (bv / D));
+    if (a == i) continue;                                  // uniform over the workgroup
+    for (int base = blockIdx.x * blockDim.x; base < inner; base += gridDim.x * blockDim.x) {
+      const int r = base + threadIdx.x;
+      int l = 0, m = 0;
+      double gd = 0.0;
+      if (r < inner) {
+        const int er = r % (nv - 1), q = r / (nv - 1);
+        const int mr = q % (no - 1);
+        l = q / (no - 1);
+        m = mr + (mr >= l);
+        const int e = er + (er >= l);
+        if (!(m < l && e == m) && !((i == 0 || l == 0 || m == 0) && (a == 0 || l == 0 || e == 0))) {
+          const int j = l < m ? l : m, k = l < m ? m : l;
+          const int b = l < e ? l : e, c = l < e ? e : l;
+          const double bv = b_mixed_adj(A, i, a, j, k, b, c);
+          const double D = A.ev[a] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+          scatter_mixed(A, i, a, j, k, b, c, -4.0 * bv / D);
+          gd = 2.0 * (bv / D) * (bv / D);
+          atomicAdd(&sacc.ev[e], gd);
+        }
+      }
+      // particles {a, l, e}, holes {i, l, m}, omega
+      rp += gd; rh -= gd; ro -= gd;
+      wave_keyed_add(sacc.ev, sacc.eo, l, gd, -gd);
+      wave_keyed_add(sacc.eo, nullptr, m, -gd, 0.0);
     }
+    s_row_flush(sacc, a, i, rp, rh, ro);
   }
   s_flush(A, sacc);
 }

@@ -1292,7 +1292,7 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
   constexpr int NB_NORM = 256;
   int64_t need = nd;                                           // swap
   for (int k = 0; k < 7; ++k) need += dsz[k];
-  const int64_t ntmp = (int64_t)no * nv * nv + (int64_t)no * no * no;
+  const int64_t ntmp = nd + (int64_t)no * no * no * nv;      // per-batch Gram blocks (summed afterwards)
   const int64_t npart = (int64_t)64 * nov;
   need += ntmp + (int64_t)n * n + 2 * (int64_t)nov * nov + nov + nv + no + 8 + npart + 7 * NB_NORM + 8 +
           2 * (int64_t)na * nov + (int64_t)na * nv * no + (int64_t)na * no * no;
@@ -1337,26 +1337,28 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
     box_ranges(k, lo_o, lo_v);
     const int ro = no - lo_o, rv = nv - lo_v;
     const double sc = sb_h[k];
-    const int64_t pq = (int64_t)ro * rv * rv;
+    const int64_t v2 = (int64_t)rv * rv;
     double* Gv = G + (int64_t)(no + lo_v) * n + no + lo_v;
     double* Go = G + (int64_t)lo_o * n + lo_o;
-    // virtual slots: sum over (P, Q, c) of X[P][Q][c][a] X[P][Q][c][e] (left slot); the
-    // right slot equals it for virtual-antisymmetric boxes and S~, else from the transposed copy
+    // Gram blocks per batch (summed afterwards), batches small enough to fill the chip.
+    // Virtual slots: sum over (P, Q, c) of X[P][Q][c][a] X[P][Q][c][e] (left slot, one batch
+    // per (P, Q)); the right slot equals it for virtual-antisymmetric boxes and S~, else it
+    // comes from the transposed copy.
     const bool vir_dense = (k == B_H12 || k == B_H22);
-    ESMP2_TRY(gram(h, dn[k], ro, pq, rv, 1, ro * rv, rv, vir_dense ? sc : 2.0 * sc, Gv, n, tmp));
+    ESMP2_TRY(gram(h, dn[k], ro * ro, v2, rv, 1, rv, rv, vir_dense ? sc : 2.0 * sc, Gv, n, tmp));
     if (vir_dense) {
       hipLaunchKernelGGL(k_swap_mid, dim3(1024), dim3(256), 0, s, (const double*)dn[k], swp, (int64_t)ro * ro, rv,
                          rv, (int64_t)1);
-      ESMP2_TRY(gram(h, swp, ro, pq, rv, 1, ro * rv, rv, sc, Gv, n, tmp));
+      ESMP2_TRY(gram(h, swp, ro * ro, v2, rv, 1, rv, rv, sc, Gv, n, tmp));
     }
-    // occupied slots: -sum over (k, A, B) of X[i][k][AB] X[m][k][AB] (first slot); the second
-    // equals it for occupied-antisymmetric boxes and S~, else from the transposed copy
+    // Occupied slots: -sum over (k, A, B) of X[i][k][AB] X[m][k][AB] (first slot, one batch
+    // per (k, A)); the second equals it for occupied-antisymmetric boxes and S~, else it
+    // comes from the transposed copy.
     const bool occ_dense = (k == B_H21 || k == B_H22);
-    const int64_t v2 = (int64_t)rv * rv;
-    ESMP2_TRY(gram(h, dn[k], ro, v2, ro, ro * v2, (int)v2, 1, occ_dense ? -sc : -2.0 * sc, Go, n, tmp));
+    ESMP2_TRY(gram(h, dn[k], ro * rv, rv, ro, ro * v2, rv, 1, occ_dense ? -sc : -2.0 * sc, Go, n, tmp));
     if (occ_dense) {
       hipLaunchKernelGGL(k_swap_mid, dim3(1024), dim3(256), 0, s, (const double*)dn[k], swp, (int64_t)1, ro, ro, v2);
-      ESMP2_TRY(gram(h, swp, ro, v2, ro, ro * v2, (int)v2, 1, -sc, Go, n, tmp));
+      ESMP2_TRY(gram(h, swp, ro * rv, rv, ro, ro * v2, rv, 1, -sc, Go, n, tmp));
     }
     hipLaunchKernelGGL(k_sumsq, dim3(NB_NORM), dim3(256), 0, s, (const double*)dn[k], dsz[k], npt + k * NB_NORM);
   }
