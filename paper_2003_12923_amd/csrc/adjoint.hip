@@ -42,13 +42,15 @@ __global__ void k_swap_mid(const double* in, double* out, int64_t outer, int d0,
   }
 }
 
-// G[r * ld + c] += alpha * sum_b tmp[b][r][c]  (nb batches of m x n, fixed order)
+// G[r * ld + c] += alpha * sum_b tmp[b][r][c]  (nb batches of m x n); the batches are
+// split over gridDim.y workgroup rows, each adding its part atomically
 __global__ void k_batch_sum_acc(const double* tmp, int nb, int m, int n, double alpha, double* G, int ld) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * n) return;
+  const int b0 = (int)((int64_t)nb * blockIdx.y / gridDim.y), b1 = (int)((int64_t)nb * (blockIdx.y + 1) / gridDim.y);
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += tmp[(int64_t)b * m * n + e];
-  G[(int64_t)(e / n) * ld + e % n] += alpha * s;
+  for (int b = b0; b < b1; ++b) s += tmp[(int64_t)b * m * n + e];
+  unsafeAtomicAdd(&G[(int64_t)(e / n) * ld + e % n], alpha * s);
 }
 
 // Strided bilinear contraction:
@@ -104,16 +106,18 @@ __global__ __launch_bounds__(256) void k_sumsq(const double* v, int64_t n, doubl
 
 // scal[0] = coefficient of omega in <x, A x>_W (+ S-triples, scal[2]), scal[1] = coefficient of kappa
 //   from the squared norms nrm[box] = s_box * |X_box|^2 (partials, nb per box)
+// one wavefront
 __global__ void k_norm_scalars(const double* part, int nb, const double* sbox, double* scal) {
-  if (threadIdx.x != 0) return;
   double nrm[7];
   for (int k = 0; k < 7; ++k) {
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[k * nb + b];
-    nrm[k] = sbox[k] * s;
+    for (int b = threadIdx.x; b < nb; b += 64) s += part[k * nb + b];
+    nrm[k] = sbox[k] * wave_sum(s);
   }
-  scal[0] = -(nrm[B_T2] + nrm[B_S2]);
-  scal[1] = nrm[B_T3] + nrm[B_H11] + nrm[B_H12] + nrm[B_H21] + nrm[B_H22];
+  if (threadIdx.x == 0) {
+    scal[0] = -(nrm[B_T2] + nrm[B_S2]);
+    scal[1] = nrm[B_T3] + nrm[B_H11] + nrm[B_H12] + nrm[B_H21] + nrm[B_H22];
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -1235,10 +1235,12 @@ esmp2_status esmp2_solve_batch(esmp2_handle* hs, int n, const esmp2_solve_opts* 
 // ---------------------------------------------------------------------------
 // dE2/dF~ and dE2/dB~ (rotation held fixed)
 // ---------------------------------------------------------------------------
-// lenA, lenB, lenOut: element counts of the operands and the output; every index the
-// launch can form is checked against them on the host first.
-static esmp2_status contract(esmp2_handle h, double* part, const Contr& c, int64_t lenA, int64_t lenB,
-                             double alpha, double* out, int64_t lenOut, int64_t dst, int64_t so0, int64_t so1) {
+// npart_cap: size of the partials buffer; lenA, lenB, lenOut: element counts of the
+// operands and the output; every index the launch can form is checked against them
+// on the host first.
+static esmp2_status contract(esmp2_handle h, double* part, int64_t npart_cap, const Contr& c, int64_t lenA,
+                             int64_t lenB, double alpha, double* out, int64_t lenOut, int64_t dst, int64_t so0,
+                             int64_t so1) {
   const int64_t ncon = (int64_t)c.nC[0] * c.nC[1] * c.nC[2] * c.nC[3];
   const int nout = c.nE[0] * c.nE[1];
   if (nout <= 0 || ncon <= 0) return ESMP2_OK;
@@ -1247,7 +1249,8 @@ static esmp2_status contract(esmp2_handle h, double* part, const Contr& c, int64
   for (int k = 0; k < 4; ++k) { hiA += (c.nC[k] - 1) * c.aC[k]; hiB += (c.nC[k] - 1) * c.bC[k]; }
   if (c.oA < 0 || c.oB < 0 || dst < 0 || hiA >= lenA || hiB >= lenB || hiO >= lenOut)
     return fail(h, ESMP2_HIP_ERROR, "internal: gradient contraction out of range");
-  const int nsplit = (int)std::min<int64_t>(64, std::max<int64_t>(1, ncon / 4096));
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(1024, npart_cap / nout));
+  const int nsplit = (int)std::min<int64_t>(cap, std::max<int64_t>(1, ncon / 4096));
   hipLaunchKernelGGL(k_contract, dim3(nout, nsplit), dim3(256), 0, h->stream, c, part);
   hipLaunchKernelGGL(k_contract_fin, dim3(nblk(nout)), dim3(256), 0, h->stream, (const double*)part, c.nE[0],
                      c.nE[1], nsplit, alpha, out, dst, so0, so1);
@@ -1264,8 +1267,9 @@ static esmp2_status gram(esmp2_handle h, const double* X, int nb, int64_t sb, in
   g.sAb = sb; g.sAi = si; g.sAk = sk; g.sBb = sb; g.sBk = sk; g.sBj = si;
   g.sCb = (int64_t)m * m; g.sCi = m; g.sCj = 1; g.alpha = 1.0; g.beta = 0.0;
   ESMP2_HIP(gemm(h->stream, nb, g));
-  hipLaunchKernelGGL(k_batch_sum_acc, dim3(nblk((int64_t)m * m)), dim3(256), 0, h->stream, (const double*)tmp, nb, m,
-                     m, alpha, G, ld);
+  const int ny = std::max(1, std::min(nb / 8, 2048 / (int)nblk((int64_t)m * m)));   // batch split
+  hipLaunchKernelGGL(k_batch_sum_acc, dim3(nblk((int64_t)m * m), ny), dim3(256), 0, h->stream, (const double*)tmp,
+                     nb, m, m, alpha, G, ld);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
@@ -1392,73 +1396,73 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
     // transfers through the t' row of F_vv: G[t'][e], e >= 1
     c = C(H11, 1, H12, 0); E(c, 0, v1, 0, v1);
     K(c, 0, no, sT2[0], sH12[0]); K(c, 1, no, sT2[1], sH12[1]); K(c, 2, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 2.0, G, N * N, N * no + no + 1, 1, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 2.0, G, N * N, N * no + no + 1, 1, 0));
     c = C(H21, 1, H22, 0); E(c, 0, v1, 0, v1);
     K(c, 0, o1, sH21[0], sH22[0]); K(c, 1, o1, sH21[1], sH22[1]); K(c, 2, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N * no + no + 1, 1, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 4.0, G, N * N, N * no + no + 1, 1, 0));
     // transfers through the t column of F_oo: G[m][t], m >= 1
     c = C(H11, (int64_t)nv * nv, H21, 0); E(c, 0, o1, 0, sH21[0]);
     K(c, 0, o1, sT2[1], sH21[1]); K(c, 1, nv * nv, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -2.0, G, N * N, N, N, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), -2.0, G, N * N, N, N, 0));
     c = C(H12, (int64_t)v1 * v1, H22, 0); E(c, 0, o1, 0, sH22[0]);
     K(c, 0, o1, sH12[1], sH22[1]); K(c, 1, v1 * v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, N, N, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), -4.0, G, N * N, N, N, 0));
     // f_ov couplings (doubles -> L-triples; the de-excitation doubles them): G[i][n_occ + a]
     const int64_t ov = no;     // column offset of the virtual block
     // L-triples <- T2
     c = C(T3, 0, T2, sT2[0] + sT2[1] + sT2[2] + 1);
     K(c, 0, o1, sT3[0], sT2[0]); K(c, 1, o1, sT3[1], sT2[1]); K(c, 2, v1, sT3[2], sT2[2]); K(c, 3, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 1.0, G, N * N, ov, 0, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 1.0, G, N * N, ov, 0, 0));
     c = C(T3, 0, T2, sT2[1] + sT2[2] + 1); E(c, 0, o1, sT3[0], 0);
     K(c, 0, o1, sT3[1], sT2[1]); K(c, 1, v1, sT3[2], sT2[2]); K(c, 2, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -2.0, G, N * N, N + ov, N, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), -2.0, G, N * N, N + ov, N, 0));
     c = C(T3, 0, T2, sT2[0] + sT2[1] + 1); E(c, 0, v1, sT3[2], 0);
     K(c, 0, o1, sT3[0], sT2[0]); K(c, 1, o1, sT3[1], sT2[1]); K(c, 2, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -2.0, G, N * N, ov + 1, 1, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), -2.0, G, N * N, ov + 1, 1, 0));
     c = C(T3, 0, T2, sT2[1] + 1); E(c, 0, o1, sT3[0], 0); E(c, 1, v1, sT3[2], 0);
     K(c, 0, o1, sT3[1], sT2[1]); K(c, 1, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
     // S3 boxes <- T2 (through the flip partner of T2: sg)
     const double sg = (double)d.sg;
     c = C(H11, 0, T2, 0); K(c, 0, (int)nd, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), sg * 1.0, G, N * N, ov, 0, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), sg * 1.0, G, N * N, ov, 0, 0));
     c = C(H12, 0, T2, 1); E(c, 0, v1, v1, 0);
     K(c, 0, no, sH12[0], sT2[0]); K(c, 1, no, sH12[1], sT2[1]); K(c, 2, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), sg * 2.0, G, N * N, ov + 1, 1, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), sg * 2.0, G, N * N, ov + 1, 1, 0));
     c = C(H21, 0, T2, sT2[1]); E(c, 0, o1, sH21[0], 0);
     K(c, 0, o1, sH21[1], sT2[1]); K(c, 1, nv * nv, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), sg * 2.0, G, N * N, N + ov, N, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), sg * 2.0, G, N * N, N + ov, N, 0));
     c = C(H22, 0, T2, sT2[1] + 1); E(c, 0, o1, sH22[0], 0); E(c, 1, v1, v1, 0);
     K(c, 0, o1, sH22[1], sT2[1]); K(c, 1, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), sg * 4.0, G, N * N, N + ov + 1, N, 1));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), sg * 4.0, G, N * N, N + ov + 1, N, 1));
     // S3 boxes <- S~
     c = C(H11, 0, St, 0); E(c, 0, no, sT2[0], 0); E(c, 1, nv, nv, 0);
     K(c, 0, no, sT2[1], sT2[1]); K(c, 1, nv, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, ov, N, 1));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 4.0, G, N * N, ov, N, 1));
     c = C(H12, 0, St, nv + 1); E(c, 0, no, sH12[0], 0);
     K(c, 0, no, sH12[1], sT2[1]); K(c, 1, v1, v1, nv); K(c, 2, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, ov, N, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 4.0, G, N * N, ov, N, 0));
     c = C(H12, 0, St, nv); E(c, 0, no, sH12[0], 0); E(c, 1, v1, 1, 0);
     K(c, 0, no, sH12[1], sT2[1]); K(c, 1, v1, v1, nv);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, ov + 1, N, 1));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), -4.0, G, N * N, ov + 1, N, 1));
     c = C(H21, 0, St, sT2[0] + sT2[1]); E(c, 0, nv, nv, 0);
     K(c, 0, o1, sH21[0], sT2[0]); K(c, 1, o1, sH21[1], sT2[1]); K(c, 2, nv, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, ov, 1, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 4.0, G, N * N, ov, 1, 0));
     c = C(H21, 0, St, sT2[0]); E(c, 0, o1, sH21[1], 0); E(c, 1, nv, nv, 0);
     K(c, 0, o1, sH21[0], sT2[0]); K(c, 1, nv, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, N + ov, N, 1));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), -4.0, G, N * N, N + ov, N, 1));
     c = C(H22, 0, St, sT2[0] + sT2[1] + nv + 1);
     K(c, 0, o1, sH22[0], sT2[0]); K(c, 1, o1, sH22[1], sT2[1]); K(c, 2, v1, v1, nv); K(c, 3, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, ov, 0, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 4.0, G, N * N, ov, 0, 0));
     c = C(H22, 0, St, sT2[0] + nv + 1); E(c, 0, o1, sH22[1], 0);
     K(c, 0, o1, sH22[0], sT2[0]); K(c, 1, v1, v1, nv); K(c, 2, v1, 1, 1);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, N + ov, N, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), -4.0, G, N * N, N + ov, N, 0));
     c = C(H22, 0, St, sT2[0] + sT2[1] + nv); E(c, 0, v1, 1, 0);
     K(c, 0, o1, sH22[0], sT2[0]); K(c, 1, o1, sH22[1], sT2[1]); K(c, 2, v1, v1, nv);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), -4.0, G, N * N, ov + 1, 1, 0));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), -4.0, G, N * N, ov + 1, 1, 0));
     c = C(H22, 0, St, sT2[0] + nv); E(c, 0, o1, sH22[1], 0); E(c, 1, v1, 1, 0);
     K(c, 0, o1, sH22[0], sT2[0]); K(c, 1, v1, v1, nv);
-    ESMP2_TRY(contract(h, part, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
+    ESMP2_TRY(contract(h, part, npart, c, len(c.A), len(c.B), 4.0, G, N * N, N + ov + 1, N, 1));
   }
   // ---- 3. transposes of the right-hand side and of E2_S
   RhsAdjArgs ra{d, x, h->lam, GV, GM, Gf};
