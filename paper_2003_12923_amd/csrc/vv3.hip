@@ -30,29 +30,36 @@ struct V3Ctx {
   T sg;                  // S2: the flip partner of batch (i, j) is sg times the transpose of (j, i)
 };
 
-// element (r, c) of the embedded batch matrix; branch-free select, in-bounds address
+// Element (r, c) of the embedded batch matrix as an in-bounds offset into c.src
+// and a factor code f: 0 (outside the matrix or on the diagonal of a packed
+// antisymmetric one: the element is zero), 1 (as stored), 2 (negated).  The
+// load is issued at once and the factor applied only when the value is
+// stashed in LDS, so that the load stays in flight across the matrix-core work.
 template <int FMT, class T>
-__device__ inline T x3(const V3Ctx<T>& c, int r, int col) {
+__device__ inline int x3_off(const V3Ctx<T>& c, int r, int col, int& f) {
   if (FMT == K3_PACK || FMT == K3_PACKRED) {
     const int off = (FMT == K3_PACKRED) ? 1 : 0;
-    int rr = r - off, cc = col - off;
-    bool ok = rr >= 0 && cc >= 0 && rr < c.m && cc < c.m && rr != cc;
-    int lo = min(rr, cc), hi = max(rr, cc);
-    int idx = ok ? lo * c.m - lo * (lo + 1) / 2 + (hi - lo - 1) : 0;
-    T v = c.src[idx];
-    return ok ? (rr < cc ? v : -v) : T(0);
+    const int rr = r - off, cc = col - off;
+    const bool ok = rr >= 0 && cc >= 0 && rr < c.m && cc < c.m && rr != cc;
+    const int lo = min(rr, cc), hi = max(rr, cc);
+    f = ok ? (rr < cc ? 1 : 2) : 0;
+    return ok ? lo * c.m - lo * (lo + 1) / 2 + (hi - lo - 1) : 0;
   } else if (FMT == K3_DENSERED) {
-    int rr = r - 1, cc = col - 1;
-    bool ok = rr >= 0 && cc >= 0 && rr < c.m && cc < c.m;
-    T v = c.src[ok ? rr * c.m + cc : 0];
-    return ok ? v : T(0);
+    const int rr = r - 1, cc = col - 1;
+    const bool ok = rr >= 0 && cc >= 0 && rr < c.m && cc < c.m;
+    f = ok ? 1 : 0;
+    return ok ? rr * c.m + cc : 0;
   } else {
-    bool ok = r < c.m && col < c.m;
-    T v = c.src[ok ? r * c.m + col : 0];
-    return ok ? v : T(0);
+    const bool ok = r < c.m && col < c.m;
+    f = ok ? 1 : 0;
+    return ok ? r * c.m + col : 0;
   }
 }
 
+template <class T>
+__device__ inline T apply_code(T v, int f) {
+  return f == 1 ? v : (f == 2 ? -v : T(0));
+}
 
 template <int FMT, class T>
 __device__ inline void y3(const V3Ctx<T>& c, int r, int col, T val, bool diag_tile) {
@@ -138,22 +145,35 @@ __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx<T>& c
   // staging map (512 threads): A chunk (MV rows x 16 k): thread -> k = tid & 15,
   //   rows (tid >> 4) + 32 t;  B chunk (16 k x MV cols): thread -> k = tid >> 5,
   //   cols (tid & 31) + 32 t;  t < ceil(NT / 2), rows / cols < MV
+  // Raw values are loaded in fetch and their factor codes (2 bits per value in
+  // fa / fb) applied in stash.  Rows / columns beyond MV (odd NT) load element 0
+  // of F and are not stashed.
   constexpr int NS = (NT + 1) / 2;
   T pa[NS], pb[NS];
+  int fa = 0, fb = 0;
   const int ka = tid & 15, ra = tid >> 4, kb4 = tid >> 5, cb = tid & 31;
   auto fetch = [&](int k0) {
     const bool second = k0 >= MV;
     const int kb = second ? k0 - MV : k0;
+    fa = 0;
+    fb = 0;
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       const int r = ra + 32 * t, col = cb + 32 * t;
       const bool okr = (2 * NS == NT) || r < MV, okc = (2 * NS == NT) || col < MV;
+      int f;
       if (second) {
-        pa[t] = okr ? x3<FMT, T>(c, r, kb + ka) : T(0);
-        pb[t] = okc ? c.F[(kb + kb4) * MV + col] : T(0);
+        const int o = x3_off<FMT, T>(c, r, kb + ka, f);
+        pa[t] = c.src[o];
+        fa |= (okr ? f : 0) << (2 * t);
+        pb[t] = c.F[okc ? (kb + kb4) * MV + col : 0];
+        fb |= (okc ? 1 : 0) << (2 * t);
       } else {
-        pa[t] = okr ? c.F[r * MV + kb + ka] : T(0);
-        pb[t] = okc ? x3<FMT, T>(c, kb + kb4, col) : T(0);
+        pa[t] = c.F[okr ? r * MV + kb + ka : 0];
+        fa |= (okr ? 1 : 0) << (2 * t);
+        const int o = x3_off<FMT, T>(c, kb + kb4, col, f);
+        pb[t] = c.src[o];
+        fb |= (okc ? f : 0) << (2 * t);
       }
     }
   };
@@ -161,8 +181,8 @@ __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx<T>& c
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       const int r = ra + 32 * t, col = cb + 32 * t;
-      if ((2 * NS == NT) || r < MV) As[buf][ka][r] = pa[t];
-      if ((2 * NS == NT) || col < MV) Bs[buf][kb4][col] = pb[t];
+      if ((2 * NS == NT) || r < MV) As[buf][ka][r] = apply_code(pa[t], (fa >> (2 * t)) & 3);
+      if ((2 * NS == NT) || col < MV) Bs[buf][kb4][col] = apply_code(pb[t], (fb >> (2 * t)) & 3);
     }
   };
   constexpr int NCH = 2 * MV / 16;                 // even for every instantiated NT
