@@ -45,7 +45,8 @@ __global__ void k_topfock(const double* Ft, const double* lam, int no, int nv, i
   if (g == 0) { sc[0] = om; sc[1] = ka; sc[2] = 2.0 * tr + om; }
   if (g < (int64_t)mv * mv) {
     int a = g / mv, b = g % mv;
-    double v = (a < nv && b < nv) ? Ft[(no + a) * n + no + b] : 0.0;
+    // symmetric to the last bit (the Sylvester kernel reads F' by rows for both of its operands)
+    double v = (a < nv && b < nv) ? 0.5 * (Ft[(no + a) * n + no + b] + Ft[(no + b) * n + no + a]) : 0.0;
     Fd[g] = v + ((a == b && a < nv) ? -0.5 * om : 0.0);
     Fl[g] = v + ((a == b && a < nv) ? 0.5 * ka : 0.0);
     if (a < nv && b < nv) fv[a * nv + b] = v;

@@ -74,7 +74,7 @@ __global__ void k_fock_blocks(const double* Fh, int no, int nv, int mv, double o
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g < (int64_t)mv * mv) {
     const int a = g / mv, b = g % mv;
-    const double v = (a < nv && b < nv) ? Fh[(no + a) * n + no + b] : 0.0;
+    const double v = (a < nv && b < nv) ? 0.5 * (Fh[(no + a) * n + no + b] + Fh[(no + b) * n + no + a]) : 0.0;
     Fd[g] = v + ((a == b && a < nv) ? -0.5 * om : 0.0);
     Fl[g] = v + ((a == b && a < nv) ? 0.5 * ka : 0.0);
     if (a < nv && b < nv) fv[a * nv + b] = v;

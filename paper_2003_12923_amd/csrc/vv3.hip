@@ -1,15 +1,12 @@
-// Specialised Sylvester kernel Y = F' X + X F' on FP64 matrix cores for the
+// Specialised Sylvester kernel Y = F' X + X F' on the matrix cores for the
 // padded virtual dimension mv = 16 * NT (NT <= 10 tiles), one batch matrix per
-// workgroup of 8 wavefronts, two per SIMD: the output tiles are dealt to the
-// four SIMDs in blocks and each block is split between the SIMD's two
-// wavefronts, so that one wavefront's LDS waits and staging overlap the
-// other's matrix-core work (and each holds half the accumulators).
-// Everything that varies per job -- the storage format of X, the output
-// symmetry, and the block of 16x16 output tiles a wavefront owns -- is a
-// template parameter, so the matrix-core loop is straight-line code.  K runs
-// over 2*mv (k < mv: A = F', B = X; k >= mv: A = X, B = F') in 16-wide chunks
-// staged through double-buffered LDS; the next chunk is loaded into registers
-// while the current one is multiplied.
+// workgroup of 8 wavefronts, two per SIMD, each with its own list of 16x16
+// output tiles (balanced within every SIMD).  Everything that varies per job
+// -- the storage format of X, the output symmetry, the tiles a wavefront owns
+// -- is a template parameter, so the matrix-core loop is straight-line code.
+// K runs over 2*mv (k < mv: A = F', B = X; k >= mv: A = X, B = F') in 16-wide
+// chunks staged through double-buffered LDS, the loads of later chunks in
+// flight while the current one is multiplied.
 #include <type_traits>
 #include "common.h"
 #include "mfma.h"
@@ -95,156 +92,208 @@ __device__ inline void y3(const V3Ctx<T>& c, int r, int col, T val, bool diag_ti
 
 constexpr int V3_THREADS = 512;
 
-// rows of the first part when the upper triangle (diagonal included) of an
-// n x n tile block is split by rows into two parts of nearly equal tile counts
-constexpr int tri_split_rows(int n) {
-  int acc = 0, r = 0;
-  while (r < n && 2 * (acc + (n - r)) <= n * (n + 1) / 2 + (n - r)) { acc += n - r; ++r; }
-  return r;
-}
-
-// tile block owned by a wavefront.  SIMD s = WAVE % 4 owns a block (one of the
-// four quadrants of a dense output; for an upper-triangular output: the two
-// diagonal triangles and two rectangles above them); wavefront WAVE / 4 of
-// that SIMD takes the first or the second part of it (triangles split by rows,
-// rectangles by columns).
-template <int NT, bool TRIKIND, int WAVE>
-struct WRect {
-  static constexpr int S = WAVE & 3, PART = WAVE >> 2;
-  static constexpr int H = (NT + 1) / 2;
-  static constexpr int SPLIT = H + (NT - H) / 2;
-  static constexpr int BR0 = TRIKIND ? (S == 3 ? H : 0) : ((S >> 1) * H);
-  static constexpr int BR1 = TRIKIND ? (S == 3 ? NT : H) : ((S >> 1) ? NT : H);
-  static constexpr int BC0 = TRIKIND ? (S == 0 ? 0 : S == 1 ? SPLIT : H) : ((S & 1) * H);
-  static constexpr int BC1 = TRIKIND ? (S == 0 ? H : S == 1 ? NT : S == 2 ? SPLIT : NT) : ((S & 1) ? NT : H);
-  static constexpr bool TRI = TRIKIND && (S == 0 || S == 3);
-  static constexpr int RS = tri_split_rows(BR1 - BR0);        // triangle: rows of the first part
-  static constexpr int CS = (BC1 - BC0 + 1) / 2;              // rectangle: columns of the first part
-  static constexpr int R0 = TRI ? (PART ? BR0 + RS : BR0) : BR0;
-  static constexpr int R1 = TRI ? (PART ? BR1 : BR0 + RS) : BR1;
-  static constexpr int C0 = TRI ? (PART ? BC0 + RS : BC0) : (PART ? BC0 + CS : BC0);
-  static constexpr int C1 = TRI ? BC1 : (PART ? BC1 : BC0 + CS);
-  static constexpr int NR = R1 - R0 > 0 ? R1 - R0 : 1;
-  static constexpr int NC = C1 - C0 > 0 ? C1 - C0 : 1;
-  static constexpr bool EMPTY = (R1 <= R0) || (C1 <= C0);
+// Output tiles of one batch matrix dealt to the 8 wavefronts (wavefront w runs
+// on SIMD w % 4).  A single wavefront keeps the FP64 matrix core busy only
+// about 40 % of the time, two interleaved ones about 90 %, so both
+// wavefronts of a SIMD get the same number of tiles (within one) and keep the
+// core fed together to the end of every K step.  Dense output: SIMD s takes a
+// quadrant, its tiles in column-major order split in two halves.  Upper
+// triangle (diagonal tiles included): all its tiles in column-major order cut
+// into 8 consecutive runs, SIMD s taking runs 2s and 2s + 1.  A wavefront
+// reads the A operands of its distinct tile rows and the B operands of its
+// distinct tile columns.
+template <int NT, bool TRI, int WAVE>
+struct TileSet {
+  int n = 0, nr = 0, nc = 0;                        // tiles, distinct tile rows, distinct tile columns
+  int ti[32] = {}, tj[32] = {};                     // tile n = (ti[n], tj[n])
+  int ri[32] = {}, ci[32] = {};                     // its row / column among rows[] / cols[]
+  int rows[16] = {}, cols[16] = {};
+  constexpr void add(int i, int j) {
+    int a = -1, b = -1;
+    for (int k = 0; k < nr; ++k)
+      if (rows[k] == i) a = k;
+    if (a < 0) { rows[nr] = i; a = nr++; }
+    for (int k = 0; k < nc; ++k)
+      if (cols[k] == j) b = k;
+    if (b < 0) { cols[nc] = j; b = nc++; }
+    ti[n] = i; tj[n] = j; ri[n] = a; ci[n] = b; ++n;
+  }
+  constexpr TileSet() {
+    const int S = WAVE & 3, PART = WAVE >> 2;
+    if (!TRI) {
+      const int H = (NT + 1) / 2;
+      const int r0 = (S >> 1) * H, r1 = (S >> 1) ? NT : H, c0 = (S & 1) * H, c1 = (S & 1) ? NT : H;
+      const int half = ((r1 - r0) * (c1 - c0) + 1) / 2;
+      int k = 0;
+      for (int j = c0; j < c1; ++j)
+        for (int i = r0; i < r1; ++i) {
+          if ((k < half) == (PART == 0)) add(i, j);
+          ++k;
+        }
+    } else {
+      const int tot = NT * (NT + 1) / 2, g = 2 * S + PART;
+      const int b0 = g * tot / 8, b1 = (g + 1) * tot / 8;
+      int k = 0;
+      for (int j = 0; j < NT; ++j)
+        for (int i = 0; i <= j; ++i) {
+          if (k >= b0 && k < b1) add(i, j);
+          ++k;
+        }
+    }
+  }
 };
 
+// One batch matrix, one wavefront's tiles.  K runs over 2*mv in chunks of 16
+// (k < mv: A = F', B = X; k >= mv: A = X, B = F'), each chunk staged in one of
+// two LDS buffers while the other is multiplied.  The X operand (an HBM
+// stream, long load latency) is loaded three chunks ahead into two register
+// sets that alternate; the F' operand (the same for every job, so L2
+// resident) two chunks ahead.  F' is symmetric, so its A slab (first half)
+// and B slab (second half) are both read as rows of F'.
 template <class T, int FMT, int NT, int WAVE>
 __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx<T>& c, T (*As)[16][16 * NT + 1],
                                                                T (*Bs)[16][16 * NT + 1]) {
   constexpr int MV = 16 * NT;
   constexpr bool TRIKIND = (FMT == K3_PACK || FMT == K3_PACKRED || FMT == K3_S2DIAG);
-  using Rc = WRect<NT, TRIKIND, WAVE>;
+  constexpr TileSet<NT, TRIKIND, WAVE> TS{};
+  static_assert(TS.n > 0, "every wavefront owns at least one tile");
   const int tid = threadIdx.x, l = tid & 63;
   typedef typename MfmaAcc<T>::type AccT;
-  AccT acc[Rc::NR][Rc::NC];
+  AccT acc[TS.n];
 #pragma unroll
-  for (int i = 0; i < Rc::NR; ++i)
-#pragma unroll
-    for (int j = 0; j < Rc::NC; ++j) acc[i][j] = AccT{0, 0, 0, 0};
-  // staging map (512 threads): A chunk (MV rows x 16 k): thread -> k = tid & 15,
-  //   rows (tid >> 4) + 32 t;  B chunk (16 k x MV cols): thread -> k = tid >> 5,
-  //   cols (tid & 31) + 32 t;  t < ceil(NT / 2), rows / cols < MV
-  // Raw values are loaded in fetch and their factor codes (2 bits per value in
-  // fa / fb) applied in stash.  Rows / columns beyond MV (odd NT) load element 0
-  // of F and are not stashed.
+  for (int i = 0; i < TS.n; ++i) acc[i] = AccT{0, 0, 0, 0};
+  // staging map (512 threads), t < ceil(NT / 2):
+  //   F' slab and the X B slab (first half): k = tid >> 5, columns (tid & 31) + 32 t
+  //   X A slab (second half): k = tid & 15, rows (tid >> 4) + 32 t
+  // X values are loaded raw and their factor codes (2 bits per value) applied
+  // when stashed.  Rows / columns beyond MV (odd NT) load element 0 and are
+  // not stashed.
   constexpr int NS = (NT + 1) / 2;
-  T pa[NS], pb[NS];
-  int fa = 0, fb = 0;
+  T rf[NS], rx0[NS], rx1[NS];
+  int fx0 = 0, fx1 = 0;
   const int ka = tid & 15, ra = tid >> 4, kb4 = tid >> 5, cb = tid & 31;
-  auto fetch = [&](int k0) {
+  auto fetchF = [&](int k0) {
+    const int kb = k0 >= MV ? k0 - MV : k0;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int col = cb + 32 * t;
+      const bool okc = (2 * NS == NT) || col < MV;
+      rf[t] = c.F[okc ? (kb + kb4) * MV + col : 0];
+    }
+  };
+  auto stashF = [&](int k0, int buf) {
+    T (*D)[16 * NT + 1] = k0 >= MV ? Bs[buf] : As[buf];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const int col = cb + 32 * t;
+      if ((2 * NS == NT) || col < MV) D[kb4][col] = rf[t];
+    }
+  };
+  auto fetchX = [&](int k0, T* rx, int& fx) {
     const bool second = k0 >= MV;
     const int kb = second ? k0 - MV : k0;
-    fa = 0;
-    fb = 0;
+    fx = 0;
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      const int r = ra + 32 * t, col = cb + 32 * t;
-      const bool okr = (2 * NS == NT) || r < MV, okc = (2 * NS == NT) || col < MV;
       int f;
       if (second) {
+        const int r = ra + 32 * t;
+        const bool okr = (2 * NS == NT) || r < MV;
         const int o = x3_off<FMT, T>(c, r, kb + ka, f);
-        pa[t] = c.src[o];
-        fa |= (okr ? f : 0) << (2 * t);
-        pb[t] = c.F[okc ? (kb + kb4) * MV + col : 0];
-        fb |= (okc ? 1 : 0) << (2 * t);
+        rx[t] = c.src[o];
+        fx |= (okr ? f : 0) << (2 * t);
       } else {
-        pa[t] = c.F[okr ? r * MV + kb + ka : 0];
-        fa |= (okr ? 1 : 0) << (2 * t);
+        const int col = cb + 32 * t;
+        const bool okc = (2 * NS == NT) || col < MV;
         const int o = x3_off<FMT, T>(c, kb + kb4, col, f);
-        pb[t] = c.src[o];
-        fb |= (okc ? f : 0) << (2 * t);
+        rx[t] = c.src[o];
+        fx |= (okc ? f : 0) << (2 * t);
       }
     }
   };
-  auto stash = [&](int buf) {
+  auto stashX = [&](int k0, int buf, const T* rx, int fx) {
+    const bool second = k0 >= MV;
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      const int r = ra + 32 * t, col = cb + 32 * t;
-      if ((2 * NS == NT) || r < MV) As[buf][ka][r] = apply_code(pa[t], (fa >> (2 * t)) & 3);
-      if ((2 * NS == NT) || col < MV) Bs[buf][kb4][col] = apply_code(pb[t], (fb >> (2 * t)) & 3);
+      const T v = apply_code(rx[t], (fx >> (2 * t)) & 3);
+      if (second) {
+        const int r = ra + 32 * t;
+        if ((2 * NS == NT) || r < MV) As[buf][ka][r] = v;
+      } else {
+        const int col = cb + 32 * t;
+        if ((2 * NS == NT) || col < MV) Bs[buf][kb4][col] = v;
+      }
     }
   };
-  constexpr int NCH = 2 * MV / 16;                 // even for every instantiated NT
-  // One K chunk from LDS buffer BUF; with STASH / FETCH the staging of chunks
-  // q+1 and q+2 is placed between the matrix-core groups, so that its loads
-  // and LDS stores issue while the matrix cores are busy.  The buffer and the
-  // staging switches are compile-time, so the loop body has no branches and
-  // the accumulators stay in place across iterations.
-  auto chunk = [&](int q, auto buf_c, auto stash_c, auto fetch_c) {
-    constexpr int BUF = decltype(buf_c)::value;
-    constexpr bool STASH = decltype(stash_c)::value, FETCH = decltype(fetch_c)::value;
-    if constexpr (!Rc::EMPTY) {
+  constexpr int NCH = 2 * MV / 16;                 // even, >= 10 for every instantiated NT
+  // Chunk q from LDS buffer BUF = q % 2.  STAGE 3: stash chunk q+1 (F' and X,
+  // the X values in register set (q+1) % 2 = BUF ^ 1), then load F' of chunk
+  // q+2 and X of chunk q+3 into that register set; 2: no X load; 1: stash
+  // only; 0: nothing.  The staging sits between the matrix-core groups, at a
+  // K step that differs between the two wavefronts of a SIMD, so that one
+  // wavefront's staging overlaps the other's matrix-core work.  Buffer,
+  // register set and stage are compile-time, so the loop body has no
+  // branches and the accumulators stay in place.
+  auto chunk = [&](int q, auto buf_c, auto stage_c) {
+    constexpr int BUF = decltype(buf_c)::value, STAGE = decltype(stage_c)::value;
+    constexpr int KST = (WAVE >> 2) ? 2 : 0;
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        T a[Rc::NR], b[Rc::NC];
+    for (int ks = 0; ks < 4; ++ks) {
+      T a[TS.nr], b[TS.nc];
 #pragma unroll
-        for (int t = 0; t < Rc::NR; ++t) a[t] = As[BUF][ks * 4 + (l >> 4)][(Rc::R0 + t) * 16 + (l & 15)];
+      for (int t = 0; t < TS.nr; ++t) a[t] = As[BUF][ks * 4 + (l >> 4)][TS.rows[t] * 16 + (l & 15)];
 #pragma unroll
-        for (int t = 0; t < Rc::NC; ++t) b[t] = Bs[BUF][ks * 4 + (l >> 4)][(Rc::C0 + t) * 16 + (l & 15)];
+      for (int t = 0; t < TS.nc; ++t) b[t] = Bs[BUF][ks * 4 + (l >> 4)][TS.cols[t] * 16 + (l & 15)];
 #pragma unroll
-        for (int i = 0; i < Rc::NR; ++i)
-#pragma unroll
-          for (int j = 0; j < Rc::NC; ++j)
-            if (!Rc::TRI || Rc::C0 + j >= Rc::R0 + i) acc[i][j] = mfma16x16x4(a[i], b[j], acc[i][j]);
-        if constexpr (STASH) { if (ks == 0) stash(BUF ^ 1); }     // chunk q+1 (loaded one chunk ago)
-        if constexpr (FETCH) { if (ks == 1) fetch((q + 2) * 16); }
+      for (int n = 0; n < TS.n; ++n) acc[n] = mfma16x16x4(a[TS.ri[n]], b[TS.ci[n]], acc[n]);
+      if constexpr (STAGE >= 1) {
+        if (ks == KST) {
+          stashF((q + 1) * 16, BUF ^ 1);
+          if constexpr (BUF == 0) stashX((q + 1) * 16, BUF ^ 1, rx1, fx1);
+          else stashX((q + 1) * 16, BUF ^ 1, rx0, fx0);
+        }
       }
-    } else {
-      if constexpr (STASH) stash(BUF ^ 1);
-      if constexpr (FETCH) fetch((q + 2) * 16);
+      if constexpr (STAGE >= 2) {
+        if (ks == KST + 1) {
+          fetchF((q + 2) * 16);                    // before the X loads: the next stash waits on it alone
+          if constexpr (STAGE >= 3) {
+            if constexpr (BUF == 0) fetchX((q + 3) * 16, rx1, fx1);
+            else fetchX((q + 3) * 16, rx0, fx0);
+          }
+        }
+      }
     }
     __syncthreads();
   };
   using B0 = std::integral_constant<int, 0>;
   using B1 = std::integral_constant<int, 1>;
-  using Yes = std::true_type;
-  using No = std::false_type;
-  fetch(0);
-  stash(0);
-  fetch(16);
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  using S3 = std::integral_constant<int, 3>;
+  // prologue: chunk 0 in LDS buffer 0, F' and X of chunk 1 and X of chunk 2 in flight
+  fetchF(0);
+  fetchX(0, rx0, fx0);
+  stashF(0, 0);
+  stashX(0, 0, rx0, fx0);
+  fetchF(16);
+  fetchX(16, rx1, fx1);
+  fetchX(32, rx0, fx0);
   __syncthreads();
-  // the first pair of chunks outside the loop: the accumulators enter the loop
-  // as matrix-core results rather than as the zero initialisation
-  chunk(0, B0{}, Yes{}, Yes{});
-  chunk(1, B1{}, Yes{}, Yes{});
-  for (int q = 2; q < NCH - 2; q += 2) {
-    chunk(q, B0{}, Yes{}, Yes{});
-    chunk(q + 1, B1{}, Yes{}, Yes{});
+  for (int q = 0; q < NCH - 4; q += 2) {
+    chunk(q, B0{}, S3{});
+    chunk(q + 1, B1{}, S3{});
   }
-  chunk(NCH - 2, B0{}, Yes{}, No{});
-  chunk(NCH - 1, B1{}, No{}, No{});
-  if (Rc::EMPTY) return;
+  chunk(NCH - 4, B0{}, S3{});
+  chunk(NCH - 3, B1{}, S2{});
+  chunk(NCH - 2, B0{}, S1{});
+  chunk(NCH - 1, B1{}, S0{});
 #pragma unroll
-  for (int i = 0; i < Rc::NR; ++i)
+  for (int n = 0; n < TS.n; ++n)
 #pragma unroll
-    for (int j = 0; j < Rc::NC; ++j) {
-      if (Rc::TRI && Rc::C0 + j < Rc::R0 + i) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = (Rc::R0 + i) * 16 + mfma_row_t<T>(l, q), col = (Rc::C0 + j) * 16 + (l & 15);
-        y3<FMT, T>(c, r, col, acc[i][j][q], Rc::R0 + i == Rc::C0 + j);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int r = TS.ti[n] * 16 + mfma_row_t<T>(l, q), col = TS.tj[n] * 16 + (l & 15);
+      y3<FMT, T>(c, r, col, acc[n][q], TS.ti[n] == TS.tj[n]);
     }
 }
 
