@@ -699,7 +699,7 @@ static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv;
   hipStream_t s = h->stream;
-  hipLaunchKernelGGL(k_sym_s2<T>, dim3(nblk((int64_t)no * no * nv * nv)), dim3(256), 0, s, d, x, w.S);
+  hipLaunchKernelGGL(k_sym_s2<T>, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, x, w.S);
   SideArgs<T> sa{};
   sa.d = d; sa.x = x; sa.fov = w.fov;
   T* p = w.side;
@@ -1332,7 +1332,7 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
   ESMP2_HIP(hipMemcpyAsync(sbox, sb_h, sizeof(sb_h), hipMemcpyHostToDevice, s));
   // ---- 1. dense boxes (S2 flip-symmetrised)
   for (int k = 0; k < 7; ++k) {
-    if (k == B_S2) hipLaunchKernelGGL(k_sym_s2<double>, dim3(nblk(nd)), dim3(256), 0, s, d, x, dn[k]);
+    if (k == B_S2) hipLaunchKernelGGL(k_sym_s2<double>, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, x, dn[k]);
     else hipLaunchKernelGGL(k_unpack_box, dim3(1024), dim3(256), 0, s, d, k, x, dn[k]);
   }
   ESMP2_HIP(hipGetLastError());

@@ -127,21 +127,23 @@ __global__ __launch_bounds__(256) void k_gemv(GemvArgs<T> A) {
                               anti ? hasc[2] : wr[2] != nullptr};
   const int c = tid;                   // column owned (storage index)
   T cacc[GV_MAXW] = {0, 0, 0};
+  // rows r0..r0+15 of this thread's column (zeros below the diagonal of a packed batch)
+  auto load_slab = [&](int r0, T* v) {
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      const int r = r0 + rr;
+      const bool ok = c < m && r < m && (!anti || c > r);
+      const int64_t idx = !ok ? 0 : (anti ? (int64_t)(r * m - r * (r + 1) / 2 + (c - r - 1)) : (int64_t)r * m + c);
+      const T x = X[idx];
+      v[rr] = ok ? x : T(0);
+    }
+  };
+  T v[16], vn[16];
+  load_slab(0, v);
   for (int r0 = 0; r0 < m; r0 += 16) {
     __syncthreads();
-    // stage rows r0..r0+15 (zeros below the diagonal of a packed batch); the
-    // thread of each column accumulates the column sums on the way
+    // stage the slab; the thread of each column accumulates the column sums on the way
     if (c < m) {
-      T v[16];
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {           // all loads of the slab first (in flight together)
-        const int r = r0 + rr;
-        v[rr] = 0;
-        if (r < m) {
-          if (anti) { if (c > r) v[rr] = X[r * m - r * (r + 1) / 2 + (c - r - 1)]; }
-          else v[rr] = X[(int64_t)r * m + c];
-        }
-      }
 #pragma unroll
       for (int rr = 0; rr < 16; ++rr) {
         const int r = r0 + rr;
@@ -153,6 +155,8 @@ __global__ __launch_bounds__(256) void k_gemv(GemvArgs<T> A) {
         }
       }
     }
+    // the next slab's loads are in flight during the row sums of this one
+    if (r0 + 16 < m) load_slab(r0 + 16, vn);
     __syncthreads();
     // row sums: 16 lanes per staged row, each over every 16th column, then a
     // 4-step reduction inside the 16-lane group
@@ -163,12 +167,18 @@ __global__ __launch_bounds__(256) void k_gemv(GemvArgs<T> A) {
         if (!hasr[k]) continue;
         const T* w = anti ? swc[k] : swr[k];
         T sacc = 0;
-        for (int cc = seg; cc < m; cc += 16) sacc += tile[rr][cc] * w[cc + lo];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {            // m <= 192
+          const int cc = seg + 16 * i;
+          if (cc < m) sacc += tile[rr][cc] * w[cc + lo];
+        }
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o);
         if (seg == 0 && r0 + rr < m) rowres[k][r0 + rr] = sacc;
       }
     }
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) v[rr] = vn[rr];
   }
   // column sums move from the thread of each storage column to the output threads through LDS
   __syncthreads();

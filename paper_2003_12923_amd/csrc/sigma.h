@@ -56,6 +56,11 @@ struct PairTables {
 constexpr int GO = 8;   // inner (virtual-pair) indices per workgroup of the occupied-index kernel
 
 template <class T> __global__ void k_sym_s2(Dims d, const T* x, T* S);
+// workgroups of k_sym_s2: one per 32 x 32 block of (a, b) of each batch (i, j)
+inline int64_t sym_s2_blocks(const Dims& d) {
+  const int nt = (d.nv + 31) / 32;
+  return (int64_t)d.no * d.no * nt * nt;
+}
 template <class T, int TW> __global__ void k_vv(VVArgs<T> A);
 template <class T, int NT> __global__ void k_vv3(VVArgs<T> A);
 template <class T> __global__ void k_side(SideArgs<T> A);

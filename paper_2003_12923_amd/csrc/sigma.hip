@@ -21,42 +21,50 @@ namespace esmp2 {
 // ---------------------------------------------------------------------------
 template <class T>
 struct Look {
+  // Branch-free: the load is always issued (at the box's first element when
+  // the Pauli principle forbids the amplitude) and the exact zero or the sign
+  // of the reordering applied by a select, so that a caller's lookups issue
+  // back to back and their latencies overlap.
   Dims d;
   const T* x;
   const T* S;      // flip-symmetrised S2, dense [i][j][a][b]
   __device__ T T2(int i, int j, int a, int b) const {
-    if (i == j || a == b) return 0;
-    T s = 1;
-    if (i > j) { int t = i; i = j; j = t; s = -s; }
-    if (a > b) { int t = a; a = b; b = t; s = -s; }
-    return s * x[d.off[B_T2] + (int64_t)tri_idx(i, j, d.no) * d.npv + tri_idx(a, b, d.nv)];
+    const bool z = (i == j) | (a == b);
+    const T s = ((i > j) != (a > b)) ? T(-1) : T(1);
+    const int64_t k = z ? 0 : (int64_t)tri_idx(min(i, j), max(i, j), d.no) * d.npv + tri_idx(min(a, b), max(a, b), d.nv);
+    const T v = x[d.off[B_T2] + k];
+    return z ? T(0) : s * v;
   }
   __device__ T T3(int j, int k, int b, int c) const {      // all indices >= 1
-    if (j == k || b == c) return 0;
-    T s = 1;
-    if (j > k) { int t = j; j = k; k = t; s = -s; }
-    if (b > c) { int t = b; b = c; c = t; s = -s; }
-    return s * x[d.off[B_T3] + (int64_t)tri_idx(j - 1, k - 1, d.no - 1) * d.npv1 + tri_idx(b - 1, c - 1, d.nv - 1)];
+    const bool z = (j == k) | (b == c);
+    const T s = ((j > k) != (b > c)) ? T(-1) : T(1);
+    const int64_t o = z ? 0
+                        : (int64_t)tri_idx(min(j, k) - 1, max(j, k) - 1, d.no - 1) * d.npv1 +
+                              tri_idx(min(b, c) - 1, max(b, c) - 1, d.nv - 1);
+    const T v = x[d.off[B_T3] + o];
+    return z ? T(0) : s * v;
   }
   __device__ T H11(int j, int k, int b, int c) const {
-    if (j == k || b == c) return 0;
-    T s = 1;
-    if (j > k) { int t = j; j = k; k = t; s = -s; }
-    if (b > c) { int t = b; b = c; c = t; s = -s; }
-    return s * x[d.off[B_H11] + (int64_t)tri_idx(j, k, d.no) * d.npv + tri_idx(b, c, d.nv)];
+    const bool z = (j == k) | (b == c);
+    const T s = ((j > k) != (b > c)) ? T(-1) : T(1);
+    const int64_t o = z ? 0 : (int64_t)tri_idx(min(j, k), max(j, k), d.no) * d.npv + tri_idx(min(b, c), max(b, c), d.nv);
+    const T v = x[d.off[B_H11] + o];
+    return z ? T(0) : s * v;
   }
   __device__ T H12(int j, int k, int a, int c) const {     // a, c >= 1
-    if (j == k) return 0;
-    T s = 1;
-    if (j > k) { int t = j; j = k; k = t; s = -s; }
-    int m1 = d.nv - 1;
-    return s * x[d.off[B_H12] + ((int64_t)tri_idx(j, k, d.no) * m1 + (a - 1)) * m1 + (c - 1)];
+    const bool z = j == k;
+    const T s = j > k ? T(-1) : T(1);
+    const int m1 = d.nv - 1;
+    const int64_t o = z ? 0 : ((int64_t)tri_idx(min(j, k), max(j, k), d.no) * m1 + (a - 1)) * m1 + (c - 1);
+    const T v = x[d.off[B_H12] + o];
+    return z ? T(0) : s * v;
   }
   __device__ T H21(int i, int k, int b, int c) const {     // i, k >= 1
-    if (b == c) return 0;
-    T s = 1;
-    if (b > c) { int t = b; b = c; c = t; s = -s; }
-    return s * x[d.off[B_H21] + ((int64_t)(i - 1) * (d.no - 1) + (k - 1)) * d.npv + tri_idx(b, c, d.nv)];
+    const bool z = b == c;
+    const T s = b > c ? T(-1) : T(1);
+    const int64_t o = z ? 0 : ((int64_t)(i - 1) * (d.no - 1) + (k - 1)) * d.npv + tri_idx(min(b, c), max(b, c), d.nv);
+    const T v = x[d.off[B_H21] + o];
+    return z ? T(0) : s * v;
   }
   __device__ T H22(int i, int k, int a, int c) const {     // all >= 1
     int m1 = d.nv - 1;
@@ -71,15 +79,33 @@ struct Look {
 // S~ = (x_S2 + sg flip x_S2)/2, flip: (i,j,a,b) -> (j,i,b,a); sg = +1 singlet, -1 triplet
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void k_sym_s2(Dims d, const T* x, T* S) {
-  const int g = (int)xcd_remap<16>(blockIdx.x, gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
-  const int nv2 = d.nv * d.nv;
-  if (g >= d.no * d.no * nv2) return;     // the S2 box holds < 2^31 amplitudes
-  const int o = g / nv2, v = g - o * nv2;
+__global__ __launch_bounds__(256) void k_sym_s2(Dims d, const T* x, T* S) {
+  // one 32 x 32 block of (a, b) of one batch (i, j); the partner block (j, i)
+  // is read in its own (row-major) order and transposed through LDS
+  __shared__ T tl[32][33];
+  const int nv = d.nv, nt = (nv + 31) / 32;
+  const int blk = (int)xcd_remap<16>(blockIdx.x, gridDim.x);
+  const int o = blk / (nt * nt), t = blk - o * (nt * nt);
   const int i = o / d.no, j = o - i * d.no;
-  const int a = v / d.nv, b = v - a * d.nv;
+  const int a0 = (t / nt) * 32, b0 = (t % nt) * 32;
+  const int64_t nv2 = (int64_t)nv * nv;
   const T* s2 = x + d.off[B_S2];
-  S[g] = T(0.5) * (s2[g] + T(d.sg) * s2[(j * d.no + i) * nv2 + b * d.nv + a]);
+  const T* P = s2 + ((int64_t)j * d.no + i) * nv2;
+  const T* X = s2 + ((int64_t)i * d.no + j) * nv2;
+  T* Sd = S + ((int64_t)i * d.no + j) * nv2;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int b = b0 + r, a = a0 + tx;
+    tl[r][tx] = (b < nv && a < nv) ? P[b * nv + a] : T(0);
+  }
+  __syncthreads();
+  const T sg = T(d.sg);
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int a = a0 + r, b = b0 + tx;
+    if (a < nv && b < nv) Sd[a * nv + b] = T(0.5) * (X[a * nv + b] + sg * tl[tx][r]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -356,17 +382,23 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
       if (i >= 1 && a >= 1) y += ftt * L.T3(i, j, a, b);
       ys += ftt * L.H11(i, j, a, b);
       if (i == 0) {
-        if (a >= 1)
+        if (a >= 1) {
+#pragma unroll 4
           for (int m = 1; m < no; ++m) y -= FOV(m, 0) * L.T3(m, j, a, b);
+        }
+#pragma unroll 4
         for (int m = 1; m < no; ++m) ys += FOV(m, 0) * L.H21(m, j, a, b);
       }
       if (a == 0) {
         if (i >= 1) y -= A.t3_t[tri_idx(i - 1, j - 1, no - 1) * nv + b];
         ys += A.h12_t[batch * nv + b];
         if (i == 0) {
+#pragma unroll 4
           for (int m = 1; m < no; ++m) {
-            if (m < j) y += A.t3_p1[tri_idx(m - 1, j - 1, no - 1) * nv + b];
-            else if (m > j) y -= A.t3_p2[tri_idx(j - 1, m - 1, no - 1) * nv + b];
+            const bool lt = m < j;
+            const int pi = (m == j) ? 0 : tri_idx(min(m, j) - 1, max(m, j) - 1, no - 1);
+            const T tv = (lt ? A.t3_p1 : A.t3_p2)[pi * nv + b];
+            y += lt ? tv : (m > j ? -tv : T(0));
             ys += A.h22_i[((m - 1) * (no - 1) + (j - 1)) * nv + b];
           }
         }
@@ -382,16 +414,23 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
         T dd = 0;
         if (p == 0) {
           if (xx == 0) {
+#pragma unroll 4
             for (int m = 0; m < no; ++m) {
-              if (m < q) dd += A.h11_p1[tri_idx(m, q, no) * nv + z];
-              else if (m > q) dd -= A.h11_p2[tri_idx(q, m, no) * nv + z];
+              const bool lt = m < q;
+              const int pi = (m == q) ? 0 : tri_idx(min(m, q), max(m, q), no);
+              const T tv = (lt ? A.h11_p1 : A.h11_p2)[pi * nv + z];
+              dd += lt ? tv : (m > q ? -tv : T(0));
             }
           } else if (z >= 1) {
+#pragma unroll 4
             for (int m = 0; m < no; ++m) dd += FOV(m, 0) * L.H12(m, q, xx, z);
           } else {
+#pragma unroll 4
             for (int m = 0; m < no; ++m) {
-              if (m < q) dd -= A.h12_u1[tri_idx(m, q, no) * nv + xx];
-              else if (m > q) dd += A.h12_u2[tri_idx(q, m, no) * nv + xx];
+              const bool lt = m < q;
+              const int pi = (m == q) ? 0 : tri_idx(min(m, q), max(m, q), no);
+              const T tv = (lt ? A.h12_u1 : A.h12_u2)[pi * nv + xx];
+              dd += lt ? -tv : (m > q ? tv : T(0));
             }
           }
         } else if (q >= 1) {
@@ -400,10 +439,13 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
           else dd -= A.h22_ut[((p - 1) * (no - 1) + (q - 1)) * nv + xx];
         } else {
           if (xx == 0) {
+#pragma unroll 4
             for (int m = 1; m < no; ++m) dd -= A.h21_k[((p - 1) * (no - 1) + (m - 1)) * nv + z];
           } else if (z >= 1) {
+#pragma unroll 4
             for (int m = 1; m < no; ++m) dd -= FOV(m, 0) * L.H22(p, m, xx, z);
           } else {
+#pragma unroll 4
             for (int m = 1; m < no; ++m) dd += A.h22_uk[((p - 1) * (no - 1) + (m - 1)) * nv + xx];
           }
         }
@@ -420,8 +462,10 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
     }
     case B_H11: {
       const int j = p0, k = q0, t = P.pv[v], b = t >> 16, c = t & 0xffff;
-      if (j == 0)
+      if (j == 0) {
+#pragma unroll 4
         for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H21(m, k, b, c);
+      }
       y += T(d.sg) * ftt * L.T2(j, k, b, c);                 // flip partner of T2 (down-down)
       y += FOV(j, b) * L.St(0, k, 0, c) - FOV(k, b) * L.St(0, j, 0, c)
          - FOV(j, c) * L.St(0, k, 0, b) + FOV(k, c) * L.St(0, j, 0, b);
@@ -430,8 +474,10 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
     case B_H12: {
       const int j = p0, k = q0, a = v / m1 + 1, c = v - (a - 1) * m1 + 1;
       y += fv[a * nv + 0] * L.H11(j, k, 0, c);
-      if (j == 0)
+      if (j == 0) {
+#pragma unroll 4
         for (int m = 1; m < no; ++m) y -= fo[m * no + 0] * L.H22(m, k, a, c);
+      }
       y += T(d.sg) * FOV(0, a) * L.T2(j, k, 0, c);
       y += FOV(j, 0) * L.St(0, k, a, c) - FOV(k, 0) * L.St(0, j, a, c)
          - FOV(j, c) * L.St(0, k, a, 0) + FOV(k, c) * L.St(0, j, a, 0);
@@ -490,8 +536,10 @@ namespace esmp2 {
 // GO consecutive inner indices, all occupied batches staged in LDS.
 // ---------------------------------------------------------------------------
 
+constexpr int OO_THREADS = 256, OO_R = 8;
+
 template <class T>
-__global__ __launch_bounds__(256) void k_oo(GatherArgs<T> A, int4 tiles0, int4 tiles1) {
+__global__ __launch_bounds__(OO_THREADS) void k_oo(GatherArgs<T> A, int4 tiles0, int4 tiles1) {
   extern __shared__ __align__(16) unsigned char sm_raw[];
   T* sm = reinterpret_cast<T*>(sm_raw);
   const Dims& d = A.d;
@@ -517,17 +565,30 @@ __global__ __launch_bounds__(256) void k_oo(GatherArgs<T> A, int4 tiles0, int4 t
   const T* src = (box == B_S2) ? A.S : A.x + d.off[box];
   const int tw = min(GO, inner - t0);
   const int tid = threadIdx.x;
-  for (int e = tid; e < nbat * GO; e += blockDim.x) {
-    const int o = e / GO, vl = e % GO;
-    const bool ok = vl < tw;
-    tin[o * (GO + 1) + vl] = ok ? src[(int64_t)o * inner + t0 + vl] : T(0);
-    T t = 0;
-    // box-transfer rows (inner pairs (t', c) are the first nv-1 packed pairs)
-    if (ok && (box == B_H11 || box == B_H21) && t0 + vl < nv - 1) {
-      const int c = t0 + vl + 1;
-      t = A.side_tr[((box == B_H11 ? 0 : (int64_t)d.npo) + o) * nv + c];
+  const int ne = nbat * GO;
+  // staging: OO_R elements per thread per round, all loads of a round issued
+  // before the first LDS store, so their latencies overlap
+  for (int e0 = 0; e0 < ne; e0 += OO_R * OO_THREADS) {
+    T vin[OO_R], vtr[OO_R];
+#pragma unroll
+    for (int u = 0; u < OO_R; ++u) {
+      const int e = e0 + u * OO_THREADS + tid;
+      const int o = e / GO, vl = e % GO;
+      const bool ok = e < ne && vl < tw;
+      vin[u] = ok ? src[(int64_t)o * inner + t0 + vl] : T(0);
+      // box-transfer rows (inner pairs (t', c) are the first nv-1 packed pairs)
+      const bool trow = ok && (box == B_H11 || box == B_H21) && t0 + vl < nv - 1;
+      vtr[u] = trow ? A.side_tr[((box == B_H11 ? 0 : (int64_t)d.npo) + o) * nv + (t0 + vl + 1)] : T(0);
     }
-    tout[o * (GO + 1) + vl] = t;
+#pragma unroll
+    for (int u = 0; u < OO_R; ++u) {
+      const int e = e0 + u * OO_THREADS + tid;
+      if (e < ne) {
+        const int o = e / GO, vl = e % GO;
+        tin[o * (GO + 1) + vl] = vin[u];
+        tout[o * (GO + 1) + vl] = vtr[u];
+      }
+    }
   }
   {
     int p = tid >> 4, q = tid & 15, code = 0;
@@ -573,9 +634,20 @@ __global__ __launch_bounds__(256) void k_oo(GatherArgs<T> A, int4 tiles0, int4 t
   }
   __syncthreads();
   T* y = A.y + d.off[box];
-  for (int e = tid; e < nbat * GO; e += blockDim.x) {
-    const int o = e / GO, vl = e % GO;
-    if (vl < tw) y[(int64_t)o * inner + t0 + vl] += tout[o * (GO + 1) + vl];
+  for (int e0 = 0; e0 < ne; e0 += OO_R * OO_THREADS) {
+    T vy[OO_R];
+#pragma unroll
+    for (int u = 0; u < OO_R; ++u) {
+      const int e = e0 + u * OO_THREADS + tid;
+      const int o = e / GO, vl = e % GO;
+      vy[u] = (e < ne && vl < tw) ? y[(int64_t)o * inner + t0 + vl] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < OO_R; ++u) {
+      const int e = e0 + u * OO_THREADS + tid;
+      const int o = e / GO, vl = e % GO;
+      if (e < ne && vl < tw) y[(int64_t)o * inner + t0 + vl] = vy[u] + tout[o * (GO + 1) + vl];
+    }
   }
 }
 
