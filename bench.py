@@ -9,9 +9,9 @@ right-hand side + S-triple energy, FP64 Jacobi-preconditioned CG to
 ||b+Ax||_W/||b||_W <= 1e-8 and E2, with the Krylov solve in the
 pinned-semicanonical basis (the library's fastest FP64 solve; E2 is the same
 in every basis).  ms_per_step is that step's time-to-E2.  The same steps are
-also timed with the solve in the TOP basis and with the mixed-precision solve
-(FP32 inner CG inside FP64 refinement, same FP64 stopping test), each with its
-E2 difference.
+also timed with the solve in the TOP basis and with the mixed-precision solves
+(FP32 inner CG inside FP64 refinement, and the same around the operator with
+BF16 Sylvester operands; same FP64 stopping test), each with its E2 difference.
 
 value = H0-sigma GFLOP/s of the paper's operator (the TOP-basis sigma, all
 its kernels, FP64): algorithmic sigma flops / sigma time, timed with HIP events
@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -115,6 +116,20 @@ def main():
     vv32_ms, vv32_n = h.profile(False)[P.ESMP2_FP32]
     mixed_ms = 1e3 * (t1 - t0) / args.steps
 
+    # the same steps refined around the BF16 operator (TOP basis: BF16 operands
+    # in the Sylvester products, FP32 elsewhere, FP64 refinement)
+    for _ in range(args.warmup):
+        step(P.ESMP2_BF16)
+    torch.cuda.synchronize()
+    h.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res_b = step(P.ESMP2_BF16)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vvb_ms, vvb_n = h.profile(False)[P.ESMP2_BF16]
+    bf16_ms = 1e3 * (t1 - t0) / args.steps
+
     # the same solves in the pinned-semicanonical basis
     sc_ms, res_sc = timed(P.ESMP2_FP64, P.ESMP2_BASIS_SEMICANONICAL)
     scm_ms, res_scm = timed(P.ESMP2_FP32, P.ESMP2_BASIS_SEMICANONICAL)
@@ -137,6 +152,7 @@ def main():
 
     sigma_ms = time_sigma(x, P.ESMP2_FP64)
     sigma32_ms = time_sigma(x.float(), P.ESMP2_FP32)
+    sigmab_ms = time_sigma(x.float(), P.ESMP2_BF16)
 
     # the batched workload: 32 independent states of uneven size, one handle and one
     # stream each, solved together (pinned-semicanonical basis, FP64)
@@ -261,6 +277,15 @@ def main():
                   "sylvester_fp32": {"avg_launch_ms": round(vv32_ms / max(vv32_n, 1), 4), "launches": vv32_n,
                                      "achieved_tflops": round(vv_flops / (vv32_ms / max(vv32_n, 1) * 1e-3) / 1e12, 3),
                                      "peak_tflops": PEAK_FP32_TFLOPS}},
+        "mixed_bf16_top_basis": {"time_to_e2_ms": round(bf16_ms, 4), "speedup_vs_fp64": round(ms_per_step / bf16_ms, 3),
+                  "e2": res_b["e2"], "e2_minus_fp64": res_b["e2"] - res["e2"],
+                  "e2_minus_oracle": None if gold is None else res_b["e2"] - gold["e2"],
+                  "inner_iterations": res_b["iterations"], "outer_fp64_steps": res_b["outer"],
+                  "rel_resid": res_b["rel_resid"], "sigma_bf16_ms": round(sigmab_ms, 4),
+                  "sigma_bf16_gflops": round(sig_flops / sigmab_ms / 1e6, 2),
+                  "sylvester_bf16": {"avg_launch_ms": round(vvb_ms / max(vvb_n, 1), 4), "launches": vvb_n,
+                                     "achieved_tflops": round(vv_flops / (vvb_ms / max(vvb_n, 1) * 1e-3) / 1e12, 3),
+                                     "peak_tflops": PEAK_BF16_TFLOPS}},
         "semicanonical": {
             "fp64": {"time_to_e2_ms": round(sc_ms, 4), "speedup_vs_top_fp64": round(ms_per_step / sc_ms, 3),
                      "e2": res_sc["e2"], "iterations": res_sc["iterations"],

@@ -78,8 +78,16 @@ typedef enum {
 
 typedef enum {
   ESMP2_FP64 = 0,           /* FP64 everywhere                                       */
-  ESMP2_FP32 = 1            /* the operator in FP32 (FP32 inputs, Fock blocks rounded
+  ESMP2_FP32 = 1,           /* the operator in FP32 (FP32 inputs, Fock blocks rounded
                                to FP32, FP32 matrix-core accumulation)               */
+  ESMP2_BF16 = 2            /* the FP32 operator except that the virtual-pair Fock
+                               products (the Sylvester part) take BF16 operands: F'
+                               and the amplitudes are rounded to BF16 (nearest even)
+                               on the way into the matrix cores, which accumulate in
+                               FP32.  FP32 vectors.  TOP basis only, padded virtual
+                               dimension 80, 112 or 160 (else ESMP2_UNSUPPORTED).  In
+                               a solve: FP64 iterative refinement around inner solves
+                               with this operator (inner_tol 0 selects 1e-2)       */
 } esmp2_precision;
 
 typedef enum {
@@ -92,13 +100,13 @@ typedef enum {
 typedef struct {
   double tol;               /* stop when ||b + A x||_W / ||b||_W <= tol (e.g. 1e-8)   */
   int max_iter;             /* conjugate-gradient iteration cap                      */
-  int precision;            /* esmp2_precision of the solve: FP64, or FP32 inner
-                               solves inside FP64 iterative refinement               */
+  int precision;            /* esmp2_precision of the solve: FP64, or FP32 / BF16
+                               inner solves inside FP64 iterative refinement         */
   const double* x0;         /* device, n_amp, initial guess (warm start) or NULL      */
   double* x_out;            /* device, n_amp, receives the solution, or NULL          */
   double* resid_hist;       /* host, max_iter entries of ||r||/||b|| per iteration, or NULL
                                (FP32: the inner residual estimate times the outer one) */
-  double inner_tol;         /* FP32 only: smallest relative residual reduction asked of
+  double inner_tol;         /* FP32 / BF16: smallest relative residual reduction asked of
                                one inner FP32 solve, in [0, 1); 0 selects 1e-5         */
   int basis;                /* esmp2_basis of the Krylov solve (results are the same) */
 } esmp2_solve_opts;
@@ -110,7 +118,7 @@ typedef struct {
   double e0;                /* E0 = <Psi0|F|Psi0>                                     */
   double rel_resid;         /* final ||b + A x||_W / ||b||_W                          */
   int iterations;           /* conjugate-gradient iterations (all inner ones in FP32) */
-  int outer;                /* refinement steps (FP32 precision), 0 otherwise         */
+  int outer;                /* refinement steps (FP32 / BF16 precision), 0 otherwise  */
   int status;               /* esmp2_status of the solve                              */
 } esmp2_solve_result;
 
@@ -169,13 +177,16 @@ esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* 
 
 /* y = (H0 - E0) x on doubles + L-triples (paper Sec. II.C).
  *   x, y: device, n_amp elements each (double for ESMP2_FP64, float for
- *   ESMP2_FP32); x and y must not overlap.  Requires esmp2_rotate_top. */
+ *   ESMP2_FP32 and ESMP2_BF16); x and y must not overlap.  Requires
+ *   esmp2_rotate_top.  ESMP2_BF16 returns ESMP2_UNSUPPORTED unless the padded
+ *   virtual dimension is 80, 112 or 160. */
 esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision);
 
 /* Jacobi-preconditioned conjugate gradient for A x = -b (A = H0 - E0 on D + L,
  * weighted inner product), then E2 (paper Sec. III.A and Sec. II.C).  Builds the
  * right-hand side first if esmp2_build_rhs has not been called.  Synchronises.
- * With precision = ESMP2_FP32, iterative refinement: the FP64 residual
+ * With precision = ESMP2_FP32 (or ESMP2_BF16: the same with the BF16 operator,
+ * TOP basis only), iterative refinement: the FP64 residual
  * r = -b - A x is recomputed with the FP64 operator after each inner solve
  * A d = r / ||r|| run by FP32 conjugate gradient (FP32 operator and vectors, FP64
  * reductions) to a relative reduction max(inner_tol, tol / (2 ||r||/||b||)); the
@@ -245,7 +256,7 @@ esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A
 
 /* Timing of the virtual-pair Sylvester kernel (the dominant sigma kernel) with
  * HIP events recorded on the handle's stream around each of its launches.
- * vv_ms[2], vv_launches[2] (host, indexed by esmp2_precision) receive the
+ * vv_ms[3], vv_launches[3] (host, indexed by esmp2_precision) receive the
  * accumulated milliseconds and launch counts since the last call, which are then
  * reset; recording is switched on (enable != 0) or off.  Waits for the recorded
  * events.  Either output may be NULL. */

@@ -7,6 +7,6 @@ been built.  PyTorch supplies device memory and the stream.
 """
 from ._lib import (ESMP2_OK, ESMP2_INVALID_ARG, ESMP2_BAD_ORDER, ESMP2_NOT_SPD,  # noqa: F401
                    ESMP2_NOT_CONVERGED, ESMP2_OOM, ESMP2_HIP_ERROR, ESMP2_UNSUPPORTED,
-                   ESMP2_FP64, ESMP2_FP32, ESMP2_BASIS_TOP, ESMP2_BASIS_SEMICANONICAL, Esmp2Error,
+                   ESMP2_FP64, ESMP2_FP32, ESMP2_BF16, ESMP2_BASIS_TOP, ESMP2_BASIS_SEMICANONICAL, Esmp2Error,
                    Handle, lib, LIB_PATH, solve_batch)
 from .autograd import e2_top  # noqa: F401,E402

@@ -12,7 +12,7 @@ lib = C.CDLL(LIB_PATH)
 
 (ESMP2_OK, ESMP2_INVALID_ARG, ESMP2_BAD_ORDER, ESMP2_NOT_SPD, ESMP2_NOT_CONVERGED,
  ESMP2_OOM, ESMP2_HIP_ERROR, ESMP2_UNSUPPORTED) = range(8)
-ESMP2_FP64, ESMP2_FP32 = 0, 1
+ESMP2_FP64, ESMP2_FP32, ESMP2_BF16 = 0, 1, 2
 ESMP2_BASIS_TOP, ESMP2_BASIS_SEMICANONICAL = 0, 1
 STATUS_NAMES = ["OK", "INVALID_ARG", "BAD_ORDER", "NOT_SPD", "NOT_CONVERGED", "OOM",
                 "HIP_ERROR", "UNSUPPORTED"]
@@ -159,9 +159,9 @@ class Handle:
 
     def profile(self, enable=True):
         """{precision: (ms, launches)} of the Sylvester kernel since the last call."""
-        ms, n = (C.c_double * 2)(), (C.c_int64 * 2)()
+        ms, n = (C.c_double * 3)(), (C.c_int64 * 3)()
         self._check(lib.esmp2_profile(self.h, 1 if enable else 0, ms, n))
-        return {ESMP2_FP64: (ms[0], n[0]), ESMP2_FP32: (ms[1], n[1])}
+        return {ESMP2_FP64: (ms[0], n[0]), ESMP2_FP32: (ms[1], n[1]), ESMP2_BF16: (ms[2], n[2])}
 
     def fock_from_core(self, hcore, B, Cm, n_occ, n_vir, n_aux, F_out):
         return self._check(lib.esmp2_fock_from_core(self.h, n_occ, n_vir, n_aux, _ptr(hcore), _ptr(B), _ptr(Cm),

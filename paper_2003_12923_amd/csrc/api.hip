@@ -8,6 +8,7 @@
 #include <vector>
 #include <new>
 #include <algorithm>
+#include <type_traits>
 #include <atomic>
 #include <thread>
 
@@ -115,8 +116,8 @@ struct esmp2_handle_ {
   bool prof = false;
   struct Ev { hipEvent_t a, b; int prec; };
   std::vector<Ev> ev_vv;
-  double vv_ms[2] = {0.0, 0.0};
-  int64_t vv_launches[2] = {0, 0};
+  double vv_ms[3] = {0.0, 0.0, 0.0};
+  int64_t vv_launches[3] = {0, 0, 0};
 };
 
 static esmp2_status fail(esmp2_handle h, esmp2_status s, const std::string& msg) {
@@ -260,7 +261,7 @@ esmp2_status esmp2_profile(esmp2_handle h, int enable, double* vv_ms, int64_t* v
   if (!h) return ESMP2_INVALID_ARG;
   ESMP2_HIP(hipSetDevice(h->device));
   drain_events(h);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     if (vv_ms) vv_ms[k] = h->vv_ms[k];
     if (vv_launches) vv_launches[k] = h->vv_launches[k];
     h->vv_ms[k] = 0.0;
@@ -754,7 +755,13 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
       e0 = e1 = nullptr;
     }
   }
-  if (d.mv == 160) {
+  if (w.prec == ESMP2_BF16) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (d.mv == 160) hipLaunchKernelGGL((k_vv3b<10>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+      else if (d.mv == 112) hipLaunchKernelGGL((k_vv3b<7>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+      else hipLaunchKernelGGL((k_vv3b<5>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+    }
+  } else if (d.mv == 160) {
     hipLaunchKernelGGL((k_vv3<T, 10>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
   } else if (d.mv == 112) {
     hipLaunchKernelGGL((k_vv3<T, 7>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
@@ -811,6 +818,14 @@ static esmp2_status sigma_arrow(esmp2_handle h, const SigmaBufs<T>& w, const T* 
 
 static esmp2_status sigma64(esmp2_handle h, const double* x, double* y) { return sigma_t(h, bufs64(h), x, y); }
 static esmp2_status sigma32(esmp2_handle h, const float* x, float* y) { return sigma_t(h, bufs32(h), x, y); }
+// the FP32 operator with BF16 operands in the Sylvester products
+static SigmaBufs<float> bufs_bf16(esmp2_handle h) {
+  SigmaBufs<float> w = bufs32(h);
+  w.prec = ESMP2_BF16;
+  return w;
+}
+// padded virtual dimensions with a BF16 Sylvester kernel
+static bool bf16_supported(const Dims& d) { return d.mv == 160 || d.mv == 112 || d.mv == 80; }
 
 // ---------------------------------------------------------------------------
 // pinned-semicanonical basis
@@ -987,6 +1002,11 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision) 
   ESMP2_HIP(hipSetDevice(h->device));
   if (precision == ESMP2_FP64) return sigma64(h, (const double*)x, (double*)y);
   if (precision == ESMP2_FP32) return sigma32(h, (const float*)x, (float*)y);
+  if (precision == ESMP2_BF16) {
+    if (!bf16_supported(h->d))
+      return fail(h, ESMP2_UNSUPPORTED, "BF16 Sylvester products need a padded virtual dimension of 80, 112 or 160");
+    return sigma_t(h, bufs_bf16(h), (const float*)x, (float*)y);
+  }
   return fail(h, ESMP2_INVALID_ARG, "unknown precision");
 }
 
@@ -1097,7 +1117,9 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
   const int64_t n = d.off[7];
   hipStream_t s = h->stream;
   const unsigned NB = PCG_BLOCKS;
-  const double floor_eta = opts->inner_tol > 0 ? opts->inner_tol : 1e-5;
+  // an operator with BF16 operands is accurate to ~1e-3 relative: ask its inner
+  // solves for two digits and let the FP64 refinement do the rest
+  const double floor_eta = opts->inner_tol > 0 ? opts->inner_tol : (c.s32.prec == ESMP2_BF16 ? 1e-2 : 1e-5);
   wdot(h, c.b, c.b, SC_BB);
   if (opts->x0) {
     if (c.rotated) {
@@ -1171,11 +1193,15 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
   if (!opts || !res) return fail(h, ESMP2_INVALID_ARG, "null opts/result");
   if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
   if (!(opts->tol > 0) || opts->max_iter < 1) return fail(h, ESMP2_INVALID_ARG, "tol > 0 and max_iter >= 1");
-  if (opts->precision != ESMP2_FP64 && opts->precision != ESMP2_FP32)
+  if (opts->precision != ESMP2_FP64 && opts->precision != ESMP2_FP32 && opts->precision != ESMP2_BF16)
     return fail(h, ESMP2_INVALID_ARG, "unknown precision");
+  if (opts->precision == ESMP2_BF16 && (opts->basis != ESMP2_BASIS_TOP || !bf16_supported(h->d)))
+    return fail(h, ESMP2_UNSUPPORTED,
+                "BF16 applies to the Sylvester products of the TOP-basis operator, padded virtual dimension 80, 112 "
+                "or 160");
   if (opts->basis != ESMP2_BASIS_TOP && opts->basis != ESMP2_BASIS_SEMICANONICAL)
     return fail(h, ESMP2_INVALID_ARG, "unknown basis");
-  if (opts->precision == ESMP2_FP32 && !(opts->inner_tol >= 0 && opts->inner_tol < 1))
+  if (opts->precision != ESMP2_FP64 && !(opts->inner_tol >= 0 && opts->inner_tol < 1))
     return fail(h, ESMP2_INVALID_ARG, "inner_tol must lie in [0, 1)");
   ESMP2_HIP(hipSetDevice(h->device));
   memset(res, 0, sizeof(*res));
@@ -1191,6 +1217,7 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
     }
     c = ctx_sc(h);
   }
+  if (opts->precision == ESMP2_BF16) c.s32.prec = ESMP2_BF16;
   return opts->precision == ESMP2_FP64 ? solve64(h, c, opts, res) : solve_mixed(h, c, opts, res);
 }
 

@@ -63,6 +63,7 @@ inline int64_t sym_s2_blocks(const Dims& d) {
 }
 template <class T, int TW> __global__ void k_vv(VVArgs<T> A);
 template <class T, int NT> __global__ void k_vv3(VVArgs<T> A);
+template <int NT> __global__ void k_vv3b(VVArgs<float> A);
 template <class T> __global__ void k_side(SideArgs<T> A);
 template <class T> __global__ void k_couple(GatherArgs<T> A, PairTables P, const int4* chunks);
 template <class T> __global__ void k_oo(GatherArgs<T> A, int4 tiles0, int4 tiles1);
