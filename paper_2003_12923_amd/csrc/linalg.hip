@@ -16,7 +16,8 @@ namespace esmp2 {
 // ---------------------------------------------------------------------------
 // C[b] = alpha * A[b] * B[b] + beta * C[b]
 //   A(i,k) = A[b*sAb + i*sAi + k*sAk],  B(k,j) = B[b*sBb + k*sBk + j*sBj],
-//   C(i,j) = C[b*sCb + i*sCi + j*sCj].  Tile 64x64x16, 4 wavefronts of 32x32.
+//   C(i,j) = C[b*sCb + i*sCi + j*sCj].  Tile 64x64x16, 4 wavefronts of 32x32,
+//   double-buffered K chunks.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
   const double* A; const double* B; double* C;
@@ -26,8 +27,8 @@ struct GemmArgs {
 };
 
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
+  __shared__ double As[2][16][64 + 1];
+  __shared__ double Bs[2][16][64 + 1];
   const int b = blockIdx.z;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
@@ -38,32 +39,62 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) acc[i][j] = (f64x4){0, 0, 0, 0};
   const bool a_kfast = (g.sAk == 1);
   const bool b_jfast = (g.sBj == 1) || (g.sBk != 1);
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
+  // K chunks of 16 through two LDS buffers: the next chunk is loaded into
+  // registers while the current one is multiplied (loads always in bounds: an
+  // element outside the matrix reads element 0 and is replaced by zero)
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int e = tid + 256 * r;
+      const int e = tid + 256 * r;
       int mm, kk;
       if (a_kfast) { mm = e >> 4; kk = e & 15; } else { mm = e & 63; kk = e >> 6; }
-      int gi = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gi < g.M && gk < g.K) ? A[gi * g.sAi + gk * g.sAk] : 0.0;
+      const int gi = m0 + mm, gk = k0 + kk;
+      const bool oka = gi < g.M && gk < g.K;
+      const double va = A[oka ? gi * g.sAi + gk * g.sAk : 0];
+      ra[r] = oka ? va : 0.0;
       int nn;
       if (b_jfast) { nn = e & 63; kk = e >> 6; } else { nn = e >> 4; kk = e & 15; }
-      int gj = n0 + nn;
-      gk = k0 + kk;
-      Bs[kk][nn] = (gj < g.N && gk < g.K) ? Bm[gk * g.sBk + gj * g.sBj] : 0.0;
+      const int gj = n0 + nn, gk2 = k0 + kk;
+      const bool okb = gj < g.N && gk2 < g.K;
+      const double vb = Bm[okb ? gk2 * g.sBk + gj * g.sBj : 0];
+      rb[r] = okb ? vb : 0.0;
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int mm, kk;
+      if (a_kfast) { mm = e >> 4; kk = e & 15; } else { mm = e & 63; kk = e >> 6; }
+      As[buf][kk][mm] = ra[r];
+      int nn;
+      if (b_jfast) { nn = e & 63; kk = e >> 6; } else { nn = e >> 4; kk = e & 15; }
+      Bs[buf][kk][nn] = rb[r];
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    const bool more = k0 + 16 < g.K;
+    if (more) load(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      double a0 = As[ks * 4 + (l >> 4)][wm + (l & 15)];
-      double a1 = As[ks * 4 + (l >> 4)][wm + 16 + (l & 15)];
-      double b0 = Bs[ks * 4 + (l >> 4)][wn + (l & 15)];
-      double b1 = Bs[ks * 4 + (l >> 4)][wn + 16 + (l & 15)];
+      double a0 = As[buf][ks * 4 + (l >> 4)][wm + (l & 15)];
+      double a1 = As[buf][ks * 4 + (l >> 4)][wm + 16 + (l & 15)];
+      double b0 = Bs[buf][ks * 4 + (l >> 4)][wn + (l & 15)];
+      double b1 = Bs[buf][ks * 4 + (l >> 4)][wn + 16 + (l & 15)];
       acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
       acc[0][1] = mfma16x16x4(a0, b1, acc[0][1]);
       acc[1][0] = mfma16x16x4(a1, b0, acc[1][0]);
       acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   double* C = g.C + b * g.sCb;
   for (int ti = 0; ti < 2; ++ti)
