@@ -234,9 +234,9 @@ def main():
     if os.path.exists(tfile):
         import hashlib
         t = json.load(open(tfile))
-        src = os.path.join(ROOT, "paper_2003_12923_amd", "csrc", "vv3.hip")
-        if (t.get("workload") == args.workload and
-                t.get("source_sha256") == hashlib.sha256(open(src, "rb").read()).hexdigest()):
+        srcs = [os.path.join(ROOT, "paper_2003_12923_amd", "csrc", f) for f in ("vv3.hip", "vv3.h")]
+        digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
+        if t.get("workload") == args.workload and t.get("source_sha256") == digest:
             traffic = round(t["fetch_bytes"] + t["write_bytes"])
 
     gold = None

@@ -520,8 +520,10 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P, c
     default: inner = m1 * m1; break;
   }
   if (v >= inner) return;
+  T* yp = A.y + d.off[box] + (int64_t)batch * inner + v;
+  const T y0 = *yp;                  // issued ahead of the lookups: its latency overlaps theirs
   const T y = couple_terms(A, P, box, batch, p0, q0, v);
-  A.y[d.off[box] + (int64_t)batch * inner + v] += y;
+  *yp = y0 + y;
 }
 
 }  // namespace esmp2
