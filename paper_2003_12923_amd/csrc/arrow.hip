@@ -110,7 +110,7 @@ __device__ __attribute__((always_inline)) inline double arrow_element(const Arro
 template <class T>
 __global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, const int4* chunks, double* pq) {
   const Dims& d = A.ga.d;
-  const int4 ch = chunks[xcd_remap<16>(blockIdx.x, gridDim.x)];
+  const int4 ch = chunks[xcd_remap<32>(blockIdx.x, gridDim.x)];
   const int box = ch.x, batch = ch.y, v = ch.z + (int)threadIdx.x;
   const int i = ch.w >> 16, j = ch.w & 0xffff;      // occupied indices of the batch (actual orbitals)
   const int nv = d.nv, m1 = nv - 1;

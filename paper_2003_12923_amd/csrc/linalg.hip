@@ -340,53 +340,44 @@ __device__ inline int pk(int r, int c, int n) {   // packed upper index (r <= c)
 // workgroup of 1024 threads, A packed (upper) in dynamic LDS.
 // Outputs: refl (m x m, row k = reflector k on entries k+1..m-1), rbeta[m],
 // d[m] (diagonal), e[m] (e[k] = T[k][k+1]).
+// Step k needs two barriers: the scalars of the reflector (the norm of row k
+// beyond the first subdiagonal) and K = b v.p / 2 are short reductions that
+// every wavefront computes for itself; v is read straight from row k of A
+// (untouched by step k's update), and w = p - K v is formed inside the
+// rank-2 update.
 __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, double* refl, double* rbeta,
                                                   double* d, double* e) {
   extern __shared__ double A[];
-  __shared__ double v[256], p[256];
-  __shared__ double red[16];
-  __shared__ double sh[4];
+  __shared__ double p[256];
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, nw = blockDim.x >> 6;
   for (int r = 0; r < m; ++r)
     for (int c = r + tid; c < m; c += blockDim.x) A[pk(r, c, m)] = Ain[r * m + c];
   __syncthreads();
   auto at = [&](int r, int c) -> double { return r <= c ? A[pk(r, c, m)] : A[pk(c, r, m)]; };
   for (int k = 0; k < m - 2; ++k) {
-    // x = A[k][k+1..m-1]
+    // reflector scalars, in every wavefront (same reduction order everywhere)
     double s = 0.0;
-    for (int i = k + 2 + tid; i < m; i += blockDim.x) { double x = A[pk(k, i, m)]; s += x * x; }
-    s = wave_sum(s);
-    if (l == 0) red[wave] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double sig = 0.0;
-      for (int w = 0; w < nw; ++w) sig += red[w];
-      double x0 = A[pk(k, k + 1, m)];
-      double b = 0.0, alpha = x0, v0 = 0.0;
-      if (sig > 0.0) {
-        double nrm = sqrt(x0 * x0 + sig);
-        alpha = (x0 >= 0) ? -nrm : nrm;
-        v0 = x0 - alpha;
-        b = 2.0 / (v0 * v0 + sig);
-      }
-      sh[0] = b; sh[1] = alpha; sh[2] = v0;
+    for (int i = k + 2 + l; i < m; i += 64) { const double x = A[pk(k, i, m)]; s += x * x; }
+    const double sig = wave_sum(s);
+    const double x0 = A[pk(k, k + 1, m)];
+    double b = 0.0, alpha = x0, v0 = 0.0;
+    if (sig > 0.0) {
+      const double nrm = sqrt(x0 * x0 + sig);
+      alpha = (x0 >= 0) ? -nrm : nrm;
+      v0 = x0 - alpha;
+      b = 2.0 / (v0 * v0 + sig);
     }
-    __syncthreads();
-    const double b = sh[0];
-    for (int i = k + 1 + tid; i < m; i += blockDim.x) {
-      double vi = (i == k + 1) ? sh[2] : A[pk(k, i, m)];
-      v[i] = (b > 0.0) ? vi : 0.0;
-      refl[k * m + i] = v[i];
-    }
-    if (tid == 0) { rbeta[k] = b; e[k] = sh[1]; }
-    __syncthreads();
+    // v_i = v0 (i = k+1), A[k][i] (i > k+1); zero when the row is already reduced
+    auto vv = [&](int i) -> double { return b > 0.0 ? (i == k + 1 ? v0 : A[pk(k, i, m)]) : 0.0; };
+    for (int i = k + 1 + tid; i < m; i += blockDim.x) refl[k * m + i] = vv(i);
+    if (tid == 0) { rbeta[k] = b; e[k] = alpha; }
     if (b > 0.0) {
       // p = b A22 v : 8 threads per row
       const int len = m - k - 1;
       for (int t = tid; t < len * 8; t += blockDim.x) {
-        int i = k + 1 + t / 8, part = t % 8;
+        const int i = k + 1 + t / 8, part = t % 8;
         double acc = 0.0;
-        for (int j = k + 1 + part; j < m; j += 8) acc += at(i, j) * v[j];
+        for (int j = k + 1 + part; j < m; j += 8) acc += at(i, j) * vv(j);
         acc += __shfl_xor(acc, 1);
         acc += __shfl_xor(acc, 2);
         acc += __shfl_xor(acc, 4);
@@ -394,19 +385,16 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
       }
       __syncthreads();
       double kk = 0.0;
-      for (int i = k + 1 + tid; i < m; i += blockDim.x) kk += v[i] * p[i];
-      kk = wave_sum(kk);
-      if (l == 0) red[wave] = kk;
-      __syncthreads();
-      double K = 0.0;
-      for (int w = 0; w < nw; ++w) K += red[w];
-      K *= 0.5 * b;
-      // w = p - K v (in place in p), then A22 -= v w^T + w v^T (upper part)
-      __syncthreads();
-      for (int i = k + 1 + tid; i < m; i += blockDim.x) p[i] -= K * v[i];
-      __syncthreads();
-      for (int i = k + 1 + wave; i < m; i += nw)
-        for (int j = i + l; j < m; j += 64) A[pk(i, j, m)] -= v[i] * p[j] + p[i] * v[j];
+      for (int i = k + 1 + l; i < m; i += 64) kk += vv(i) * p[i];
+      const double K = 0.5 * b * wave_sum(kk);
+      // A22 -= v w^T + w v^T (upper part), w = p - K v
+      for (int i = k + 1 + wave; i < m; i += nw) {
+        const double vi = vv(i), wi = p[i] - K * vi;
+        for (int j = i + l; j < m; j += 64) {
+          const double vj = vv(j);
+          A[pk(i, j, m)] -= vi * (p[j] - K * vj) + wi * vj;
+        }
+      }
     }
     __syncthreads();
   }

@@ -508,7 +508,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P, const int4* chunks) {
   const Dims& d = A.d;
   // chunk: (box, batch, first inner index, (p << 16) | q occupied indices of the batch)
-  const int4 ch = chunks[xcd_remap<16>(blockIdx.x, gridDim.x)];
+  const int4 ch = chunks[xcd_remap<32>(blockIdx.x, gridDim.x)];
   const int box = ch.x, batch = ch.y, v = ch.z + (int)threadIdx.x;
   const int p0 = ch.w >> 16, q0 = ch.w & 0xffff;
   const int nv = d.nv, m1 = nv - 1;
