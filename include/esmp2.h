@@ -262,6 +262,32 @@ esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A
  * events.  Either output may be NULL. */
 esmp2_status esmp2_profile(esmp2_handle h, int enable, double* vv_ms, int64_t* vv_launches);
 
+/* Variants of the virtual-pair Sylvester products (the dominant sigma kernel):
+ *   0  the specialised kernel: one batch matrix per workgroup of 8 wavefronts
+ *      with balanced tile lists (padded virtual dimension 80, 112 or 160; the
+ *      only variant with BF16 operands)
+ *   1..5  the generic kernel with output blocks of 32 v x 32 v per workgroup
+ * Without a choice, a handle uses the variant esmp2_autotune recorded for its
+ * (n_occ, n_vir, precision) in this process, else 0 where available, else
+ * min((mv / 16 + 1) / 2, 5) (mv = n_vir rounded up to 16). */
+#define ESMP2_SYLVESTER_VARIANTS 6
+
+/* Autotuner: times every available variant on this handle's problem (`reps`
+ * launches each after one warm-up, HIP events on the handle's stream, on a
+ * zero input in the handle's own work vectors), records the fastest for
+ * (n_occ, n_vir, precision) for every handle of the process, and clears this
+ * handle's own choice so that the recorded one applies.  Synchronises.
+ *   variant_out: host, the fastest variant, or NULL
+ *   ms_out: host, ESMP2_SYLVESTER_VARIANTS average milliseconds per launch
+ *           (-1 for a variant not available at this size), or NULL
+ * Requires esmp2_rotate_top; reps in [1, 1000]; ESMP2_UNSUPPORTED for BF16 at
+ * a size without the specialised kernel. */
+esmp2_status esmp2_autotune(esmp2_handle h, int precision, int reps, int* variant_out, double* ms_out);
+
+/* Fix the variant of one precision for this handle (-1: automatic, as above).
+ * ESMP2_INVALID_ARG for a variant not available at this size and precision. */
+esmp2_status esmp2_set_sylvester_variant(esmp2_handle h, int precision, int variant);
+
 /* Message of the last failing call on this handle (never NULL). */
 const char* esmp2_last_error(esmp2_handle h);
 

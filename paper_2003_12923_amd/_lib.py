@@ -13,6 +13,7 @@ lib = C.CDLL(LIB_PATH)
 (ESMP2_OK, ESMP2_INVALID_ARG, ESMP2_BAD_ORDER, ESMP2_NOT_SPD, ESMP2_NOT_CONVERGED,
  ESMP2_OOM, ESMP2_HIP_ERROR, ESMP2_UNSUPPORTED) = range(8)
 ESMP2_FP64, ESMP2_FP32, ESMP2_BF16 = 0, 1, 2
+SYLVESTER_VARIANTS = 6
 ESMP2_BASIS_TOP, ESMP2_BASIS_SEMICANONICAL = 0, 1
 STATUS_NAMES = ["OK", "INVALID_ARG", "BAD_ORDER", "NOT_SPD", "NOT_CONVERGED", "OOM",
                 "HIP_ERROR", "UNSUPPORTED"]
@@ -50,6 +51,8 @@ _sig = {
     "esmp2_set_problem_top": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int],
                               C.c_int),
     "esmp2_gradient": ([_H, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "esmp2_autotune": ([_H, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)], C.c_int),
+    "esmp2_set_sylvester_variant": ([_H, C.c_int, C.c_int], C.c_int),
     "esmp2_last_error": ([_H], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -162,6 +165,16 @@ class Handle:
         ms, n = (C.c_double * 3)(), (C.c_int64 * 3)()
         self._check(lib.esmp2_profile(self.h, 1 if enable else 0, ms, n))
         return {ESMP2_FP64: (ms[0], n[0]), ESMP2_FP32: (ms[1], n[1]), ESMP2_BF16: (ms[2], n[2])}
+
+    def autotune(self, precision=ESMP2_FP64, reps=5):
+        """Time every Sylvester variant; returns (fastest, [ms per launch or -1])."""
+        v = C.c_int(-1)
+        ms = (C.c_double * SYLVESTER_VARIANTS)()
+        self._check(lib.esmp2_autotune(self.h, precision, reps, C.byref(v), ms))
+        return v.value, list(ms)
+
+    def set_sylvester_variant(self, precision, variant):
+        return self._check(lib.esmp2_set_sylvester_variant(self.h, precision, variant))
 
     def fock_from_core(self, hcore, B, Cm, n_occ, n_vir, n_aux, F_out):
         return self._check(lib.esmp2_fock_from_core(self.h, n_occ, n_vir, n_aux, _ptr(hcore), _ptr(B), _ptr(Cm),

@@ -11,6 +11,9 @@
 #include <type_traits>
 #include <atomic>
 #include <thread>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 // Kernels come from the other sources of the same translation unit (esmp2_all.hip).
 
@@ -113,6 +116,7 @@ struct esmp2_handle_ {
   double* gv;                    // row/column GEMVs of the arrow-shaped Fock blocks (FP64 or FP32 use)
   // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream,
   // per operator precision (index = esmp2_precision)
+  int vv_variant[3] = {-1, -1, -1};   // Sylvester variant per esmp2_precision, -1: automatic
   bool prof = false;
   struct Ev { hipEvent_t a, b; int prec; };
   std::vector<Ev> ev_vv;
@@ -724,6 +728,64 @@ static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const
   return ga;
 }
 
+// Sylvester-product variants: 0 = the specialised kernel (padded virtual
+// dimension 80, 112 or 160; BF16 operands only there), 1..5 = the generic
+// kernel with 32 TW x 32 TW output blocks per workgroup, TW = variant.
+constexpr int VV_VARIANTS = 6;
+
+static bool vv_specialised(const Dims& d) { return d.mv == 160 || d.mv == 112 || d.mv == 80; }
+
+static bool vv_variant_ok(const Dims& d, int prec, int v) {
+  if (prec == ESMP2_BF16) return v == 0 && vv_specialised(d);
+  return v == 0 ? vv_specialised(d) : (v >= 1 && v < VV_VARIANTS);
+}
+
+// Choices of esmp2_autotune, shared by every handle of the process (key: n_occ, n_vir, precision)
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tune;
+
+static int vv_variant(esmp2_handle h, int prec) {
+  const Dims& d = h->d;
+  if (h->vv_variant[prec] >= 0 && vv_variant_ok(d, prec, h->vv_variant[prec])) return h->vv_variant[prec];
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(d.no, d.nv, prec));
+    if (it != g_tune.end() && vv_variant_ok(d, prec, it->second)) return it->second;
+  }
+  if (vv_specialised(d)) return 0;
+  return std::min((d.mv / 16 + 1) / 2, 5);
+}
+
+template <class T>
+static void launch_vv(esmp2_handle h, const VVArgs<T>& va, int prec, int variant, hipStream_t s) {
+  const Dims& d = h->d;
+  if (variant == 0) {
+    if (prec == ESMP2_BF16) {
+      if constexpr (std::is_same<T, float>::value) {
+        if (d.mv == 160) hipLaunchKernelGGL((k_vv3b<10>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+        else if (d.mv == 112) hipLaunchKernelGGL((k_vv3b<7>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+        else hipLaunchKernelGGL((k_vv3b<5>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+      }
+    } else if (d.mv == 160) {
+      hipLaunchKernelGGL((k_vv3<T, 10>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+    } else if (d.mv == 112) {
+      hipLaunchKernelGGL((k_vv3<T, 7>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+    } else {
+      hipLaunchKernelGGL((k_vv3<T, 5>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
+    }
+    return;
+  }
+  const int nb = (d.mv + 32 * variant - 1) / (32 * variant);
+  const dim3 grid(h->njobs, nb, nb);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((k_vv<T, 1>), grid, dim3(256), 0, s, va); break;
+    case 2: hipLaunchKernelGGL((k_vv<T, 2>), grid, dim3(256), 0, s, va); break;
+    case 3: hipLaunchKernelGGL((k_vv<T, 3>), grid, dim3(256), 0, s, va); break;
+    case 4: hipLaunchKernelGGL((k_vv<T, 4>), grid, dim3(256), 0, s, va); break;
+    default: hipLaunchKernelGGL((k_vv<T, 5>), grid, dim3(256), 0, s, va); break;
+  }
+}
+
 template <class T>
 static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y) {
   const Dims& d = h->d;
@@ -741,11 +803,6 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
   const bool oo_mfma = no <= 16 && lds_oo <= 160 * 1024 - 2048;
   // virtual-pair Sylvester products (+ the diagonal constants folded into F')
   VVArgs<T> va{d, x, w.S, y, w.Fd, w.Fl, w.side_tr, h->jobs, h->jobs4};
-  const int tiles = d.mv / 16;
-  int tw = (tiles + 1) / 2;
-  if (tw > 5) tw = 5;
-  const int nb = (d.mv + 32 * tw - 1) / (32 * tw);
-  dim3 grid(h->njobs, nb, nb);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->prof) {
     if (h->ev_vv.size() >= 4096) drain_events(h);
@@ -755,25 +812,7 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
       e0 = e1 = nullptr;
     }
   }
-  if (w.prec == ESMP2_BF16) {
-    if constexpr (std::is_same<T, float>::value) {
-      if (d.mv == 160) hipLaunchKernelGGL((k_vv3b<10>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
-      else if (d.mv == 112) hipLaunchKernelGGL((k_vv3b<7>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
-      else hipLaunchKernelGGL((k_vv3b<5>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
-    }
-  } else if (d.mv == 160) {
-    hipLaunchKernelGGL((k_vv3<T, 10>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
-  } else if (d.mv == 112) {
-    hipLaunchKernelGGL((k_vv3<T, 7>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
-  } else if (d.mv == 80) {
-    hipLaunchKernelGGL((k_vv3<T, 5>), dim3(h->njobs4), dim3(V3_THREADS), 0, s, va);
-  } else switch (tw) {
-    case 1: hipLaunchKernelGGL((k_vv<T, 1>), grid, dim3(256), 0, s, va); break;
-    case 2: hipLaunchKernelGGL((k_vv<T, 2>), grid, dim3(256), 0, s, va); break;
-    case 3: hipLaunchKernelGGL((k_vv<T, 3>), grid, dim3(256), 0, s, va); break;
-    case 4: hipLaunchKernelGGL((k_vv<T, 4>), grid, dim3(256), 0, s, va); break;
-    default: hipLaunchKernelGGL((k_vv<T, 5>), grid, dim3(256), 0, s, va); break;
-  }
+  launch_vv(h, va, w.prec, vv_variant(h, w.prec), s);
   if (e0) {
     (void)hipEventRecord(e1, s);
     h->ev_vv.push_back({e0, e1, w.prec});
@@ -1008,6 +1047,70 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision) 
     return sigma_t(h, bufs_bf16(h), (const float*)x, (float*)y);
   }
   return fail(h, ESMP2_INVALID_ARG, "unknown precision");
+}
+
+esmp2_status esmp2_set_sylvester_variant(esmp2_handle h, int precision, int variant) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (precision < ESMP2_FP64 || precision > ESMP2_BF16) return fail(h, ESMP2_INVALID_ARG, "unknown precision");
+  if (h->state < 1) return fail(h, ESMP2_BAD_ORDER, "esmp2_set_problem first");
+  if (variant != -1 && !vv_variant_ok(h->d, precision, variant))
+    return fail(h, ESMP2_INVALID_ARG, "Sylvester variant not available for this size and precision");
+  h->vv_variant[precision] = variant;
+  return ESMP2_OK;
+}
+
+esmp2_status esmp2_autotune(esmp2_handle h, int precision, int reps, int* variant_out, double* ms_out) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (precision < ESMP2_FP64 || precision > ESMP2_BF16) return fail(h, ESMP2_INVALID_ARG, "unknown precision");
+  if (reps < 1 || reps > 1000) return fail(h, ESMP2_INVALID_ARG, "reps must lie in [1, 1000]");
+  if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
+  if (precision == ESMP2_BF16 && !vv_specialised(h->d))
+    return fail(h, ESMP2_UNSUPPORTED, "BF16 Sylvester products need a padded virtual dimension of 80, 112 or 160");
+  ESMP2_HIP(hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  const int64_t n = h->d.off[7];
+  double ms[VV_VARIANTS];
+  hipEvent_t a = nullptr, b = nullptr;
+  ESMP2_HIP(hipEventCreate(&a));
+  ESMP2_HIP(hipEventCreate(&b));
+  auto time_all = [&](auto w, auto* x, auto* y) -> esmp2_status {
+    ESMP2_HIP(hipMemsetAsync(x, 0, sizeof(*x) * n, s));
+    VVArgs<typename std::remove_pointer<decltype(x)>::type> va{h->d, x, w.S, y, w.Fd, w.Fl, w.side_tr, h->jobs,
+                                                                 h->jobs4};
+    (void)sigma_prologue(h, w, x, y);       // the flip-symmetrised S2 block the kernels read
+    for (int v = 0; v < VV_VARIANTS; ++v) {
+      ms[v] = -1.0;
+      if (!vv_variant_ok(h->d, precision, v)) continue;
+      launch_vv(h, va, precision, v, s);
+      ESMP2_HIP(hipEventRecord(a, s));
+      for (int r = 0; r < reps; ++r) launch_vv(h, va, precision, v, s);
+      ESMP2_HIP(hipEventRecord(b, s));
+      ESMP2_HIP(hipEventSynchronize(b));
+      float t = 0.f;
+      ESMP2_HIP(hipEventElapsedTime(&t, a, b));
+      ms[v] = t / reps;
+    }
+    return ESMP2_OK;
+  };
+  esmp2_status st;
+  if (precision == ESMP2_FP64) st = time_all(bufs64(h), h->p, h->q);
+  else if (precision == ESMP2_FP32) st = time_all(bufs32(h), h->p32, h->q32);
+  else st = time_all(bufs_bf16(h), h->p32, h->q32);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != ESMP2_OK) return st;
+  int best = -1;
+  for (int v = 0; v < VV_VARIANTS; ++v)
+    if (ms[v] >= 0 && (best < 0 || ms[v] < ms[best])) best = v;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(h->d.no, h->d.nv, precision)] = best;
+  }
+  h->vv_variant[precision] = -1;
+  if (variant_out) *variant_out = best;
+  if (ms_out)
+    for (int v = 0; v < VV_VARIANTS; ++v) ms_out[v] = ms[v];
+  return ESMP2_OK;
 }
 
 }  // extern "C"
