@@ -84,6 +84,34 @@ def test_every_variant_and_the_tuned_choice(lib, no, nv, na, seed):
     h.close()
 
 
+@pytest.mark.parametrize("no,nv,na,seed", [(5, 40, 12, 31), (4, 80, 12, 32)])
+def test_every_variant_triplet(lib, no, nv, na, seed):
+    """Every variant with the M_s = 0 triplet reference (flip partners of opposite sign)."""
+    print(f"[case] triplet variants n_occ={no} n_vir={nv} n_aux={na} seed={seed}", flush=True)
+    prob = synth.make_problem(no, nv, na, seed)
+    lam, R = topbasis.top_rotation(prob.F, prob.C, no)
+    Ft, Bt = topbasis.rotate(prob.F, prob.B, R)
+    lam, Ft, Bt = (np.ascontiguousarray(a) for a in (lam, Ft, Bt))
+    h = lib.Handle(0)
+    dev = [torch.from_numpy(a).cuda() for a in (Ft, Bt, lam)]
+    h.set_problem_top(dev[0], dev[1], dev[2], no, nv, na, spin=1)
+    h.rotate_top(False)
+    n, _ = h.space()
+    x = synth.random_amplitudes(n, seed + 700)
+    ref = structured.Structured(Ft, lam, no, spin=1).sigma(x)
+    xt = torch.from_numpy(x).cuda()
+    mv = 16 * ((nv + 15) // 16)
+    for v in ([0] if mv in (80, 112, 160) else []) + [1, 2, 3, 4, 5]:
+        h.set_sylvester_variant(lib.ESMP2_FP64, v)
+        y = torch.full_like(xt, float("nan"))
+        h.sigma(xt, y)
+        torch.cuda.synchronize()
+        err = np.abs(y.cpu().numpy() - ref).max()
+        print(f"[triplet variant {v}] max err {err:.3e}", flush=True)
+        assert err <= 1e-12 * np.abs(ref).max()
+    h.close()
+
+
 def test_autotune_fp32_and_bad_arguments(lib):
     prob = synth.config_problem("c5")
     print(f"[case] n_occ={prob.n_occ} n_vir={prob.n_vir} n_aux={prob.n_aux}", flush=True)

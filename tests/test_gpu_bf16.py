@@ -141,3 +141,49 @@ def test_bf16_unsupported_cases(lib):
         h.solve(tol=1e-8, max_iter=10, precision=lib.ESMP2_BF16, basis=lib.ESMP2_BASIS_SEMICANONICAL)
     assert e.value.status == lib.ESMP2_UNSUPPORTED
     h.close()
+
+
+@pytest.mark.parametrize("no,nv,na,seed", [(4, 80, 16, 21), (3, 112, 12, 22)])
+def test_sigma_bf16_triplet(lib, no, nv, na, seed):
+    """The M_s = 0 triplet (flip partners with opposite amplitudes) through the BF16 kernel."""
+    print(f"[case] triplet bf16 n_occ={no} n_vir={nv} n_aux={na} seed={seed}", flush=True)
+    prob = synth.make_problem(no, nv, na, seed)
+    lam, R = topbasis.top_rotation(prob.F, prob.C, no)
+    Ft, Bt = topbasis.rotate(prob.F, prob.B, R)
+    lam, Ft, Bt = (np.ascontiguousarray(a) for a in (lam, Ft, Bt))
+    h = lib.Handle(0)
+    dev = [torch.from_numpy(a).cuda() for a in (Ft, Bt, lam)]
+    h.set_problem_top(dev[0], dev[1], dev[2], no, nv, na, spin=1)
+    h.rotate_top(False)
+    op = structured.Structured(Ft, lam, no, spin=1)
+    n, offs = h.space()
+    x = synth.random_amplitudes(n, seed + 600)
+    ref = op.sigma(x)
+    xt = torch.from_numpy(x).to(torch.float32).cuda()
+    yb = torch.full_like(xt, float("nan"))
+    h.sigma(xt, yb, precision=lib.ESMP2_BF16)
+    torch.cuda.synchronize()
+    y = yb.cpu().numpy().astype(np.float64)
+    mv = 16 * ((nv + 15) // 16)
+    K = 2 * mv + 2 * no + 24
+    gam = K * U32 / (1 - K * U32)
+    bound = (2 * UB + UB * UB + gam + 2 * U32) * _op_norm_bound(Ft, lam, no) * np.abs(x).max()
+    err = np.abs(y - ref)
+    print(f"[bf16 triplet sigma] max err {err.max():.3e} bound {bound:.3e}", flush=True)
+    assert err.max() <= bound
+    assert np.sqrt((err ** 2).mean()) <= 2 * UB * np.sqrt((ref ** 2).mean())
+    h.close()
+
+
+def test_bf16_refined_e2_triplet_workload(lib):
+    g = GOLD["c5_triplet"]
+    prob = synth.config_problem("c5")
+    print("[case] triplet c5 bf16", flush=True)
+    h = lib.Handle(0).load(prob, spin=1)
+    h.rotate_top()
+    res = h.solve(tol=1e-8, max_iter=500, precision=lib.ESMP2_BF16)
+    print(f"[c5 triplet bf16] E2 {res['e2']:.12f} oracle {g['e2']:.12f} diff {res['e2'] - g['e2']:.3e} "
+          f"outer {res['outer']}", flush=True)
+    assert res["status"] == 0 and res["rel_resid"] <= 1e-8
+    assert abs(res["e2"] - g["e2"]) <= 1e-6
+    h.close()
