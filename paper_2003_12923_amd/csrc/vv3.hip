@@ -13,8 +13,9 @@
 namespace esmp2 {
 
 // One batch matrix, one wavefront's tiles.  K runs over 2*mv in chunks of 16
-// (k < mv: A = F', B = X; k >= mv: A = X, B = F'), each chunk staged in one of
-// two LDS buffers while the other is multiplied.  The X operand (an HBM
+// (k < mv: A = F', B = X; k >= mv: A = X, B = F'; the two halves taken in
+// turns), each chunk staged in one of two LDS buffers while the other is
+// multiplied.  The X operand (an HBM
 // stream, long load latency) is loaded three chunks ahead into two register
 // sets that alternate; the F' operand (the same for every job, so L2
 // resident) two chunks ahead.  F' is symmetric, so its A slab (first half)
@@ -95,6 +96,11 @@ __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx<T>& c
     }
   };
   constexpr int NCH = 2 * MV / 16;                 // even, >= 10 for every instantiated NT
+  // K order: the two halves interleaved (chunk q = 2c: F'X over k in [16c, 16c+16);
+  // q = 2c+1: XF' over the same k), so that the second read of an X slab --
+  // the same stored data for a packed antisymmetric or a symmetric batch, and
+  // the same F' rows -- follows the first while it is still in L2
+  auto K0 = [&](int q) { return (q & 1) ? MV + 16 * (q >> 1) : 16 * (q >> 1); };
   // Chunk q from LDS buffer BUF = q % 2.  STAGE 3: stash chunk q+1 (F' and X,
   // the X values in register set (q+1) % 2 = BUF ^ 1), then load F' of chunk
   // q+2 and X of chunk q+3 into that register set; 2: no X load; 1: stash
@@ -117,17 +123,17 @@ __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx<T>& c
       for (int n = 0; n < TS.n; ++n) acc[n] = mfma16x16x4(a[TS.ri[n]], b[TS.ci[n]], acc[n]);
       if constexpr (STAGE >= 1) {
         if (ks == KST) {
-          stashF((q + 1) * 16, BUF ^ 1);
-          if constexpr (BUF == 0) stashX((q + 1) * 16, BUF ^ 1, rx1, fx1);
-          else stashX((q + 1) * 16, BUF ^ 1, rx0, fx0);
+          stashF(K0(q + 1), BUF ^ 1);
+          if constexpr (BUF == 0) stashX(K0(q + 1), BUF ^ 1, rx1, fx1);
+          else stashX(K0(q + 1), BUF ^ 1, rx0, fx0);
         }
       }
       if constexpr (STAGE >= 2) {
         if (ks == KST + 1) {
-          fetchF((q + 2) * 16);                    // before the X loads: the next stash waits on it alone
+          fetchF(K0(q + 2));                    // before the X loads: the next stash waits on it alone
           if constexpr (STAGE >= 3) {
-            if constexpr (BUF == 0) fetchX((q + 3) * 16, rx1, fx1);
-            else fetchX((q + 3) * 16, rx0, fx0);
+            if constexpr (BUF == 0) fetchX(K0(q + 3), rx1, fx1);
+            else fetchX(K0(q + 3), rx0, fx0);
           }
         }
       }
@@ -141,13 +147,13 @@ __device__ __attribute__((always_inline)) inline void vv3_body(const V3Ctx<T>& c
   using S2 = std::integral_constant<int, 2>;
   using S3 = std::integral_constant<int, 3>;
   // prologue: chunk 0 in LDS buffer 0, F' and X of chunk 1 and X of chunk 2 in flight
-  fetchF(0);
-  fetchX(0, rx0, fx0);
-  stashF(0, 0);
-  stashX(0, 0, rx0, fx0);
-  fetchF(16);
-  fetchX(16, rx1, fx1);
-  fetchX(32, rx0, fx0);
+  fetchF(K0(0));
+  fetchX(K0(0), rx0, fx0);
+  stashF(K0(0), 0);
+  stashX(K0(0), 0, rx0, fx0);
+  fetchF(K0(1));
+  fetchX(K0(1), rx1, fx1);
+  fetchX(K0(2), rx0, fx0);
   __syncthreads();
   for (int q = 0; q < NCH - 4; q += 2) {
     chunk(q, B0{}, S3{});

@@ -105,6 +105,11 @@ __device__ __attribute__((always_inline)) inline void vv3b_body(const V3Ctx<floa
     }
   };
   constexpr int NCH = 2 * MV / 16;
+  // K order: the two halves interleaved (chunk q = 2c: F'X over k in [16c, 16c+16);
+  // q = 2c+1: XF' over the same k), so that the second read of an X slab --
+  // the same stored data for a packed antisymmetric or a symmetric batch, and
+  // the same F' rows -- follows the first while it is still in L2
+  auto K0 = [&](int q) { return (q & 1) ? MV + 16 * (q >> 1) : 16 * (q >> 1); };
   auto chunk = [&](int q, auto buf_c, auto stage_c) {
     constexpr int BUF = decltype(buf_c)::value, STAGE = decltype(stage_c)::value;
     const unsigned short* A = lds + BUF * BUFSZ;
@@ -120,15 +125,15 @@ __device__ __attribute__((always_inline)) inline void vv3b_body(const V3Ctx<floa
     for (int n = 0; n < TS.n; ++n)
       acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[TS.ri[n]], b[TS.ci[n]], acc[n], 0, 0, 0);
     if constexpr (STAGE >= 1) {
-      stashF((q + 1) * 16, BUF ^ 1);
-      if constexpr (BUF == 0) stashX((q + 1) * 16, BUF ^ 1, rx1, fx1);
-      else stashX((q + 1) * 16, BUF ^ 1, rx0, fx0);
+      stashF(K0(q + 1), BUF ^ 1);
+      if constexpr (BUF == 0) stashX(K0(q + 1), BUF ^ 1, rx1, fx1);
+      else stashX(K0(q + 1), BUF ^ 1, rx0, fx0);
     }
     if constexpr (STAGE >= 2) {
-      fetchF((q + 2) * 16);
+      fetchF(K0(q + 2));
       if constexpr (STAGE >= 3) {
-        if constexpr (BUF == 0) fetchX((q + 3) * 16, rx1, fx1);
-        else fetchX((q + 3) * 16, rx0, fx0);
+        if constexpr (BUF == 0) fetchX(K0(q + 3), rx1, fx1);
+        else fetchX(K0(q + 3), rx0, fx0);
       }
     }
     __syncthreads();
@@ -139,13 +144,13 @@ __device__ __attribute__((always_inline)) inline void vv3b_body(const V3Ctx<floa
   using S1 = std::integral_constant<int, 1>;
   using S2 = std::integral_constant<int, 2>;
   using S3 = std::integral_constant<int, 3>;
-  fetchF(0);
-  fetchX(0, rx0, fx0);
-  stashF(0, 0);
-  stashX(0, 0, rx0, fx0);
-  fetchF(16);
-  fetchX(16, rx1, fx1);
-  fetchX(32, rx0, fx0);
+  fetchF(K0(0));
+  fetchX(K0(0), rx0, fx0);
+  stashF(K0(0), 0);
+  stashX(K0(0), 0, rx0, fx0);
+  fetchF(K0(1));
+  fetchX(K0(1), rx1, fx1);
+  fetchX(K0(2), rx0, fx0);
   __syncthreads();
   for (int q = 0; q < NCH - 4; q += 2) {
     chunk(q, B0{}, S3{});
