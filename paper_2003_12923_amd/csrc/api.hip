@@ -104,6 +104,7 @@ struct esmp2_handle_ {
   // pinned-semicanonical basis: rotations (t and t' fixed), operator blocks, rotated rhs,
   // Jacobi diagonal, dense scratch of the amplitude rotation
   bool have_sc = false;
+  bool dinv32_ok = false, dinv32_sc_ok = false;   // FP32 copies of the preconditioners, made on first use
   // side stream: the semicanonical eigenproblems run there while the main
   // stream builds the right-hand side (default priority, non-blocking)
   hipStream_t aux = nullptr;
@@ -635,7 +636,7 @@ static esmp2_status build_rhs(esmp2_handle h) {
   hipLaunchKernelGGL(k_rhs, dim3(nblk(namp)), dim3(256), 0, s, ra);
   DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv, h->blockmin};
   hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
-  hipLaunchKernelGGL(k_to_f32, dim3(PCG_BLOCKS), dim3(256), 0, s, (const double*)h->dinv, h->dinv32, namp);
+  h->dinv32_ok = false;
   hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
   // E2_S
   // grids of at most 1024 blocks each; partials laid out one kernel after the other
@@ -978,7 +979,7 @@ static esmp2_status semican_setup(esmp2_handle h) {
                      h->fov32_sc, (int64_t)no * nv);
   DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv_sc, h->blockmin};
   hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
-  hipLaunchKernelGGL(k_to_f32, dim3(PCG_BLOCKS), dim3(256), 0, s, (const double*)h->dinv_sc, h->dinv32_sc, namp);
+  h->dinv32_sc_ok = false;
   st = rotate_amplitudes(h, h->b, h->b_sc, true);
   if (st != ESMP2_OK) return st;
   ESMP2_HIP(hipGetLastError());
@@ -1223,6 +1224,13 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
   // an operator with BF16 operands is accurate to ~1e-3 relative: ask its inner
   // solves for two digits and let the FP64 refinement do the rest
   const double floor_eta = opts->inner_tol > 0 ? opts->inner_tol : (c.s32.prec == ESMP2_BF16 ? 1e-2 : 1e-5);
+  // the FP32 preconditioner of the inner solves, made once per right-hand side and basis
+  bool& d32_ok = c.rotated ? h->dinv32_sc_ok : h->dinv32_ok;
+  if (!d32_ok) {
+    hipLaunchKernelGGL(k_to_f32, dim3(NB), dim3(256), 0, s, c.rotated ? (const double*)h->dinv_sc : (const double*)h->dinv,
+                       c.rotated ? h->dinv32_sc : h->dinv32, n);
+    d32_ok = true;
+  }
   wdot(h, c.b, c.b, SC_BB);
   if (opts->x0) {
     if (c.rotated) {
