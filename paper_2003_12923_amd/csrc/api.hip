@@ -92,7 +92,7 @@ struct esmp2_handle_ {
   int4* jobs4 = nullptr;
   int njobs4 = 0;
   int* pairs = nullptr;          // (p << 16) | q tables: virtual pairs, shifted virtual, occupied, shifted occupied
-  int4* chunks = nullptr;        // coupling kernel work: (box, batch, first inner index, (p << 16) | q)
+  int4* chunks = nullptr;        // coupling kernel work: (box, batch, first inner index or S2 tile, (p << 16) | q)
   int nchunks = 0;
   double* pq_part = nullptr;     // per-chunk parts of <p, Ap>_W
   // Krylov vectors
@@ -389,7 +389,13 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
         } else {
           p = k / (no - 1) + 1; q = k % (no - 1) + 1;
         }
-        for (int v0 = 0; v0 < inner[bx]; v0 += 256) chunks.push_back(make_int4(bx, k, v0, (p << 16) | q));
+        if (bx == B_S2) {             // 16 x 16 tiles of (a, b), row-major
+          const int nt = (nv + 15) / 16;
+          for (int ta = 0; ta < nt; ++ta)
+            for (int tb = 0; tb < nt; ++tb) chunks.push_back(make_int4(bx, k, (ta << 16) | tb, (p << 16) | q));
+        } else {
+          for (int v0 = 0; v0 < inner[bx]; v0 += 256) chunks.push_back(make_int4(bx, k, v0, (p << 16) | q));
+        }
       }
   }
   h->nchunks = (int)chunks.size();

@@ -99,7 +99,8 @@ __global__ __launch_bounds__(256) void k_arrow_side(ArrowArgs<T> A) {
 
 // y = sigma for every amplitude: diagonal, arrow terms of both Fock blocks,
 // transfer rows, couplings.  One workgroup per chunk of 256 inner indices of
-// one batch matrix (the coupling kernel's chunk table).
+// one batch matrix, 16 x 16 tiles of (a, b) in S2 (the coupling kernel's chunk
+// table).
 // With pq != nullptr each workgroup also writes its part of <x, y>_W (the CG
 // denominator p.Ap) to pq[blockIdx.x].
 template <class T>
@@ -111,7 +112,7 @@ template <class T>
 __global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, const int4* chunks, double* pq) {
   const Dims& d = A.ga.d;
   const int4 ch = chunks[xcd_remap<32>(blockIdx.x, gridDim.x)];
-  const int box = ch.x, batch = ch.y, v = ch.z + (int)threadIdx.x;
+  const int box = ch.x, batch = ch.y;
   const int i = ch.w >> 16, j = ch.w & 0xffff;      // occupied indices of the batch (actual orbitals)
   const int nv = d.nv, m1 = nv - 1;
   int inner;
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, con
     case B_T3: inner = d.npv1; break;
     default: inner = m1 * m1; break;
   }
+  const int v = chunk_inner(box, ch.z, (int)threadIdx.x, nv, inner);
   double part = 0.0;
   if (v < inner) part = arrow_element(A, P, box, batch, i, j, v, inner);
   if (pq) {

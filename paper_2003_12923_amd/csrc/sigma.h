@@ -53,6 +53,18 @@ struct PairTables {
   const int* po1;    // occupied pairs of no - 1
 };
 
+// Inner index of thread `tid` of a coupling chunk (256 threads).  The S2 box
+// (dense nv x nv per batch) is cut into 16 x 16 tiles of (a, b), chunk.z =
+// (tile row << 16) | tile column, so that a wavefront reads four 128-byte
+// runs both of X[a][b] and of the transposed X[b][a] of a partner batch; every
+// other box takes 256 consecutive inner indices from chunk.z.  Returns `inner`
+// for a thread outside the box.
+__device__ inline int chunk_inner(int box, int z, int tid, int nv, int inner) {
+  if (box != B_S2) return z + tid;
+  const int a = 16 * (z >> 16) + (tid >> 4), b = 16 * (z & 0xffff) + (tid & 15);
+  return (a < nv && b < nv) ? a * nv + b : inner;
+}
+
 constexpr int GO = 8;   // inner (virtual-pair) indices per workgroup of the occupied-index kernel
 
 template <class T> __global__ void k_sym_s2(Dims d, const T* x, T* S);

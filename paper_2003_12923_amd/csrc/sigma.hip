@@ -507,9 +507,9 @@ __device__ __attribute__((always_inline)) inline T couple_terms(const GatherArgs
 template <class T>
 __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P, const int4* chunks) {
   const Dims& d = A.d;
-  // chunk: (box, batch, first inner index, (p << 16) | q occupied indices of the batch)
+  // chunk: (box, batch, first inner index or S2 tile, (p << 16) | q occupied indices of the batch)
   const int4 ch = chunks[xcd_remap<32>(blockIdx.x, gridDim.x)];
-  const int box = ch.x, batch = ch.y, v = ch.z + (int)threadIdx.x;
+  const int box = ch.x, batch = ch.y;
   const int p0 = ch.w >> 16, q0 = ch.w & 0xffff;
   const int nv = d.nv, m1 = nv - 1;
   int inner;
@@ -519,6 +519,7 @@ __global__ __launch_bounds__(256) void k_couple(GatherArgs<T> A, PairTables P, c
     case B_T3: inner = d.npv1; break;
     default: inner = m1 * m1; break;
   }
+  const int v = chunk_inner(box, ch.z, (int)threadIdx.x, nv, inner);
   if (v >= inner) return;
   T* yp = A.y + d.off[box] + (int64_t)batch * inner + v;
   const T y0 = *yp;                  // issued ahead of the lookups: its latency overlaps theirs
