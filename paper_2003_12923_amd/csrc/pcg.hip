@@ -24,8 +24,21 @@ __global__ __launch_bounds__(256) void k_dot(const T* x, const T* y, int64_t n, 
 
 // sc[base + k] = sum of partials[k*nb .. k*nb+nb-1], one block per sum
 __global__ void k_finish(const double* partial, int nb, double* sc, int base) {
+  // each thread adds its indices i, i + blockDim.x, ... in that order; the
+  // loads of eight of them are issued before the adds (a long partial list is
+  // otherwise one load latency per element)
   Acc2 acc;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc.add(partial[(int64_t)blockIdx.x * nb + i]);
+  const double* pp = partial + (int64_t)blockIdx.x * nb;
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * blockDim.x) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * (int)blockDim.x;
+      v[u] = i < nb ? pp[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc.add(v[u]);     // adding an exact zero leaves (s, c) unchanged
+  }
   double s = block_sum2(acc);
   if (threadIdx.x == 0) sc[base + blockIdx.x] = s;
 }
