@@ -13,6 +13,7 @@
 #include <thread>
 #include <map>
 #include <mutex>
+#include <set>
 #include <tuple>
 
 // Kernels come from the other sources of the same translation unit (esmp2_all.hip).
@@ -172,6 +173,29 @@ static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs
 // Eigenpairs of a symmetric m x m matrix A (device, contiguous) by the
 // tridiagonal route of the AVO step: evals ascending, Y[i*m + k] = component i
 // of eigenvector k.  Scratch ws: 2 m^2 + 3 m doubles (m <= TRI_MAX).
+// Raise a kernel's dynamic-LDS limit to what the device allows, once per
+// process and device, before its first launch.  The limit is process-wide
+// state of the function: setting it per launch, with sizes that differ
+// between the host threads of a batched solve, would race with their launches.
+static hipError_t allow_device_lds(const void* fn) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count({fn, dev})) return hipSuccess;
+  int per_block = 0;
+  if ((e = hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+  hipFuncAttributes fa{};
+  if ((e = hipFuncGetAttributes(&fa, fn)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, per_block - (int)fa.sharedSizeBytes)) !=
+      hipSuccess)
+    return e;
+  done.insert({fn, dev});
+  return hipSuccess;
+}
+
 static esmp2_status sym_eig(esmp2_handle h, hipStream_t s, const double* A, int m, double* evals, double* Y,
                             double* ws) {
   if (m <= 0) return ESMP2_OK;
@@ -184,7 +208,7 @@ static esmp2_status sym_eig(esmp2_handle h, hipStream_t s, const double* A, int 
   }
   if (m > TRI_MAX) return fail(h, ESMP2_UNSUPPORTED, "eigenproblem order beyond the tridiagonal solver's limit");
   size_t lt = sizeof(double) * (size_t)m * (m + 1) / 2;
-  ESMP2_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lt));
+  ESMP2_HIP(allow_device_lds((const void*)k_tridiag));
   hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), lt, s, A, m, refl, vec, vec + m, vec + 2 * m);
   hipLaunchKernelGGL(k_tri_eig, dim3(m), dim3(64), 0, s, vec + m, vec + 2 * m, m, evals, Zt);
   hipLaunchKernelGGL(k_cluster_mgs, dim3(1), dim3(64), 0, s, evals, m, Zt);
@@ -477,7 +501,7 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   if (!h->top_given) {
     // SVD of C
     size_t lds = sizeof(double) * (no * nv + no * no);
-    ESMP2_HIP(hipFuncSetAttribute((const void*)k_svd_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ESMP2_HIP(allow_device_lds((const void*)k_svd_jacobi));
     hipLaunchKernelGGL(k_svd_jacobi, dim3(1), dim3(1024), lds, s, h->C, no, nv, h->lam, h->U, h->V, h->iinfo);
     // semicanonical AVOs: complement of the TOP virtuals, F restricted to it,
     // tridiagonal eigensolver, back-transformation, Loewdin re-orthonormalisation
@@ -492,7 +516,7 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
       double* AV2 = AV + (size_t)nv * nv;                 // nv x m  (rs holds 11 nv^2)
       size_t lc = sizeof(double) * 2 * (size_t)nv * no;
       if (m > 0) {   // n_vir == n_occ: no AVOs
-      ESMP2_HIP(hipFuncSetAttribute((const void*)k_complement_qr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc));
+      ESMP2_HIP(allow_device_lds((const void*)k_complement_qr));
       hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), lc, s, (const double*)h->V, nv, no, refl);
       if (m > 0) hipLaunchKernelGGL(k_complement_apply, dim3(m), dim3(64), 0, s, (const double*)refl, nv, no, Q2);
       GemmArgs g{};
@@ -834,7 +858,7 @@ static esmp2_status sigma_t(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T
       int nt = (nbat[k] > 0 && inner[k] > 0) ? (inner[k] + GO - 1) / GO : 0;
       pre[k + 1] = pre[k] + nt;
     }
-    ESMP2_HIP(hipFuncSetAttribute((const void*)k_oo<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_oo));
+    ESMP2_HIP(allow_device_lds((const void*)k_oo<T>));
     hipLaunchKernelGGL(k_oo<T>, dim3(pre[7]), dim3(256), lds_oo, s, ga, make_int4(pre[1], pre[2], pre[3], pre[4]),
                        make_int4(pre[5], pre[6], pre[7], 0));
   } else {
