@@ -73,7 +73,7 @@ def main():
 
     def step(precision=P.ESMP2_FP64, basis=P.ESMP2_BASIS_TOP):
         h.rotate_top(lam_out=False)
-        h.build_rhs()
+        h.build_rhs(e2_s=False)
         return h.solve(tol=args.tol, max_iter=300, precision=precision, basis=basis)
 
     def timed(precision, basis):
@@ -167,7 +167,7 @@ def main():
         t0 = time.perf_counter()
         for hh in hs:
             hh.rotate_top(lam_out=False)
-            hh.build_rhs()
+            hh.build_rhs(e2_s=False)
             hh.solve(tol=args.tol, max_iter=300, basis=P.ESMP2_BASIS_SEMICANONICAL)
         torch.cuda.synchronize()
         seq_ms = 1e3 * (time.perf_counter() - t0)

@@ -171,7 +171,10 @@ esmp2_status esmp2_space(esmp2_handle h, int64_t* n_amp, int64_t* box_offsets);
 /* Right-hand side b_mu = <mu|H|Psi0> on the seven boxes, E0 and the
  * S-triple energy E2_S = -sum_S b^2/D (paper Sec. II.B-II.D).
  *   b_out: device, n_amp doubles, or NULL (b is kept in the handle either way)
- *   e0, e2_s: host scalars or NULL (non-NULL synchronises the stream).
+ *   e0, e2_s: host scalars or NULL.  The call synchronises the stream (the
+ *   denominator check).  E2_S is summed on the handle's side stream, beside
+ *   the solve that follows; a non-NULL e2_s waits for it, with NULL it is
+ *   waited for only by esmp2_solve, whose result reports it.
  * Returns ESMP2_NOT_SPD if a denominator of the first-order space is <= 0. */
 esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* e2_s);
 

@@ -138,10 +138,12 @@ class Handle:
         self._check(lib.esmp2_space(self.h, C.byref(n), offs))
         return n.value, list(offs)
 
-    def build_rhs(self, b_out=None):
+    def build_rhs(self, b_out=None, e2_s=True):
+        """Returns (E0, E2_S).  With e2_s=False the S-triple energy is not waited
+        for (it is computed beside the solve and reported in its result): (E0, None)."""
         e0, e2s = C.c_double(), C.c_double()
-        self._check(lib.esmp2_build_rhs(self.h, _ptr(b_out), C.byref(e0), C.byref(e2s)))
-        return e0.value, e2s.value
+        self._check(lib.esmp2_build_rhs(self.h, _ptr(b_out), C.byref(e0), C.byref(e2s) if e2_s else None))
+        return e0.value, (e2s.value if e2_s else None)
 
     def sigma(self, x, y, precision=ESMP2_FP64):
         return self._check(lib.esmp2_sigma(self.h, _ptr(x), _ptr(y), precision))

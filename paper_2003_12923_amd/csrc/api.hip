@@ -20,6 +20,8 @@
 
 using namespace esmp2;
 
+static constexpr int E2S_CAP = 3 * 1024;   // E2_S partial sums: three grids of at most 1024 workgroups
+
 // ---------------------------------------------------------------------------
 // small helper kernels local to the orchestration
 // ---------------------------------------------------------------------------
@@ -111,6 +113,12 @@ struct esmp2_handle_ {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fock_ready = nullptr, ev_sc_eig = nullptr;
   bool sc_pending = false;       // eigenproblems queued on the side stream, not yet joined
+  // E2_S (S-triples, inverted directly) also runs on the side stream, beside the
+  // solve: partials, then the sum at e2s_part[E2S_CAP]
+  double* e2s_part = nullptr;
+  hipEvent_t ev_rhs_ready = nullptr, ev_e2s = nullptr;
+  bool e2s_pending = false;      // queued on the side stream, not yet joined by the main stream
+  bool e2s_dev = false;          // the sum is on the device, not yet read into e2s
   bool sc_eig = false;           // To, Tv hold the rotation of the current TOP basis
   double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *dinv_sc, *b_sc;
   float *Fd32_sc, *Fl32_sc, *fo32_sc, *fv32_sc, *fov32_sc, *dinv32_sc;
@@ -154,8 +162,25 @@ static void release(esmp2_handle h) {
   h->have_sc = false;
   h->sc_pending = false;
   h->sc_eig = false;
+  h->e2s_pending = false;
+  h->e2s_dev = false;
   h->gws = nullptr;
   h->gws_n = 0;
+}
+
+// The main stream waits for E2_S queued on the side stream; with read, its
+// value is also copied into h->e2s (a synchronous point).
+static esmp2_status join_e2s(esmp2_handle h, bool read) {
+  if (h->e2s_pending) {
+    ESMP2_HIP(hipStreamWaitEvent(h->stream, h->ev_e2s, 0));
+    h->e2s_pending = false;
+  }
+  if (read && h->e2s_dev) {
+    ESMP2_HIP(hipMemcpyAsync(&h->e2s, h->e2s_part + E2S_CAP, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    ESMP2_HIP(hipStreamSynchronize(h->stream));
+    h->e2s_dev = false;
+  }
+  return ESMP2_OK;
 }
 
 template <class T>
@@ -259,10 +284,14 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
   h->stream = (hipStream_t)stream;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_fock_ready, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_sc_eig, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->ev_sc_eig, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_rhs_ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_e2s, hipEventDisableTiming) != hipSuccess) {
     if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->ev_fock_ready) (void)hipEventDestroy(h->ev_fock_ready);
     if (h->ev_sc_eig) (void)hipEventDestroy(h->ev_sc_eig);
+    if (h->ev_rhs_ready) (void)hipEventDestroy(h->ev_rhs_ready);
+    if (h->ev_e2s) (void)hipEventDestroy(h->ev_e2s);
     delete h;
     return ESMP2_HIP_ERROR;
   }
@@ -280,6 +309,8 @@ esmp2_status esmp2_destroy(esmp2_handle h) {
   (void)hipStreamDestroy(h->aux);
   (void)hipEventDestroy(h->ev_fock_ready);
   (void)hipEventDestroy(h->ev_sc_eig);
+  (void)hipEventDestroy(h->ev_rhs_ready);
+  (void)hipEventDestroy(h->ev_e2s);
   delete h;
   return ESMP2_OK;
 }
@@ -349,6 +380,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
             dalloc(h, &h->Mint, (size_t)no * nv * no * nv) && dalloc(h, &h->b, namp) &&
             dalloc(h, &h->dinv, namp) && dalloc(h, &h->blockmin, nblk(namp)) &&
             dalloc(h, &h->partial, (size_t)4 * PCG_BLOCKS) && dalloc(h, &h->sc, SC_N) &&
+            dalloc(h, &h->e2s_part, (size_t)E2S_CAP + 1) &&
             dalloc(h, &h->S, (size_t)no * no * nv * nv) &&
             dalloc(h, &h->side, (size_t)nv * (3 * d.npo1 + 2 * d.npo + 3 * d.npo + 5 * (no - 1) * (no - 1))) &&
             dalloc(h, &h->side_tr, (size_t)nv * (d.npo + (no - 1) * (no - 1))) &&
@@ -491,7 +523,12 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, n = d.n, na = d.naux, mv = d.mv;
   hipStream_t s = h->stream;
-  // side-stream work of a previous rotation shares the scratch: order after it
+  // side-stream work of a previous rotation shares the scratch, and E2_S reads
+  // what the rotation rewrites: order after both
+  {
+    const esmp2_status st = join_e2s(h, false);
+    if (st != ESMP2_OK) return st;
+  }
   if (h->sc_pending) {
     ESMP2_HIP(hipStreamWaitEvent(s, h->ev_sc_eig, 0));
     h->sc_pending = false;
@@ -641,6 +678,10 @@ esmp2_status esmp2_space(esmp2_handle h, int64_t* n_amp, int64_t* box_offsets) {
 }
 
 static esmp2_status build_rhs(esmp2_handle h) {
+  {
+    const esmp2_status st = join_e2s(h, false);   // the previous E2_S still reads Vint and e2s_part
+    if (st != ESMP2_OK) return st;
+  }
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
   const int64_t namp = d.off[7];
@@ -668,25 +709,33 @@ static esmp2_status build_rhs(esmp2_handle h) {
   hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
   h->dinv32_ok = false;
   hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
-  // E2_S
-  // grids of at most 1024 blocks each; partials laid out one kernel after the other
+  // E2_S on the side stream (after the eigenproblems queued there), beside the
+  // solve: it reads Vint, lam, eo, ev, omega and the pair tables, which the
+  // next rotation or right-hand side rewrites only after joining it.  Grids of
+  // at most 1024 blocks each; partials laid out one kernel after the other.
+  ESMP2_HIP(hipEventRecord(h->ev_rhs_ready, s));
+  ESMP2_HIP(hipStreamWaitEvent(h->aux, h->ev_rhs_ready, 0));
   const int* pv = h->pairs;
-  E2sArgs ea{d, h->Vint, h->lam, h->eo, h->ev, h->omega, h->partial, pv, pv + d.npv, pv + d.npv + d.npv1,
+  E2sArgs ea{d, h->Vint, h->lam, h->eo, h->ev, h->omega, h->e2s_part, pv, pv + d.npv, pv + d.npv + d.npv1,
              pv + d.npv + d.npv1 + d.npo};
   const int y1 = std::max(1, no - 1), x1 = std::max(1, 1024 / y1);
   const int y3 = std::min(1024, no * nv), x3 = std::max(1, 1024 / y3);
   const int nb1 = x1 * y1, nb3 = x3 * y3;
-  hipLaunchKernelGGL(k_e2s_same, dim3(x1, y1), dim3(256), 0, s, ea);
-  ea.partial = h->partial + nb1;
-  hipLaunchKernelGGL(k_e2s_mixed_a, dim3(x1, y1), dim3(256), 0, s, ea);
-  ea.partial = h->partial + 2 * nb1;
-  hipLaunchKernelGGL(k_e2s_mixed_b, dim3(x3, y3), dim3(256), 0, s, ea);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, h->partial, 2 * nb1 + nb3, h->sc + SC_TMP + 1, -1.0);
-  double tmp[2];
-  ESMP2_HIP(hipMemcpyAsync(tmp, h->sc + SC_TMP, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (2 * nb1 + nb3 > E2S_CAP) return fail(h, ESMP2_HIP_ERROR, "internal: E2_S partials beyond their buffer");
+  hipLaunchKernelGGL(k_e2s_same, dim3(x1, y1), dim3(256), 0, h->aux, ea);
+  ea.partial = h->e2s_part + nb1;
+  hipLaunchKernelGGL(k_e2s_mixed_a, dim3(x1, y1), dim3(256), 0, h->aux, ea);
+  ea.partial = h->e2s_part + 2 * nb1;
+  hipLaunchKernelGGL(k_e2s_mixed_b, dim3(x3, y3), dim3(256), 0, h->aux, ea);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, h->aux, (const double*)h->e2s_part, 2 * nb1 + nb3,
+                     h->e2s_part + E2S_CAP, -1.0);
+  ESMP2_HIP(hipEventRecord(h->ev_e2s, h->aux));
+  h->e2s_pending = true;
+  h->e2s_dev = true;
+  double tmp[1];
+  ESMP2_HIP(hipMemcpyAsync(tmp, h->sc + SC_TMP, sizeof(double), hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
   ESMP2_HIP(hipGetLastError());
-  h->e2s = tmp[1];
   if (!(tmp[0] > 0.0)) return fail(h, ESMP2_NOT_SPD, "a diagonal denominator of the first-order space is <= 0");
   h->have_rhs = true;
   h->have_sc = false;
@@ -703,7 +752,11 @@ esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* 
   if (b_out)
     ESMP2_HIP(hipMemcpyAsync(b_out, h->b, sizeof(double) * h->d.off[7], hipMemcpyDeviceToDevice, h->stream));
   if (e0) *e0 = h->e0;
-  if (e2_s) *e2_s = h->e2s;
+  if (e2_s) {
+    st = join_e2s(h, true);
+    if (st != ESMP2_OK) return st;
+    *e2_s = h->e2s;
+  }
   return ESMP2_OK;
 }
 
@@ -1162,6 +1215,10 @@ static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_sol
                                  esmp2_solve_result* res, double rel, int it, int outer, esmp2_status status) {
   const int64_t n = h->d.off[7];
   hipStream_t s = h->stream;
+  {
+    const esmp2_status st = join_e2s(h, true);
+    if (st != ESMP2_OK) return st;
+  }
   double hs[SC_N];
   wdot(h, c.b, (const double*)h->x, SC_BX);
   wdot(h, (const double*)h->x, (const double*)h->r, SC_XR);

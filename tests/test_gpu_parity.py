@@ -157,3 +157,29 @@ def test_e2_workloads(lib, name):
     xs = xo.cpu().numpy()[idx]
     assert np.abs(xs - np.array(g["x_sample"])).max() <= 1e-8 * np.abs(g["x_sample"]).max()
     h.close()
+
+
+@pytest.mark.parametrize("name", ["c5", "c2"])
+def test_e2s_deferred_to_the_solve(lib, name):
+    """E2_S is summed on the side stream beside the solve: without waiting for
+    it in build_rhs, the solve's result still carries the oracle's E2_S and E2,
+    in both bases and over repeated rotate / right-hand side / solve steps."""
+    g = GOLD[name]
+    prob = synth.config_problem(name)
+    h = _handle(lib, prob)
+    for rep in range(3):
+        for basis in (lib.ESMP2_BASIS_TOP, lib.ESMP2_BASIS_SEMICANONICAL):
+            print(f"[{name}] deferred E2_S rep {rep} basis {basis}", flush=True)
+            h.rotate_top(lam_out=False)
+            e0, none = h.build_rhs(e2_s=False)
+            assert none is None and abs(e0 - g["e0"]) < 1e-11
+            res = h.solve(tol=1e-10, max_iter=300, basis=basis)
+            assert res["status"] == 0
+            assert abs(res["e2_s"] - g["e2_s"]) < 1e-10
+            assert abs(res["e2"] - g["e2"]) < 1e-10
+    # and the value asked for directly after a deferred one
+    h.rotate_top(lam_out=False)
+    h.build_rhs(e2_s=False)
+    _, e2s = h.build_rhs()
+    assert abs(e2s - g["e2_s"]) < 1e-10
+    h.close()
