@@ -353,7 +353,6 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
   for (int r = 0; r < m; ++r)
     for (int c = r + tid; c < m; c += blockDim.x) A[pk(r, c, m)] = Ain[r * m + c];
   __syncthreads();
-  auto at = [&](int r, int c) -> double { return r <= c ? A[pk(r, c, m)] : A[pk(c, r, m)]; };
   for (int k = 0; k < m - 2; ++k) {
     // reflector scalars, in every wavefront (same reduction order everywhere)
     double s = 0.0;
@@ -367,17 +366,24 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
       v0 = x0 - alpha;
       b = 2.0 / (v0 * v0 + sig);
     }
-    // v_i = v0 (i = k+1), A[k][i] (i > k+1); zero when the row is already reduced
-    auto vv = [&](int i) -> double { return b > 0.0 ? (i == k + 1 ? v0 : A[pk(k, i, m)]) : 0.0; };
+    // v_i = v0 (i = k+1), A[k][i] (i > k+1); zero when the row is already reduced.
+    // Row r of the packed matrix starts at pk(r, r): A[r][c] = A[pk(r, r) - r + c].
+    const int rk = pk(k, k, m) - k;
+    auto vv = [&](int i) -> double { return b > 0.0 ? (i == k + 1 ? v0 : A[rk + i]) : 0.0; };
     for (int i = k + 1 + tid; i < m; i += blockDim.x) refl[k * m + i] = vv(i);
     if (tid == 0) { rbeta[k] = b; e[k] = alpha; }
     if (b > 0.0) {
-      // p = b A22 v : 8 threads per row
+      // p = b A22 v : 8 threads per row, thread `part` over j = k+1+part, k+9+part, ...
+      // in increasing order: below the diagonal from column i of the rows above,
+      // then along row i (no per-element test of which triangle holds A[i][j])
       const int len = m - k - 1;
       for (int t = tid; t < len * 8; t += blockDim.x) {
         const int i = k + 1 + t / 8, part = t % 8;
         double acc = 0.0;
-        for (int j = k + 1 + part; j < m; j += 8) acc += at(i, j) * vv(j);
+        int j = k + 1 + part;
+        for (; j < i; j += 8) acc += A[pk(j, j, m) - j + i] * vv(j);
+        const int ri = pk(i, i, m) - i;
+        for (; j < m; j += 8) acc += A[ri + j] * vv(j);
         acc += __shfl_xor(acc, 1);
         acc += __shfl_xor(acc, 2);
         acc += __shfl_xor(acc, 4);
@@ -390,9 +396,10 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
       // A22 -= v w^T + w v^T (upper part), w = p - K v
       for (int i = k + 1 + wave; i < m; i += nw) {
         const double vi = vv(i), wi = p[i] - K * vi;
+        const int ri = pk(i, i, m) - i;
         for (int j = i + l; j < m; j += 64) {
           const double vj = vv(j);
-          A[pk(i, j, m)] -= vi * (p[j] - K * vj) + wi * vj;
+          A[ri + j] -= vi * (p[j] - K * vj) + wi * vj;
         }
       }
     }
