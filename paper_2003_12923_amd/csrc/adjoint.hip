@@ -134,19 +134,12 @@ struct RhsAdjArgs {
   double* Gf;     // dE/df^Phi[j][b]
 };
 
-__device__ inline int box_of_adj(const Dims& d, int64_t g, int64_t& loc) {
-  int k = 0;
-  while (k < 6 && g >= d.off[k + 1]) ++k;
-  loc = g - d.off[k];
-  return k;
-}
-
 __global__ void k_rhs_adj(RhsAdjArgs A) {
   const Dims& d = A.d;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= d.off[7]) return;
-  int64_t loc;
-  const int box = box_of_adj(d, g, loc);
+  int loc;
+  const int box = box_of(d, g, loc);        // 32-bit local index (a box holds < 2^31 amplitudes)
   const int no = d.no, nv = d.nv, nov = no * nv;
   const double s2 = 0.70710678118654752440;
   auto c = [&](int l) -> double { return A.lam[l] * s2; };

@@ -92,11 +92,13 @@ struct RhsArgs {
   double* b;
 };
 
-// Box and local index of a flat amplitude index.
-__device__ inline int box_of(const Dims& d, int64_t g, int64_t& loc) {
+// Box and local index of a flat amplitude index.  A box holds fewer than 2^31
+// amplitudes (at most 64^2 x 192^2), so the local index and the index
+// arithmetic on it are 32-bit (a 64-bit division is a long software sequence).
+__device__ inline int box_of(const Dims& d, int64_t g, int& loc) {
   int k = 0;
   while (k < 6 && g >= d.off[k + 1]) ++k;
-  loc = g - d.off[k];
+  loc = (int)(g - d.off[k]);
   return k;
 }
 
@@ -104,7 +106,7 @@ __global__ void k_rhs(RhsArgs A) {
   const Dims& d = A.d;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= d.off[7]) return;
-  int64_t loc;
+  int loc;
   int box = box_of(d, g, loc);
   const int no = d.no, nv = d.nv, nov = no * nv;
   const double s2 = 0.70710678118654752440;
@@ -205,7 +207,7 @@ struct DiagArgs {
   double* blockmin;
 };
 
-__device__ inline double diag_of(const Dims& d, int box, int64_t loc, const double* eo, const double* ev,
+__device__ inline double diag_of(const Dims& d, int box, int loc, const double* eo, const double* ev,
                                  double om) {
   const int no = d.no, nv = d.nv;
   const double base = ev[0] - eo[0] - om;
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(256) void k_diag(DiagArgs A) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double mn = 1e300;
   if (g < A.d.off[7]) {
-    int64_t loc;
+    int loc;
     int box = box_of(A.d, g, loc);
     double D = diag_of(A.d, box, loc, A.eo, A.ev, A.omega);
     A.dinv[g] = 1.0 / D;
