@@ -17,7 +17,7 @@ value = H0-sigma GFLOP/s of the paper's operator (the TOP-basis sigma, all
 its kernels, FP64): algorithmic sigma flops / sigma time, timed with HIP events
 on the library's stream.  The roofline object covers its dominant kernel (the
 virtual-pair Sylvester kernel on the FP64 matrix cores), timed with HIP events
-around each launch.  cpu_baseline times the CPU oracle's sigma on the same
+around each of its launches in sigma applications of their own.  cpu_baseline times the CPU oracle's sigma on the same
 workload.
 """
 import argparse
@@ -89,7 +89,6 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    h.profile(True)
     n_sigma = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -98,7 +97,6 @@ def main():
         n_sigma += res["iterations"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    vv_ms, vv_n = h.profile(False)[P.ESMP2_FP64]
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
     value = n_sigma * sig_flops / wall / 1e9
@@ -107,13 +105,11 @@ def main():
     for _ in range(args.warmup):
         step(P.ESMP2_FP32)
     torch.cuda.synchronize()
-    h.profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res_m = step(P.ESMP2_FP32)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    vv32_ms, vv32_n = h.profile(False)[P.ESMP2_FP32]
     mixed_ms = 1e3 * (t1 - t0) / args.steps
 
     # the same steps refined around the BF16 operator (TOP basis: BF16 operands
@@ -121,13 +117,11 @@ def main():
     for _ in range(args.warmup):
         step(P.ESMP2_BF16)
     torch.cuda.synchronize()
-    h.profile(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res_b = step(P.ESMP2_BF16)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    vvb_ms, vvb_n = h.profile(False)[P.ESMP2_BF16]
     bf16_ms = 1e3 * (t1 - t0) / args.steps
 
     # the same solves in the pinned-semicanonical basis
@@ -153,6 +147,21 @@ def main():
     sigma_ms = time_sigma(x, P.ESMP2_FP64)
     sigma32_ms = time_sigma(x.float(), P.ESMP2_FP32)
     sigmab_ms = time_sigma(x.float(), P.ESMP2_BF16)
+
+    # the Sylvester kernel alone: HIP events on the library's stream around each
+    # of its launches in 20 more sigma applications per precision (nothing runs
+    # beside them; inside a solve the S-triple sum may share the GPU)
+    def profile_vv(xv, precision, reps=20):
+        y = torch.empty_like(xv)
+        h.profile(True)
+        for _ in range(reps):
+            h.sigma(xv, y, precision)
+        torch.cuda.synchronize()
+        return h.profile(False)[precision]
+
+    vv_ms, vv_n = profile_vv(x, P.ESMP2_FP64)
+    vv32_ms, vv32_n = profile_vv(x.float(), P.ESMP2_FP32)
+    vvb_ms, vvb_n = profile_vv(x.float(), P.ESMP2_BF16)
 
     # the batched workload: 32 independent states of uneven size, one handle and one
     # stream each, solved together (pinned-semicanonical basis, FP64)
