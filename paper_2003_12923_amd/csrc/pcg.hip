@@ -11,13 +11,33 @@ namespace esmp2 {
 
 __device__ inline double wgt(int64_t g, int64_t s0, int64_t s1) { return (g >= s0 && g < s1) ? 1.0 : 2.0; }
 
+// Grid-stride vector kernels take PCG_U elements per thread per round (g,
+// g + stride, ...; the same order as a plain grid-stride loop, so the same
+// sums): all loads of a round are issued before its first store, which the
+// compiler cannot do across the stores of a plain loop (the vectors may alias
+// as far as it knows), and their latencies overlap.
+constexpr int PCG_U = 4;
+
 // partial[block] = sum_g w_g x_g y_g   (grid-stride, fixed grid -> deterministic)
 template <class T>
 __global__ __launch_bounds__(256) void k_dot(const T* x, const T* y, int64_t n, int64_t s0, int64_t s1,
                                              double* partial) {
   Acc2 acc;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
-    acc.add(wgt(g, s0, s1) * (double)x[g] * (double)y[g]);
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    T xv[PCG_U], yv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      xv[u] = x[gg];
+      yv[u] = y[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) acc.add(wgt(g, s0, s1) * (double)xv[u] * (double)yv[u]);
+    }
+  }
   double s = block_sum2(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -50,13 +70,26 @@ __global__ __launch_bounds__(256) void k_update_xr(T* x, T* r, const T* p, const
                                                    int64_t s0, int64_t s1, const double* sc, double* partial) {
   const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
   double rz = 0.0, rr = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-    const T rg = r[g] - alpha * q[g];
-    x[g] += alpha * p[g];
-    r[g] = rg;
-    const double w = wgt(g, s0, s1), rd = (double)rg;
-    rz += w * rd * rd * (double)dinv[g];
-    rr += w * rd * rd;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    T xv[PCG_U], rv[PCG_U], pv[PCG_U], qv[PCG_U], dv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      xv[u] = x[gg]; rv[u] = r[gg]; pv[u] = p[gg]; qv[u] = q[gg]; dv[u] = dinv[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) {
+        const T rg = rv[u] - alpha * qv[u];
+        x[g] = xv[u] + alpha * pv[u];
+        r[g] = rg;
+        const double w = wgt(g, s0, s1), rd = (double)rg;
+        rz += w * rd * rd * (double)dv[u];
+        rr += w * rd * rd;
+      }
+    }
   }
   double a = block_sum(rz);
   double b = block_sum(rr);
@@ -67,8 +100,20 @@ __global__ __launch_bounds__(256) void k_update_xr(T* x, T* r, const T* p, const
 template <class T>
 __global__ __launch_bounds__(256) void k_update_p(T* p, const T* r, const T* dinv, int64_t n, const double* sc) {
   const T beta = (T)(sc[SC_RHO_NEW] / sc[SC_RHO]);
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
-    p[g] = dinv[g] * r[g] + beta * p[g];
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    T pv[PCG_U], rv[PCG_U], dv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      pv[u] = p[gg]; rv[u] = r[gg]; dv[u] = dinv[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) p[g] = dv[u] * rv[u] + beta * pv[u];
+    }
+  }
 }
 
 __global__ void k_roll_rho(double* sc) {
