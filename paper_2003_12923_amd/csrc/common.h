@@ -65,9 +65,10 @@ __host__ __device__ inline int tri_idx(int p, int q, int m) {
 
 // Inverse of tri_idx: packed index -> (p,q).
 __device__ inline void tri_pq(int idx, int m, int& p, int& q) {
-  // p is the largest row with start(p) <= idx, start(p) = p*m - p(p+1)/2
-  double mm = 2.0 * m - 1.0;
-  int pp = (int)floor((mm - sqrt(mm * mm - 8.0 * (double)idx)) * 0.5);
+  // p is the largest row with start(p) <= idx, start(p) = p*m - p(p+1)/2; a
+  // single-precision estimate from the quadratic, made exact by the two loops
+  const float mm = 2.0f * m - 1.0f;
+  int pp = (int)floorf((mm - sqrtf(fmaxf(mm * mm - 8.0f * (float)idx, 0.0f))) * 0.5f);
   if (pp < 0) pp = 0;
   while (pp > 0 && pp * m - pp * (pp + 1) / 2 > idx) --pp;
   while ((pp + 1) * m - (pp + 1) * (pp + 2) / 2 <= idx) ++pp;
