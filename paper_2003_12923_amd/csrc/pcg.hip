@@ -125,13 +125,26 @@ __global__ __launch_bounds__(256) void k_init(const double* b, const double* y, 
                                               const double* dinv, int64_t n, int64_t s0, int64_t s1,
                                               double* partial) {
   double rz = 0.0, rr = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-    double rg = -b[g] - (y ? y[g] : 0.0);
-    r[g] = rg;
-    p[g] = dinv[g] * rg;
-    double w = wgt(g, s0, s1);
-    rz += w * rg * rg * dinv[g];
-    rr += w * rg * rg;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    double bv[PCG_U], yv[PCG_U], dv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      bv[u] = b[gg]; yv[u] = y ? y[gg] : 0.0; dv[u] = dinv[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) {
+        const double rg = -bv[u] - yv[u];
+        r[g] = rg;
+        p[g] = dv[u] * rg;
+        const double w = wgt(g, s0, s1);
+        rz += w * rg * rg * dv[u];
+        rr += w * rg * rg;
+      }
+    }
   }
   double a = block_sum(rz);
   double c = block_sum(rr);
@@ -142,10 +155,23 @@ __global__ __launch_bounds__(256) void k_init(const double* b, const double* y, 
 __global__ __launch_bounds__(256) void k_resid(const double* b, const double* y, double* r, int64_t n, int64_t s0,
                                                int64_t s1, double* partial) {
   Acc2 acc;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-    const double rg = -b[g] - (y ? y[g] : 0.0);
-    r[g] = rg;
-    acc.add(wgt(g, s0, s1) * rg * rg);
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    double bv[PCG_U], yv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      bv[u] = b[gg]; yv[u] = y ? y[gg] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) {
+        const double rg = -bv[u] - yv[u];
+        r[g] = rg;
+        acc.add(wgt(g, s0, s1) * rg * rg);
+      }
+    }
   }
   double s = block_sum2(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -158,14 +184,28 @@ __global__ __launch_bounds__(256) void k_init_inner(const double* r64, double sc
                                                     double* partial) {
   const double inv = 1.0 / scale;
   double rz = 0.0, rr = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-    const float rg = (float)(r64[g] * inv);
-    r[g] = rg;
-    d[g] = 0.f;
-    p[g] = dinv[g] * rg;
-    const double w = wgt(g, s0, s1), rd = (double)rg;
-    rz += w * rd * rd * (double)dinv[g];
-    rr += w * rd * rd;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    double rv[PCG_U];
+    float dv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      rv[u] = r64[gg]; dv[u] = dinv[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) {
+        const float rg = (float)(rv[u] * inv);
+        r[g] = rg;
+        d[g] = 0.f;
+        p[g] = dv[u] * rg;
+        const double w = wgt(g, s0, s1), rd = (double)rg;
+        rz += w * rd * rd * (double)dv[u];
+        rr += w * rd * rd;
+      }
+    }
   }
   double a = block_sum(rz);
   double c = block_sum(rr);
@@ -175,8 +215,21 @@ __global__ __launch_bounds__(256) void k_init_inner(const double* r64, double sc
 // x += scale d, the refinement update in FP64
 __global__ __launch_bounds__(256) void k_refine(double* x, const float* d, double scale, int64_t n) {
   const double s = scale;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
-    x[g] += s * (double)d[g];
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    double xv[PCG_U];
+    float dv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      xv[u] = x[gg]; dv[u] = d[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) x[g] = xv[u] + s * (double)dv[u];
+    }
+  }
 }
 
 // b = fl32(a), round to nearest
