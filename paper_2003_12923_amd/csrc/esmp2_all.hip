@@ -1,9 +1,8 @@
-// Single translation unit of libesmp2.
+// Translation unit of libesmp2 holding everything but the Sylvester kernels,
+// whose instantiations (vv3.hip, vv3b.hip) are compiled as objects of their own.
 #include "linalg.hip"
 #include "rhs.hip"
 #include "sigma.hip"
-#include "vv3.hip"
-#include "vv3b.hip"
 #include "pcg.hip"
 #include "semican.hip"
 #include "arrow.hip"

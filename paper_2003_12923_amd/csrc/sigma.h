@@ -74,6 +74,7 @@ inline int64_t sym_s2_blocks(const Dims& d) {
   return (int64_t)d.no * d.no * nt * nt;
 }
 template <class T, int TW> __global__ void k_vv(VVArgs<T> A);
+constexpr int V3_THREADS = 512;   // workgroup of the specialised Sylvester kernels: 8 wavefronts
 template <class T, int NT> __global__ void k_vv3(VVArgs<T> A);
 template <int NT> __global__ void k_vv3b(VVArgs<float> A);
 template <class T> __global__ void k_side(SideArgs<T> A);

@@ -85,8 +85,6 @@ __device__ inline void y3(const V3Ctx<T>& c, int r, int col, T val, bool diag_ti
   }
 }
 
-constexpr int V3_THREADS = 512;
-
 // Output tiles of one batch matrix dealt to the 8 wavefronts (wavefront w runs
 // on SIMD w % 4).  A single wavefront keeps the FP64 matrix core busy only
 // about 40 % of the time, two interleaved ones about 90 %, so both

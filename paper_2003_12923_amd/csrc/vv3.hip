@@ -203,11 +203,10 @@ __global__ __launch_bounds__(V3_THREADS, 1) void k_vv3(VVArgs<T> A) {
   }
 }
 
-template __global__ void k_vv3<double, 10>(VVArgs<double>);
-template __global__ void k_vv3<double, 7>(VVArgs<double>);
-template __global__ void k_vv3<double, 5>(VVArgs<double>);
-template __global__ void k_vv3<float, 10>(VVArgs<float>);
-template __global__ void k_vv3<float, 7>(VVArgs<float>);
-template __global__ void k_vv3<float, 5>(VVArgs<float>);
+// One instantiation per object file (the build compiles this source once per
+// (type, NT) pair, in parallel): ESMP2_VV3_T and ESMP2_VV3_NT select it.
+#if defined(ESMP2_VV3_T) && defined(ESMP2_VV3_NT)
+template __global__ void k_vv3<ESMP2_VV3_T, ESMP2_VV3_NT>(VVArgs<ESMP2_VV3_T>);
+#endif
 
 }  // namespace esmp2

@@ -196,8 +196,9 @@ __global__ __launch_bounds__(V3_THREADS, 1) void k_vv3b(VVArgs<float> A) {
   }
 }
 
-template __global__ void k_vv3b<10>(VVArgs<float>);
-template __global__ void k_vv3b<7>(VVArgs<float>);
-template __global__ void k_vv3b<5>(VVArgs<float>);
+// One instantiation per object file, selected by ESMP2_VV3_NT (see vv3.hip).
+#if defined(ESMP2_VV3_NT)
+template __global__ void k_vv3b<ESMP2_VV3_NT>(VVArgs<float>);
+#endif
 
 }  // namespace esmp2
