@@ -185,6 +185,49 @@ esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* 
  *   virtual dimension is 80, 112 or 160. */
 esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision);
 
+/* y = (H0 - E0) x in a chosen basis of the first-order space (paper Sec. II.C;
+ * doubles + L-triples are mapped onto themselves by every rotation of the
+ * occupied orbitals other than t and of the virtuals other than t', Sec. II.B).
+ *   basis = ESMP2_BASIS_TOP: esmp2_sigma.
+ *   basis = ESMP2_BASIS_SEMICANONICAL: x and y are amplitudes of the pinned-
+ *     semicanonical basis: occupied orbitals 1.. rotated by the eigenvectors of
+ *     F~_oo[1:,1:] and virtuals 1.. by those of F~_vv[1:,1:] (t and t' fixed;
+ *     eigenvalues ascending, each eigenvector signed so that its largest-
+ *     magnitude component is positive; new orbital P' = sum_P T[P][P'] P).  In
+ *     that basis the two Fock blocks are diagonal and the operator is applied
+ *     by the O(n_occ^2 n_vir^2) arrow kernels; its diagonal constants omega and
+ *     kappa stay those of the TOP basis.  The first such call after
+ *     esmp2_rotate_top builds the rotation and the operator blocks.
+ *   x, y: device, n_amp elements (double for ESMP2_FP64, float for ESMP2_FP32;
+ *   ESMP2_BF16 is ESMP2_UNSUPPORTED in the semicanonical basis), not
+ *   overlapping.  Requires esmp2_rotate_top.  Queued on the handle's stream. */
+esmp2_status esmp2_sigma_basis(esmp2_handle h, const void* x, void* y, int precision, int basis);
+
+/* Determinant coefficients of an amplitude vector (paper Sec. II.B: Psi1 over
+ * the M_s = 0 doubles and triples of the closed shell; reading: canonical
+ * phase with the alpha string first, then the beta string, each ascending).
+ *   x: device, n_amp doubles, amplitudes of the TOP basis (e.g. esmp2_solve's
+ *      x_out)
+ *   coeff: device, n doubles; det_key: device, n int64; n >= 2 n_amp - n_S2
+ *      (n_S2 = box_offsets[2] - box_offsets[1]).  Entries 0 .. n_amp-1 hold the
+ *      determinant of every stored amplitude in layout order, entries n_amp ..
+ *      2 n_amp - n_S2 - 1 the spin-flip partner of every amplitude outside S2
+ *      in layout order (S2 stores both members of each flip pair, so each S2
+ *      determinant appears once, with the flip-symmetrised amplitude
+ *      (x + sg x_partner)/2, sg = +1 singlet, -1 triplet; a flip partner
+ *      outside S2 carries sg x).  Coefficient = phase of the amplitude's
+ *      operator string (the layout table above) in the canonical order, times
+ *      the amplitude.
+ *   det_key: the determinant as its excitation from the closed shell: holes in
+ *      bits 0-29 and particles in bits 30-59, 10 bits per spin-orbital, each
+ *      group ascending, 1023 in the unused third slots of a double.
+ *      Spin-orbital numbering: alpha orbital p -> p, beta p -> N + p; spatial
+ *      orbitals: occupied 0 .. n_occ-1, then the virtuals (virtual a -> n_occ + a).
+ * Requires esmp2_set_problem (any later state).  Queued on the handle's stream;
+ * does not synchronise. */
+esmp2_status esmp2_export_determinants(esmp2_handle h, const double* x, double* coeff, int64_t* det_key,
+                                       int64_t n);
+
 /* Jacobi-preconditioned conjugate gradient for A x = -b (A = H0 - E0 on D + L,
  * weighted inner product), then E2 (paper Sec. III.A and Sec. II.C).  Builds the
  * right-hand side first if esmp2_build_rhs has not been called.  Synchronises.

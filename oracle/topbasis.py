@@ -62,3 +62,20 @@ def rotate(F, B, R):
 def eri_from_factor(Bt):
     """(pq|rs) = sum_Q B[Q,p,q] B[Q,r,s] (full tensor; tiny sizes only)."""
     return np.einsum("Qpq,Qrs->pqrs", Bt, Bt, optimize=True)
+
+
+def pinned_semicanonical(Ft, n_occ):
+    """Rotation (To, Tv) of the occupied orbitals other than t = 0 and of the
+    virtuals other than t' = 0 that diagonalises their Fock blocks
+    Ft[1:no, 1:no] and Ft[no+1:, no+1:] (t and t' fixed).  Doubles +
+    L-triples are mapped onto themselves by such rotations (an L-triple
+    keeps t among its holes and t' among its particles, Sec. II.B).
+    Eigenvalues ascending; each eigenvector signed so that its
+    largest-magnitude component is positive (the library's convention).
+    New orbital P' = sum_P T[P, P'] P."""
+    no = n_occ
+    nv = Ft.shape[0] - no
+    To, Tv = np.eye(no), np.eye(nv)
+    To[1:, 1:] = _fix_sign(np.linalg.eigh(Ft[1:no, 1:no])[1])[0]
+    Tv[1:, 1:] = _fix_sign(np.linalg.eigh(Ft[no + 1:, no + 1:])[1])[0]
+    return To, Tv

@@ -53,6 +53,8 @@ _sig = {
     "esmp2_gradient": ([_H, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "esmp2_autotune": ([_H, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)], C.c_int),
     "esmp2_set_sylvester_variant": ([_H, C.c_int, C.c_int], C.c_int),
+    "esmp2_sigma_basis": ([_H, C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
+    "esmp2_export_determinants": ([_H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
     "esmp2_last_error": ([_H], C.c_char_p),
 }
 for _name, (_args, _res) in _sig.items():
@@ -147,6 +149,13 @@ class Handle:
 
     def sigma(self, x, y, precision=ESMP2_FP64):
         return self._check(lib.esmp2_sigma(self.h, _ptr(x), _ptr(y), precision))
+
+    def sigma_basis(self, x, y, precision=ESMP2_FP64, basis=ESMP2_BASIS_TOP):
+        return self._check(lib.esmp2_sigma_basis(self.h, _ptr(x), _ptr(y), precision, basis))
+
+    def export_determinants(self, x, coeff, keys):
+        """Determinant coefficients and keys of the TOP-basis amplitudes x (device tensors)."""
+        return self._check(lib.esmp2_export_determinants(self.h, _ptr(x), _ptr(coeff), _ptr(keys), coeff.numel()))
 
     def solve(self, tol=1e-8, max_iter=200, precision=ESMP2_FP64, x0=None, x_out=None,
               history=False, inner_tol=0.0, basis=ESMP2_BASIS_TOP, allow=(ESMP2_NOT_CONVERGED,)):

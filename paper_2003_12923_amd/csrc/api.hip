@@ -67,8 +67,23 @@ __global__ void k_topfock(const double* Ft, const double* lam, int no, int nv, i
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
+// Page-locked host block of one handle: every scalar the host reads back from
+// the device lands here.  A copy into it is DMA into memory the handle owns,
+// so no call leaves a device-to-host copy pending into pageable or stack
+// memory, on any return path.
+struct PinnedScalars {
+  double sc[SC_N];       // conjugate-gradient scalars (SC_* slots)
+  double rot[4];         // omega, kappa, E0 of the rotation
+  double lam[64];        // singular values (n_occ <= 64)
+  double tmp[4];
+  double e2s;
+  int info[4];
+  int bad[4];
+};
+
 struct esmp2_handle_ {
   int device = 0;
+  PinnedScalars* pin = nullptr;
   hipStream_t stream = nullptr;
   std::string err = "no error";
   int state = 0;                 // 0 empty, 1 problem set, 2 rotated, 3 rhs built
@@ -106,7 +121,8 @@ struct esmp2_handle_ {
   float *d32, *r32, *p32, *q32, *dinv32;
   // pinned-semicanonical basis: rotations (t and t' fixed), operator blocks, rotated rhs,
   // Jacobi diagonal, dense scratch of the amplitude rotation
-  bool have_sc = false;
+  bool have_sc_op = false;       // the operator blocks of the pinned-semicanonical basis are built
+  bool have_sc = false;          // ... and the right-hand side is rotated into that basis
   bool dinv32_ok = false, dinv32_sc_ok = false;   // FP32 copies of the preconditioners, made on first use
   // side stream: the semicanonical eigenproblems run there while the main
   // stream builds the right-hand side (default priority, non-blocking)
@@ -160,6 +176,7 @@ static void release(esmp2_handle h) {
   h->state = 0;
   h->have_rhs = false;
   h->have_sc = false;
+  h->have_sc_op = false;
   h->sc_pending = false;
   h->sc_eig = false;
   h->e2s_pending = false;
@@ -176,8 +193,9 @@ static esmp2_status join_e2s(esmp2_handle h, bool read) {
     h->e2s_pending = false;
   }
   if (read && h->e2s_dev) {
-    ESMP2_HIP(hipMemcpyAsync(&h->e2s, h->e2s_part + E2S_CAP, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    ESMP2_HIP(hipMemcpyAsync(&h->pin->e2s, h->e2s_part + E2S_CAP, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     ESMP2_HIP(hipStreamSynchronize(h->stream));
+    h->e2s = h->pin->e2s;
     h->e2s_dev = false;
   }
   return ESMP2_OK;
@@ -282,7 +300,8 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
   if (!h) return ESMP2_OOM;
   h->device = device;
   h->stream = (hipStream_t)stream;
-  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+  if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&h->pin, sizeof(PinnedScalars), 0) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_fock_ready, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_sc_eig, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_rhs_ready, hipEventDisableTiming) != hipSuccess ||
@@ -292,6 +311,7 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
     if (h->ev_sc_eig) (void)hipEventDestroy(h->ev_sc_eig);
     if (h->ev_rhs_ready) (void)hipEventDestroy(h->ev_rhs_ready);
     if (h->ev_e2s) (void)hipEventDestroy(h->ev_e2s);
+    if (h->pin) (void)hipHostFree(h->pin);
     delete h;
     return ESMP2_HIP_ERROR;
   }
@@ -311,6 +331,7 @@ esmp2_status esmp2_destroy(esmp2_handle h) {
   (void)hipEventDestroy(h->ev_sc_eig);
   (void)hipEventDestroy(h->ev_rhs_ready);
   (void)hipEventDestroy(h->ev_e2s);
+  (void)hipHostFree(h->pin);
   delete h;
   return ESMP2_OK;
 }
@@ -477,10 +498,9 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
   hipLaunchKernelGGL(k_finite, dim3(1024), dim3(256), 0, h->stream, h->B, (int64_t)na * n * n, bad);
   if (C) hipLaunchKernelGGL(k_finite, dim3(64), dim3(256), 0, h->stream, h->C, (int64_t)no * nv, bad);
   else hipLaunchKernelGGL(k_finite, dim3(1), dim3(64), 0, h->stream, h->lam, (int64_t)no, bad);
-  int hbad = 0;
-  ESMP2_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  ESMP2_HIP(hipMemcpyAsync(h->pin->bad, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   ESMP2_HIP(hipStreamSynchronize(h->stream));
-  if (hbad) { release(h); return fail(h, ESMP2_INVALID_ARG, C ? "NaN or Inf in F, B or C" : "NaN or Inf in F, B or lam"); }
+  if (h->pin->bad[0]) { release(h); return fail(h, ESMP2_INVALID_ARG, C ? "NaN or Inf in F, B or C" : "NaN or Inf in F, B or lam"); }
   h->top_given = (C == nullptr);
   h->state = 1;
   return ESMP2_OK;
@@ -654,18 +674,19 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     hipLaunchKernelGGL(k_extract_blocks, dim3(1024), dim3(256), 0, s, (const double*)h->B, no, nv, na, h->Bov,
                        h->Bvt, h->Boo);
   }
-  double sc[3];
-  int info[1];
-  ESMP2_HIP(hipMemcpyAsync(sc, h->sc_rot, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  ESMP2_HIP(hipMemcpyAsync(info, h->iinfo, sizeof(int), hipMemcpyDeviceToHost, s));
-  if (lambda_out) ESMP2_HIP(hipMemcpyAsync(lambda_out, h->lam, no * sizeof(double), hipMemcpyDeviceToHost, s));
+  PinnedScalars* pin = h->pin;
+  ESMP2_HIP(hipMemcpyAsync(pin->rot, h->sc_rot, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipMemcpyAsync(pin->info, h->iinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (lambda_out) ESMP2_HIP(hipMemcpyAsync(pin->lam, h->lam, no * sizeof(double), hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
   ESMP2_HIP(hipGetLastError());
-  h->omega = sc[0]; h->kappa = sc[1]; h->e0 = sc[2];
-  h->svd_sweeps = info[0];
+  if (lambda_out) memcpy(lambda_out, pin->lam, no * sizeof(double));
+  h->omega = pin->rot[0]; h->kappa = pin->rot[1]; h->e0 = pin->rot[2];
+  h->svd_sweeps = pin->info[0];
   h->state = 2;
   h->have_rhs = false;
   h->have_sc = false;
+  h->have_sc_op = false;
   return ESMP2_OK;
 }
 
@@ -732,11 +753,10 @@ static esmp2_status build_rhs(esmp2_handle h) {
   ESMP2_HIP(hipEventRecord(h->ev_e2s, h->aux));
   h->e2s_pending = true;
   h->e2s_dev = true;
-  double tmp[1];
-  ESMP2_HIP(hipMemcpyAsync(tmp, h->sc + SC_TMP, sizeof(double), hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipMemcpyAsync(h->pin->tmp, h->sc + SC_TMP, sizeof(double), hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
   ESMP2_HIP(hipGetLastError());
-  if (!(tmp[0] > 0.0)) return fail(h, ESMP2_NOT_SPD, "a diagonal denominator of the first-order space is <= 0");
+  if (!(h->pin->tmp[0] > 0.0)) return fail(h, ESMP2_NOT_SPD, "a diagonal denominator of the first-order space is <= 0");
   h->have_rhs = true;
   h->have_sc = false;
   h->state = 3;
@@ -1021,9 +1041,9 @@ static esmp2_status rotate_amplitudes(esmp2_handle h, const double* x, double* y
 }
 
 // Rotation diagonalising F~_oo[1:,1:] and F~_vv[1:,1:], the operator blocks in
-// the new basis (TOP-basis omega and kappa), its Jacobi diagonal and the
-// rotated right-hand side.  Requires the right-hand side.
-static esmp2_status semican_setup(esmp2_handle h) {
+// the new basis (TOP-basis omega and kappa) and its Jacobi diagonal.  Requires
+// the rotation to the TOP basis.
+static esmp2_status semican_operator(esmp2_handle h) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, n = d.n, mv = d.mv;
   const int64_t namp = d.off[7];
@@ -1035,7 +1055,6 @@ static esmp2_status semican_setup(esmp2_handle h) {
     h->sc_eig = true;
   }
   if (!h->sc_eig) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
-  esmp2_status st;
   // Fh = T^T F~ T
   hipLaunchKernelGGL(k_blkdiag, dim3(nblk((int64_t)n * n)), dim3(256), 0, s, (const double*)h->To,
                      (const double*)h->Tv, no, nv, h->Tsc);
@@ -1063,7 +1082,19 @@ static esmp2_status semican_setup(esmp2_handle h) {
   DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv_sc, h->blockmin};
   hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
   h->dinv32_sc_ok = false;
-  st = rotate_amplitudes(h, h->b, h->b_sc, true);
+  ESMP2_HIP(hipGetLastError());
+  h->have_sc_op = true;
+  return ESMP2_OK;
+}
+
+// The operator of the pinned-semicanonical basis (if not built yet) and the
+// right-hand side rotated into it.  Requires the right-hand side.
+static esmp2_status semican_setup(esmp2_handle h) {
+  if (!h->have_sc_op) {
+    const esmp2_status st = semican_operator(h);
+    if (st != ESMP2_OK) return st;
+  }
+  const esmp2_status st = rotate_amplitudes(h, h->b, h->b_sc, true);
   if (st != ESMP2_OK) return st;
   ESMP2_HIP(hipGetLastError());
   h->have_sc = true;
@@ -1131,6 +1162,42 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision) 
     return sigma_t(h, bufs_bf16(h), (const float*)x, (float*)y);
   }
   return fail(h, ESMP2_INVALID_ARG, "unknown precision");
+}
+
+esmp2_status esmp2_sigma_basis(esmp2_handle h, const void* x, void* y, int precision, int basis) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (basis == ESMP2_BASIS_TOP) return esmp2_sigma(h, x, y, precision);
+  if (basis != ESMP2_BASIS_SEMICANONICAL) return fail(h, ESMP2_INVALID_ARG, "unknown basis");
+  if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
+  if (!x || !y) return fail(h, ESMP2_INVALID_ARG, "null vector");
+  if (x == y) return fail(h, ESMP2_INVALID_ARG, "x and y must not overlap");
+  if (precision != ESMP2_FP64 && precision != ESMP2_FP32) {
+    if (precision == ESMP2_BF16)
+      return fail(h, ESMP2_UNSUPPORTED, "the pinned-semicanonical operator has no Sylvester products (no BF16 form)");
+    return fail(h, ESMP2_INVALID_ARG, "unknown precision");
+  }
+  ESMP2_HIP(hipSetDevice(h->device));
+  if (!h->have_sc_op) {
+    const esmp2_status st = semican_operator(h);
+    if (st != ESMP2_OK) return st;
+  }
+  const OpCtx c = ctx_sc(h);
+  if (precision == ESMP2_FP64) return sigma_arrow(h, c.s64, (const double*)x, (double*)y);
+  return sigma_arrow(h, c.s32, (const float*)x, (float*)y);
+}
+
+esmp2_status esmp2_export_determinants(esmp2_handle h, const double* x, double* coeff, int64_t* det_key,
+                                       int64_t n) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (h->state < 1) return fail(h, ESMP2_BAD_ORDER, "esmp2_set_problem first");
+  const Dims& d = h->d;
+  const int64_t namp = d.off[7], ndet = 2 * namp - (d.off[B_S2 + 1] - d.off[B_S2]);
+  if (!x || !coeff || !det_key) return fail(h, ESMP2_INVALID_ARG, "null pointer");
+  if (n < ndet) return fail(h, ESMP2_INVALID_ARG, "output arrays shorter than 2 n_amp - n_S2 determinants");
+  ESMP2_HIP(hipSetDevice(h->device));
+  hipLaunchKernelGGL(k_export_dets, dim3(nblk(namp)), dim3(256), 0, h->stream, d, x, coeff, det_key);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
 }
 
 esmp2_status esmp2_set_sylvester_variant(esmp2_handle h, int precision, int variant) {
@@ -1219,10 +1286,10 @@ static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_sol
     const esmp2_status st = join_e2s(h, true);
     if (st != ESMP2_OK) return st;
   }
-  double hs[SC_N];
+  const double* hs = h->pin->sc;
   wdot(h, c.b, (const double*)h->x, SC_BX);
   wdot(h, (const double*)h->x, (const double*)h->r, SC_XR);
-  ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+  ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
   if (opts->x_out) {
     if (c.rotated) {
       esmp2_status st = rotate_amplitudes(h, h->x, opts->x_out, false);
@@ -1270,8 +1337,8 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   }
   // rho = <r, D^-1 r> into SC_RHO and <r, r> into SC_RHO + 1 = SC_PQ
   hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);
-  double hs[SC_N];
-  ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+  double* hs = h->pin->sc;
+  ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
   const double bn = sqrt(hs[SC_BB]);
   double rel = sqrt(hs[SC_PQ]) / bn;
@@ -1283,7 +1350,7 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
     hipLaunchKernelGGL(k_update_xr<double>, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, c.dinv, n, d.off[1],
                        d.off[2], h->sc, h->partial);
     hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);  // RHO_NEW, RR
-    ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+    ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
     ESMP2_HIP(hipStreamSynchronize(s));
     if (!(hs[SC_PQ] > 0.0)) { status = ESMP2_NOT_SPD; h->err = "p.Ap <= 0 in conjugate gradient"; break; }
     ++it;
@@ -1336,8 +1403,8 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
                        d.off[2], h->partial);
   }
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RR);
-  double hs[SC_N];
-  ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+  double* hs = h->pin->sc;
+  ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
   const double bn = sqrt(hs[SC_BB]);
   double rel = sqrt(hs[SC_RR]) / bn;
@@ -1350,7 +1417,7 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
     hipLaunchKernelGGL(k_init_inner, dim3(NB), dim3(256), 0, s, (const double*)h->r, scale, h->r32, h->p32, h->d32,
                        c.dinv32, n, d.off[1], d.off[2], h->partial);
     hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);  // RHO, rr0
-    ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+    ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
     ESMP2_HIP(hipStreamSynchronize(s));
     const double rr0 = hs[SC_PQ];
     while (it < opts->max_iter) {
@@ -1360,7 +1427,7 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
                          (const float*)h->q32, c.dinv32, n, d.off[1], d.off[2], (const double*)h->sc,
                          h->partial);
       hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);
-      ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+      ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
       ESMP2_HIP(hipStreamSynchronize(s));
       if (!(hs[SC_PQ] > 0.0)) { status = ESMP2_NOT_SPD; h->err = "p.Ap <= 0 in conjugate gradient"; break; }
       ++it;
@@ -1378,7 +1445,7 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
     hipLaunchKernelGGL(k_resid, dim3(NB), dim3(256), 0, s, c.b, (const double*)h->q, h->r, n, d.off[1], d.off[2],
                        h->partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RR);
-    ESMP2_HIP(hipMemcpyAsync(hs, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
+    ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
     ESMP2_HIP(hipStreamSynchronize(s));
     rel = sqrt(hs[SC_RR]) / bn;
   }

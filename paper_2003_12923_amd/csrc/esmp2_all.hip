@@ -8,4 +8,5 @@
 #include "arrow.hip"
 #include "gemv.hip"
 #include "adjoint.hip"
+#include "export.hip"
 #include "api.hip"

@@ -10,6 +10,11 @@ their flat index in the seven-box layout.
 For the batched workload ("c4": 32 independent states of uneven size) it
 holds E0 and E2 with its parts per state.
 
+Names ending in "_semican" hold sigma of the same seeded random x applied by
+the operator of the pinned-semicanonical basis (``topbasis.pinned_semicanonical``:
+the occupied orbitals other than t and the virtuals other than t' rotated to
+diagonalise their Fock blocks), at the same sampled indices.
+
 Names ending in "_triplet" hold the same quantities for the M_s = 0 triplet
 reference (beta singles with the opposite sign).
 
@@ -71,6 +76,25 @@ def run(name, spin=0):
     return out
 
 
+def run_semican(name):
+    p = synth.config_problem(name)
+    t0 = time.time()
+    lam, R = topbasis.top_rotation(p.F, p.C, p.n_occ)
+    Ft, _ = topbasis.rotate(p.F, p.B, R)
+    op = structured.Structured(Ft, lam, p.n_occ)
+    To, Tv = topbasis.pinned_semicanonical(Ft, p.n_occ)
+    T = np.zeros_like(Ft)
+    T[:p.n_occ, :p.n_occ], T[p.n_occ:, p.n_occ:] = To, Tv
+    op2 = structured.Structured(T.T @ Ft @ T, lam, p.n_occ, omega=op.omega)
+    from oracle.layout import box_offsets
+    off = [int(v) for v in box_offsets(p.n_occ, p.n_vir)]
+    xr = synth.random_amplitudes(op.dim, 1234)
+    sig = op2.sigma(xr)
+    idx = sample_indices(op.dim, off, 99)
+    return dict(n_occ=p.n_occ, n_vir=p.n_vir, dim=op.dim, sample_idx=idx, sigma_seed=1234,
+                sigma_sample=sig[idx].tolist(), seconds=time.time() - t0)
+
+
 def run_batched():
     states = []
     for (no, nv, na, seed) in synth.batched_sizes():
@@ -125,6 +149,11 @@ if __name__ == "__main__":
         if nm.endswith("_triplet"):
             data[nm] = run(nm[:-8], spin=1)
             print(nm, data[nm]["e2"], data[nm]["iters"], data[nm]["seconds"], flush=True)
+            json.dump(data, open(path, "w"), indent=1)
+            continue
+        if nm.endswith("_semican"):
+            data[nm] = run_semican(nm[:-8])
+            print(nm, "%.1fs" % data[nm]["seconds"], flush=True)
             json.dump(data, open(path, "w"), indent=1)
             continue
         if nm.endswith("_grad"):

@@ -25,8 +25,8 @@ def lib():
     return p
 
 
-# padded virtual dimensions 16, 48 (generic kernel only), 80 and 112 (specialised kernel too)
-SIZES = [(4, 16, 20, 1), (5, 40, 30, 2), (8, 80, 20, 3), (3, 100, 16, 4)]
+# padded virtual dimensions 16, 48 (generic kernel only), 80, 112 and 160 (specialised kernel too)
+SIZES = [(4, 16, 20, 1), (5, 40, 30, 2), (8, 80, 20, 3), (3, 100, 16, 4), (4, 155, 16, 5)]
 
 
 @pytest.mark.parametrize("no,nv,na,seed", SIZES)

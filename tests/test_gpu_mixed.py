@@ -48,7 +48,8 @@ def _op_norm_bound(Ft, lam, no):
     return 2 * rs(fv) + 2 * rs(fo) + 12 * np.abs(fov).max() * max(no, Ft.shape[0] - no) + abs(om) + abs(ka)
 
 
-CANON = [(3, 5, 8, 1), (4, 16, 48, 3), (5, 40, 30, 4), (6, 100, 40, 5), (3, 180, 20, 6), (8, 80, 20, 7)]
+CANON = [(3, 5, 8, 1), (4, 16, 48, 3), (5, 40, 30, 4), (6, 100, 40, 5), (3, 180, 20, 6), (8, 80, 20, 7),
+         (3, 160, 20, 8), (4, 159, 24, 9), (6, 150, 16, 10)]
 
 
 @pytest.mark.parametrize("no,nv,na,seed", CANON)

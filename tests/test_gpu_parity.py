@@ -54,7 +54,10 @@ def test_gemm_f64_matches_reference(lib):
     h.close()
 
 
-CANON = [(3, 5, 8, 1), (4, 7, 9, 2), (4, 16, 48, 3), (5, 40, 30, 4), (6, 100, 40, 5), (3, 180, 20, 6)]
+# padded virtual dimensions 16, 16, 16, 48, 112, 192, and 160 (the specialised
+# Sylvester kernel of the timed workload) with full and ragged virtual spaces
+CANON = [(3, 5, 8, 1), (4, 7, 9, 2), (4, 16, 48, 3), (5, 40, 30, 4), (6, 100, 40, 5), (3, 180, 20, 6),
+         (3, 160, 20, 7), (4, 159, 24, 8), (6, 150, 16, 9)]
 
 
 @pytest.mark.parametrize("no,nv,na,seed", CANON)
@@ -83,7 +86,7 @@ def test_sigma_elementwise(lib, no, nv, na, seed):
     h.close()
 
 
-@pytest.mark.parametrize("no,nv,na,seed", CANON[:5])
+@pytest.mark.parametrize("no,nv,na,seed", CANON[:5] + CANON[7:8])
 def test_rhs_elementwise(lib, no, nv, na, seed):
     prob = synth.make_canonical_problem(no, nv, na, seed)
     h = _handle(lib, prob)

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import structured
+from oracle import structured, topbasis
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -86,4 +86,105 @@ def test_semican_mixed(lib, name):
     assert abs(res["e2"] - g["e2"]) <= 1e-6
     with pytest.raises(lib.Esmp2Error):
         h.solve(tol=1e-8, max_iter=10, basis=7)
+    h.close()
+
+
+U32 = 2.0 ** -24
+
+
+def _semican_operator(prob):
+    """The oracle's operator in its own pinned-semicanonical basis (rotation of
+    the input to the TOP basis, then of the non-pinned orbitals)."""
+    no = prob.n_occ
+    lam, R = topbasis.top_rotation(prob.F, prob.C, no)
+    Ft, _ = topbasis.rotate(prob.F, prob.B, R)
+    op = structured.Structured(Ft, lam, no)
+    To, Tv = topbasis.pinned_semicanonical(Ft, no)
+    T = np.zeros_like(Ft)
+    T[:no, :no], T[no:, no:] = To, Tv
+    Fh = T.T @ Ft @ T
+    return structured.Structured(Fh, lam, no, omega=op.omega), Fh, lam
+
+
+def _op_norm_bound(Fh, lam, no, omega):
+    """Upper bound of the infinity norm of A = H0 - E0 on doubles + L-triples."""
+    fo, fv, fov = Fh[:no, :no], Fh[no:, no:], Fh[:no, no:]
+    rs = lambda M: np.abs(M).sum(axis=1).max()
+    ka = fv[0, 0] - fo[0, 0] - omega
+    return 2 * rs(fv) + 2 * rs(fo) + 12 * np.abs(fov).max() * max(no, Fh.shape[0] - no) + abs(omega) + abs(ka)
+
+
+# random orbital basis (both rotations included), padded virtual dimensions up to
+# 160, an occupied space beyond one 16 x 16 tile
+SEMI = [(3, 5, 8, 1), (4, 7, 9, 2), (4, 16, 48, 3), (5, 40, 30, 4), (6, 100, 40, 5), (4, 159, 24, 8),
+        (6, 150, 16, 9), (17, 18, 12, 10), (2, 2, 3, 11)]
+
+
+@pytest.mark.parametrize("no,nv,na,seed", SEMI)
+def test_sigma_semicanonical_elementwise(lib, no, nv, na, seed):
+    """sigma in the pinned-semicanonical basis (the operator of the headline
+    solve: arrow kernels and per-batch GEMVs) against the oracle's operator
+    in the oracle's own semicanonical basis, every element: FP64 to 1e-12 of
+    the largest, FP32 within the FP32 forward-error bound."""
+    prob = synth.make_problem(no, nv, na, seed)
+    h = _handle(lib, prob)
+    h.rotate_top()
+    op2, Fh, lam = _semican_operator(prob)
+    n, offs = h.space()
+    assert n == op2.dim
+    x = synth.random_amplitudes(n, seed + 300)
+    ref = op2.sigma(x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.full_like(xt, float("nan"))
+    h.sigma_basis(xt, yt, lib.ESMP2_FP64, lib.ESMP2_BASIS_SEMICANONICAL)
+    x32 = xt.to(torch.float32)
+    y32 = torch.full_like(x32, float("nan"))
+    h.sigma_basis(x32, y32, lib.ESMP2_FP32, lib.ESMP2_BASIS_SEMICANONICAL)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    scale = np.abs(ref).max()
+    for k in range(7):
+        lo, hi = offs[k], offs[k + 1]
+        if hi > lo:
+            err = np.abs(y[lo:hi] - ref[lo:hi]).max()
+            assert err <= 1e-12 * scale, (k, err, scale)
+    y = y32.cpu().numpy().astype(np.float64)
+    mv = 16 * ((nv + 15) // 16)
+    K = 2 * mv + 2 * no + 24
+    gam = K * U32 / (1 - K * U32)
+    bound = (gam + 2 * U32) * _op_norm_bound(Fh, lam, no, op2.omega) * np.abs(x).max()
+    err = np.abs(y - ref).max()
+    print(f"[semican sigma] fp32 max err {err:.3e} bound {bound:.3e}", flush=True)
+    assert np.isfinite(y).all() and err <= bound
+    with pytest.raises(lib.Esmp2Error):
+        h.sigma_basis(x32, y32, lib.ESMP2_BF16, lib.ESMP2_BASIS_SEMICANONICAL)
+    with pytest.raises(lib.Esmp2Error):
+        h.sigma_basis(xt, yt, lib.ESMP2_FP64, 5)
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_sigma_semicanonical_workloads(lib, name):
+    """At the workload sizes, in the launch configuration of the timed solve:
+    sampled sigma of the stored random vector in the semicanonical basis
+    against the oracle's stored values; then the TOP-basis solve still gives
+    the oracle's E2 (the semicanonical set-up leaves the TOP operator alone)."""
+    g = GOLD[name + "_semican"]
+    prob = synth.config_problem(name)
+    h = _handle(lib, prob)
+    h.rotate_top()
+    n, _ = h.space()
+    assert n == g["dim"]
+    x = synth.random_amplitudes(n, g["sigma_seed"])
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.empty_like(xt)
+    h.sigma_basis(xt, yt, lib.ESMP2_FP64, lib.ESMP2_BASIS_SEMICANONICAL)
+    torch.cuda.synchronize()
+    idx = np.array(g["sample_idx"])
+    ref = np.array(g["sigma_sample"])
+    sig = yt.cpu().numpy()[idx]
+    print(f"[{name} semican sigma] max rel err {np.abs(sig - ref).max() / np.abs(ref).max():.3e}", flush=True)
+    assert np.abs(sig - ref).max() <= 1e-11 * np.abs(ref).max()
+    res = h.solve(tol=1e-10, max_iter=300)
+    assert res["status"] == 0 and abs(res["e2"] - GOLD[name]["e2"]) < 1e-10
     h.close()

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import explicit, frontend, gradient, layout, structured, topbasis
+from oracle import explicit, frontend, gradient, layout, opcount, structured, topbasis
 
 MICRO = [(2, 4, 6, 0), (3, 5, 8, 1), (3, 6, 8, 2), (4, 6, 10, 3), (4, 7, 9, 4)]
 
@@ -509,3 +509,49 @@ def test_gradient_homogeneity():
     # and directly: E2(s F~, sqrt(s) B~) = s E2
     s = 1.7
     assert abs(gradient.e2_of(s * Ft, np.sqrt(s) * Bt, lam, no) - s * L.e2) < 1e-14
+
+
+def _costs():
+    """The product's size arithmetic (a plain module, loaded by path so that the
+    library itself need not be built for this CPU test)."""
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2003_12923_amd",
+                        "costs.py")
+    spec = importlib.util.spec_from_file_location("_esmp2_costs", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("no,nv", [(2, 2), (2, 3), (3, 3), (3, 4), (3, 5), (4, 5), (4, 6), (5, 6), (5, 8)])
+def test_flop_count_equals_enumerated_nonzeros(no, nv):
+    """P-l: the closed-form algorithmic work of sigma (2 x nnz of H0 - E0 on
+    D + L in the representative basis, by class) equals the nonzeros of the
+    explicit determinant operator with a generic Fock matrix, mapped to the
+    representative rows, class by class."""
+    e = opcount.rep_nnz(no, nv)
+    c = _costs().sigma_nnz(no, nv)
+    for k in ("diag", "vir", "occ", "ov", "total"):
+        assert e[k] == c[k], (k, e[k], c[k])
+    assert e["dim"] == c["diag"]
+    # every stored amplitude is a row, except the redundant half of S2
+    assert c["diag"] == _costs().amplitudes(no, nv) - (no * no * nv * nv - no * nv) // 2
+
+
+def test_flop_count_scaling_exponents():
+    """P-l: log-log regressions of the counted work over the paper's ranges
+    (Sec. III.B: N_v = 100 with N_o = 30..50, N_o = 30 with N_v = 50..100)
+    give the categories of Table I's H0 rows: virtual-index contractions
+    N_o^2 N_v^3, occupied-index ones N_o^3 N_v^2, doubles <-> triples
+    N_o^2 N_v^2; nothing in sigma grows faster than N_o^2 N_v^3 (fifth order)."""
+    costs = _costs()
+    O, V = np.arange(30, 51), np.arange(50, 101)
+    expect = {"vir": (2, 3), "occ": (3, 2), "ov": (2, 2), "diag": (2, 2)}
+    for cls, (eo, ev) in expect.items():
+        so = np.polyfit(np.log(O), np.log([costs.sigma_nnz(int(o), 100)[cls] for o in O]), 1)[0]
+        sv = np.polyfit(np.log(V), np.log([costs.sigma_nnz(30, int(v))[cls] for v in V]), 1)[0]
+        assert abs(so - eo) < 0.1 and abs(sv - ev) < 0.1, (cls, so, sv)
+    so = np.polyfit(np.log(O), np.log([costs.sigma_nnz(int(o), 100)["total"] for o in O]), 1)[0]
+    sv = np.polyfit(np.log(V), np.log([costs.sigma_nnz(30, int(v))["total"] for v in V]), 1)[0]
+    assert so + sv < 5.05
