@@ -282,6 +282,20 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
 esmp2_status esmp2_fock_from_core(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* hcore,
                                   const double* B, const double* C, double* F_out);
 
+/* Allocation-free form of esmp2_fock_from_core, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and layout; the
+ * intermediates (the density, the exchange matrix, the Coulomb weights and a
+ * 16-auxiliary-index chunk of the exchange GEMM) live in a static workspace
+ * of 9.57 MB per GPU that the library holds until the process ends, so it
+ * calls no allocator.  Limits: n_occ + n_vir <= 256 and n_aux <= 16384, else
+ * ESMP2_INVALID_ARG.  Queued on the handle's stream; does not synchronise.
+ * Every call on one GPU shares that GPU's workspace: calls that overlap on
+ * one GPU (two streams, or two host threads) race and must be ordered by the
+ * caller.  Nothing in the workspace needs to start at zero. */
+esmp2_status esmp2_fock_from_core_noalloc(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* hcore,
+                                          const double* B, const double* C, double* F_out);
+
 /* Batched workload: n independent states, one handle each (esmp2_set_problem
  * done, every handle on its own stream for the states to overlap on the
  * device).  For every handle: rotation, right-hand side, solve with `opts`,

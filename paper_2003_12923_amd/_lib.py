@@ -48,6 +48,8 @@ _sig = {
                           C.c_int),
     "esmp2_fock_from_core": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
                              C.c_int),
+    "esmp2_fock_from_core_noalloc": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p], C.c_int),
     "esmp2_set_problem_top": ([_H, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int],
                               C.c_int),
     "esmp2_gradient": ([_H, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
@@ -190,6 +192,10 @@ class Handle:
     def fock_from_core(self, hcore, B, Cm, n_occ, n_vir, n_aux, F_out):
         return self._check(lib.esmp2_fock_from_core(self.h, n_occ, n_vir, n_aux, _ptr(hcore), _ptr(B), _ptr(Cm),
                                                     _ptr(F_out)))
+
+    def fock_from_core_noalloc(self, hcore, B, Cm, n_occ, n_vir, n_aux, F_out):
+        return self._check(lib.esmp2_fock_from_core_noalloc(self.h, n_occ, n_vir, n_aux, _ptr(hcore), _ptr(B),
+                                                            _ptr(Cm), _ptr(F_out)))
 
     def gemm_f64(self, A, B, Cm):
         m, k = A.shape

@@ -289,6 +289,8 @@ static esmp2_status launch_semican_eig(esmp2_handle h) {
   return ESMP2_OK;
 }
 
+static esmp2_status scratch_address(esmp2_handle h, double** out);
+
 extern "C" {
 
 esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
@@ -314,6 +316,19 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
     if (h->pin) (void)hipHostFree(h->pin);
     delete h;
     return ESMP2_HIP_ERROR;
+  }
+  {
+    double* ws = nullptr;   // the allocation-free entry point's workspace on this device
+    if (scratch_address(h, &ws) != ESMP2_OK) {
+      (void)hipStreamDestroy(h->aux);
+      (void)hipEventDestroy(h->ev_fock_ready);
+      (void)hipEventDestroy(h->ev_sc_eig);
+      (void)hipEventDestroy(h->ev_rhs_ready);
+      (void)hipEventDestroy(h->ev_e2s);
+      (void)hipHostFree(h->pin);
+      delete h;
+      return ESMP2_HIP_ERROR;
+    }
   }
   *out = h;
   return ESMP2_OK;
@@ -1796,6 +1811,84 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
   if (dF)
     hipLaunchKernelGGL(k_grad_f_finish, dim3(nblk((int64_t)n * n)), dim3(256), 0, s, G, (const double*)h->lam,
                        (const double*)Gf, (const double*)Gev, (const double*)Geo, (const double*)scal, no, nv, dF);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of esmp2_fock_from_core: its intermediates live in
+// one static device array per GPU.  Layout (doubles, n = n_occ + n_vir):
+// gamma (n^2), K (n^2), the Coulomb weights d (n_aux), then the per-chunk
+// GEMM intermediate T[p][Q][r] of FOCK_QCHUNK auxiliary indices (FOCK_QCHUNK n^2).
+// ---------------------------------------------------------------------------
+constexpr int FOCK_NMAX = 256, FOCK_AUXMAX = 16384, FOCK_QCHUNK = 16;
+constexpr size_t FOCK_SCRATCH_DOUBLES =
+    (size_t)2 * FOCK_NMAX * FOCK_NMAX + FOCK_AUXMAX + (size_t)FOCK_QCHUNK * FOCK_NMAX * FOCK_NMAX;   // 9.57 MB
+static __device__ __align__(256) double scratch[FOCK_SCRATCH_DOUBLES];
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the array's host-side name is not a device address).
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[64] = {};
+
+static esmp2_status scratch_address(esmp2_handle h, double** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (h->device < 0 || h->device >= 64) return fail(h, ESMP2_INVALID_ARG, "device ordinal beyond 63");
+  if (!g_scratch_ptr[h->device]) {
+    void* p = nullptr;
+    ESMP2_HIP(hipSetDevice(h->device));
+    ESMP2_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[h->device] = (double*)p;
+  }
+  *out = g_scratch_ptr[h->device];
+  return ESMP2_OK;
+}
+
+extern "C" {
+
+esmp2_status esmp2_fock_from_core_noalloc(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* hcore,
+                                          const double* B, const double* C, double* F_out) {
+  if (!h) return ESMP2_INVALID_ARG;
+  if (!hcore || !B || !C || !F_out) return fail(h, ESMP2_INVALID_ARG, "null pointer");
+  if (n_occ < 1 || n_vir < n_occ || n_aux < 1)
+    return fail(h, ESMP2_INVALID_ARG, "need 1 <= n_occ <= n_vir and n_aux >= 1");
+  if (n_occ + n_vir > FOCK_NMAX || n_aux > FOCK_AUXMAX)
+    return fail(h, ESMP2_INVALID_ARG, "sizes beyond the static workspace: n_occ + n_vir <= 256, n_aux <= 16384");
+  ESMP2_HIP(hipSetDevice(h->device));
+  double* ws = nullptr;
+  {
+    const esmp2_status st = scratch_address(h, &ws);
+    if (st != ESMP2_OK) return st;
+  }
+  const int n = n_occ + n_vir;
+  const int64_t nn = (int64_t)n * n;
+  hipStream_t s = h->stream;
+  double* gam = ws;
+  double* K = gam + nn;
+  double* d = K + nn;
+  double* T = d + n_aux;
+  hipLaunchKernelGGL(k_ref_density, dim3(nblk(nn)), dim3(256), 0, s, C, n_occ, n_vir, gam);
+  hipLaunchKernelGGL(k_coulomb_weights, dim3(n_aux), dim3(256), 0, s, B, (const double*)gam, n, d);
+  // K[p][q] = sum_Q sum_r (B[Q] gamma)[p][r] B[Q][r][q], FOCK_QCHUNK auxiliary
+  // indices at a time; the first chunk writes K (beta = 0), so nothing in the
+  // workspace needs clearing
+  for (int q0 = 0; q0 < n_aux; q0 += FOCK_QCHUNK) {
+    const int qc = std::min(FOCK_QCHUNK, n_aux - q0);
+    GemmArgs g{};
+    g.A = B + (int64_t)q0 * nn; g.B = gam; g.C = T; g.M = n; g.N = n; g.K = n;
+    g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1;
+    g.sCb = n; g.sCi = (int64_t)qc * n; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, qc, g));
+    g = GemmArgs{};
+    g.A = T; g.B = B + (int64_t)q0 * nn; g.C = K; g.M = n; g.N = n; g.K = qc * n;
+    g.sAi = (int64_t)qc * n; g.sAk = 1; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1;
+    g.beta = q0 == 0 ? 0.0 : 1.0;
+    ESMP2_HIP(gemm(s, 1, g));
+  }
+  hipLaunchKernelGGL(k_fock_combine, dim3(nblk(nn)), dim3(256), 0, s, hcore, B, (const double*)d, (const double*)K, n,
+                     n_aux, F_out);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
