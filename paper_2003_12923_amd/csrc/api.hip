@@ -101,7 +101,7 @@ struct esmp2_handle_ {
   double omega = 0, kappa = 0, e0 = 0, e2s = 0;
   int svd_sweeps = 0;
   // rhs
-  double *fphi, *fphi_part, *X, *Vint, *Mint, *b, *dinv, *blockmin, *partial, *sc;
+  double *fphi, *fphi_part, *X, *Vint, *Mint, *b, *blockmin, *partial, *sc;
   bool have_rhs = false;
   // sigma scratch
   double *S, *side, *side_tr;
@@ -118,12 +118,12 @@ struct esmp2_handle_ {
   // FP32 operator (Fock blocks rounded from the FP64 ones, work buffers) and
   // the FP32 vectors of the inner solves of the mixed-precision refinement
   float *Fd32, *Fl32, *fo32, *fv32, *fov32, *S32, *side32, *side_tr32;
-  float *d32, *r32, *p32, *q32, *dinv32;
+  float *d32, *r32, *p32, *q32;
+  float* dinv32;                 // Jacobi preconditioner (FP32, for the FP64 and the FP32 solves)
   // pinned-semicanonical basis: rotations (t and t' fixed), operator blocks, rotated rhs,
   // Jacobi diagonal, dense scratch of the amplitude rotation
   bool have_sc_op = false;       // the operator blocks of the pinned-semicanonical basis are built
   bool have_sc = false;          // ... and the right-hand side is rotated into that basis
-  bool dinv32_ok = false, dinv32_sc_ok = false;   // FP32 copies of the preconditioners, made on first use
   // side stream: the semicanonical eigenproblems run there while the main
   // stream builds the right-hand side (default priority, non-blocking)
   hipStream_t aux = nullptr;
@@ -136,7 +136,7 @@ struct esmp2_handle_ {
   bool e2s_pending = false;      // queued on the side stream, not yet joined by the main stream
   bool e2s_dev = false;          // the sum is on the device, not yet read into e2s
   bool sc_eig = false;           // To, Tv hold the rotation of the current TOP basis
-  double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *dinv_sc, *b_sc;
+  double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *b_sc;
   float *Fd32_sc, *Fl32_sc, *fo32_sc, *fv32_sc, *fov32_sc, *dinv32_sc;
   double *dense0, *dense1;
   double* gv;                    // row/column GEMVs of the arrow-shaped Fock blocks (FP64 or FP32 use)
@@ -414,7 +414,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
             dalloc(h, &h->fphi_part, (size_t)FPHI_QCHUNKS * no * nv + na) &&
             dalloc(h, &h->X, (size_t)na * no * nv) && dalloc(h, &h->Vint, (size_t)no * nv * no * nv) &&
             dalloc(h, &h->Mint, (size_t)no * nv * no * nv) && dalloc(h, &h->b, namp) &&
-            dalloc(h, &h->dinv, namp) && dalloc(h, &h->blockmin, nblk(namp)) &&
+            dalloc(h, &h->blockmin, nblk(namp)) &&
             dalloc(h, &h->partial, (size_t)4 * PCG_BLOCKS) && dalloc(h, &h->sc, SC_N) &&
             dalloc(h, &h->e2s_part, (size_t)E2S_CAP + 1) &&
             dalloc(h, &h->S, (size_t)no * no * nv * nv) &&
@@ -433,7 +433,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
        dalloc(h, &h->Fh, (size_t)n * n) && dalloc(h, &h->fo_sc, no * no) && dalloc(h, &h->fv_sc, (size_t)nv * nv) &&
        dalloc(h, &h->fov_sc, (size_t)no * nv) && dalloc(h, &h->eo_sc, no) && dalloc(h, &h->ev_sc, nv) &&
        dalloc(h, &h->Fd_sc, (size_t)mv * mv) && dalloc(h, &h->Fl_sc, (size_t)mv * mv) &&
-       dalloc(h, &h->dinv_sc, namp) && dalloc(h, &h->b_sc, namp) && dalloc(h, &h->Fd32_sc, (size_t)mv * mv) &&
+       dalloc(h, &h->b_sc, namp) && dalloc(h, &h->Fd32_sc, (size_t)mv * mv) &&
        dalloc(h, &h->Fl32_sc, (size_t)mv * mv) && dalloc(h, &h->fo32_sc, no * no) &&
        dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
        dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense) &&
@@ -741,9 +741,8 @@ static esmp2_status build_rhs(esmp2_handle h) {
   ESMP2_HIP(gemm(s, 1, g));
   RhsArgs ra{d, h->Vint, h->Mint, h->fphi, h->lam, h->b};
   hipLaunchKernelGGL(k_rhs, dim3(nblk(namp)), dim3(256), 0, s, ra);
-  DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv, h->blockmin};
+  DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv32, h->blockmin};
   hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
-  h->dinv32_ok = false;
   hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
   // E2_S on the side stream (after the eigenproblems queued there), beside the
   // solve: it reads Vint, lam, eo, ev, omega and the pair tables, which the
@@ -1094,9 +1093,8 @@ static esmp2_status semican_operator(esmp2_handle h) {
                      (int64_t)nv * nv);
   hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)no * nv)), dim3(256), 0, s, (const double*)h->fov_sc,
                      h->fov32_sc, (int64_t)no * nv);
-  DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv_sc, h->blockmin};
+  DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv32_sc, h->blockmin};
   hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
-  h->dinv32_sc_ok = false;
   ESMP2_HIP(hipGetLastError());
   h->have_sc_op = true;
   return ESMP2_OK;
@@ -1119,7 +1117,6 @@ static esmp2_status semican_setup(esmp2_handle h) {
 // Everything a solve needs in one basis
 struct OpCtx {
   const double* b;
-  const double* dinv;
   const float* dinv32;
   SigmaBufs<double> s64;
   SigmaBufs<float> s32;
@@ -1151,10 +1148,10 @@ static esmp2_status apply_op_dot(esmp2_handle h, const OpCtx& c, const SigmaBufs
   return ESMP2_OK;
 }
 
-static OpCtx ctx_top(esmp2_handle h) { return OpCtx{h->b, h->dinv, h->dinv32, bufs64(h), bufs32(h), false, false}; }
+static OpCtx ctx_top(esmp2_handle h) { return OpCtx{h->b, h->dinv32, bufs64(h), bufs32(h), false, false}; }
 
 static OpCtx ctx_sc(esmp2_handle h) {
-  OpCtx c{h->b_sc, h->dinv_sc, h->dinv32_sc, bufs64(h), bufs32(h), true, true};
+  OpCtx c{h->b_sc, h->dinv32_sc, bufs64(h), bufs32(h), true, true};
   c.s64.Fd = h->Fd_sc; c.s64.Fl = h->Fl_sc; c.s64.fo = h->fo_sc; c.s64.fv = h->fv_sc; c.s64.fov = h->fov_sc;
   c.s32.Fd = h->Fd32_sc; c.s32.Fl = h->Fl32_sc; c.s32.fo = h->fo32_sc; c.s32.fv = h->fv32_sc;
   c.s32.fov = h->fov32_sc;
@@ -1343,11 +1340,11 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
     }
     esmp2_status st = apply_op(h, c, c.s64, (const double*)h->x, h->q);
     if (st != ESMP2_OK) return st;
-    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, h->q, h->r, h->p, c.dinv, n, d.off[1], d.off[2],
+    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, h->q, h->r, h->p, c.dinv32, n, d.off[1], d.off[2],
                        h->partial);
   } else {
     ESMP2_HIP(hipMemsetAsync(h->x, 0, sizeof(double) * n, s));
-    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv, n,
+    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv32, n,
                        d.off[1], d.off[2], h->partial);
   }
   // rho = <r, D^-1 r> into SC_RHO and <r, r> into SC_RHO + 1 = SC_PQ
@@ -1362,8 +1359,8 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   while (rel > opts->tol && it < opts->max_iter) {
     esmp2_status st = apply_op_dot(h, c, c.s64, (const double*)h->p, h->q);
     if (st != ESMP2_OK) return st;
-    hipLaunchKernelGGL(k_update_xr<double>, dim3(NB), dim3(256), 0, s, h->x, h->r, h->p, h->q, c.dinv, n, d.off[1],
-                       d.off[2], h->sc, h->partial);
+    hipLaunchKernelGGL(k_update_r<double>, dim3(NB), dim3(256), 0, s, h->r, (const double*)h->q, c.dinv32, n,
+                       d.off[1], d.off[2], (const double*)h->sc, h->partial);
     hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);  // RHO_NEW, RR
     ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
     ESMP2_HIP(hipStreamSynchronize(s));
@@ -1371,8 +1368,13 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
     ++it;
     rel = sqrt(hs[SC_RR]) / bn;
     if (opts->resid_hist) opts->resid_hist[it - 1] = rel;
-    if (rel <= opts->tol) break;
-    hipLaunchKernelGGL(k_update_p<double>, dim3(NB), dim3(256), 0, s, h->p, h->r, c.dinv, n, h->sc);
+    if (rel <= opts->tol || it >= opts->max_iter) {   // last step: x += alpha p only
+      hipLaunchKernelGGL(k_update_x<double>, dim3(NB), dim3(256), 0, s, h->x, (const double*)h->p, n,
+                         (const double*)h->sc);
+      break;
+    }
+    hipLaunchKernelGGL(k_update_px<double>, dim3(NB), dim3(256), 0, s, h->x, h->p, (const double*)h->r, c.dinv32, n,
+                       (const double*)h->sc);
     hipLaunchKernelGGL(k_roll_rho, dim3(1), dim3(64), 0, s, h->sc);
   }
   if (status == ESMP2_OK && rel > opts->tol) { status = ESMP2_NOT_CONVERGED; h->err = "max_iter reached"; }
@@ -1393,13 +1395,6 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
   // an operator with BF16 operands is accurate to ~1e-3 relative: ask its inner
   // solves for two digits and let the FP64 refinement do the rest
   const double floor_eta = opts->inner_tol > 0 ? opts->inner_tol : (c.s32.prec == ESMP2_BF16 ? 1e-2 : 1e-5);
-  // the FP32 preconditioner of the inner solves, made once per right-hand side and basis
-  bool& d32_ok = c.rotated ? h->dinv32_sc_ok : h->dinv32_ok;
-  if (!d32_ok) {
-    hipLaunchKernelGGL(k_to_f32, dim3(NB), dim3(256), 0, s, c.rotated ? (const double*)h->dinv_sc : (const double*)h->dinv,
-                       c.rotated ? h->dinv32_sc : h->dinv32, n);
-    d32_ok = true;
-  }
   wdot(h, c.b, c.b, SC_BB);
   if (opts->x0) {
     if (c.rotated) {
@@ -1438,9 +1433,8 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
     while (it < opts->max_iter) {
       esmp2_status st = apply_op_dot(h, c, c.s32, (const float*)h->p32, h->q32);
       if (st != ESMP2_OK) return st;
-      hipLaunchKernelGGL(k_update_xr<float>, dim3(NB), dim3(256), 0, s, h->d32, h->r32, (const float*)h->p32,
-                         (const float*)h->q32, c.dinv32, n, d.off[1], d.off[2], (const double*)h->sc,
-                         h->partial);
+      hipLaunchKernelGGL(k_update_r<float>, dim3(NB), dim3(256), 0, s, h->r32, (const float*)h->q32, c.dinv32, n,
+                         d.off[1], d.off[2], (const double*)h->sc, h->partial);
       hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO_NEW);
       ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
       ESMP2_HIP(hipStreamSynchronize(s));
@@ -1448,8 +1442,12 @@ static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solv
       ++it;
       const double irel = sqrt(hs[SC_RR] / rr0);
       if (opts->resid_hist) opts->resid_hist[it - 1] = irel * rel;   // estimate of the FP64 residual
-      if (irel <= eta) break;
-      hipLaunchKernelGGL(k_update_p<float>, dim3(NB), dim3(256), 0, s, h->p32, (const float*)h->r32,
+      if (irel <= eta || it >= opts->max_iter) {   // last step of this inner solve: d += alpha p only
+        hipLaunchKernelGGL(k_update_x<float>, dim3(NB), dim3(256), 0, s, h->d32, (const float*)h->p32, n,
+                           (const double*)h->sc);
+        break;
+      }
+      hipLaunchKernelGGL(k_update_px<float>, dim3(NB), dim3(256), 0, s, h->d32, h->p32, (const float*)h->r32,
                          c.dinv32, n, (const double*)h->sc);
       hipLaunchKernelGGL(k_roll_rho, dim3(1), dim3(64), 0, s, h->sc);
     }

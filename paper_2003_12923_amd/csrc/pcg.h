@@ -8,11 +8,13 @@ constexpr int PCG_BLOCKS = 1024;
 template <class T> __global__ void k_dot(const T* x, const T* y, int64_t n, int64_t s0, int64_t s1, double* partial);
 __global__ void k_finish(const double* partial, int nb, double* sc, int base);
 template <class T>
-__global__ void k_update_xr(T* x, T* r, const T* p, const T* q, const T* dinv, int64_t n, int64_t s0, int64_t s1,
-                            const double* sc, double* partial);
-template <class T> __global__ void k_update_p(T* p, const T* r, const T* dinv, int64_t n, const double* sc);
+__global__ void k_update_r(T* r, const T* q, const float* dinv, int64_t n, int64_t s0, int64_t s1, const double* sc,
+                           double* partial);
+template <class T>
+__global__ void k_update_px(T* x, T* p, const T* r, const float* dinv, int64_t n, const double* sc);
+template <class T> __global__ void k_update_x(T* x, const T* p, int64_t n, const double* sc);
 __global__ void k_roll_rho(double* sc);
-__global__ void k_init(const double* b, const double* y, double* r, double* p, const double* dinv, int64_t n,
+__global__ void k_init(const double* b, const double* y, double* r, double* p, const float* dinv, int64_t n,
                        int64_t s0, int64_t s1, double* partial);
 __global__ void k_resid(const double* b, const double* y, double* r, int64_t n, int64_t s0, int64_t s1,
                         double* partial);

@@ -63,27 +63,32 @@ __global__ void k_finish(const double* partial, int nb, double* sc, int base) {
   if (threadIdx.x == 0) sc[base + blockIdx.x] = s;
 }
 
-// alpha = sc[RHO] / sc[PQ];  x += alpha p;  r -= alpha q;
-// partials of <r, D^-1 r>_W and <r, r>_W (two partial arrays of gridDim.x each)
+// The preconditioner M = D^-1 is stored in FP32 (rounded once): any fixed
+// symmetric positive diagonal is a valid Jacobi preconditioner, the iterates,
+// residuals and E2 stay FP64, and the vector passes read half the bytes.
+//
+// alpha = sc[RHO] / sc[PQ];  r -= alpha q;  partials of <r, M r>_W and <r, r>_W
+// (two partial arrays of gridDim.x each).  x is updated with p in k_update_px,
+// which reads p anyway.
 template <class T>
-__global__ __launch_bounds__(256) void k_update_xr(T* x, T* r, const T* p, const T* q, const T* dinv, int64_t n,
-                                                   int64_t s0, int64_t s1, const double* sc, double* partial) {
+__global__ __launch_bounds__(256) void k_update_r(T* r, const T* q, const float* dinv, int64_t n, int64_t s0,
+                                                  int64_t s1, const double* sc, double* partial) {
   const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
   double rz = 0.0, rr = 0.0;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
-    T xv[PCG_U], rv[PCG_U], pv[PCG_U], qv[PCG_U], dv[PCG_U];
+    T rv[PCG_U], qv[PCG_U];
+    float dv[PCG_U];
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      xv[u] = x[gg]; rv[u] = r[gg]; pv[u] = p[gg]; qv[u] = q[gg]; dv[u] = dinv[gg];
+      rv[u] = r[gg]; qv[u] = q[gg]; dv[u] = dinv[gg];
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
       if (g < n) {
         const T rg = rv[u] - alpha * qv[u];
-        x[g] = xv[u] + alpha * pv[u];
         r[g] = rg;
         const double w = wgt(g, s0, s1), rd = (double)rg;
         rz += w * rd * rd * (double)dv[u];
@@ -96,22 +101,48 @@ __global__ __launch_bounds__(256) void k_update_xr(T* x, T* r, const T* p, const
   if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = b; }
 }
 
-// p = D^-1 r + beta p,  beta = sc[RHO_NEW] / sc[RHO]
+// alpha = sc[RHO] / sc[PQ], beta = sc[RHO_NEW] / sc[RHO]:  x += alpha p;  p = M r + beta p
 template <class T>
-__global__ __launch_bounds__(256) void k_update_p(T* p, const T* r, const T* dinv, int64_t n, const double* sc) {
+__global__ __launch_bounds__(256) void k_update_px(T* x, T* p, const T* r, const float* dinv, int64_t n,
+                                                   const double* sc) {
+  const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
   const T beta = (T)(sc[SC_RHO_NEW] / sc[SC_RHO]);
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
-    T pv[PCG_U], rv[PCG_U], dv[PCG_U];
+    T xv[PCG_U], pv[PCG_U], rv[PCG_U];
+    float dv[PCG_U];
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      pv[u] = p[gg]; rv[u] = r[gg]; dv[u] = dinv[gg];
+      xv[u] = x[gg]; pv[u] = p[gg]; rv[u] = r[gg]; dv[u] = dinv[gg];
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
-      if (g < n) p[g] = dv[u] * rv[u] + beta * pv[u];
+      if (g < n) {
+        x[g] = xv[u] + alpha * pv[u];
+        p[g] = (T)dv[u] * rv[u] + beta * pv[u];
+      }
+    }
+  }
+}
+
+// x += alpha p, alpha = sc[RHO] / sc[PQ]: the update of the last iteration
+template <class T>
+__global__ __launch_bounds__(256) void k_update_x(T* x, const T* p, int64_t n, const double* sc) {
+  const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    T xv[PCG_U], pv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      xv[u] = x[gg]; pv[u] = p[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) x[g] = xv[u] + alpha * pv[u];
     }
   }
 }
@@ -120,14 +151,15 @@ __global__ void k_roll_rho(double* sc) {
   if (threadIdx.x == 0) sc[SC_RHO] = sc[SC_RHO_NEW];
 }
 
-// r = -b - y (y = A x0) or r = -b;  p = D^-1 r;  partials of <r, D^-1 r>, <r, r>
+// r = -b - y (y = A x0) or r = -b;  p = M r;  partials of <r, M r>, <r, r>
 __global__ __launch_bounds__(256) void k_init(const double* b, const double* y, double* r, double* p,
-                                              const double* dinv, int64_t n, int64_t s0, int64_t s1,
+                                              const float* dinv, int64_t n, int64_t s0, int64_t s1,
                                               double* partial) {
   double rz = 0.0, rr = 0.0;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
-    double bv[PCG_U], yv[PCG_U], dv[PCG_U];
+    double bv[PCG_U], yv[PCG_U];
+    float dv[PCG_U];
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
@@ -139,9 +171,9 @@ __global__ __launch_bounds__(256) void k_init(const double* b, const double* y, 
       if (g < n) {
         const double rg = -bv[u] - yv[u];
         r[g] = rg;
-        p[g] = dv[u] * rg;
+        p[g] = (double)dv[u] * rg;
         const double w = wgt(g, s0, s1);
-        rz += w * rg * rg * dv[u];
+        rz += w * rg * rg * (double)dv[u];
         rr += w * rg * rg;
       }
     }
@@ -240,11 +272,13 @@ __global__ void k_to_f32(const double* a, float* b, int64_t n) {
 
 template __global__ void k_dot<double>(const double*, const double*, int64_t, int64_t, int64_t, double*);
 template __global__ void k_dot<float>(const float*, const float*, int64_t, int64_t, int64_t, double*);
-template __global__ void k_update_xr<double>(double*, double*, const double*, const double*, const double*, int64_t,
-                                             int64_t, int64_t, const double*, double*);
-template __global__ void k_update_xr<float>(float*, float*, const float*, const float*, const float*, int64_t,
-                                            int64_t, int64_t, const double*, double*);
-template __global__ void k_update_p<double>(double*, const double*, const double*, int64_t, const double*);
-template __global__ void k_update_p<float>(float*, const float*, const float*, int64_t, const double*);
+template __global__ void k_update_r<double>(double*, const double*, const float*, int64_t, int64_t, int64_t,
+                                           const double*, double*);
+template __global__ void k_update_r<float>(float*, const float*, const float*, int64_t, int64_t, int64_t,
+                                          const double*, double*);
+template __global__ void k_update_px<double>(double*, double*, const double*, const float*, int64_t, const double*);
+template __global__ void k_update_px<float>(float*, float*, const float*, const float*, int64_t, const double*);
+template __global__ void k_update_x<double>(double*, const double*, int64_t, const double*);
+template __global__ void k_update_x<float>(float*, const float*, int64_t, const double*);
 
 }  // namespace esmp2

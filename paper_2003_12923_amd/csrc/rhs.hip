@@ -203,7 +203,7 @@ struct DiagArgs {
   const double* eo;     // TOP-basis occupied orbital energies F~_ii
   const double* ev;     // TOP-basis virtual orbital energies F~_aa
   double omega;
-  double* dinv;
+  float* dinv;          // the Jacobi preconditioner 1/D, rounded once to FP32
   double* blockmin;
 };
 
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_diag(DiagArgs A) {
     int loc;
     int box = box_of(A.d, g, loc);
     double D = diag_of(A.d, box, loc, A.eo, A.ev, A.omega);
-    A.dinv[g] = 1.0 / D;
+    A.dinv[g] = (float)(1.0 / D);
     mn = D;
   }
   // block minimum
