@@ -15,6 +15,11 @@ the operator of the pinned-semicanonical basis (``topbasis.pinned_semicanonical`
 the occupied orbitals other than t and the virtuals other than t' rotated to
 diagonalise their Fock blocks), at the same sampled indices.
 
+Names "topk_<n_occ>_<n_vir>_<n_aux>_<seed>_<k>" hold ESMP2-TOP(k) values of
+``oracle.topk`` (k large TOPs): E2 and its parts, E0, and sampled elements
+of b and of sigma of a seeded random vector (layout of the TOP(k) sets,
+operator-string phase of the one-TOP layout), on ``synth.make_problem``.
+
 Names ending in "_triplet" hold the same quantities for the M_s = 0 triplet
 reference (beta singles with the opposite sign).
 
@@ -95,6 +100,26 @@ def run_semican(name):
                 sigma_sample=sig[idx].tolist(), seconds=time.time() - t0)
 
 
+def run_topk(name):
+    no, nv, na, seed, k = (int(v) for v in name.split("_")[1:])
+    p = synth.make_problem(no, nv, na, seed)
+    t0 = time.time()
+    lam, R = topbasis.top_rotation(p.F, p.C, no)
+    Ft, Bt = topbasis.rotate(p.F, p.B, R)
+    from oracle import topk
+    tk = topk.TopK(Ft, Bt, lam, no, k)
+    r = tk.solve(tol=1e-11, max_iter=400)
+    xr = np.where(tk.live, synth.random_amplitudes(tk.dim, 4321), 0.0)
+    sig = tk.phase * tk.sigma(tk.phase * xr)          # operator-string phase on both sides
+    rng = np.random.default_rng(77)
+    live = np.where(tk.live)[0]
+    idx = sorted(set(int(i) for i in rng.choice(live, 400, replace=False)))
+    return dict(n_occ=no, n_vir=nv, n_aux=na, seed=seed, n_top=k, dim=tk.dim, e2=r["e2"], e2_dl=r["e2_dl"],
+                e2_s=r["e2_s"], e0=r["e0"], iters=r["iters"], rel_resid=r["rel"], sample_idx=idx,
+                b_sample=(tk.phase * r["b"])[idx].tolist(), sigma_seed=4321, sigma_sample=sig[idx].tolist(),
+                seconds=time.time() - t0)
+
+
 def run_batched():
     states = []
     for (no, nv, na, seed) in synth.batched_sizes():
@@ -149,6 +174,11 @@ if __name__ == "__main__":
         if nm.endswith("_triplet"):
             data[nm] = run(nm[:-8], spin=1)
             print(nm, data[nm]["e2"], data[nm]["iters"], data[nm]["seconds"], flush=True)
+            json.dump(data, open(path, "w"), indent=1)
+            continue
+        if nm.startswith("topk_"):
+            data[nm] = run_topk(nm)
+            print(nm, data[nm]["e2"], "%.1fs" % data[nm]["seconds"], flush=True)
             json.dump(data, open(path, "w"), indent=1)
             continue
         if nm.endswith("_semican"):

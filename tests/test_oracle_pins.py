@@ -555,3 +555,80 @@ def test_flop_count_scaling_exponents():
     so = np.polyfit(np.log(O), np.log([costs.sigma_nnz(int(o), 100)["total"] for o in O]), 1)[0]
     sv = np.polyfit(np.log(V), np.log([costs.sigma_nnz(30, int(v))["total"] for v in V]), 1)[0]
     assert so + sv < 5.05
+
+
+def _topk_case(no, nv, na, seed, k, spin):
+    from oracle import topk
+    p, lam, Ft, Bt = _rotated(no, nv, na, seed)
+    ex = explicit.ExplicitESMP2(Ft, topbasis.eri_from_factor(Bt), lam, no, n_top=k, sign=-1 if spin else 1)
+    r1 = ex.solve(dense=True)
+    tk = topk.TopK(Ft, Bt, lam, no, k, spin=spin)
+    return ex, r1, tk
+
+
+@pytest.mark.parametrize("no,nv,na,seed,k,spin", [(2, 3, 4, 0, 2, 0), (3, 4, 6, 1, 2, 0), (3, 5, 6, 2, 3, 0),
+                                                  (3, 5, 7, 3, 2, 1), (4, 5, 6, 4, 2, 0), (4, 5, 6, 4, 4, 0),
+                                                  (3, 4, 6, 1, 1, 0)])
+def test_topk_equals_explicit(no, nv, na, seed, k, spin):
+    """TOP(k) (paper Sec. II.C: L = triples containing any large TOP, up to
+    TOP(all)): the oracle's determinant-level operator, right-hand side, S-triple
+    energy and E2 equal the explicit construction with k large TOPs, and the
+    layout covers every determinant of D + L exactly once."""
+    from oracle import topk
+    ex, r1, tk = _topk_case(no, nv, na, seed, k, spin)
+    dets = tk.determinants()
+    live = np.where(tk.live)[0]
+    idx = np.array([ex.index[dets[i]] for i in live])
+    assert len(set(idx)) == len(idx)
+    nons2 = [i for i in live if tk.box[i] != 1]
+    assert len(live) + len(nons2) == len(ex.DL)               # own determinants + spin-flip partners
+    b = tk.rhs()
+    np.testing.assert_allclose(b[live], ex.b[idx], rtol=0, atol=1e-14 * max(1.0, np.abs(ex.b).max()))
+    rng = np.random.default_rng(seed + 7)
+    x = np.where(tk.live, rng.standard_normal(tk.dim), 0.0)
+    cx = tk._coeff(x)
+    c = np.zeros(len(ex.DL))
+    c[idx] = cx[live]
+    fh, fp = tk._flip(tk.holes), tk._flip(tk.parts)
+    for i in nons2:
+        d = tk.phi
+        for v in fh[i]:
+            if v != topk.SENT:
+                d ^= 1 << int(v)
+        for v in fp[i]:
+            if v != topk.SENT:
+                d |= 1 << int(v)
+        c[ex.index[d]] = tk.sg * cx[i]
+    yd = ex.A @ c
+    y = tk.sigma(x)
+    assert np.abs(y[live] - yd[idx]).max() <= 1e-13 * np.abs(yd).max()
+    r2 = tk.solve(tol=1e-13)
+    assert abs(r2["e2"] - r1["e2"]) < 1e-13 * abs(r1["e2"])
+    assert abs(r2["e2_s"] - r1["e2_s"]) < 1e-13 * abs(r1["e2"])
+
+
+def test_topk_one_equals_structured():
+    """TOP(1) through the generic TOP(k) operator equals the seven-box oracle
+    (same layout, canonical versus operator-string phase) at a size the explicit
+    construction cannot reach."""
+    from oracle import topk
+    p, lam, Ft, Bt = _rotated(4, 12, 14, 9)
+    tk = topk.TopK(Ft, Bt, lam, 4, 1)
+    st = structured.Structured(Ft, lam, 4)
+    x = synth.random_amplitudes(st.dim, 3)
+    y = tk.phase * tk.sigma(tk.phase * x)
+    ref = st.sigma(x)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    r = tk.solve(tol=1e-12)
+    r1 = structured.solve(Ft, Bt, lam, 4, tol=1e-12)
+    assert abs(r["e2"] - r1["e2"]) < 1e-12 * abs(r1["e2"])
+
+
+def test_topk_more_large_tops_lower_e2_s_share():
+    """Moving TOPs from S into L: with every TOP large (TOP(all)) the S-triple
+    space is empty (Sec. III.B, Table II), so E2_S = 0; E2 changes with k."""
+    from oracle import topk
+    p, lam, Ft, Bt = _rotated(3, 5, 6, 2)
+    rs = [topk.TopK(Ft, Bt, lam, 3, k).solve(tol=1e-13) for k in (1, 2, 3)]
+    assert abs(rs[2]["e2_s"]) < 1e-13 * abs(rs[0]["e2_s"])
+    assert abs(rs[0]["e2"] - rs[1]["e2"]) > 1e-12 and abs(rs[1]["e2"] - rs[2]["e2"]) > 1e-12
