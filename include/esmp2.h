@@ -22,7 +22,12 @@
  *     and a factor B with (pq|rs) = sum_Q B[Q][p][q] B[Q][r][s]; the one-electron
  *     operator is h = F - G[gamma(Psi0)].
  *   - Reference: Psi0 = sum_ia C[i][a] (E^up_ai + E^dn_ai)/sqrt(2) |Phi>, singlet,
- *     ||C||_F = 1.  Only n_top = 1 (one large TOP, "ESMP2-TOP(1)") is supported.
+ *     ||C||_F = 1.
+ *   - Large TOPs (paper Sec. II.C): the n_top TOPs of the largest singular values
+ *     are "large"; the L-triples are the triples containing a large TOP (spatial
+ *     occupied l among the holes and spatial virtual l' among the particles).
+ *     n_top = 1 is ESMP2-TOP(1), the default and fast path; n_top = n_occ is
+ *     TOP(all).
  *   - TOP basis: singular values in descending order; the TOP virtual of occupied
  *     l is virtual l; the remaining virtuals (AVOs) diagonalise the Fock matrix in
  *     their span (ascending).  Every occupied TOP orbital and AVO is signed so that
@@ -41,6 +46,13 @@
  *     (u/d = spin up/down).  Boxes other than S2 stand for a spin-flip pair of
  *     determinants (inner-product weight 2); S2 entries are single determinants
  *     (weight 1) and enter the operator flip-symmetrised.
+ *   - With n_top = k > 1 the vector holds the boxes above (set 0, TOP t = 0) and
+ *     then, for each further large TOP s = 1 .. k-1, the five L-boxes 2..6 again
+ *     with TOP s in place of TOP 0 (occupied orbitals 0 and s swapped, virtuals
+ *     0' and s' swapped in the operator strings): set s starts at
+ *     box_offsets[2] + s (box_offsets[7] - box_offsets[2]).  A triple that
+ *     contains a larger TOP r < s is stored in set r only; its slot in set s is
+ *     masked (always zero).
  *
  * Memory and streams
  *   - A handle is bound to one device and one stream at creation.  All work is
@@ -73,7 +85,7 @@ typedef enum {
   ESMP2_NOT_CONVERGED = 4,  /* max_iter reached; result holds the partial state     */
   ESMP2_OOM = 5,            /* device allocation failed                              */
   ESMP2_HIP_ERROR = 6,      /* a HIP runtime call failed                             */
-  ESMP2_UNSUPPORTED = 7     /* option not implemented (n_top != 1, triplet, ...)     */
+  ESMP2_UNSUPPORTED = 7     /* option not implemented for these sizes / this mode    */
 } esmp2_status;
 
 typedef enum {
@@ -136,7 +148,13 @@ esmp2_status esmp2_destroy(esmp2_handle h);
  *   spin: 0 = singlet reference, 1 = the M_s = 0 component of the triplet
  *         (paper Sec. II.A: the beta singles enter Psi0 with the opposite
  *         sign; the first-order amplitudes are then antisymmetric under the
- *         flip of every spin); n_top: 1 (only value supported).
+ *         flip of every spin)
+ *   n_top: number of large TOPs, 1 <= n_top <= n_occ (else ESMP2_INVALID_ARG).
+ *         n_top > 1 (ESMP2-TOP(k), up to TOP(all)) applies the operator by a
+ *         generic determinant-level kernel, O(N_o + N_v) per amplitude, and
+ *         supports the FP64 solve in the TOP basis, esmp2_sigma (FP64),
+ *         esmp2_build_rhs and esmp2_export_determinants; the other calls
+ *         return ESMP2_UNSUPPORTED.
  * Requires 2 <= n_occ <= n_vir, n_aux >= 1.  Checks F, B, C for NaN/Inf
  * (synchronises the stream).  Resets any previous problem. */
 esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux,
@@ -165,7 +183,9 @@ esmp2_status esmp2_set_problem_top(esmp2_handle h, int n_occ, int n_vir, int n_a
 esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out);
 
 /* Size of the amplitude vector and the start offsets of the seven boxes;
- * box_offsets has 8 entries (box_offsets[7] == *n_amp).  Either may be NULL. */
+ * box_offsets has 8 entries (box_offsets[7] == *n_amp for n_top = 1; for n_top
+ * = k > 1, *n_amp = box_offsets[2] + k (box_offsets[7] - box_offsets[2]) and
+ * the offsets are those of set 0).  Either may be NULL. */
 esmp2_status esmp2_space(esmp2_handle h, int64_t* n_amp, int64_t* box_offsets);
 
 /* Right-hand side b_mu = <mu|H|Psi0> on the seven boxes, E0 and the
@@ -217,7 +237,8 @@ esmp2_status esmp2_sigma_basis(esmp2_handle h, const void* x, void* y, int preci
  *      (x + sg x_partner)/2, sg = +1 singlet, -1 triplet; a flip partner
  *      outside S2 carries sg x).  Coefficient = phase of the amplitude's
  *      operator string (the layout table above) in the canonical order, times
- *      the amplitude.
+ *      the amplitude.  With n_top > 1, n_amp is the TOP(k) size and a masked
+ *      slot writes key -1 and coefficient 0 in both of its entries.
  *   det_key: the determinant as its excitation from the closed shell: holes in
  *      bits 0-29 and particles in bits 30-59, 10 bits per spin-orbital, each
  *      group ascending, 1023 in the unused third slots of a double.

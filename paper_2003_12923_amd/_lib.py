@@ -203,14 +203,14 @@ class Handle:
         return self._check(lib.esmp2_gemm_f64(self.h, m, n, k, _ptr(A), _ptr(B), _ptr(Cm)))
 
     # convenience: bind a synthetic problem held in numpy arrays
-    def load(self, prob, spin=0):
+    def load(self, prob, spin=0, n_top=1):
         import torch
         dev = f"cuda:{self.device}"
         self._F = torch.from_numpy(prob.F).to(dev)
         self._B = torch.from_numpy(prob.B).to(dev)
         self._C = torch.from_numpy(prob.C).to(dev)
         self._n_occ = prob.n_occ
-        self.set_problem(self._F, self._B, self._C, prob.n_occ, prob.n_vir, prob.n_aux, spin=spin)
+        self.set_problem(self._F, self._B, self._C, prob.n_occ, prob.n_vir, prob.n_aux, spin=spin, n_top=n_top)
         return self
 
 

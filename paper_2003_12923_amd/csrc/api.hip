@@ -30,6 +30,10 @@ __global__ void k_finite(const double* v, int64_t n, int* bad) {
     if (!isfinite(v[g])) bad[0] = 1;
 }
 
+__global__ void k_add_to(double* dst, const double* src) {
+  if (threadIdx.x == 0) dst[0] += src[0];
+}
+
 __global__ void k_sub_identity(double* E, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) E[(int64_t)i * n + i] -= 1.0;
@@ -91,6 +95,11 @@ struct esmp2_handle_ {
   double* gws = nullptr;         // workspace of the gradient (allocated on first use)
   size_t gws_n = 0;
   Dims d{};
+  int ntop = 1;                  // large TOPs (ESMP2-TOP(k)); k > 1: the TOP(k) layout and operator
+  int64_t namp = 0;              // amplitudes: off[7] for one large TOP, off[2] + k (off[7] - off[2]) for k
+  signed char* s0 = nullptr;     // TOP(k): canonical phase of every element's operator string (0: masked slot)
+  double *Ft_s = nullptr, *Bov_s = nullptr, *Bvt_s = nullptr, *Boo_s = nullptr, *lam_s = nullptr;   // relabelled inputs
+  double* btmp = nullptr;        // TOP(k): one-TOP right-hand side of one relabelled problem
   std::vector<void*> allocs;     // everything owned, freed at reset/destroy
   // inputs
   double *F = nullptr, *B = nullptr, *C = nullptr;
@@ -379,6 +388,20 @@ esmp2_status esmp2_gemm_f64(esmp2_handle h, int m, int n, int k, const double* A
   return ESMP2_OK;
 }
 
+// kernel arguments of the TOP(k) path
+static TopkArgs topk_args(esmp2_handle h) {
+  TopkArgs a{};
+  a.d = h->d;
+  a.k = h->ntop;
+  a.L1 = h->d.off[7] - h->d.off[2];
+  a.namp = h->namp;
+  a.Ft = h->Ft;
+  a.omega = h->omega;
+  a.sg = h->d.sg;
+  a.s0 = h->s0;
+  return a;
+}
+
 static esmp2_status check_sizes(esmp2_handle h, int n_occ, int n_vir, int n_aux) {
   if (n_occ < 2 || n_vir < n_occ || n_aux < 1)
     return fail(h, ESMP2_INVALID_ARG, "need 2 <= n_occ <= n_vir and n_aux >= 1");
@@ -391,7 +414,7 @@ static esmp2_status check_sizes(esmp2_handle h, int n_occ, int n_vir, int n_aux)
 // either C (the ESMF singles, rotated to the TOP basis later) or, for a problem
 // already in the TOP basis, its singular values lam.
 static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* F,
-                                  const double* B, const double* C, const double* lam, int spin) {
+                                  const double* B, const double* C, const double* lam, int spin, int n_top) {
   ESMP2_HIP(hipSetDevice(h->device));
   ESMP2_HIP(hipStreamSynchronize(h->stream));
   release(h);
@@ -399,7 +422,9 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
   d.sg = spin ? -1 : 1;
   h->d = d;
   const int no = n_occ, nv = n_vir, n = d.n, na = n_aux, mv = d.mv;
-  const int64_t namp = d.off[7];
+  h->ntop = n_top;
+  h->namp = d.off[2] + (int64_t)n_top * (d.off[7] - d.off[2]);
+  const int64_t namp = h->namp;
   bool ok = dalloc(h, &h->F, (size_t)n * n) && dalloc(h, &h->B, (size_t)na * n * n) &&
             dalloc(h, &h->C, (size_t)no * nv) && dalloc(h, &h->lam, no) && dalloc(h, &h->U, no * no) &&
             dalloc(h, &h->V, (size_t)nv * no) && dalloc(h, &h->rs, (size_t)11 * nv * nv) &&
@@ -416,7 +441,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
             dalloc(h, &h->Mint, (size_t)no * nv * no * nv) && dalloc(h, &h->b, namp) &&
             dalloc(h, &h->blockmin, nblk(namp)) &&
             dalloc(h, &h->partial, (size_t)4 * PCG_BLOCKS) && dalloc(h, &h->sc, SC_N) &&
-            dalloc(h, &h->e2s_part, (size_t)E2S_CAP + 1) &&
+            dalloc(h, &h->e2s_part, (size_t)E2S_CAP + 2) &&
             dalloc(h, &h->S, (size_t)no * no * nv * nv) &&
             dalloc(h, &h->side, (size_t)nv * (3 * d.npo1 + 2 * d.npo + 3 * d.npo + 5 * (no - 1) * (no - 1))) &&
             dalloc(h, &h->side_tr, (size_t)nv * (d.npo + (no - 1) * (no - 1))) &&
@@ -438,6 +463,10 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
        dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
        dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense) &&
        dalloc(h, &h->gv, (size_t)nv * (2 * d.npo + 2 * no * no + (no - 1) * (no - 1)));
+  if (n_top > 1)
+    ok = ok && dalloc(h, &h->s0, namp) && dalloc(h, &h->Ft_s, (size_t)n * n) &&
+         dalloc(h, &h->Bov_s, (size_t)na * no * nv) && dalloc(h, &h->Bvt_s, (size_t)na * nv * no) &&
+         dalloc(h, &h->Boo_s, (size_t)na * no * no) && dalloc(h, &h->lam_s, no) && dalloc(h, &h->btmp, d.off[7]);
   if (!ok) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
   // vv job table
   std::vector<int2> jobs;
@@ -517,6 +546,11 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
   ESMP2_HIP(hipStreamSynchronize(h->stream));
   if (h->pin->bad[0]) { release(h); return fail(h, ESMP2_INVALID_ARG, C ? "NaN or Inf in F, B or C" : "NaN or Inf in F, B or lam"); }
   h->top_given = (C == nullptr);
+  if (n_top > 1) {
+    const TopkArgs ta = topk_args(h);
+    hipLaunchKernelGGL(k_topk_phase, dim3(nblk(namp)), dim3(256), 0, h->stream, ta, h->s0);
+    ESMP2_HIP(hipGetLastError());
+  }
   h->state = 1;
   return ESMP2_OK;
 }
@@ -528,8 +562,8 @@ esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux, 
   esmp2_status st = check_sizes(h, n_occ, n_vir, n_aux);
   if (st != ESMP2_OK) return st;
   if (spin != 0 && spin != 1) return fail(h, ESMP2_INVALID_ARG, "spin must be 0 (singlet) or 1 (triplet)");
-  if (n_top != 1) return fail(h, ESMP2_UNSUPPORTED, "only n_top = 1 (ESMP2-TOP(1)) is implemented");
-  return setup_problem(h, n_occ, n_vir, n_aux, F, B, C, nullptr, spin);
+  if (n_top < 1 || n_top > n_occ) return fail(h, ESMP2_INVALID_ARG, "n_top must lie in [1, n_occ]");
+  return setup_problem(h, n_occ, n_vir, n_aux, F, B, C, nullptr, spin, n_top);
 }
 
 esmp2_status esmp2_set_problem_top(esmp2_handle h, int n_occ, int n_vir, int n_aux, const double* Ft,
@@ -548,7 +582,7 @@ esmp2_status esmp2_set_problem_top(esmp2_handle h, int n_occ, int n_vir, int n_a
     s2 += l[k] * l[k];
   }
   if (!(fabs(s2 - 1.0) <= 1e-10)) return fail(h, ESMP2_INVALID_ARG, "sum of lam^2 must be 1 (normalised reference)");
-  return setup_problem(h, n_occ, n_vir, n_aux, Ft, Bt, nullptr, lam, spin);
+  return setup_problem(h, n_occ, n_vir, n_aux, Ft, Bt, nullptr, lam, spin, 1);
 }
 
 esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
@@ -708,8 +742,36 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
 esmp2_status esmp2_space(esmp2_handle h, int64_t* n_amp, int64_t* box_offsets) {
   if (!h) return ESMP2_INVALID_ARG;
   if (h->state < 1) return fail(h, ESMP2_BAD_ORDER, "esmp2_set_problem first");
-  if (n_amp) *n_amp = h->d.off[7];
+  if (n_amp) *n_amp = h->namp;
   if (box_offsets) for (int k = 0; k < 8; ++k) box_offsets[k] = h->d.off[k];
+  return ESMP2_OK;
+}
+
+// The one-TOP right-hand side b_mu = <mu|H|Psi0> of the problem given by its
+// TOP-basis blocks (Ft, Bov, Bvt, Boo, lam) into b (one-TOP layout); scratch:
+// fphi, X, Vint, Mint.
+static esmp2_status rhs_core(esmp2_handle h, const double* Ft, const double* Bov, const double* Bvt,
+                             const double* Boo, const double* lam, double* b) {
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
+  hipStream_t s = h->stream;
+  double* dq = h->fphi_part + (size_t)FPHI_QCHUNKS * nov;
+  hipLaunchKernelGGL(k_fphi_dq, dim3(nblk(na)), dim3(256), 0, s, Bvt, Boo, lam, no, nv, na, dq);
+  hipLaunchKernelGGL(k_fphi_part, dim3(FPHI_QCHUNKS, no), dim3(256), 0, s, Bov, Bvt, Boo, lam, (const double*)dq, no,
+                     nv, na, h->fphi_part);
+  hipLaunchKernelGGL(k_fphi_sum, dim3(nblk(nov)), dim3(256), 0, s, Ft, (const double*)h->fphi_part, no, nv,
+                     FPHI_QCHUNKS, h->fphi);
+  hipLaunchKernelGGL(k_make_x, dim3(nblk((int64_t)na * nov)), dim3(256), 0, s, Bvt, Boo, lam, no, nv, na, h->X);
+  GemmArgs g{};
+  // V[(ia),(jb)] = sum_Q Bov[Q][(ia)] Bov[Q][(jb)]
+  g.A = Bov; g.B = Bov; g.C = h->Vint; g.M = nov; g.N = nov; g.K = na;
+  g.sAi = 1; g.sAk = nov; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));
+  g.A = h->X; g.C = h->Mint;
+  ESMP2_HIP(gemm(s, 1, g));
+  RhsArgs ra{d, h->Vint, h->Mint, h->fphi, lam, b};
+  hipLaunchKernelGGL(k_rhs, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
+  ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
 
@@ -719,30 +781,21 @@ static esmp2_status build_rhs(esmp2_handle h) {
     if (st != ESMP2_OK) return st;
   }
   const Dims& d = h->d;
-  const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
-  const int64_t namp = d.off[7];
+  const int no = d.no, nv = d.nv;
+  const int64_t namp = h->namp;
   hipStream_t s = h->stream;
-  double* dq = h->fphi_part + (size_t)FPHI_QCHUNKS * nov;
-  hipLaunchKernelGGL(k_fphi_dq, dim3(nblk(na)), dim3(256), 0, s, (const double*)h->Bvt, (const double*)h->Boo,
-                     (const double*)h->lam, no, nv, na, dq);
-  hipLaunchKernelGGL(k_fphi_part, dim3(FPHI_QCHUNKS, no), dim3(256), 0, s, (const double*)h->Bov,
-                     (const double*)h->Bvt, (const double*)h->Boo, (const double*)h->lam, (const double*)dq, no, nv,
-                     na, h->fphi_part);
-  hipLaunchKernelGGL(k_fphi_sum, dim3(nblk(nov)), dim3(256), 0, s, (const double*)h->Ft,
-                     (const double*)h->fphi_part, no, nv, FPHI_QCHUNKS, h->fphi);
-  hipLaunchKernelGGL(k_make_x, dim3(nblk((int64_t)na * nov)), dim3(256), 0, s, h->Bvt, h->Boo, h->lam, no, nv, na,
-                     h->X);
-  GemmArgs g{};
-  // V[(ia),(jb)] = sum_Q Bov[Q][(ia)] Bov[Q][(jb)]
-  g.A = h->Bov; g.B = h->Bov; g.C = h->Vint; g.M = nov; g.N = nov; g.K = na;
-  g.sAi = 1; g.sAk = nov; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, 1, g));
-  g.A = h->X; g.C = h->Mint;
-  ESMP2_HIP(gemm(s, 1, g));
-  RhsArgs ra{d, h->Vint, h->Mint, h->fphi, h->lam, h->b};
-  hipLaunchKernelGGL(k_rhs, dim3(nblk(namp)), dim3(256), 0, s, ra);
-  DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv32, h->blockmin};
-  hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
+  {
+    const esmp2_status st = rhs_core(h, h->Ft, h->Bov, h->Bvt, h->Boo, h->lam, h->ntop > 1 ? h->btmp : h->b);
+    if (st != ESMP2_OK) return st;
+  }
+  if (h->ntop == 1) {
+    DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv32, h->blockmin};
+    hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
+  } else {
+    const TopkArgs ta = topk_args(h);
+    hipLaunchKernelGGL(k_topk_bset, dim3(nblk(d.off[7])), dim3(256), 0, s, ta, 0, (const double*)h->btmp, h->b);
+    hipLaunchKernelGGL(k_topk_diag, dim3(nblk(namp)), dim3(256), 0, s, ta, h->dinv32, h->blockmin);
+  }
   hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
   // E2_S on the side stream (after the eigenproblems queued there), beside the
   // solve: it reads Vint, lam, eo, ev, omega and the pair tables, which the
@@ -767,6 +820,28 @@ static esmp2_status build_rhs(esmp2_handle h) {
   ESMP2_HIP(hipEventRecord(h->ev_e2s, h->aux));
   h->e2s_pending = true;
   h->e2s_dev = true;
+  if (h->ntop > 1) {
+    // the other large TOPs: the one-TOP right-hand side of each relabelled
+    // problem (after E2_S has read Vint), its L-boxes into set s; then the
+    // S-triples that TOP(k) moves into L leave E2_S
+    const esmp2_status st0 = join_e2s(h, false);
+    if (st0 != ESMP2_OK) return st0;
+    const TopkArgs ta = topk_args(h);
+    for (int t = 1; t < h->ntop; ++t) {
+      hipLaunchKernelGGL(k_topk_permute, dim3(1024), dim3(256), 0, s, t, no, nv, d.naux, (const double*)h->Ft,
+                         (const double*)h->Bov, (const double*)h->Bvt, (const double*)h->Boo, (const double*)h->lam,
+                         h->Ft_s, h->Bov_s, h->Bvt_s, h->Boo_s, h->lam_s);
+      const esmp2_status st = rhs_core(h, h->Ft_s, h->Bov_s, h->Bvt_s, h->Boo_s, h->lam_s, h->btmp);
+      if (st != ESMP2_OK) return st;
+      hipLaunchKernelGGL(k_topk_bset, dim3(nblk(d.off[7] - d.off[2])), dim3(256), 0, s, ta, t,
+                         (const double*)h->btmp, h->b);
+    }
+    hipLaunchKernelGGL(k_topk_e2s, dim3(PCG_BLOCKS), dim3(256), 0, s, ta, (const double*)h->b, h->partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, (const double*)h->partial, (int)PCG_BLOCKS,
+                       h->e2s_part + E2S_CAP + 1, 1.0);
+    hipLaunchKernelGGL(k_add_to, dim3(1), dim3(64), 0, s, h->e2s_part + E2S_CAP, (const double*)h->e2s_part + E2S_CAP + 1);
+    ESMP2_HIP(hipGetLastError());
+  }
   ESMP2_HIP(hipMemcpyAsync(h->pin->tmp, h->sc + SC_TMP, sizeof(double), hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
   ESMP2_HIP(hipGetLastError());
@@ -784,7 +859,7 @@ esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* 
   esmp2_status st = build_rhs(h);
   if (st != ESMP2_OK) return st;
   if (b_out)
-    ESMP2_HIP(hipMemcpyAsync(b_out, h->b, sizeof(double) * h->d.off[7], hipMemcpyDeviceToDevice, h->stream));
+    ESMP2_HIP(hipMemcpyAsync(b_out, h->b, sizeof(double) * h->namp, hipMemcpyDeviceToDevice, h->stream));
   if (e0) *e0 = h->e0;
   if (e2_s) {
     st = join_e2s(h, true);
@@ -1124,8 +1199,19 @@ struct OpCtx {
   bool arrow;        // the operator through the arrow kernels
 };
 
+// y = A x of ESMP2-TOP(k), k > 1 (FP64)
+static esmp2_status sigma_topk(esmp2_handle h, const double* x, double* y) {
+  const TopkArgs ta = topk_args(h);
+  hipLaunchKernelGGL(k_topk_sigma, dim3(nblk(h->namp)), dim3(256), 0, h->stream, ta, x, y);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
 template <class T>
 static esmp2_status apply_op(esmp2_handle h, const OpCtx& c, const SigmaBufs<T>& w, const T* x, T* y) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (h->ntop > 1) return sigma_topk(h, x, y);
+  }
   return c.arrow ? sigma_arrow(h, w, x, y) : sigma_t(h, w, x, y);
 }
 
@@ -1135,6 +1221,14 @@ static void wdot(esmp2_handle h, const T* x, const T* y, int slot);
 // y = A x and sc[SC_PQ] = <x, y>_W (fused into the operator where it writes every element once)
 template <class T>
 static esmp2_status apply_op_dot(esmp2_handle h, const OpCtx& c, const SigmaBufs<T>& w, const T* x, T* y) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (h->ntop > 1) {
+      const esmp2_status st = sigma_topk(h, x, y);
+      if (st != ESMP2_OK) return st;
+      wdot(h, x, (const T*)y, SC_PQ);
+      return ESMP2_OK;
+    }
+  }
   if (c.arrow && h->nchunks > 0) {
     esmp2_status st = sigma_arrow(h, w, x, y, h->pq_part);
     if (st != ESMP2_OK) return st;
@@ -1166,6 +1260,10 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision) 
   if (!x || !y) return fail(h, ESMP2_INVALID_ARG, "null vector");
   if (x == y) return fail(h, ESMP2_INVALID_ARG, "x and y must not overlap");
   ESMP2_HIP(hipSetDevice(h->device));
+  if (h->ntop > 1) {
+    if (precision != ESMP2_FP64) return fail(h, ESMP2_UNSUPPORTED, "more than one large TOP: FP64 only");
+    return sigma_topk(h, (const double*)x, (double*)y);
+  }
   if (precision == ESMP2_FP64) return sigma64(h, (const double*)x, (double*)y);
   if (precision == ESMP2_FP32) return sigma32(h, (const float*)x, (float*)y);
   if (precision == ESMP2_BF16) {
@@ -1183,6 +1281,7 @@ esmp2_status esmp2_sigma_basis(esmp2_handle h, const void* x, void* y, int preci
   if (h->state < 2) return fail(h, ESMP2_BAD_ORDER, "esmp2_rotate_top first");
   if (!x || !y) return fail(h, ESMP2_INVALID_ARG, "null vector");
   if (x == y) return fail(h, ESMP2_INVALID_ARG, "x and y must not overlap");
+  if (h->ntop > 1) return fail(h, ESMP2_UNSUPPORTED, "more than one large TOP: TOP basis only");
   if (precision != ESMP2_FP64 && precision != ESMP2_FP32) {
     if (precision == ESMP2_BF16)
       return fail(h, ESMP2_UNSUPPORTED, "the pinned-semicanonical operator has no Sylvester products (no BF16 form)");
@@ -1203,11 +1302,16 @@ esmp2_status esmp2_export_determinants(esmp2_handle h, const double* x, double* 
   if (!h) return ESMP2_INVALID_ARG;
   if (h->state < 1) return fail(h, ESMP2_BAD_ORDER, "esmp2_set_problem first");
   const Dims& d = h->d;
-  const int64_t namp = d.off[7], ndet = 2 * namp - (d.off[B_S2 + 1] - d.off[B_S2]);
+  const int64_t namp = h->namp, ndet = 2 * namp - (d.off[B_S2 + 1] - d.off[B_S2]);
   if (!x || !coeff || !det_key) return fail(h, ESMP2_INVALID_ARG, "null pointer");
   if (n < ndet) return fail(h, ESMP2_INVALID_ARG, "output arrays shorter than 2 n_amp - n_S2 determinants");
   ESMP2_HIP(hipSetDevice(h->device));
-  hipLaunchKernelGGL(k_export_dets, dim3(nblk(namp)), dim3(256), 0, h->stream, d, x, coeff, det_key);
+  if (h->ntop > 1) {
+    const TopkArgs ta = topk_args(h);
+    hipLaunchKernelGGL(k_topk_export, dim3(nblk(namp)), dim3(256), 0, h->stream, ta, x, coeff, det_key);
+  } else {
+    hipLaunchKernelGGL(k_export_dets, dim3(nblk(namp)), dim3(256), 0, h->stream, d, x, coeff, det_key);
+  }
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
@@ -1282,7 +1386,7 @@ esmp2_status esmp2_autotune(esmp2_handle h, int precision, int reps, int* varian
 template <class T>
 static void wdot(esmp2_handle h, const T* x, const T* y, int slot) {
   const Dims& d = h->d;
-  hipLaunchKernelGGL(k_dot<T>, dim3(PCG_BLOCKS), dim3(256), 0, h->stream, x, y, d.off[7], d.off[1], d.off[2],
+  hipLaunchKernelGGL(k_dot<T>, dim3(PCG_BLOCKS), dim3(256), 0, h->stream, x, y, h->namp, d.off[1], d.off[2],
                      h->partial);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, h->stream, h->partial, PCG_BLOCKS, h->sc, slot);
 }
@@ -1292,7 +1396,7 @@ extern "C" {
 // E2 (Hylleraas form <b,x>_W - <x,r>_W, r = -b - A x) and the result record
 static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
                                  esmp2_solve_result* res, double rel, int it, int outer, esmp2_status status) {
-  const int64_t n = h->d.off[7];
+  const int64_t n = h->namp;
   hipStream_t s = h->stream;
   {
     const esmp2_status st = join_e2s(h, true);
@@ -1327,7 +1431,7 @@ static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_sol
 static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
                             esmp2_solve_result* res) {
   const Dims& d = h->d;
-  const int64_t n = d.off[7];
+  const int64_t n = h->namp;
   hipStream_t s = h->stream;
   const unsigned NB = PCG_BLOCKS;
   wdot(h, c.b, c.b, SC_BB);   // ||b||_W^2
@@ -1389,7 +1493,7 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
 static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
                                 esmp2_solve_result* res) {
   const Dims& d = h->d;
-  const int64_t n = d.off[7];
+  const int64_t n = h->namp;
   hipStream_t s = h->stream;
   const unsigned NB = PCG_BLOCKS;
   // an operator with BF16 operands is accurate to ~1e-3 relative: ask its inner
@@ -1481,6 +1585,8 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
     return fail(h, ESMP2_INVALID_ARG, "unknown basis");
   if (opts->precision != ESMP2_FP64 && !(opts->inner_tol >= 0 && opts->inner_tol < 1))
     return fail(h, ESMP2_INVALID_ARG, "inner_tol must lie in [0, 1)");
+  if (h->ntop > 1 && (opts->precision != ESMP2_FP64 || opts->basis != ESMP2_BASIS_TOP))
+    return fail(h, ESMP2_UNSUPPORTED, "more than one large TOP: FP64 solve in the TOP basis only");
   ESMP2_HIP(hipSetDevice(h->device));
   memset(res, 0, sizeof(*res));
   if (!h->have_rhs) {
@@ -1590,6 +1696,7 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
   if (!h) return ESMP2_INVALID_ARG;
   if (h->state < 3) return fail(h, ESMP2_BAD_ORDER, "esmp2_build_rhs (and a solve for x) first");
   if (!x || (!dF && !dB)) return fail(h, ESMP2_INVALID_ARG, "x and at least one of dF, dB are required");
+  if (h->ntop > 1) return fail(h, ESMP2_UNSUPPORTED, "gradient with more than one large TOP");
   ESMP2_HIP(hipSetDevice(h->device));
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, n = d.n, na = d.naux, nov = no * nv;

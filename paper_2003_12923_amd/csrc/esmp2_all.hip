@@ -9,4 +9,5 @@
 #include "gemv.hip"
 #include "adjoint.hip"
 #include "export.hip"
+#include "topk.hip"
 #include "api.hip"

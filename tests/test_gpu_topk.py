@@ -1,0 +1,165 @@
+"""GPU parity of ESMP2-TOP(k), several large transition-orbital pairs (paper
+Sec. II.C: the L-triples are those that contain a large TOP; k = n_occ is
+TOP(all), Sec. III.B, Table II), through the C ABI, against the oracle's
+TOP(k) operator (oracle.topk, pinned to the explicit determinant
+construction): sigma and b element by element, E0, E2_S and E2, and the
+exported determinant solution against the explicit one.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import explicit, topbasis, topk
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_12923_amd as p
+    return p
+
+
+def _setup(lib, no, nv, na, seed, k, spin=0):
+    print(f"[case] TOP({k}) n_occ={no} n_vir={nv} n_aux={na} seed={seed} spin={spin}", flush=True)
+    prob = synth.make_problem(no, nv, na, seed) if seed >= 0 else synth.config_problem("c1")
+    lam, R = topbasis.top_rotation(prob.F, prob.C, no)
+    Ft, Bt = topbasis.rotate(prob.F, prob.B, R)
+    tk = topk.TopK(Ft, Bt, lam, no, k, spin=spin)
+    h = lib.Handle(0).load(prob, spin=spin, n_top=k)
+    h.rotate_top()
+    return h, tk, Ft, Bt, lam
+
+
+CASES = [(3, 5, 6, 2, 2, 0), (3, 5, 6, 2, 3, 0), (4, 7, 9, 4, 2, 0), (3, 5, 7, 3, 2, 1), (5, 12, 14, 6, 3, 0),
+         (4, 16, 48, -1, 2, 0), (4, 16, 48, -1, 4, 0)]
+
+
+@pytest.mark.parametrize("no,nv,na,seed,k,spin", CASES)
+def test_topk_sigma_rhs_e2(lib, no, nv, na, seed, k, spin):
+    h, tk, Ft, Bt, lam = _setup(lib, no, nv, na, seed, k, spin)
+    n, offs = h.space()
+    assert n == tk.dim
+    ph = tk.phase
+    # sigma of a random vector (operator-string phase on both sides; masked slots zero)
+    x = np.where(tk.live, synth.random_amplitudes(n, seed + 50), 0.0)
+    ref = ph * tk.sigma(ph * x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.full_like(xt, float("nan"))
+    h.sigma(xt, yt)
+    bt = torch.full_like(xt, float("nan"))
+    e0, e2s = h.build_rhs(bt)
+    torch.cuda.synchronize()
+    y, b = yt.cpu().numpy(), bt.cpu().numpy()
+    err = np.abs(y - ref).max()
+    print(f"[topk sigma] max err {err:.3e} of {np.abs(ref).max():.3e}", flush=True)
+    assert np.isfinite(y).all() and err <= 1e-12 * np.abs(ref).max()
+    assert np.all(y[~tk.live] == 0.0)
+    bref = ph * tk.rhs()
+    assert np.abs(b - bref).max() <= 1e-12 * np.abs(bref).max()
+    r = tk.solve(tol=1e-12)
+    assert abs(e0 - r["e0"]) < 1e-12 * max(1.0, abs(r["e0"]))
+    assert abs(e2s - r["e2_s"]) < 1e-12 * max(1e-3, abs(r["e2"]))
+    res = h.solve(tol=1e-11, max_iter=500)
+    print(f"[topk E2] gpu {res['e2']:.14f} oracle {r['e2']:.14f} diff {res['e2'] - r['e2']:.3e} "
+          f"iters {res['iterations']}", flush=True)
+    assert res["status"] == 0 and abs(res["e2"] - r["e2"]) < 1e-10
+    h.close()
+
+
+@pytest.mark.parametrize("no,nv,na,seed,k,spin", [(3, 5, 6, 2, 2, 0), (3, 5, 6, 2, 3, 0), (3, 5, 7, 3, 2, 1)])
+def test_topk_exported_determinants(lib, no, nv, na, seed, k, spin):
+    """The TOP(k) solution on determinants equals the explicit construction's."""
+    h, tk, Ft, Bt, lam = _setup(lib, no, nv, na, seed, k, spin)
+    ex = explicit.ExplicitESMP2(Ft, topbasis.eri_from_factor(Bt), lam, no, n_top=k, sign=-1 if spin else 1)
+    ref = ex.solve(dense=True)
+    n, offs = h.space()
+    xo = torch.empty(n, dtype=torch.float64, device="cuda")
+    res = h.solve(tol=1e-13, max_iter=500, x_out=xo)
+    assert res["status"] == 0 and abs(res["e2"] - ref["e2"]) < 1e-10
+    ndet = 2 * n - (offs[2] - offs[1])
+    coeff = torch.full((ndet,), float("nan"), dtype=torch.float64, device="cuda")
+    keys = torch.full((ndet,), -2, dtype=torch.int64, device="cuda")
+    h.export_determinants(xo, coeff, keys)
+    torch.cuda.synchronize()
+    c, kk = coeff.cpu().numpy(), keys.cpu().numpy()
+    got = np.zeros(len(ex.DL))
+    seen = set()
+    for key, v in zip(kk, c):
+        if key == -1:
+            assert v == 0.0
+            continue
+        d = ex.phi
+        for s in range(3):
+            hh, pp = (int(key) >> (10 * s)) & 1023, (int(key) >> (30 + 10 * s)) & 1023
+            if hh != 1023:
+                d ^= 1 << hh
+            if pp != 1023:
+                d |= 1 << pp
+        assert d not in seen
+        seen.add(d)
+        got[ex.index[d]] = v
+    assert seen == set(ex.DL)
+    err = np.abs(got - ex.x).max()
+    print(f"[topk export] {len(seen)} determinants, max err {err:.3e}", flush=True)
+    assert err <= 1e-12 * max(1.0, np.abs(ex.x).max())
+    h.close()
+
+
+def test_topk_workload_sample(lib):
+    """The largest size the oracle's TOP(2) reaches in minutes, n_occ = 6,
+    n_vir = 40: E2 and sampled sigma and b against stored oracle values."""
+    name = "topk_6_40_30_5_2"
+    if name not in GOLD:
+        pytest.skip("stored oracle values not generated")
+    g = GOLD[name]
+    prob = synth.make_problem(g["n_occ"], g["n_vir"], g["n_aux"], g["seed"])
+    print(f"[case] {name}", flush=True)
+    h = lib.Handle(0).load(prob, n_top=g["n_top"])
+    h.rotate_top()
+    n, _ = h.space()
+    assert n == g["dim"]
+    x = synth.random_amplitudes(n, g["sigma_seed"])
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.empty_like(xt)
+    h.sigma(xt, yt)
+    bt = torch.empty_like(xt)
+    e0, e2s = h.build_rhs(bt)
+    torch.cuda.synchronize()
+    idx = np.array(g["sample_idx"])
+    ref = np.array(g["sigma_sample"])
+    assert np.abs(yt.cpu().numpy()[idx] - ref).max() <= 1e-11 * np.abs(ref).max()
+    bref = np.array(g["b_sample"])
+    assert np.abs(bt.cpu().numpy()[idx] - bref).max() <= 1e-12 * np.abs(bref).max()
+    assert abs(e0 - g["e0"]) < 1e-11 and abs(e2s - g["e2_s"]) < 1e-10
+    res = h.solve(tol=1e-11, max_iter=500)
+    print(f"[{name}] E2 gpu {res['e2']:.12f} oracle {g['e2']:.12f} diff {res['e2'] - g['e2']:.3e}", flush=True)
+    assert res["status"] == 0 and abs(res["e2"] - g["e2"]) < 1e-10
+    h.close()
+
+
+def test_topk_arguments(lib):
+    prob = synth.make_problem(3, 5, 6, 2)
+    h = lib.Handle(0)
+    for bad in (0, 4):
+        with pytest.raises(lib.Esmp2Error):
+            h.load(prob, n_top=bad)
+    h.load(prob, n_top=2)
+    h.rotate_top()
+    for kw in (dict(precision=lib.ESMP2_FP32), dict(basis=lib.ESMP2_BASIS_SEMICANONICAL)):
+        with pytest.raises(lib.Esmp2Error):
+            h.solve(tol=1e-8, max_iter=50, **kw)
+    n, _ = h.space()
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    h.build_rhs()
+    with pytest.raises(lib.Esmp2Error):
+        h.gradient(x, dF=torch.zeros((8, 8), dtype=torch.float64, device="cuda"))
+    h.close()
