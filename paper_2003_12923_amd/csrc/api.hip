@@ -83,6 +83,7 @@ struct PinnedScalars {
   double e2s;
   int info[4];
   int bad[4];
+  int active[2];         // batched solve: states still iterating, two iterations in flight
 };
 
 struct esmp2_handle_ {
@@ -893,11 +894,18 @@ static SigmaBufs<float> bufs32(esmp2_handle h) {
 // S~ and the per-batch side contractions with f_ov; returns the argument
 // block of the coupling terms.
 template <class T>
-static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y, bool arrow = false) {
+struct PrologueArgs {
+  GemvArgs<T> gv;
+  GatherArgs<T> ga;
+  int jobs;       // workgroups of the GEMV launch
+};
+
+// the argument blocks of the prologue's kernels and of the coupling terms
+// (pointer arithmetic only; nothing is launched)
+template <class T>
+static PrologueArgs<T> prologue_args(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y, bool arrow) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv;
-  hipStream_t s = h->stream;
-  hipLaunchKernelGGL(k_sym_s2<T>, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, x, w.S);
   SideArgs<T> sa{};
   sa.d = d; sa.x = x; sa.fov = w.fov;
   T* p = w.side;
@@ -908,17 +916,27 @@ static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const
   const int n2 = (no - 1) * (no - 1);
   sa.h21_t = take(n2); sa.h21_k = take(n2);
   sa.h22_ut = take(n2); sa.h22_i = take(n2); sa.h22_uk = take(n2);
+  PrologueArgs<T> r{};
   // per-batch GEMVs: the side contractions, and with the arrow-shaped Fock blocks
   // also the t'-row products (T2 and S2 batches join the job list)
-  GemvArgs<T> gva{sa, w.S, w.fv, (T*)h->gv, w.side_tr, arrow ? 1 : 0};
-  const int jobs = d.npo1 + 2 * d.npo + 2 * n2 + (arrow ? d.npo + no * no : 0);
-  hipLaunchKernelGGL(k_gemv<T>, dim3(jobs), dim3(256), 0, s, gva);
-  GatherArgs<T> ga{};
+  r.gv = GemvArgs<T>{sa, w.S, w.fv, (T*)h->gv, w.side_tr, arrow ? 1 : 0};
+  r.jobs = d.npo1 + 2 * d.npo + 2 * n2 + (arrow ? d.npo + no * no : 0);
+  GatherArgs<T>& ga = r.ga;
   ga.d = d; ga.x = x; ga.S = w.S; ga.y = y; ga.fo = w.fo; ga.fv = w.fv; ga.fov = w.fov; ga.side_tr = w.side_tr;
   ga.t3_t = sa.t3_t; ga.t3_p1 = sa.t3_p1; ga.t3_p2 = sa.t3_p2; ga.h11_p1 = sa.h11_p1; ga.h11_p2 = sa.h11_p2;
   ga.h12_t = sa.h12_t; ga.h12_u1 = sa.h12_u1; ga.h12_u2 = sa.h12_u2; ga.h21_t = sa.h21_t; ga.h21_k = sa.h21_k;
   ga.h22_ut = sa.h22_ut; ga.h22_i = sa.h22_i; ga.h22_uk = sa.h22_uk;
-  return ga;
+  return r;
+}
+
+template <class T>
+static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const T* x, T* y, bool arrow = false) {
+  const Dims& d = h->d;
+  hipStream_t s = h->stream;
+  hipLaunchKernelGGL(k_sym_s2<T>, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, x, w.S);
+  const PrologueArgs<T> r = prologue_args(h, w, x, y, arrow);
+  hipLaunchKernelGGL(k_gemv<T>, dim3(r.jobs), dim3(256), 0, s, r.gv);
+  return r.ga;
 }
 
 // Sylvester-product variants: 0 = the specialised kernel (padded virtual
@@ -1605,6 +1623,166 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
   return opts->precision == ESMP2_FP64 ? solve64(h, c, opts, res) : solve_mixed(h, c, opts, res);
 }
 
+}  // extern "C"
+
+// The batched FP64 conjugate gradient of many one-TOP states in the
+// pinned-semicanonical basis (set up, with their right-hand sides, beforehand):
+// every step is one launch for all states (see batch.hip), each state's
+// scalars, convergence test and stop live on the device, and the host polls the
+// number of states still iterating one iteration behind the launches, so the
+// device never waits for the host between iterations.
+static esmp2_status solve_batch_sc64(esmp2_handle* hs, int n, const esmp2_solve_opts* opts,
+                                     esmp2_solve_result* res) {
+  esmp2_handle h0 = hs[0];
+  hipStream_t s = h0->stream;
+  std::vector<BState> st(n);
+  std::vector<int> first[3];
+  int64_t tot[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) first[k].resize(n + 1);
+  for (int i = 0; i < n; ++i) {
+    esmp2_handle h = hs[i];
+    const OpCtx c = ctx_sc(h);
+    const PrologueArgs<double> pa = prologue_args(h, c.s64, (const double*)h->p, h->q, true);
+    BState& B = st[i];
+    memset(&B, 0, sizeof(B));
+    B.d = h->d;
+    B.gv = pa.gv;
+    B.aa = ArrowArgs<double>{pa.ga, c.s64.Fd, c.s64.Fl, c.s64.side_tr, h->gv};
+    const int* pv = h->pairs;
+    const Dims& d = h->d;
+    B.pt = PairTables{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
+    B.chunks = (const int4*)h->chunks;
+    B.nsym = (int)sym_s2_blocks(d);
+    B.ngemv = pa.jobs;
+    B.nchunks = h->nchunks;
+    B.x = h->x; B.r = h->r; B.p = h->p; B.q = h->q; B.sc = h->sc; B.partial = h->partial; B.pq = h->pq_part;
+    B.S = c.s64.S;
+    B.b = c.b;
+    B.dinv = c.dinv32;
+    B.n = h->namp;
+    B.mode = BS_DONE;
+    const int cnt[3] = {B.nsym, B.ngemv, B.nchunks};
+    for (int k = 0; k < 3; ++k) {
+      first[k][i] = (int)tot[k];
+      tot[k] += cnt[k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (tot[k] <= 0 || tot[k] >= (int64_t)INT32_MAX) return fail(h0, ESMP2_INVALID_ARG, "batch too large");
+    first[k][n] = (int)tot[k];
+  }
+  if ((int64_t)n * 2 * BATCH_CG_BLOCKS >= (int64_t)INT32_MAX) return fail(h0, ESMP2_INVALID_ARG, "batch too large");
+  // device copies of the state records, the first-block tables and the counter
+  BState* dS = nullptr;
+  int* dfirst = nullptr;
+  int* dact = nullptr;
+  auto cleanup = [&]() {
+    if (dS) (void)hipFree(dS);
+    if (dfirst) (void)hipFree(dfirst);
+    if (dact) (void)hipFree(dact);
+  };
+  if (hipMalloc(&dS, sizeof(BState) * n) != hipSuccess || hipMalloc(&dfirst, sizeof(int) * 3 * (n + 1)) != hipSuccess ||
+      hipMalloc(&dact, sizeof(int)) != hipSuccess) {
+    cleanup();
+    return fail(h0, ESMP2_OOM, "device allocation of the batch records");
+  }
+  std::vector<int> fcat;
+  for (int k = 0; k < 3; ++k) fcat.insert(fcat.end(), first[k].begin(), first[k].end());
+  hipError_t e = hipMemcpyAsync(dS, st.data(), sizeof(BState) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dfirst, fcat.data(), sizeof(int) * fcat.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);    // the host vectors go out of scope with this call
+  if (e != hipSuccess) { cleanup(); return fail(h0, ESMP2_HIP_ERROR, hipGetErrorString(e)); }
+  const int* f_sym = dfirst;
+  const int* f_gemv = dfirst + (n + 1);
+  const int* f_arrow = dfirst + 2 * (n + 1);
+  const unsigned NBV = (unsigned)(n * BATCH_CG_BLOCKS);
+  const unsigned nsmall = (unsigned)((n + 63) / 64);
+  volatile int* act = h0->pin->active;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  auto fin = [&](esmp2_status r, const char* msg) {
+    for (auto& v : ev)
+      if (v) (void)hipEventDestroy(v);
+    cleanup();
+    return msg ? fail(h0, r, msg) : r;
+  };
+  for (auto& v : ev)
+    if (hipEventCreateWithFlags(&v, hipEventDisableTiming) != hipSuccess) return fin(ESMP2_HIP_ERROR, "event");
+  // start: x = 0, r = -b, p = M r, <b, b>, then the states converged already drop out
+  hipLaunchKernelGGL(kb_init, dim3(NBV), dim3(256), 0, s, dS);
+  hipLaunchKernelGGL(kb_dot_bb, dim3(NBV), dim3(256), 0, s, dS);
+  hipLaunchKernelGGL(kb_finish_init, dim3(3 * n), dim3(1024), 0, s, dS);
+  hipLaunchKernelGGL(kb_zero, dim3(1), dim3(64), 0, s, dact);
+  hipLaunchKernelGGL(kb_start, dim3(nsmall), dim3(64), 0, s, dS, n, opts->tol, dact);
+  act[0] = act[1] = -1;
+  if (hipMemcpyAsync((void*)&act[0], dact, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipEventRecord(ev[0], s) != hipSuccess)
+    return fin(ESMP2_HIP_ERROR, "enqueue of the batched start");
+  // iterations: launch iteration k + 1, then read the count left by iteration k
+  for (int k = 0;; ++k) {
+    if (k > opts->max_iter + 1) return fin(ESMP2_HIP_ERROR, "internal: batched iteration count exceeded");
+    hipLaunchKernelGGL(kb_sym, dim3((unsigned)tot[0]), dim3(256), 0, s, (const BState*)dS, f_sym, n);
+    hipLaunchKernelGGL(kb_gemv, dim3((unsigned)tot[1]), dim3(256), 0, s, (const BState*)dS, f_gemv, n);
+    hipLaunchKernelGGL(kb_arrow, dim3((unsigned)tot[2]), dim3(256), 0, s, (const BState*)dS, f_arrow, n);
+    hipLaunchKernelGGL(kb_finish_pq, dim3(n), dim3(1024), 0, s, dS);
+    hipLaunchKernelGGL(kb_update_r, dim3(NBV), dim3(256), 0, s, dS);
+    hipLaunchKernelGGL(kb_finish_r, dim3(2 * n), dim3(1024), 0, s, dS);
+    hipLaunchKernelGGL(kb_zero, dim3(1), dim3(64), 0, s, dact);
+    hipLaunchKernelGGL(kb_check, dim3(nsmall), dim3(64), 0, s, dS, n, opts->tol, opts->max_iter, dact);
+    hipLaunchKernelGGL(kb_update, dim3(NBV), dim3(256), 0, s, dS);
+    hipLaunchKernelGGL(kb_roll, dim3(nsmall), dim3(64), 0, s, dS, n);
+    const int nx = (k + 1) & 1;
+    if (hipEventSynchronize(ev[nx]) != hipSuccess) return fin(ESMP2_HIP_ERROR, "batched iteration");
+    act[nx] = -1;
+    if (hipMemcpyAsync((void*)&act[nx], dact, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(ev[nx], s) != hipSuccess)
+      return fin(ESMP2_HIP_ERROR, "enqueue of a batched iteration");
+    if (hipEventSynchronize(ev[k & 1]) != hipSuccess) return fin(ESMP2_HIP_ERROR, "batched iteration");
+    if (act[k & 1] == 0) break;     // the iteration just launched finds every state stopped
+  }
+  // E2 = <b, x>_W - <x, r>_W and E2_S, for every state, then one wait
+  for (int i = 0; i < n; ++i) {
+    esmp2_handle h = hs[i];
+    if (h->e2s_pending) {
+      if (hipStreamWaitEvent(s, h->ev_e2s, 0) != hipSuccess) return fin(ESMP2_HIP_ERROR, "E2_S join");
+      h->e2s_pending = false;
+    }
+  }
+  hipLaunchKernelGGL(kb_e2_dots, dim3(2 * NBV), dim3(256), 0, s, dS);
+  hipLaunchKernelGGL(kb_finish_e2, dim3(2 * n), dim3(1024), 0, s, dS);
+  e = hipMemcpyAsync(st.data(), dS, sizeof(BState) * n, hipMemcpyDeviceToHost, s);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    esmp2_handle h = hs[i];
+    e = hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && h->e2s_dev)
+      e = hipMemcpyAsync(&h->pin->e2s, h->e2s_part + E2S_CAP, sizeof(double), hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fin(ESMP2_HIP_ERROR, hipGetErrorString(e));
+  esmp2_status ret = ESMP2_OK;
+  for (int i = 0; i < n; ++i) {
+    esmp2_handle h = hs[i];
+    if (h->e2s_dev) { h->e2s = h->pin->e2s; h->e2s_dev = false; }
+    const double* sc = h->pin->sc;
+    esmp2_solve_result& r = res[i];
+    const BState& B = st[i];
+    r.e2_dl = sc[SC_BX] - sc[SC_XR];
+    r.e2_s = h->e2s;
+    r.e2 = r.e2_dl + r.e2_s;
+    r.e0 = h->e0;
+    r.rel_resid = B.rel;
+    r.iterations = B.it;
+    r.outer = 0;
+    r.status = (esmp2_status)B.status;
+    if (B.status == ESMP2_NOT_SPD) h->err = "p.Ap <= 0 in conjugate gradient";
+    if (B.status == ESMP2_NOT_CONVERGED) h->err = "max_iter reached";
+    if (B.status != ESMP2_OK && ret == ESMP2_OK) ret = (esmp2_status)B.status;
+  }
+  return fin(ret, nullptr);
+}
+
+extern "C" {
+
 esmp2_status esmp2_solve_batch(esmp2_handle* hs, int n, const esmp2_solve_opts* opts, esmp2_solve_result* res,
                                int n_threads) {
   if (n < 0 || (n > 0 && (!hs || !res)) || !opts) return ESMP2_INVALID_ARG;
@@ -1617,6 +1795,12 @@ esmp2_status esmp2_solve_batch(esmp2_handle* hs, int n, const esmp2_solve_opts* 
       if (hs[j] == hs[i]) return fail(hs[i], ESMP2_INVALID_ARG, "a handle appears twice in the batch");
   }
   if (n == 0) return ESMP2_OK;
+  // one launch per step for all states: FP64, pinned-semicanonical basis, one
+  // large TOP, every state on one device; otherwise one solve per state
+  bool together = opts->precision == ESMP2_FP64 && opts->basis == ESMP2_BASIS_SEMICANONICAL &&
+                  opts->tol > 0 && opts->max_iter >= 1;
+  for (int i = 0; i < n; ++i)
+    together = together && hs[i]->ntop == 1 && hs[i]->device == hs[0]->device;
   const int nt = std::max(1, std::min(n, n_threads > 0 ? n_threads : 8));
   std::vector<esmp2_status> st(n, ESMP2_OK);
   std::atomic<int> next{0};
@@ -1626,8 +1810,18 @@ esmp2_status esmp2_solve_batch(esmp2_handle* hs, int n, const esmp2_solve_opts* 
       memset(&res[i], 0, sizeof(res[i]));
       esmp2_status s = esmp2_rotate_top(h, nullptr);
       if (s == ESMP2_OK) s = esmp2_build_rhs(h, nullptr, nullptr, nullptr);
-      if (s == ESMP2_OK) s = esmp2_solve(h, opts, &res[i]);
-      else res[i].status = s;
+      if (together) {
+        // set-up only: the operator blocks and right-hand side of the basis
+        if (s == ESMP2_OK && hipSetDevice(h->device) != hipSuccess) s = fail(h, ESMP2_HIP_ERROR, "hipSetDevice");
+        if (s == ESMP2_OK && !h->have_sc) s = semican_setup(h);
+        if (s == ESMP2_OK && hipStreamSynchronize(h->stream) != hipSuccess) s = fail(h, ESMP2_HIP_ERROR, "set-up");
+        if (s == ESMP2_OK && h->nchunks <= 0) s = fail(h, ESMP2_UNSUPPORTED, "internal: no coupling chunks");
+        res[i].status = s;
+      } else if (s == ESMP2_OK) {
+        s = esmp2_solve(h, opts, &res[i]);
+      } else {
+        res[i].status = s;
+      }
       st[i] = s;
     }
   };
@@ -1641,6 +1835,11 @@ esmp2_status esmp2_solve_batch(esmp2_handle* hs, int n, const esmp2_solve_opts* 
   for (auto& t : pool) t.join();
   for (int i = 0; i < n; ++i)
     if (st[i] != ESMP2_OK) return st[i];
+  if (together) {
+    esmp2_handle h = hs[0];
+    ESMP2_HIP(hipSetDevice(h->device));
+    return solve_batch_sc64(hs, n, opts, res);
+  }
   return ESMP2_OK;
 }
 

@@ -109,9 +109,9 @@ __device__ __attribute__((always_inline)) inline double arrow_element(const Arro
                                                                       int inner);
 
 template <class T>
-__global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, const int4* chunks, double* pq) {
+__device__ __attribute__((always_inline)) inline void arrow_body(const ArrowArgs<T>& A, const PairTables& P, const int4* chunks, double* pq, int bid_, int nb_) {
   const Dims& d = A.ga.d;
-  const int4 ch = chunks[xcd_remap<32>(blockIdx.x, gridDim.x)];
+  const int4 ch = chunks[xcd_remap<32>(bid_, nb_)];
   const int box = ch.x, batch = ch.y;
   const int i = ch.w >> 16, j = ch.w & 0xffff;      // occupied indices of the batch (actual orbitals)
   const int nv = d.nv, m1 = nv - 1;
@@ -127,8 +127,13 @@ __global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, con
   if (v < inner) part = arrow_element(A, P, box, batch, i, j, v, inner);
   if (pq) {
     const double s = block_sum(part);
-    if (threadIdx.x == 0) pq[blockIdx.x] = s;
+    if (threadIdx.x == 0) pq[bid_] = s;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_arrow(ArrowArgs<T> A, PairTables P, const int4* chunks, double* pq) {
+  arrow_body<T>(A, P, chunks, pq, blockIdx.x, gridDim.x);
 }
 
 template <class T>

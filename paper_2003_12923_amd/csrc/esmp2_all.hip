@@ -10,4 +10,5 @@
 #include "adjoint.hip"
 #include "export.hip"
 #include "topk.hip"
+#include "batch.hip"
 #include "api.hip"

@@ -27,14 +27,14 @@ struct GemvArgs {
 constexpr int GV_MAXW = 3;     // weight vectors per pass
 
 template <class T>
-__global__ __launch_bounds__(256) void k_gemv(GemvArgs<T> A) {
+__device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, int bid_, int nb_) {
   const SideArgs<T>& sd = A.sd;
   const Dims& d = sd.d;
   const int no = d.no, nv = d.nv, n2 = (no - 1) * (no - 1);
   __shared__ T tile[16][193];
   __shared__ T rowres[GV_MAXW][192];
   // ---- job -> box, batch, occupied indices
-  int job = blockIdx.x, box;
+  int job = bid_, box;
   if (job < d.npo1) box = B_T3;
   else if ((job -= d.npo1) < d.npo) box = B_H11;
   else if ((job -= d.npo) < d.npo) box = B_H12;
@@ -198,6 +198,11 @@ __global__ __launch_bounds__(256) void k_gemv(GemvArgs<T> A) {
     if (oc[k]) oc[k][c] = in ? colres[k * 192 + cs] - (anti ? rowres[k][cs] : T(0)) : T(0);
     if (orow[k] && !anti) orow[k][c] = in ? rowres[k][cs] : T(0);
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gemv(GemvArgs<T> A) {
+  gemv_body<T>(A, blockIdx.x, gridDim.x);
 }
 
 template __global__ void k_gemv<double>(GemvArgs<double>);

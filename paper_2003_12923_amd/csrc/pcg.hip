@@ -20,11 +20,11 @@ constexpr int PCG_U = 4;
 
 // partial[block] = sum_g w_g x_g y_g   (grid-stride, fixed grid -> deterministic)
 template <class T>
-__global__ __launch_bounds__(256) void k_dot(const T* x, const T* y, int64_t n, int64_t s0, int64_t s1,
-                                             double* partial) {
+__device__ __attribute__((always_inline)) inline void dot_body(const T* x, const T* y, int64_t n, int64_t s0, int64_t s1,
+                                             double* partial, int bid_, int nb_) {
   Acc2 acc;
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+  const int64_t st = (int64_t)nb_ * blockDim.x;
+  for (int64_t g0 = (int64_t)bid_ * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
     T xv[PCG_U], yv[PCG_U];
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
@@ -39,16 +39,22 @@ __global__ __launch_bounds__(256) void k_dot(const T* x, const T* y, int64_t n, 
     }
   }
   double s = block_sum2(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) partial[bid_] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_dot(const T* x, const T* y, int64_t n, int64_t s0, int64_t s1,
+                                             double* partial) {
+  dot_body<T>(x, y, n, s0, s1, partial, blockIdx.x, gridDim.x);
 }
 
 // sc[base + k] = sum of partials[k*nb .. k*nb+nb-1], one block per sum
-__global__ void k_finish(const double* partial, int nb, double* sc, int base) {
+__device__ __attribute__((always_inline)) inline void finish_body(const double* partial, int nb, double* sc, int base, int bid_, int nb_) {
   // each thread adds its indices i, i + blockDim.x, ... in that order; the
   // loads of eight of them are issued before the adds (a long partial list is
   // otherwise one load latency per element)
   Acc2 acc;
-  const double* pp = partial + (int64_t)blockIdx.x * nb;
+  const double* pp = partial + (int64_t)bid_ * nb;
   for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * blockDim.x) {
     double v[8];
 #pragma unroll
@@ -60,7 +66,11 @@ __global__ void k_finish(const double* partial, int nb, double* sc, int base) {
     for (int u = 0; u < 8; ++u) acc.add(v[u]);     // adding an exact zero leaves (s, c) unchanged
   }
   double s = block_sum2(acc);
-  if (threadIdx.x == 0) sc[base + blockIdx.x] = s;
+  if (threadIdx.x == 0) sc[base + bid_] = s;
+}
+
+__global__ void k_finish(const double* partial, int nb, double* sc, int base) {
+  finish_body(partial, nb, sc, base, blockIdx.x, gridDim.x);
 }
 
 // The preconditioner M = D^-1 is stored in FP32 (rounded once): any fixed
@@ -71,12 +81,12 @@ __global__ void k_finish(const double* partial, int nb, double* sc, int base) {
 // (two partial arrays of gridDim.x each).  x is updated with p in k_update_px,
 // which reads p anyway.
 template <class T>
-__global__ __launch_bounds__(256) void k_update_r(T* r, const T* q, const float* dinv, int64_t n, int64_t s0,
-                                                  int64_t s1, const double* sc, double* partial) {
+__device__ __attribute__((always_inline)) inline void update_r_body(T* r, const T* q, const float* dinv, int64_t n, int64_t s0,
+                                                  int64_t s1, const double* sc, double* partial, int bid_, int nb_) {
   const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
   double rz = 0.0, rr = 0.0;
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+  const int64_t st = (int64_t)nb_ * blockDim.x;
+  for (int64_t g0 = (int64_t)bid_ * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
     T rv[PCG_U], qv[PCG_U];
     float dv[PCG_U];
 #pragma unroll
@@ -98,17 +108,23 @@ __global__ __launch_bounds__(256) void k_update_r(T* r, const T* q, const float*
   }
   double a = block_sum(rz);
   double b = block_sum(rr);
-  if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = b; }
+  if (threadIdx.x == 0) { partial[bid_] = a; partial[nb_ + bid_] = b; }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_update_r(T* r, const T* q, const float* dinv, int64_t n, int64_t s0,
+                                                  int64_t s1, const double* sc, double* partial) {
+  update_r_body<T>(r, q, dinv, n, s0, s1, sc, partial, blockIdx.x, gridDim.x);
 }
 
 // alpha = sc[RHO] / sc[PQ], beta = sc[RHO_NEW] / sc[RHO]:  x += alpha p;  p = M r + beta p
 template <class T>
-__global__ __launch_bounds__(256) void k_update_px(T* x, T* p, const T* r, const float* dinv, int64_t n,
-                                                   const double* sc) {
+__device__ __attribute__((always_inline)) inline void update_px_body(T* x, T* p, const T* r, const float* dinv, int64_t n,
+                                                   const double* sc, int bid_, int nb_) {
   const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
   const T beta = (T)(sc[SC_RHO_NEW] / sc[SC_RHO]);
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+  const int64_t st = (int64_t)nb_ * blockDim.x;
+  for (int64_t g0 = (int64_t)bid_ * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
     T xv[PCG_U], pv[PCG_U], rv[PCG_U];
     float dv[PCG_U];
 #pragma unroll
@@ -127,12 +143,18 @@ __global__ __launch_bounds__(256) void k_update_px(T* x, T* p, const T* r, const
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void k_update_px(T* x, T* p, const T* r, const float* dinv, int64_t n,
+                                                   const double* sc) {
+  update_px_body<T>(x, p, r, dinv, n, sc, blockIdx.x, gridDim.x);
+}
+
 // x += alpha p, alpha = sc[RHO] / sc[PQ]: the update of the last iteration
 template <class T>
-__global__ __launch_bounds__(256) void k_update_x(T* x, const T* p, int64_t n, const double* sc) {
+__device__ __attribute__((always_inline)) inline void update_x_body(T* x, const T* p, int64_t n, const double* sc, int bid_, int nb_) {
   const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+  const int64_t st = (int64_t)nb_ * blockDim.x;
+  for (int64_t g0 = (int64_t)bid_ * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
     T xv[PCG_U], pv[PCG_U];
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
@@ -147,17 +169,22 @@ __global__ __launch_bounds__(256) void k_update_x(T* x, const T* p, int64_t n, c
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void k_update_x(T* x, const T* p, int64_t n, const double* sc) {
+  update_x_body<T>(x, p, n, sc, blockIdx.x, gridDim.x);
+}
+
 __global__ void k_roll_rho(double* sc) {
   if (threadIdx.x == 0) sc[SC_RHO] = sc[SC_RHO_NEW];
 }
 
 // r = -b - y (y = A x0) or r = -b;  p = M r;  partials of <r, M r>, <r, r>
-__global__ __launch_bounds__(256) void k_init(const double* b, const double* y, double* r, double* p,
+__device__ __attribute__((always_inline)) inline void init_body(const double* b, const double* y, double* r, double* p,
                                               const float* dinv, int64_t n, int64_t s0, int64_t s1,
-                                              double* partial) {
+                                              double* partial, int bid_, int nb_) {
   double rz = 0.0, rr = 0.0;
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+  const int64_t st = (int64_t)nb_ * blockDim.x;
+  for (int64_t g0 = (int64_t)bid_ * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
     double bv[PCG_U], yv[PCG_U];
     float dv[PCG_U];
 #pragma unroll
@@ -180,7 +207,13 @@ __global__ __launch_bounds__(256) void k_init(const double* b, const double* y, 
   }
   double a = block_sum(rz);
   double c = block_sum(rr);
-  if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = c; }
+  if (threadIdx.x == 0) { partial[bid_] = a; partial[nb_ + bid_] = c; }
+}
+
+__global__ __launch_bounds__(256) void k_init(const double* b, const double* y, double* r, double* p,
+                                              const float* dinv, int64_t n, int64_t s0, int64_t s1,
+                                              double* partial) {
+  init_body(b, y, r, p, dinv, n, s0, s1, partial, blockIdx.x, gridDim.x);
 }
 
 // FP64 residual of the refinement: r = -b - y (y = A x, or NULL for x = 0);  partials of <r, r>_W

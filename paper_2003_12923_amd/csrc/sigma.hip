@@ -79,12 +79,12 @@ struct Look {
 // S~ = (x_S2 + sg flip x_S2)/2, flip: (i,j,a,b) -> (j,i,b,a); sg = +1 singlet, -1 triplet
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256) void k_sym_s2(Dims d, const T* x, T* S) {
+__device__ __attribute__((always_inline)) inline void sym_s2_body(Dims d, const T* x, T* S, int bid_, int nb_) {
   // one 32 x 32 block of (a, b) of one batch (i, j); the partner block (j, i)
   // is read in its own (row-major) order and transposed through LDS
   __shared__ T tl[32][33];
   const int nv = d.nv, nt = (nv + 31) / 32;
-  const int blk = (int)xcd_remap<16>(blockIdx.x, gridDim.x);
+  const int blk = (int)xcd_remap<16>(bid_, nb_);
   const int o = blk / (nt * nt), t = blk - o * (nt * nt);
   const int i = o / d.no, j = o - i * d.no;
   const int a0 = (t / nt) * 32, b0 = (t % nt) * 32;
@@ -106,6 +106,11 @@ __global__ __launch_bounds__(256) void k_sym_s2(Dims d, const T* x, T* S) {
     const int a = a0 + r, b = b0 + tx;
     if (a < nv && b < nv) Sd[a * nv + b] = T(0.5) * (X[a * nv + b] + sg * tl[tx][r]);
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_sym_s2(Dims d, const T* x, T* S) {
+  sym_s2_body<T>(d, x, S, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
