@@ -321,11 +321,19 @@ esmp2_status esmp2_fock_from_core_noalloc(esmp2_handle h, int n_occ, int n_vir, 
  * done, every handle on its own stream for the states to overlap on the
  * device).  For every handle: rotation, right-hand side, solve with `opts`,
  * E2 into results[i] (host array of n).  A pool of n_threads host threads
- * (<= 0: 8) takes the states in order; each state's calls are the ones above,
- * issued on that state's stream, so the device runs several states' kernels
- * at once.  opts->x0, x_out and resid_hist must be NULL.  Synchronises.  Every
- * state is attempted; returns ESMP2_OK or the status of the first failing
- * state (results[i].status holds each one). */
+ * (<= 0: 8) takes the states in order for their set-up, issued on each
+ * state's stream.  With opts->precision ESMP2_FP64, opts->basis
+ * ESMP2_BASIS_SEMICANONICAL, one large TOP per state and every handle on one
+ * device, the conjugate gradients of all states then run together on the
+ * first handle's stream: one launch per step covers every state, each state's
+ * scalars, convergence test and stop (tol, max_iter) are decided on the
+ * device, and the host reads only the number of states still iterating; the
+ * results equal each state's own esmp2_solve to rounding (the reductions are
+ * split over fewer blocks).  Any other options: each thread runs
+ * esmp2_solve for its states.  opts->x0, x_out and resid_hist must be NULL.
+ * Synchronises.  Every state is attempted; returns ESMP2_OK or the status of
+ * the first failing state (results[i].status holds each one).  Temporary
+ * device memory: one record of about 1 KB per state. */
 esmp2_status esmp2_solve_batch(esmp2_handle* handles, int n, const esmp2_solve_opts* opts,
                                esmp2_solve_result* results, int n_threads);
 
