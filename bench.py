@@ -46,7 +46,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-state batched workload")
     ap.add_argument("--counter-run", type=int, default=0, metavar="N",
                     help="for hardware-counter passes: a 256 MiB device copy (the calibration "
-                         "kernel of known size), then N FP64 and N FP32 sigma applications; no timing")
+                         "kernel of known size), then N FP64 and N FP32 sigma applications in the TOP "
+                         "basis and N FP64 in the pinned-semicanonical basis; no timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -356,8 +357,9 @@ def main():
 
 
 def counter_run(args):
-    """Kernels for the FETCH_SIZE / WRITE_SIZE passes: one copy of 2^25 doubles
-    (256 MiB read + 256 MiB written), then sigma applications of the workload."""
+    """Kernels for the hardware-counter passes: one copy of 2^25 doubles (256 MiB
+    read + 256 MiB written), then sigma applications of the workload: N FP64 and
+    N FP32 in the TOP basis, N FP64 in the pinned-semicanonical basis."""
     import torch
     import synth
     import paper_2003_12923_amd as P
@@ -377,6 +379,10 @@ def counter_run(args):
     x32, y32 = x.float(), torch.empty(n_amp, dtype=torch.float32, device="cuda")
     for _ in range(args.counter_run):
         h.sigma(x32, y32, P.ESMP2_FP32)
+    # the operator of the pinned-semicanonical basis (the timed solve's), FP64
+    h.build_rhs(e2_s=False)
+    for _ in range(args.counter_run):
+        h.sigma_basis(x, y, P.ESMP2_FP64, P.ESMP2_BASIS_SEMICANONICAL)
     torch.cuda.synchronize()
     h.close()
     print("sigma done", flush=True)
