@@ -75,7 +75,8 @@ def build(verbose=False, incremental=False, jobs=None):
         sys.stderr.write("\n".join(errs))
         raise RuntimeError("hipcc failed building libesmp2.so")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for o, _ in res] + ["-o", tmp]
+    # rocBLAS serves the plain strided GEMMs of the set-up (rotations, integral blocks)
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for o, _ in res] + ["-o", tmp, "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -2184,12 +2184,12 @@ esmp2_status esmp2_fock_from_core_noalloc(esmp2_handle h, int n_occ, int n_vir, 
     g.A = B + (int64_t)q0 * nn; g.B = gam; g.C = T; g.M = n; g.N = n; g.K = n;
     g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1;
     g.sCb = n; g.sCi = (int64_t)qc * n; g.sCj = 1; g.alpha = 1; g.beta = 0;
-    ESMP2_HIP(gemm(s, qc, g));
+    ESMP2_HIP(gemm_native(s, qc, g));      // the hand-written kernel: no library workspace
     g = GemmArgs{};
     g.A = T; g.B = B + (int64_t)q0 * nn; g.C = K; g.M = n; g.N = n; g.K = qc * n;
     g.sAi = (int64_t)qc * n; g.sAk = 1; g.sBk = n; g.sBj = 1; g.sCi = n; g.sCj = 1; g.alpha = 1;
     g.beta = q0 == 0 ? 0.0 : 1.0;
-    ESMP2_HIP(gemm(s, 1, g));
+    ESMP2_HIP(gemm_native(s, 1, g));
   }
   hipLaunchKernelGGL(k_fock_combine, dim3(nblk(nn)), dim3(256), 0, s, hcore, B, (const double*)d, (const double*)K, n,
                      n_aux, F_out);

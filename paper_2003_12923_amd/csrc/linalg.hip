@@ -10,6 +10,9 @@
 #include "mfma.h"
 #include "reduce.h"
 #include <math.h>
+#include <rocblas/rocblas.h>
+#include <algorithm>
+#include <vector>
 
 namespace esmp2 {
 
@@ -110,11 +113,67 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-hipError_t gemm(hipStream_t s, int batch, const GemmArgs& g) {
+// the hand-written kernel (allocates nothing)
+hipError_t gemm_native(hipStream_t s, int batch, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || batch <= 0) return hipSuccess;
   dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, batch);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
   return hipGetLastError();
+}
+
+// rocBLAS handle of this host thread on the current device (created on first
+// use, kept until the process ends); null if it cannot be created
+static rocblas_handle blas_handle() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+  thread_local std::vector<rocblas_handle> hs;
+  if ((int)hs.size() <= dev) hs.resize(dev + 1, nullptr);
+  if (!hs[dev] && rocblas_create_handle(&hs[dev]) != rocblas_status_success) hs[dev] = nullptr;
+  return hs[dev];
+}
+
+// One column-major operand of rocBLAS from a strided one: element (r, c) of an
+// R x C matrix at r * sr + c * sc.  Unit row stride: op N, ld = sc; unit column
+// stride: op T of the stored C x R matrix, ld = sr.  False if neither is unit or
+// the leading dimension is too small.
+static bool blas_operand(int64_t sr, int64_t sc, int R, int C, rocblas_operation& op, rocblas_int& ld) {
+  if (sr == 1 && sc >= R && sc <= INT32_MAX) { op = rocblas_operation_none; ld = (rocblas_int)std::max<int64_t>(sc, 1); return true; }
+  if (sc == 1 && sr >= C && sr <= INT32_MAX) { op = rocblas_operation_transpose; ld = (rocblas_int)std::max<int64_t>(sr, 1); return true; }
+  if (R == 1 && sc == 1) { op = rocblas_operation_none; ld = 1; return true; }
+  if (C == 1 && sr == 1) { op = rocblas_operation_none; ld = (rocblas_int)std::max(R, 1); return true; }
+  return false;
+}
+
+// C[b] = alpha A[b] B[b] + beta C[b] for plain strided operands through rocBLAS
+// (one strided-batched DGEMM); false when the layout has no such form or the
+// call fails before anything is queued
+static bool gemm_blas(hipStream_t s, int batch, const GemmArgs& g) {
+  if (g.K <= 0) return false;
+  rocblas_handle bh = blas_handle();
+  if (!bh || rocblas_set_stream(bh, s) != rocblas_status_success) return false;
+  rocblas_operation oa, ob;
+  rocblas_int la, lb;
+  rocblas_status st;
+  if (g.sCj == 1 && g.sCi >= g.N && g.sCi <= INT32_MAX) {
+    // row-major C: C^T (N x M) = B^T (N x K) A^T (K x M)
+    if (!blas_operand(g.sBj, g.sBk, g.N, g.K, ob, lb) || !blas_operand(g.sAk, g.sAi, g.K, g.M, oa, la)) return false;
+    st = rocblas_dgemm_strided_batched(bh, ob, oa, g.N, g.M, g.K, &g.alpha, g.B, lb, g.sBb, g.A, la, g.sAb, &g.beta,
+                                       g.C, (rocblas_int)g.sCi, g.sCb, batch);
+  } else if (g.sCi == 1 && g.sCj >= g.M && g.sCj <= INT32_MAX) {
+    // column-major C: C (M x N) = A (M x K) B (K x N)
+    if (!blas_operand(g.sAi, g.sAk, g.M, g.K, oa, la) || !blas_operand(g.sBk, g.sBj, g.K, g.N, ob, lb)) return false;
+    st = rocblas_dgemm_strided_batched(bh, oa, ob, g.M, g.N, g.K, &g.alpha, g.A, la, g.sAb, g.B, lb, g.sBb, &g.beta,
+                                       g.C, (rocblas_int)g.sCj, g.sCb, batch);
+  } else {
+    return false;
+  }
+  return st == rocblas_status_success;
+}
+
+hipError_t gemm(hipStream_t s, int batch, const GemmArgs& g) {
+  if (g.M <= 0 || g.N <= 0 || batch <= 0) return hipSuccess;
+  if (gemm_blas(s, batch, g)) return hipGetLastError();
+  return gemm_native(s, batch, g);
 }
 
 // ---------------------------------------------------------------------------
