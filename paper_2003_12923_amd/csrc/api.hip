@@ -222,6 +222,8 @@ static bool dalloc(esmp2_handle h, T** p, size_t count) {
 }
 
 static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+// workgroups of the grid-stride Jacobi-diagonal kernel (<= nblk(n): blockmin holds one entry per workgroup)
+static inline unsigned diag_grid(int64_t n) { return std::min<unsigned>(nblk(n), (unsigned)DIAG_BLOCKS); }
 
 // Eigenpairs of a symmetric m x m matrix A (device, contiguous) by the
 // tridiagonal route of the AVO step: evals ascending, Y[i*m + k] = component i
@@ -791,13 +793,14 @@ static esmp2_status build_rhs(esmp2_handle h) {
   }
   if (h->ntop == 1) {
     DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv32, h->blockmin};
-    hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
+    hipLaunchKernelGGL(k_diag, dim3(diag_grid(namp)), dim3(256), 0, s, da);
   } else {
     const TopkArgs ta = topk_args(h);
     hipLaunchKernelGGL(k_topk_bset, dim3(nblk(d.off[7])), dim3(256), 0, s, ta, 0, (const double*)h->btmp, h->b);
     hipLaunchKernelGGL(k_topk_diag, dim3(nblk(namp)), dim3(256), 0, s, ta, h->dinv32, h->blockmin);
   }
-  hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
+  hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin,
+                     (int64_t)(h->ntop > 1 ? nblk(namp) : diag_grid(namp)), h->sc + SC_TMP);
   // E2_S on the side stream (after the eigenproblems queued there), beside the
   // solve: it reads Vint, lam, eo, ev, omega and the pair tables, which the
   // next rotation or right-hand side rewrites only after joining it.  Grids of
@@ -1187,7 +1190,7 @@ static esmp2_status semican_operator(esmp2_handle h) {
   hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)no * nv)), dim3(256), 0, s, (const double*)h->fov_sc,
                      h->fov32_sc, (int64_t)no * nv);
   DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv32_sc, h->blockmin};
-  hipLaunchKernelGGL(k_diag, dim3(nblk(namp)), dim3(256), 0, s, da);
+  hipLaunchKernelGGL(k_diag, dim3(diag_grid(namp)), dim3(256), 0, s, da);
   ESMP2_HIP(hipGetLastError());
   h->have_sc_op = true;
   return ESMP2_OK;

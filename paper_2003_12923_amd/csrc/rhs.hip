@@ -250,15 +250,18 @@ __device__ inline double diag_of(const Dims& d, int box, int loc, const double* 
   }
 }
 
+// grid-stride over the amplitudes (a grid of at most DIAG_BLOCKS workgroups)
+constexpr int DIAG_BLOCKS = 2048;
+
 __global__ __launch_bounds__(256) void k_diag(DiagArgs A) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double mn = 1e300;
-  if (g < A.d.off[7]) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < A.d.off[7];
+       g += (int64_t)gridDim.x * blockDim.x) {
     int loc;
     int box = box_of(A.d, g, loc);
     double D = diag_of(A.d, box, loc, A.eo, A.ev, A.omega);
     A.dinv[g] = (float)(1.0 / D);
-    mn = D;
+    mn = fmin(mn, D);
   }
   // block minimum
   for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o));
