@@ -416,7 +416,7 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
     // reflector scalars, in every wavefront (same reduction order everywhere)
     double s = 0.0;
     for (int i = k + 2 + l; i < m; i += 64) { const double x = A[pk(k, i, m)]; s += x * x; }
-    const double sig = wave_sum(s);
+    const double sig = wave_sum_dpp(s);
     const double x0 = A[pk(k, k + 1, m)];
     double b = 0.0, alpha = x0, v0 = 0.0;
     if (sig > 0.0) {
@@ -443,15 +443,16 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
         for (; j < i; j += 8) acc += A[pk(j, j, m) - j + i] * vv(j);
         const int ri = pk(i, i, m) - i;
         for (; j < m; j += 8) acc += A[ri + j] * vv(j);
-        acc += __shfl_xor(acc, 1);
-        acc += __shfl_xor(acc, 2);
-        acc += __shfl_xor(acc, 4);
+        // sum of the 8 lanes of the row (whole groups of 8 are active together)
+        acc += dpp_move<0xb1, 0xf>(acc);     // quad_perm [1,0,3,2]
+        acc += dpp_move<0x4e, 0xf>(acc);     // quad_perm [2,3,0,1]
+        acc += dpp_move<0x141, 0xf>(acc);    // row_half_mirror: the other quad of the 8
         if (part == 0) p[i] = b * acc;
       }
       __syncthreads();
       double kk = 0.0;
       for (int i = k + 1 + l; i < m; i += 64) kk += vv(i) * p[i];
-      const double K = 0.5 * b * wave_sum(kk);
+      const double K = 0.5 * b * wave_sum_dpp(kk);
       // A22 -= v w^T + w v^T (upper part), w = p - K v
       for (int i = k + 1 + wave; i < m; i += nw) {
         const double vi = vv(i), wi = p[i] - K * vi;

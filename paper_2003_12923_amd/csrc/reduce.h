@@ -7,6 +7,32 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Wavefront sum through DPP lane moves (no LDS traffic): quad sums, 8- and
+// 16-lane sums by mirrors, then rows 1 and 3 take rows 0 and 2 (row_bcast:15)
+// and row 3 takes lanes 0-31 (row_bcast:31); lane 63 holds the total, read back
+// into every lane.  A fixed order, the same in every wavefront.  All 64 lanes
+// must be active.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_move<0xb1, 0xf>(v);     // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e, 0xf>(v);     // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xf>(v);    // row_half_mirror
+  v += dpp_move<0x140, 0xf>(v);    // row_mirror
+  v += dpp_move<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Sum over the workgroup (blockDim.x a multiple of 64, <= 1024); result valid in thread 0.
 __device__ inline double block_sum(double v) {
   __shared__ double ws[16];

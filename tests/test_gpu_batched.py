@@ -87,7 +87,8 @@ def test_batched_stops_per_state(lib, handles):
         assert abs(one["rel_resid"] - r["rel_resid"]) <= 1e-6 * one["rel_resid"]
     res = lib.solve_batch(hs, tol=2.0, max_iter=50, basis=lib.ESMP2_BASIS_SEMICANONICAL)
     for r in res:
-        assert r["status"] == 0 and r["iterations"] == 0 and r["rel_resid"] == 1.0
+        # ||r|| / ||b|| at x = 0 from two reductions of the same numbers in different orders
+        assert r["status"] == 0 and r["iterations"] == 0 and abs(r["rel_resid"] - 1.0) < 1e-13
         assert r["e2"] == r["e2_s"] and r["e2_dl"] == 0.0
 
 
