@@ -211,9 +211,9 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi(const double* __restrict__ 
           double x = C[p * nv + a], y = C[q * nv + a];
           al += x * x; be += y * y; ga += x * y;
         }
-        for (int o = 32; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o); be += __shfl_xor(be, o); ga += __shfl_xor(ga, o);
-        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
         if (fabs(ga) > 1e-15 * sqrt(al * be) && fabs(ga) > 1e-300) {
           double ze = (be - al) / (2.0 * ga);
           double t = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi(const double* __restrict__ 
   for (int k = wave; k < no; k += nwave) {
     double s2 = 0;
     for (int a = l; a < nv; a += 64) s2 += C[k * nv + a] * C[k * nv + a];
-    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+    s2 = wave_sum(s2);
     if (l == 0) nrm[k] = sqrt(s2);
   }
   __syncthreads();
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
     // reflector scalars, in every wavefront (same reduction order everywhere)
     double s = 0.0;
     for (int i = k + 2 + l; i < m; i += 64) { const double x = A[pk(k, i, m)]; s += x * x; }
-    const double sig = wave_sum_dpp(s);
+    const double sig = wave_sum(s);
     const double x0 = A[pk(k, k + 1, m)];
     double b = 0.0, alpha = x0, v0 = 0.0;
     if (sig > 0.0) {
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* Ain, int m, doub
       __syncthreads();
       double kk = 0.0;
       for (int i = k + 1 + l; i < m; i += 64) kk += vv(i) * p[i];
-      const double K = 0.5 * b * wave_sum_dpp(kk);
+      const double K = 0.5 * b * wave_sum(kk);
       // A22 -= v w^T + w v^T (upper part), w = p - K v
       for (int i = k + 1 + wave; i < m; i += nw) {
         const double vi = vv(i), wi = p[i] - K * vi;

@@ -1,11 +1,6 @@
-// Deterministic FP64 block reductions (wavefront shuffle tree, then LDS).
+// Deterministic FP64 block reductions (wavefront DPP tree, then LDS).
 #pragma once
 #include <hip/hip_runtime.h>
-
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 
 // Wavefront sum through DPP lane moves (no LDS traffic): quad sums, 8- and
 // 16-lane sums by mirrors, then rows 1 and 3 take rows 0 and 2 (row_bcast:15)
@@ -20,7 +15,7 @@ __device__ inline double dpp_move(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ inline double wave_sum_dpp(double v) {
+__device__ inline double wave_sum(double v) {
   v += dpp_move<0xb1, 0xf>(v);     // quad_perm [1,0,3,2]
   v += dpp_move<0x4e, 0xf>(v);     // quad_perm [2,3,0,1]
   v += dpp_move<0x141, 0xf>(v);    // row_half_mirror
@@ -61,14 +56,30 @@ struct Acc2 {
   __device__ inline double value() const { return s + c; }
 };
 
-__device__ inline Acc2 wave_sum2(Acc2 a) {
-  for (int o = 32; o > 0; o >>= 1) {
-    Acc2 b;
-    b.s = __shfl_xor(a.s, o);
-    b.c = __shfl_xor(a.c, o);
-    a.add(b);
-  }
+template <int CTRL, int ROWS>
+__device__ inline Acc2 acc2_dpp_step(Acc2 a) {
+  Acc2 b;
+  b.s = dpp_move<CTRL, ROWS>(a.s);       // a disabled row receives (0, 0), which leaves (s, c) unchanged
+  b.c = dpp_move<CTRL, ROWS>(a.c);
+  a.add(b);
   return a;
+}
+
+// Compensated wavefront sum, the DPP order of wave_sum; every lane gets the total.
+__device__ inline Acc2 wave_sum2(Acc2 a) {
+  a = acc2_dpp_step<0xb1, 0xf>(a);
+  a = acc2_dpp_step<0x4e, 0xf>(a);
+  a = acc2_dpp_step<0x141, 0xf>(a);
+  a = acc2_dpp_step<0x140, 0xf>(a);
+  a = acc2_dpp_step<0x142, 0xa>(a);
+  a = acc2_dpp_step<0x143, 0xc>(a);
+  Acc2 r;
+  const long long bs = __double_as_longlong(a.s), bc = __double_as_longlong(a.c);
+  r.s = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(bs >> 32), 63) << 32) |
+                             (unsigned)__builtin_amdgcn_readlane((int)(bs & 0xffffffff), 63));
+  r.c = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(bc >> 32), 63) << 32) |
+                             (unsigned)__builtin_amdgcn_readlane((int)(bc & 0xffffffff), 63));
+  return r;
 }
 
 // Compensated workgroup sum; result valid in thread 0.
