@@ -1128,8 +1128,11 @@ static esmp2_status rotate_amplitudes(esmp2_handle h, const double* x, double* y
     const int64_t sro = forward ? d.no : 1, sco = forward ? 1 : d.no;
     const int64_t srv = forward ? d.nv : 1, scv = forward ? 1 : d.nv;
     const int64_t nd = (int64_t)ro * ro * rv * rv;
-    hipLaunchKernelGGL(k_unpack_box, dim3(nblk(nd)), dim3(256), 0, s, d, box, x, h->dense0);
-    ESMP2_HIP(contract_index(s, 3, ro, rv, Gv, srv, scv, h->dense0, h->dense1));
+    // S2 and H2P2 are stored dense in exactly the [P][Q][A][B] order: read from
+    // x and written to y in place of the unpack and pack passes
+    const bool dense_box = box == B_S2 || box == B_H22;
+    if (!dense_box) hipLaunchKernelGGL(k_unpack_box, dim3(nblk(nd)), dim3(256), 0, s, d, box, x, h->dense0);
+    ESMP2_HIP(contract_index(s, 3, ro, rv, Gv, srv, scv, dense_box ? x + d.off[box] : h->dense0, h->dense1));
     ESMP2_HIP(contract_index(s, 2, ro, rv, Gv, srv, scv, h->dense1, h->dense0));
     const int64_t v2 = (int64_t)rv * rv;
     dim3 grid_o((unsigned)((v2 + 255) / 256), (unsigned)ro);
@@ -1142,9 +1145,10 @@ static esmp2_status rotate_amplitudes(esmp2_handle h, const double* x, double* y
         hipLaunchKernelGGL(k_rot_occ<64>, grid_o, dim3(256), 0, s, in, out, Go, sro, sco, ro, v2, which);
     };
     rot_occ(h->dense0, h->dense1, 0);
-    rot_occ(h->dense1, h->dense0, 1);
-    hipLaunchKernelGGL(k_pack_box, dim3(nblk(d.off[box + 1] - d.off[box])), dim3(256), 0, s, d, box,
-                       (const double*)h->dense0, y);
+    rot_occ(h->dense1, dense_box ? y + d.off[box] : h->dense0, 1);
+    if (!dense_box)
+      hipLaunchKernelGGL(k_pack_box, dim3(nblk(d.off[box + 1] - d.off[box])), dim3(256), 0, s, d, box,
+                         (const double*)h->dense0, y);
   }
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
