@@ -172,8 +172,11 @@ __device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, i
           const int cc = seg + 16 * i;
           if (cc < m) sacc += tile[rr][cc] * w[cc + lo];
         }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o);
+        // sum over the 16-lane group (DPP: quads, then the mirrored quad and half)
+        sacc += dpp_move<0xb1, 0xf>(sacc);
+        sacc += dpp_move<0x4e, 0xf>(sacc);
+        sacc += dpp_move<0x141, 0xf>(sacc);
+        sacc += dpp_move<0x140, 0xf>(sacc);
         if (seg == 0 && r0 + rr < m) rowres[k][r0 + rr] = sacc;
       }
     }
