@@ -210,8 +210,28 @@ class Handle:
         self._B = torch.from_numpy(prob.B).to(dev)
         self._C = torch.from_numpy(prob.C).to(dev)
         self._n_occ = prob.n_occ
+        self.n_top = n_top
         self.set_problem(self._F, self._B, self._C, prob.n_occ, prob.n_vir, prob.n_aux, spin=spin, n_top=n_top)
         return self
+
+    def load_threshold(self, prob, eta, spin=0):
+        """Bind prob with the large TOPs chosen by a singular-value threshold
+        (paper Sec. II.C): one rotation with one large TOP gives the singular
+        values of C, then the problem is bound again with
+        n_top = large_top_count(lambda, eta) (the amplitude layout depends on it).
+        The chosen count is in self.n_top."""
+        self.load(prob, spin=spin, n_top=1)
+        k = large_top_count(self.rotate_top(), eta)
+        if k != 1:
+            self.load(prob, spin=spin, n_top=k)
+        return self
+
+
+def large_top_count(lam, eta):
+    """Number of transition-orbital pairs treated as large under the threshold
+    eta on the singular values of C (paper Sec. II.C): those with lambda >= eta,
+    at least one (the dominant pair is always large)."""
+    return max(1, sum(1 for v in lam if v >= eta))
 
 
 def solve_batch(handles, tol=1e-8, max_iter=300, precision=ESMP2_FP64, basis=ESMP2_BASIS_TOP, inner_tol=0.0,

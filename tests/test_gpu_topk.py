@@ -163,3 +163,25 @@ def test_topk_arguments(lib):
     with pytest.raises(lib.Esmp2Error):
         h.gradient(x, dF=torch.zeros((8, 8), dtype=torch.float64, device="cuda"))
     h.close()
+
+
+def test_topk_threshold_selection(lib):
+    """Large TOPs chosen by a singular-value threshold (Sec. II.C): the count of
+    lambda >= eta, at least one; the bound problem equals the one bound with that
+    count directly (same space, same E2)."""
+    prob = synth.config_problem("c1")
+    lam = topbasis.top_rotation(prob.F, prob.C, prob.n_occ)[0]
+    assert lib.large_top_count(lam, 2.0) == 1 and lib.large_top_count(lam, 0.0) == len(lam)
+    eta = 0.5 * (lam[1] + lam[2])                     # two pairs at or above the threshold
+    assert lib.large_top_count(lam, eta) == 2
+    print(f"[case] c1 threshold eta={eta:.3e}", flush=True)
+    h = lib.Handle(0).load_threshold(prob, eta)
+    assert h.n_top == 2
+    h.rotate_top()
+    r = h.solve(tol=1e-11, max_iter=500)
+    h2 = lib.Handle(0).load(prob, n_top=2)
+    h2.rotate_top()
+    r2 = h2.solve(tol=1e-11, max_iter=500)
+    assert h.space() == h2.space() and r["status"] == 0 and abs(r["e2"] - r2["e2"]) < 1e-12
+    h.close()
+    h2.close()
