@@ -676,11 +676,11 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   hipLaunchKernelGGL(k_topfock, dim3(nblk((int64_t)mv * mv > n * n ? (int64_t)mv * mv : (int64_t)n * n)), dim3(256),
                      0, s, h->Ft, h->lam, no, nv, mv, h->fo, h->fv, h->fov, h->eo, h->ev, h->Fd, h->Fl, h->sc_rot);
   // the FP32 operator's Fock blocks, rounded from the FP64 ones
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, h->Fd, h->Fd32, (int64_t)mv * mv);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, h->Fl, h->Fl32, (int64_t)mv * mv);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk(no * no)), dim3(256), 0, s, h->fo, h->fo32, (int64_t)no * no);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, h->fv, h->fv32, (int64_t)nv * nv);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)no * nv)), dim3(256), 0, s, h->fov, h->fov32, (int64_t)no * nv);
+  {
+    const ToF32Set t{{h->Fd, h->Fl, h->fo, h->fv, h->fov}, {h->Fd32, h->Fl32, h->fo32, h->fv32, h->fov32},
+                     {(int64_t)mv * mv, (int64_t)mv * mv, (int64_t)no * no, (int64_t)nv * nv, (int64_t)no * nv}};
+    hipLaunchKernelGGL(k_to_f32_set, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, t);
+  }
   {
     esmp2_status st = launch_semican_eig(h);
     if (st != ESMP2_OK) return st;
@@ -1183,16 +1183,12 @@ static esmp2_status semican_operator(esmp2_handle h) {
   hipLaunchKernelGGL(k_fock_blocks, dim3(nblk((int64_t)mv * mv > n * n ? (int64_t)mv * mv : (int64_t)n * n)),
                      dim3(256), 0, s, (const double*)h->Fh, no, nv, mv, h->omega, h->kappa, h->fo_sc, h->fv_sc,
                      h->fov_sc, h->eo_sc, h->ev_sc, h->Fd_sc, h->Fl_sc);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, (const double*)h->Fd_sc, h->Fd32_sc,
-                     (int64_t)mv * mv);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, (const double*)h->Fl_sc, h->Fl32_sc,
-                     (int64_t)mv * mv);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk(no * no)), dim3(256), 0, s, (const double*)h->fo_sc, h->fo32_sc,
-                     (int64_t)no * no);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, (const double*)h->fv_sc, h->fv32_sc,
-                     (int64_t)nv * nv);
-  hipLaunchKernelGGL(k_to_f32, dim3(nblk((int64_t)no * nv)), dim3(256), 0, s, (const double*)h->fov_sc,
-                     h->fov32_sc, (int64_t)no * nv);
+  {
+    const ToF32Set t{{h->Fd_sc, h->Fl_sc, h->fo_sc, h->fv_sc, h->fov_sc},
+                     {h->Fd32_sc, h->Fl32_sc, h->fo32_sc, h->fv32_sc, h->fov32_sc},
+                     {(int64_t)mv * mv, (int64_t)mv * mv, (int64_t)no * no, (int64_t)nv * nv, (int64_t)no * nv}};
+    hipLaunchKernelGGL(k_to_f32_set, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, t);
+  }
   DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv32_sc, h->blockmin};
   hipLaunchKernelGGL(k_diag, dim3(diag_grid(namp)), dim3(256), 0, s, da);
   ESMP2_HIP(hipGetLastError());

@@ -303,6 +303,21 @@ __global__ void k_to_f32(const double* a, float* b, int64_t n) {
     b[g] = (float)a[g];
 }
 
+// up to five FP64 -> FP32 conversions in one launch (the Fock blocks of an operator)
+struct ToF32Set {
+  const double* a[5];
+  float* b[5];
+  int64_t n[5];
+};
+
+__global__ void k_to_f32_set(ToF32Set t) {
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    for (int64_t g = g0; g < t.n[k]; g += st) t.b[k][g] = (float)t.a[k][g];
+}
+
 template __global__ void k_dot<double>(const double*, const double*, int64_t, int64_t, int64_t, double*);
 template __global__ void k_dot<float>(const float*, const float*, int64_t, int64_t, int64_t, double*);
 template __global__ void k_update_r<double>(double*, const double*, const float*, int64_t, int64_t, int64_t,
