@@ -152,9 +152,11 @@ esmp2_status esmp2_destroy(esmp2_handle h);
  *   n_top: number of large TOPs, 1 <= n_top <= n_occ (else ESMP2_INVALID_ARG).
  *         n_top > 1 (ESMP2-TOP(k), up to TOP(all)) applies the operator by a
  *         generic determinant-level kernel, O(N_o + N_v) per amplitude, and
- *         supports the FP64 solve in the TOP basis, esmp2_sigma (FP64),
- *         esmp2_build_rhs and esmp2_export_determinants; the other calls
- *         return ESMP2_UNSUPPORTED.
+ *         supports the solve in the TOP basis (FP64, or FP64 refinement around
+ *         the same operator on FP32 vectors), esmp2_sigma (FP64 or FP32),
+ *         esmp2_build_rhs and esmp2_export_determinants; BF16, the
+ *         pinned-semicanonical basis and the gradient return
+ *         ESMP2_UNSUPPORTED.
  * Requires 2 <= n_occ <= n_vir, n_aux >= 1.  Checks F, B, C for NaN/Inf
  * (synchronises the stream).  Resets any previous problem. */
 esmp2_status esmp2_set_problem(esmp2_handle h, int n_occ, int n_vir, int n_aux,

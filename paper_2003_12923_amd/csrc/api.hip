@@ -1220,19 +1220,18 @@ struct OpCtx {
   bool arrow;        // the operator through the arrow kernels
 };
 
-// y = A x of ESMP2-TOP(k), k > 1 (FP64)
-static esmp2_status sigma_topk(esmp2_handle h, const double* x, double* y) {
+// y = A x of ESMP2-TOP(k), k > 1 (FP64 or FP32 vectors)
+template <class T>
+static esmp2_status sigma_topk(esmp2_handle h, const T* x, T* y) {
   const TopkArgs ta = topk_args(h);
-  hipLaunchKernelGGL(k_topk_sigma, dim3(nblk(h->namp)), dim3(256), 0, h->stream, ta, x, y);
+  hipLaunchKernelGGL(k_topk_sigma<T>, dim3(nblk(h->namp)), dim3(256), 0, h->stream, ta, x, y);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
 
 template <class T>
 static esmp2_status apply_op(esmp2_handle h, const OpCtx& c, const SigmaBufs<T>& w, const T* x, T* y) {
-  if constexpr (std::is_same<T, double>::value) {
-    if (h->ntop > 1) return sigma_topk(h, x, y);
-  }
+  if (h->ntop > 1) return sigma_topk(h, x, y);
   return c.arrow ? sigma_arrow(h, w, x, y) : sigma_t(h, w, x, y);
 }
 
@@ -1242,13 +1241,11 @@ static void wdot(esmp2_handle h, const T* x, const T* y, int slot);
 // y = A x and sc[SC_PQ] = <x, y>_W (fused into the operator where it writes every element once)
 template <class T>
 static esmp2_status apply_op_dot(esmp2_handle h, const OpCtx& c, const SigmaBufs<T>& w, const T* x, T* y) {
-  if constexpr (std::is_same<T, double>::value) {
-    if (h->ntop > 1) {
-      const esmp2_status st = sigma_topk(h, x, y);
-      if (st != ESMP2_OK) return st;
-      wdot(h, x, (const T*)y, SC_PQ);
-      return ESMP2_OK;
-    }
+  if (h->ntop > 1) {
+    const esmp2_status st = sigma_topk(h, x, y);
+    if (st != ESMP2_OK) return st;
+    wdot(h, x, (const T*)y, SC_PQ);
+    return ESMP2_OK;
   }
   if (c.arrow && h->nchunks > 0) {
     esmp2_status st = sigma_arrow(h, w, x, y, h->pq_part);
@@ -1282,8 +1279,9 @@ esmp2_status esmp2_sigma(esmp2_handle h, const void* x, void* y, int precision) 
   if (x == y) return fail(h, ESMP2_INVALID_ARG, "x and y must not overlap");
   ESMP2_HIP(hipSetDevice(h->device));
   if (h->ntop > 1) {
-    if (precision != ESMP2_FP64) return fail(h, ESMP2_UNSUPPORTED, "more than one large TOP: FP64 only");
-    return sigma_topk(h, (const double*)x, (double*)y);
+    if (precision == ESMP2_FP64) return sigma_topk(h, (const double*)x, (double*)y);
+    if (precision == ESMP2_FP32) return sigma_topk(h, (const float*)x, (float*)y);
+    return fail(h, ESMP2_UNSUPPORTED, "more than one large TOP: FP64 or FP32");
   }
   if (precision == ESMP2_FP64) return sigma64(h, (const double*)x, (double*)y);
   if (precision == ESMP2_FP32) return sigma32(h, (const float*)x, (float*)y);
@@ -1606,8 +1604,8 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
     return fail(h, ESMP2_INVALID_ARG, "unknown basis");
   if (opts->precision != ESMP2_FP64 && !(opts->inner_tol >= 0 && opts->inner_tol < 1))
     return fail(h, ESMP2_INVALID_ARG, "inner_tol must lie in [0, 1)");
-  if (h->ntop > 1 && (opts->precision != ESMP2_FP64 || opts->basis != ESMP2_BASIS_TOP))
-    return fail(h, ESMP2_UNSUPPORTED, "more than one large TOP: FP64 solve in the TOP basis only");
+  if (h->ntop > 1 && (opts->precision == ESMP2_BF16 || opts->basis != ESMP2_BASIS_TOP))
+    return fail(h, ESMP2_UNSUPPORTED, "more than one large TOP: FP64 or FP32-refined solve in the TOP basis only");
   ESMP2_HIP(hipSetDevice(h->device));
   memset(res, 0, sizeof(*res));
   if (!h->have_rhs) {

@@ -200,7 +200,8 @@ __device__ inline int nbelow(int v, const int* h, const int* p, int nh, int no, 
 
 // amplitude of element e's own determinant in the operator-string convention
 // (S2 flip-symmetrised)
-__device__ inline double own_amp(const TopkArgs& A, const double* x, int64_t e) {
+template <class T>
+__device__ inline double own_amp(const TopkArgs& A, const T* x, int64_t e) {
   const Dims& d = A.d;
   if (e >= d.off[B_S2] && e < d.off[B_S2 + 1]) {
     int r = (int)(e - d.off[B_S2]);
@@ -209,13 +210,14 @@ __device__ inline double own_amp(const TopkArgs& A, const double* x, int64_t e) 
     const int a = r % nv; r /= nv;
     const int j = r % no, i = r / no;
     const int64_t pe = d.off[B_S2] + (((int64_t)j * no + i) * nv + b) * nv + a;
-    return 0.5 * (x[e] + A.sg * x[pe]);
+    return 0.5 * ((double)x[e] + A.sg * (double)x[pe]);
   }
-  return x[e];
+  return (double)x[e];
 }
 
 // coefficient of determinant (h, p) in Psi (0 outside D + L)
-__device__ inline double det_coeff(const TopkArgs& A, const double* x, const int* h, const int* p, int nh) {
+template <class T>
+__device__ inline double det_coeff(const TopkArgs& A, const T* x, const int* h, const int* p, int nh) {
   bool own = true;
   const int64_t e = topk_pos(A, h, p, nh, own);
   if (e < 0) return 0.0;
@@ -228,14 +230,16 @@ __device__ inline bool holds(const int* v, int n, int x) {
   return r;
 }
 
-// y = (H0 - E0) x on D + L of TOP(k), one thread per element
-__global__ __launch_bounds__(256) void k_topk_sigma(TopkArgs A, const double* x, double* y) {
+// y = (H0 - E0) x on D + L of TOP(k), one thread per element; T: the storage of x and y
+// (FP64, or FP32 for the inner solves of the mixed-precision refinement), arithmetic in FP64
+template <class T>
+__global__ __launch_bounds__(256) void k_topk_sigma(TopkArgs A, const T* x, T* y) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= A.namp) return;
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv, N = d.n;
   int h[3], p[3], nh, set, box;
-  if (!topk_decode(A, g, h, p, nh, set, box)) { y[g] = 0.0; return; }
+  if (!topk_decode(A, g, h, p, nh, set, box)) { y[g] = T(0); return; }
   const double* F = A.Ft;
   double diag = -A.omega;
   for (int q = 0; q < nh; ++q) diag += F[(p[q] % N) * (N + 1)] - F[(h[q] % N) * (N + 1)];
@@ -312,8 +316,11 @@ __global__ __launch_bounds__(256) void k_topk_sigma(TopkArgs A, const double* x,
         }
     }
   }
-  y[g] = (double)A.s0[g] * acc;
+  y[g] = T((double)A.s0[g] * acc);
 }
+
+template __global__ void k_topk_sigma<double>(TopkArgs, const double*, double*);
+template __global__ void k_topk_sigma<float>(TopkArgs, const float*, float*);
 
 // s0[g]: canonical phase of element g's operator string (the one-TOP layout's
 // string with the set's relabelling); 0 for a masked slot

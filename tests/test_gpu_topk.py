@@ -154,7 +154,7 @@ def test_topk_arguments(lib):
             h.load(prob, n_top=bad)
     h.load(prob, n_top=2)
     h.rotate_top()
-    for kw in (dict(precision=lib.ESMP2_FP32), dict(basis=lib.ESMP2_BASIS_SEMICANONICAL)):
+    for kw in (dict(precision=lib.ESMP2_BF16), dict(basis=lib.ESMP2_BASIS_SEMICANONICAL)):
         with pytest.raises(lib.Esmp2Error):
             h.solve(tol=1e-8, max_iter=50, **kw)
     n, _ = h.space()
@@ -185,3 +185,32 @@ def test_topk_threshold_selection(lib):
     assert h.space() == h2.space() and r["status"] == 0 and abs(r["e2"] - r2["e2"]) < 1e-12
     h.close()
     h2.close()
+
+
+@pytest.mark.parametrize("no,nv,na,seed,k,spin", [(4, 7, 9, 4, 2, 0), (3, 5, 7, 3, 2, 1), (4, 16, 48, -1, 2, 0),
+                                                  (4, 16, 48, -1, 4, 0)])
+def test_topk_mixed_precision(lib, no, nv, na, seed, k, spin):
+    """FP64 refinement around the TOP(k) operator applied to FP32 vectors: the
+    FP32 sigma within the FP32 rounding of the FP64 one, and E2 to 1e-10 Eh of
+    the oracle at an FP64 residual of 1e-10."""
+    h, tk, Ft, Bt, lam = _setup(lib, no, nv, na, seed, k, spin)
+    n, _ = h.space()
+    x = np.where(tk.live, synth.random_amplitudes(n, seed + 60), 0.0)
+    xt = torch.from_numpy(x).cuda()
+    y64 = torch.empty_like(xt)
+    h.sigma(xt, y64)
+    x32 = xt.float()
+    y32 = torch.empty_like(x32)
+    h.sigma(x32, y32, lib.ESMP2_FP32)
+    torch.cuda.synchronize()
+    ref = y64.cpu().numpy()
+    # the same FP64 arithmetic on FP32-rounded inputs: an error of the order of 2^-24 of the inputs
+    err = np.abs(y32.double().cpu().numpy() - ref).max()
+    print(f"[topk fp32 sigma] max err {err:.3e} of {np.abs(ref).max():.3e}", flush=True)
+    assert err <= 1e-5 * np.abs(ref).max()
+    r = tk.solve(tol=1e-12)
+    res = h.solve(tol=1e-10, max_iter=500, precision=lib.ESMP2_FP32)
+    print(f"[topk mixed E2] gpu {res['e2']:.14f} oracle {r['e2']:.14f} diff {res['e2'] - r['e2']:.3e} "
+          f"inner {res['iterations']} outer {res['outer']}", flush=True)
+    assert res["status"] == 0 and res["outer"] >= 1 and abs(res["e2"] - r["e2"]) < 1e-10
+    h.close()
