@@ -476,13 +476,24 @@ constexpr int TRI_MAX = 256;
 
 // Number of eigenvalues of the tridiagonal (d, e) smaller than x; e2 = e^2.
 // d and e2 live in LDS (all lanes read the same element: a broadcast).
+// 1/q from the hardware reciprocal estimate and two Newton steps (relative
+// error at the level of the FP64 rounding): the Sturm recurrence's one division
+// per step is its critical path, and the IEEE division sequence is several times
+// longer
+__device__ inline double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(fma(-q, r, 1.0), r, r);
+  r = fma(fma(-q, r, 1.0), r, r);
+  return r;
+}
+
 __device__ inline int sturm_count(const double* d, const double* e2, int m, double x, double tiny) {
   int cnt = 0;
   double q = d[0] - x;
   if (q < 0) ++cnt;
   for (int i = 1; i < m; ++i) {
     if (fabs(q) < tiny) q = -tiny;
-    q = d[i] - x - e2[i - 1] / q;
+    q = d[i] - x - e2[i - 1] * recip(q);
     if (q < 0) ++cnt;
   }
   return cnt;
