@@ -149,6 +149,7 @@ struct esmp2_handle_ {
   double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *b_sc;
   float *Fd32_sc, *Fl32_sc, *fo32_sc, *fv32_sc, *fov32_sc, *dinv32_sc;
   double *dense0, *dense1;
+  double* rsc;            // right-hand side in the pinned-semicanonical basis: C, fphi, Bov, X, one intermediate
   double* gv;                    // row/column GEMVs of the arrow-shaped Fock blocks (FP64 or FP32 use)
   // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream,
   // per operator precision (index = esmp2_precision)
@@ -224,6 +225,21 @@ static bool dalloc(esmp2_handle h, T** p, size_t count) {
 static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 // workgroups of the grid-stride Jacobi-diagonal kernel (<= nblk(n): blockmin holds one entry per workgroup)
 static inline unsigned diag_grid(int64_t n) { return std::min<unsigned>(nblk(n), (unsigned)DIAG_BLOCKS); }
+
+// The Jacobi diagonal of a TOP(1) operator and its per-workgroup minima: by the
+// coupling chunks where the table exists.  Returns the number of minima written.
+static unsigned launch_diag(esmp2_handle h, const DiagArgs& da) {
+  if (h->nchunks > 0) {
+    const Dims& d = h->d;
+    const int* pv = h->pairs;
+    const PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
+    const unsigned g = std::min<unsigned>((unsigned)((h->nchunks + DIAG_UNROLL - 1) / DIAG_UNROLL), diag_grid(h->namp));
+    hipLaunchKernelGGL(k_diag_chunks, dim3(g), dim3(256), 0, h->stream, da, pt, (const int4*)h->chunks, h->nchunks);
+    return g;
+  }
+  hipLaunchKernelGGL(k_diag, dim3(diag_grid(h->namp)), dim3(256), 0, h->stream, da);
+  return diag_grid(h->namp);
+}
 
 // Eigenpairs of a symmetric m x m matrix A (device, contiguous) by the
 // tridiagonal route of the AVO step: evals ascending, Y[i*m + k] = component i
@@ -465,6 +481,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
        dalloc(h, &h->Fl32_sc, (size_t)mv * mv) && dalloc(h, &h->fo32_sc, no * no) &&
        dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
        dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense) &&
+       dalloc(h, &h->rsc, (size_t)no * nv * (2 + 3 * (size_t)na)) &&
        dalloc(h, &h->gv, (size_t)nv * (2 * d.npo + 2 * no * no + (no - 1) * (no - 1)));
   if (n_top > 1)
     ok = ok && dalloc(h, &h->s0, namp) && dalloc(h, &h->Ft_s, (size_t)n * n) &&
@@ -772,8 +789,8 @@ static esmp2_status rhs_core(esmp2_handle h, const double* Ft, const double* Bov
   ESMP2_HIP(gemm(s, 1, g));
   g.A = h->X; g.C = h->Mint;
   ESMP2_HIP(gemm(s, 1, g));
-  RhsArgs ra{d, h->Vint, h->Mint, h->fphi, lam, b};
-  hipLaunchKernelGGL(k_rhs, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
+  RhsArgs ra{d, h->Vint, h->Mint, h->fphi, lam, b, nullptr};
+  hipLaunchKernelGGL(k_rhs<false>, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
@@ -791,16 +808,17 @@ static esmp2_status build_rhs(esmp2_handle h) {
     const esmp2_status st = rhs_core(h, h->Ft, h->Bov, h->Bvt, h->Boo, h->lam, h->ntop > 1 ? h->btmp : h->b);
     if (st != ESMP2_OK) return st;
   }
+  unsigned nmin = nblk(namp);
   if (h->ntop == 1) {
     DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv32, h->blockmin};
-    hipLaunchKernelGGL(k_diag, dim3(diag_grid(namp)), dim3(256), 0, s, da);
+    nmin = launch_diag(h, da);
   } else {
     const TopkArgs ta = topk_args(h);
     hipLaunchKernelGGL(k_topk_bset, dim3(nblk(d.off[7])), dim3(256), 0, s, ta, 0, (const double*)h->btmp, h->b);
     hipLaunchKernelGGL(k_topk_diag, dim3(nblk(namp)), dim3(256), 0, s, ta, h->dinv32, h->blockmin);
   }
   hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin,
-                     (int64_t)(h->ntop > 1 ? nblk(namp) : diag_grid(namp)), h->sc + SC_TMP);
+                     (int64_t)nmin, h->sc + SC_TMP);
   // E2_S on the side stream (after the eigenproblems queued there), beside the
   // solve: it reads Vint, lam, eo, ev, omega and the pair tables, which the
   // next rotation or right-hand side rewrites only after joining it.  Grids of
@@ -1190,20 +1208,75 @@ static esmp2_status semican_operator(esmp2_handle h) {
     hipLaunchKernelGGL(k_to_f32_set, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, t);
   }
   DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv32_sc, h->blockmin};
-  hipLaunchKernelGGL(k_diag, dim3(diag_grid(namp)), dim3(256), 0, s, da);
+  launch_diag(h, da);
   ESMP2_HIP(hipGetLastError());
   h->have_sc_op = true;
   return ESMP2_OK;
 }
 
+// Y[q] = To^T X[q] Tv for nq stacked no x nv matrices (a tensor in (i, a)
+// taken into the pinned-semicanonical basis); tmp holds nq * no * nv.
+static hipError_t rotate_ov(esmp2_handle h, int nq, const double* X, double* tmp, double* Y) {
+  const int no = h->d.no, nv = h->d.nv;
+  GemmArgs g{};
+  g.alpha = 1; g.beta = 0;
+  // tmp[(q,i)][A] = sum_a X[(q,i)][a] Tv[a][A]
+  g.A = X; g.B = h->Tv; g.C = tmp; g.M = nq * no; g.N = nv; g.K = nv;
+  g.sAi = nv; g.sAk = 1; g.sBk = nv; g.sBj = 1; g.sCi = nv; g.sCj = 1;
+  hipError_t e = gemm(h->stream, 1, g);
+  if (e != hipSuccess) return e;
+  // Y[q][I][A] = sum_i To[i][I] tmp[q][i][A]
+  g = GemmArgs{};
+  g.alpha = 1; g.beta = 0;
+  g.A = h->To; g.B = tmp; g.C = Y; g.M = no; g.N = nv; g.K = no;
+  g.sAb = 0; g.sAi = 1; g.sAk = no; g.sBb = (int64_t)no * nv; g.sBk = nv; g.sBj = 1;
+  g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1;
+  return gemm(h->stream, nq, g);
+}
+
+// The right-hand side built in the pinned-semicanonical basis instead of
+// rotating the TOP-basis one (a four-index rotation of every box): V, M and
+// f^Phi are tensors in their (i, a) index pairs, so the three-index factors
+// Bov and X and f^Phi are rotated (To^T . Tv) and V, M rebuilt from them; the
+// singles amplitudes of Psi0, diagonal in the TOP basis, become the matrix
+// C = To^T diag(c) Tv.  Requires the TOP-basis right-hand side's Bov, X and
+// f^Phi (esmp2_build_rhs) and the rotation (semican_operator).  V and M go to
+// the dense scratch buffers (n_occ^2 n_vir^2 each): the TOP-basis V stays for
+// E2_S on the side stream.
+static esmp2_status rhs_semican(esmp2_handle h) {
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
+  hipStream_t s = h->stream;
+  double* Cs = h->rsc;
+  double* fphi = Cs + nov;
+  double* Bov = fphi + nov;
+  double* X = Bov + (size_t)na * nov;
+  double* tmp = X + (size_t)na * nov;
+  hipLaunchKernelGGL(k_singles_sc, dim3(nblk(nov)), dim3(256), 0, s, (const double*)h->To, (const double*)h->Tv,
+                     (const double*)h->lam, no, nv, Cs);
+  ESMP2_HIP(rotate_ov(h, 1, h->fphi, tmp, fphi));
+  ESMP2_HIP(rotate_ov(h, na, h->Bov, tmp, Bov));
+  ESMP2_HIP(rotate_ov(h, na, h->X, tmp, X));
+  GemmArgs g{};
+  g.A = Bov; g.B = Bov; g.C = h->dense0; g.M = nov; g.N = nov; g.K = na;
+  g.sAi = 1; g.sAk = nov; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));
+  g.A = X; g.C = h->dense1;
+  ESMP2_HIP(gemm(s, 1, g));
+  RhsArgs ra{d, h->dense0, h->dense1, fphi, h->lam, h->b_sc, Cs};
+  hipLaunchKernelGGL(k_rhs<true>, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
+  ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
 // The operator of the pinned-semicanonical basis (if not built yet) and the
-// right-hand side rotated into it.  Requires the right-hand side.
+// right-hand side in it.  Requires the right-hand side.
 static esmp2_status semican_setup(esmp2_handle h) {
   if (!h->have_sc_op) {
     const esmp2_status st = semican_operator(h);
     if (st != ESMP2_OK) return st;
   }
-  const esmp2_status st = rotate_amplitudes(h, h->b, h->b_sc, true);
+  const esmp2_status st = rhs_semican(h);
   if (st != ESMP2_OK) return st;
   ESMP2_HIP(hipGetLastError());
   h->have_sc = true;

@@ -14,6 +14,7 @@
 //   V[(i,a),(j,b)] = (ia|jb)
 //   M[(i,a),(j,b)] = c_i (a i'|b j) - c_a (a_o i|b j)   (a_o: occupied a, a < n_occ)
 #include "common.h"
+#include "sigma.h"
 #include "reduce.h"
 #include <math.h>
 
@@ -86,10 +87,11 @@ __global__ void k_make_x(const double* Bvt, const double* Boo, const double* lam
 struct RhsArgs {
   Dims d;
   const double* V;      // (ia|jb)
-  const double* M;      // c_i (a i'|b j) - c_a (a_o i|b j)
+  const double* M;      // sum_Q X[Q][(i,a)] Bov[Q][(j,b)] (c_i (a i'|b j) - c_a (a_o i|b j) in the TOP basis)
   const double* fphi;   // no x nv
   const double* lam;
   double* b;
+  const double* Cs;     // GEN: singles amplitudes C[i][a] of Psi0 in the orbital basis of V, M, fphi (no x nv)
 };
 
 // Box and local index of a flat amplitude index.  A box holds fewer than 2^31
@@ -102,6 +104,13 @@ __device__ inline int box_of(const Dims& d, int64_t g, int& loc) {
   return k;
 }
 
+// GEN = false: the TOP basis, where Psi0's singles amplitudes are diagonal,
+// C[l][l'] = c_l, and a term c_l [x = l'] is kept only where the indices meet.
+// GEN = true: any orbital basis that leaves t and t' in place (the
+// pinned-semicanonical one): every such term reads C[l][x].  The terms with a
+// pinned index (C[t][x] = c_0 [x = t'], C[l][t'] = c_0 [l = t]) keep their TOP
+// form in both.  V, M and fphi are tensors in (i, a): given in the new basis.
+template <bool GEN>
 __global__ void k_rhs(RhsArgs A) {
   const Dims& d = A.d;
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,11 +120,14 @@ __global__ void k_rhs(RhsArgs A) {
   const int no = d.no, nv = d.nv, nov = no * nv;
   const double s2 = 0.70710678118654752440;
   auto c = [&](int l) -> double { return A.lam[l] * s2; };
+  // c_l [x = l'] (TOP) or C[l][x] (GEN); occupied l, virtual x
+  auto cx = [&](int l, int x) -> double { return GEN ? A.Cs[l * nv + x] : (x == l ? c(l) : 0.0); };
   auto V = [&](int i, int a, int j, int b) -> double { return A.V[(int64_t)(i * nv + a) * nov + j * nv + b]; };
   // m[i,j,a,b] = c_i d(a,i) fphi[j][b] + M[(i,a),(j,b)]
   auto m = [&](int i, int j, int a, int b) -> double {
     double v = A.M[(int64_t)(i * nv + a) * nov + j * nv + b];
-    if (a == i) v += c(i) * A.fphi[j * nv + b];
+    if (GEN) v += cx(i, a) * A.fphi[j * nv + b];
+    else if (a == i) v += c(i) * A.fphi[j * nv + b];
     return v;
   };
   double out = 0.0;
@@ -141,20 +153,29 @@ __global__ void k_rhs(RhsArgs A) {
       ++j; ++k; ++b; ++cc;
       auto E = [&](int kk, int x) { return V(0, 0, kk, x) - V(kk, 0, 0, x); };
       out = c0 * (V(j, b, k, cc) - V(k, b, j, cc));
-      if (b == j) out += c(j) * E(k, cc);
-      if (b == k) out -= c(k) * E(j, cc);
-      if (cc == j) out -= c(j) * E(k, b);
-      if (cc == k) out += c(k) * E(j, b);
+      if (GEN) {
+        out += cx(j, b) * E(k, cc) - cx(k, b) * E(j, cc) - cx(j, cc) * E(k, b) + cx(k, cc) * E(j, b);
+      } else {
+        if (b == j) out += c(j) * E(k, cc);
+        if (b == k) out -= c(k) * E(j, cc);
+        if (cc == j) out -= c(j) * E(k, b);
+        if (cc == k) out += c(k) * E(j, b);
+      }
       break;
     }
     case B_H11: {
       int po = loc / d.npv, pv = loc % d.npv, j, k, b, cc;
       tri_pq(po, no, j, k); tri_pq(pv, nv, b, cc);
       double o2 = 0.0;                                    // beta singles (down TOP pairs)
-      if (b == j) o2 += c(j) * V(0, 0, k, cc);
-      if (b == k) o2 -= c(k) * V(0, 0, j, cc);
-      if (cc == j) o2 -= c(j) * V(0, 0, k, b);
-      if (cc == k) o2 += c(k) * V(0, 0, j, b);
+      if (GEN) {
+        o2 = cx(j, b) * V(0, 0, k, cc) - cx(k, b) * V(0, 0, j, cc) - cx(j, cc) * V(0, 0, k, b)
+           + cx(k, cc) * V(0, 0, j, b);
+      } else {
+        if (b == j) o2 += c(j) * V(0, 0, k, cc);
+        if (b == k) o2 -= c(k) * V(0, 0, j, cc);
+        if (cc == j) o2 -= c(j) * V(0, 0, k, b);
+        if (cc == k) o2 += c(k) * V(0, 0, j, b);
+      }
       out = c0 * (V(j, b, k, cc) - V(k, b, j, cc)) + sg * o2;
       break;
     }
@@ -164,9 +185,13 @@ __global__ void k_rhs(RhsArgs A) {
       tri_pq(po, no, j, k);
       int a = r / m1 + 1, cc = r % m1 + 1;
       if (j == 0) out += c0 * V(0, a, k, cc);            // all from the beta singles
-      if (cc == j) out -= c(j) * V(0, a, k, 0);
       if (k == 0) out -= c0 * V(0, a, j, cc);
-      if (cc == k) out += c(k) * V(0, a, j, 0);
+      if (GEN) {
+        out += cx(k, cc) * V(0, a, j, 0) - cx(j, cc) * V(0, a, k, 0);
+      } else {
+        if (cc == j) out -= c(j) * V(0, a, k, 0);
+        if (cc == k) out += c(k) * V(0, a, j, 0);
+      }
       out *= sg;
       break;
     }
@@ -175,9 +200,13 @@ __global__ void k_rhs(RhsArgs A) {
       int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
       tri_pq(pv, nv, b, cc);
       if (b == 0) out += c0 * V(i, 0, k, cc);            // all from the beta singles
-      if (b == k) out -= c(k) * V(i, 0, 0, cc);
       if (cc == 0) out -= c0 * V(i, 0, k, b);
-      if (cc == k) out += c(k) * V(i, 0, 0, b);
+      if (GEN) {
+        out += cx(k, cc) * V(i, 0, 0, b) - cx(k, b) * V(i, 0, 0, cc);
+      } else {
+        if (b == k) out -= c(k) * V(i, 0, 0, cc);
+        if (cc == k) out += c(k) * V(i, 0, 0, b);
+      }
       out *= sg;
       break;
     }
@@ -187,14 +216,32 @@ __global__ void k_rhs(RhsArgs A) {
       int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
       int a = r / m1 + 1, cc = r % m1 + 1;
       double o2 = c0 * V(i, a, k, cc);                   // beta singles
-      if (cc == k) o2 += c(k) * V(i, a, 0, 0);
+      if (GEN) o2 += cx(k, cc) * V(i, a, 0, 0);
+      else if (cc == k) o2 += c(k) * V(i, a, 0, 0);
       out = sg * o2;
-      if (a == i) out += c(i) * (V(0, 0, k, cc) - V(k, 0, 0, cc));    // the alpha single i -> i'
+      if (GEN) out += cx(i, a) * (V(0, 0, k, cc) - V(k, 0, 0, cc));
+      else if (a == i) out += c(i) * (V(0, 0, k, cc) - V(k, 0, 0, cc));    // the alpha single i -> i'
       break;
     }
   }
   A.b[g] = out;
 }
+
+// Singles amplitudes of Psi0 in a basis reached from the TOP one by the
+// orbital rotations To (occupied) and Tv (virtual): C[I][A] = sum_l To[l][I]
+// c_l Tv[l][A], c_l = lambda_l / sqrt(2) on the pair (l, l').
+__global__ void k_singles_sc(const double* To, const double* Tv, const double* lam, int no, int nv, double* C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= no * nv) return;
+  const int I = e / nv, A = e % nv;
+  const double s2 = 0.70710678118654752440;
+  double v = 0.0;
+  for (int l = 0; l < no; ++l) v += To[l * no + I] * (lam[l] * s2) * Tv[l * nv + A];
+  C[e] = v;
+}
+
+template __global__ void k_rhs<false>(RhsArgs);
+template __global__ void k_rhs<true>(RhsArgs);
 
 // Diagonal D_mu = (sum of particle minus hole orbital energies) - omega and its
 // inverse; also records the minimum (for the NOT_SPD check) per block.
@@ -264,6 +311,69 @@ __global__ __launch_bounds__(256) void k_diag(DiagArgs A) {
     mn = fmin(mn, D);
   }
   // block minimum
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o));
+  __shared__ double ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) A.blockmin[blockIdx.x] = fmin(fmin(ws[0], ws[1]), fmin(ws[2], ws[3]));
+}
+
+// The same diagonal walked by coupling chunks (box, batch, inner range; the
+// table of the coupling kernels): the occupied indices come with the chunk and
+// the virtual pair from the pair tables, so no element decodes its position by
+// square roots.  Each workgroup takes DIAG_UNROLL consecutive chunks per pass,
+// their table reads issued together (the walk is bound by the latency of the
+// chunk -> pair -> orbital-energy reads, not by the 4-byte stores), grid-stride
+// over the passes; blockmin[blockIdx.x] as k_diag.
+constexpr int DIAG_UNROLL = 4;
+
+__device__ inline int chunk_inner_count(const Dims& d, int box) {
+  switch (box) {
+    case B_T2: case B_H11: case B_H21: return d.npv;
+    case B_S2: return d.nv * d.nv;
+    case B_T3: return d.npv1;
+    default: return (d.nv - 1) * (d.nv - 1);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_diag_chunks(DiagArgs A, PairTables P, const int4* chunks, int nchunks) {
+  const Dims& d = A.d;
+  const int nv = d.nv, m1 = nv - 1;
+  const double base = A.ev[0] - A.eo[0] - A.omega;   // the pinned pair of the L-triples
+  double mn = 1e300;
+  for (int c0 = blockIdx.x * DIAG_UNROLL; c0 < nchunks; c0 += gridDim.x * DIAG_UNROLL) {
+    int4 ch[DIAG_UNROLL];
+    int v[DIAG_UNROLL], inner[DIAG_UNROLL], t[DIAG_UNROLL];
+#pragma unroll
+    for (int u = 0; u < DIAG_UNROLL; ++u) ch[u] = chunks[min(c0 + u, nchunks - 1)];
+#pragma unroll
+    for (int u = 0; u < DIAG_UNROLL; ++u) {
+      inner[u] = chunk_inner_count(d, ch[u].x);
+      v[u] = c0 + u < nchunks ? chunk_inner(ch[u].x, ch[u].z, (int)threadIdx.x, nv, inner[u]) : inner[u];
+      const int box = ch[u].x;
+      t[u] = 0;
+      if (v[u] < inner[u]) {
+        if (box == B_T2 || box == B_H11 || box == B_H21) t[u] = P.pv[v[u]];
+        else if (box == B_T3) t[u] = P.pv1[v[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < DIAG_UNROLL; ++u) {
+      if (v[u] >= inner[u]) continue;
+      const int box = ch[u].x, i = ch[u].w >> 16, j = ch[u].w & 0xffff;
+      int a, b;
+      switch (box) {
+        case B_T2: case B_H11: case B_H21: a = t[u] >> 16; b = t[u] & 0xffff; break;
+        case B_S2: a = v[u] / nv; b = v[u] - a * nv; break;
+        case B_T3: a = (t[u] >> 16) + 1; b = (t[u] & 0xffff) + 1; break;
+        default: a = v[u] / m1 + 1; b = v[u] - (a - 1) * m1 + 1; break;
+      }
+      const double D = box >= B_T3 ? base + A.ev[a] + A.ev[b] - A.eo[i] - A.eo[j]
+                                   : A.ev[a] + A.ev[b] - A.eo[i] - A.eo[j] - A.omega;
+      A.dinv[d.off[box] + (int64_t)ch[u].y * inner[u] + v[u]] = (float)(1.0 / D);
+      mn = fmin(mn, D);
+    }
+  }
   for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o));
   __shared__ double ws[4];
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mn;
