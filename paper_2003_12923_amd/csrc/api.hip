@@ -113,6 +113,8 @@ struct esmp2_handle_ {
   // rhs
   double *fphi, *fphi_part, *X, *Vint, *Mint, *b, *blockmin, *partial, *sc;
   bool have_rhs = false;
+  bool sc_vir_early = false;    // launch_sc_vir_early has queued the virtual eigenproblem
+  bool b_top_pending = false;   // build_rhs left the TOP-basis b (and M) for ensure_b_top
   // sigma scratch
   double *S, *side, *side_tr;
   int2* jobs = nullptr;
@@ -149,6 +151,7 @@ struct esmp2_handle_ {
   double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *b_sc;
   float *Fd32_sc, *Fl32_sc, *fo32_sc, *fv32_sc, *fov32_sc, *dinv32_sc;
   double *dense0, *dense1;
+  double* rs2;            // scratch of the side stream's virtual eigenproblem (10 nv^2 + 8 nv)
   double* rsc;            // right-hand side in the pinned-semicanonical basis: C, fphi, Bov, X, one intermediate
   double* gv;                    // row/column GEMVs of the arrow-shaped Fock blocks (FP64 or FP32 use)
   // opt-in timing of the virtual-pair kernel with HIP events on the handle's stream,
@@ -289,9 +292,58 @@ static esmp2_status sym_eig(esmp2_handle h, hipStream_t s, const double* A, int 
 }
 
 
+// The virtual eigenproblem of the pinned-semicanonical rotation, queued on the
+// side stream right after the SVD, beside the AVO eigenproblem of the main
+// stream: virtuals 1.. of that basis span the complement of t' (virtual TOP
+// vector 0), whatever basis the AVO step picks inside it, so they are the
+// eigenvectors of F_vv on that complement, S = Q' Y' (Q' from one Householder
+// reflector of t').  launch_semican_eig takes them into the TOP basis once W
+// exists.  Scratch: rs2 = [Q' | Tt | Fa | Y' | S | ws (2 m^2 + 3 m) | refl | t' | evals].
+static esmp2_status launch_sc_vir_early(esmp2_handle h) {
+  const Dims& d = h->d;
+  const int no = d.no, nv = d.nv, n = d.n, m = nv - 1;
+  hipStream_t s = h->aux;
+  ESMP2_HIP(hipEventRecord(h->ev_fock_ready, h->stream));
+  ESMP2_HIP(hipStreamWaitEvent(s, h->ev_fock_ready, 0));
+  const size_t v2 = (size_t)nv * nv;
+  double* Qp = h->rs2;             // nv x m
+  double* Tt = Qp + v2;            // nv x m
+  double* Fa = Tt + v2;            // m x m
+  double* Yp = Fa + v2;            // m x m
+  double* S = Yp + v2;             // nv x m
+  double* ws = S + v2;             // 2 m^2 + 3 m
+  double* refl = ws + 3 * v2;      // nv + 1
+  double* tp = refl + 2 * nv;      // nv
+  double* evals = tp + 2 * nv;     // m
+  hipLaunchKernelGGL(k_take_column, dim3(nblk(nv)), dim3(256), 0, s, (const double*)h->V, no, nv, tp);
+  ESMP2_HIP(allow_device_lds((const void*)k_complement_qr));
+  hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), sizeof(double) * 2 * (size_t)nv, s, (const double*)tp, nv,
+                     1, refl);
+  hipLaunchKernelGGL(k_complement_apply, dim3(m), dim3(64), 0, s, (const double*)refl, nv, 1, Qp);
+  GemmArgs g{};
+  g.A = h->F + (int64_t)no * n + no; g.B = Qp; g.C = Tt; g.M = nv; g.N = m; g.K = nv;
+  g.sAi = n; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));
+  g = GemmArgs{};
+  g.A = Qp; g.B = Tt; g.C = Fa; g.M = m; g.N = m; g.K = nv;
+  g.sAi = 1; g.sAk = m; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));
+  const esmp2_status st = sym_eig(h, s, Fa, m, evals, Yp, ws);
+  if (st != ESMP2_OK) return st;
+  g = GemmArgs{};
+  g.A = Qp; g.B = Yp; g.C = S; g.M = nv; g.N = m; g.K = m;
+  g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(s, 1, g));
+  ESMP2_HIP(hipGetLastError());
+  h->sc_vir_early = true;
+  return ESMP2_OK;
+}
+
 // The two eigenproblems of the pinned-semicanonical rotation (F~_oo[1:,1:],
 // F~_vv[1:,1:]), queued on the side stream as soon as F~ exists; semican_setup
-// joins them.  Scratch: rs.
+// joins them.  The virtual one, when launch_sc_vir_early has solved it in the
+// original basis, only needs its vectors taken into the TOP basis: W[:, 1:]^T S.
+// Scratch: rs.
 static esmp2_status launch_semican_eig(esmp2_handle h) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, n = d.n;
@@ -306,10 +358,20 @@ static esmp2_status launch_semican_eig(esmp2_handle h) {
   esmp2_status st = sym_eig(h, s, A, no - 1, evals, Y, ws);
   if (st != ESMP2_OK) return st;
   hipLaunchKernelGGL(k_embed_rotation, dim3(nblk(no * no)), dim3(256), 0, s, (const double*)Y, no, h->To);
-  hipLaunchKernelGGL(k_block_copy, dim3(256), dim3(256), 0, s, (const double*)h->Ft, (int64_t)(no + 1) * n + no + 1,
-                     n, nv - 1, A);
-  st = sym_eig(h, s, A, nv - 1, evals, Y, ws);
-  if (st != ESMP2_OK) return st;
+  if (h->sc_vir_early) {
+    // Y[a-1][A-1] = sum_k W[k][a] S[k][A-1], a >= 1 (W = R[no:, no:])
+    const int m = nv - 1;
+    GemmArgs g{};
+    g.A = h->R + (int64_t)no * n + no + 1; g.B = h->rs2 + 4 * (size_t)nv * nv; g.C = Y; g.M = m; g.N = m; g.K = nv;
+    g.sAi = 1; g.sAk = n; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, 1, g));
+    h->sc_vir_early = false;
+  } else {
+    hipLaunchKernelGGL(k_block_copy, dim3(256), dim3(256), 0, s, (const double*)h->Ft, (int64_t)(no + 1) * n + no + 1,
+                       n, nv - 1, A);
+    st = sym_eig(h, s, A, nv - 1, evals, Y, ws);
+    if (st != ESMP2_OK) return st;
+  }
   hipLaunchKernelGGL(k_embed_rotation, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, (const double*)Y, nv, h->Tv);
   ESMP2_HIP(hipGetLastError());
   ESMP2_HIP(hipEventRecord(h->ev_sc_eig, s));
@@ -482,6 +544,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
        dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
        dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense) &&
        dalloc(h, &h->rsc, (size_t)no * nv * (2 + 3 * (size_t)na)) &&
+       dalloc(h, &h->rs2, (size_t)10 * nv * nv + 8 * (size_t)nv) &&
        dalloc(h, &h->gv, (size_t)nv * (2 * d.npo + 2 * no * no + (no - 1) * (no - 1)));
   if (n_top > 1)
     ok = ok && dalloc(h, &h->s0, namp) && dalloc(h, &h->Ft_s, (size_t)n * n) &&
@@ -629,6 +692,10 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     size_t lds = sizeof(double) * (no * nv + no * no);
     ESMP2_HIP(allow_device_lds((const void*)k_svd_jacobi));
     hipLaunchKernelGGL(k_svd_jacobi, dim3(1), dim3(1024), lds, s, h->C, no, nv, h->lam, h->U, h->V, h->iinfo);
+    {
+      const esmp2_status st = launch_sc_vir_early(h);
+      if (st != ESMP2_OK) return st;
+    }
     // semicanonical AVOs: complement of the TOP virtuals, F restricted to it,
     // tridiagonal eigensolver, back-transformation, Loewdin re-orthonormalisation
     {
@@ -771,7 +838,7 @@ esmp2_status esmp2_space(esmp2_handle h, int64_t* n_amp, int64_t* box_offsets) {
 // TOP-basis blocks (Ft, Bov, Bvt, Boo, lam) into b (one-TOP layout); scratch:
 // fphi, X, Vint, Mint.
 static esmp2_status rhs_core(esmp2_handle h, const double* Ft, const double* Bov, const double* Bvt,
-                             const double* Boo, const double* lam, double* b) {
+                             const double* Boo, const double* lam, double* b, bool defer_b = false) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
   hipStream_t s = h->stream;
@@ -787,11 +854,30 @@ static esmp2_status rhs_core(esmp2_handle h, const double* Ft, const double* Bov
   g.A = Bov; g.B = Bov; g.C = h->Vint; g.M = nov; g.N = nov; g.K = na;
   g.sAi = 1; g.sAk = nov; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1; g.beta = 0;
   ESMP2_HIP(gemm(s, 1, g));
+  if (defer_b) return ESMP2_OK;
   g.A = h->X; g.C = h->Mint;
   ESMP2_HIP(gemm(s, 1, g));
   RhsArgs ra{d, h->Vint, h->Mint, h->fphi, lam, b, nullptr};
   hipLaunchKernelGGL(k_rhs<false>, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
   ESMP2_HIP(hipGetLastError());
+  return ESMP2_OK;
+}
+
+// The one-TOP right-hand side in the TOP basis, left for later by build_rhs
+// (a solve in the pinned-semicanonical basis builds its own from X, f^Phi and
+// Bov and never reads this one): M = X^T Bov and b from V, M, f^Phi.
+static esmp2_status ensure_b_top(esmp2_handle h) {
+  if (!h->b_top_pending) return ESMP2_OK;
+  const Dims& d = h->d;
+  const int nov = d.no * d.nv;
+  GemmArgs g{};
+  g.A = h->X; g.B = h->Bov; g.C = h->Mint; g.M = nov; g.N = nov; g.K = d.naux;
+  g.sAi = 1; g.sAk = nov; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1; g.beta = 0;
+  ESMP2_HIP(gemm(h->stream, 1, g));
+  RhsArgs ra{d, h->Vint, h->Mint, h->fphi, h->lam, h->b, nullptr};
+  hipLaunchKernelGGL(k_rhs<false>, dim3(nblk(d.off[7])), dim3(256), 0, h->stream, ra);
+  ESMP2_HIP(hipGetLastError());
+  h->b_top_pending = false;
   return ESMP2_OK;
 }
 
@@ -805,8 +891,11 @@ static esmp2_status build_rhs(esmp2_handle h) {
   const int64_t namp = h->namp;
   hipStream_t s = h->stream;
   {
-    const esmp2_status st = rhs_core(h, h->Ft, h->Bov, h->Bvt, h->Boo, h->lam, h->ntop > 1 ? h->btmp : h->b);
+    h->b_top_pending = false;
+    const esmp2_status st = rhs_core(h, h->Ft, h->Bov, h->Bvt, h->Boo, h->lam, h->ntop > 1 ? h->btmp : h->b,
+                                     h->ntop == 1);
     if (st != ESMP2_OK) return st;
+    h->b_top_pending = h->ntop == 1;
   }
   unsigned nmin = nblk(namp);
   if (h->ntop == 1) {
@@ -880,8 +969,11 @@ esmp2_status esmp2_build_rhs(esmp2_handle h, double* b_out, double* e0, double* 
   ESMP2_HIP(hipSetDevice(h->device));
   esmp2_status st = build_rhs(h);
   if (st != ESMP2_OK) return st;
-  if (b_out)
+  if (b_out) {
+    st = ensure_b_top(h);
+    if (st != ESMP2_OK) return st;
     ESMP2_HIP(hipMemcpyAsync(b_out, h->b, sizeof(double) * h->namp, hipMemcpyDeviceToDevice, h->stream));
+  }
   if (e0) *e0 = h->e0;
   if (e2_s) {
     st = join_e2s(h, true);
@@ -1526,8 +1618,8 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   const int64_t n = h->namp;
   hipStream_t s = h->stream;
   const unsigned NB = PCG_BLOCKS;
-  wdot(h, c.b, c.b, SC_BB);   // ||b||_W^2
   if (opts->x0) {
+    wdot(h, c.b, c.b, SC_BB);   // ||b||_W^2
     if (c.rotated) {
       esmp2_status st0 = rotate_amplitudes(h, opts->x0, h->x, true);
       if (st0 != ESMP2_OK) return st0;
@@ -1537,18 +1629,18 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
     esmp2_status st = apply_op(h, c, c.s64, (const double*)h->x, h->q);
     if (st != ESMP2_OK) return st;
     hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, h->q, h->r, h->p, c.dinv32, n, d.off[1], d.off[2],
-                       h->partial);
+                       h->partial, (double*)nullptr);
   } else {
-    ESMP2_HIP(hipMemsetAsync(h->x, 0, sizeof(double) * n, s));
+    // x = 0 in the same pass; r = -b exactly, so <r, r>_W is ||b||_W^2
     hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv32, n,
-                       d.off[1], d.off[2], h->partial);
+                       d.off[1], d.off[2], h->partial, h->x);
   }
   // rho = <r, D^-1 r> into SC_RHO and <r, r> into SC_RHO + 1 = SC_PQ
   hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);
   double* hs = h->pin->sc;
   ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
   ESMP2_HIP(hipStreamSynchronize(s));
-  const double bn = sqrt(hs[SC_BB]);
+  const double bn = sqrt(opts->x0 ? hs[SC_BB] : hs[SC_PQ]);
   double rel = sqrt(hs[SC_PQ]) / bn;
   int it = 0;
   esmp2_status status = ESMP2_OK;
@@ -1683,6 +1775,10 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
   memset(res, 0, sizeof(*res));
   if (!h->have_rhs) {
     esmp2_status st = build_rhs(h);
+    if (st != ESMP2_OK) { res->status = st; return st; }
+  }
+  if (opts->basis == ESMP2_BASIS_TOP) {
+    esmp2_status st = ensure_b_top(h);
     if (st != ESMP2_OK) { res->status = st; return st; }
   }
   OpCtx c = ctx_top(h);
@@ -1971,6 +2067,7 @@ esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double*
   if (!x || (!dF && !dB)) return fail(h, ESMP2_INVALID_ARG, "x and at least one of dF, dB are required");
   if (h->ntop > 1) return fail(h, ESMP2_UNSUPPORTED, "gradient with more than one large TOP");
   ESMP2_HIP(hipSetDevice(h->device));
+  ESMP2_TRY(ensure_b_top(h));
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, n = d.n, na = d.naux, nov = no * nv;
   const int o1 = no - 1, v1 = nv - 1;

@@ -363,6 +363,12 @@ __global__ __launch_bounds__(256) void k_complement_qr(const double* Vin, int nv
 // Q2 (nv x m, m = nv - no) column c = H_0 H_1 ... H_{no-1} e_{no+c}: the
 // orthonormal complement of the TOP virtuals.  One wavefront per column; lane
 // l owns rows l, l + 64, l + 128 (nv <= 192).
+// dst[i] = src[i*ld], i < n (a column of a row-major matrix)
+__global__ void k_take_column(const double* src, int ld, int n, double* dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[(int64_t)i * ld];
+}
+
 __global__ __launch_bounds__(64) void k_complement_apply(const double* refl, int nv, int no, double* Q2) {
   const int c = blockIdx.x, l = threadIdx.x, m = nv - no;
   const double* beta = refl + no * nv;

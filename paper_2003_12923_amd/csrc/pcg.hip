@@ -178,10 +178,11 @@ __global__ void k_roll_rho(double* sc) {
   if (threadIdx.x == 0) sc[SC_RHO] = sc[SC_RHO_NEW];
 }
 
-// r = -b - y (y = A x0) or r = -b;  p = M r;  partials of <r, M r>, <r, r>
+// r = -b - y (y = A x0) or r = -b;  p = M r;  partials of <r, M r>, <r, r>;
+// xz = 0 where given (the start x = 0)
 __device__ __attribute__((always_inline)) inline void init_body(const double* b, const double* y, double* r, double* p,
                                               const float* dinv, int64_t n, int64_t s0, int64_t s1,
-                                              double* partial, int bid_, int nb_) {
+                                              double* partial, int bid_, int nb_, double* xz = nullptr) {
   double rz = 0.0, rr = 0.0;
   const int64_t st = (int64_t)nb_ * blockDim.x;
   for (int64_t g0 = (int64_t)bid_ * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
@@ -199,6 +200,7 @@ __device__ __attribute__((always_inline)) inline void init_body(const double* b,
         const double rg = -bv[u] - yv[u];
         r[g] = rg;
         p[g] = (double)dv[u] * rg;
+        if (xz) xz[g] = 0.0;
         const double w = wgt(g, s0, s1);
         rz += w * rg * rg * (double)dv[u];
         rr += w * rg * rg;
@@ -212,8 +214,8 @@ __device__ __attribute__((always_inline)) inline void init_body(const double* b,
 
 __global__ __launch_bounds__(256) void k_init(const double* b, const double* y, double* r, double* p,
                                               const float* dinv, int64_t n, int64_t s0, int64_t s1,
-                                              double* partial) {
-  init_body(b, y, r, p, dinv, n, s0, s1, partial, blockIdx.x, gridDim.x);
+                                              double* partial, double* xz) {
+  init_body(b, y, r, p, dinv, n, s0, s1, partial, blockIdx.x, gridDim.x, xz);
 }
 
 // FP64 residual of the refinement: r = -b - y (y = A x, or NULL for x = 0);  partials of <r, r>_W
