@@ -75,6 +75,13 @@ __global__ void k_topfock(const double* Ft, const double* lam, int no, int nv, i
 // the device lands here.  A copy into it is DMA into memory the handle owns,
 // so no call leaves a device-to-host copy pending into pageable or stack
 // memory, on any return path.
+// return the status of a call that fails
+#define ESMP2_TRY(call)                          \
+  do {                                           \
+    esmp2_status st_ = (call);                   \
+    if (st_ != ESMP2_OK) return st_;             \
+  } while (0)
+
 struct PinnedScalars {
   double sc[SC_N];       // conjugate-gradient scalars (SC_* slots)
   double rot[4];         // omega, kappa, E0 of the rotation
@@ -84,6 +91,7 @@ struct PinnedScalars {
   int info[4];
   int bad[4];
   int active[2];         // batched solve: states still iterating, two iterations in flight
+  CgCtl cg[2];           // device-stopped solve: the control word after iteration i, slot i % 2
 };
 
 struct esmp2_handle_ {
@@ -145,6 +153,8 @@ struct esmp2_handle_ {
   // solve: partials, then the sum at e2s_part[E2S_CAP]
   double* e2s_part = nullptr;
   hipEvent_t ev_rhs_ready = nullptr, ev_e2s = nullptr;
+  hipEvent_t ev_cg[2] = {nullptr, nullptr};   // device-stopped solve: control word of iteration i copied (i % 2)
+  double* cgctl = nullptr;                    // its control word (a CgCtl)
   bool e2s_pending = false;      // queued on the side stream, not yet joined by the main stream
   bool e2s_dev = false;          // the sum is on the device, not yet read into e2s
   bool sc_eig = false;           // To, Tv hold the rotation of the current TOP basis
@@ -397,8 +407,12 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
       hipEventCreateWithFlags(&h->ev_fock_ready, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_sc_eig, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_rhs_ready, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_e2s, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->ev_e2s, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_cg[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_cg[1], hipEventDisableTiming) != hipSuccess) {
     if (h->aux) (void)hipStreamDestroy(h->aux);
+    if (h->ev_cg[0]) (void)hipEventDestroy(h->ev_cg[0]);
+    if (h->ev_cg[1]) (void)hipEventDestroy(h->ev_cg[1]);
     if (h->ev_fock_ready) (void)hipEventDestroy(h->ev_fock_ready);
     if (h->ev_sc_eig) (void)hipEventDestroy(h->ev_sc_eig);
     if (h->ev_rhs_ready) (void)hipEventDestroy(h->ev_rhs_ready);
@@ -415,6 +429,8 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
       (void)hipEventDestroy(h->ev_sc_eig);
       (void)hipEventDestroy(h->ev_rhs_ready);
       (void)hipEventDestroy(h->ev_e2s);
+      (void)hipEventDestroy(h->ev_cg[0]);
+      (void)hipEventDestroy(h->ev_cg[1]);
       (void)hipHostFree(h->pin);
       delete h;
       return ESMP2_HIP_ERROR;
@@ -436,6 +452,8 @@ esmp2_status esmp2_destroy(esmp2_handle h) {
   (void)hipEventDestroy(h->ev_sc_eig);
   (void)hipEventDestroy(h->ev_rhs_ready);
   (void)hipEventDestroy(h->ev_e2s);
+  (void)hipEventDestroy(h->ev_cg[0]);
+  (void)hipEventDestroy(h->ev_cg[1]);
   (void)hipHostFree(h->pin);
   delete h;
   return ESMP2_OK;
@@ -544,7 +562,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
        dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
        dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense) &&
        dalloc(h, &h->rsc, (size_t)no * nv * (2 + 3 * (size_t)na)) &&
-       dalloc(h, &h->rs2, (size_t)10 * nv * nv + 8 * (size_t)nv) &&
+       dalloc(h, &h->rs2, (size_t)10 * nv * nv + 8 * (size_t)nv) && dalloc(h, &h->cgctl, 4) &&
        dalloc(h, &h->gv, (size_t)nv * (2 * d.npo + 2 * no * no + (no - 1) * (no - 1)));
   if (n_top > 1)
     ok = ok && dalloc(h, &h->s0, namp) && dalloc(h, &h->Ft_s, (size_t)n * n) &&
@@ -1579,7 +1597,8 @@ extern "C" {
 
 // E2 (Hylleraas form <b,x>_W - <x,r>_W, r = -b - A x) and the result record
 static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
-                                 esmp2_solve_result* res, double rel, int it, int outer, esmp2_status status) {
+                                 esmp2_solve_result* res, double rel, int it, int outer, esmp2_status status,
+                                 bool dots_ready = false) {
   const int64_t n = h->namp;
   hipStream_t s = h->stream;
   {
@@ -1587,8 +1606,10 @@ static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_sol
     if (st != ESMP2_OK) return st;
   }
   const double* hs = h->pin->sc;
-  wdot(h, c.b, (const double*)h->x, SC_BX);
-  wdot(h, (const double*)h->x, (const double*)h->r, SC_XR);
+  if (!dots_ready) {
+    wdot(h, c.b, (const double*)h->x, SC_BX);
+    wdot(h, (const double*)h->x, (const double*)h->r, SC_XR);
+  }
   ESMP2_HIP(hipMemcpyAsync(h->pin->sc, h->sc, sizeof(double) * SC_N, hipMemcpyDeviceToHost, s));
   if (opts->x_out) {
     if (c.rotated) {
@@ -1609,6 +1630,68 @@ static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_sol
   res->outer = outer;
   res->status = status;
   return status;
+}
+
+// The FP64 iterations of solve64 in the pinned-semicanonical basis with the
+// stop decided on the device (cgdev.hip): iteration i + 1 is queued before the
+// host reads the control word of iteration i.  Starts from the state k_init
+// left (x = x0 or 0, r, p, rho); bn = ||b||_W.
+static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
+                                esmp2_solve_result* res, double bn, double rel0) {
+  const Dims& d = h->d;
+  const int64_t n = h->namp;
+  hipStream_t s = h->stream;
+  const unsigned NB = PCG_BLOCKS;
+  CgCtl* ctl = (CgCtl*)h->cgctl;
+  const SigmaBufs<double>& w = c.s64;
+  const PrologueArgs<double> pa = prologue_args(h, w, (const double*)h->p, h->q, true);
+  const ArrowArgs<double> aa{pa.ga, w.Fd, w.Fl, w.side_tr, h->gv};
+  const int* pv = h->pairs;
+  const PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
+  hipLaunchKernelGGL(kd_ctl_init, dim3(1), dim3(64), 0, s, ctl, rel0);
+  auto enqueue = [&](int slot) -> esmp2_status {
+    hipLaunchKernelGGL(kd_sym, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, (const double*)h->p, w.S,
+                       (const CgCtl*)ctl);
+    hipLaunchKernelGGL(kd_gemv, dim3(pa.jobs), dim3(256), 0, s, pa.gv, (const CgCtl*)ctl);
+    hipLaunchKernelGGL(kd_arrow, dim3(h->nchunks), dim3(256), 0, s, aa, pt, (const int4*)h->chunks, h->pq_part,
+                       (const CgCtl*)ctl);
+    hipLaunchKernelGGL(kd_finish_pq, dim3(1), dim3(1024), 0, s, (const double*)h->pq_part, h->nchunks, h->sc, ctl);
+    hipLaunchKernelGGL(kd_update_r, dim3(NB), dim3(256), 0, s, h->r, (const double*)h->q, c.dinv32, n, d.off[1],
+                       d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl);
+    hipLaunchKernelGGL(kd_finish_r, dim3(2), dim3(1024), 0, s, (const double*)h->partial, (int)NB, h->sc, ctl, bn,
+                       opts->tol, opts->max_iter);
+    ESMP2_HIP(hipMemcpyAsync(&h->pin->cg[slot], ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));
+    ESMP2_HIP(hipEventRecord(h->ev_cg[slot], s));
+    hipLaunchKernelGGL(kd_update_px, dim3(NB), dim3(256), 0, s, h->x, h->p, (const double*)h->r, c.b, c.dinv32, n,
+                       d.off[1], d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl);
+    ESMP2_HIP(hipGetLastError());
+    return ESMP2_OK;
+  };
+  ESMP2_TRY(enqueue(0));
+  int queued = 1;
+  CgCtl last{};
+  for (int i = 0;; ++i) {
+    if (queued < opts->max_iter) {            // the next iteration before this one's outcome
+      ESMP2_TRY(enqueue(queued & 1));
+      ++queued;
+    }
+    ESMP2_HIP(hipEventSynchronize(h->ev_cg[i & 1]));
+    last = h->pin->cg[i & 1];
+    if (last.status != ESMP2_NOT_SPD && opts->resid_hist && last.it >= 1) opts->resid_hist[last.it - 1] = last.rel;
+    if (last.mode != CG_RUN || i + 1 >= queued) break;
+  }
+  esmp2_status status = (esmp2_status)last.status;
+  if (last.mode == CG_RUN) {                  // not reached: the device stops at max_iter
+    status = ESMP2_NOT_CONVERGED;
+  }
+  if (status == ESMP2_NOT_SPD) {
+    h->err = "p.Ap <= 0 in conjugate gradient";
+    return finish_solve(h, c, opts, res, last.rel, last.it, 0, status);
+  }
+  if (status == ESMP2_NOT_CONVERGED) h->err = "max_iter reached";
+  // the Hylleraas dots from the parts of the last update
+  hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, (const double*)h->partial, (int)NB, h->sc, (int)SC_BX);
+  return finish_solve(h, c, opts, res, last.rel, last.it, 0, status, true);
 }
 
 // Jacobi-preconditioned conjugate gradient in FP64 for A x = -b
@@ -1642,6 +1725,8 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   ESMP2_HIP(hipStreamSynchronize(s));
   const double bn = sqrt(opts->x0 ? hs[SC_BB] : hs[SC_PQ]);
   double rel = sqrt(hs[SC_PQ]) / bn;
+  if (c.arrow && h->nchunks > 0 && h->ntop == 1 && rel > opts->tol && opts->max_iter > 0)
+    return solve64_dev(h, c, opts, res, bn, rel);
   int it = 0;
   esmp2_status status = ESMP2_OK;
   while (rel > opts->tol && it < opts->max_iter) {
@@ -2055,11 +2140,6 @@ static esmp2_status gram(esmp2_handle h, const double* X, int nb, int64_t sb, in
   return ESMP2_OK;
 }
 
-#define ESMP2_TRY(call)                          \
-  do {                                           \
-    esmp2_status st_ = (call);                   \
-    if (st_ != ESMP2_OK) return st_;             \
-  } while (0)
 
 esmp2_status esmp2_gradient(esmp2_handle h, const double* x, double* dF, double* dB) {
   if (!h) return ESMP2_INVALID_ARG;

@@ -1,0 +1,135 @@
+// One state's FP64 conjugate gradient in the pinned-semicanonical basis with
+// its convergence test and stop on the device.  The host queues iteration
+// i + 1 before it reads the outcome of iteration i, so the GPU never waits for
+// the host; a state that has stopped turns the kernels of the queued iteration
+// into no-ops.  The kernels are those of the host-driven loop (same bodies,
+// same sums), each with a check of the control word first.
+//
+// Control word (device memory), one iteration:
+//   pq finish    LAST -> DONE (the queued iteration after the last one);
+//                RUN: rho <- rho_new (from the second iteration on), <p, Ap>_W
+//   update_r     RUN only
+//   finish_r     RUN only: <r, M r>_W, <r, r>_W, then the test: p.Ap <= 0 ->
+//                DONE (not SPD); ||r||_W / ||b||_W <= tol or max_iter -> LAST
+//   update_px    RUN: x += alpha p, p = M r + beta p;  LAST: x += alpha p and
+//                the parts of the Hylleraas dots <b, x>_W, <x, r>_W
+#include "common.h"
+#include "sigma.h"
+#include "pcg.h"
+#include "reduce.h"
+
+namespace esmp2 {
+
+enum { CG_RUN = 0, CG_LAST = 1, CG_DONE = 2 };
+
+struct CgCtl {
+  int mode, it, status, pad;
+  double rel;     // last ||r||_W / ||b||_W
+};
+
+__global__ void kd_ctl_init(CgCtl* c, double rel0) {
+  if (threadIdx.x == 0) {
+    c->mode = CG_RUN;
+    c->it = 0;
+    c->status = ESMP2_OK;
+    c->rel = rel0;
+  }
+}
+
+__global__ __launch_bounds__(256) void kd_sym(Dims d, const double* x, double* S, const CgCtl* c) {
+  if (c->mode != CG_RUN) return;
+  sym_s2_body<double>(d, x, S, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void kd_gemv(GemvArgs<double> A, const CgCtl* c) {
+  if (c->mode != CG_RUN) return;
+  gemv_body<double>(A, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void kd_arrow(ArrowArgs<double> A, PairTables P, const int4* chunks, double* pq,
+                                                const CgCtl* c) {
+  if (c->mode != CG_RUN) return;
+  arrow_body<double>(A, P, chunks, pq, blockIdx.x, gridDim.x);
+}
+
+// one block
+__global__ __launch_bounds__(1024) void kd_finish_pq(const double* pq, int nb, double* sc, CgCtl* c) {
+  const int mode = c->mode;
+  if (mode == CG_LAST) {
+    if (threadIdx.x == 0) c->mode = CG_DONE;
+    return;
+  }
+  if (mode != CG_RUN) return;
+  if (threadIdx.x == 0 && c->it > 0) sc[SC_RHO] = sc[SC_RHO_NEW];
+  finish_body(pq, nb, sc, SC_PQ, 0, 1);
+}
+
+__global__ __launch_bounds__(256) void kd_update_r(double* r, const double* q, const float* dinv, int64_t n,
+                                                   int64_t s0, int64_t s1, const double* sc, double* partial,
+                                                   const CgCtl* c) {
+  if (c->mode != CG_RUN) return;
+  update_r_body<double>(r, q, dinv, n, s0, s1, sc, partial, blockIdx.x, gridDim.x);
+}
+
+// two blocks: sc[SC_RHO_NEW], sc[SC_RR]; block 1 then takes the decision.
+// Block 0 may read the control word after block 1 has changed it and skip
+// rho_new: no stopped state reads rho_new.
+__global__ __launch_bounds__(1024) void kd_finish_r(const double* partial, int nb, double* sc, CgCtl* c, double bn,
+                                                    double tol, int max_iter) {
+  if (c->mode != CG_RUN) return;
+  finish_body(partial, nb, sc, SC_RHO_NEW, blockIdx.x, 2);
+  if (blockIdx.x != 1 || threadIdx.x != 0) return;
+  const double pq = sc[SC_PQ];
+  if (!(pq > 0.0)) {
+    c->status = ESMP2_NOT_SPD;
+    c->mode = CG_DONE;
+    return;
+  }
+  const int it = c->it + 1;
+  const double rel = sqrt(sc[SC_RR]) / bn;
+  c->it = it;
+  c->rel = rel;
+  if (rel <= tol || it >= max_iter) {
+    if (rel > tol) c->status = ESMP2_NOT_CONVERGED;
+    c->mode = CG_LAST;
+  }
+}
+
+__global__ __launch_bounds__(256) void kd_update_px(double* x, double* p, const double* r, const double* b,
+                                                    const float* dinv, int64_t n, int64_t s0, int64_t s1,
+                                                    const double* sc, double* partial, const CgCtl* c) {
+  const int mode = c->mode;
+  if (mode == CG_RUN) {
+    update_px_body<double>(x, p, r, dinv, n, sc, blockIdx.x, gridDim.x);
+    return;
+  }
+  if (mode != CG_LAST) return;
+  // x += alpha p, with the weighted dots of the new x against b and r
+  const double alpha = sc[SC_RHO] / sc[SC_PQ];
+  Acc2 bx, xr;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    double xv[PCG_U], pv[PCG_U], bv[PCG_U], rv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      xv[u] = x[gg]; pv[u] = p[gg]; bv[u] = b[gg]; rv[u] = r[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) {
+        const double xn = xv[u] + alpha * pv[u];
+        x[g] = xn;
+        const double w = wgt(g, s0, s1);
+        bx.add(w * bv[u] * xn);
+        xr.add(w * xn * rv[u]);
+      }
+    }
+  }
+  const double a = block_sum2(bx);
+  const double d = block_sum2(xr);
+  if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = d; }
+}
+
+}  // namespace esmp2

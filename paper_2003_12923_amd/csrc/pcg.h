@@ -15,7 +15,7 @@ __global__ void k_update_px(T* x, T* p, const T* r, const float* dinv, int64_t n
 template <class T> __global__ void k_update_x(T* x, const T* p, int64_t n, const double* sc);
 __global__ void k_roll_rho(double* sc);
 __global__ void k_init(const double* b, const double* y, double* r, double* p, const float* dinv, int64_t n,
-                       int64_t s0, int64_t s1, double* partial);
+                       int64_t s0, int64_t s1, double* partial, double* xz);
 __global__ void k_resid(const double* b, const double* y, double* r, int64_t n, int64_t s0, int64_t s1,
                         double* partial);
 __global__ void k_init_inner(const double* r64, double scale, float* r, float* p, float* d,
