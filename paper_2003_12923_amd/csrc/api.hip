@@ -1066,7 +1066,10 @@ static GatherArgs<T> sigma_prologue(esmp2_handle h, const SigmaBufs<T>& w, const
   hipStream_t s = h->stream;
   hipLaunchKernelGGL(k_sym_s2<T>, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, x, w.S);
   const PrologueArgs<T> r = prologue_args(h, w, x, y, arrow);
-  hipLaunchKernelGGL(k_gemv<T>, dim3(r.jobs), dim3(256), 0, s, r.gv);
+  if (d.nv <= 160)
+    hipLaunchKernelGGL((k_gemv<T, 160>), dim3(r.jobs), dim3(256), 0, s, r.gv);
+  else
+    hipLaunchKernelGGL((k_gemv<T, 192>), dim3(r.jobs), dim3(256), 0, s, r.gv);
   return r.ga;
 }
 
@@ -1652,7 +1655,10 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
   auto enqueue = [&](int slot) -> esmp2_status {
     hipLaunchKernelGGL(kd_sym, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, (const double*)h->p, w.S,
                        (const CgCtl*)ctl);
-    hipLaunchKernelGGL(kd_gemv, dim3(pa.jobs), dim3(256), 0, s, pa.gv, (const CgCtl*)ctl);
+    if (d.nv <= 160)
+      hipLaunchKernelGGL(kd_gemv<160>, dim3(pa.jobs), dim3(256), 0, s, pa.gv, (const CgCtl*)ctl);
+    else
+      hipLaunchKernelGGL(kd_gemv<192>, dim3(pa.jobs), dim3(256), 0, s, pa.gv, (const CgCtl*)ctl);
     hipLaunchKernelGGL(kd_arrow, dim3(h->nchunks), dim3(256), 0, s, aa, pt, (const int4*)h->chunks, h->pq_part,
                        (const CgCtl*)ctl);
     hipLaunchKernelGGL(kd_finish_pq, dim3(1), dim3(1024), 0, s, (const double*)h->pq_part, h->nchunks, h->sc, ctl);
@@ -1951,6 +1957,8 @@ static esmp2_status solve_batch_sc64(esmp2_handle* hs, int n, const esmp2_solve_
   const int* f_gemv = dfirst + (n + 1);
   const int* f_arrow = dfirst + 2 * (n + 1);
   const unsigned NBV = (unsigned)(n * BATCH_CG_BLOCKS);
+  int nv_max = 0;                  // the LDS arrays of the GEMV kernel hold the largest virtual dimension
+  for (int i = 0; i < n; ++i) nv_max = std::max(nv_max, hs[i]->d.nv);
   const unsigned nsmall = (unsigned)((n + 63) / 64);
   volatile int* act = h0->pin->active;
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1976,7 +1984,10 @@ static esmp2_status solve_batch_sc64(esmp2_handle* hs, int n, const esmp2_solve_
   for (int k = 0;; ++k) {
     if (k > opts->max_iter + 1) return fin(ESMP2_HIP_ERROR, "internal: batched iteration count exceeded");
     hipLaunchKernelGGL(kb_sym, dim3((unsigned)tot[0]), dim3(256), 0, s, (const BState*)dS, f_sym, n);
-    hipLaunchKernelGGL(kb_gemv, dim3((unsigned)tot[1]), dim3(256), 0, s, (const BState*)dS, f_gemv, n);
+    if (nv_max <= 160)
+      hipLaunchKernelGGL(kb_gemv<160>, dim3((unsigned)tot[1]), dim3(256), 0, s, (const BState*)dS, f_gemv, n);
+    else
+      hipLaunchKernelGGL(kb_gemv<192>, dim3((unsigned)tot[1]), dim3(256), 0, s, (const BState*)dS, f_gemv, n);
     hipLaunchKernelGGL(kb_arrow, dim3((unsigned)tot[2]), dim3(256), 0, s, (const BState*)dS, f_arrow, n);
     hipLaunchKernelGGL(kb_finish_pq, dim3(n), dim3(1024), 0, s, dS);
     hipLaunchKernelGGL(kb_update_r, dim3(NBV), dim3(256), 0, s, dS);

@@ -60,12 +60,13 @@ __global__ __launch_bounds__(256) void kb_sym(const BState* S, const int* first,
   sym_s2_body<double>(B.d, (const double*)B.p, B.S, local, B.nsym);
 }
 
-__global__ __launch_bounds__(256) void kb_gemv(const BState* S, const int* first, int ns) {
+template <int MV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MV <= 160 ? 5 : 4))) void kb_gemv(const BState* S, const int* first, int ns) {
   int local;
   const int s = state_of(first, ns, blockIdx.x, local);
   const BState& B = S[s];
   if (B.mode != BS_RUN) return;
-  gemv_body<double>(B.gv, local, B.ngemv);
+  gemv_body<double, MV>(B.gv, local, B.ngemv);
 }
 
 __global__ __launch_bounds__(256) void kb_arrow(const BState* S, const int* first, int ns) {

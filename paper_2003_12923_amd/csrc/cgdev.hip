@@ -41,9 +41,10 @@ __global__ __launch_bounds__(256) void kd_sym(Dims d, const double* x, double* S
   sym_s2_body<double>(d, x, S, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(256) void kd_gemv(GemvArgs<double> A, const CgCtl* c) {
+template <int MV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MV <= 160 ? 5 : 4))) void kd_gemv(GemvArgs<double> A, const CgCtl* c) {
   if (c->mode != CG_RUN) return;
-  gemv_body<double>(A, blockIdx.x, gridDim.x);
+  gemv_body<double, MV>(A, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void kd_arrow(ArrowArgs<double> A, PairTables P, const int4* chunks, double* pq,

@@ -26,13 +26,15 @@ struct GemvArgs {
 
 constexpr int GV_MAXW = 3;     // weight vectors per pass
 
-template <class T>
+// MV: the largest virtual dimension the LDS arrays hold (160 or 192); with
+// MV = 160 the FP64 kernel's LDS (32.1 KB) lets five workgroups share a CU.
+template <class T, int MV>
 __device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, int bid_, int nb_) {
   const SideArgs<T>& sd = A.sd;
   const Dims& d = sd.d;
   const int no = d.no, nv = d.nv, n2 = (no - 1) * (no - 1);
-  __shared__ T tile[16][193];
-  __shared__ T rowres[GV_MAXW][192];
+  __shared__ T tile[16][MV + 1];
+  __shared__ T rowres[GV_MAXW][MV];
   // ---- job -> box, batch, occupied indices
   int job = bid_, box;
   if (job < d.npo1) box = B_T3;
@@ -108,10 +110,10 @@ __device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, i
       break;
   }
   // weights in LDS (zero where a weight vector is absent or u at index 0)
-  __shared__ T swc[GV_MAXW][192], swr[GV_MAXW][192];
+  __shared__ T swc[GV_MAXW][MV], swr[GV_MAXW][MV];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int e = tid; e < GV_MAXW * 192; e += blockDim.x) {
-    const int k = e / 192, i = e % 192;
+  for (int e = tid; e < GV_MAXW * MV; e += blockDim.x) {
+    const int k = e / MV, i = e % MV;
     T vc = 0, vr = 0;
     if (i < nv) {
       if (wc[k] && !(uc && k == 2 && i == 0)) vc = wc[k][i];
@@ -142,6 +144,8 @@ __device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, i
   load_slab(0, v);
   for (int r0 = 0; r0 < m; r0 += 16) {
     __syncthreads();
+    // the next slab's loads are in flight during the column and row sums of this one
+    if (r0 + 16 < m) load_slab(r0 + 16, vn);
     // stage the slab; the thread of each column accumulates the column sums on the way
     if (c < m) {
 #pragma unroll
@@ -155,8 +159,6 @@ __device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, i
         }
       }
     }
-    // the next slab's loads are in flight during the row sums of this one
-    if (r0 + 16 < m) load_slab(r0 + 16, vn);
     __syncthreads();
     // row sums: 16 lanes per staged row, each over every 16th column, then a
     // 4-step reduction inside the 16-lane group
@@ -168,7 +170,7 @@ __device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, i
         const T* w = anti ? swc[k] : swr[k];
         T sacc = 0;
 #pragma unroll
-        for (int i = 0; i < 12; ++i) {            // m <= 192
+        for (int i = 0; i < MV / 16; ++i) {       // m <= MV
           const int cc = seg + 16 * i;
           if (cc < m) sacc += tile[rr][cc] * w[cc + lo];
         }
@@ -185,10 +187,10 @@ __device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, i
   }
   // column sums move from the thread of each storage column to the output threads through LDS
   __syncthreads();
-  T* colres = &tile[0][0];               // reuse: [GV_MAXW][192] fits in 16 x 193
+  T* colres = &tile[0][0];               // reuse: [GV_MAXW][MV] fits in 16 x (MV + 1)
   if (c < m) {
 #pragma unroll
-    for (int k = 0; k < GV_MAXW; ++k) colres[k * 192 + c] = cacc[k];
+    for (int k = 0; k < GV_MAXW; ++k) colres[k * MV + c] = cacc[k];
   }
   __syncthreads();
   if (c >= nv) return;
@@ -198,17 +200,21 @@ __device__ __attribute__((always_inline)) inline void gemv_body(GemvArgs<T> A, i
   const bool in = cs >= 0 && cs < m;
 #pragma unroll
   for (int k = 0; k < GV_MAXW; ++k) {
-    if (oc[k]) oc[k][c] = in ? colres[k * 192 + cs] - (anti ? rowres[k][cs] : T(0)) : T(0);
+    if (oc[k]) oc[k][c] = in ? colres[k * MV + cs] - (anti ? rowres[k][cs] : T(0)) : T(0);
     if (orow[k] && !anti) orow[k][c] = in ? rowres[k][cs] : T(0);
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_gemv(GemvArgs<T> A) {
-  gemv_body<T>(A, blockIdx.x, gridDim.x);
+// five workgroups of 256 per CU where the LDS allows it (MV = 160): the whole
+// grid of a c3-sized operator in one round
+template <class T, int MV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MV <= 160 ? 5 : 4))) void k_gemv(GemvArgs<T> A) {
+  gemv_body<T, MV>(A, blockIdx.x, gridDim.x);
 }
 
-template __global__ void k_gemv<double>(GemvArgs<double>);
-template __global__ void k_gemv<float>(GemvArgs<float>);
+template __global__ void k_gemv<double, 160>(GemvArgs<double>);
+template __global__ void k_gemv<double, 192>(GemvArgs<double>);
+template __global__ void k_gemv<float, 160>(GemvArgs<float>);
+template __global__ void k_gemv<float, 192>(GemvArgs<float>);
 
 }  // namespace esmp2
