@@ -415,17 +415,20 @@ __device__ inline void sort3(int& x, int& y, int& z) {
   if (x > y) { int t = x; x = y; y = t; }
 }
 
-// grid (x, y): y walks the smallest TOP l >= 1, x the (j<k, b<c) pairs
-// excluding l (grid-stride in x).
+// grid (x, y): y walks the smallest TOP l >= 1, x the chunks of 256 (b<c)
+// pairs of one (j<k) pair, both excluding l (grid-stride in x): the occupied
+// pair is uniform in a workgroup, a lane takes one virtual pair.
 __global__ __launch_bounds__(256) void k_e2s_same(E2sArgs A) {
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv, nov = no * nv;
-  const int per_l = d.npo1 * d.npv1;
+  const int nch = (d.npv1 + 255) / 256, nt = d.npo1 * nch;
   const double s2 = 0.70710678118654752440;
   double acc = 0.0;
   for (int l = 1 + blockIdx.y; l < no; l += gridDim.y)
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < per_l; r += gridDim.x * blockDim.x) {
-      const int to = A.po1[r / d.npv1], tv = A.pv1[r % d.npv1];
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+      const int pi = t / nch, vi = (t - pi * nch) * 256 + (int)threadIdx.x;
+      if (vi >= d.npv1) continue;
+      const int to = A.po1[pi], tv = A.pv1[vi];
       const int jr = to >> 16, kr = to & 0xffff, br = tv >> 16, cr = tv & 0xffff;
       const int j = jr + (jr >= l), k = kr + (kr >= l), b = br + (br >= l), c = cr + (cr >= l);
       if ((j < l && (j == b || j == c)) || (k < l && (k == b || k == c))) continue;
@@ -468,15 +471,18 @@ __device__ inline double b_mixed(const E2sArgs& A, int i, int a, int j, int k, i
   return bv;
 }
 
-// grid (x, y): y walks the up hole i >= 1 of the up TOP pair, x the (j<k, b<c) pairs
+// grid (x, y): y walks the up hole i >= 1 of the up TOP pair, x the chunks of
+// 256 (b<c) pairs of one (j<k) pair (grid-stride in x)
 __global__ __launch_bounds__(256) void k_e2s_mixed_a(E2sArgs A) {
   const Dims& d = A.d;
   const int no = d.no;
-  const int per_i = d.npo * d.npv;
+  const int nch = (d.npv + 255) / 256, nt = d.npo * nch;
   double acc = 0.0;
   for (int i = 1 + blockIdx.y; i < no; i += gridDim.y)
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < per_i; r += gridDim.x * blockDim.x) {
-      const int to = A.po[r / d.npv], tv = A.pv[r % d.npv];
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+      const int pi = t / nch, vi = (t - pi * nch) * 256 + (int)threadIdx.x;
+      if (vi >= d.npv) continue;
+      const int to = A.po[pi], tv = A.pv[vi];
       const int j = to >> 16, k = to & 0xffff, b = tv >> 16, c = tv & 0xffff;
       if ((j == 0 || k == 0) && (b == 0 || c == 0)) continue;     // contains t
       double bv = b_mixed(A, i, i, j, k, b, c);
@@ -487,27 +493,44 @@ __global__ __launch_bounds__(256) void k_e2s_mixed_a(E2sArgs A) {
   if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
-// grid (x, y): y walks the up excitation (i, a), a != i; x the (l, m, e) triples
-// of the down pair (holes {l, m}, particles {l', e})
+// grid (x, y): y walks the up excitation (i, a), a != i; a wavefront takes one
+// (l, m) pair of down holes (uniform: no index decode per item), its lanes the
+// down particle e != l' (holes {l, m}, particles {l', e}).  With a != i only
+// the beta singles of b_mixed enter, and with the holes and particles sharing
+// l their four Kronecker terms reduce to
+//   bd = s lam_l V(i a|m e) + [l < m, e = m] lam_m V(i a|l l),
+//   s = +1 if (l < m) == (l < e), else -1
+// (the case m < l, e = m belongs to the smaller TOP m and is skipped).
 __global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
   const Dims& d = A.d;
-  const int no = d.no, nv = d.nv;
-  const int inner = no * (no - 1) * (nv - 1);       // index = (l * (no-1) + mr) * (nv-1) + er
+  const int no = d.no, nv = d.nv, o1 = no - 1, v1 = nv - 1, nov = no * nv;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int nq = no * o1;                              // q = l * (no-1) + mr
+  const double s2 = 0.70710678118654752440, sg = (double)d.sg;
   double acc = 0.0;
   for (int ia = blockIdx.y; ia < no * nv; ia += gridDim.y) {
     const int i = ia / nv, a = ia - i * nv;
     if (a == i) continue;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < inner; r += gridDim.x * blockDim.x) {
-      const int er = r % (nv - 1), q = r / (nv - 1);
-      const int mr = q % (no - 1), l = q / (no - 1);
-      const int m = mr + (mr >= l), e = er + (er >= l);
-      if (m < l && e == m) continue;                                // smaller down TOP m
-      if ((i == 0 || l == 0 || m == 0) && (a == 0 || l == 0 || e == 0)) continue;   // contains t
+    const double* Vr = A.V + (int64_t)ia * nov;        // row (i, a) of V
+    for (int q = blockIdx.x * nw + wave; q < nq; q += gridDim.x * nw) {
+      const int l = q / o1, mr = q - l * o1;
+      const int m = mr + (mr >= l);
       const int j = l < m ? l : m, k = l < m ? m : l;
-      const int b = l < e ? l : e, c = l < e ? e : l;
-      const double bv = b_mixed(A, i, a, j, k, b, c);
-      const double D = A.ev[a] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
-      acc += 2.0 * bv * bv / D;
+      const bool t_hole = i == 0 || l == 0 || m == 0;
+      const double cl = A.lam[l] * s2, cm = A.lam[m] * s2;
+      const double vll = Vr[l * nv + l];
+      for (int er = lane; er < v1; er += 64) {
+        const int e = er + (er >= l);
+        if (m < l && e == m) continue;                              // smaller down TOP m
+        if (t_hole && (a == 0 || l == 0 || e == 0)) continue;       // contains t
+        const int b = l < e ? l : e, c = l < e ? e : l;
+        const double t = cl * Vr[m * nv + e];
+        double bd = ((l < m) == (l < e)) ? t : -t;
+        if (l < m && e == m) bd += cm * vll;
+        const double bv = sg * bd;
+        const double D = A.ev[a] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+        acc += 2.0 * bv * bv / D;
+      }
     }
   }
   double s = block_sum(acc);
