@@ -160,7 +160,7 @@ struct esmp2_handle_ {
   bool sc_eig = false;           // To, Tv hold the rotation of the current TOP basis
   double *To, *Tv, *Tsc, *Fh, *fo_sc, *fv_sc, *fov_sc, *eo_sc, *ev_sc, *Fd_sc, *Fl_sc, *b_sc;
   float *Fd32_sc, *Fl32_sc, *fo32_sc, *fv32_sc, *fov32_sc, *dinv32_sc;
-  double *dense0, *dense1;
+  double *dense0, *dense1;       // two n_occ^2 n_vir^2 halves of one allocation
   double* rs2;            // scratch of the side stream's virtual eigenproblem (10 nv^2 + 8 nv)
   double* rsc;            // right-hand side in the pinned-semicanonical basis: C, fphi, Bov, X, one intermediate
   double* gv;                    // row/column GEMVs of the arrow-shaped Fock blocks (FP64 or FP32 use)
@@ -367,7 +367,7 @@ static esmp2_status launch_semican_eig(esmp2_handle h) {
   hipLaunchKernelGGL(k_block_copy, dim3(64), dim3(256), 0, s, (const double*)h->Ft, (int64_t)n + 1, n, no - 1, A);
   esmp2_status st = sym_eig(h, s, A, no - 1, evals, Y, ws);
   if (st != ESMP2_OK) return st;
-  hipLaunchKernelGGL(k_embed_rotation, dim3(nblk(no * no)), dim3(256), 0, s, (const double*)Y, no, h->To);
+  hipLaunchKernelGGL(k_embed_rotation, dim3(no), dim3(64), 0, s, (const double*)Y, no, h->To);
   if (h->sc_vir_early) {
     // Y[a-1][A-1] = sum_k W[k][a] S[k][A-1], a >= 1 (W = R[no:, no:])
     const int m = nv - 1;
@@ -382,7 +382,7 @@ static esmp2_status launch_semican_eig(esmp2_handle h) {
     st = sym_eig(h, s, A, nv - 1, evals, Y, ws);
     if (st != ESMP2_OK) return st;
   }
-  hipLaunchKernelGGL(k_embed_rotation, dim3(nblk((int64_t)nv * nv)), dim3(256), 0, s, (const double*)Y, nv, h->Tv);
+  hipLaunchKernelGGL(k_embed_rotation, dim3(nv), dim3(64), 0, s, (const double*)Y, nv, h->Tv);
   ESMP2_HIP(hipGetLastError());
   ESMP2_HIP(hipEventRecord(h->ev_sc_eig, s));
   h->sc_pending = true;
@@ -560,7 +560,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
        dalloc(h, &h->b_sc, namp) && dalloc(h, &h->Fd32_sc, (size_t)mv * mv) &&
        dalloc(h, &h->Fl32_sc, (size_t)mv * mv) && dalloc(h, &h->fo32_sc, no * no) &&
        dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
-       dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, dense) && dalloc(h, &h->dense1, dense) &&
+       dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, 2 * dense) &&
        dalloc(h, &h->rsc, (size_t)no * nv * (2 + 3 * (size_t)na)) &&
        dalloc(h, &h->rs2, (size_t)10 * nv * nv + 8 * (size_t)nv) && dalloc(h, &h->cgctl, 4) &&
        dalloc(h, &h->gv, (size_t)nv * (2 * d.npo + 2 * no * no + (no - 1) * (no - 1)));
@@ -568,6 +568,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
     ok = ok && dalloc(h, &h->s0, namp) && dalloc(h, &h->Ft_s, (size_t)n * n) &&
          dalloc(h, &h->Bov_s, (size_t)na * no * nv) && dalloc(h, &h->Bvt_s, (size_t)na * nv * no) &&
          dalloc(h, &h->Boo_s, (size_t)na * no * no) && dalloc(h, &h->lam_s, no) && dalloc(h, &h->btmp, d.off[7]);
+  if (ok) h->dense1 = h->dense0 + dense;        // the second half of one allocation
   if (!ok) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
   // vv job table
   std::vector<int2> jobs;
@@ -758,7 +759,7 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
       g.sAi = m; g.sAk = 1; g.sBk = m; g.sBj = 1; g.sCi = m; g.sCj = 1; g.alpha = -0.5; g.beta = 1.0;
       ESMP2_HIP(gemm(s, 1, g));
       }
-      hipLaunchKernelGGL(k_assemble_r2, dim3(1), dim3(1024), 0, s, h->U, h->V, AV2, h->evals, no, nv, h->R, h->avo);
+      hipLaunchKernelGGL(k_assemble_r2, dim3(n), dim3(64), 0, s, h->U, h->V, AV2, h->evals, no, nv, h->R, h->avo);
     }
     // F~ = R^T F R
     g = GemmArgs{};
@@ -1328,8 +1329,9 @@ static esmp2_status semican_operator(esmp2_handle h) {
 }
 
 // Y[q] = To^T X[q] Tv for nq stacked no x nv matrices (a tensor in (i, a)
-// taken into the pinned-semicanonical basis); tmp holds nq * no * nv.
-static hipError_t rotate_ov(esmp2_handle h, int nq, const double* X, double* tmp, double* Y) {
+// taken into the pinned-semicanonical basis); Y[q] starts at Y + q * ldy;
+// tmp holds nq * no * nv.
+static hipError_t rotate_ov(esmp2_handle h, int nq, const double* X, double* tmp, double* Y, int64_t ldy) {
   const int no = h->d.no, nv = h->d.nv;
   GemmArgs g{};
   g.alpha = 1; g.beta = 0;
@@ -1343,7 +1345,7 @@ static hipError_t rotate_ov(esmp2_handle h, int nq, const double* X, double* tmp
   g.alpha = 1; g.beta = 0;
   g.A = h->To; g.B = tmp; g.C = Y; g.M = no; g.N = nv; g.K = no;
   g.sAb = 0; g.sAi = 1; g.sAk = no; g.sBb = (int64_t)no * nv; g.sBk = nv; g.sBj = 1;
-  g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1;
+  g.sCb = ldy; g.sCi = nv; g.sCj = 1;
   return gemm(h->stream, nq, g);
 }
 
@@ -1362,19 +1364,18 @@ static esmp2_status rhs_semican(esmp2_handle h) {
   hipStream_t s = h->stream;
   double* Cs = h->rsc;
   double* fphi = Cs + nov;
-  double* Bov = fphi + nov;
-  double* X = Bov + (size_t)na * nov;
-  double* tmp = X + (size_t)na * nov;
+  double* W = fphi + nov;                       // W[Q] = [Bov[Q] | X[Q]], 2 nov per Q
+  double* tmp = W + 2 * (size_t)na * nov;
   hipLaunchKernelGGL(k_singles_sc, dim3(nblk(nov)), dim3(256), 0, s, (const double*)h->To, (const double*)h->Tv,
                      (const double*)h->lam, no, nv, Cs);
-  ESMP2_HIP(rotate_ov(h, 1, h->fphi, tmp, fphi));
-  ESMP2_HIP(rotate_ov(h, na, h->Bov, tmp, Bov));
-  ESMP2_HIP(rotate_ov(h, na, h->X, tmp, X));
+  ESMP2_HIP(rotate_ov(h, 1, h->fphi, tmp, fphi, nov));
+  ESMP2_HIP(rotate_ov(h, na, h->Bov, tmp, W, 2 * (int64_t)nov));
+  ESMP2_HIP(rotate_ov(h, na, h->X, tmp, W + nov, 2 * (int64_t)nov));
+  // [V; M] = [Bov | X]^T Bov in one product: V into dense0, M into dense1 = dense0 + nov^2
   GemmArgs g{};
-  g.A = Bov; g.B = Bov; g.C = h->dense0; g.M = nov; g.N = nov; g.K = na;
-  g.sAi = 1; g.sAk = nov; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, 1, g));
-  g.A = X; g.C = h->dense1;
+  g.A = W; g.B = W; g.C = h->dense0; g.M = 2 * nov; g.N = nov; g.K = na;
+  g.sAi = 1; g.sAk = 2 * (int64_t)nov; g.sBk = 2 * (int64_t)nov; g.sBj = 1; g.sCi = nov; g.sCj = 1;
+  g.alpha = 1; g.beta = 0;
   ESMP2_HIP(gemm(s, 1, g));
   RhsArgs ra{d, h->dense0, h->dense1, fphi, h->lam, h->b_sc, Cs};
   hipLaunchKernelGGL(k_rhs<true>, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);

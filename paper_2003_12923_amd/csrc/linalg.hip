@@ -687,25 +687,40 @@ __global__ __launch_bounds__(64) void k_backtransform(const double* refl, const 
   }
 }
 
+// Sign of column x[0], x[ld], ..., x[(len-1) ld] that makes its first entry of
+// largest magnitude positive (+1 for a zero column), for the 64 lanes of a
+// wavefront: lane-local first maxima, then the larger magnitude and on a tie
+// the smaller index, which is the first maximum of the whole column.
+__device__ inline double col_sign(const double* x, int len, int ld, int l) {
+  double best = 0.0, val = 0.0;
+  int idx = 1 << 30;
+  for (int i = l; i < len; i += 64) {
+    const double y = x[(int64_t)i * ld];
+    if (fabs(y) > best) { best = fabs(y); val = y; idx = i; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double b2 = __shfl_xor(best, o), v2 = __shfl_xor(val, o);
+    const int i2 = __shfl_xor(idx, o);
+    if (b2 > best || (b2 == best && i2 < idx)) { best = b2; val = v2; idx = i2; }
+  }
+  return val < 0 ? -1.0 : 1.0;
+}
+
 // R[:no,:no] = U,  R[no:, no:2no] = V,  R[no:, 2no + c] = AVO[:, c] (signed:
-// largest-|entry| positive);  avo_eps[c] = eigenvalue c.
-__global__ void k_assemble_r2(const double* U, const double* V, const double* AVO, const double* evals, int no,
-                              int nv, double* R, double* avo_eps) {
-  const int n = no + nv, m = nv - no;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int e = tid; e < n * n; e += gridDim.x * blockDim.x) R[e] = 0.0;
-  __syncthreads();
-  // (single block launch: the zeroing above and the writes below are ordered by the barrier)
-  for (int e = tid; e < no * no; e += blockDim.x) R[(e / no) * n + (e % no)] = U[e];
-  for (int e = tid; e < nv * no; e += blockDim.x) R[(no + e / no) * n + no + (e % no)] = V[e];
-  for (int c = tid; c < m; c += blockDim.x) {
-    double best = 0, sg = 1.0;
-    for (int a = 0; a < nv; ++a) {
-      double v = AVO[a * m + c];
-      if (fabs(v) > best) { best = fabs(v); sg = v < 0 ? -1.0 : 1.0; }
-    }
-    for (int a = 0; a < nv; ++a) R[(no + a) * n + 2 * no + c] = sg * AVO[a * m + c];
-    avo_eps[c] = evals[c];
+// largest-|entry| positive);  avo_eps[c] = eigenvalue c.  One wavefront per
+// column of R.
+__global__ __launch_bounds__(64) void k_assemble_r2(const double* U, const double* V, const double* AVO,
+                                                    const double* evals, int no, int nv, double* R, double* avo_eps) {
+  const int n = no + nv, m = nv - no, col = blockIdx.x, l = threadIdx.x;
+  if (col < no) {
+    for (int r = l; r < n; r += 64) R[r * n + col] = r < no ? U[r * no + col] : 0.0;
+  } else if (col < 2 * no) {
+    for (int r = l; r < n; r += 64) R[r * n + col] = r >= no ? V[(r - no) * no + (col - no)] : 0.0;
+  } else {
+    const int c = col - 2 * no;
+    const double sg = col_sign(AVO + c, nv, m, l);
+    for (int r = l; r < n; r += 64) R[r * n + col] = r >= no ? sg * AVO[(r - no) * m + c] : 0.0;
+    if (l == 0) avo_eps[c] = evals[c];
   }
 }
 

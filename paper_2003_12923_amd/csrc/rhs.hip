@@ -25,7 +25,7 @@ namespace esmp2 {
 //   G_ia = sum_Q [ dq_Q Bov_Q[i][a] - (1/2) sum_k w_k Bov_Q[i][k] Bvt_Q[a][k]
 //                  + (1/2) sum_k w_k Boo_Q[i][k] Bov_Q[k][a] ],
 //   dq_Q = sum_k w_k (Bvt_Q[k][k] - Boo_Q[k][k]),  w_k = lam_k^2.
-constexpr int FPHI_QCHUNKS = 16;
+constexpr int FPHI_QCHUNKS = 64;   // 64 x n_occ workgroups: enough to spread the n_aux sum over the chip
 
 __global__ void k_fphi_dq(const double* Bvt, const double* Boo, const double* lam, int no, int nv, int naux,
                           double* dq) {

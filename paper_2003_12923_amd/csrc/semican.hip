@@ -34,23 +34,16 @@ __global__ void k_eig1(const double* A, double* evals, double* Y) {
 
 // T (n x n) = identity with T[1:, 1:] = Y (Y: (n-1) x (n-1), column k = eigenvector k).
 // Each eigenvector is signed so that its largest-magnitude entry is positive.
-__global__ void k_embed_rotation(const double* Y, int n, double* T) {
-  const int m = n - 1;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
-    const int r = e / n, c = e % n;
-    double v;
-    if (r == 0 || c == 0) {
-      v = (r == c) ? 1.0 : 0.0;
-    } else {
-      double best = 0.0, sg = 1.0;
-      for (int i = 0; i < m; ++i) {
-        const double y = Y[i * m + (c - 1)];
-        if (fabs(y) > best) { best = fabs(y); sg = y < 0 ? -1.0 : 1.0; }
-      }
-      v = sg * Y[(r - 1) * m + (c - 1)];
-    }
-    T[e] = v;
+__global__ __launch_bounds__(64) void k_embed_rotation(const double* Y, int n, double* T) {
+  // one wavefront per column c of T
+  const int m = n - 1, c = blockIdx.x, l = threadIdx.x;
+  if (c == 0) {
+    for (int r = l; r < n; r += 64) T[r * n] = r == 0 ? 1.0 : 0.0;
+    return;
   }
+  const double sg = col_sign(Y + (c - 1), m, m, l);
+  if (l == 0) T[c] = 0.0;
+  for (int r = 1 + l; r < n; r += 64) T[r * n + c] = sg * Y[(r - 1) * m + (c - 1)];
 }
 
 // T (n x n) = blkdiag(To, Tv)
