@@ -640,45 +640,54 @@ __global__ __launch_bounds__(64) void k_cluster_mgs(const double* evals, int m, 
 }
 
 // Y[:, k] = G_0 ... G_{m-3} Z[k, :]; one workgroup (64 threads) per column.
-// Each lane keeps its entries of the column (i = l + 64 s) in registers and
-// has the next reflector's entries in flight while it applies the current one.
+// Each lane keeps its entries of the column (i = l + 64 s) in registers; the
+// reflector coefficients sit in LDS and the entries of the next BT_AHEAD
+// reflectors are in flight while it applies the current one (one reflector's
+// arithmetic is far shorter than a load's latency).
+constexpr int BT_AHEAD = 3;
+
 __global__ __launch_bounds__(64) void k_backtransform(const double* refl, const double* rbeta, int m,
                                                       const double* Z, double* Y) {
   constexpr int S = TRI_MAX / 64;
   const int k = blockIdx.x, l = threadIdx.x;
-  double y[S], cur[S], nxt[S];
+  __shared__ double sb[TRI_MAX];
+  for (int j = l; j < m; j += 64) sb[j] = j <= m - 3 ? rbeta[j] : 0.0;
+  double y[S], buf[BT_AHEAD + 1][S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int i = l + 64 * s;
     y[s] = (i < m) ? Z[(size_t)k * m + i] : 0.0;
   }
-  const int j0 = m - 3;
-  if (j0 >= 0) {
+  // reflector j (entries i > j) into buf slot (j0 - j) % (BT_AHEAD + 1)
+  auto load = [&](int j, double* dst) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int i = l + 64 * s;
-      cur[s] = (i < m && i > j0) ? refl[(size_t)j0 * m + i] : 0.0;
+      dst[s] = (j >= 0 && i < m && i > j) ? refl[(size_t)j * m + i] : 0.0;
     }
-  }
-  for (int j = j0; j >= 0; --j) {
-    const double b = rbeta[j];
-    if (j > 0) {
+  };
+  const int j0 = m - 3;
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int i = l + 64 * s;
-        nxt[s] = (i < m && i > j - 1) ? refl[(size_t)(j - 1) * m + i] : 0.0;
+  for (int a = 0; a < BT_AHEAD; ++a) load(j0 - a, buf[a]);
+  __syncthreads();
+  for (int j = j0; j >= 0; j -= BT_AHEAD + 1) {
+    // BT_AHEAD + 1 reflectors per pass so that the slots have fixed names
+#pragma unroll
+    for (int a = 0; a <= BT_AHEAD; ++a) {
+      const int jj = j - a;
+      if (jj < 0) break;
+      load(jj - BT_AHEAD, buf[(a + BT_AHEAD) % (BT_AHEAD + 1)]);
+      const double b = sb[jj];
+      if (b != 0.0) {
+        const double* cur = buf[a];
+        double t = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) t += cur[s] * y[s];
+        t = wave_sum(t) * b;
+#pragma unroll
+        for (int s = 0; s < S; ++s) y[s] -= t * cur[s];
       }
     }
-    if (b != 0.0) {
-      double t = 0.0;
-#pragma unroll
-      for (int s = 0; s < S; ++s) t += cur[s] * y[s];
-      t = wave_sum(t) * b;
-#pragma unroll
-      for (int s = 0; s < S; ++s) y[s] -= t * cur[s];
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) cur[s] = nxt[s];
   }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
