@@ -1653,7 +1653,9 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
   const int* pv = h->pairs;
   const PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
   hipLaunchKernelGGL(kd_ctl_init, dim3(1), dim3(64), 0, s, ctl, rel0);
-  auto enqueue = [&](int slot) -> esmp2_status {
+  // a solve from x = 0 leaves r and x unwritten at the start: the first iteration reads -b for r
+  const int from_zero = opts->x0 ? 0 : 1;
+  auto enqueue = [&](int slot, int first) -> esmp2_status {
     hipLaunchKernelGGL(kd_sym, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, (const double*)h->p, w.S,
                        (const CgCtl*)ctl);
     if (d.nv <= 160)
@@ -1664,22 +1666,22 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
                        (const CgCtl*)ctl);
     hipLaunchKernelGGL(kd_finish_pq, dim3(1), dim3(1024), 0, s, (const double*)h->pq_part, h->nchunks, h->sc, ctl);
     hipLaunchKernelGGL(kd_update_r, dim3(NB), dim3(256), 0, s, h->r, (const double*)h->q, c.dinv32, n, d.off[1],
-                       d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl);
+                       d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl, c.b, first);
     hipLaunchKernelGGL(kd_finish_r, dim3(2), dim3(1024), 0, s, (const double*)h->partial, (int)NB, h->sc, ctl, bn,
                        opts->tol, opts->max_iter);
     ESMP2_HIP(hipMemcpyAsync(&h->pin->cg[slot], ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));
     ESMP2_HIP(hipEventRecord(h->ev_cg[slot], s));
     hipLaunchKernelGGL(kd_update_px, dim3(NB), dim3(256), 0, s, h->x, h->p, (const double*)h->r, c.b, c.dinv32, n,
-                       d.off[1], d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl);
+                       d.off[1], d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl, first);
     ESMP2_HIP(hipGetLastError());
     return ESMP2_OK;
   };
-  ESMP2_TRY(enqueue(0));
+  ESMP2_TRY(enqueue(0, from_zero));
   int queued = 1;
   CgCtl last{};
   for (int i = 0;; ++i) {
     if (queued < opts->max_iter) {            // the next iteration before this one's outcome
-      ESMP2_TRY(enqueue(queued & 1));
+      ESMP2_TRY(enqueue(queued & 1, 0));
       ++queued;
     }
     ESMP2_HIP(hipEventSynchronize(h->ev_cg[i & 1]));
@@ -1693,6 +1695,9 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
   }
   if (status == ESMP2_NOT_SPD) {
     h->err = "p.Ap <= 0 in conjugate gradient";
+    if (from_zero && last.it == 0)    // stopped before the first update: x = 0, r = -b
+      hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv32, n,
+                         d.off[1], d.off[2], h->partial, h->x);
     return finish_solve(h, c, opts, res, last.rel, last.it, 0, status);
   }
   if (status == ESMP2_NOT_CONVERGED) h->err = "max_iter reached";
@@ -1708,6 +1713,10 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   const int64_t n = h->namp;
   hipStream_t s = h->stream;
   const unsigned NB = PCG_BLOCKS;
+  // the device-stopped iterations (pinned-semicanonical basis): from x = 0 the
+  // start stores neither r nor x (the first iteration reads -b for r)
+  const bool dev = c.arrow && h->nchunks > 0 && h->ntop == 1 && opts->max_iter > 0;
+  const bool lazy = dev && !opts->x0;
   if (opts->x0) {
     wdot(h, c.b, c.b, SC_BB);   // ||b||_W^2
     if (c.rotated) {
@@ -1722,8 +1731,8 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
                        h->partial, (double*)nullptr);
   } else {
     // x = 0 in the same pass; r = -b exactly, so <r, r>_W is ||b||_W^2
-    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv32, n,
-                       d.off[1], d.off[2], h->partial, h->x);
+    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, lazy ? nullptr : h->r, h->p,
+                       c.dinv32, n, d.off[1], d.off[2], h->partial, lazy ? nullptr : h->x);
   }
   // rho = <r, D^-1 r> into SC_RHO and <r, r> into SC_RHO + 1 = SC_PQ
   hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, h->partial, (int)NB, h->sc, SC_RHO);
@@ -1732,8 +1741,10 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   ESMP2_HIP(hipStreamSynchronize(s));
   const double bn = sqrt(opts->x0 ? hs[SC_BB] : hs[SC_PQ]);
   double rel = sqrt(hs[SC_PQ]) / bn;
-  if (c.arrow && h->nchunks > 0 && h->ntop == 1 && rel > opts->tol && opts->max_iter > 0)
-    return solve64_dev(h, c, opts, res, bn, rel);
+  if (dev && rel > opts->tol) return solve64_dev(h, c, opts, res, bn, rel);
+  if (lazy)      // converged at the start: x = 0 and r = -b for the Hylleraas dots
+    hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv32, n,
+                       d.off[1], d.off[2], h->partial, h->x);
   int it = 0;
   esmp2_status status = ESMP2_OK;
   while (rel > opts->tol && it < opts->max_iter) {

@@ -13,6 +13,8 @@
 //                DONE (not SPD); ||r||_W / ||b||_W <= tol or max_iter -> LAST
 //   update_px    RUN: x += alpha p, p = M r + beta p;  LAST: x += alpha p and
 //                the parts of the Hylleraas dots <b, x>_W, <x, r>_W
+// The first iteration of a solve from x = 0 (first = 1) takes r = -b and
+// x = alpha p without reading r or x: the start stores neither.
 #include "common.h"
 #include "sigma.h"
 #include "pcg.h"
@@ -67,9 +69,39 @@ __global__ __launch_bounds__(1024) void kd_finish_pq(const double* pq, int nb, d
 
 __global__ __launch_bounds__(256) void kd_update_r(double* r, const double* q, const float* dinv, int64_t n,
                                                    int64_t s0, int64_t s1, const double* sc, double* partial,
-                                                   const CgCtl* c) {
+                                                   const CgCtl* c, const double* b, int first) {
   if (c->mode != CG_RUN) return;
-  update_r_body<double>(r, q, dinv, n, s0, s1, sc, partial, blockIdx.x, gridDim.x);
+  if (!first) {
+    update_r_body<double>(r, q, dinv, n, s0, s1, sc, partial, blockIdx.x, gridDim.x);
+    return;
+  }
+  // r = -b - alpha q (the same sums as update_r_body with r = -b)
+  const double alpha = sc[SC_RHO] / sc[SC_PQ];
+  double rz = 0.0, rr = 0.0;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    double bv[PCG_U], qv[PCG_U];
+    float dv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      bv[u] = b[gg]; qv[u] = q[gg]; dv[u] = dinv[gg];
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) {
+        const double rg = -bv[u] - alpha * qv[u];
+        r[g] = rg;
+        const double w = wgt(g, s0, s1);
+        rz += w * rg * rg * (double)dv[u];
+        rr += w * rg * rg;
+      }
+    }
+  }
+  double a = block_sum(rz);
+  double d = block_sum(rr);
+  if (threadIdx.x == 0) { partial[blockIdx.x] = a; partial[gridDim.x + blockIdx.x] = d; }
 }
 
 // two blocks: sc[SC_RHO_NEW], sc[SC_RR]; block 1 then takes the decision.
@@ -98,10 +130,33 @@ __global__ __launch_bounds__(1024) void kd_finish_r(const double* partial, int n
 
 __global__ __launch_bounds__(256) void kd_update_px(double* x, double* p, const double* r, const double* b,
                                                     const float* dinv, int64_t n, int64_t s0, int64_t s1,
-                                                    const double* sc, double* partial, const CgCtl* c) {
+                                                    const double* sc, double* partial, const CgCtl* c, int first) {
   const int mode = c->mode;
-  if (mode == CG_RUN) {
+  if (mode == CG_RUN && !first) {
     update_px_body<double>(x, p, r, dinv, n, sc, blockIdx.x, gridDim.x);
+    return;
+  }
+  if (mode == CG_RUN) {     // x = alpha p;  p = M r + beta p
+    const double alpha = sc[SC_RHO] / sc[SC_PQ];
+    const double beta = sc[SC_RHO_NEW] / sc[SC_RHO];
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+      double pv[PCG_U], rv[PCG_U];
+      float dv[PCG_U];
+#pragma unroll
+      for (int u = 0; u < PCG_U; ++u) {
+        const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+        pv[u] = p[gg]; rv[u] = r[gg]; dv[u] = dinv[gg];
+      }
+#pragma unroll
+      for (int u = 0; u < PCG_U; ++u) {
+        const int64_t g = g0 + u * st;
+        if (g < n) {
+          x[g] = 0.0 + alpha * pv[u];
+          p[g] = (double)dv[u] * rv[u] + beta * pv[u];
+        }
+      }
+    }
     return;
   }
   if (mode != CG_LAST) return;
@@ -114,7 +169,7 @@ __global__ __launch_bounds__(256) void kd_update_px(double* x, double* p, const 
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      xv[u] = x[gg]; pv[u] = p[gg]; bv[u] = b[gg]; rv[u] = r[gg];
+      xv[u] = first ? 0.0 : x[gg]; pv[u] = p[gg]; bv[u] = b[gg]; rv[u] = r[gg];
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {

@@ -179,7 +179,8 @@ __global__ void k_roll_rho(double* sc) {
 }
 
 // r = -b - y (y = A x0) or r = -b;  p = M r;  partials of <r, M r>, <r, r>;
-// xz = 0 where given (the start x = 0)
+// xz = 0 where given (the start x = 0); r not stored when null (a solve whose
+// first iteration reads -b for r)
 __device__ __attribute__((always_inline)) inline void init_body(const double* b, const double* y, double* r, double* p,
                                               const float* dinv, int64_t n, int64_t s0, int64_t s1,
                                               double* partial, int bid_, int nb_, double* xz = nullptr) {
@@ -198,7 +199,7 @@ __device__ __attribute__((always_inline)) inline void init_body(const double* b,
       const int64_t g = g0 + u * st;
       if (g < n) {
         const double rg = -bv[u] - yv[u];
-        r[g] = rg;
+        if (r) r[g] = rg;
         p[g] = (double)dv[u] * rg;
         if (xz) xz[g] = 0.0;
         const double w = wgt(g, s0, s1);
