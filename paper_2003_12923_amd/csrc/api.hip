@@ -122,7 +122,7 @@ struct esmp2_handle_ {
   double *fphi, *fphi_part, *X, *Vint, *Mint, *b, *blockmin, *partial, *sc;
   bool have_rhs = false;
   bool sc_vir_early = false;    // launch_sc_vir_early has queued the virtual eigenproblem
-  bool b_top_pending = false;   // build_rhs left the TOP-basis b (and M) for ensure_b_top
+  bool b_top_pending = false;   // build_rhs left the TOP-basis b, M and 1/D for ensure_b_top
   // sigma scratch
   double *S, *side, *side_tr;
   int2* jobs = nullptr;
@@ -882,9 +882,9 @@ static esmp2_status rhs_core(esmp2_handle h, const double* Ft, const double* Bov
   return ESMP2_OK;
 }
 
-// The one-TOP right-hand side in the TOP basis, left for later by build_rhs
-// (a solve in the pinned-semicanonical basis builds its own from X, f^Phi and
-// Bov and never reads this one): M = X^T Bov and b from V, M, f^Phi.
+// The one-TOP right-hand side and Jacobi diagonal in the TOP basis, left for
+// later by build_rhs (a solve in the pinned-semicanonical basis builds its own
+// and never reads these): M = X^T Bov, b from V, M, f^Phi, and 1/D.
 static esmp2_status ensure_b_top(esmp2_handle h) {
   if (!h->b_top_pending) return ESMP2_OK;
   const Dims& d = h->d;
@@ -895,6 +895,8 @@ static esmp2_status ensure_b_top(esmp2_handle h) {
   ESMP2_HIP(gemm(h->stream, 1, g));
   RhsArgs ra{d, h->Vint, h->Mint, h->fphi, h->lam, h->b, nullptr};
   hipLaunchKernelGGL(k_rhs<false>, dim3(nblk(d.off[7])), dim3(256), 0, h->stream, ra);
+  DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv32, h->blockmin};
+  (void)launch_diag(h, da);
   ESMP2_HIP(hipGetLastError());
   h->b_top_pending = false;
   return ESMP2_OK;
@@ -916,17 +918,17 @@ static esmp2_status build_rhs(esmp2_handle h) {
     if (st != ESMP2_OK) return st;
     h->b_top_pending = h->ntop == 1;
   }
-  unsigned nmin = nblk(namp);
   if (h->ntop == 1) {
-    DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv32, h->blockmin};
-    nmin = launch_diag(h, da);
+    // the smallest denominator from the orbital energies; the TOP-basis
+    // diagonal itself waits for ensure_b_top with b
+    hipLaunchKernelGGL(k_diag_min, dim3(1), dim3(64), 0, s, d, (const double*)h->eo, (const double*)h->ev, h->omega,
+                       h->sc + SC_TMP);
   } else {
     const TopkArgs ta = topk_args(h);
     hipLaunchKernelGGL(k_topk_bset, dim3(nblk(d.off[7])), dim3(256), 0, s, ta, 0, (const double*)h->btmp, h->b);
     hipLaunchKernelGGL(k_topk_diag, dim3(nblk(namp)), dim3(256), 0, s, ta, h->dinv32, h->blockmin);
+    hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin, (int64_t)nblk(namp), h->sc + SC_TMP);
   }
-  hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, s, h->blockmin,
-                     (int64_t)nmin, h->sc + SC_TMP);
   // E2_S on the side stream (after the eigenproblems queued there), beside the
   // solve: it reads Vint, lam, eo, ev, omega and the pair tables, which the
   // next rotation or right-hand side rewrites only after joining it.  Grids of

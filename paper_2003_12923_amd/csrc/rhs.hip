@@ -381,6 +381,56 @@ __global__ __launch_bounds__(256) void k_diag_chunks(DiagArgs A, PairTables P, c
   if (threadIdx.x == 0) A.blockmin[blockIdx.x] = fmin(fmin(ws[0], ws[1]), fmin(ws[2], ws[3]));
 }
 
+// The smallest diagonal denominator D of the one-TOP space, from the orbital
+// energies alone: D separates into particle minus hole energies, so the
+// minimum over a box is its smallest particle sum minus its largest hole sum
+// (two distinct indices for a packed pair, any two for a free pair; virtual
+// and occupied index 0 excluded where the box excludes t' or t).  One
+// wavefront: per-lane two smallest (largest) values, merged by shuffles.
+__device__ inline void merge_two_small(double& s1, double& s2) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double t1 = __shfl_xor(s1, o), t2 = __shfl_xor(s2, o);
+    const double n1 = fmin(s1, t1), n2 = fmin(fmax(s1, t1), fmin(s2, t2));
+    s1 = n1; s2 = n2;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_diag_min(Dims d, const double* eo, const double* ev, double omega,
+                                                 double* out) {
+  const int no = d.no, nv = d.nv, l = threadIdx.x;
+  // two smallest virtual energies over [lo, nv) and two largest occupied ones
+  // over [lo, no) (the largest as the smallest of -eo)
+  double va1 = 1e300, va2 = 1e300, vb1 = 1e300, vb2 = 1e300;
+  double oa1 = 1e300, oa2 = 1e300, ob1 = 1e300, ob2 = 1e300;
+  auto ins = [](double e, double& s1, double& s2) {
+    if (e < s1) { s2 = s1; s1 = e; } else if (e < s2) s2 = e;
+  };
+  for (int a = l; a < nv; a += 64) {
+    ins(ev[a], va1, va2);
+    if (a >= 1) ins(ev[a], vb1, vb2);
+  }
+  for (int i = l; i < no; i += 64) {
+    ins(-eo[i], oa1, oa2);
+    if (i >= 1) ins(-eo[i], ob1, ob2);
+  }
+  merge_two_small(va1, va2);
+  merge_two_small(vb1, vb2);
+  merge_two_small(oa1, oa2);
+  merge_two_small(ob1, ob2);
+  if (l != 0) return;
+  const double base = ev[0] - eo[0] - omega;
+  double mn = 1e300;
+  auto take = [&](int box, double v) { if (d.off[box + 1] > d.off[box]) mn = fmin(mn, v); };
+  take(B_T2, (va1 + va2) + (oa1 + oa2) - omega);
+  take(B_S2, 2.0 * va1 + 2.0 * oa1 - omega);
+  take(B_T3, base + (vb1 + vb2) + (ob1 + ob2));
+  take(B_H11, base + (va1 + va2) + (oa1 + oa2));
+  take(B_H12, base + 2.0 * vb1 + (oa1 + oa2));
+  take(B_H21, base + (va1 + va2) + 2.0 * ob1);
+  take(B_H22, base + 2.0 * vb1 + 2.0 * ob1);
+  out[0] = mn;
+}
+
 __global__ void k_min_reduce(const double* v, int64_t n, double* out) {
   double mn = 1e300;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) mn = fmin(mn, v[i]);
