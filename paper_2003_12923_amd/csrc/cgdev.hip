@@ -85,14 +85,14 @@ __global__ __launch_bounds__(256) void kd_update_r(double* r, const double* q, c
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      bv[u] = b[gg]; qv[u] = q[gg]; dv[u] = dinv[gg];
+      bv[u] = ldnt(b + gg); qv[u] = ldnt(q + gg); dv[u] = ldnt(dinv + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
       if (g < n) {
         const double rg = -bv[u] - alpha * qv[u];
-        r[g] = rg;
+        stnt(rg, r + g);
         const double w = wgt(g, s0, s1);
         rz += w * rg * rg * (double)dv[u];
         rr += w * rg * rg;
@@ -146,14 +146,14 @@ __global__ __launch_bounds__(256) void kd_update_px(double* x, double* p, const 
 #pragma unroll
       for (int u = 0; u < PCG_U; ++u) {
         const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-        pv[u] = p[gg]; rv[u] = r[gg]; dv[u] = dinv[gg];
+        pv[u] = ldnt(p + gg); rv[u] = ldnt(r + gg); dv[u] = ldnt(dinv + gg);
       }
 #pragma unroll
       for (int u = 0; u < PCG_U; ++u) {
         const int64_t g = g0 + u * st;
         if (g < n) {
-          x[g] = 0.0 + alpha * pv[u];
-          p[g] = (double)dv[u] * rv[u] + beta * pv[u];
+          stnt(0.0 + alpha * pv[u], x + g);
+          stnt((double)dv[u] * rv[u] + beta * pv[u], p + g);
         }
       }
     }

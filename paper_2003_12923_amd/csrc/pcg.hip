@@ -18,6 +18,16 @@ __device__ inline double wgt(int64_t g, int64_t s0, int64_t s1) { return (g >= s
 // as far as it knows), and their latencies overlap.
 constexpr int PCG_U = 4;
 
+// Streaming accesses of the CG vector updates: nontemporal loads and stores
+// (each vector is touched once per pass; keeping it out of the caches lets the
+// pass run at a higher fraction of HBM bandwidth)
+template <class T> __device__ __attribute__((always_inline)) inline T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <class T> __device__ __attribute__((always_inline)) inline void stnt(T v, T* p) {
+  __builtin_nontemporal_store(v, p);
+}
+
 // partial[block] = sum_g w_g x_g y_g   (grid-stride, fixed grid -> deterministic)
 template <class T>
 __device__ __attribute__((always_inline)) inline void dot_body(const T* x, const T* y, int64_t n, int64_t s0, int64_t s1,
@@ -92,14 +102,14 @@ __device__ __attribute__((always_inline)) inline void update_r_body(T* r, const 
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      rv[u] = r[gg]; qv[u] = q[gg]; dv[u] = dinv[gg];
+      rv[u] = ldnt(r + gg); qv[u] = ldnt(q + gg); dv[u] = ldnt(dinv + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
       if (g < n) {
         const T rg = rv[u] - alpha * qv[u];
-        r[g] = rg;
+        stnt(rg, r + g);
         const double w = wgt(g, s0, s1), rd = (double)rg;
         rz += w * rd * rd * (double)dv[u];
         rr += w * rd * rd;
@@ -130,14 +140,14 @@ __device__ __attribute__((always_inline)) inline void update_px_body(T* x, T* p,
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      xv[u] = x[gg]; pv[u] = p[gg]; rv[u] = r[gg]; dv[u] = dinv[gg];
+      xv[u] = ldnt(x + gg); pv[u] = ldnt(p + gg); rv[u] = ldnt(r + gg); dv[u] = ldnt(dinv + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
       if (g < n) {
-        x[g] = xv[u] + alpha * pv[u];
-        p[g] = (T)dv[u] * rv[u] + beta * pv[u];
+        stnt(xv[u] + alpha * pv[u], x + g);
+        stnt((T)dv[u] * rv[u] + beta * pv[u], p + g);
       }
     }
   }
@@ -192,16 +202,16 @@ __device__ __attribute__((always_inline)) inline void init_body(const double* b,
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      bv[u] = b[gg]; yv[u] = y ? y[gg] : 0.0; dv[u] = dinv[gg];
+      bv[u] = ldnt(b + gg); yv[u] = y ? ldnt(y + gg) : 0.0; dv[u] = ldnt(dinv + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
       if (g < n) {
         const double rg = -bv[u] - yv[u];
-        if (r) r[g] = rg;
-        p[g] = (double)dv[u] * rg;
-        if (xz) xz[g] = 0.0;
+        if (r) stnt(rg, r + g);
+        stnt((double)dv[u] * rg, p + g);
+        if (xz) stnt(0.0, xz + g);
         const double w = wgt(g, s0, s1);
         rz += w * rg * rg * (double)dv[u];
         rr += w * rg * rg;
