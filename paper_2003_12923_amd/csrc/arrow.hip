@@ -198,7 +198,7 @@ __device__ __attribute__((always_inline)) inline double arrow_element(const Arro
     y += G.side_tr[((box == B_H11 ? 0 : (int64_t)d.npo) + batch) * nv + b];
   y += couple_terms(G, P, box, batch, i, j, v);
   const int64_t g = d.off[box] + (int64_t)batch * inner + v;
-  G.y[g] = y;
+  __builtin_nontemporal_store(y, G.y + g);
   return (box == B_S2 ? 1.0 : 2.0) * (double)G.x[g] * (double)y;     // weighted product for <x, y>_W
 }
 

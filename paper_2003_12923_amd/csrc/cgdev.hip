@@ -169,14 +169,14 @@ __global__ __launch_bounds__(256) void kd_update_px(double* x, double* p, const 
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      xv[u] = first ? 0.0 : x[gg]; pv[u] = p[gg]; bv[u] = b[gg]; rv[u] = r[gg];
+      xv[u] = first ? 0.0 : ldnt(x + gg); pv[u] = ldnt(p + gg); bv[u] = ldnt(b + gg); rv[u] = ldnt(r + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
       if (g < n) {
         const double xn = xv[u] + alpha * pv[u];
-        x[g] = xn;
+        stnt(xn, x + g);
         const double w = wgt(g, s0, s1);
         bx.add(w * bv[u] * xn);
         xr.add(w * xn * rv[u]);

@@ -39,8 +39,8 @@ __device__ __attribute__((always_inline)) inline void dot_body(const T* x, const
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      xv[u] = x[gg];
-      yv[u] = y[gg];
+      xv[u] = ldnt(x + gg);
+      yv[u] = ldnt(y + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
@@ -169,12 +169,12 @@ __device__ __attribute__((always_inline)) inline void update_x_body(T* x, const 
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      xv[u] = x[gg]; pv[u] = p[gg];
+      xv[u] = ldnt(x + gg); pv[u] = ldnt(p + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
-      if (g < n) x[g] = xv[u] + alpha * pv[u];
+      if (g < n) stnt(xv[u] + alpha * pv[u], x + g);
     }
   }
 }
@@ -239,14 +239,14 @@ __global__ __launch_bounds__(256) void k_resid(const double* b, const double* y,
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      bv[u] = b[gg]; yv[u] = y ? y[gg] : 0.0;
+      bv[u] = ldnt(b + gg); yv[u] = y ? ldnt(y + gg) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
       if (g < n) {
         const double rg = -bv[u] - yv[u];
-        r[g] = rg;
+        stnt(rg, r + g);
         acc.add(wgt(g, s0, s1) * rg * rg);
       }
     }
@@ -269,16 +269,16 @@ __global__ __launch_bounds__(256) void k_init_inner(const double* r64, double sc
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      rv[u] = r64[gg]; dv[u] = dinv[gg];
+      rv[u] = ldnt(r64 + gg); dv[u] = ldnt(dinv + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
       if (g < n) {
         const float rg = (float)(rv[u] * inv);
-        r[g] = rg;
-        d[g] = 0.f;
-        p[g] = dv[u] * rg;
+        stnt(rg, r + g);
+        stnt(0.f, d + g);
+        stnt(dv[u] * rg, p + g);
         const double w = wgt(g, s0, s1), rd = (double)rg;
         rz += w * rd * rd * (double)dv[u];
         rr += w * rd * rd;
@@ -300,12 +300,12 @@ __global__ __launch_bounds__(256) void k_refine(double* x, const float* d, doubl
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-      xv[u] = x[gg]; dv[u] = d[gg];
+      xv[u] = ldnt(x + gg); dv[u] = ldnt(d + gg);
     }
 #pragma unroll
     for (int u = 0; u < PCG_U; ++u) {
       const int64_t g = g0 + u * st;
-      if (g < n) x[g] = xv[u] + s * (double)dv[u];
+      if (g < n) stnt(xv[u] + s * (double)dv[u], x + g);
     }
   }
 }
