@@ -569,21 +569,26 @@ __global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
       const bool t_hole = i == 0 || l == 0 || m == 0;
       const double cl = A.lam[l] * s2, cm = A.lam[m] * s2;
       const double vll = Vr[l * nv + l];
+      // D = dq + ev[e]: the particles are {a, l', e}, the holes {i, l, m}
+      const double dq = A.ev[a] + A.ev[l] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
       for (int er = lane; er < v1; er += 64) {
         const int e = er + (er >= l);
         if (m < l && e == m) continue;                              // smaller down TOP m
         if (t_hole && (a == 0 || l == 0 || e == 0)) continue;       // contains t
-        const int b = l < e ? l : e, c = l < e ? e : l;
         const double t = cl * Vr[m * nv + e];
         double bd = ((l < m) == (l < e)) ? t : -t;
         if (l < m && e == m) bd += cm * vll;
         const double bv = sg * bd;
-        const double D = A.ev[a] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
-        acc += 2.0 * bv * bv / D;
+        // 1/D from the hardware estimate and two Newton steps (FP64 rounding level)
+        const double D = dq + A.ev[e];
+        double r = __builtin_amdgcn_rcp(D);
+        r = fma(fma(-D, r, 1.0), r, r);
+        r = fma(fma(-D, r, 1.0), r, r);
+        acc += bv * bv * r;
       }
     }
   }
-  double s = block_sum(acc);
+  double s = block_sum(2.0 * acc);
   if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
