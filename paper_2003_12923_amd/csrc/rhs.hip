@@ -459,6 +459,15 @@ struct E2sArgs {
   const int *pv, *pv1, *po, *po1;   // pair tables ((p << 16) | q, p < q) of nv, nv-1, no, no-1
 };
 
+// 1/D for the S-triple sums: the hardware reciprocal estimate refined by two
+// Newton steps (relative error at the FP64 rounding level; D > 0 here)
+__device__ inline double recip_fast(double D) {
+  double r = __builtin_amdgcn_rcp(D);
+  r = fma(fma(-D, r, 1.0), r, r);
+  r = fma(fma(-D, r, 1.0), r, r);
+  return r;
+}
+
 __device__ inline void sort3(int& x, int& y, int& z) {
   if (x > y) { int t = x; x = y; y = t; }
   if (y > z) { int t = y; y = z; z = t; }
@@ -497,9 +506,9 @@ __global__ __launch_bounds__(256) void k_e2s_same(E2sArgs A) {
           bv += sg * A.lam[I[q]] * s2 * anti;
         }
       double D = A.ev[P[0]] + A.ev[P[1]] + A.ev[P[2]] - A.eo[I[0]] - A.eo[I[1]] - A.eo[I[2]] - A.omega;
-      acc += 2.0 * bv * bv / D;
+      acc += bv * bv * recip_fast(D);
     }
-  double s = block_sum(acc);
+  double s = block_sum(2.0 * acc);
   if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
@@ -537,9 +546,9 @@ __global__ __launch_bounds__(256) void k_e2s_mixed_a(E2sArgs A) {
       if ((j == 0 || k == 0) && (b == 0 || c == 0)) continue;     // contains t
       double bv = b_mixed(A, i, i, j, k, b, c);
       double D = A.ev[i] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
-      acc += 2.0 * bv * bv / D;
+      acc += bv * bv * recip_fast(D);
     }
-  double s = block_sum(acc);
+  double s = block_sum(2.0 * acc);
   if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
@@ -579,12 +588,7 @@ __global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
         double bd = ((l < m) == (l < e)) ? t : -t;
         if (l < m && e == m) bd += cm * vll;
         const double bv = sg * bd;
-        // 1/D from the hardware estimate and two Newton steps (FP64 rounding level)
-        const double D = dq + A.ev[e];
-        double r = __builtin_amdgcn_rcp(D);
-        r = fma(fma(-D, r, 1.0), r, r);
-        r = fma(fma(-D, r, 1.0), r, r);
-        acc += bv * bv * r;
+        acc += bv * bv * recip_fast(dq + A.ev[e]);
       }
     }
   }
