@@ -1666,9 +1666,10 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
       hipLaunchKernelGGL(kd_gemv<192>, dim3(pa.jobs), dim3(256), 0, s, pa.gv, (const CgCtl*)ctl);
     hipLaunchKernelGGL(kd_arrow, dim3(h->nchunks), dim3(256), 0, s, aa, pt, (const int4*)h->chunks, h->pq_part,
                        (const CgCtl*)ctl);
-    hipLaunchKernelGGL(kd_finish_pq, dim3(1), dim3(1024), 0, s, (const double*)h->pq_part, h->nchunks, h->sc, ctl);
+    hipLaunchKernelGGL(kd_finish_pq, dim3(PQ_PARTS), dim3(1024), 0, s, (const double*)h->pq_part, h->nchunks, h->sc,
+                       ctl);
     hipLaunchKernelGGL(kd_update_r, dim3(NB), dim3(256), 0, s, h->r, (const double*)h->q, c.dinv32, n, d.off[1],
-                       d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl, c.b, first);
+                       d.off[2], (const double*)h->sc, h->partial, h->sc, (const CgCtl*)ctl, c.b, first);
     hipLaunchKernelGGL(kd_finish_r, dim3(2), dim3(1024), 0, s, (const double*)h->partial, (int)NB, h->sc, ctl, bn,
                        opts->tol, opts->max_iter);
     ESMP2_HIP(hipMemcpyAsync(&h->pin->cg[slot], ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));

@@ -7,7 +7,10 @@
 //
 // Control word (device memory), one iteration:
 //   pq finish    LAST -> DONE (the queued iteration after the last one);
-//                RUN: rho <- rho_new (from the second iteration on), <p, Ap>_W
+//                RUN: rho <- rho_new (from the second iteration on), eight
+//                partial sums of <p, Ap>_W (eight workgroups)
+//   update_r     RUN only; every workgroup adds the eight parts in one order
+//                (workgroup 0 also stores the sum for the later kernels)
 //   update_r     RUN only
 //   finish_r     RUN only: <r, M r>_W, <r, r>_W, then the test: p.Ap <= 0 ->
 //                DONE (not SPD); ||r||_W / ||b||_W <= tol or max_iter -> LAST
@@ -55,28 +58,39 @@ __global__ __launch_bounds__(256) void kd_arrow(ArrowArgs<double> A, PairTables 
   arrow_body<double>(A, P, chunks, pq, blockIdx.x, gridDim.x);
 }
 
-// one block
+// PQ_PARTS workgroups: part k of the arrow kernel's per-chunk parts into sc[SC_PQ8 + k]
 __global__ __launch_bounds__(1024) void kd_finish_pq(const double* pq, int nb, double* sc, CgCtl* c) {
   const int mode = c->mode;
   if (mode == CG_LAST) {
-    if (threadIdx.x == 0) c->mode = CG_DONE;
+    if (threadIdx.x == 0 && blockIdx.x == 0) c->mode = CG_DONE;
     return;
   }
   if (mode != CG_RUN) return;
-  if (threadIdx.x == 0 && c->it > 0) sc[SC_RHO] = sc[SC_RHO_NEW];
-  finish_body(pq, nb, sc, SC_PQ, 0, 1);
+  if (threadIdx.x == 0 && blockIdx.x == 0 && c->it > 0) sc[SC_RHO] = sc[SC_RHO_NEW];
+  const int lo = (int)((int64_t)nb * blockIdx.x / PQ_PARTS), hi = (int)((int64_t)nb * (blockIdx.x + 1) / PQ_PARTS);
+  finish_body(pq + lo, hi - lo, sc + SC_PQ8 + blockIdx.x, 0, 0, 1);
+}
+
+// <p, Ap>_W from its eight parts (the same order in every workgroup)
+__device__ inline double pq_sum(const double* sc) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < PQ_PARTS; ++k) s += sc[SC_PQ8 + k];
+  return s;
 }
 
 __global__ __launch_bounds__(256) void kd_update_r(double* r, const double* q, const float* dinv, int64_t n,
                                                    int64_t s0, int64_t s1, const double* sc, double* partial,
-                                                   const CgCtl* c, const double* b, int first) {
+                                                   double* scw, const CgCtl* c, const double* b, int first) {
   if (c->mode != CG_RUN) return;
+  const double pq = pq_sum(sc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) scw[SC_PQ] = pq;
+  const double alpha = sc[SC_RHO] / pq;
   if (!first) {
-    update_r_body<double>(r, q, dinv, n, s0, s1, sc, partial, blockIdx.x, gridDim.x);
+    update_r_body_a<double>(r, q, dinv, n, s0, s1, alpha, partial, blockIdx.x, gridDim.x);
     return;
   }
   // r = -b - alpha q (the same sums as update_r_body with r = -b)
-  const double alpha = sc[SC_RHO] / sc[SC_PQ];
   double rz = 0.0, rr = 0.0;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {

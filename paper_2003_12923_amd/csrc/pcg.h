@@ -3,6 +3,8 @@
 
 namespace esmp2 {
 enum { SC_RHO = 0, SC_PQ = 1, SC_RHO_NEW = 2, SC_RR = 3, SC_BX = 4, SC_XR = 5, SC_BB = 6, SC_TMP = 7, SC_N = 16 };
+// slots 8..15: the device-stopped solve's eight partial sums of <p, Ap>_W
+constexpr int SC_PQ8 = 8, PQ_PARTS = 8;
 constexpr int PCG_BLOCKS = 1024;
 
 template <class T> __global__ void k_dot(const T* x, const T* y, int64_t n, int64_t s0, int64_t s1, double* partial);

@@ -91,9 +91,9 @@ __global__ void k_finish(const double* partial, int nb, double* sc, int base) {
 // (two partial arrays of gridDim.x each).  x is updated with p in k_update_px,
 // which reads p anyway.
 template <class T>
-__device__ __attribute__((always_inline)) inline void update_r_body(T* r, const T* q, const float* dinv, int64_t n, int64_t s0,
-                                                  int64_t s1, const double* sc, double* partial, int bid_, int nb_) {
-  const T alpha = (T)(sc[SC_RHO] / sc[SC_PQ]);
+__device__ __attribute__((always_inline)) inline void update_r_body_a(T* r, const T* q, const float* dinv, int64_t n,
+                                                    int64_t s0, int64_t s1, T alpha, double* partial, int bid_,
+                                                    int nb_) {
   double rz = 0.0, rr = 0.0;
   const int64_t st = (int64_t)nb_ * blockDim.x;
   for (int64_t g0 = (int64_t)bid_ * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
@@ -119,6 +119,12 @@ __device__ __attribute__((always_inline)) inline void update_r_body(T* r, const 
   double a = block_sum(rz);
   double b = block_sum(rr);
   if (threadIdx.x == 0) { partial[bid_] = a; partial[nb_ + bid_] = b; }
+}
+
+template <class T>
+__device__ __attribute__((always_inline)) inline void update_r_body(T* r, const T* q, const float* dinv, int64_t n, int64_t s0,
+                                                  int64_t s1, const double* sc, double* partial, int bid_, int nb_) {
+  update_r_body_a<T>(r, q, dinv, n, s0, s1, (T)(sc[SC_RHO] / sc[SC_PQ]), partial, bid_, nb_);
 }
 
 template <class T>
