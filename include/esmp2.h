@@ -192,9 +192,12 @@ esmp2_status esmp2_space(esmp2_handle h, int64_t* n_amp, int64_t* box_offsets);
 
 /* Right-hand side b_mu = <mu|H|Psi0> on the seven boxes, E0 and the
  * S-triple energy E2_S = -sum_S b^2/D (paper Sec. II.B-II.D).
- *   b_out: device, n_amp doubles, or NULL (b is kept in the handle either way)
+ *   b_out: device, n_amp doubles, or NULL.  For n_top = 1 the TOP-basis b and
+ *   Jacobi diagonal are formed when b_out, a TOP-basis solve or the gradient
+ *   first needs them (a semicanonical solve builds its own b from the same
+ *   integral factors).
  *   e0, e2_s: host scalars or NULL.  The call synchronises the stream (the
- *   denominator check).  E2_S is summed on the handle's side stream, beside
+ *   denominator check: the smallest denominator, from the orbital energies).  E2_S is summed on the handle's side stream, beside
  *   the solve that follows; a non-NULL e2_s waits for it, with NULL it is
  *   waited for only by esmp2_solve, whose result reports it.
  * Returns ESMP2_NOT_SPD if a denominator of the first-order space is <= 0. */
@@ -266,9 +269,14 @@ esmp2_status esmp2_export_determinants(esmp2_handle h, const double* x, double* 
  * virtuals other than t' (Sec. II.B: an L-triple keeps t and t'), so the
  * operator is covariant and E2 unchanged; the solve runs after the rotation
  * that diagonalises those two Fock blocks, where the Jacobi preconditioner is
- * close to the operator.  The first such solve after build_rhs computes the
- * rotation (two small eigenproblems) and rotates b.  In both bases x0 and x_out
- * are amplitudes of the TOP basis (rotated on the way in and out). */
+ * close to the operator.  The rotation's eigenproblems are solved by
+ * esmp2_rotate_top on the side stream; the first such solve after build_rhs
+ * forms the operator blocks and builds b in the new basis from the rotated
+ * integral factors and singles amplitudes.  In FP64 the conjugate gradient
+ * decides convergence on the device and the host reads each iteration's
+ * outcome one iteration behind (one extra, empty iteration is queued after
+ * the last).  In both bases x0 and x_out are amplitudes of the TOP basis
+ * (rotated on the way in and out). */
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
                          esmp2_solve_result* result);
 
