@@ -188,3 +188,29 @@ def test_sigma_semicanonical_workloads(lib, name):
     res = h.solve(tol=1e-10, max_iter=300)
     assert res["status"] == 0 and abs(res["e2"] - GOLD[name]["e2"]) < 1e-10
     h.close()
+
+
+def test_semican_device_stop_paths(lib):
+    """The semicanonical FP64 solve decides its stop on the device: stopped
+    at max_iter = k it reports k iterations, NOT_CONVERGED and exactly the
+    residual the full run reached after k iterations (the same kernels up to
+    there); a tolerance met by the start (x = 0) stops before the first
+    iteration with E2 = E2_S; the full run matches the oracle (c1)."""
+    prob = synth.config_problem("c1")
+    h = _handle(lib, prob)
+    h.rotate_top()
+    sc = lib.ESMP2_BASIS_SEMICANONICAL
+    full = h.solve(tol=1e-12, max_iter=300, basis=sc, history=True)
+    hist = full["history"]
+    assert full["status"] == 0 and len(hist) == full["iterations"] >= 4
+    assert abs(full["e2"] - GOLD["c1"]["e2"]) < 1e-10
+    assert hist[-1] == full["rel_resid"] <= 1e-12
+    for k in (1, 2, 3):
+        r = h.solve(tol=1e-12, max_iter=k, basis=sc, history=True)
+        print(f"[stop at {k}] rel {r['rel_resid']:.6e} full run {hist[k - 1]:.6e}", flush=True)
+        assert r["status"] == lib.ESMP2_NOT_CONVERGED and r["iterations"] == k
+        assert r["rel_resid"] == hist[k - 1] and np.array_equal(r["history"], hist[:k])
+    r0 = h.solve(tol=2.0, max_iter=300, basis=sc)      # ||r0|| / ||b|| = 1 <= 2
+    assert r0["status"] == 0 and r0["iterations"] == 0 and r0["rel_resid"] == 1.0
+    assert r0["e2_dl"] == 0.0 and r0["e2"] == r0["e2_s"]
+    h.close()
