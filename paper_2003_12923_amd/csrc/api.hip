@@ -254,6 +254,20 @@ static unsigned launch_diag(esmp2_handle h, const DiagArgs& da) {
   return diag_grid(h->namp);
 }
 
+// The right-hand side kernel: by the coupling chunks where the table exists
+// (one large TOP), else one thread per flat position.
+template <bool GEN>
+static void launch_rhs(esmp2_handle h, const RhsArgs& ra, hipStream_t s) {
+  const Dims& d = h->d;
+  if (h->ntop == 1 && h->nchunks > 0) {
+    const int* pv = h->pairs;
+    const PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
+    hipLaunchKernelGGL(k_rhs_chunks<GEN>, dim3(h->nchunks), dim3(256), 0, s, ra, pt, (const int4*)h->chunks);
+  } else {
+    hipLaunchKernelGGL(k_rhs<GEN>, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
+  }
+}
+
 // Eigenpairs of a symmetric m x m matrix A (device, contiguous) by the
 // tridiagonal route of the AVO step: evals ascending, Y[i*m + k] = component i
 // of eigenvector k.  Scratch ws: 2 m^2 + 3 m doubles (m <= TRI_MAX).
@@ -877,7 +891,7 @@ static esmp2_status rhs_core(esmp2_handle h, const double* Ft, const double* Bov
   g.A = h->X; g.C = h->Mint;
   ESMP2_HIP(gemm(s, 1, g));
   RhsArgs ra{d, h->Vint, h->Mint, h->fphi, lam, b, nullptr};
-  hipLaunchKernelGGL(k_rhs<false>, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
+  launch_rhs<false>(h, ra, s);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
@@ -894,7 +908,7 @@ static esmp2_status ensure_b_top(esmp2_handle h) {
   g.sAi = 1; g.sAk = nov; g.sBk = nov; g.sBj = 1; g.sCi = nov; g.sCj = 1; g.alpha = 1; g.beta = 0;
   ESMP2_HIP(gemm(h->stream, 1, g));
   RhsArgs ra{d, h->Vint, h->Mint, h->fphi, h->lam, h->b, nullptr};
-  hipLaunchKernelGGL(k_rhs<false>, dim3(nblk(d.off[7])), dim3(256), 0, h->stream, ra);
+  launch_rhs<false>(h, ra, h->stream);
   DiagArgs da{d, h->eo, h->ev, h->omega, h->dinv32, h->blockmin};
   (void)launch_diag(h, da);
   ESMP2_HIP(hipGetLastError());
@@ -1380,7 +1394,7 @@ static esmp2_status rhs_semican(esmp2_handle h) {
   g.alpha = 1; g.beta = 0;
   ESMP2_HIP(gemm(s, 1, g));
   RhsArgs ra{d, h->dense0, h->dense1, fphi, h->lam, h->b_sc, Cs};
-  hipLaunchKernelGGL(k_rhs<true>, dim3(nblk(d.off[7])), dim3(256), 0, s, ra);
+  launch_rhs<true>(h, ra, s);
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }

@@ -110,14 +110,15 @@ __device__ inline int box_of(const Dims& d, int64_t g, int& loc) {
 // pinned-semicanonical one): every such term reads C[l][x].  The terms with a
 // pinned index (C[t][x] = c_0 [x = t'], C[l][t'] = c_0 [l = t]) keep their TOP
 // form in both.  V, M and fphi are tensors in (i, a): given in the new basis.
+// b of one amplitude of box `box` with occupied indices (P, Q) and virtual
+// indices (X, Y) in the box's own naming (actual orbitals): T2 and S2 (i, j,
+// a, b); T3 and H1P1 (j, k, b, c); H1P2 (j, k, a, c); H2P1 (i, k, b, c);
+// H2P2 (i, k, a, c).
 template <bool GEN>
-__global__ void k_rhs(RhsArgs A) {
+__device__ __attribute__((always_inline)) inline double rhs_element(const RhsArgs& A, int box, int P, int Q, int X,
+                                                                    int Y) {
   const Dims& d = A.d;
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= d.off[7]) return;
-  int loc;
-  int box = box_of(d, g, loc);
-  const int no = d.no, nv = d.nv, nov = no * nv;
+  const int nv = d.nv, nov = d.no * nv;
   const double s2 = 0.70710678118654752440;
   auto c = [&](int l) -> double { return A.lam[l] * s2; };
   // c_l [x = l'] (TOP) or C[l][x] (GEN); occupied l, virtual x
@@ -135,22 +136,17 @@ __global__ void k_rhs(RhsArgs A) {
   const double sg = (double)d.sg;
   switch (box) {
     case B_T2: {
-      int po = loc / d.npv, pv = loc % d.npv, i, j, a, b;
-      tri_pq(po, no, i, j); tri_pq(pv, nv, a, b);
+      const int i = P, j = Q, a = X, b = Y;
       out = m(i, j, a, b) - m(j, i, a, b) - m(i, j, b, a) + m(j, i, b, a);
       break;
     }
     case B_S2: {
-      int i = loc / (nov * nv), r = loc % (nov * nv);
-      int j = r / (nv * nv); r %= nv * nv;
-      int a = r / nv, b = r % nv;
+      const int i = P, j = Q, a = X, b = Y;
       out = m(i, j, a, b) + sg * m(j, i, b, a);        // second term: the beta singles
       break;
     }
     case B_T3: {
-      int po = loc / d.npv1, pv = loc % d.npv1, j, k, b, cc;
-      tri_pq(po, no - 1, j, k); tri_pq(pv, nv - 1, b, cc);
-      ++j; ++k; ++b; ++cc;
+      const int j = P, k = Q, b = X, cc = Y;
       auto E = [&](int kk, int x) { return V(0, 0, kk, x) - V(kk, 0, 0, x); };
       out = c0 * (V(j, b, k, cc) - V(k, b, j, cc));
       if (GEN) {
@@ -164,8 +160,7 @@ __global__ void k_rhs(RhsArgs A) {
       break;
     }
     case B_H11: {
-      int po = loc / d.npv, pv = loc % d.npv, j, k, b, cc;
-      tri_pq(po, no, j, k); tri_pq(pv, nv, b, cc);
+      const int j = P, k = Q, b = X, cc = Y;
       double o2 = 0.0;                                    // beta singles (down TOP pairs)
       if (GEN) {
         o2 = cx(j, b) * V(0, 0, k, cc) - cx(k, b) * V(0, 0, j, cc) - cx(j, cc) * V(0, 0, k, b)
@@ -180,10 +175,7 @@ __global__ void k_rhs(RhsArgs A) {
       break;
     }
     case B_H12: {
-      int m1 = nv - 1;
-      int po = loc / (m1 * m1), r = loc % (m1 * m1), j, k;
-      tri_pq(po, no, j, k);
-      int a = r / m1 + 1, cc = r % m1 + 1;
+      const int j = P, k = Q, a = X, cc = Y;
       if (j == 0) out += c0 * V(0, a, k, cc);            // all from the beta singles
       if (k == 0) out -= c0 * V(0, a, j, cc);
       if (GEN) {
@@ -196,9 +188,7 @@ __global__ void k_rhs(RhsArgs A) {
       break;
     }
     case B_H21: {
-      int o = loc / d.npv, pv = loc % d.npv, b, cc;
-      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-      tri_pq(pv, nv, b, cc);
+      const int i = P, k = Q, b = X, cc = Y;
       if (b == 0) out += c0 * V(i, 0, k, cc);            // all from the beta singles
       if (cc == 0) out -= c0 * V(i, 0, k, b);
       if (GEN) {
@@ -211,10 +201,7 @@ __global__ void k_rhs(RhsArgs A) {
       break;
     }
     default: {  // B_H22
-      int m1 = nv - 1;
-      int o = loc / (m1 * m1), r = loc % (m1 * m1);
-      int i = o / (no - 1) + 1, k = o % (no - 1) + 1;
-      int a = r / m1 + 1, cc = r % m1 + 1;
+      const int i = P, k = Q, a = X, cc = Y;
       double o2 = c0 * V(i, a, k, cc);                   // beta singles
       if (GEN) o2 += cx(k, cc) * V(i, a, 0, 0);
       else if (cc == k) o2 += c(k) * V(i, a, 0, 0);
@@ -224,7 +211,76 @@ __global__ void k_rhs(RhsArgs A) {
       break;
     }
   }
-  A.b[g] = out;
+  return out;
+}
+
+// one thread per amplitude, the indices decoded from the flat position
+template <bool GEN>
+__global__ void k_rhs(RhsArgs A) {
+  const Dims& d = A.d;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.off[7]) return;
+  int loc;
+  const int box = box_of(d, g, loc);
+  const int no = d.no, nv = d.nv, m1 = nv - 1;
+  int P, Q, X, Y;
+  switch (box) {
+    case B_T2: tri_pq(loc / d.npv, no, P, Q); tri_pq(loc % d.npv, nv, X, Y); break;
+    case B_S2: P = loc / (no * nv * nv); Q = (loc / (nv * nv)) % no; X = (loc / nv) % nv; Y = loc % nv; break;
+    case B_T3:
+      tri_pq(loc / d.npv1, no - 1, P, Q); tri_pq(loc % d.npv1, nv - 1, X, Y);
+      ++P; ++Q; ++X; ++Y;
+      break;
+    case B_H11: tri_pq(loc / d.npv, no, P, Q); tri_pq(loc % d.npv, nv, X, Y); break;
+    case B_H12: {
+      tri_pq(loc / (m1 * m1), no, P, Q);
+      const int r = loc % (m1 * m1);
+      X = r / m1 + 1; Y = r % m1 + 1;
+      break;
+    }
+    case B_H21: {
+      const int o = loc / d.npv;
+      P = o / (no - 1) + 1; Q = o % (no - 1) + 1;
+      tri_pq(loc % d.npv, nv, X, Y);
+      break;
+    }
+    default: {
+      const int o = loc / (m1 * m1), r = loc % (m1 * m1);
+      P = o / (no - 1) + 1; Q = o % (no - 1) + 1;
+      X = r / m1 + 1; Y = r % m1 + 1;
+      break;
+    }
+  }
+  A.b[g] = rhs_element<GEN>(A, box, P, Q, X, Y);
+}
+
+// The same by the coupling chunks (box, batch, inner range; 16 x 16 tiles of
+// (a, b) in S2, so that the transposed integral reads M[(j,b),(i,a)] come in
+// 128-byte runs): the occupied indices come with the chunk, the virtual pair
+// from the pair tables, no square roots.
+template <bool GEN>
+__global__ __launch_bounds__(256) void k_rhs_chunks(RhsArgs A, PairTables T, const int4* chunks) {
+  const Dims& d = A.d;
+  const int4 ch = chunks[blockIdx.x];
+  const int box = ch.x, batch = ch.y, P = ch.w >> 16, Q = ch.w & 0xffff;
+  const int nv = d.nv, m1 = nv - 1;
+  int inner;
+  switch (box) {
+    case B_T2: case B_H11: case B_H21: inner = d.npv; break;
+    case B_S2: inner = nv * nv; break;
+    case B_T3: inner = d.npv1; break;
+    default: inner = m1 * m1; break;
+  }
+  const int v = chunk_inner(box, ch.z, (int)threadIdx.x, nv, inner);
+  if (v >= inner) return;
+  int X, Y;
+  switch (box) {
+    case B_T2: case B_H11: case B_H21: { const int t = T.pv[v]; X = t >> 16; Y = t & 0xffff; break; }
+    case B_S2: X = v / nv; Y = v - X * nv; break;
+    case B_T3: { const int t = T.pv1[v]; X = (t >> 16) + 1; Y = (t & 0xffff) + 1; break; }
+    default: X = v / m1 + 1; Y = v - (X - 1) * m1 + 1; break;
+  }
+  __builtin_nontemporal_store(rhs_element<GEN>(A, box, P, Q, X, Y), A.b + d.off[box] + (int64_t)batch * inner + v);
 }
 
 // Singles amplitudes of Psi0 in a basis reached from the TOP one by the
@@ -242,6 +298,8 @@ __global__ void k_singles_sc(const double* To, const double* Tv, const double* l
 
 template __global__ void k_rhs<false>(RhsArgs);
 template __global__ void k_rhs<true>(RhsArgs);
+template __global__ void k_rhs_chunks<false>(RhsArgs, PairTables, const int4*);
+template __global__ void k_rhs_chunks<true>(RhsArgs, PairTables, const int4*);
 
 // Diagonal D_mu = (sum of particle minus hole orbital energies) - omega and its
 // inverse; also records the minimum (for the NOT_SPD check) per block.
