@@ -154,6 +154,8 @@ struct esmp2_handle_ {
   double* e2s_part = nullptr;
   hipEvent_t ev_rhs_ready = nullptr, ev_e2s = nullptr;
   hipEvent_t ev_cg[2] = {nullptr, nullptr};   // device-stopped solve: control word of iteration i copied (i % 2)
+  hipEvent_t ev_bz = nullptr;                 // side stream: B_vv V of the rotation done
+  double* Tz = nullptr;                       // B[Q][vir, vir] V, n_aux x n_vir x n_occ
   double* cgctl = nullptr;                    // its control word (a CgCtl)
   bool e2s_pending = false;      // queued on the side stream, not yet joined by the main stream
   bool e2s_dev = false;          // the sum is on the device, not yet read into e2s
@@ -339,6 +341,17 @@ static esmp2_status launch_sc_vir_early(esmp2_handle h) {
   double* refl = ws + 3 * v2;      // nv + 1
   double* tp = refl + 2 * nv;      // nv
   double* evals = tp + 2 * nv;     // m
+  // the rotation's B_vv V (the TOP virtuals V from the SVD; the AVOs are not
+  // needed): Tz[Q] = B[Q][vir, vir] V, first on the side stream
+  {
+    GemmArgs g{};
+    const int64_t nn = (int64_t)n * n;
+    g.A = h->B + (int64_t)no * n + no; g.B = h->V; g.C = h->Tz; g.M = nv; g.N = no; g.K = nv;
+    g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = no; g.sBj = 1; g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1;
+    g.alpha = 1; g.beta = 0;
+    ESMP2_HIP(gemm(s, d.naux, g));
+    ESMP2_HIP(hipEventRecord(h->ev_bz, s));
+  }
   hipLaunchKernelGGL(k_take_column, dim3(nblk(nv)), dim3(256), 0, s, (const double*)h->V, no, nv, tp);
   ESMP2_HIP(allow_device_lds((const void*)k_complement_qr));
   hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), sizeof(double) * 2 * (size_t)nv, s, (const double*)tp, nv,
@@ -423,10 +436,12 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
       hipEventCreateWithFlags(&h->ev_rhs_ready, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_e2s, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_cg[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_cg[1], hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->ev_cg[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_bz, hipEventDisableTiming) != hipSuccess) {
     if (h->aux) (void)hipStreamDestroy(h->aux);
     if (h->ev_cg[0]) (void)hipEventDestroy(h->ev_cg[0]);
     if (h->ev_cg[1]) (void)hipEventDestroy(h->ev_cg[1]);
+    if (h->ev_bz) (void)hipEventDestroy(h->ev_bz);
     if (h->ev_fock_ready) (void)hipEventDestroy(h->ev_fock_ready);
     if (h->ev_sc_eig) (void)hipEventDestroy(h->ev_sc_eig);
     if (h->ev_rhs_ready) (void)hipEventDestroy(h->ev_rhs_ready);
@@ -445,6 +460,7 @@ esmp2_status esmp2_create(esmp2_handle* out, int device, void* stream) {
       (void)hipEventDestroy(h->ev_e2s);
       (void)hipEventDestroy(h->ev_cg[0]);
       (void)hipEventDestroy(h->ev_cg[1]);
+      (void)hipEventDestroy(h->ev_bz);
       (void)hipHostFree(h->pin);
       delete h;
       return ESMP2_HIP_ERROR;
@@ -468,6 +484,7 @@ esmp2_status esmp2_destroy(esmp2_handle h) {
   (void)hipEventDestroy(h->ev_e2s);
   (void)hipEventDestroy(h->ev_cg[0]);
   (void)hipEventDestroy(h->ev_cg[1]);
+  (void)hipEventDestroy(h->ev_bz);
   (void)hipHostFree(h->pin);
   delete h;
   return ESMP2_OK;
@@ -544,6 +561,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
             dalloc(h, &h->evals, nv) && dalloc(h, &h->R, (size_t)n * n) &&
             dalloc(h, &h->avo, nv) && dalloc(h, &h->Ft, (size_t)n * n) &&
             dalloc(h, &h->T, std::max((size_t)na * no * nv, (size_t)n * n)) &&
+            dalloc(h, &h->Tz, (size_t)na * nv * no) &&
             dalloc(h, &h->Bov, (size_t)na * no * nv) && dalloc(h, &h->Bvt, (size_t)na * nv * no) &&
             dalloc(h, &h->Boo, (size_t)na * no * no) && dalloc(h, &h->iinfo, 8) && dalloc(h, &h->fo, no * no) &&
             dalloc(h, &h->fv, (size_t)nv * nv) && dalloc(h, &h->fov, (size_t)no * nv) && dalloc(h, &h->eo, no) &&
@@ -816,14 +834,10 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)no * nv; g.sBk = nv; g.sBj = 1;
     g.sCb = (int64_t)no * nv; g.sCi = nv; g.sCj = 1; g.alpha = 1; g.beta = 0;
     ESMP2_HIP(gemm(s, na, g));
-    // T[Q] (nv x no) = B[Q][vir, vir] W[:, :no]
+    // Tz[Q] = B[Q][vir, vir] W[:, :no] came from the side stream (W[:, :no] = V)
+    ESMP2_HIP(hipStreamWaitEvent(s, h->ev_bz, 0));
     g = GemmArgs{};
-    g.A = h->B + (int64_t)no * n + no; g.B = h->R + (int64_t)no * n + no; g.C = h->T; g.M = nv; g.N = no; g.K = nv;
-    g.sAb = nn; g.sAi = n; g.sAk = 1; g.sBb = 0; g.sBk = n; g.sBj = 1; g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1;
-    g.alpha = 1; g.beta = 0;
-    ESMP2_HIP(gemm(s, na, g));
-    g = GemmArgs{};
-    g.A = h->R + (int64_t)no * n + no; g.B = h->T; g.C = h->Bvt; g.M = nv; g.N = no; g.K = nv;
+    g.A = h->R + (int64_t)no * n + no; g.B = h->Tz; g.C = h->Bvt; g.M = nv; g.N = no; g.K = nv;
     g.sAb = 0; g.sAi = 1; g.sAk = n; g.sBb = (int64_t)nv * no; g.sBk = no; g.sBj = 1;
     g.sCb = (int64_t)nv * no; g.sCi = no; g.sCj = 1; g.alpha = 1; g.beta = 0;
     ESMP2_HIP(gemm(s, na, g));
