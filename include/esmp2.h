@@ -275,7 +275,9 @@ esmp2_status esmp2_export_determinants(esmp2_handle h, const double* x, double* 
  * integral factors and singles amplitudes.  In FP64 the conjugate gradient
  * decides convergence on the device and the host reads each iteration's
  * outcome one iteration behind (one extra, empty iteration is queued after
- * the last).  In both bases x0 and x_out are amplitudes of the TOP basis
+ * the last); from x0 = NULL with tol < 1 the kernel that builds b also forms
+ * the start (r = -b, its preconditioned copy and their two dots) and the host
+ * reads nothing before the first iteration.  In both bases x0 and x_out are amplitudes of the TOP basis
  * (rotated on the way in and out). */
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
                          esmp2_solve_result* result);

@@ -132,7 +132,8 @@ struct esmp2_handle_ {
   int* pairs = nullptr;          // (p << 16) | q tables: virtual pairs, shifted virtual, occupied, shifted occupied
   int4* chunks = nullptr;        // coupling kernel work: (box, batch, first inner index or S2 tile, (p << 16) | q)
   int nchunks = 0;
-  double* pq_part = nullptr;     // per-chunk parts of <p, Ap>_W
+  double* pq_part = nullptr;     // per-chunk parts of <p, Ap>_W (2 nchunks: also the fused CG start's two dots)
+  bool sc_init_ready = false;    // rhs_semican left the CG start from x = 0 in p and pq_part
   // Krylov vectors
   double *x, *r, *p, *q;
   // FP32 operator (Fock blocks rounded from the FP64 ones, work buffers) and
@@ -202,6 +203,7 @@ static void release(esmp2_handle h) {
   h->state = 0;
   h->have_rhs = false;
   h->have_sc = false;
+  h->sc_init_ready = false;
   h->have_sc_op = false;
   h->sc_pending = false;
   h->sc_eig = false;
@@ -655,7 +657,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
   }
   h->nchunks = (int)chunks.size();
   if (!dalloc(h, &h->jobs, jobs.size()) || !dalloc(h, &h->jobs4, j4.size()) || !dalloc(h, &h->pairs, pairs.size()) ||
-      !dalloc(h, &h->chunks, chunks.size()) || !dalloc(h, &h->pq_part, chunks.size())) {
+      !dalloc(h, &h->chunks, chunks.size()) || !dalloc(h, &h->pq_part, 2 * chunks.size())) {
     release(h);
     return fail(h, ESMP2_OOM, "device allocation failed");
   }
@@ -869,6 +871,7 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
   h->state = 2;
   h->have_rhs = false;
   h->have_sc = false;
+  h->sc_init_ready = false;
   h->have_sc_op = false;
   return ESMP2_OK;
 }
@@ -1008,6 +1011,7 @@ static esmp2_status build_rhs(esmp2_handle h) {
   if (!(h->pin->tmp[0] > 0.0)) return fail(h, ESMP2_NOT_SPD, "a diagonal denominator of the first-order space is <= 0");
   h->have_rhs = true;
   h->have_sc = false;
+  h->sc_init_ready = false;
   h->state = 3;
   return ESMP2_OK;
 }
@@ -1388,7 +1392,9 @@ static hipError_t rotate_ov(esmp2_handle h, int nq, const double* X, double* tmp
 // f^Phi (esmp2_build_rhs) and the rotation (semican_operator).  V and M go to
 // the dense scratch buffers (n_occ^2 n_vir^2 each): the TOP-basis V stays for
 // E2_S on the side stream.
-static esmp2_status rhs_semican(esmp2_handle h) {
+// With init, the kernel of b also starts the FP64 conjugate gradient from x = 0
+// (p and the parts of its two dots, for solve64).
+static esmp2_status rhs_semican(esmp2_handle h, bool init) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
   hipStream_t s = h->stream;
@@ -1408,19 +1414,22 @@ static esmp2_status rhs_semican(esmp2_handle h) {
   g.alpha = 1; g.beta = 0;
   ESMP2_HIP(gemm(s, 1, g));
   RhsArgs ra{d, h->dense0, h->dense1, fphi, h->lam, h->b_sc, Cs};
+  const bool fused = init && h->ntop == 1 && h->nchunks > 0;     // the chunk kernel
+  if (fused) { ra.dinv = h->dinv32_sc; ra.p = h->p; ra.part = h->pq_part; }
   launch_rhs<true>(h, ra, s);
+  h->sc_init_ready = fused;
   ESMP2_HIP(hipGetLastError());
   return ESMP2_OK;
 }
 
 // The operator of the pinned-semicanonical basis (if not built yet) and the
 // right-hand side in it.  Requires the right-hand side.
-static esmp2_status semican_setup(esmp2_handle h) {
+static esmp2_status semican_setup(esmp2_handle h, bool init = false) {
   if (!h->have_sc_op) {
     const esmp2_status st = semican_operator(h);
     if (st != ESMP2_OK) return st;
   }
-  const esmp2_status st = rhs_semican(h);
+  const esmp2_status st = rhs_semican(h, init);
   if (st != ESMP2_OK) return st;
   ESMP2_HIP(hipGetLastError());
   h->have_sc = true;
@@ -1669,9 +1678,12 @@ static esmp2_status finish_solve(esmp2_handle h, const OpCtx& c, const esmp2_sol
 // The FP64 iterations of solve64 in the pinned-semicanonical basis with the
 // stop decided on the device (cgdev.hip): iteration i + 1 is queued before the
 // host reads the control word of iteration i.  Starts from the state k_init
-// left (x = x0 or 0, r, p, rho); bn = ||b||_W.
+// (or the fused start of the right-hand side kernel) left: x = x0 or 0, r, p,
+// rho, and <r, r>_W in sc; ||b||_W^2 is in sc[SC_BB] for a start from x0.
+// rel0: the host's relative residual of the start, or (rel_on_device) the
+// device computes it and may stop before the first iteration.
 static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
-                                esmp2_solve_result* res, double bn, double rel0) {
+                                esmp2_solve_result* res, double rel0, bool rel_on_device) {
   const Dims& d = h->d;
   const int64_t n = h->namp;
   hipStream_t s = h->stream;
@@ -1682,9 +1694,10 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
   const ArrowArgs<double> aa{pa.ga, w.Fd, w.Fl, w.side_tr, h->gv};
   const int* pv = h->pairs;
   const PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
-  hipLaunchKernelGGL(kd_ctl_init, dim3(1), dim3(64), 0, s, ctl, rel0);
   // a solve from x = 0 leaves r and x unwritten at the start: the first iteration reads -b for r
   const int from_zero = opts->x0 ? 0 : 1;
+  hipLaunchKernelGGL(kd_ctl_init, dim3(1), dim3(64), 0, s, ctl, h->sc, from_zero, opts->tol, rel0,
+                     rel_on_device ? 1 : 0);
   auto enqueue = [&](int slot, int first) -> esmp2_status {
     hipLaunchKernelGGL(kd_sym, dim3(sym_s2_blocks(d)), dim3(256), 0, s, d, (const double*)h->p, w.S,
                        (const CgCtl*)ctl);
@@ -1698,7 +1711,7 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
                        ctl);
     hipLaunchKernelGGL(kd_update_r, dim3(NB), dim3(256), 0, s, h->r, (const double*)h->q, c.dinv32, n, d.off[1],
                        d.off[2], (const double*)h->sc, h->partial, h->sc, (const CgCtl*)ctl, c.b, first);
-    hipLaunchKernelGGL(kd_finish_r, dim3(2), dim3(1024), 0, s, (const double*)h->partial, (int)NB, h->sc, ctl, bn,
+    hipLaunchKernelGGL(kd_finish_r, dim3(2), dim3(1024), 0, s, (const double*)h->partial, (int)NB, h->sc, ctl,
                        opts->tol, opts->max_iter);
     ESMP2_HIP(hipMemcpyAsync(&h->pin->cg[slot], ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));
     ESMP2_HIP(hipEventRecord(h->ev_cg[slot], s));
@@ -1731,6 +1744,12 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
                          d.off[1], d.off[2], h->partial, h->x);
     return finish_solve(h, c, opts, res, last.rel, last.it, 0, status);
   }
+  if (last.it == 0) {                 // stopped at the start (b = 0): x = 0, r = -b
+    if (from_zero)
+      hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv32, n,
+                         d.off[1], d.off[2], h->partial, h->x);
+    return finish_solve(h, c, opts, res, last.rel, 0, 0, status);
+  }
   if (status == ESMP2_NOT_CONVERGED) h->err = "max_iter reached";
   // the Hylleraas dots from the parts of the last update
   hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, (const double*)h->partial, (int)NB, h->sc, (int)SC_BX);
@@ -1748,6 +1767,14 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   // start stores neither r nor x (the first iteration reads -b for r)
   const bool dev = c.arrow && h->nchunks > 0 && h->ntop == 1 && opts->max_iter > 0;
   const bool lazy = dev && !opts->x0;
+  // the right-hand side kernel has started this solve (p, the parts of its two
+  // dots); from x = 0 the relative residual is 1 (b != 0): no host read needed
+  const bool fused = lazy && c.rotated && h->sc_init_ready && opts->tol < 1.0;
+  h->sc_init_ready = false;
+  if (fused) {
+    hipLaunchKernelGGL(k_finish, dim3(2), dim3(1024), 0, s, (const double*)h->pq_part, h->nchunks, h->sc, SC_RHO);
+    return solve64_dev(h, c, opts, res, 0.0, true);
+  }
   if (opts->x0) {
     wdot(h, c.b, c.b, SC_BB);   // ||b||_W^2
     if (c.rotated) {
@@ -1772,7 +1799,7 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
   ESMP2_HIP(hipStreamSynchronize(s));
   const double bn = sqrt(opts->x0 ? hs[SC_BB] : hs[SC_PQ]);
   double rel = sqrt(hs[SC_PQ]) / bn;
-  if (dev && rel > opts->tol) return solve64_dev(h, c, opts, res, bn, rel);
+  if (dev && rel > opts->tol) return solve64_dev(h, c, opts, res, rel, false);
   if (lazy)      // converged at the start: x = 0 and r = -b for the Hylleraas dots
     hipLaunchKernelGGL(k_init, dim3(NB), dim3(256), 0, s, c.b, (const double*)nullptr, h->r, h->p, c.dinv32, n,
                        d.off[1], d.off[2], h->partial, h->x);
@@ -1810,6 +1837,7 @@ static esmp2_status solve64(esmp2_handle h, const OpCtx& c, const esmp2_solve_op
 // as it reaches the target; inner_tol bounds what an FP32 operator can deliver.
 static esmp2_status solve_mixed(esmp2_handle h, const OpCtx& c, const esmp2_solve_opts* opts,
                                 esmp2_solve_result* res) {
+  h->sc_init_ready = false;
   const Dims& d = h->d;
   const int64_t n = h->namp;
   hipStream_t s = h->stream;
@@ -1918,7 +1946,7 @@ esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts, esmp2_sol
   OpCtx c = ctx_top(h);
   if (opts->basis == ESMP2_BASIS_SEMICANONICAL) {
     if (!h->have_sc) {
-      esmp2_status st = semican_setup(h);
+      esmp2_status st = semican_setup(h, opts->precision == ESMP2_FP64 && !opts->x0);
       if (st != ESMP2_OK) { res->status = st; return st; }
     }
     c = ctx_sc(h);

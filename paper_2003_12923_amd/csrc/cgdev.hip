@@ -14,6 +14,7 @@
 //   update_r     RUN only
 //   finish_r     RUN only: <r, M r>_W, <r, r>_W, then the test: p.Ap <= 0 ->
 //                DONE (not SPD); ||r||_W / ||b||_W <= tol or max_iter -> LAST
+//                (||b||_W^2 in sc[SC_BB] from the start)
 //   update_px    RUN: x += alpha p, p = M r + beta p;  LAST: x += alpha p and
 //                the parts of the Hylleraas dots <b, x>_W, <x, r>_W
 // The first iteration of a solve from x = 0 (first = 1) takes r = -b and
@@ -32,12 +33,17 @@ struct CgCtl {
   double rel;     // last ||r||_W / ||b||_W
 };
 
-__global__ void kd_ctl_init(CgCtl* c, double rel0) {
+// The start: ||b||_W^2 into sc[SC_BB] (from <r, r>_W when r = -b), the
+// relative residual (from the host's value or from sc), RUN unless it is
+// already within tol (or not a number: b = 0).
+__global__ void kd_ctl_init(CgCtl* c, double* sc, int from_zero, double tol, double rel0, int rel_on_device) {
   if (threadIdx.x == 0) {
-    c->mode = CG_RUN;
+    if (from_zero) sc[SC_BB] = sc[SC_PQ];
+    const double rel = rel_on_device ? sqrt(sc[SC_PQ]) / sqrt(sc[SC_BB]) : rel0;
+    c->mode = rel > tol ? CG_RUN : CG_DONE;
     c->it = 0;
     c->status = ESMP2_OK;
-    c->rel = rel0;
+    c->rel = rel;
   }
 }
 
@@ -121,8 +127,8 @@ __global__ __launch_bounds__(256) void kd_update_r(double* r, const double* q, c
 // two blocks: sc[SC_RHO_NEW], sc[SC_RR]; block 1 then takes the decision.
 // Block 0 may read the control word after block 1 has changed it and skip
 // rho_new: no stopped state reads rho_new.
-__global__ __launch_bounds__(1024) void kd_finish_r(const double* partial, int nb, double* sc, CgCtl* c, double bn,
-                                                    double tol, int max_iter) {
+__global__ __launch_bounds__(1024) void kd_finish_r(const double* partial, int nb, double* sc, CgCtl* c, double tol,
+                                                    int max_iter) {
   if (c->mode != CG_RUN) return;
   finish_body(partial, nb, sc, SC_RHO_NEW, blockIdx.x, 2);
   if (blockIdx.x != 1 || threadIdx.x != 0) return;
@@ -133,7 +139,7 @@ __global__ __launch_bounds__(1024) void kd_finish_r(const double* partial, int n
     return;
   }
   const int it = c->it + 1;
-  const double rel = sqrt(sc[SC_RR]) / bn;
+  const double rel = sqrt(sc[SC_RR]) / sqrt(sc[SC_BB]);
   c->it = it;
   c->rel = rel;
   if (rel <= tol || it >= max_iter) {

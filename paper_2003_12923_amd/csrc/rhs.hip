@@ -92,6 +92,12 @@ struct RhsArgs {
   const double* lam;
   double* b;
   const double* Cs;     // GEN: singles amplitudes C[i][a] of Psi0 in the orbital basis of V, M, fphi (no x nv)
+  // the start of a conjugate gradient from x = 0 in the same pass (chunk kernel,
+  // when p is set): r = -b, p = dinv r, and per workgroup the parts of
+  // <r, dinv r>_W into part[blk] and of <r, r>_W into part[nblocks + blk]
+  const float* dinv = nullptr;
+  double* p = nullptr;
+  double* part = nullptr;
 };
 
 // Box and local index of a flat amplitude index.  A box holds fewer than 2^31
@@ -272,15 +278,32 @@ __global__ __launch_bounds__(256) void k_rhs_chunks(RhsArgs A, PairTables T, con
     default: inner = m1 * m1; break;
   }
   const int v = chunk_inner(box, ch.z, (int)threadIdx.x, nv, inner);
-  if (v >= inner) return;
-  int X, Y;
-  switch (box) {
-    case B_T2: case B_H11: case B_H21: { const int t = T.pv[v]; X = t >> 16; Y = t & 0xffff; break; }
-    case B_S2: X = v / nv; Y = v - X * nv; break;
-    case B_T3: { const int t = T.pv1[v]; X = (t >> 16) + 1; Y = (t & 0xffff) + 1; break; }
-    default: X = v / m1 + 1; Y = v - (X - 1) * m1 + 1; break;
+  const bool in = v < inner;
+  const int64_t g = d.off[box] + (int64_t)batch * inner + v;
+  double rz = 0.0, rr = 0.0;
+  if (in) {
+    const float dv = A.p ? A.dinv[g] : 0.0f;
+    int X, Y;
+    switch (box) {
+      case B_T2: case B_H11: case B_H21: { const int t = T.pv[v]; X = t >> 16; Y = t & 0xffff; break; }
+      case B_S2: X = v / nv; Y = v - X * nv; break;
+      case B_T3: { const int t = T.pv1[v]; X = (t >> 16) + 1; Y = (t & 0xffff) + 1; break; }
+      default: X = v / m1 + 1; Y = v - (X - 1) * m1 + 1; break;
+    }
+    const double bv = rhs_element<GEN>(A, box, P, Q, X, Y);
+    __builtin_nontemporal_store(bv, A.b + g);
+    if (A.p) {
+      const double rg = -bv, w = box == B_S2 ? 1.0 : 2.0;
+      __builtin_nontemporal_store((double)dv * rg, A.p + g);
+      rz = w * rg * rg * (double)dv;
+      rr = w * rg * rg;
+    }
   }
-  __builtin_nontemporal_store(rhs_element<GEN>(A, box, P, Q, X, Y), A.b + d.off[box] + (int64_t)batch * inner + v);
+  if (A.p) {               // the same for every workgroup of the launch
+    const double a = block_sum(rz);
+    const double c = block_sum(rr);
+    if (threadIdx.x == 0) { A.part[blockIdx.x] = a; A.part[gridDim.x + blockIdx.x] = c; }
+  }
 }
 
 // Singles amplitudes of Psi0 in a basis reached from the TOP one by the
