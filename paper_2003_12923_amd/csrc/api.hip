@@ -1321,9 +1321,10 @@ static esmp2_status rotate_amplitudes(esmp2_handle h, const double* x, double* y
 }
 
 // Rotation diagonalising F~_oo[1:,1:] and F~_vv[1:,1:], the operator blocks in
-// the new basis (TOP-basis omega and kappa) and its Jacobi diagonal.  Requires
-// the rotation to the TOP basis.
-static esmp2_status semican_operator(esmp2_handle h) {
+// the new basis (TOP-basis omega and kappa) and its Jacobi diagonal (unless the
+// right-hand side kernel that follows forms it: diag = false).  Requires the
+// rotation to the TOP basis.
+static esmp2_status semican_operator(esmp2_handle h, bool diag = true) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, n = d.n, mv = d.mv;
   const int64_t namp = d.off[7];
@@ -1355,8 +1356,10 @@ static esmp2_status semican_operator(esmp2_handle h) {
                      {(int64_t)mv * mv, (int64_t)mv * mv, (int64_t)no * no, (int64_t)nv * nv, (int64_t)no * nv}};
     hipLaunchKernelGGL(k_to_f32_set, dim3(nblk((int64_t)mv * mv)), dim3(256), 0, s, t);
   }
-  DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv32_sc, h->blockmin};
-  launch_diag(h, da);
+  if (diag) {
+    DiagArgs da{d, h->eo_sc, h->ev_sc, h->omega, h->dinv32_sc, h->blockmin};
+    launch_diag(h, da);
+  }
   ESMP2_HIP(hipGetLastError());
   h->have_sc_op = true;
   return ESMP2_OK;
@@ -1392,8 +1395,8 @@ static hipError_t rotate_ov(esmp2_handle h, int nq, const double* X, double* tmp
 // f^Phi (esmp2_build_rhs) and the rotation (semican_operator).  V and M go to
 // the dense scratch buffers (n_occ^2 n_vir^2 each): the TOP-basis V stays for
 // E2_S on the side stream.
-// With init, the kernel of b also starts the FP64 conjugate gradient from x = 0
-// (p and the parts of its two dots, for solve64).
+// With init, the kernel of b also forms the Jacobi diagonal and starts the FP64
+// conjugate gradient from x = 0 (p and the parts of its two dots, for solve64).
 static esmp2_status rhs_semican(esmp2_handle h, bool init) {
   const Dims& d = h->d;
   const int no = d.no, nv = d.nv, na = d.naux, nov = no * nv;
@@ -1415,7 +1418,10 @@ static esmp2_status rhs_semican(esmp2_handle h, bool init) {
   ESMP2_HIP(gemm(s, 1, g));
   RhsArgs ra{d, h->dense0, h->dense1, fphi, h->lam, h->b_sc, Cs};
   const bool fused = init && h->ntop == 1 && h->nchunks > 0;     // the chunk kernel
-  if (fused) { ra.dinv = h->dinv32_sc; ra.p = h->p; ra.part = h->pq_part; }
+  if (fused) {
+    ra.dinv = h->dinv32_sc; ra.p = h->p; ra.part = h->pq_part;
+    ra.eo = h->eo_sc; ra.ev = h->ev_sc; ra.omega = h->omega;
+  }
   launch_rhs<true>(h, ra, s);
   h->sc_init_ready = fused;
   ESMP2_HIP(hipGetLastError());
@@ -1426,7 +1432,8 @@ static esmp2_status rhs_semican(esmp2_handle h, bool init) {
 // right-hand side in it.  Requires the right-hand side.
 static esmp2_status semican_setup(esmp2_handle h, bool init = false) {
   if (!h->have_sc_op) {
-    const esmp2_status st = semican_operator(h);
+    // the right-hand side kernel forms the diagonal where it also starts the solve
+    const esmp2_status st = semican_operator(h, !(init && h->ntop == 1 && h->nchunks > 0));
     if (st != ESMP2_OK) return st;
   }
   const esmp2_status st = rhs_semican(h, init);

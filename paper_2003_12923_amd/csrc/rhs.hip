@@ -92,12 +92,17 @@ struct RhsArgs {
   const double* lam;
   double* b;
   const double* Cs;     // GEN: singles amplitudes C[i][a] of Psi0 in the orbital basis of V, M, fphi (no x nv)
-  // the start of a conjugate gradient from x = 0 in the same pass (chunk kernel,
-  // when p is set): r = -b, p = dinv r, and per workgroup the parts of
-  // <r, dinv r>_W into part[blk] and of <r, r>_W into part[nblocks + blk]
-  const float* dinv = nullptr;
+  // the Jacobi diagonal and the start of a conjugate gradient from x = 0 in the
+  // same pass (chunk kernel, when p is set): dinv = 1/D from the orbital
+  // energies eo, ev of this basis (as k_diag_chunks), r = -b, p = dinv r, and
+  // per workgroup the parts of <r, dinv r>_W into part[blk] and of <r, r>_W
+  // into part[nblocks + blk]
+  float* dinv = nullptr;
   double* p = nullptr;
   double* part = nullptr;
+  const double* eo = nullptr;
+  const double* ev = nullptr;
+  double omega = 0.0;
 };
 
 // Box and local index of a flat amplitude index.  A box holds fewer than 2^31
@@ -282,13 +287,19 @@ __global__ __launch_bounds__(256) void k_rhs_chunks(RhsArgs A, PairTables T, con
   const int64_t g = d.off[box] + (int64_t)batch * inner + v;
   double rz = 0.0, rr = 0.0;
   if (in) {
-    const float dv = A.p ? A.dinv[g] : 0.0f;
     int X, Y;
     switch (box) {
       case B_T2: case B_H11: case B_H21: { const int t = T.pv[v]; X = t >> 16; Y = t & 0xffff; break; }
       case B_S2: X = v / nv; Y = v - X * nv; break;
       case B_T3: { const int t = T.pv1[v]; X = (t >> 16) + 1; Y = (t & 0xffff) + 1; break; }
       default: X = v / m1 + 1; Y = v - (X - 1) * m1 + 1; break;
+    }
+    float dv = 0.0f;
+    if (A.p) {
+      const double D = box >= B_T3 ? (A.ev[0] - A.eo[0] - A.omega) + A.ev[X] + A.ev[Y] - A.eo[P] - A.eo[Q]
+                                   : A.ev[X] + A.ev[Y] - A.eo[P] - A.eo[Q] - A.omega;
+      dv = (float)(1.0 / D);
+      __builtin_nontemporal_store(dv, A.dinv + g);
     }
     const double bv = rhs_element<GEN>(A, box, P, Q, X, Y);
     __builtin_nontemporal_store(bv, A.b + g);
