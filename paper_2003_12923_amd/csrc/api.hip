@@ -564,13 +564,13 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
             dalloc(h, &h->avo, nv) && dalloc(h, &h->Ft, (size_t)n * n) &&
             dalloc(h, &h->T, std::max((size_t)na * no * nv, (size_t)n * n)) &&
             dalloc(h, &h->Tz, (size_t)na * nv * no) &&
-            dalloc(h, &h->Bov, (size_t)na * no * nv) && dalloc(h, &h->Bvt, (size_t)na * nv * no) &&
+            dalloc(h, &h->Bov, 2 * (size_t)na * no * nv) && dalloc(h, &h->Bvt, (size_t)na * nv * no) &&
             dalloc(h, &h->Boo, (size_t)na * no * no) && dalloc(h, &h->iinfo, 8) && dalloc(h, &h->fo, no * no) &&
             dalloc(h, &h->fv, (size_t)nv * nv) && dalloc(h, &h->fov, (size_t)no * nv) && dalloc(h, &h->eo, no) &&
             dalloc(h, &h->ev, nv) && dalloc(h, &h->Fd, (size_t)mv * mv) && dalloc(h, &h->Fl, (size_t)mv * mv) &&
             dalloc(h, &h->sc_rot, 8) && dalloc(h, &h->fphi, (size_t)no * nv) &&
             dalloc(h, &h->fphi_part, (size_t)FPHI_QCHUNKS * no * nv + na) &&
-            dalloc(h, &h->X, (size_t)na * no * nv) && dalloc(h, &h->Vint, (size_t)no * nv * no * nv) &&
+            dalloc(h, &h->Vint, (size_t)no * nv * no * nv) &&
             dalloc(h, &h->Mint, (size_t)no * nv * no * nv) && dalloc(h, &h->b, namp) &&
             dalloc(h, &h->blockmin, nblk(namp)) &&
             dalloc(h, &h->partial, (size_t)4 * PCG_BLOCKS) && dalloc(h, &h->sc, SC_N) &&
@@ -595,7 +595,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
        dalloc(h, &h->Fl32_sc, (size_t)mv * mv) && dalloc(h, &h->fo32_sc, no * no) &&
        dalloc(h, &h->fv32_sc, (size_t)nv * nv) && dalloc(h, &h->fov32_sc, (size_t)no * nv) &&
        dalloc(h, &h->dinv32_sc, namp) && dalloc(h, &h->dense0, 2 * dense) &&
-       dalloc(h, &h->rsc, (size_t)no * nv * (2 + 3 * (size_t)na)) &&
+       dalloc(h, &h->rsc, (size_t)no * nv * (2 + 4 * (size_t)na)) &&
        dalloc(h, &h->rs2, (size_t)10 * nv * nv + 8 * (size_t)nv) && dalloc(h, &h->cgctl, 4) &&
        dalloc(h, &h->gv, (size_t)nv * (2 * d.npo + 2 * no * no + (no - 1) * (no - 1)));
   if (n_top > 1)
@@ -603,6 +603,7 @@ static esmp2_status setup_problem(esmp2_handle h, int n_occ, int n_vir, int n_au
          dalloc(h, &h->Bov_s, (size_t)na * no * nv) && dalloc(h, &h->Bvt_s, (size_t)na * nv * no) &&
          dalloc(h, &h->Boo_s, (size_t)na * no * no) && dalloc(h, &h->lam_s, no) && dalloc(h, &h->btmp, d.off[7]);
   if (ok) h->dense1 = h->dense0 + dense;        // the second half of one allocation
+  if (ok) h->X = h->Bov + (size_t)na * no * nv;  // right after Bov: the two are rotated as one stack
   if (!ok) { release(h); return fail(h, ESMP2_OOM, "device allocation failed"); }
   // vv job table
   std::vector<int2> jobs;
@@ -1403,19 +1404,20 @@ static esmp2_status rhs_semican(esmp2_handle h, bool init) {
   hipStream_t s = h->stream;
   double* Cs = h->rsc;
   double* fphi = Cs + nov;
-  double* W = fphi + nov;                       // W[Q] = [Bov[Q] | X[Q]], 2 nov per Q
-  double* tmp = W + 2 * (size_t)na * nov;
+  double* W = fphi + nov;                       // [Bov; X] rotated: 2 na nov
+  double* tmp = W + 2 * (size_t)na * nov;       // 2 na nov
   hipLaunchKernelGGL(k_singles_sc, dim3(nblk(nov)), dim3(256), 0, s, (const double*)h->To, (const double*)h->Tv,
                      (const double*)h->lam, no, nv, Cs);
   ESMP2_HIP(rotate_ov(h, 1, h->fphi, tmp, fphi, nov));
-  ESMP2_HIP(rotate_ov(h, na, h->Bov, tmp, W, 2 * (int64_t)nov));
-  ESMP2_HIP(rotate_ov(h, na, h->X, tmp, W + nov, 2 * (int64_t)nov));
-  // [V; M] = [Bov | X]^T Bov in one product: V into dense0, M into dense1 = dense0 + nov^2
+  // X = Bov + na nov: both factors rotated as one stack of 2 na matrices
+  ESMP2_HIP(rotate_ov(h, 2 * na, h->Bov, tmp, W, nov));
+  // [V; M] = [Bov | X]^T Bov, two products in one call: V into dense0, M into dense1 = dense0 + nov^2
   GemmArgs g{};
-  g.A = W; g.B = W; g.C = h->dense0; g.M = 2 * nov; g.N = nov; g.K = na;
-  g.sAi = 1; g.sAk = 2 * (int64_t)nov; g.sBk = 2 * (int64_t)nov; g.sBj = 1; g.sCi = nov; g.sCj = 1;
+  g.A = W; g.B = W; g.C = h->dense0; g.M = nov; g.N = nov; g.K = na;
+  g.sAb = (int64_t)na * nov; g.sAi = 1; g.sAk = nov; g.sBb = 0; g.sBk = nov; g.sBj = 1;
+  g.sCb = (int64_t)nov * nov; g.sCi = nov; g.sCj = 1;
   g.alpha = 1; g.beta = 0;
-  ESMP2_HIP(gemm(s, 1, g));
+  ESMP2_HIP(gemm(s, 2, g));
   RhsArgs ra{d, h->dense0, h->dense1, fphi, h->lam, h->b_sc, Cs};
   const bool fused = init && h->ntop == 1 && h->nchunks > 0;     // the chunk kernel
   if (fused) {

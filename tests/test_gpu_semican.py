@@ -195,21 +195,30 @@ def test_semican_device_stop_paths(lib):
     at max_iter = k it reports k iterations, NOT_CONVERGED and exactly the
     residual the full run reached after k iterations (the same kernels up to
     there); a tolerance met by the start (x = 0) stops before the first
-    iteration with E2 = E2_S; the full run matches the oracle (c1)."""
+    iteration with E2 = E2_S; the full run matches the oracle (c1).  Every
+    run but the last two starts right after the right-hand side is built, so
+    that all take the start the right-hand side kernel forms; a second solve
+    on the same b starts through k_init (other partial sums: equal to
+    rounding)."""
     prob = synth.config_problem("c1")
     h = _handle(lib, prob)
     h.rotate_top()
     sc = lib.ESMP2_BASIS_SEMICANONICAL
+    h.build_rhs()
     full = h.solve(tol=1e-12, max_iter=300, basis=sc, history=True)
     hist = full["history"]
     assert full["status"] == 0 and len(hist) == full["iterations"] >= 4
     assert abs(full["e2"] - GOLD["c1"]["e2"]) < 1e-10
     assert hist[-1] == full["rel_resid"] <= 1e-12
     for k in (1, 2, 3):
+        h.build_rhs()
         r = h.solve(tol=1e-12, max_iter=k, basis=sc, history=True)
         print(f"[stop at {k}] rel {r['rel_resid']:.6e} full run {hist[k - 1]:.6e}", flush=True)
         assert r["status"] == lib.ESMP2_NOT_CONVERGED and r["iterations"] == k
         assert r["rel_resid"] == hist[k - 1] and np.array_equal(r["history"], hist[:k])
+    r2 = h.solve(tol=1e-12, max_iter=300, basis=sc, history=True)     # same b: the k_init start
+    assert r2["status"] == 0 and abs(r2["e2"] - full["e2"]) < 1e-12
+    assert np.allclose(r2["history"][:4], hist[:4], rtol=1e-10, atol=0)
     r0 = h.solve(tol=2.0, max_iter=300, basis=sc)      # ||r0|| / ||b|| = 1 <= 2
     assert r0["status"] == 0 and r0["iterations"] == 0 and r0["rel_resid"] == 1.0
     assert r0["e2_dl"] == 0.0 and r0["e2"] == r0["e2_s"]
