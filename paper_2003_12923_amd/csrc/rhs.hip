@@ -622,65 +622,90 @@ __device__ inline double b_mixed(const E2sArgs& A, int i, int a, int j, int k, i
   return bv;
 }
 
-// grid (x, y): y walks the up hole i >= 1 of the up TOP pair, x the chunks of
-// 256 (b<c) pairs of one (j<k) pair (grid-stride in x)
+// The grid's workgroups stride over the chunks of 256 (b<c) pairs of one (j<k)
+// pair; a lane loads the pair's antisymmetrised integral once and runs over the
+// up hole i >= 1 of the up TOP pair (a = i), which enters only through lam_i,
+// the denominator and the rare Kronecker terms of b_mixed.
 __global__ __launch_bounds__(256) void k_e2s_mixed_a(E2sArgs A) {
   const Dims& d = A.d;
-  const int no = d.no;
+  const int no = d.no, nv = d.nv, nov = no * nv;
   const int nch = (d.npv + 255) / 256, nt = d.npo * nch;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x, nb = gridDim.x * gridDim.y;
+  const double s2 = 0.70710678118654752440;
+  auto V = [&](int p, int x, int q, int y) { return A.V[(int64_t)(p * nv + x) * nov + q * nv + y]; };
   double acc = 0.0;
-  for (int i = 1 + blockIdx.y; i < no; i += gridDim.y)
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-      const int pi = t / nch, vi = (t - pi * nch) * 256 + (int)threadIdx.x;
-      if (vi >= d.npv) continue;
-      const int to = A.po[pi], tv = A.pv[vi];
-      const int j = to >> 16, k = to & 0xffff, b = tv >> 16, c = tv & 0xffff;
-      if ((j == 0 || k == 0) && (b == 0 || c == 0)) continue;     // contains t
-      double bv = b_mixed(A, i, i, j, k, b, c);
-      double D = A.ev[i] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+  for (int t = bid; t < nt; t += nb) {
+    const int pi = t / nch, vi = (t - pi * nch) * 256 + (int)threadIdx.x;
+    if (vi >= d.npv) continue;
+    const int to = A.po[pi], tv = A.pv[vi];
+    const int j = to >> 16, k = to & 0xffff, b = tv >> 16, c = tv & 0xffff;
+    if ((j == 0 || k == 0) && (b == 0 || c == 0)) continue;     // contains t
+    const double vd = V(j, b, k, c) - V(k, b, j, c);
+    const bool kron = b == j || b == k || c == j || c == k;
+    for (int i = 1; i < no; ++i) {
+      const double bv = kron ? b_mixed(A, i, i, j, k, b, c) : A.lam[i] * s2 * vd;
+      const double D = A.ev[i] + A.ev[b] + A.ev[c] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
       acc += bv * bv * recip_fast(D);
     }
+  }
   double s = block_sum(2.0 * acc);
   if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
-// grid (x, y): y walks the up excitation (i, a), a != i; a wavefront takes one
-// (l, m) pair of down holes (uniform: no index decode per item), its lanes the
-// down particle e != l' (holes {l, m}, particles {l', e}).  With a != i only
-// the beta singles of b_mixed enter, and with the holes and particles sharing
-// l their four Kronecker terms reduce to
+// A wavefront per (up excitation (i, a), a != i; down hole m), the grid's
+// wavefronts striding over these pairs; its lanes take the down particles e
+// (64 at a time), whose integrals V(i a|m e) it loads once for every other
+// down hole l (holes {l, m}, particles {l', e}, e != l).  With a != i only the
+// beta singles of b_mixed enter, and with the holes and particles sharing l
+// their four Kronecker terms reduce to
 //   bd = s lam_l V(i a|m e) + [l < m, e = m] lam_m V(i a|l l),
 //   s = +1 if (l < m) == (l < e), else -1
-// (the case m < l, e = m belongs to the smaller TOP m and is skipped).
+// (the case m < l, e = m belongs to the smaller TOP m and is skipped; l = 0
+// with t' among the particles is an L-triple).
 __global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
   const Dims& d = A.d;
-  const int no = d.no, nv = d.nv, o1 = no - 1, v1 = nv - 1, nov = no * nv;
+  const int no = d.no, nv = d.nv, nov = no * nv;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  const int nq = no * o1;                              // q = l * (no-1) + mr
+  const int64_t nitem = (int64_t)nov * no;             // item = (i a) * no + m
+  const int64_t gw = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * nw + wave;
+  const int64_t NW = (int64_t)gridDim.x * gridDim.y * nw;
   const double s2 = 0.70710678118654752440, sg = (double)d.sg;
+  constexpr int EU = 3;                                // particles per lane in registers (64 EU per pass)
   double acc = 0.0;
-  for (int ia = blockIdx.y; ia < no * nv; ia += gridDim.y) {
+  for (int64_t it = gw; it < nitem; it += NW) {
+    const int ia = (int)(it / no), m = (int)(it - (int64_t)ia * no);
     const int i = ia / nv, a = ia - i * nv;
     if (a == i) continue;
     const double* Vr = A.V + (int64_t)ia * nov;        // row (i, a) of V
-    for (int q = blockIdx.x * nw + wave; q < nq; q += gridDim.x * nw) {
-      const int l = q / o1, mr = q - l * o1;
-      const int m = mr + (mr >= l);
-      const int j = l < m ? l : m, k = l < m ? m : l;
-      const bool t_hole = i == 0 || l == 0 || m == 0;
-      const double cl = A.lam[l] * s2, cm = A.lam[m] * s2;
-      const double vll = Vr[l * nv + l];
-      // D = dq + ev[e]: the particles are {a, l', e}, the holes {i, l, m}
-      const double dq = A.ev[a] + A.ev[l] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
-      for (int er = lane; er < v1; er += 64) {
-        const int e = er + (er >= l);
-        if (m < l && e == m) continue;                              // smaller down TOP m
-        if (t_hole && (a == 0 || l == 0 || e == 0)) continue;       // contains t
-        const double t = cl * Vr[m * nv + e];
-        double bd = ((l < m) == (l < e)) ? t : -t;
-        if (l < m && e == m) bd += cm * vll;
-        const double bv = sg * bd;
-        acc += bv * bv * recip_fast(dq + A.ev[e]);
+    const bool t_hole = i == 0 || m == 0;              // with l >= 1
+    const double cm = A.lam[m] * s2;
+    for (int e0 = 0; e0 < nv; e0 += 64 * EU) {
+      double vme[EU], eve[EU];
+#pragma unroll
+      for (int u = 0; u < EU; ++u) {
+        const int e = e0 + lane + 64 * u;
+        vme[u] = e < nv ? Vr[m * nv + e] : 0.0;
+        eve[u] = e < nv ? A.ev[e] : 0.0;
+      }
+      for (int l = 1; l < no; ++l) {
+        if (l == m) continue;
+        const int j = l < m ? l : m, k = l < m ? m : l;
+        const double cl = A.lam[l] * s2;
+        const double vll = Vr[l * nv + l];
+        // D = dq + ev[e]: the particles are {a, l', e}, the holes {i, l, m}
+        const double dq = A.ev[a] + A.ev[l] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
+#pragma unroll
+        for (int u = 0; u < EU; ++u) {
+          const int e = e0 + lane + 64 * u;
+          if (e >= nv || e == l) continue;
+          if (m < l && e == m) continue;                              // smaller down TOP m
+          if (t_hole && (a == 0 || e == 0)) continue;                 // contains t
+          const double t = cl * vme[u];
+          double bd = ((l < m) == (l < e)) ? t : -t;
+          if (l < m && e == m) bd += cm * vll;
+          const double bv = sg * bd;
+          acc += bv * bv * recip_fast(dq + eve[u]);
+        }
       }
     }
   }
