@@ -566,40 +566,66 @@ __device__ inline void sort3(int& x, int& y, int& z) {
   if (x > y) { int t = x; x = y; y = t; }
 }
 
-// grid (x, y): y walks the smallest TOP l >= 1, x the chunks of 256 (b<c)
-// pairs of one (j<k) pair, both excluding l (grid-stride in x): the occupied
-// pair is uniform in a workgroup, a lane takes one virtual pair.
+// b of the same-spin triple {l, j, k; l', b, c} from every contained TOP pair
+__device__ inline double b_same(const E2sArgs& A, int l, int j, int k, int b, int c) {
+  const int nv = A.d.nv, nov = A.d.no * nv;
+  const double s2 = 0.70710678118654752440;
+  int I[3] = {l, j, k}, P[3] = {l, b, c};
+  sort3(I[0], I[1], I[2]);
+  sort3(P[0], P[1], P[2]);
+  double bv = 0.0;
+  for (int p = 0; p < 3; ++p)
+    for (int q = 0; q < 3; ++q) {
+      if (P[p] != I[q]) continue;
+      int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
+      int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
+      double anti = A.V[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2] -
+                    A.V[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2];
+      double sg = ((p + q) & 1) ? -1.0 : 1.0;
+      bv += sg * A.lam[I[q]] * s2 * anti;
+    }
+  return bv;
+}
+
+// The grid's workgroups stride over the chunks of 256 (b<c) pairs of one (j<k)
+// pair (all orbitals); a lane runs over the smallest TOP l >= 1 outside both
+// pairs.  Unless b or c is one of j, k, the one contained TOP pair is (l, l'),
+// whose integral <j b||k c> does not depend on l: loaded once, then only the
+// sign (positions of l among the sorted holes and particles), lam_l and the
+// denominator change with l.
 __global__ __launch_bounds__(256) void k_e2s_same(E2sArgs A) {
   const Dims& d = A.d;
   const int no = d.no, nv = d.nv, nov = no * nv;
-  const int nch = (d.npv1 + 255) / 256, nt = d.npo1 * nch;
+  const int nch = (d.npv + 255) / 256, nt = d.npo * nch;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x, nb = gridDim.x * gridDim.y;
   const double s2 = 0.70710678118654752440;
   double acc = 0.0;
-  for (int l = 1 + blockIdx.y; l < no; l += gridDim.y)
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-      const int pi = t / nch, vi = (t - pi * nch) * 256 + (int)threadIdx.x;
-      if (vi >= d.npv1) continue;
-      const int to = A.po1[pi], tv = A.pv1[vi];
-      const int jr = to >> 16, kr = to & 0xffff, br = tv >> 16, cr = tv & 0xffff;
-      const int j = jr + (jr >= l), k = kr + (kr >= l), b = br + (br >= l), c = cr + (cr >= l);
-      if ((j < l && (j == b || j == c)) || (k < l && (k == b || k == c))) continue;
+  for (int t = bid; t < nt; t += nb) {
+    const int pi = t / nch, vi = (t - pi * nch) * 256 + (int)threadIdx.x;
+    if (vi >= d.npv) continue;
+    const int to = A.po[pi], tv = A.pv[vi];
+    const int j = to >> 16, k = to & 0xffff, b = tv >> 16, c = tv & 0xffff;
+    const bool kron = b == j || b == k || c == j || c == k;
+    const double anti = kron ? 0.0
+                             : A.V[(int64_t)(j * nv + b) * nov + k * nv + c] -
+                               A.V[(int64_t)(k * nv + b) * nov + j * nv + c];
+    for (int l = 1; l < no; ++l) {
+      if (l == j || l == k || l == b || l == c) continue;
+      if ((j < l && (j == b || j == c)) || (k < l && (k == b || k == c))) continue;   // a smaller TOP
       int I[3] = {l, j, k}, P[3] = {l, b, c};
       sort3(I[0], I[1], I[2]);
       sort3(P[0], P[1], P[2]);
-      double bv = 0.0;
-      for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) {
-          if (P[p] != I[q]) continue;
-          int a1 = P[p == 0 ? 1 : 0], a2 = P[p == 2 ? 1 : 2];
-          int i1 = I[q == 0 ? 1 : 0], i2 = I[q == 2 ? 1 : 2];
-          double anti = A.V[(int64_t)(i1 * nv + a1) * nov + i2 * nv + a2] -
-                        A.V[(int64_t)(i2 * nv + a1) * nov + i1 * nv + a2];
-          double sg = ((p + q) & 1) ? -1.0 : 1.0;
-          bv += sg * A.lam[I[q]] * s2 * anti;
-        }
+      double bv;
+      if (kron) {
+        bv = b_same(A, l, j, k, b, c);
+      } else {
+        const int pp = (l > b) + (l > c), qq = (l > j) + (l > k);    // positions of l
+        bv = (((pp + qq) & 1) ? -1.0 : 1.0) * A.lam[l] * s2 * anti;
+      }
       double D = A.ev[P[0]] + A.ev[P[1]] + A.ev[P[2]] - A.eo[I[0]] - A.eo[I[1]] - A.eo[I[2]] - A.omega;
       acc += bv * bv * recip_fast(D);
     }
+  }
   double s = block_sum(2.0 * acc);
   if (threadIdx.x == 0) A.partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
