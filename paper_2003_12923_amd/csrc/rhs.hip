@@ -705,6 +705,9 @@ __global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
     const double* Vr = A.V + (int64_t)ia * nov;        // row (i, a) of V
     const bool t_hole = i == 0 || m == 0;              // with l >= 1
     const double cm = A.lam[m] * s2;
+    // V(i a|l l) of every l, one per lane, loaded together (read back per l by
+    // a lane broadcast: a load per l would wait once per iteration)
+    const double vll_lane = lane < no ? Vr[lane * nv + lane] : 0.0;
     for (int e0 = 0; e0 < nv; e0 += 64 * EU) {
       double vme[EU], eve[EU];
 #pragma unroll
@@ -717,7 +720,10 @@ __global__ __launch_bounds__(256) void k_e2s_mixed_b(E2sArgs A) {
         if (l == m) continue;
         const int j = l < m ? l : m, k = l < m ? m : l;
         const double cl = A.lam[l] * s2;
-        const double vll = Vr[l * nv + l];
+        const long long vb = __double_as_longlong(vll_lane);
+        const double vll = __longlong_as_double(
+            ((long long)__builtin_amdgcn_readlane((int)(vb >> 32), l) << 32) |
+            (unsigned)__builtin_amdgcn_readlane((int)(vb & 0xffffffff), l));
         // D = dq + ev[e]: the particles are {a, l', e}, the holes {i, l, m}
         const double dq = A.ev[a] + A.ev[l] - A.eo[i] - A.eo[j] - A.eo[k] - A.omega;
 #pragma unroll
