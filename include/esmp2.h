@@ -277,7 +277,11 @@ esmp2_status esmp2_export_determinants(esmp2_handle h, const double* x, double* 
  * outcome one iteration behind (one extra, empty iteration is queued after
  * the last); from x0 = NULL with tol < 1 the kernel that builds b also forms
  * the start (r = -b, its preconditioned copy and their two dots) and the host
- * reads nothing before the first iteration.  In both bases x0 and x_out are amplitudes of the TOP basis
+ * reads nothing before the first iteration.  From x0 = NULL without x_out no x
+ * is formed: E2_DL is the Hylleraas value of the iterates accumulated from the
+ * solve's scalars, -sum_i alpha_i rho_i (for conjugate gradient from zero
+ * <b, p_i>_W = -rho_i and <x_k, r_k>_W = 0; equal to the value from x to
+ * rounding).  In both bases x0 and x_out are amplitudes of the TOP basis
  * (rotated on the way in and out). */
 esmp2_status esmp2_solve(esmp2_handle h, const esmp2_solve_opts* opts,
                          esmp2_solve_result* result);

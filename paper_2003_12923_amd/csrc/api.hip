@@ -1705,6 +1705,8 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
   const PairTables pt{pv, pv + d.npv, pv + d.npv + d.npv1, pv + d.npv + d.npv1 + d.npo};
   // a solve from x = 0 leaves r and x unwritten at the start: the first iteration reads -b for r
   const int from_zero = opts->x0 ? 0 : 1;
+  // from x = 0 without x_out no x is kept: E2_DL from the iterates' scalars (cgdev.hip)
+  const int no_x = (from_zero && !opts->x_out) ? 1 : 0;
   hipLaunchKernelGGL(kd_ctl_init, dim3(1), dim3(64), 0, s, ctl, h->sc, from_zero, opts->tol, rel0,
                      rel_on_device ? 1 : 0);
   auto enqueue = [&](int slot, int first) -> esmp2_status {
@@ -1719,13 +1721,13 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
     hipLaunchKernelGGL(kd_finish_pq, dim3(PQ_PARTS), dim3(1024), 0, s, (const double*)h->pq_part, h->nchunks, h->sc,
                        ctl);
     hipLaunchKernelGGL(kd_update_r, dim3(NB), dim3(256), 0, s, h->r, (const double*)h->q, c.dinv32, n, d.off[1],
-                       d.off[2], (const double*)h->sc, h->partial, h->sc, (const CgCtl*)ctl, c.b, first);
+                       d.off[2], (const double*)h->sc, h->partial, h->sc, (const CgCtl*)ctl, c.b, first, no_x);
     hipLaunchKernelGGL(kd_finish_r, dim3(2), dim3(1024), 0, s, (const double*)h->partial, (int)NB, h->sc, ctl,
                        opts->tol, opts->max_iter);
     ESMP2_HIP(hipMemcpyAsync(&h->pin->cg[slot], ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, s));
     ESMP2_HIP(hipEventRecord(h->ev_cg[slot], s));
     hipLaunchKernelGGL(kd_update_px, dim3(NB), dim3(256), 0, s, h->x, h->p, (const double*)h->r, c.b, c.dinv32, n,
-                       d.off[1], d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl, first);
+                       d.off[1], d.off[2], (const double*)h->sc, h->partial, (const CgCtl*)ctl, first, no_x);
     ESMP2_HIP(hipGetLastError());
     return ESMP2_OK;
   };
@@ -1745,6 +1747,11 @@ static esmp2_status solve64_dev(esmp2_handle h, const OpCtx& c, const esmp2_solv
   esmp2_status status = (esmp2_status)last.status;
   if (last.mode == CG_RUN) {                  // not reached: the device stops at max_iter
     status = ESMP2_NOT_CONVERGED;
+  }
+  if (no_x) {    // sc[SC_BX] holds the sum over the iterations (0 before the first), sc[SC_XR] = 0
+    if (status == ESMP2_NOT_SPD) h->err = "p.Ap <= 0 in conjugate gradient";
+    else if (status == ESMP2_NOT_CONVERGED) h->err = "max_iter reached";
+    return finish_solve(h, c, opts, res, last.rel, last.it, 0, status, true);
   }
   if (status == ESMP2_NOT_SPD) {
     h->err = "p.Ap <= 0 in conjugate gradient";

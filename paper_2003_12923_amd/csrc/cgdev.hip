@@ -19,6 +19,11 @@
 //                the parts of the Hylleraas dots <b, x>_W, <x, r>_W
 // The first iteration of a solve from x = 0 (first = 1) takes r = -b and
 // x = alpha p without reading r or x: the start stores neither.
+// A solve from x = 0 whose x nobody reads (no_x) keeps no x at all: for the
+// iterates of conjugate gradient from zero <b, p_i>_W = -rho_i and
+// <x_k, r_k>_W = 0, so the Hylleraas value <b, x>_W - <x, r>_W is the sum
+// -sum_i alpha_i rho_i, which update_r adds up in sc[SC_BX] (sc[SC_XR] = 0);
+// update_px then writes p only and the last update has nothing to do.
 #include "common.h"
 #include "sigma.h"
 #include "pcg.h"
@@ -38,6 +43,8 @@ struct CgCtl {
 // already within tol (or not a number: b = 0).
 __global__ void kd_ctl_init(CgCtl* c, double* sc, int from_zero, double tol, double rel0, int rel_on_device) {
   if (threadIdx.x == 0) {
+    sc[SC_BX] = 0.0;
+    sc[SC_XR] = 0.0;
     if (from_zero) sc[SC_BB] = sc[SC_PQ];
     const double rel = rel_on_device ? sqrt(sc[SC_PQ]) / sqrt(sc[SC_BB]) : rel0;
     c->mode = rel > tol ? CG_RUN : CG_DONE;
@@ -87,11 +94,15 @@ __device__ inline double pq_sum(const double* sc) {
 
 __global__ __launch_bounds__(256) void kd_update_r(double* r, const double* q, const float* dinv, int64_t n,
                                                    int64_t s0, int64_t s1, const double* sc, double* partial,
-                                                   double* scw, const CgCtl* c, const double* b, int first) {
+                                                   double* scw, const CgCtl* c, const double* b, int first,
+                                                   int no_x) {
   if (c->mode != CG_RUN) return;
   const double pq = pq_sum(sc);
-  if (blockIdx.x == 0 && threadIdx.x == 0) scw[SC_PQ] = pq;
   const double alpha = sc[SC_RHO] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scw[SC_PQ] = pq;
+    if (no_x && pq > 0.0) scw[SC_BX] -= alpha * sc[SC_RHO];   // Hylleraas value of the iterates
+  }
   if (!first) {
     update_r_body_a<double>(r, q, dinv, n, s0, s1, alpha, partial, blockIdx.x, gridDim.x);
     return;
@@ -150,8 +161,29 @@ __global__ __launch_bounds__(1024) void kd_finish_r(const double* partial, int n
 
 __global__ __launch_bounds__(256) void kd_update_px(double* x, double* p, const double* r, const double* b,
                                                     const float* dinv, int64_t n, int64_t s0, int64_t s1,
-                                                    const double* sc, double* partial, const CgCtl* c, int first) {
+                                                    const double* sc, double* partial, const CgCtl* c, int first,
+                                                    int no_x) {
   const int mode = c->mode;
+  if (no_x) {            // p = M r + beta p only
+    if (mode != CG_RUN) return;
+    const double beta = sc[SC_RHO_NEW] / sc[SC_RHO];
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+      double pv[PCG_U], rv[PCG_U];
+      float dv[PCG_U];
+#pragma unroll
+      for (int u = 0; u < PCG_U; ++u) {
+        const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+        pv[u] = ldnt(p + gg); rv[u] = ldnt(r + gg); dv[u] = ldnt(dinv + gg);
+      }
+#pragma unroll
+      for (int u = 0; u < PCG_U; ++u) {
+        const int64_t g = g0 + u * st;
+        if (g < n) stnt((double)dv[u] * rv[u] + beta * pv[u], p + g);
+      }
+    }
+    return;
+  }
   if (mode == CG_RUN && !first) {
     update_px_body<double>(x, p, r, dinv, n, sc, blockIdx.x, gridDim.x);
     return;

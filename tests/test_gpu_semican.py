@@ -73,6 +73,43 @@ def test_semican_workloads(lib, name):
     h.close()
 
 
+@pytest.mark.parametrize("name", ["c1", "c5", "c3"])
+def test_semican_energy_without_x(lib, name):
+    """From x = 0 without x_out the FP64 semicanonical solve keeps no x: E2_DL
+    is -sum_i alpha_i rho_i, the Hylleraas value <b, x>_W - <x, r>_W of the
+    conjugate-gradient iterates (<b, p_i>_W = -rho_i, <x_k, r_k>_W = 0).  Both
+    runs start from a fresh b (the same start): the same iterates (residual
+    histories equal to rounding: the p updates of the two kernels may contract
+    into fused multiply-adds differently), E2 equal to rounding and to the
+    oracle."""
+    g = GOLD[name]
+    prob = synth.config_problem(name)
+    h = _handle(lib, prob)
+    h.rotate_top()
+    n, _ = h.space()
+    sc = lib.ESMP2_BASIS_SEMICANONICAL
+    h.build_rhs()
+    free = h.solve(tol=1e-10, max_iter=300, basis=sc, history=True)
+    h.build_rhs()
+    xo = torch.empty(n, dtype=torch.float64, device="cuda")
+    kept = h.solve(tol=1e-10, max_iter=300, basis=sc, history=True, x_out=xo)
+    torch.cuda.synchronize()
+    print(f"[{name} no x] E2 {free['e2']:.12f} with x {kept['e2']:.12f} diff {free['e2'] - kept['e2']:.3e} "
+          f"oracle diff {free['e2'] - g['e2']:.3e}", flush=True)
+    assert free["status"] == 0 and kept["status"] == 0 and free["iterations"] == kept["iterations"]
+    assert np.allclose(free["history"], kept["history"], rtol=1e-10, atol=0)
+    assert abs(free["e2"] - kept["e2"]) < 1e-11 * max(1.0, abs(kept["e2"]))
+    assert abs(free["e2"] - g["e2"]) < 1e-10 and free["e2_s"] == kept["e2_s"]
+    # stopped at max_iter: the partial sum equals the Hylleraas value of that iterate
+    h.build_rhs()
+    f2 = h.solve(tol=1e-14, max_iter=2, basis=sc)
+    h.build_rhs()
+    k2 = h.solve(tol=1e-14, max_iter=2, basis=sc, x_out=xo)
+    assert f2["status"] == k2["status"] == lib.ESMP2_NOT_CONVERGED
+    assert abs(f2["e2"] - k2["e2"]) < 1e-11 * max(1.0, abs(k2["e2"]))
+    h.close()
+
+
 @pytest.mark.parametrize("name", ["c5", "c3"])
 def test_semican_mixed(lib, name):
     g = GOLD[name]
