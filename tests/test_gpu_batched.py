@@ -58,7 +58,8 @@ def test_batched_states(lib, handles, basis):
 
 def test_batched_matches_one_by_one(lib, handles):
     """The batch gives each state the E2 of its own solve on its own stream (the
-    reduction blocks differ, so to rounding), after the same iteration count."""
+    reduction blocks differ and the one-state solve takes E2 from its scalars,
+    so to rounding: 1e-14 of |E2|), after the same iteration count."""
     res = lib.solve_batch(handles[:4], tol=1e-8, basis=lib.ESMP2_BASIS_SEMICANONICAL, n_threads=3)
     for h, r in zip(handles[:4], res):
         h.rotate_top(False)
@@ -66,7 +67,8 @@ def test_batched_matches_one_by_one(lib, handles):
         one = h.solve(tol=1e-8, max_iter=300, basis=lib.ESMP2_BASIS_SEMICANONICAL)
         print(f"[batched vs one] E2 {r['e2']:.15f} {one['e2']:.15f} iters {r['iterations']} {one['iterations']}",
               flush=True)
-        assert abs(one["e2"] - r["e2"]) < 1e-13 and abs(one["iterations"] - r["iterations"]) <= 1
+        assert abs(one["e2"] - r["e2"]) < 1e-14 * max(1.0, abs(one["e2"]))
+        assert abs(one["iterations"] - r["iterations"]) <= 1
     assert all(r["status"] == 0 for r in res)
 
 
