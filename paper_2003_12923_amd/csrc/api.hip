@@ -2003,7 +2003,7 @@ static esmp2_status solve_batch_sc64(esmp2_handle* hs, int n, const esmp2_solve_
     B.nsym = (int)sym_s2_blocks(d);
     B.ngemv = pa.jobs;
     B.nchunks = h->nchunks;
-    B.x = h->x; B.r = h->r; B.p = h->p; B.q = h->q; B.sc = h->sc; B.partial = h->partial; B.pq = h->pq_part;
+    B.r = h->r; B.p = h->p; B.q = h->q; B.sc = h->sc; B.partial = h->partial; B.pq = h->pq_part;
     B.S = c.s64.S;
     B.b = c.b;
     B.dinv = c.dinv32;
@@ -2057,7 +2057,7 @@ static esmp2_status solve_batch_sc64(esmp2_handle* hs, int n, const esmp2_solve_
   };
   for (auto& v : ev)
     if (hipEventCreateWithFlags(&v, hipEventDisableTiming) != hipSuccess) return fin(ESMP2_HIP_ERROR, "event");
-  // start: x = 0, r = -b, p = M r, <b, b>, then the states converged already drop out
+  // start from x = 0: r = -b, p = M r, <b, b>, then the states converged already drop out
   hipLaunchKernelGGL(kb_init, dim3(NBV), dim3(256), 0, s, dS);
   hipLaunchKernelGGL(kb_dot_bb, dim3(NBV), dim3(256), 0, s, dS);
   hipLaunchKernelGGL(kb_finish_init, dim3(3 * n), dim3(1024), 0, s, dS);
@@ -2092,7 +2092,7 @@ static esmp2_status solve_batch_sc64(esmp2_handle* hs, int n, const esmp2_solve_
     if (hipEventSynchronize(ev[k & 1]) != hipSuccess) return fin(ESMP2_HIP_ERROR, "batched iteration");
     if (act[k & 1] == 0) break;     // the iteration just launched finds every state stopped
   }
-  // E2 = <b, x>_W - <x, r>_W and E2_S, for every state, then one wait
+  // E2 = -sum_i alpha_i rho_i (in sc, batch.hip) and E2_S, for every state, then one wait
   for (int i = 0; i < n; ++i) {
     esmp2_handle h = hs[i];
     if (h->e2s_pending) {
@@ -2100,8 +2100,6 @@ static esmp2_status solve_batch_sc64(esmp2_handle* hs, int n, const esmp2_solve_
       h->e2s_pending = false;
     }
   }
-  hipLaunchKernelGGL(kb_e2_dots, dim3(2 * NBV), dim3(256), 0, s, dS);
-  hipLaunchKernelGGL(kb_finish_e2, dim3(2 * n), dim3(1024), 0, s, dS);
   e = hipMemcpyAsync(st.data(), dS, sizeof(BState) * n, hipMemcpyDeviceToHost, s);
   for (int i = 0; i < n && e == hipSuccess; ++i) {
     esmp2_handle h = hs[i];

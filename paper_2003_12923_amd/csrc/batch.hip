@@ -8,7 +8,10 @@
 // state from a table of first blocks and runs the one-state kernel body with
 // its local block index.  A state that has stopped leaves its blocks at once.
 // The operator is the one of the pinned-semicanonical basis (arrow kernels),
-// applied to p into q.
+// applied to p into q.  No x is kept (the batch returns energies only): each
+// state's E2_DL is the Hylleraas value of its iterates, -sum_i alpha_i rho_i
+// (for conjugate gradient from zero <b, p_i>_W = -rho_i and <x_k, r_k>_W = 0),
+// added up in sc[SC_BX] as the state iterates (sc[SC_XR] = 0).
 #include "common.h"
 #include "sigma.h"
 #include "pcg.h"
@@ -29,12 +32,12 @@ struct BState {
   const int4* chunks;
   int nsym, ngemv, nchunks;
   // Krylov vectors and scalars (the handle's)
-  double *x, *r, *p, *q, *sc, *partial, *pq, *S;
+  double *r, *p, *q, *sc, *partial, *pq, *S;
   const double* b;
   const float* dinv;
   int64_t n;
   // device-side control
-  int mode;            // BS_RUN: iterating; BS_LAST: x += alpha p then stop; BS_DONE
+  int mode;            // BS_RUN: iterating; BS_LAST: the last update done, stop; BS_DONE
   int it, status;      // iterations done, esmp2_status
   double rel;          // last ||r||_W / ||b||_W
 };
@@ -112,6 +115,7 @@ __global__ void kb_check(BState* S, int ns, double tol, int max_iter, int* activ
     B.mode = BS_DONE;
     return;
   }
+  B.sc[SC_BX] -= (sc[SC_RHO] / sc[SC_PQ]) * sc[SC_RHO];     // alpha_i rho_i of this iteration
   B.it += 1;
   B.rel = sqrt(sc[SC_RR] / sc[SC_BB]);
   if (B.rel <= tol || B.it >= max_iter) {
@@ -122,14 +126,12 @@ __global__ void kb_check(BState* S, int ns, double tol, int max_iter, int* activ
   }
 }
 
-// x += alpha p, and p = M r + beta p for a state that goes on; BATCH_CG_BLOCKS per state
+// p = M r + beta p for a state that goes on; BATCH_CG_BLOCKS per state
 __global__ __launch_bounds__(256) void kb_update(BState* S) {
   BState& B = S[blockIdx.x / BATCH_CG_BLOCKS];
   const int bid = blockIdx.x % BATCH_CG_BLOCKS;
   if (B.mode == BS_RUN)
-    update_px_body<double>(B.x, B.p, (const double*)B.r, B.dinv, B.n, (const double*)B.sc, bid, BATCH_CG_BLOCKS);
-  else if (B.mode == BS_LAST)
-    update_x_body<double>(B.x, (const double*)B.p, B.n, (const double*)B.sc, bid, BATCH_CG_BLOCKS);
+    update_p_body<double>(B.p, (const double*)B.r, B.dinv, B.n, (const double*)B.sc, bid, BATCH_CG_BLOCKS);
 }
 
 // rho <- rho_new for the states that go on; BS_LAST -> BS_DONE
@@ -141,12 +143,10 @@ __global__ void kb_roll(BState* S, int ns) {
   else if (B.mode == BS_LAST) B.mode = BS_DONE;
 }
 
-// start: x = 0, r = -b, p = M r, partials of <r, M r>, <r, r>, and <b, b>
+// start (x = 0): r = -b, p = M r, partials of <r, M r>, <r, r>, and <b, b>
 __global__ __launch_bounds__(256) void kb_init(BState* S) {
   BState& B = S[blockIdx.x / BATCH_CG_BLOCKS];
   const int bid = blockIdx.x % BATCH_CG_BLOCKS;
-  for (int64_t g = (int64_t)bid * blockDim.x + threadIdx.x; g < B.n; g += (int64_t)BATCH_CG_BLOCKS * blockDim.x)
-    B.x[g] = 0.0;
   init_body(B.b, (const double*)nullptr, B.r, B.p, B.dinv, B.n, B.d.off[1], B.d.off[2], B.partial, bid,
             BATCH_CG_BLOCKS);
 }
@@ -178,6 +178,8 @@ __global__ void kb_start(BState* S, int ns, double tol, int* active) {
   BState& B = S[s];
   B.it = 0;
   B.status = ESMP2_OK;
+  B.sc[SC_BX] = 0.0;
+  B.sc[SC_XR] = 0.0;
   B.rel = sqrt(B.sc[SC_RR] / B.sc[SC_BB]);
   if (B.rel <= tol) {
     B.mode = BS_DONE;
@@ -185,24 +187,6 @@ __global__ void kb_start(BState* S, int ns, double tol, int* active) {
     B.mode = BS_RUN;
     atomicAdd(active, 1);
   }
-}
-
-// the Hylleraas dot products of the end, <b, x> and <x, r>; BATCH_CG_BLOCKS per state
-__global__ __launch_bounds__(256) void kb_e2_dots(BState* S) {
-  BState& B = S[blockIdx.x / (2 * BATCH_CG_BLOCKS)];
-  const int k = blockIdx.x % (2 * BATCH_CG_BLOCKS);
-  const int which = k / BATCH_CG_BLOCKS, bid = k % BATCH_CG_BLOCKS;
-  if (which == 0)
-    dot_body<double>(B.b, (const double*)B.x, B.n, B.d.off[1], B.d.off[2], B.partial, bid, BATCH_CG_BLOCKS);
-  else
-    dot_body<double>((const double*)B.x, (const double*)B.r, B.n, B.d.off[1], B.d.off[2],
-                     B.partial + BATCH_CG_BLOCKS, bid, BATCH_CG_BLOCKS);
-}
-
-// sc[SC_BX], sc[SC_XR] (= SC_BX + 1); two blocks per state
-__global__ __launch_bounds__(1024) void kb_finish_e2(BState* S) {
-  BState& B = S[blockIdx.x >> 1];
-  finish_body(B.partial, BATCH_CG_BLOCKS, B.sc, SC_BX, blockIdx.x & 1, 2);
 }
 
 }  // namespace esmp2

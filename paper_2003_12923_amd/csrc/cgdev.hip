@@ -165,23 +165,7 @@ __global__ __launch_bounds__(256) void kd_update_px(double* x, double* p, const 
                                                     int no_x) {
   const int mode = c->mode;
   if (no_x) {            // p = M r + beta p only
-    if (mode != CG_RUN) return;
-    const double beta = sc[SC_RHO_NEW] / sc[SC_RHO];
-    const int64_t st = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
-      double pv[PCG_U], rv[PCG_U];
-      float dv[PCG_U];
-#pragma unroll
-      for (int u = 0; u < PCG_U; ++u) {
-        const int64_t g = g0 + u * st, gg = g < n ? g : 0;
-        pv[u] = ldnt(p + gg); rv[u] = ldnt(r + gg); dv[u] = ldnt(dinv + gg);
-      }
-#pragma unroll
-      for (int u = 0; u < PCG_U; ++u) {
-        const int64_t g = g0 + u * st;
-        if (g < n) stnt((double)dv[u] * rv[u] + beta * pv[u], p + g);
-      }
-    }
+    if (mode == CG_RUN) update_p_body<double>(p, r, dinv, n, sc, blockIdx.x, gridDim.x);
     return;
   }
   if (mode == CG_RUN && !first) {

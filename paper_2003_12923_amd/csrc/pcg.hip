@@ -134,6 +134,28 @@ __global__ __launch_bounds__(256) void k_update_r(T* r, const T* q, const float*
 }
 
 // alpha = sc[RHO] / sc[PQ], beta = sc[RHO_NEW] / sc[RHO]:  x += alpha p;  p = M r + beta p
+// p = M r + beta p alone (a solve that keeps no x)
+template <class T>
+__device__ __attribute__((always_inline)) inline void update_p_body(T* p, const T* r, const float* dinv, int64_t n,
+                                                  const double* sc, int bid_, int nb_) {
+  const T beta = (T)(sc[SC_RHO_NEW] / sc[SC_RHO]);
+  const int64_t st = (int64_t)nb_ * blockDim.x;
+  for (int64_t g0 = (int64_t)bid_ * blockDim.x + threadIdx.x; g0 < n; g0 += PCG_U * st) {
+    T pv[PCG_U], rv[PCG_U];
+    float dv[PCG_U];
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st, gg = g < n ? g : 0;
+      pv[u] = ldnt(p + gg); rv[u] = ldnt(r + gg); dv[u] = ldnt(dinv + gg);
+    }
+#pragma unroll
+    for (int u = 0; u < PCG_U; ++u) {
+      const int64_t g = g0 + u * st;
+      if (g < n) stnt((T)dv[u] * rv[u] + beta * pv[u], p + g);
+    }
+  }
+}
+
 template <class T>
 __device__ __attribute__((always_inline)) inline void update_px_body(T* x, T* p, const T* r, const float* dinv, int64_t n,
                                                    const double* sc, int bid_, int nb_) {
