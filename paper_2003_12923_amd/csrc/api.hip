@@ -745,7 +745,7 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
     // SVD of C
     size_t lds = sizeof(double) * (no * nv + no * no);
     ESMP2_HIP(allow_device_lds((const void*)k_svd_jacobi));
-    hipLaunchKernelGGL(k_svd_jacobi, dim3(1), dim3(1024), lds, s, h->C, no, nv, h->lam, h->U, h->V, h->iinfo);
+    hipLaunchKernelGGL(k_svd_jacobi, dim3(1), dim3(512), lds, s, h->C, no, nv, h->lam, h->U, h->V, h->iinfo);
     {
       const esmp2_status st = launch_sc_vir_early(h);
       if (st != ESMP2_OK) return st;

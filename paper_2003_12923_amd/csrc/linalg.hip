@@ -176,6 +176,15 @@ hipError_t gemm(hipStream_t s, int batch, const GemmArgs& g) {
   return gemm_native(s, batch, g);
 }
 
+// 1/q: the hardware reciprocal estimate refined by two Newton steps (relative
+// error at the level of the FP64 rounding)
+__device__ inline double rcp_refined(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(fma(-q, r, 1.0), r, r);
+  r = fma(fma(-q, r, 1.0), r, r);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // One-sided Jacobi SVD of C (no x nv, no <= nv, no <= 64, no*nv <= 8192):
 // rows of C are rotated pairwise until mutually orthogonal; C = U diag(lam) Vt.
@@ -206,22 +215,37 @@ __global__ __launch_bounds__(1024) void k_svd_jacobi(const double* __restrict__ 
         int p = player(pr), q = player(P - 1 - pr);
         if (p > q) { int t = p; p = q; q = t; }
         if (q >= no) continue;
+        // the two rows stay in registers (nv <= 192: three columns per lane)
+        double xr[3], yr[3];
         double al = 0, be = 0, ga = 0;
-        for (int a = l; a < nv; a += 64) {
-          double x = C[p * nv + a], y = C[q * nv + a];
-          al += x * x; be += y * y; ga += x * y;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int a = l + 64 * u;
+          xr[u] = a < nv ? C[p * nv + a] : 0.0;
+          yr[u] = a < nv ? C[q * nv + a] : 0.0;
+          al += xr[u] * xr[u]; be += yr[u] * yr[u]; ga += xr[u] * yr[u];
         }
         al = wave_sum(al);
         be = wave_sum(be);
         ga = wave_sum(ga);
-        if (fabs(ga) > 1e-15 * sqrt(al * be) && fabs(ga) > 1e-300) {
-          double ze = (be - al) / (2.0 * ga);
-          double t = (ze >= 0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
-          double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          for (int a = l; a < nv; a += 64) {
-            double x = C[p * nv + a], y = C[q * nv + a];
-            C[p * nv + a] = c * x - s * y;
-            C[q * nv + a] = s * x + c * y;
+        if (ga * ga > 1e-30 * (al * be) && fabs(ga) > 1e-300) {
+          // the angle only sets how well ga is annihilated (refined reciprocals
+          // suffice); c = (1 + t^2)^(-1/2) to the rounding level keeps the
+          // rotation orthogonal
+          const double ze = (be - al) * (0.5 * rcp_refined(ga));
+          const double t = (ze >= 0 ? 1.0 : -1.0) * rcp_refined(fabs(ze) + sqrt(1.0 + ze * ze));
+          const double w = 1.0 + t * t;
+          double c = __builtin_amdgcn_rsq(w);
+          c = fma(0.5 * c, fma(-w * c, c, 1.0), c);
+          c = fma(0.5 * c, fma(-w * c, c, 1.0), c);
+          const double s = c * t;
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            const int a = l + 64 * u;
+            if (a < nv) {
+              C[p * nv + a] = c * xr[u] - s * yr[u];
+              C[q * nv + a] = s * xr[u] + c * yr[u];
+            }
           }
           for (int k = l; k < no; k += 64) {
             double x = Us[k * no + p], y = Us[k * no + q];
