@@ -356,7 +356,7 @@ static esmp2_status launch_sc_vir_early(esmp2_handle h) {
   }
   hipLaunchKernelGGL(k_take_column, dim3(nblk(nv)), dim3(256), 0, s, (const double*)h->V, no, nv, tp);
   ESMP2_HIP(allow_device_lds((const void*)k_complement_qr));
-  hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), sizeof(double) * 2 * (size_t)nv, s, (const double*)tp, nv,
+  hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(1024), sizeof(double) * 3 * (size_t)nv, s, (const double*)tp, nv,
                      1, refl);
   hipLaunchKernelGGL(k_complement_apply, dim3(m), dim3(64), 0, s, (const double*)refl, nv, 1, Qp);
   GemmArgs g{};
@@ -761,10 +761,10 @@ esmp2_status esmp2_rotate_top(esmp2_handle h, double* lambda_out) {
       double* Ym = refl + (size_t)nv * nv;                // m x m
       double* AV = Ym + (size_t)nv * nv;                  // nv x m; with AV2.. the eigensolver's scratch
       double* AV2 = AV + (size_t)nv * nv;                 // nv x m  (rs holds 11 nv^2)
-      size_t lc = sizeof(double) * 2 * (size_t)nv * no;
+      size_t lc = sizeof(double) * (size_t)nv * (2 * no + 1);    // padded working copy + reflectors
       if (m > 0) {   // n_vir == n_occ: no AVOs
       ESMP2_HIP(allow_device_lds((const void*)k_complement_qr));
-      hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(256), lc, s, (const double*)h->V, nv, no, refl);
+      hipLaunchKernelGGL(k_complement_qr, dim3(1), dim3(1024), lc, s, (const double*)h->V, nv, no, refl);
       if (m > 0) hipLaunchKernelGGL(k_complement_apply, dim3(m), dim3(64), 0, s, (const double*)refl, nv, no, Q2);
       GemmArgs g{};
       g.A = h->F + (int64_t)no * n + no; g.B = Q2; g.C = Tt; g.M = nv; g.N = m; g.K = nv;

@@ -346,37 +346,41 @@ namespace esmp2 {
 // Single workgroup (256 threads).  Vin: nv x no row-major.  Householder QR of
 // Vin; reflector j (entries j..nv-1, zero above) into refl[j*nv + i], its
 // coefficient into refl[no*nv + j].
-__global__ __launch_bounds__(256) void k_complement_qr(const double* Vin, int nv, int no, double* refl) {
+__global__ __launch_bounds__(1024) void k_complement_qr(const double* Vin, int nv, int no, double* refl) {
   extern __shared__ double sm[];
-  double* W = sm;                    // nv x no working copy, column j reduced in place
-  double* vv = W + nv * no;          // reflectors: no x nv (row j = reflector j, entries j..nv-1)
+  // nv x no working copy, column j reduced in place; rows padded to no + 1 so
+  // that a wavefront walking one column spreads over the LDS banks
+  const int ld = no + 1;
+  double* W = sm;
+  double* vv = W + nv * ld;          // reflectors: no x nv (row j = reflector j, entries j..nv-1)
   __shared__ double beta[64];
-  __shared__ double red[4];
-  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
-  for (int e = tid; e < nv * no; e += blockDim.x) W[e] = Vin[e];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63, nw = blockDim.x >> 6;
+  for (int e = tid; e < nv * no; e += blockDim.x) W[(e / no) * ld + e % no] = Vin[e];
   __syncthreads();
   for (int j = 0; j < no; ++j) {
     double s = 0.0;
-    for (int i = j + 1 + tid; i < nv; i += blockDim.x) s += W[i * no + j] * W[i * no + j];
+    for (int i = j + 1 + tid; i < nv; i += blockDim.x) s += W[i * ld + j] * W[i * ld + j];
     s = wave_sum(s);
     if (l == 0) red[wave] = s;
     __syncthreads();
-    double sig = red[0] + red[1] + red[2] + red[3];
-    double x0 = W[j * no + j];
+    double sig = 0.0;
+    for (int w = 0; w < nw; ++w) sig += red[w];
+    double x0 = W[j * ld + j];
     double nrm = sqrt(x0 * x0 + sig);
     double alpha = (x0 >= 0) ? -nrm : nrm;
     double v0 = x0 - alpha;
     double vtv = v0 * v0 + sig;
     double b = (vtv > 0) ? 2.0 / vtv : 0.0;
-    for (int i = tid; i < nv; i += blockDim.x) vv[j * nv + i] = (i < j) ? 0.0 : (i == j ? v0 : W[i * no + j]);
+    for (int i = tid; i < nv; i += blockDim.x) vv[j * nv + i] = (i < j) ? 0.0 : (i == j ? v0 : W[i * ld + j]);
     if (tid == 0) beta[j] = b;
     __syncthreads();
     // apply H_j = 1 - b v v^T to the remaining columns c > j (one wave per column)
-    for (int c = j + 1 + wave; c < no; c += blockDim.x >> 6) {
+    for (int c = j + 1 + wave; c < no; c += nw) {
       double t = 0.0;
-      for (int i = l; i < nv; i += 64) if (i >= j) t += vv[j * nv + i] * W[i * no + c];
+      for (int i = l; i < nv; i += 64) if (i >= j) t += vv[j * nv + i] * W[i * ld + c];
       t = wave_sum(t) * b;
-      for (int i = l; i < nv; i += 64) if (i >= j) W[i * no + c] -= t * vv[j * nv + i];
+      for (int i = l; i < nv; i += 64) if (i >= j) W[i * ld + c] -= t * vv[j * nv + i];
     }
     __syncthreads();
   }
