@@ -574,6 +574,17 @@ __global__ __launch_bounds__(OO_THREADS) void k_oo(GatherArgs<T> A, int4 tiles0,
   const int tw = min(GO, inner - t0);
   const int tid = threadIdx.x;
   const int ne = nbat * GO;
+  T* y = A.y + d.off[box];
+  // y of the first output round, issued with the staging so that its latency
+  // overlaps the staging and the matrix-core products (no other kernel writes
+  // y meanwhile; the workgroups own disjoint parts of it)
+  T vy0[OO_R];
+#pragma unroll
+  for (int u = 0; u < OO_R; ++u) {
+    const int e = u * OO_THREADS + tid;
+    const int o = e / GO, vl = e % GO;
+    vy0[u] = (e < ne && vl < tw) ? y[(int64_t)o * inner + t0 + vl] : T(0);
+  }
   // staging: OO_R elements per thread per round, all loads of a round issued
   // before the first LDS store, so their latencies overlap
   for (int e0 = 0; e0 < ne; e0 += OO_R * OO_THREADS) {
@@ -641,14 +652,13 @@ __global__ __launch_bounds__(OO_THREADS) void k_oo(GatherArgs<T> A, int4 tiles0,
     }
   }
   __syncthreads();
-  T* y = A.y + d.off[box];
   for (int e0 = 0; e0 < ne; e0 += OO_R * OO_THREADS) {
     T vy[OO_R];
 #pragma unroll
     for (int u = 0; u < OO_R; ++u) {
       const int e = e0 + u * OO_THREADS + tid;
       const int o = e / GO, vl = e % GO;
-      vy[u] = (e < ne && vl < tw) ? y[(int64_t)o * inner + t0 + vl] : T(0);
+      vy[u] = e0 == 0 ? vy0[u] : (e < ne && vl < tw) ? y[(int64_t)o * inner + t0 + vl] : T(0);
     }
 #pragma unroll
     for (int u = 0; u < OO_R; ++u) {
