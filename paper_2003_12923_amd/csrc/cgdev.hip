@@ -11,7 +11,6 @@
 //                partial sums of <p, Ap>_W (eight workgroups)
 //   update_r     RUN only; every workgroup adds the eight parts in one order
 //                (workgroup 0 also stores the sum for the later kernels)
-//   update_r     RUN only
 //   finish_r     RUN only: <r, M r>_W, <r, r>_W, then the test: p.Ap <= 0 ->
 //                DONE (not SPD); ||r||_W / ||b||_W <= tol or max_iter -> LAST
 //                (||b||_W^2 in sc[SC_BB] from the start)
