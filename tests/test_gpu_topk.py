@@ -114,10 +114,12 @@ def test_topk_exported_determinants(lib, no, nv, na, seed, k, spin):
     h.close()
 
 
-def test_topk_workload_sample(lib):
-    """The largest size the oracle's TOP(2) reaches in minutes, n_occ = 6,
-    n_vir = 40: E2 and sampled sigma and b against stored oracle values."""
-    name = "topk_6_40_30_5_2"
+@pytest.mark.parametrize("name", ["topk_6_40_30_5_2", "topk_10_100_300_1_2"])
+def test_topk_workload_sample(lib, name):
+    """TOP(2) at the largest sizes the oracle's determinant-level operator
+    reaches, n_occ = 6, n_vir = 40 (minutes) and the n_occ = 10, n_vir = 100
+    problem of the c2 size (hours): E2 and sampled sigma and b against stored
+    oracle values."""
     if name not in GOLD:
         pytest.skip("stored oracle values not generated")
     g = GOLD[name]
