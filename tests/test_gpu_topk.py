@@ -116,10 +116,11 @@ def test_topk_exported_determinants(lib, no, nv, na, seed, k, spin):
 
 @pytest.mark.parametrize("name", ["topk_6_40_30_5_2", "topk_10_100_300_1_2"])
 def test_topk_workload_sample(lib, name):
-    """TOP(2) at the largest sizes the oracle's determinant-level operator
-    reaches, n_occ = 6, n_vir = 40 (minutes) and the n_occ = 10, n_vir = 100
-    problem of the c2 size (hours): E2 and sampled sigma and b against stored
-    oracle values."""
+    """TOP(2) against stored values of the oracle's determinant-level
+    operator: n_occ = 6, n_vir = 40 (minutes of oracle time), and the
+    n_occ = 10, n_vir = 100 problem of the c2 size, skipped until its values
+    are stored (more than eight hours of oracle time): E2 and sampled sigma
+    and b."""
     if name not in GOLD:
         pytest.skip("stored oracle values not generated")
     g = GOLD[name]
