@@ -114,13 +114,13 @@ def test_topk_exported_determinants(lib, no, nv, na, seed, k, spin):
     h.close()
 
 
-@pytest.mark.parametrize("name", ["topk_6_40_30_5_2", "topk_10_100_300_1_2"])
+@pytest.mark.parametrize("name", ["topk_6_40_30_5_2", "topk_8_56_120_3_2", "topk_10_100_300_1_2"])
 def test_topk_workload_sample(lib, name):
     """TOP(2) against stored values of the oracle's determinant-level
-    operator: n_occ = 6, n_vir = 40 (minutes of oracle time), and the
-    n_occ = 10, n_vir = 100 problem of the c2 size, skipped until its values
-    are stored (more than eight hours of oracle time): E2 and sampled sigma
-    and b."""
+    operator: n_occ = 6, n_vir = 40 and n_occ = 8, n_vir = 56 (minutes of
+    oracle time), and the n_occ = 10, n_vir = 100 problem of the c2 size,
+    skipped until its values are stored (more than eight hours of oracle
+    time): E2 and sampled sigma and b."""
     if name not in GOLD:
         pytest.skip("stored oracle values not generated")
     g = GOLD[name]
